@@ -1,0 +1,20 @@
+"""FP64 CPU oracle for the Adam-based inflation protocol (test infrastructure).
+
+Only the tests, the smoke check and the CPU-baseline leg of the benchmark
+may import this package.  It wraps `rcp_oracle.c` (plain C, -ffp-contract=off)
+through ctypes and adds the schedule builder of Eq. (trigger).  It shares no
+code with the HIP library.
+"""
+from .oracle import (build, lib, splitmix64, u01, pairs_brute, pairs_cells,
+                     rows_pairs, energy_grad, rows_grad, shrink, phi, rsa,
+                     run, Params, Schedule, n_trig, default_schedule,
+                     time_iterations, set_threads, num_threads, RunState,
+                     default_params, absolute_schedule, Result)
+from . import oracle
+
+__all__ = [
+    "build", "lib", "splitmix64", "u01", "pairs_brute", "pairs_cells",
+    "rows_pairs", "energy_grad", "rows_grad", "shrink", "phi", "rsa", "run",
+    "Params", "Schedule", "n_trig", "default_schedule", "time_iterations",
+    "set_threads", "num_threads", "RunState",
+]

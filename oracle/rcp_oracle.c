@@ -1,0 +1,906 @@
+/*
+ * FP64 CPU oracle for the Adam-based inflation protocol.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the library or its Python binding
+ * may include, link or call this file; it is built and called by the tests,
+ * by the smoke check and by the CPU-baseline leg of the benchmark.  It
+ * shares no code with the HIP path.
+ *
+ * What is computed, and where the paper defines it:
+ *   - soft finite-range overlap energy E = (eps/2) sum_{i<j} (1 - r/d)^2
+ *     Theta(1 - r/d) - mu sum_i D_i with d = (D_i + D_j)/2 and D_i = kappa D0_i
+ *     (App. A, Eq. (energy)); eps = 1 (Adam is invariant to its scale);
+ *   - the gradient of E w.r.t. the positions and kappa (derived from
+ *     Eq. (energy); the paper does not print it);
+ *   - Adam (Kingma and Ba, bias corrected) on every coordinate and on kappa
+ *     (App. A);
+ *   - the annealing schedule, read as a table of rungs (App. A and
+ *     Eq. (trigger)); the rung values themselves are unstated in the paper;
+ *   - the stop rule: in the final rung, max fractional overlap below the
+ *     tolerance (5e-4 in App. A);
+ *   - shrink to contact: the largest kappa' <= kappa with no overlapping pair
+ *     (Sec. 2, App. A);
+ *   - random sequential addition at low volume fraction (App. A mentions a
+ *     cell-list placement without overlap; the algorithm is our reading);
+ *   - candidate pairs: brute force O(N^2), per-row brute force for subsets,
+ *     and a plain size-class cell list (App. A uses a k-d tree; any method
+ *     that returns the same pair set is equivalent).
+ *
+ * Floating point: compiled with -ffp-contract=off; every quantity is double.
+ * Sums of many terms (energy, kappa gradient) use Neumaier compensation.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_MAX_RUNGS 16
+
+/* ------------------------------------------------------------------ */
+/* SplitMix64 (Steele, Lea, Flood 2014), addressed as a counter stream */
+/* ------------------------------------------------------------------ */
+uint64_t orc_splitmix64(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + (k + 1u) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+double orc_u01(uint64_t seed, uint64_t i, uint64_t attempt, int axis)
+{
+    uint64_t k = ((i << 24) | attempt) * 4u + (uint64_t)axis;
+    return (double)(orc_splitmix64(seed, k) >> 11) * 0x1p-53;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+/* ------------------------------------------------------------------ */
+/* Minimum image and the canonical pair predicate                      */
+/* ------------------------------------------------------------------ */
+/* Positions live in [0, L).  The separation is shifted by one box length
+ * when it exceeds half a box (the largest sphere may not meet its own image,
+ * Sec. 2).  Exactly at +-L/2 no shift is applied. */
+static inline double mimg(double d, double L, double hL)
+{
+    if (d > hL) return d - L;
+    if (d < -hL) return d + L;
+    return d;
+}
+
+static inline double sep2(const double *x, int64_t i, int64_t j, double L,
+                          double hL, double *dx, double *dy, double *dz)
+{
+    *dx = mimg(x[3 * j] - x[3 * i], L, hL);
+    *dy = mimg(x[3 * j + 1] - x[3 * i + 1], L, hL);
+    *dz = mimg(x[3 * j + 2] - x[3 * i + 2], L, hL);
+    return (*dx * *dx + *dy * *dy) + *dz * *dz;
+}
+
+/* Neighbour-list cutoff of a pair listed at scale kb:
+ *   c = kb * ((1 + g) * (0.5 * (D0_i + D0_j)) + 2 s D0_min).
+ * The pair is listed iff r^2 < c^2.  opg = 1 + g and sk2 = (2 s) D0_min are
+ * computed once by the caller. */
+static inline double cutoff(double di, double dj, double kb, double opg,
+                            double sk2)
+{
+    return kb * (opg * (0.5 * (di + dj)) + sk2);
+}
+
+/* ------------------------------------------------------------------ */
+/* Pair sets                                                          */
+/* ------------------------------------------------------------------ */
+typedef struct { int32_t i, j; } pair_t;
+
+static int cmp_pair(const void *a, const void *b)
+{
+    const pair_t *p = a, *q = b;
+    if (p->i != q->i) return p->i < q->i ? -1 : 1;
+    if (p->j != q->j) return p->j < q->j ? -1 : 1;
+    return 0;
+}
+
+/* All pairs i<j with r^2 < c^2, by testing every pair.  Output is already
+ * lexicographic.  Returns the number of pairs (may exceed cap; then only
+ * cap are written). */
+int64_t orc_pairs_brute(int64_t n, const double *x, const double *d0, double L,
+                        double kb, double s, double g, double d0min,
+                        int32_t *pi, int32_t *pj, int64_t cap)
+{
+    const double hL = 0.5 * L, opg = 1.0 + g, sk2 = (2.0 * s) * d0min;
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = i + 1; j < n; ++j) {
+            double dx, dy, dz;
+            double r2 = sep2(x, i, j, L, hL, &dx, &dy, &dz);
+            double c = cutoff(d0[i], d0[j], kb, opg, sk2);
+            if (r2 < c * c) {
+                if (cnt < cap) { pi[cnt] = (int32_t)i; pj[cnt] = (int32_t)j; }
+                ++cnt;
+            }
+        }
+    return cnt;
+}
+
+/* For each requested row i, every j != i with r^2 < c^2, ascending j, by
+ * testing all N candidates.  Pass nbr == NULL to get the counts only.
+ * offs[k] is where row k's list starts in nbr (caller computes it from the
+ * counts of a first call). */
+void orc_rows_pairs(int64_t n, const double *x, const double *d0, double L,
+                    double kb, double s, double g, double d0min,
+                    const int64_t *rows, int64_t nrows, int64_t *counts,
+                    const int64_t *offs, int32_t *nbr)
+{
+    const double hL = 0.5 * L, opg = 1.0 + g, sk2 = (2.0 * s) * d0min;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nrows; ++k) {
+        int64_t i = rows[k], c = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx, dy, dz;
+            double r2 = sep2(x, i, j, L, hL, &dx, &dy, &dz);
+            double cc = cutoff(d0[i], d0[j], kb, opg, sk2);
+            if (r2 < cc * cc) {
+                if (nbr) nbr[offs[k] + c] = (int32_t)j;
+                ++c;
+            }
+        }
+        counts[k] = c;
+    }
+}
+
+/* Size-class cell list.  Class of particle i: floor(log2(D0_i / D0_min)).
+ * Class l gets a cubic grid whose cells are at least as wide as the largest
+ * cutoff between a class-l particle and any particle of class <= l, so a
+ * particle of class <= l finds every listed partner of class l in the 27
+ * cells around it.  Each particle searches its own class (partners with a
+ * larger index only) and every larger class. */
+typedef struct { int64_t key; int32_t idx; } kv_t;
+
+static int cmp_kv(const void *a, const void *b)
+{
+    const kv_t *p = a, *q = b;
+    if (p->key != q->key) return p->key < q->key ? -1 : 1;
+    return p->idx < q->idx ? -1 : (p->idx > q->idx);
+}
+
+typedef struct {
+    int nlev;
+    int *lev;          /* class of each particle */
+    int64_t *nc;       /* cells per axis per class */
+    double *w;         /* cell width per class */
+    int64_t *start;    /* start of class l in kv */
+    int64_t *count;
+    kv_t *kv;          /* particles sorted by (class, cell) */
+} cells_t;
+
+static int64_t cell_of(double xv, double w, int64_t nc)
+{
+    int64_t c = (int64_t)(xv / w);
+    if (c < 0) c = 0;
+    if (c >= nc) c = nc - 1;
+    return c;
+}
+
+static void cells_build(cells_t *C, int64_t n, const double *x, const double *d0,
+                        double L, double kb, double opg, double sk2, double d0min)
+{
+    C->lev = malloc(sizeof(int) * (size_t)n);
+    int nlev = 1;
+    for (int64_t i = 0; i < n; ++i) {
+        int l = (int)floor(log2(d0[i] / d0min));
+        if (l < 0) l = 0;
+        C->lev[i] = l;
+        if (l + 1 > nlev) nlev = l + 1;
+    }
+    C->nlev = nlev;
+    double *dmax = calloc((size_t)nlev, sizeof(double));
+    C->count = calloc((size_t)nlev, sizeof(int64_t));
+    C->start = calloc((size_t)nlev + 1, sizeof(int64_t));
+    C->nc = calloc((size_t)nlev, sizeof(int64_t));
+    C->w = calloc((size_t)nlev, sizeof(double));
+    for (int64_t i = 0; i < n; ++i) {
+        if (d0[i] > dmax[C->lev[i]]) dmax[C->lev[i]] = d0[i];
+        C->count[C->lev[i]]++;
+    }
+    double run = 0.0;
+    for (int l = 0; l < nlev; ++l) {
+        if (dmax[l] > run) run = dmax[l];
+        double h = kb * (opg * run + sk2) * (1.0 + 1e-12);
+        int64_t nc = (int64_t)floor(L / h);
+        if (nc < 1) nc = 1;
+        if (nc > (1 << 20)) nc = 1 << 20;
+        C->nc[l] = nc;
+        C->w[l] = L / (double)nc;
+        C->start[l + 1] = C->start[l] + C->count[l];
+    }
+    C->kv = malloc(sizeof(kv_t) * (size_t)(n > 0 ? n : 1));
+    int64_t *fill = calloc((size_t)nlev, sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i) {
+        int l = C->lev[i];
+        int64_t nc = C->nc[l];
+        double w = C->w[l];
+        int64_t cx = cell_of(x[3 * i], w, nc), cy = cell_of(x[3 * i + 1], w, nc),
+                cz = cell_of(x[3 * i + 2], w, nc);
+        kv_t e = {(cx * nc + cy) * nc + cz, (int32_t)i};
+        C->kv[C->start[l] + fill[l]++] = e;
+    }
+    for (int l = 0; l < nlev; ++l)
+        qsort(C->kv + C->start[l], (size_t)C->count[l], sizeof(kv_t), cmp_kv);
+    free(fill);
+    free(dmax);
+}
+
+static void cells_free(cells_t *C)
+{
+    free(C->lev); free(C->nc); free(C->w); free(C->start); free(C->count);
+    free(C->kv);
+}
+
+static int64_t lower_key(const kv_t *a, int64_t n, int64_t key)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (a[mid].key < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+/* Half pairs found from particle i: partners of the same class with a larger
+ * index, and partners of every larger class.  Writes up to cap partners
+ * into out (if non-NULL) and returns how many there are. */
+static int64_t cells_search(const cells_t *C, int64_t i, const double *x,
+                            const double *d0, double L, double kb, double opg,
+                            double sk2, int32_t *out)
+{
+    const double hL = 0.5 * L;
+    int64_t cnt = 0;
+    for (int l = C->lev[i]; l < C->nlev; ++l) {
+        if (C->count[l] == 0) continue;
+        int64_t nc = C->nc[l];
+        double w = C->w[l];
+        int64_t c[3];
+        for (int a = 0; a < 3; ++a) c[a] = cell_of(x[3 * i + a], w, nc);
+        int64_t lo = nc >= 3 ? -1 : 0, hi = nc >= 3 ? 1 : nc - 1;
+        const kv_t *kv = C->kv + C->start[l];
+        for (int64_t ox = lo; ox <= hi; ++ox)
+            for (int64_t oy = lo; oy <= hi; ++oy)
+                for (int64_t oz = lo; oz <= hi; ++oz) {
+                    int64_t ax, ay, az;
+                    if (nc >= 3) {
+                        ax = (c[0] + ox + nc) % nc;
+                        ay = (c[1] + oy + nc) % nc;
+                        az = (c[2] + oz + nc) % nc;
+                    } else {
+                        ax = ox; ay = oy; az = oz;
+                    }
+                    int64_t key = (ax * nc + ay) * nc + az;
+                    for (int64_t p = lower_key(kv, C->count[l], key);
+                         p < C->count[l] && kv[p].key == key; ++p) {
+                        int64_t j = kv[p].idx;
+                        if (l == C->lev[i] && j <= i) continue;
+                        double dx, dy, dz;
+                        double r2 = sep2(x, i, j, L, hL, &dx, &dy, &dz);
+                        double cc = cutoff(d0[i], d0[j], kb, opg, sk2);
+                        if (r2 < cc * cc) {
+                            if (out) out[cnt] = (int32_t)j;
+                            ++cnt;
+                        }
+                    }
+                }
+    }
+    return cnt;
+}
+
+/* Half pair list in search order (deterministic, independent of threads). */
+static int64_t cells_half_pairs(int64_t n, const double *x, const double *d0,
+                                double L, double kb, double s, double g,
+                                double d0min, int32_t **pi_out, int32_t **pj_out)
+{
+    const double opg = 1.0 + g, sk2 = (2.0 * s) * d0min;
+    cells_t C;
+    cells_build(&C, n, x, d0, L, kb, opg, sk2, d0min);
+    int64_t *cnt = malloc(sizeof(int64_t) * (size_t)(n + 1));
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i)
+        cnt[i] = cells_search(&C, i, x, d0, L, kb, opg, sk2, NULL);
+    int64_t tot = 0;
+    for (int64_t i = 0; i < n; ++i) { int64_t c = cnt[i]; cnt[i] = tot; tot += c; }
+    cnt[n] = tot;
+    int32_t *pi = malloc(sizeof(int32_t) * (size_t)(tot > 0 ? tot : 1));
+    int32_t *pj = malloc(sizeof(int32_t) * (size_t)(tot > 0 ? tot : 1));
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t k = cells_search(&C, i, x, d0, L, kb, opg, sk2, pj + cnt[i]);
+        for (int64_t q = 0; q < k; ++q) pi[cnt[i] + q] = (int32_t)i;
+    }
+    free(cnt);
+    cells_free(&C);
+    *pi_out = pi;
+    *pj_out = pj;
+    return tot;
+}
+
+/* Canonical pair set from the cell list: (min, max) per pair, sorted. */
+int64_t orc_pairs_cells(int64_t n, const double *x, const double *d0, double L,
+                        double kb, double s, double g, double d0min,
+                        int32_t *pi, int32_t *pj, int64_t cap)
+{
+    int32_t *a, *b;
+    int64_t tot = cells_half_pairs(n, x, d0, L, kb, s, g, d0min, &a, &b);
+    pair_t *p = malloc(sizeof(pair_t) * (size_t)(tot > 0 ? tot : 1));
+    for (int64_t k = 0; k < tot; ++k) {
+        p[k].i = a[k] < b[k] ? a[k] : b[k];
+        p[k].j = a[k] < b[k] ? b[k] : a[k];
+    }
+    qsort(p, (size_t)tot, sizeof(pair_t), cmp_pair);
+    for (int64_t k = 0; k < tot && k < cap; ++k) { pi[k] = p[k].i; pj[k] = p[k].j; }
+    free(p); free(a); free(b);
+    return tot;
+}
+
+/* ------------------------------------------------------------------ */
+/* Energy and gradient                                                 */
+/* ------------------------------------------------------------------ */
+typedef struct { double s, c; } nsum_t;   /* Neumaier running sum */
+
+static inline void nadd(nsum_t *a, double v)
+{
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v)) a->c += (a->s - t) + v;
+    else a->c += (v - t) + a->s;
+    a->s = t;
+}
+static inline double nval(const nsum_t *a) { return a->s + a->c; }
+
+/* Energy terms over a list of half pairs (i, j); pairs with r >= d add
+ * nothing.  out = [E_overlap, E_growth, dE/dkappa overlap part,
+ * dE/dkappa growth part, max fractional overlap, number overlapping].
+ * gx (n x 3, may be NULL): dE/dx.  gscale (n x 3, may be NULL): per
+ * component sum of |pair contributions|, the scale used by the parity
+ * tolerance.  Pairs are processed in the order given. */
+void orc_energy_grad(int64_t n, const double *x, const double *d0, double L,
+                     double kappa, double mu, int64_t np, const int32_t *pi,
+                     const int32_t *pj, double *out, double *gx, double *gscale)
+{
+    const double hL = 0.5 * L;
+    nsum_t E = {0, 0}, S = {0, 0}, D = {0, 0};
+    double maxd = 0.0;
+    int64_t nov = 0;
+    if (gx) memset(gx, 0, sizeof(double) * 3 * (size_t)n);
+    if (gscale) memset(gscale, 0, sizeof(double) * 3 * (size_t)n);
+    for (int64_t p = 0; p < np; ++p) {
+        int64_t i = pi[p], j = pj[p];
+        double dx, dy, dz;
+        double r2 = sep2(x, i, j, L, hL, &dx, &dy, &dz);
+        double r = sqrt(r2);
+        double d = kappa * (0.5 * (d0[i] + d0[j]));
+        if (!(r < d)) continue;
+        double delta = 1.0 - r / d;
+        nadd(&E, 0.5 * delta * delta);
+        nadd(&S, delta * r / d);
+        if (delta > maxd) maxd = delta;
+        ++nov;
+        if (r > 0.0) {
+            double f = delta / (d * r);   /* dE/dx_i = f (x_j - x_i)_mi */
+            double c[3] = {f * dx, f * dy, f * dz};
+            for (int a = 0; a < 3; ++a) {
+                if (gx) { gx[3 * i + a] += c[a]; gx[3 * j + a] -= c[a]; }
+                if (gscale) {
+                    gscale[3 * i + a] += fabs(c[a]);
+                    gscale[3 * j + a] += fabs(c[a]);
+                }
+            }
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) nadd(&D, d0[i]);
+    out[0] = nval(&E);
+    out[1] = -mu * kappa * nval(&D);
+    out[2] = nval(&S) / kappa;
+    out[3] = -mu * nval(&D);
+    out[4] = maxd;
+    out[5] = (double)nov;
+}
+
+/* Per-row quantities for a subset of rows, by testing all N partners with
+ * the true overlap condition r < d (no list).  For row k (particle i):
+ * g[3k..3k+2] = dE/dx_i, gscale likewise, rowstat[3k] = sum_j delta^2/2
+ * (each pair's energy counted in full for this row), rowstat[3k+1] =
+ * sum_j delta r / d, rowstat[3k+2] = max_j delta. */
+void orc_rows_grad(int64_t n, const double *x, const double *d0, double L,
+                   double kappa, const int64_t *rows, int64_t nrows, double *g,
+                   double *gscale, double *rowstat)
+{
+    const double hL = 0.5 * L;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < nrows; ++k) {
+        int64_t i = rows[k];
+        double gg[3] = {0, 0, 0}, sc[3] = {0, 0, 0}, e = 0, s = 0, m = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx, dy, dz;
+            double r2 = sep2(x, i, j, L, hL, &dx, &dy, &dz);
+            double d = kappa * (0.5 * (d0[i] + d0[j]));
+            if (!(r2 < d * d)) continue;
+            double r = sqrt(r2);
+            if (!(r < d)) continue;
+            double delta = 1.0 - r / d;
+            e += 0.5 * delta * delta;
+            s += delta * r / d;
+            if (delta > m) m = delta;
+            if (r > 0.0) {
+                double f = delta / (d * r);
+                double c[3] = {f * dx, f * dy, f * dz};
+                for (int a = 0; a < 3; ++a) { gg[a] += c[a]; sc[a] += fabs(c[a]); }
+            }
+        }
+        for (int a = 0; a < 3; ++a) {
+            g[3 * k + a] = gg[a];
+            if (gscale) gscale[3 * k + a] = sc[a];
+        }
+        if (rowstat) { rowstat[3 * k] = e; rowstat[3 * k + 1] = s; rowstat[3 * k + 2] = m; }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Shrink to contact (Sec. 2; App. A)                                  */
+/* ------------------------------------------------------------------ */
+/* Largest double k with fl(fl(k dd) * fl(k dd)) <= r2, where dd is the pair's
+ * relative mean diameter.  That map is monotone in k, so the admissible
+ * k form a down-set and this maximum is unique. */
+static double pair_kmax(double r2, double dd)
+{
+    double k = sqrt(r2) / dd;
+    while (k > 0.0 && (k * dd) * (k * dd) > r2) k = nextafter(k, 0.0);
+    for (;;) {
+        double up = nextafter(k, INFINITY);
+        if ((up * dd) * (up * dd) <= r2) k = up; else break;
+    }
+    return k;
+}
+
+/* kappa' = min(kappa, min over the pairs of pair_kmax).  Touching (r = d)
+ * counts as no overlap. */
+double orc_shrink(int64_t n, const double *x, const double *d0, double L,
+                  double kappa, int64_t np, const int32_t *pi, const int32_t *pj)
+{
+    (void)n;
+    const double hL = 0.5 * L;
+    double kp = kappa;
+    for (int64_t p = 0; p < np; ++p) {
+        double dx, dy, dz;
+        double r2 = sep2(x, pi[p], pj[p], L, hL, &dx, &dy, &dz);
+        double dd = 0.5 * (d0[pi[p]] + d0[pj[p]]);
+        double k = pair_kmax(r2, dd);
+        if (k < kp) kp = k;
+    }
+    return kp;
+}
+
+double orc_phi(int64_t n, const double *d0, double L, double kappa)
+{
+    nsum_t s = {0, 0};
+    for (int64_t i = 0; i < n; ++i) nadd(&s, d0[i] * d0[i] * d0[i]);
+    return (M_PI / 6.0) * (kappa * kappa * kappa) * nval(&s) / (L * L * L);
+}
+
+/* ------------------------------------------------------------------ */
+/* Random sequential addition (App. A: dilute start without overlap)   */
+/* ------------------------------------------------------------------ */
+/* Largest sphere first (ties: lower index first).  Attempt a of sphere i
+ * proposes (u(seed,i,a,0) L, u(seed,i,a,1) L, u(seed,i,a,2) L) and is
+ * rejected when r^2 < (kappa0 * 0.5 * (D0_i + D0_j))^2 for a placed j.
+ * Returns 0, or -1 when a sphere needs more than max_attempts. */
+typedef struct { double d; int64_t i; } ord_t;
+
+static int cmp_ord(const void *a, const void *b)
+{
+    const ord_t *p = a, *q = b;
+    if (p->d != q->d) return p->d > q->d ? -1 : 1;
+    return p->i < q->i ? -1 : (p->i > q->i);
+}
+
+int orc_rsa(int64_t n, const double *d0, double L, double kappa0, uint64_t seed,
+            int64_t max_attempts, double *x)
+{
+    const double hL = 0.5 * L;
+    ord_t *ord = malloc(sizeof(ord_t) * (size_t)n);
+    double dmax = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        ord[i].d = d0[i]; ord[i].i = i;
+        if (d0[i] > dmax) dmax = d0[i];
+    }
+    qsort(ord, (size_t)n, sizeof(ord_t), cmp_ord);
+    /* one uniform grid, cells at least kappa0 * dmax wide */
+    int64_t nc = (int64_t)floor(L / (kappa0 * dmax * (1.0 + 1e-12)));
+    if (nc < 1) nc = 1;
+    if (nc > 256) nc = 256;
+    double w = L / (double)nc;
+    int64_t ncell = nc * nc * nc;
+    int64_t *head = malloc(sizeof(int64_t) * (size_t)ncell);
+    int64_t *next = malloc(sizeof(int64_t) * (size_t)n);
+    for (int64_t c = 0; c < ncell; ++c) head[c] = -1;
+    int rc = 0;
+    for (int64_t k = 0; k < n && rc == 0; ++k) {
+        int64_t i = ord[k].i;
+        int64_t a;
+        for (a = 0; a < max_attempts; ++a) {
+            double p[3];
+            for (int ax = 0; ax < 3; ++ax) {
+                p[ax] = orc_u01(seed, (uint64_t)i, (uint64_t)a, ax) * L;
+                if (p[ax] >= L) p[ax] -= L;
+                x[3 * i + ax] = p[ax];
+            }
+            int64_t c[3];
+            for (int ax = 0; ax < 3; ++ax) c[ax] = cell_of(p[ax], w, nc);
+            int ok = 1;
+            int64_t lo = nc >= 3 ? -1 : 0, hi = nc >= 3 ? 1 : nc - 1;
+            for (int64_t ox = lo; ox <= hi && ok; ++ox)
+                for (int64_t oy = lo; oy <= hi && ok; ++oy)
+                    for (int64_t oz = lo; oz <= hi && ok; ++oz) {
+                        int64_t ax_, ay_, az_;
+                        if (nc >= 3) {
+                            ax_ = (c[0] + ox + nc) % nc;
+                            ay_ = (c[1] + oy + nc) % nc;
+                            az_ = (c[2] + oz + nc) % nc;
+                        } else { ax_ = ox; ay_ = oy; az_ = oz; }
+                        for (int64_t j = head[(ax_ * nc + ay_) * nc + az_]; j >= 0;
+                             j = next[j]) {
+                            double dx, dy, dz;
+                            double r2 = sep2(x, i, j, L, hL, &dx, &dy, &dz);
+                            double dd = kappa0 * (0.5 * (d0[i] + d0[j]));
+                            if (r2 < dd * dd) { ok = 0; break; }
+                        }
+                    }
+            if (ok) break;
+        }
+        if (a == max_attempts) { rc = -1; break; }
+        int64_t cell = (cell_of(x[3 * i], w, nc) * nc + cell_of(x[3 * i + 1], w, nc)) * nc +
+                       cell_of(x[3 * i + 2], w, nc);
+        next[i] = head[cell];
+        head[cell] = i;
+    }
+    free(head); free(next); free(ord);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Schedule, Adam and the whole inflation run (App. A)                 */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int32_t n_rungs;
+    int32_t absolute;   /* 1: mu, eta_x, eta_k below are used as given */
+    double tol;         /* stop tolerance on the max fractional overlap */
+    double mu[ORC_MAX_RUNGS];
+    double eta_x[ORC_MAX_RUNGS];
+    double eta_k[ORC_MAX_RUNGS];
+    double decay[ORC_MAX_RUNGS];
+    int64_t budget[ORC_MAX_RUNGS];
+} orc_sched;
+
+typedef struct {
+    double beta1, beta2, eps_x, eps_k, skin_s, skin_g;
+} orc_params;
+
+typedef struct {
+    double phi, kappa_shrunk, kappa, max_overlap, energy;
+    int64_t iterations, rebuilds;
+    int32_t status;      /* 0 converged, 1 iteration cap reached */
+    int32_t rung;
+} orc_result;
+
+/* Full neighbour rows (both directions) from a half-pair list; each row
+ * keeps the order in which its partners appear in the half list. */
+static void full_rows(int64_t n, int64_t np, const int32_t *pi, const int32_t *pj,
+                      int64_t **rp_out, int32_t **col_out)
+{
+    int64_t *rp = calloc((size_t)n + 1, sizeof(int64_t));
+    for (int64_t p = 0; p < np; ++p) { rp[pi[p] + 1]++; rp[pj[p] + 1]++; }
+    for (int64_t i = 0; i < n; ++i) rp[i + 1] += rp[i];
+    int64_t *fill = malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    memcpy(fill, rp, sizeof(int64_t) * (size_t)n);
+    int32_t *col = malloc(sizeof(int32_t) * (size_t)(2 * np > 0 ? 2 * np : 1));
+    for (int64_t p = 0; p < np; ++p) {
+        col[fill[pi[p]]++] = pj[p];
+        col[fill[pj[p]]++] = pi[p];
+    }
+    free(fill);
+    *rp_out = rp;
+    *col_out = col;
+}
+
+typedef struct {
+    int64_t n;
+    double L, hL, d0min, sumd0;
+    const double *d0;
+    double *x, *m, *v, *xref, *g;
+    int64_t np;
+    int32_t *pi, *pj;        /* half pairs of the current list */
+    int64_t *rp;
+    int32_t *col;
+    double kb;               /* kappa at the last list build */
+    int64_t rebuilds;
+} run_t;
+
+static void run_rebuild(run_t *R, double kappa, const orc_params *P)
+{
+    free(R->pi); free(R->pj); free(R->rp); free(R->col);
+    if (R->n <= 2048) {
+        int64_t cap = 1024, np;
+        for (;;) {
+            R->pi = malloc(sizeof(int32_t) * (size_t)cap);
+            R->pj = malloc(sizeof(int32_t) * (size_t)cap);
+            np = orc_pairs_brute(R->n, R->x, R->d0, R->L, kappa, P->skin_s,
+                                 P->skin_g, R->d0min, R->pi, R->pj, cap);
+            if (np <= cap) break;
+            free(R->pi); free(R->pj);
+            cap = np;
+        }
+        R->np = np;
+    } else {
+        R->np = cells_half_pairs(R->n, R->x, R->d0, R->L, kappa, P->skin_s,
+                                 P->skin_g, R->d0min, &R->pi, &R->pj);
+    }
+    full_rows(R->n, R->np, R->pi, R->pj, &R->rp, &R->col);
+    memcpy(R->xref, R->x, sizeof(double) * 3 * (size_t)R->n);
+    R->kb = kappa;
+    R->rebuilds++;
+}
+
+/* Gradient over full rows (parallel over rows, each row summed in list
+ * order), plus E_ov, sum delta r/d and max delta accumulated per row and
+ * then over rows in index order. */
+static void run_grad(run_t *R, double kappa, double *Eov, double *Sdrd,
+                     double *maxd)
+{
+    const int64_t n = R->n;
+    double *re = malloc(sizeof(double) * 3 * (size_t)n);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double gg[3] = {0, 0, 0}, e = 0, s = 0, m = 0;
+        for (int64_t q = R->rp[i]; q < R->rp[i + 1]; ++q) {
+            int64_t j = R->col[q];
+            double dx, dy, dz;
+            double r2 = sep2(R->x, i, j, R->L, R->hL, &dx, &dy, &dz);
+            double r = sqrt(r2);
+            double d = kappa * (0.5 * (R->d0[i] + R->d0[j]));
+            if (!(r < d)) continue;
+            double delta = 1.0 - r / d;
+            e += 0.25 * delta * delta;    /* each pair appears in two rows */
+            s += 0.5 * (delta * r / d);
+            if (delta > m) m = delta;
+            if (r > 0.0) {
+                double f = delta / (d * r);
+                gg[0] += f * dx; gg[1] += f * dy; gg[2] += f * dz;
+            }
+        }
+        R->g[3 * i] = gg[0]; R->g[3 * i + 1] = gg[1]; R->g[3 * i + 2] = gg[2];
+        re[3 * i] = e; re[3 * i + 1] = s; re[3 * i + 2] = m;
+    }
+    nsum_t E = {0, 0}, S = {0, 0};
+    double mx = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        nadd(&E, re[3 * i]);
+        nadd(&S, re[3 * i + 1]);
+        if (re[3 * i + 2] > mx) mx = re[3 * i + 2];
+    }
+    free(re);
+    *Eov = nval(&E);
+    *Sdrd = nval(&S);
+    *maxd = mx;
+}
+
+/* Rung parameters at the start of rung r, from kappa at that moment.
+ * Relative schedules scale mu so that the equilibrium summed overlap is
+ * mu~ N (from dE/dkappa = 0), and the step sizes by the current length and
+ * kappa scales; absolute schedules take the numbers as they are. */
+static void rung_start(const orc_sched *S, int r, double kappa, int64_t n,
+                       double sumd0, double d0min, double *mu, double *ex,
+                       double *ek)
+{
+    if (S->absolute) {
+        *mu = S->mu[r]; *ex = S->eta_x[r]; *ek = S->eta_k[r];
+    } else {
+        *mu = (S->mu[r] * (double)n) / (kappa * sumd0);
+        *ex = S->eta_x[r] * (kappa * d0min);
+        *ek = S->eta_k[r] * kappa;
+    }
+}
+
+/* One Adam update of parameter th with gradient g (Kingma and Ba 2015,
+ * Algorithm 1 with bias correction; b1t = beta1^t, b2t = beta2^t). */
+static inline double adam(double th, double g, double *m, double *v, double b1,
+                          double b2, double b1t, double b2t, double eta,
+                          double eps)
+{
+    *m = b1 * *m + (1.0 - b1) * g;
+    *v = b2 * *v + (1.0 - b2) * (g * g);
+    double mh = *m / (1.0 - b1t);
+    double vh = *v / (1.0 - b2t);
+    return th - eta * mh / (sqrt(vh) + eps);
+}
+
+/* The inflation run.  One iteration:
+ *   1. rebuild the list if the displacement / growth criterion failed;
+ *   2. evaluate the energy terms and gradients at (x_t, kappa_t);
+ *   3. in the final rung, stop if max delta < tol (state x_t is returned);
+ *   4. t += 1, Adam on every coordinate and on kappa, wrap positions;
+ *   5. decay the step sizes, advance the rung counter; at the end of a
+ *      rung start the next one (its mu and etas from the new kappa); at the
+ *      end of the final rung stop with status 1;
+ *   6. test the list validity for the next iteration.
+ * x (n x 3), kappa, m, v (n x 3), mk_vk[2] are in/out so a run can be split
+ * into calls; ctl holds the schedule position:
+ *   ctl[0] = t, ctl[1] = rung, ctl[2] = iterations done in the rung,
+ *   ctl[3] = 1 when the rung's parameters still have to be set.
+ * etas[0..2] = mu, eta_x, eta_k in force (in/out).
+ * max_iters bounds the number of iterations of this call (status 2 when hit).
+ * trace (may be NULL): per iteration (max delta, kappa, E_ov) up to trace_cap. */
+int orc_run(int64_t n, double *x, const double *d0, double L, double *kappa,
+            double *m, double *v, double *mk_vk, int64_t *ctl, double *etas,
+            const orc_params *P, const orc_sched *S, int64_t max_iters,
+            orc_result *res, double *trace, int64_t trace_cap)
+{
+    run_t R;
+    memset(&R, 0, sizeof R);
+    R.n = n; R.L = L; R.hL = 0.5 * L; R.d0 = d0; R.x = x; R.m = m; R.v = v;
+    R.xref = malloc(sizeof(double) * 3 * (size_t)n);
+    R.g = malloc(sizeof(double) * 3 * (size_t)n);
+    R.d0min = d0[0];
+    nsum_t sd = {0, 0};
+    for (int64_t i = 0; i < n; ++i) {
+        if (d0[i] < R.d0min) R.d0min = d0[i];
+        nadd(&sd, d0[i]);
+    }
+    R.sumd0 = nval(&sd);
+    const double b1 = P->beta1, b2 = P->beta2;
+    int64_t t = ctl[0];
+    int r = (int)ctl[1];
+    int64_t itr = ctl[2];
+    double mu = etas[0], ex = etas[1], ek = etas[2];
+    if (ctl[3]) {
+        rung_start(S, r, *kappa, n, R.sumd0, R.d0min, &mu, &ex, &ek);
+        ctl[3] = 0;
+    }
+    /* beta powers as repeated products (the same rounding on every side) */
+    double b1t = 1.0, b2t = 1.0;
+    for (int64_t k = 0; k < t; ++k) { b1t *= b1; b2t *= b2; }
+    double mk = mk_vk[0], vk = mk_vk[1];
+    int status = 2;
+    int need_build = 1;
+    double Eov = 0, Sdrd = 0, maxd = 0;
+    int64_t it;
+    for (it = 0; it < max_iters; ++it) {
+        if (need_build) run_rebuild(&R, *kappa, P);
+        run_grad(&R, *kappa, &Eov, &Sdrd, &maxd);
+        if (trace && it < trace_cap) {
+            trace[3 * it] = maxd; trace[3 * it + 1] = *kappa; trace[3 * it + 2] = Eov;
+        }
+        if (r == S->n_rungs - 1 && maxd < S->tol) { status = 0; break; }
+        double gk = Sdrd / *kappa - mu * R.sumd0;
+        t += 1;
+        b1t *= b1; b2t *= b2;
+#pragma omp parallel for schedule(static)
+        for (int64_t q = 0; q < 3 * n; ++q) {
+            double th = adam(x[q], R.g[q], &m[q], &v[q], b1, b2, b1t, b2t, ex,
+                             P->eps_x);
+            if (th < 0.0) th += L;
+            if (th >= L) th -= L;
+            x[q] = th;
+        }
+        *kappa = adam(*kappa, gk, &mk, &vk, b1, b2, b1t, b2t, ek, P->eps_k);
+        ex *= S->decay[r];
+        ek *= S->decay[r];
+        itr += 1;
+        if (itr >= S->budget[r]) {
+            if (r == S->n_rungs - 1) { status = 1; ++it; break; }
+            r += 1;
+            itr = 0;
+            rung_start(S, r, *kappa, n, R.sumd0, R.d0min, &mu, &ex, &ek);
+        }
+        /* list validity for the next iteration */
+        double lim = P->skin_s * R.kb * R.d0min;
+        double md2 = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            double dx = mimg(x[3 * i] - R.xref[3 * i], L, R.hL);
+            double dy = mimg(x[3 * i + 1] - R.xref[3 * i + 1], L, R.hL);
+            double dz = mimg(x[3 * i + 2] - R.xref[3 * i + 2], L, R.hL);
+            double d2 = (dx * dx + dy * dy) + dz * dz;
+            if (d2 > md2) md2 = d2;
+        }
+        need_build = (md2 > lim * lim) || (*kappa > (1.0 + P->skin_g) * R.kb);
+    }
+    ctl[0] = t; ctl[1] = r; ctl[2] = itr;
+    etas[0] = mu; etas[1] = ex; etas[2] = ek;
+    mk_vk[0] = mk; mk_vk[1] = vk;
+    if (res) {
+        res->iterations = it;
+        res->rebuilds = R.rebuilds;
+        res->status = status;
+        res->rung = r;
+        res->kappa = *kappa;
+        res->energy = Eov;
+        if (status != 0) {
+            /* state after the last step: evaluate it for the report */
+            run_rebuild(&R, *kappa, P);
+            run_grad(&R, *kappa, &Eov, &Sdrd, &maxd);
+            res->rebuilds = R.rebuilds;
+            res->energy = Eov;
+        }
+        res->max_overlap = maxd;
+        double kp = orc_shrink(n, x, d0, L, *kappa, R.np, R.pi, R.pj);
+        res->kappa_shrunk = kp;
+        res->phi = orc_phi(n, d0, L, kp);
+    }
+    free(R.xref); free(R.g); free(R.pi); free(R.pj); free(R.rp); free(R.col);
+    return status;
+}
+
+/* Timing helper for the CPU baseline: `iters` evaluations of gradient +
+ * Adam on a fixed list (no schedule logic, no rebuilds), in place. */
+double orc_time_iterations(int64_t n, double *x, const double *d0, double L,
+                           double kappa, double mu, double eta_x, double s,
+                           double g, int64_t iters, int64_t *np_out)
+{
+    run_t R;
+    memset(&R, 0, sizeof R);
+    R.n = n; R.L = L; R.hL = 0.5 * L; R.d0 = d0; R.x = x;
+    R.xref = malloc(sizeof(double) * 3 * (size_t)n);
+    R.g = malloc(sizeof(double) * 3 * (size_t)n);
+    double *m = calloc(3 * (size_t)n, sizeof(double));
+    double *v = calloc(3 * (size_t)n, sizeof(double));
+    R.d0min = d0[0];
+    for (int64_t i = 0; i < n; ++i) if (d0[i] < R.d0min) R.d0min = d0[i];
+    orc_params P = {0.9, 0.999, 1e-15, 1e-12, s, g};
+    run_rebuild(&R, kappa, &P);
+    if (np_out) *np_out = R.np;
+    double b1t = 1.0, b2t = 1.0, Eov, Sdrd, maxd;
+    double t0;
+#ifdef _OPENMP
+    t0 = omp_get_wtime();
+#else
+    t0 = 0;
+#endif
+    for (int64_t it = 0; it < iters; ++it) {
+        run_grad(&R, kappa, &Eov, &Sdrd, &maxd);
+        b1t *= 0.9; b2t *= 0.999;
+#pragma omp parallel for schedule(static)
+        for (int64_t q = 0; q < 3 * n; ++q) {
+            double th = adam(x[q], R.g[q], &m[q], &v[q], 0.9, 0.999, b1t, b2t,
+                             eta_x, P.eps_x);
+            if (th < 0.0) th += L;
+            if (th >= L) th -= L;
+            x[q] = th;
+        }
+        (void)mu;
+    }
+    double t1;
+#ifdef _OPENMP
+    t1 = omp_get_wtime();
+#else
+    t1 = 0;
+#endif
+    free(R.xref); free(R.g); free(R.pi); free(R.pj); free(R.rp); free(R.col);
+    free(m); free(v);
+    return t1 - t0;
+}
