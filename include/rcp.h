@@ -1,0 +1,262 @@
+/*
+ * rcp.h -- C ABI of the MI355X library for the Adam-based inflation protocol
+ * (random close packings of polydisperse spheres, 3-D periodic cube).
+ *
+ * The library keeps every per-particle array in device memory (FP64 SoA,
+ * Morton order inside; user order at this boundary) and runs every step of
+ * an inflation iteration in its own HIP kernels for gfx950.
+ *
+ * Problem statement (Sec. 1 and App. A of the paper): a list of N positive
+ * relative diameters D0_i, the spatial dimension and the domain (here a
+ * periodic cube of edge L).  Diameters are D_i = kappa D0_i with one global
+ * scale kappa.  The optimised energy is Eq. (energy):
+ *     E(x, kappa) = 1/2 sum_{i<j} (1 - r_ij/d_ij)^2 Theta(1 - r_ij/d_ij)
+ *                   - mu sum_i D_i,       d_ij = (D_i + D_j)/2,
+ * minimised jointly over positions and kappa with Adam, mu annealed through
+ * rungs whose length follows Eq. (trigger); the run stops in the final rung
+ * once the largest fractional overlap 1 - r/d is below a tolerance (5e-4 in
+ * App. A), after which kappa is reduced uniformly until no pair overlaps
+ * (Sec. 2, App. A).
+ *
+ * Conventions for every call:
+ *   - return value 0 on success, a negative RCP_E* code on failure; the
+ *     message of the last failure on the calling thread is rcp_last_error();
+ *   - positions at this boundary are row-major (n, 3) doubles in user order;
+ *   - host arrays are borrowed for the duration of the call and copied;
+ *   - device arrays given to *_dev calls are borrowed until the work queued
+ *     on the given stream has completed;
+ *   - a context is bound to one HIP stream and is not thread safe; distinct
+ *     contexts are independent;
+ *   - arguments are validated before any device work is queued.
+ */
+#ifndef RCP_H
+#define RCP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RCP_VERSION 1
+#define RCP_MAX_RUNGS 16
+
+/* error codes */
+#define RCP_OK 0
+#define RCP_EINVAL -1      /* bad argument: n <= 0, D0 <= 0 or not finite, dim != 3,
+                              non-cubic box, kappa <= 0, bad schedule              */
+#define RCP_EBOX -2        /* largest listing cutoff >= L/2 (a sphere would meet its
+                              own periodic image, Sec. 2)                          */
+#define RCP_ENOMEM -3      /* device or host allocation failed                    */
+#define RCP_EDEVICE -4     /* HIP runtime error (message has the HIP error string) */
+#define RCP_ENOTCONV -5    /* iteration cap of the final rung reached; the result
+                              struct is still filled                                */
+#define RCP_ENONFINITE -6  /* NaN or Inf in the energy or a gradient               */
+#define RCP_EPLACE -7      /* random sequential addition exceeded its attempts      */
+#define RCP_ESTATE -8      /* call not valid in the context's current state        */
+
+/* initial placement modes for rcp_pack_init */
+#define RCP_INIT_NONE 0     /* positions come later from rcp_set_state            */
+#define RCP_INIT_RSA 1      /* random sequential addition without overlap, largest
+                               sphere first (App. A: dilute, non-overlapping start) */
+#define RCP_INIT_UNIFORM 2  /* i.i.d. uniform positions, overlaps allowed         */
+
+typedef struct rcp_ctx rcp_ctx;
+
+/* Optimiser and neighbour-list parameters.  size must be sizeof(rcp_params).
+ *   beta1, beta2, eps_x, eps_k: Adam (Kingma and Ba) for positions and for
+ *     kappa; eps_x <= 0 selects 1e-12 / (kappa0 * max D0).
+ *   skin_s, skin_g: a pair is listed at scale kb when
+ *       r^2 < c^2,  c = kb ((1 + g)(D0_i + D0_j)/2 + 2 s D0_min),
+ *     and the list stays valid while every particle moved less than
+ *     s kb D0_min and kappa <= (1 + g) kb (App. A rebuilds on accumulated
+ *     displacement; the skin form is ours).
+ *   level_ratio_pow2: size classes are floor(log2(D0/D0_min) / p), p >= 1.
+ */
+typedef struct {
+    uint32_t size;
+    double beta1, beta2, eps_x, eps_k;
+    double skin_s, skin_g;
+    int32_t level_ratio_pow2;
+} rcp_params;
+
+/* Launch tuning (performance only; results do not depend on it except
+ * through summation order).  size must be sizeof(rcp_tuning).
+ *   heavy_threshold: rows with more listed partners than this are handled
+ *     one wavefront per row, the rest one thread per row;
+ *   graph_iters: iterations captured per HIP graph launch (1 = no graph);
+ *   heavy_blocks: blocks reserved per packing for heavy rows (0 = auto);
+ *   xcd_remap: 1 = map consecutive row blocks to the same XCD. */
+typedef struct {
+    uint32_t size;
+    int32_t heavy_threshold;
+    int32_t graph_iters;
+    int32_t heavy_blocks;
+    int32_t xcd_remap;
+} rcp_tuning;
+
+/* Annealing schedule: a table of rungs run in order (App. A).  Rung r lasts
+ * budget[r] iterations; the last rung is the final relaxation, where the
+ * stop test max delta < tol is applied before each update, and budget of the
+ * last rung is its iteration cap.  decay[r] multiplies both step sizes after
+ * every iteration of rung r.  When absolute == 0, at the start of rung r:
+ *     mu    = (mu[r] * N) / (kappa * sum D0)
+ *     eta_x = eta_x[r] * (kappa * D0_min)
+ *     eta_k = eta_k[r] * kappa
+ * with kappa its value at that moment; when absolute != 0 the three numbers
+ * are used as given.  size must be sizeof(rcp_schedule). */
+typedef struct {
+    uint32_t size;
+    int32_t n_rungs;
+    int32_t absolute;
+    double tol;
+    double mu[RCP_MAX_RUNGS];
+    double eta_x[RCP_MAX_RUNGS];
+    double eta_k[RCP_MAX_RUNGS];
+    double decay[RCP_MAX_RUNGS];
+    int64_t budget[RCP_MAX_RUNGS];
+} rcp_schedule;
+
+/* Energy terms at the current state (rcp_energy_grad). */
+typedef struct {
+    double E_overlap;      /* 1/2 sum delta^2 over overlapping pairs          */
+    double E_growth;       /* -mu kappa sum D0                                 */
+    double dE_dkappa_overlap;  /* sum delta r / (kappa d)                      */
+    double dE_dkappa_growth;   /* -mu sum D0                                   */
+    double max_overlap;    /* max fractional overlap 1 - r/d (0 if none)       */
+    int64_t n_overlap;     /* number of overlapping pairs                      */
+} rcp_energy;
+
+/* Outcome of an inflation run (per packing). */
+typedef struct {
+    double phi;                 /* volume fraction after shrink to contact     */
+    double kappa;               /* kappa' after shrink                          */
+    double kappa_before_shrink;
+    double max_overlap;         /* at the returned (pre-shrink) state           */
+    double energy;              /* overlap energy at the returned state         */
+    int64_t iterations;         /* Adam updates taken                           */
+    int64_t rebuilds;           /* neighbour-list builds                        */
+    int32_t status;             /* 0 converged, RCP_ENOTCONV, RCP_ENONFINITE,
+                                   1 = stopped by max_iters                     */
+    int32_t rung;               /* rung index at return                          */
+} rcp_result;
+
+/* Timing and counters accumulated by a context (HIP events on its stream). */
+typedef struct {
+    int64_t iterations;         /* iterations executed (all packings, summed)  */
+    int64_t particle_updates;   /* sum over iterations of the packing's N      */
+    int64_t rebuilds;
+    int64_t graph_launches;
+    int64_t nnz;                /* listed partners (both directions) now        */
+    int64_t n_heavy;            /* rows handled one wavefront per row now       */
+    double iterate_ms;          /* time in iteration launches                   */
+    double rebuild_ms;          /* time in neighbour-list builds                */
+    double shrink_ms;
+} rcp_stats;
+
+int rcp_version(void);
+const char *rcp_last_error(void);
+void rcp_params_default(rcp_params *p);
+void rcp_tuning_default(rcp_tuning *t);
+
+/* Default rung table for a packing of n spheres in dimension dim, with the
+ * principal budget of Eq. (trigger), n_trig = ceil(4000 Y + X sqrt(n dim)
+ * - 2000), floored at n_min.  Returns RCP_EINVAL for n <= 0 or dim < 1. */
+int rcp_schedule_default(int64_t n, int dim, int Y, int X, int64_t n_min,
+                         rcp_schedule *out);
+
+/* Create a context for n_prob independent packings (1 for a plain solve;
+ * several for a batched census).  Packing k has n[k] spheres with relative
+ * diameters d0[k][0..n[k]) (host), cube edge box[k], starting scale
+ * kappa0[k] and placement seed seeds[k] (SplitMix64 counter stream, see
+ * rcp_pack_init).  dim must be 3.  stream is a hipStream_t (NULL: the
+ * library creates one).  Returns RCP_EBOX if a packing's largest cutoff
+ * is not below L/2. */
+int rcp_census_init(int dim, int n_prob, const int64_t *n,
+                    const double *const *d0, const double *box,
+                    const double *kappa0, const uint64_t *seeds, int init_mode,
+                    const rcp_params *params, void *stream, rcp_ctx **out);
+
+/* One packing: the n_prob = 1 case of rcp_census_init.  box points at dim
+ * edge lengths that must be equal.  Placement draws uniform numbers u =
+ * (SplitMix64(seed, ((i << 24) | attempt) * 4 + axis) >> 11) * 2^-53 and
+ * position u * L per axis (Steele, Lea and Flood 2014). */
+int rcp_pack_init(int dim, const double *box, int64_t n, const double *d0,
+                  double kappa0, uint64_t seed, int init_mode,
+                  const rcp_params *params, void *stream, rcp_ctx **out);
+
+int rcp_set_tuning(rcp_ctx *ctx, const rcp_tuning *t);
+
+/* Replace positions (row-major (n, 3), user order, wrapped into [0, L)) and
+ * kappa of packing k; host or device pointer.  Resets the Adam moments and
+ * the schedule position and marks the neighbour list stale. */
+int rcp_set_state(rcp_ctx *ctx, int k, const double *x, double kappa,
+                  int is_device);
+
+/* Copy positions (n, 3, user order), kappa and optionally the working
+ * diameters kappa D0 (n) of packing k to host memory. */
+int rcp_get_state(rcp_ctx *ctx, int k, double *x, double *kappa, double *diam);
+
+/* Build the neighbour list of packing k at its current (x, kappa), with
+ * kb = kappa.  n_pairs (may be NULL) receives the number of listed pairs
+ * (each counted once). */
+int rcp_neighbor_build(rcp_ctx *ctx, int k, int64_t *n_pairs);
+
+/* Canonical pair set of the current list of packing k: i < j in user
+ * indices, lexicographic.  Writes min(count, cap) pairs and sets *count. */
+int rcp_get_pairs(rcp_ctx *ctx, int k, int32_t *i, int32_t *j, int64_t cap,
+                  int64_t *count);
+
+/* Energy terms and gradient of Eq. (energy) at packing k's current state
+ * with the given mu; rebuilds the list first if it is not valid.  grad_x
+ * (n, 3, user order, host) may be NULL. */
+int rcp_energy_grad(rcp_ctx *ctx, int k, double mu, rcp_energy *e,
+                    double *grad_x);
+
+/* n_steps Adam updates of every packing with fixed mu, eta_x, eta_k
+ * (absolute numbers), the neighbour list rebuilt whenever its validity
+ * test fails.  Equivalent to rcp_inflate_run with a one-rung absolute
+ * schedule of budget n_steps and no stop test. */
+int rcp_adam_step(rcp_ctx *ctx, double mu, double eta_x, double eta_k,
+                  int64_t n_steps);
+
+/* Run the schedule (sched[k] for packing k, or sched[0] for all when
+ * per_packing == 0) until every packing has stopped, hit its cap, or
+ * max_iters iterations were taken (0: no limit); then shrink each packing
+ * to contact.  results has n_prob entries.  Returns 0, or RCP_ENOTCONV /
+ * RCP_ENONFINITE if any packing ended that way. */
+int rcp_inflate_run(rcp_ctx *ctx, const rcp_schedule *sched, int per_packing,
+                    int64_t max_iters, rcp_result *results);
+
+/* Census entry point: rcp_inflate_run over every packing of a context made
+ * by rcp_census_init, one launch per iteration for the whole batch. */
+int rcp_census_run(rcp_ctx *ctx, const rcp_schedule *sched, int per_packing,
+                   int64_t max_iters, rcp_result *results);
+
+/* Shrink to contact of packing k at its current state (Sec. 2, App. A):
+ * kappa' is the largest double <= kappa such that every listed pair has
+ * fl(fl(kappa' d0)^2) <= r^2 with d0 = (D0_i + D0_j)/2; phi is the volume
+ * fraction at kappa'. */
+int rcp_shrink(rcp_ctx *ctx, int k, double *kappa_shrunk, double *phi);
+
+/* Raw device entry points for torch.autograd.Function (packing 0).
+ * x_dev: (n, 3) row-major positions in user order on the device; the list
+ * is rebuilt at (x_dev, kappa) if it is not valid there (this synchronises
+ * the stream).  rcp_energy_dev writes E = E_overlap + E_growth to E_dev[0]
+ * and max overlap to E_dev[1].  rcp_adjoint_dev writes dE/dx (n, 3, user
+ * order) to gx_dev and dE/dkappa to gk_dev[0]. */
+int rcp_energy_dev(rcp_ctx *ctx, const double *x_dev, double kappa, double mu,
+                   double *E_dev, void *stream);
+int rcp_adjoint_dev(rcp_ctx *ctx, const double *x_dev, double kappa, double mu,
+                    double *gx_dev, double *gk_dev, void *stream);
+
+int rcp_get_stats(rcp_ctx *ctx, rcp_stats *s);
+int rcp_reset_stats(rcp_ctx *ctx);
+int rcp_num_packings(rcp_ctx *ctx);
+int64_t rcp_num_particles(rcp_ctx *ctx, int k);
+void rcp_destroy(rcp_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RCP_H */

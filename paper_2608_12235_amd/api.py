@@ -1,0 +1,184 @@
+"""Python view of the C ABI: one Packing object per rcp_ctx (argument marshalling only)."""
+import ctypes as C
+
+import numpy as np
+
+from ._lib import (lib, check, Params, Tuning, Schedule, Energy, Result, Stats,
+                   RCP_INIT_NONE, RCP_INIT_RSA, RCP_INIT_UNIFORM, RcpError)
+
+_INIT = {"none": RCP_INIT_NONE, "rsa": RCP_INIT_RSA, "uniform": RCP_INIT_UNIFORM}
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def make_params(**kw):
+    p = Params()
+    lib().rcp_params_default(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def make_tuning(**kw):
+    t = Tuning()
+    lib().rcp_tuning_default(C.byref(t))
+    for k, v in kw.items():
+        if not hasattr(t, k):
+            raise KeyError(k)
+        setattr(t, k, v)
+    return t
+
+
+def default_schedule(n, dim=3, Y=2, X=9, n_min=5000):
+    s = Schedule()
+    check(lib().rcp_schedule_default(n, dim, Y, X, n_min, C.byref(s)))
+    return s
+
+
+def absolute_schedule(mu, eta_x, eta_k, n_steps, tol=-1.0):
+    s = Schedule()
+    s.size = C.sizeof(Schedule)
+    s.n_rungs, s.absolute, s.tol = 1, 1, tol
+    s.mu[0], s.eta_x[0], s.eta_k[0], s.decay[0], s.budget[0] = mu, eta_x, eta_k, 1.0, n_steps
+    return s
+
+
+def schedule_from_rungs(rungs, tol=5e-4, absolute=0):
+    """rungs: list of (mu, eta_x, eta_k, decay, budget)."""
+    s = Schedule()
+    s.size = C.sizeof(Schedule)
+    s.n_rungs, s.absolute, s.tol = len(rungs), absolute, tol
+    for r, (mu, ex, ek, dc, b) in enumerate(rungs):
+        s.mu[r], s.eta_x[r], s.eta_k[r], s.decay[r], s.budget[r] = mu, ex, ek, dc, int(b)
+    return s
+
+
+def _result_dict(r):
+    return {f: getattr(r, f) for f, _ in Result._fields_}
+
+
+class Packing:
+    """One or several independent periodic packings on the GPU (an rcp_ctx)."""
+
+    def __init__(self, d0, L, kappa0=1.0, seed=0, init="rsa", params=None, stream=None,
+                 tuning=None):
+        d0s = d0 if isinstance(d0, (list, tuple)) else [d0]
+        Ls = L if isinstance(L, (list, tuple, np.ndarray)) else [L]
+        P = len(d0s)
+        k0 = kappa0 if isinstance(kappa0, (list, tuple, np.ndarray)) else [kappa0] * P
+        seeds = seed if isinstance(seed, (list, tuple, np.ndarray)) else [seed] * P
+        self._d0 = [np.ascontiguousarray(a, np.float64) for a in d0s]
+        self.n = [a.shape[0] for a in self._d0]
+        self.L = [float(v) for v in Ls]
+        ns = (C.c_int64 * P)(*self.n)
+        ptrs = (C.POINTER(C.c_double) * P)(*[_dp(a) for a in self._d0])
+        box = (C.c_double * P)(*self.L)
+        kap = (C.c_double * P)(*[float(v) for v in k0])
+        sd = (C.c_uint64 * P)(*[int(v) for v in seeds])
+        self.params = params if params is not None else make_params()
+        h = C.c_void_p()
+        check(lib().rcp_census_init(3, P, ns, ptrs, box, kap, sd, _INIT[init],
+                                    C.byref(self.params), stream, C.byref(h)))
+        self._h = h
+        if tuning is not None:
+            self.set_tuning(tuning)
+
+    # ------------------------------------------------------------------
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def n_packings(self):
+        return len(self.n)
+
+    def close(self):
+        if self._h:
+            lib().rcp_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tuning(self, t):
+        check(lib().rcp_set_tuning(self._h, C.byref(t)))
+
+    def set_state(self, x, kappa, k=0):
+        x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
+        assert x.shape[0] == self.n[k]
+        check(lib().rcp_set_state(self._h, k, x.ctypes.data_as(C.c_void_p), float(kappa), 0))
+
+    def get_state(self, k=0, diameters=False):
+        x = np.empty((self.n[k], 3))
+        kap = C.c_double()
+        dm = np.empty(self.n[k]) if diameters else None
+        check(lib().rcp_get_state(self._h, k, _dp(x), C.byref(kap),
+                                  _dp(dm) if diameters else None))
+        return (x, kap.value, dm) if diameters else (x, kap.value)
+
+    def neighbor_build(self, k=0):
+        npairs = C.c_int64()
+        check(lib().rcp_neighbor_build(self._h, k, C.byref(npairs)))
+        return npairs.value
+
+    def pairs(self, k=0):
+        cnt = C.c_int64()
+        check(lib().rcp_get_pairs(self._h, k, None, None, 0, C.byref(cnt)))
+        m = cnt.value
+        pi = np.empty(max(m, 1), np.int32)
+        pj = np.empty(max(m, 1), np.int32)
+        check(lib().rcp_get_pairs(self._h, k, pi.ctypes.data_as(C.POINTER(C.c_int32)),
+                                  pj.ctypes.data_as(C.POINTER(C.c_int32)), m, C.byref(cnt)))
+        return pi[:m], pj[:m]
+
+    def energy_grad(self, mu=0.0, k=0, grad=True):
+        e = Energy()
+        g = np.empty((self.n[k], 3)) if grad else None
+        check(lib().rcp_energy_grad(self._h, k, float(mu), C.byref(e),
+                                    _dp(g) if grad else None))
+        out = {f: getattr(e, f) for f, _ in Energy._fields_}
+        out["g"] = g
+        return out
+
+    def adam_step(self, mu, eta_x, eta_k, n_steps):
+        check(lib().rcp_adam_step(self._h, float(mu), float(eta_x), float(eta_k), int(n_steps)))
+
+    def inflate_run(self, schedule=None, max_iters=0, allow_notconv=True):
+        P = self.n_packings
+        if schedule is None:
+            schedule = [default_schedule(n) for n in self.n]
+        per = isinstance(schedule, (list, tuple))
+        if per:
+            arr = (Schedule * P)(*schedule)
+            sp = C.cast(arr, C.POINTER(Schedule))
+        else:
+            sp = C.byref(schedule)
+        res = (Result * P)()
+        rc = lib().rcp_inflate_run(self._h, sp, 1 if per else 0, int(max_iters), res)
+        if rc != 0 and not (allow_notconv and rc == -5):
+            check(rc)
+        return [_result_dict(r) for r in res]
+
+    def shrink(self, k=0):
+        kp, ph = C.c_double(), C.c_double()
+        check(lib().rcp_shrink(self._h, k, C.byref(kp), C.byref(ph)))
+        return kp.value, ph.value
+
+    def stats(self):
+        s = Stats()
+        check(lib().rcp_get_stats(self._h, C.byref(s)))
+        return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+    def reset_stats(self):
+        check(lib().rcp_reset_stats(self._h))
+
+
+__all__ = ["Packing", "make_params", "make_tuning", "default_schedule",
+           "absolute_schedule", "schedule_from_rungs", "RcpError"]

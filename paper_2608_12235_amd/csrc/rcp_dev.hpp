@@ -1,0 +1,143 @@
+// Device-side data layout and helpers shared by the HIP kernels.
+//
+// Every packing ("segment") owns its own FP64 SoA arrays in Morton order
+// (level-major: size class first, then the Morton code of the particle's
+// cell in its class grid).  A per-segment record in device memory holds the
+// array pointers (written by the host) and the optimiser / schedule state
+// (written by the device), so captured HIP graphs stay valid when arrays are
+// swapped or grown.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rcp {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kMaxRungs = 16;
+constexpr int kMaxLevels = 48;
+
+// segment flags (device-owned; the host clears REBUILD / HOLD / STALE)
+enum : int32_t {
+    F_STOP = 1,        // stop test met in the final rung
+    F_CAP = 2,         // final-rung iteration cap reached
+    F_REBUILD = 4,     // list validity test failed; host must rebuild
+    F_NONFINITE = 8,   // NaN / Inf met
+    F_HOLD = 16,       // iteration limit of the current call reached
+    F_STALE = 32,      // no valid list (host has to build one first)
+    F_IDLE = F_STOP | F_CAP | F_REBUILD | F_NONFINITE | F_HOLD | F_STALE,
+};
+
+struct SchedDev {
+    int32_t n_rungs, absolute;
+    double tol;
+    double mu[kMaxRungs], eta_x[kMaxRungs], eta_k[kMaxRungs], decay[kMaxRungs];
+    int64_t budget[kMaxRungs];
+};
+
+// Array pointers of one segment (host-owned; uploaded whole).
+struct SegPtrs {
+    double *x[2][3];      // ping-pong positions, SoA
+    double *d0;           // relative diameters
+    double *m[3], *v[3];  // Adam moments
+    double *xref[3];      // positions at the last list build
+    int32_t *orig;        // sorted index -> user index
+    uint8_t *lev;         // size class
+    int32_t *rp;          // row pointers (n + 1) into col
+    int32_t *col;         // partners (segment-local sorted indices)
+    int32_t *heavy;       // rows with more than heavy_T partners
+};
+
+// Scalars of one segment.  "host" fields are set by the host; the rest are
+// owned by the device once a run is under way.
+struct SegState {
+    // host: constants
+    int64_t n;
+    double L, hL, d0min, sumd0;
+    double beta1, beta2, eps_x, eps_k;
+    int32_t heavy_T;
+    int32_t nblocks;      // iteration-grid blocks of this segment
+    int64_t bfirst;       // first of them (index into the work table)
+    // set at each list build (k_after_build)
+    double kb, disp_lim2, kappa_lim;
+    int32_t hcnt, pad0;
+    // optimiser and schedule state
+    double kappa, mk, vk, b1t, b2t, mu, eta_x, eta_k;
+    int64_t t, it_rung, iters, iter_limit;
+    int32_t rung, flags, cur, pad1;
+    // outputs of the last evaluation
+    double E_ov, S_drd, max_delta, max_disp2;
+    uint32_t ticket, pad2;
+    SchedDev sched;
+};
+
+// One block of the iteration grid.
+struct WorkItem {
+    int32_t seg;
+    int32_t kind;         // 0: rows [begin, end) one thread per row;
+                          // 1: heavy rows, block `begin` of `end` heavy blocks
+    int64_t begin, end;
+};
+
+// ------------------------------------------------------------------ math
+// Minimum image of a separation of two coordinates in [0, L): one box
+// length is removed when the separation exceeds half a box; exactly at
+// +-L/2 no shift is applied.
+__device__ __forceinline__ double min_image(double d, double L, double hL)
+{
+    return d > hL ? d - L : (d < -hL ? d + L : d);
+}
+
+// ------------------------------------------------------------ reductions
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Morton interleave of three 19-bit cell coordinates (57 bits).
+__device__ __host__ __forceinline__ uint64_t spread3(uint64_t v)
+{
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+__device__ __host__ __forceinline__ uint64_t morton3(uint64_t cx, uint64_t cy, uint64_t cz)
+{
+    return spread3(cx) | (spread3(cy) << 1) | (spread3(cz) << 2);
+}
+
+__device__ __forceinline__ uint64_t hash64(uint64_t k)
+{
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ull;
+    k ^= k >> 33;
+    return k;
+}
+
+constexpr uint64_t kEmptyKey = ~0ull;
+
+}  // namespace rcp

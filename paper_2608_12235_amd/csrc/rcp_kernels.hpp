@@ -1,0 +1,116 @@
+// Host-callable launchers of the HIP kernels (internal to the library).
+#pragma once
+#include "rcp_dev.hpp"
+
+namespace rcp {
+
+// ------------------------------------------------------------ k_sort.hip
+// Exclusive scan of n u32 counts into out[0..n]; out[n] and *total get the
+// sum.  tile_tmp needs ceil(n / 2048) entries.  in may equal out.
+void scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tile_tmp,
+                    uint32_t *total, hipStream_t s);
+// Stable LSD radix sort on the low nbits of the keys; returns 0 if the
+// result is in (k0, v0), 1 if in (k1, v1).  hist needs 256 * ceil(n/2048)
+// + 1 entries.
+int radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, int nbits,
+               uint32_t *hist, uint32_t *tile_tmp, uint32_t *total, hipStream_t s);
+
+// -------------------------------------------------------- k_neighbor.hip
+struct LevelGrid {
+    double w;        // cell width (L / nc)
+    int32_t nc;      // cells per axis
+    int32_t count;   // particles in the class
+};
+
+// Everything one segment's list build needs, passed by value.
+struct BuildArgs {
+    int64_t n;
+    int32_t nlev, mb;       // classes; Morton bits below the class field
+    double L, hL, kb, opg, sk2;
+    const double *x, *y, *z, *d0;
+    const uint8_t *lev;
+    const uint64_t *skey;   // sorted keys (after the sort)
+    uint64_t *hkey;         // hash table of occupied cells
+    int2 *hval;             // (first particle, count)
+    uint64_t hmask;
+    LevelGrid lv[kMaxLevels];
+};
+
+void launch_keys(const BuildArgs &a, uint64_t *keys, uint32_t *vals, hipStream_t s);
+
+struct PermArgs {
+    int64_t n;
+    const uint32_t *perm;
+    const double *xs[3];
+    double *xd[3];
+    double *xref[3];
+    const double *d0s; double *d0d;
+    const double *ms[3]; double *md[3];
+    const double *vs[3]; double *vd[3];
+    const int32_t *os; int32_t *od;
+    const uint8_t *ls; uint8_t *ld;
+};
+void launch_permute(const PermArgs &p, hipStream_t s);
+
+void launch_hash_build(const BuildArgs &a, int64_t cap, hipStream_t s);
+// fill == 0: cnt[i] = number of half partners; fill == 1: partners written
+// at col[ptr[i]..]
+void launch_half(const BuildArgs &a, uint32_t *cnt, const uint32_t *ptr, int32_t *col,
+                 int fill, hipStream_t s);
+void launch_in_count(int64_t n, const uint32_t *hp, const int32_t *hcol, uint32_t *in_cnt,
+                     hipStream_t s);
+void launch_pair_keys(int64_t n, const uint32_t *hp, const int32_t *hcol, uint64_t *keys,
+                      uint32_t *vals, hipStream_t s);
+void launch_add_counts(int64_t n, const uint32_t *hp, const uint32_t *in_cnt, uint32_t *out,
+                       hipStream_t s);
+void launch_full_fill(int64_t n, const uint32_t *hp, const int32_t *hcol, const uint32_t *ip,
+                      const uint32_t *src, const uint32_t *rp, int32_t *col, hipStream_t s);
+void launch_heavy_mark(int64_t n, const uint32_t *rp, int32_t T, uint32_t *flag,
+                       hipStream_t s);
+void launch_heavy_compact(int64_t n, const uint32_t *flag, const uint32_t *pos,
+                          int32_t *heavy, hipStream_t s);
+void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
+void launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
+
+// -------------------------------------------------------- k_iterate.hip
+// flags bit 0: XCD-aware block order; bit 1: the last block of each packing
+// runs its tail (otherwise launch_tail must follow).
+void launch_iterate(const SegPtrs *P, SegState *S, const WorkItem *W, double *partials,
+                    int nitems, int flags, hipStream_t s);
+void launch_tail(SegState *S, const double *partials, int nseg, hipStream_t s);
+// After a list build of segment seg: kb, validity limits, current buffer,
+// heavy count (read from hcnt_dev), clear REBUILD / STALE.
+void launch_after_build(SegState *S, int seg, double kb, double disp_lim2, double kappa_lim,
+                        int cur, const uint32_t *hcnt_dev, hipStream_t s);
+// Start a schedule on segment seg: copy the table, reset the position in it,
+// set the first rung's parameters from the current kappa.
+void launch_sched_start(SegState *S, int seg, const SchedDev &q, int reset_adam,
+                        int64_t iter_limit, hipStream_t s);
+void launch_set_flags(SegState *S, int seg, int32_t clear, int32_t set, hipStream_t s);
+
+// Energy terms / gradient of one segment at positions given in user order
+// (xu, n x 3 row-major, device) or at its current state (xu == nullptr).
+struct EvalOut {
+    double *part;     // per-block partials: E_ov, S_drd, max delta, n_overlap
+    double *gu;       // dE/dx in user order (n x 3) or nullptr
+};
+void launch_eval(const SegPtrs *P, const SegState *S, int seg, int64_t n, const double *xu,
+                 double kappa, const EvalOut &o, int nblocks, hipStream_t s);
+// Final reduction of launch_eval partials into out[0..5]: E_ov, E_growth,
+// gk_ov, gk_growth, max delta, n_overlap (mu and sum D0 given).
+void launch_eval_finish(const double *part, int nblocks, double kappa, double mu,
+                        const SegState *S, int seg, double *out, hipStream_t s);
+// Max displacement^2 of xu (user order, n x 3) against the list's xref.
+void launch_disp(const SegPtrs *P, const SegState *S, int seg, int64_t n, const double *xu,
+                 double *part, int nblocks, hipStream_t s);
+// Gather user-order positions xu (n x 3) into the current SoA buffer.
+void launch_set_positions(const SegPtrs *P, SegState *S, int seg, int64_t n, const double *xu,
+                          int cur, hipStream_t s);
+// Shrink to contact: per-block minima of the pair contact scales in
+// part[0..nblocks), their minimum in part[nblocks].
+void launch_shrink(const SegPtrs *P, const SegState *S, int seg, int64_t n, double *part,
+                   int nblocks, hipStream_t s);
+// out[0] = max of part[0..nblocks)
+void launch_max_finish(const double *part, int nblocks, double *out, hipStream_t s);
+
+}  // namespace rcp

@@ -1,0 +1,1238 @@
+// Host runtime of the library: contexts, buffers, the neighbour-list build
+// pipeline, the iteration loop (HIP graphs of K iterations, one status read
+// per graph), shrink to contact, and the C ABI of include/rcp.h.
+#include "rcp.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rcp_kernels.hpp"
+
+namespace rcp {
+double uniform01(uint64_t seed, uint64_t i, uint64_t attempt, int axis);
+void place_uniform(int64_t n, double L, uint64_t seed, double *x);
+int place_rsa(int64_t n, const double *d0, double L, double kappa0, uint64_t seed,
+              int64_t max_attempts, double *x);
+}  // namespace rcp
+
+using namespace rcp;
+
+// ------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(call)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(RCP_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));  \
+    } while (0)
+
+#define CHK(call)                    \
+    do {                             \
+        int rc_ = (call);            \
+        if (rc_ != RCP_OK) return rc_; \
+    } while (0)
+
+template <class T>
+static int dalloc(T **p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(RCP_ENOMEM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T),
+                    hipGetErrorString(e));
+    }
+    return RCP_OK;
+}
+
+template <class T>
+static void dfree(T *&p)
+{
+    if (p) (void)hipFree((void *)p);
+    p = nullptr;
+}
+
+// grow a device buffer to at least `need` elements (contents discarded)
+template <class T>
+static int dgrow(T **p, int64_t *cap, int64_t need)
+{
+    if (need <= *cap && *p) return RCP_OK;
+    int64_t c = std::max<int64_t>(need + need / 4, 1024);
+    dfree(*p);
+    CHK(dalloc(p, (size_t)c));
+    *cap = c;
+    return RCP_OK;
+}
+
+// ------------------------------------------------------------ context
+struct Seg {
+    int64_t n = 0;
+    double L = 0, d0min = 0, d0max = 0, sumd0 = 0, sumd03 = 0, kappa0 = 1;
+    uint64_t seed = 0;
+    int nlev = 1;
+    std::vector<double> dmax_upto;   // max D0 over classes <= l
+    std::vector<int64_t> lev_count;
+    // device arrays; D0, M, V, ORIG, LEV are double-buffered for the
+    // Morton permutation (live set `set`), positions ping-pong through X
+    double *X[2][3] = {};
+    double *D0[2] = {};
+    double *M[2][3] = {}, *V[2][3] = {};
+    int32_t *ORIG[2] = {};
+    uint8_t *LEV[2] = {};
+    double *XREF[3] = {};
+    int32_t *rp = nullptr, *col = nullptr, *heavy = nullptr;
+    int64_t col_cap = 0;
+    int set = 0;
+    int cur = 0;          // host copy of the live position buffer
+    int64_t npairs = 0, nnz = 0, hcnt = 0;
+    int heavy_blocks = 1, light_blocks = 0;
+    int64_t rebuilds = 0;
+    bool built = false;
+};
+
+struct rcp_ctx {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    rcp_params params{};
+    rcp_tuning tuning{};
+    std::vector<Seg> segs;
+    SegPtrs *d_ptrs = nullptr;
+    SegState *d_state = nullptr;
+    SegState *h_state = nullptr;    // pinned mirror of d_state
+    WorkItem *d_work = nullptr;
+    int nitems = 0;
+    double *d_partials = nullptr;
+    // build scratch, shared by all segments
+    uint64_t *kA = nullptr, *kB = nullptr;
+    uint32_t *vA = nullptr, *vB = nullptr;
+    int64_t kcap = 0, kcapB = 0, vcap = 0, vcapB = 0;
+    uint32_t *hist = nullptr, *tiles = nullptr, *totals = nullptr;
+    int64_t hist_cap = 0, tiles_cap = 0;
+    uint32_t *c0 = nullptr, *c1 = nullptr, *c2 = nullptr, *c3 = nullptr;
+    int64_t c0cap = 0, c1cap = 0, c2cap = 0, c3cap = 0;
+    int32_t *hcol = nullptr;
+    int64_t hcol_cap = 0;
+    uint64_t *hkey = nullptr;
+    int2 *hval = nullptr;
+    int64_t hkcap = 0, hvcap = 0;
+    double *part = nullptr;          // evaluation partials
+    int64_t part_cap = 0;
+    double *out = nullptr;           // small device results
+    double *xtmp = nullptr;          // staging of user-order positions
+    int64_t xtmp_cap = 0;
+    double *h_out = nullptr;         // pinned small results
+    // iteration graph
+    hipGraphExec_t gexec = nullptr;
+    int graph_k = 0;
+    bool graph_valid = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    rcp_stats stats{};
+};
+
+static void ptrs_of(const Seg &s, SegPtrs &p)
+{
+    for (int b = 0; b < 2; ++b)
+        for (int a = 0; a < 3; ++a) p.x[b][a] = s.X[b][a];
+    p.d0 = s.D0[s.set];
+    for (int a = 0; a < 3; ++a) {
+        p.m[a] = s.M[s.set][a];
+        p.v[a] = s.V[s.set][a];
+        p.xref[a] = s.XREF[a];
+    }
+    p.orig = s.ORIG[s.set];
+    p.lev = s.LEV[s.set];
+    p.rp = s.rp;
+    p.col = s.col;
+    p.heavy = s.heavy;
+}
+
+static int upload_ptrs(rcp_ctx *c, int k)
+{
+    SegPtrs p;
+    ptrs_of(c->segs[k], p);
+    HIPCHK(hipMemcpyAsync(c->d_ptrs + k, &p, sizeof p, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return RCP_OK;
+}
+
+static int pull_state(rcp_ctx *c)
+{
+    HIPCHK(hipMemcpyAsync(c->h_state, c->d_state, sizeof(SegState) * c->segs.size(),
+                          hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (size_t k = 0; k < c->segs.size(); ++k) c->segs[k].cur = c->h_state[k].cur;
+    return RCP_OK;
+}
+
+// write one host-owned field group of a segment's device record
+template <class T>
+static int put_field(rcp_ctx *c, int k, size_t offset, const T &v)
+{
+    HIPCHK(hipMemcpyAsync((char *)(c->d_state + k) + offset, &v, sizeof(T),
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return RCP_OK;
+}
+
+// ------------------------------------------------------------ work table
+static int auto_heavy_blocks(const rcp_ctx *c, const Seg &s)
+{
+    if (c->tuning.heavy_blocks > 0) return c->tuning.heavy_blocks;
+    // two heavy rows per wavefront on average, at least one block
+    int64_t hb = (s.hcnt + 2 * kWavesPerBlock - 1) / (2 * kWavesPerBlock);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(hb, 2048));
+}
+
+static int build_work(rcp_ctx *c)
+{
+    std::vector<WorkItem> items;
+    for (size_t k = 0; k < c->segs.size(); ++k) {
+        Seg &s = c->segs[k];
+        const int64_t first = (int64_t)items.size();
+        s.light_blocks = (int)((s.n + kBlock - 1) / kBlock);
+        for (int64_t b = 0; b < s.light_blocks; ++b) {
+            WorkItem w;
+            w.seg = (int)k;
+            w.kind = 0;
+            w.begin = b * kBlock;
+            w.end = std::min<int64_t>(s.n, (b + 1) * kBlock);
+            items.push_back(w);
+        }
+        s.heavy_blocks = auto_heavy_blocks(c, s);
+        for (int b = 0; b < s.heavy_blocks; ++b) {
+            WorkItem w;
+            w.seg = (int)k;
+            w.kind = 1;
+            w.begin = b;
+            w.end = s.heavy_blocks;
+            items.push_back(w);
+        }
+        const int32_t nb = (int32_t)(items.size() - first);
+        CHK(put_field(c, (int)k, offsetof(SegState, nblocks), nb));
+        CHK(put_field(c, (int)k, offsetof(SegState, bfirst), first));
+    }
+    if ((int)items.size() > c->nitems) {
+        dfree(c->d_work);
+        dfree(c->d_partials);
+        CHK(dalloc(&c->d_work, items.size()));
+        CHK(dalloc(&c->d_partials, 4 * items.size()));
+    }
+    c->nitems = (int)items.size();
+    HIPCHK(hipMemcpyAsync(c->d_work, items.data(), sizeof(WorkItem) * items.size(),
+                          hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->graph_valid = false;
+    return RCP_OK;
+}
+
+// ------------------------------------------------------------ list build
+static int bits_for(int64_t v)   // bits needed to hold values 0..v
+{
+    int b = 0;
+    while (v > 0) {
+        ++b;
+        v >>= 1;
+    }
+    return b;
+}
+
+// Build the list of segment k at its current positions with kb = kappa.
+static int rebuild(rcp_ctx *c, int k, double kappa)
+{
+    Seg &s = c->segs[k];
+    hipStream_t st = c->stream;
+    const int64_t n = s.n;
+    const double g = c->params.skin_g, sk = c->params.skin_s;
+    const double opg = 1.0 + g, sk2 = (2.0 * sk) * s.d0min;
+    // largest cutoff must stay below half the box (minimum image)
+    const double cmax = kappa * (opg * s.d0max + sk2);
+    if (!(cmax < 0.5 * s.L))
+        return fail(RCP_EBOX, "packing %d: listing cutoff %.17g is not below L/2 = %.17g", k,
+                    cmax, 0.5 * s.L);
+    HIPCHK(hipEventRecord(c->e0, st));
+
+    BuildArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.n = n;
+    a.nlev = s.nlev;
+    a.L = s.L;
+    a.hL = 0.5 * s.L;
+    a.kb = kappa;
+    a.opg = opg;
+    a.sk2 = sk2;
+    int maxbits = 1;
+    for (int l = 0; l < s.nlev; ++l) {
+        const double h = kappa * (opg * s.dmax_upto[l] + sk2) * (1.0 + 1e-12);
+        int64_t nc = (int64_t)std::floor(s.L / h);
+        nc = std::max<int64_t>(1, std::min<int64_t>(nc, (int64_t)1 << 19));
+        a.lv[l].nc = (int32_t)nc;
+        a.lv[l].w = s.L / (double)nc;
+        a.lv[l].count = (int32_t)s.lev_count[l];
+        maxbits = std::max(maxbits, bits_for(nc - 1));
+    }
+    a.mb = 3 * maxbits;
+    const int nbits = a.mb + bits_for(s.nlev - 1);
+
+    // scratch sized for the particle count (pairs are sized below)
+    CHK(dgrow(&c->kA, &c->kcap, n));
+    CHK(dgrow(&c->kB, &c->kcapB, n));
+    CHK(dgrow(&c->vA, &c->vcap, n));
+    CHK(dgrow(&c->vB, &c->vcapB, n));
+    const int64_t tiles = (n + 2047) / 2048 + 1;
+    CHK(dgrow(&c->hist, &c->hist_cap, 256 * tiles + 1));
+    CHK(dgrow(&c->tiles, &c->tiles_cap, 256 * tiles + 1));
+    CHK(dgrow(&c->c0, &c->c0cap, n + 1));
+    CHK(dgrow(&c->c1, &c->c1cap, n + 1));
+    CHK(dgrow(&c->c2, &c->c2cap, n + 1));
+    CHK(dgrow(&c->c3, &c->c3cap, n + 1));
+    int64_t hcap = 64;
+    while (hcap < 2 * n) hcap <<= 1;
+    CHK(dgrow(&c->hkey, &c->hkcap, hcap));
+    CHK(dgrow(&c->hval, &c->hvcap, hcap));
+
+    // 1. keys at the current positions, stable sort, permutation
+    const int cur = s.cur, ncur = cur ^ 1, set = s.set, nset = set ^ 1;
+    a.x = s.X[cur][0];
+    a.y = s.X[cur][1];
+    a.z = s.X[cur][2];
+    a.d0 = s.D0[set];
+    a.lev = s.LEV[set];
+    launch_keys(a, c->kA, c->vA, st);
+    const int par = radix_sort(c->kA, c->vA, c->kB, c->vB, n, nbits, c->hist, c->tiles,
+                               c->totals, st);
+    const uint64_t *skey = par ? c->kB : c->kA;
+    const uint32_t *perm = par ? c->vB : c->vA;
+    PermArgs pa;
+    pa.n = n;
+    pa.perm = perm;
+    for (int ax = 0; ax < 3; ++ax) {
+        pa.xs[ax] = s.X[cur][ax];
+        pa.xd[ax] = s.X[ncur][ax];
+        pa.xref[ax] = s.XREF[ax];
+        pa.ms[ax] = s.M[set][ax];
+        pa.md[ax] = s.M[nset][ax];
+        pa.vs[ax] = s.V[set][ax];
+        pa.vd[ax] = s.V[nset][ax];
+    }
+    pa.d0s = s.D0[set];
+    pa.d0d = s.D0[nset];
+    pa.os = s.ORIG[set];
+    pa.od = s.ORIG[nset];
+    pa.ls = s.LEV[set];
+    pa.ld = s.LEV[nset];
+    launch_permute(pa, st);
+    s.set = nset;
+    s.cur = ncur;
+
+    // 2. occupied-cell hash on the sorted keys
+    a.x = s.X[ncur][0];
+    a.y = s.X[ncur][1];
+    a.z = s.X[ncur][2];
+    a.d0 = s.D0[nset];
+    a.lev = s.LEV[nset];
+    a.skey = skey;
+    a.hkey = c->hkey;
+    a.hval = c->hval;
+    a.hmask = (uint64_t)hcap - 1;
+    launch_hash_build(a, hcap, st);
+
+    // 3. half partners: count, scan, fill
+    launch_half(a, c->c0, nullptr, nullptr, 0, st);
+    scan_exclusive(c->c0, c->c1, n, c->tiles, c->totals, st);
+    uint32_t tot = 0;
+    HIPCHK(hipMemcpyAsync(&tot, c->totals, sizeof tot, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const int64_t P = tot;
+    if (2 * P >= (int64_t)INT32_MAX) return fail(RCP_ENOMEM, "pair count %lld too large", (long long)P);
+    CHK(dgrow(&c->hcol, &c->hcol_cap, P));
+    CHK(dgrow(&c->kA, &c->kcap, std::max<int64_t>(P, n)));
+    CHK(dgrow(&c->kB, &c->kcapB, std::max<int64_t>(P, n)));
+    CHK(dgrow(&c->vA, &c->vcap, std::max<int64_t>(P, n)));
+    CHK(dgrow(&c->vB, &c->vcapB, std::max<int64_t>(P, n)));
+    const int64_t ptiles = (P + 2047) / 2048 + 1;
+    CHK(dgrow(&c->hist, &c->hist_cap, 256 * ptiles + 1));
+    CHK(dgrow(&c->tiles, &c->tiles_cap, 256 * ptiles + 1));
+    if (2 * P > s.col_cap) {
+        dfree(s.col);
+        s.col_cap = std::max<int64_t>(2 * P + P / 2, 1024);
+        CHK(dalloc(&s.col, (size_t)s.col_cap));
+    }
+    launch_half(a, nullptr, c->c1, c->hcol, 1, st);
+
+    // 4. transpose: in-degrees, partners sorted by target (stable), full rows
+    launch_fill_u32(c->c2, n, 0u, st);
+    launch_in_count(n, c->c1, c->hcol, c->c2, st);
+    launch_pair_keys(n, c->c1, c->hcol, c->kA, c->vA, st);
+    const int pp = radix_sort(c->kA, c->vA, c->kB, c->vB, P, std::max(1, bits_for(n - 1)),
+                              c->hist, c->tiles, c->totals, st);
+    const uint32_t *src = pp ? c->vB : c->vA;
+    scan_exclusive(c->c2, c->c3, n, c->tiles, c->totals, st);          // in pointers
+    launch_add_counts(n, c->c1, c->c2, c->c0, st);                     // full counts
+    scan_exclusive(c->c0, (uint32_t *)s.rp, n, c->tiles, c->totals, st);
+    launch_full_fill(n, c->c1, c->hcol, c->c3, src, (const uint32_t *)s.rp, s.col, st);
+
+    // 5. heavy rows
+    launch_heavy_mark(n, (const uint32_t *)s.rp, c->tuning.heavy_threshold, c->c0, st);
+    scan_exclusive(c->c0, c->c2, n, c->tiles, c->totals + 1, st);
+    launch_heavy_compact(n, c->c0, c->c2, s.heavy, st);
+
+    const double lim = sk * kappa * s.d0min * (1.0 - 1e-9);
+    launch_after_build(c->d_state, k, kappa, lim * lim, opg * kappa * (1.0 - 1e-12), ncur,
+                       c->totals + 1, st);
+    HIPCHK(hipEventRecord(c->e1, st));
+    uint32_t hc = 0;
+    HIPCHK(hipMemcpyAsync(&hc, c->totals + 1, sizeof hc, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, c->e0, c->e1));
+    c->stats.rebuild_ms += ms;
+    c->stats.rebuilds += 1;
+    const int64_t old_hb = auto_heavy_blocks(c, s);
+    s.hcnt = hc;
+    s.npairs = P;
+    s.nnz = 2 * P;
+    s.rebuilds += 1;
+    s.built = true;
+    CHK(upload_ptrs(c, k));
+    // re-plan the heavy blocks when the heavy-row count moved a lot
+    const int64_t new_hb = auto_heavy_blocks(c, s);
+    if (new_hb > 2 * s.heavy_blocks || 4 * new_hb < s.heavy_blocks) CHK(build_work(c));
+    (void)old_hb;
+    return RCP_OK;
+}
+
+// ------------------------------------------------------------ iteration loop
+static int capture_graph(rcp_ctx *c, int K)
+{
+    if (c->gexec) {
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+    const int flags = (c->tuning.xcd_remap ? 1 : 0);
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+    for (int it = 0; it < K; ++it) {
+        launch_iterate(c->d_ptrs, c->d_state, c->d_work, c->d_partials, c->nitems, flags,
+                       c->stream);
+        launch_tail(c->d_state, c->d_partials, (int)c->segs.size(), c->stream);
+    }
+    HIPCHK(hipStreamEndCapture(c->stream, &g));
+    hipError_t e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(RCP_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    c->graph_k = K;
+    c->graph_valid = true;
+    return RCP_OK;
+}
+
+static bool seg_done(int32_t f)
+{
+    return (f & (F_STOP | F_CAP | F_NONFINITE | F_HOLD)) != 0;
+}
+
+// Iterate every packing until each is done (stop, cap, non-finite, limit).
+static int run_loop(rcp_ctx *c)
+{
+    const int K = std::max(1, c->tuning.graph_iters);
+    CHK(pull_state(c));
+    for (;;) {
+        bool any = false;
+        for (size_t k = 0; k < c->segs.size(); ++k) {
+            const int32_t f = c->h_state[k].flags;
+            if (seg_done(f)) continue;
+            if (f & (F_REBUILD | F_STALE)) {
+                CHK(rebuild(c, (int)k, c->h_state[k].kappa));
+            }
+            any = true;
+        }
+        if (!any) break;
+        int64_t before = 0;
+        for (size_t k = 0; k < c->segs.size(); ++k) before += c->h_state[k].iters;
+        HIPCHK(hipEventRecord(c->e0, c->stream));
+        if (K > 1) {
+            if (!c->graph_valid || c->graph_k != K) CHK(capture_graph(c, K));
+            HIPCHK(hipGraphLaunch(c->gexec, c->stream));
+            c->stats.graph_launches += 1;
+        } else {
+            launch_iterate(c->d_ptrs, c->d_state, c->d_work, c->d_partials, c->nitems,
+                           c->tuning.xcd_remap ? 1 : 0, c->stream);
+            launch_tail(c->d_state, c->d_partials, (int)c->segs.size(), c->stream);
+        }
+        HIPCHK(hipEventRecord(c->e1, c->stream));
+        std::vector<int64_t> prev(c->segs.size());
+        for (size_t k = 0; k < c->segs.size(); ++k) prev[k] = c->h_state[k].iters;
+        CHK(pull_state(c));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, c->e0, c->e1));
+        c->stats.iterate_ms += ms;
+        for (size_t k = 0; k < c->segs.size(); ++k) {
+            const int64_t d = c->h_state[k].iters - prev[k];
+            c->stats.iterations += d;
+            c->stats.particle_updates += d * c->segs[k].n;
+        }
+        (void)before;
+    }
+    return RCP_OK;
+}
+
+static int to_sched(const rcp_schedule *q, SchedDev &d)
+{
+    if (!q || q->size != sizeof(rcp_schedule)) return fail(RCP_EINVAL, "schedule: bad size field");
+    if (q->n_rungs < 1 || q->n_rungs > RCP_MAX_RUNGS)
+        return fail(RCP_EINVAL, "schedule: n_rungs %d out of [1, %d]", q->n_rungs, RCP_MAX_RUNGS);
+    std::memset(&d, 0, sizeof d);
+    d.n_rungs = q->n_rungs;
+    d.absolute = q->absolute;
+    d.tol = q->tol;
+    for (int r = 0; r < q->n_rungs; ++r) {
+        if (q->budget[r] < 1) return fail(RCP_EINVAL, "schedule: budget[%d] < 1", r);
+        if (!std::isfinite(q->mu[r]) || !(q->eta_x[r] >= 0) || !(q->eta_k[r] >= 0) ||
+            !(q->decay[r] > 0))
+            return fail(RCP_EINVAL, "schedule: rung %d has a bad value", r);
+        d.mu[r] = q->mu[r];
+        d.eta_x[r] = q->eta_x[r];
+        d.eta_k[r] = q->eta_k[r];
+        d.decay[r] = q->decay[r];
+        d.budget[r] = q->budget[r];
+    }
+    return RCP_OK;
+}
+
+static int reset_moments(rcp_ctx *c, int k)
+{
+    Seg &s = c->segs[k];
+    for (int a = 0; a < 3; ++a) {
+        launch_fill_f64(s.M[s.set][a], s.n, 0.0, c->stream);
+        launch_fill_f64(s.V[s.set][a], s.n, 0.0, c->stream);
+    }
+    return RCP_OK;
+}
+
+static int shrink_seg(rcp_ctx *c, int k, double *kp_out, double *phi_out)
+{
+    CHK(pull_state(c));
+    if (c->h_state[k].flags & (F_REBUILD | F_STALE)) CHK(rebuild(c, k, c->h_state[k].kappa));
+    Seg &s = c->segs[k];
+    const int nb = (int)std::max<int64_t>(1, (s.n + kBlock - 1) / kBlock);
+    CHK(dgrow(&c->part, &c->part_cap, 4 * (int64_t)nb + 8));
+    HIPCHK(hipEventRecord(c->e0, c->stream));
+    launch_shrink(c->d_ptrs, c->d_state, k, s.n, c->part, nb, c->stream);
+    HIPCHK(hipEventRecord(c->e1, c->stream));
+    double kmin = 0;
+    HIPCHK(hipMemcpyAsync(&kmin, c->part + nb, sizeof kmin, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, c->e0, c->e1));
+    c->stats.shrink_ms += ms;
+    const double kappa = c->h_state[k].kappa;
+    const double kp = std::min(kappa, kmin);
+    *kp_out = kp;
+    *phi_out = (M_PI / 6.0) * (kp * kp * kp) * s.sumd03 / (s.L * s.L * s.L);
+    return RCP_OK;
+}
+
+// ------------------------------------------------------------ creation
+static int validate_seg(int64_t n, const double *d0, double L, double kappa0)
+{
+    if (n <= 0) return fail(RCP_EINVAL, "n must be positive");
+    if (n >= (int64_t)1 << 30) return fail(RCP_EINVAL, "n too large");
+    if (!d0) return fail(RCP_EINVAL, "null diameter list");
+    if (!(L > 0) || !std::isfinite(L)) return fail(RCP_EINVAL, "box edge must be positive");
+    if (!(kappa0 > 0) || !std::isfinite(kappa0)) return fail(RCP_EINVAL, "kappa0 must be positive");
+    for (int64_t i = 0; i < n; ++i)
+        if (!(d0[i] > 0) || !std::isfinite(d0[i]))
+            return fail(RCP_EINVAL, "diameter %lld is not a positive finite number", (long long)i);
+    return RCP_OK;
+}
+
+static int seg_setup(rcp_ctx *c, int k, int64_t n, const double *d0, double L, double kappa0,
+                     uint64_t seed, int init_mode)
+{
+    Seg &s = c->segs[k];
+    s.n = n;
+    s.L = L;
+    s.kappa0 = kappa0;
+    s.seed = seed;
+    s.d0min = d0[0];
+    s.d0max = d0[0];
+    double sum = 0, cs = 0, sum3 = 0, cs3 = 0;   // Neumaier sums
+    auto nadd = [](double &acc, double &comp, double v) {
+        double t = acc + v;
+        if (std::fabs(acc) >= std::fabs(v)) comp += (acc - t) + v;
+        else comp += (v - t) + acc;
+        acc = t;
+    };
+    for (int64_t i = 0; i < n; ++i) {
+        s.d0min = std::min(s.d0min, d0[i]);
+        s.d0max = std::max(s.d0max, d0[i]);
+        nadd(sum, cs, d0[i]);
+        nadd(sum3, cs3, d0[i] * d0[i] * d0[i]);
+    }
+    s.sumd0 = sum + cs;
+    s.sumd03 = sum3 + cs3;
+    const double opg = 1.0 + c->params.skin_g, sk2 = (2.0 * c->params.skin_s) * s.d0min;
+    if (!(kappa0 * (opg * s.d0max + sk2) < 0.5 * L))
+        return fail(RCP_EBOX, "packing %d: listing cutoff at kappa0 is not below L/2", k);
+    // size classes
+    const int p = std::max(1, c->params.level_ratio_pow2);
+    std::vector<uint8_t> lev(n);
+    int nlev = 1;
+    for (int64_t i = 0; i < n; ++i) {
+        int e;
+        std::frexp(d0[i] / s.d0min, &e);
+        int l = std::max(0, e - 1) / p;
+        if (l >= kMaxLevels) return fail(RCP_EINVAL, "more than %d size classes", kMaxLevels);
+        lev[i] = (uint8_t)l;
+        nlev = std::max(nlev, l + 1);
+    }
+    s.nlev = nlev;
+    s.dmax_upto.assign(nlev, 0.0);
+    s.lev_count.assign(nlev, 0);
+    for (int64_t i = 0; i < n; ++i) {
+        s.dmax_upto[lev[i]] = std::max(s.dmax_upto[lev[i]], d0[i]);
+        s.lev_count[lev[i]]++;
+    }
+    for (int l = 1; l < nlev; ++l) s.dmax_upto[l] = std::max(s.dmax_upto[l], s.dmax_upto[l - 1]);
+    // placement
+    std::vector<double> x(3 * n, 0.0);
+    if (init_mode == RCP_INIT_RSA) {
+        if (place_rsa(n, d0, L, kappa0, seed, (int64_t)1 << 22, x.data()) != 0)
+            return fail(RCP_EPLACE, "packing %d: random sequential addition failed", k);
+    } else if (init_mode == RCP_INIT_UNIFORM) {
+        place_uniform(n, L, seed, x.data());
+    } else if (init_mode != RCP_INIT_NONE) {
+        return fail(RCP_EINVAL, "unknown init_mode %d", init_mode);
+    }
+    // device arrays
+    for (int b = 0; b < 2; ++b) {
+        for (int a = 0; a < 3; ++a) {
+            CHK(dalloc(&s.X[b][a], n));
+            CHK(dalloc(&s.M[b][a], n));
+            CHK(dalloc(&s.V[b][a], n));
+        }
+        CHK(dalloc(&s.D0[b], n));
+        CHK(dalloc(&s.ORIG[b], n));
+        CHK(dalloc(&s.LEV[b], n));
+    }
+    for (int a = 0; a < 3; ++a) CHK(dalloc(&s.XREF[a], n));
+    CHK(dalloc(&s.rp, n + 1));
+    CHK(dalloc(&s.heavy, n));
+    s.col_cap = std::max<int64_t>(8 * n, 1024);
+    CHK(dalloc(&s.col, s.col_cap));
+    std::vector<double> soa(n);
+    for (int a = 0; a < 3; ++a) {
+        for (int64_t i = 0; i < n; ++i) soa[i] = x[3 * i + a];
+        HIPCHK(hipMemcpy(s.X[0][a], soa.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(s.XREF[a], soa.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+        HIPCHK(hipMemset(s.M[0][a], 0, sizeof(double) * n));
+        HIPCHK(hipMemset(s.V[0][a], 0, sizeof(double) * n));
+    }
+    HIPCHK(hipMemcpy(s.D0[0], d0, sizeof(double) * n, hipMemcpyHostToDevice));
+    std::vector<int32_t> orig(n);
+    for (int64_t i = 0; i < n; ++i) orig[i] = (int32_t)i;
+    HIPCHK(hipMemcpy(s.ORIG[0], orig.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(s.LEV[0], lev.data(), n, hipMemcpyHostToDevice));
+    std::vector<int32_t> rp0(n + 1, 0);
+    HIPCHK(hipMemcpy(s.rp, rp0.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice));
+    s.set = 0;
+    s.cur = 0;
+    // state record
+    SegState st;
+    std::memset(&st, 0, sizeof st);
+    st.n = n;
+    st.L = L;
+    st.hL = 0.5 * L;
+    st.d0min = s.d0min;
+    st.sumd0 = s.sumd0;
+    st.beta1 = c->params.beta1;
+    st.beta2 = c->params.beta2;
+    st.eps_x = c->params.eps_x > 0 ? c->params.eps_x : 1e-12 / (kappa0 * s.d0max);
+    st.eps_k = c->params.eps_k;
+    st.heavy_T = c->tuning.heavy_threshold;
+    st.kappa = kappa0;
+    st.b1t = 1.0;
+    st.b2t = 1.0;
+    st.flags = F_STALE | F_HOLD;
+    st.cur = 0;
+    HIPCHK(hipMemcpy(c->d_state + k, &st, sizeof st, hipMemcpyHostToDevice));
+    SegPtrs pp;
+    ptrs_of(s, pp);
+    HIPCHK(hipMemcpy(c->d_ptrs + k, &pp, sizeof pp, hipMemcpyHostToDevice));
+    return RCP_OK;
+}
+
+static void destroy_ctx(rcp_ctx *c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    for (auto &s : c->segs) {
+        for (int b = 0; b < 2; ++b) {
+            for (int a = 0; a < 3; ++a) {
+                dfree(s.X[b][a]);
+                dfree(s.M[b][a]);
+                dfree(s.V[b][a]);
+            }
+            dfree(s.D0[b]);
+            dfree(s.ORIG[b]);
+            dfree(s.LEV[b]);
+        }
+        for (int a = 0; a < 3; ++a) dfree(s.XREF[a]);
+        dfree(s.rp);
+        dfree(s.col);
+        dfree(s.heavy);
+    }
+    dfree(c->d_ptrs);
+    dfree(c->d_state);
+    dfree(c->d_work);
+    dfree(c->d_partials);
+    dfree(c->kA);
+    dfree(c->kB);
+    dfree(c->vA);
+    dfree(c->vB);
+    dfree(c->hist);
+    dfree(c->tiles);
+    dfree(c->totals);
+    dfree(c->c0);
+    dfree(c->c1);
+    dfree(c->c2);
+    dfree(c->c3);
+    dfree(c->hcol);
+    dfree(c->hkey);
+    dfree(c->hval);
+    dfree(c->part);
+    dfree(c->out);
+    dfree(c->xtmp);
+    if (c->h_state) (void)hipHostFree(c->h_state);
+    if (c->h_out) (void)hipHostFree(c->h_out);
+    if (c->e0) (void)hipEventDestroy(c->e0);
+    if (c->e1) (void)hipEventDestroy(c->e1);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+// ------------------------------------------------------------ C ABI
+extern "C" {
+
+int rcp_version(void) { return RCP_VERSION; }
+
+const char *rcp_last_error(void) { return g_err.c_str(); }
+
+void rcp_params_default(rcp_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->size = sizeof(rcp_params);
+    p->beta1 = 0.9;
+    p->beta2 = 0.999;
+    p->eps_x = 0.0;
+    p->eps_k = 1e-12;
+    p->skin_s = 0.5;
+    p->skin_g = 0.02;
+    p->level_ratio_pow2 = 1;
+}
+
+void rcp_tuning_default(rcp_tuning *t)
+{
+    if (!t) return;
+    std::memset(t, 0, sizeof *t);
+    t->size = sizeof(rcp_tuning);
+    t->heavy_threshold = 48;
+    t->graph_iters = 16;
+    t->heavy_blocks = 0;
+    t->xcd_remap = 1;
+}
+
+// Default rung table (our reading of App. A; the paper does not list its
+// values): a densification rung at mu~ = 1e-2 for n_trig iterations, two
+// rungs at 1e-3 and 1e-4 (n_trig/4 each), two mu cycles 1e-3 <-> 1e-4
+// (n_trig/8 each) and the final relaxation at 1e-5 with a step-size
+// half-life of a quarter of its cap (cap 2 n_trig); stop tolerance 5e-4.
+int rcp_schedule_default(int64_t n, int dim, int Y, int X, int64_t n_min, rcp_schedule *out)
+{
+    if (!out || n <= 0 || dim < 1) return fail(RCP_EINVAL, "bad arguments to rcp_schedule_default");
+    std::memset(out, 0, sizeof *out);
+    out->size = sizeof(rcp_schedule);
+    const double nt_d = std::ceil(4000.0 * Y + X * std::sqrt((double)n * dim) - 2000.0);
+    const int64_t nt = std::max<int64_t>((int64_t)nt_d, n_min);
+    struct R { double mu, ex, ek, hl, bf; };
+    const R rungs[] = {
+        {1e-2, 1e-2, 1e-3, 0.0, 1.0},      {1e-3, 5e-3, 5e-4, 0.0, 0.25},
+        {1e-4, 2.5e-3, 2.5e-4, 0.0, 0.25}, {1e-3, 2.5e-3, 2.5e-4, 0.0, 0.125},
+        {1e-4, 2.5e-3, 2.5e-4, 0.0, 0.125}, {1e-3, 2.5e-3, 2.5e-4, 0.0, 0.125},
+        {1e-4, 2.5e-3, 2.5e-4, 0.0, 0.125}, {1e-5, 1.25e-3, 1.25e-4, 0.25, 2.0},
+    };
+    out->n_rungs = (int32_t)(sizeof rungs / sizeof rungs[0]);
+    out->absolute = 0;
+    out->tol = 5e-4;
+    for (int r = 0; r < out->n_rungs; ++r) {
+        out->mu[r] = rungs[r].mu;
+        out->eta_x[r] = rungs[r].ex;
+        out->eta_k[r] = rungs[r].ek;
+        out->budget[r] = std::max<int64_t>(1, (int64_t)std::ceil(rungs[r].bf * (double)nt));
+        out->decay[r] = rungs[r].hl <= 0 ? 1.0
+                                         : std::pow(2.0, -1.0 / (rungs[r].hl * (double)out->budget[r]));
+    }
+    return RCP_OK;
+}
+
+int rcp_census_init(int dim, int n_prob, const int64_t *n, const double *const *d0,
+                    const double *box, const double *kappa0, const uint64_t *seeds,
+                    int init_mode, const rcp_params *params, void *stream, rcp_ctx **out)
+{
+    if (!out) return fail(RCP_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (dim != 3) return fail(RCP_EINVAL, "only dim = 3 is implemented (got %d)", dim);
+    if (n_prob < 1 || !n || !d0 || !box || !kappa0 || !seeds)
+        return fail(RCP_EINVAL, "bad census arguments");
+    if (params && params->size != sizeof(rcp_params)) return fail(RCP_EINVAL, "rcp_params: bad size");
+    rcp_params P;
+    if (params) P = *params;
+    else rcp_params_default(&P);
+    if (!(P.beta1 >= 0 && P.beta1 < 1) || !(P.beta2 >= 0 && P.beta2 < 1) || !(P.skin_s >= 0) ||
+        !(P.skin_g >= 0) || !(P.eps_k > 0))
+        return fail(RCP_EINVAL, "bad rcp_params values");
+    for (int k = 0; k < n_prob; ++k) CHK(validate_seg(n[k], d0[k], box[k], kappa0[k]));
+    if (init_mode < RCP_INIT_NONE || init_mode > RCP_INIT_UNIFORM)
+        return fail(RCP_EINVAL, "unknown init_mode %d", init_mode);
+    rcp_ctx *c = new rcp_ctx();
+    c->params = P;
+    rcp_tuning_default(&c->tuning);
+    c->segs.resize(n_prob);
+    int rc = RCP_OK;
+    do {
+        hipError_t e;
+        if (stream) {
+            c->stream = (hipStream_t)stream;
+        } else {
+            e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+            if (e != hipSuccess) { rc = fail(RCP_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e)); break; }
+            c->own_stream = true;
+        }
+        if ((e = hipEventCreate(&c->e0)) != hipSuccess || (e = hipEventCreate(&c->e1)) != hipSuccess) {
+            rc = fail(RCP_EDEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+            break;
+        }
+        if ((rc = dalloc(&c->d_ptrs, n_prob)) != RCP_OK) break;
+        if ((rc = dalloc(&c->d_state, n_prob)) != RCP_OK) break;
+        if ((rc = dalloc(&c->totals, 16)) != RCP_OK) break;
+        if ((rc = dalloc(&c->out, 16)) != RCP_OK) break;
+        if ((e = hipHostMalloc((void **)&c->h_state, sizeof(SegState) * n_prob, 0)) != hipSuccess) {
+            rc = fail(RCP_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+            break;
+        }
+        if ((e = hipHostMalloc((void **)&c->h_out, sizeof(double) * 16, 0)) != hipSuccess) {
+            rc = fail(RCP_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+            break;
+        }
+        for (int k = 0; k < n_prob && rc == RCP_OK; ++k)
+            rc = seg_setup(c, k, n[k], d0[k], box[k], kappa0[k], seeds[k], init_mode);
+        if (rc != RCP_OK) break;
+        rc = build_work(c);
+    } while (0);
+    if (rc != RCP_OK) {
+        std::string msg = g_err;
+        destroy_ctx(c);
+        g_err = msg;
+        return rc;
+    }
+    *out = c;
+    return RCP_OK;
+}
+
+int rcp_pack_init(int dim, const double *box, int64_t n, const double *d0, double kappa0,
+                  uint64_t seed, int init_mode, const rcp_params *params, void *stream,
+                  rcp_ctx **out)
+{
+    if (dim != 3) return fail(RCP_EINVAL, "only dim = 3 is implemented (got %d)", dim);
+    if (!box) return fail(RCP_EINVAL, "null box");
+    for (int a = 1; a < dim; ++a)
+        if (box[a] != box[0]) return fail(RCP_EINVAL, "only cubic boxes are implemented");
+    const double *dl[1] = {d0};
+    const double L = box[0];
+    return rcp_census_init(dim, 1, &n, dl, &L, &kappa0, &seed, init_mode, params, stream, out);
+}
+
+int rcp_set_tuning(rcp_ctx *c, const rcp_tuning *t)
+{
+    if (!c || !t || t->size != sizeof(rcp_tuning)) return fail(RCP_EINVAL, "bad tuning");
+    if (t->heavy_threshold < 0 || t->graph_iters < 1 || t->heavy_blocks < 0)
+        return fail(RCP_EINVAL, "bad tuning values");
+    const bool replan = t->heavy_threshold != c->tuning.heavy_threshold ||
+                        t->heavy_blocks != c->tuning.heavy_blocks;
+    c->tuning = *t;
+    c->graph_valid = false;
+    if (replan) {
+        for (size_t k = 0; k < c->segs.size(); ++k) {
+            CHK(put_field(c, (int)k, offsetof(SegState, heavy_T), (int32_t)t->heavy_threshold));
+            launch_set_flags(c->d_state, (int)k, 0, F_STALE, c->stream);
+        }
+        CHK(build_work(c));
+    }
+    return RCP_OK;
+}
+
+static int check_k(rcp_ctx *c, int k)
+{
+    if (!c) return fail(RCP_EINVAL, "null context");
+    if (k < 0 || k >= (int)c->segs.size()) return fail(RCP_EINVAL, "packing index %d out of range", k);
+    return RCP_OK;
+}
+
+int rcp_set_state(rcp_ctx *c, int k, const double *x, double kappa, int is_device)
+{
+    CHK(check_k(c, k));
+    Seg &s = c->segs[k];
+    if (!x || !(kappa > 0) || !std::isfinite(kappa)) return fail(RCP_EINVAL, "bad state");
+    CHK(dgrow(&c->xtmp, &c->xtmp_cap, 3 * s.n));
+    CHK(pull_state(c));
+    if (is_device) {
+        HIPCHK(hipMemcpyAsync(c->xtmp, x, sizeof(double) * 3 * s.n, hipMemcpyDeviceToDevice,
+                              c->stream));
+    } else {
+        std::vector<double> w(x, x + 3 * s.n);
+        for (auto &v : w) {
+            if (!std::isfinite(v) || v < -s.L || v >= 2 * s.L)
+                return fail(RCP_EINVAL, "position outside [-L, 2L)");
+            if (v < 0) v += s.L;
+            if (v >= s.L) v -= s.L;
+        }
+        HIPCHK(hipMemcpyAsync(c->xtmp, w.data(), sizeof(double) * 3 * s.n,
+                              hipMemcpyHostToDevice, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    }
+    launch_set_positions(c->d_ptrs, c->d_state, k, s.n, c->xtmp, s.cur, c->stream);
+    CHK(reset_moments(c, k));
+    SegState st = c->h_state[k];
+    st.kappa = kappa;
+    st.t = 0;
+    st.b1t = 1.0;
+    st.b2t = 1.0;
+    st.mk = 0;
+    st.vk = 0;
+    st.it_rung = 0;
+    st.rung = 0;
+    st.iters = 0;
+    st.flags = F_STALE | F_HOLD;
+    HIPCHK(hipMemcpyAsync(c->d_state + k, &st, sizeof st, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    s.built = false;
+    return RCP_OK;
+}
+
+int rcp_get_state(rcp_ctx *c, int k, double *x, double *kappa, double *diam)
+{
+    CHK(check_k(c, k));
+    CHK(pull_state(c));
+    Seg &s = c->segs[k];
+    const int64_t n = s.n;
+    std::vector<double> a(n);
+    std::vector<int32_t> orig(n);
+    HIPCHK(hipMemcpy(orig.data(), s.ORIG[s.set], sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    if (x) {
+        for (int ax = 0; ax < 3; ++ax) {
+            HIPCHK(hipMemcpy(a.data(), s.X[s.cur][ax], sizeof(double) * n, hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < n; ++i) x[3 * (int64_t)orig[i] + ax] = a[i];
+        }
+    }
+    const double kap = c->h_state[k].kappa;
+    if (kappa) *kappa = kap;
+    if (diam) {
+        HIPCHK(hipMemcpy(a.data(), s.D0[s.set], sizeof(double) * n, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < n; ++i) diam[orig[i]] = kap * a[i];
+    }
+    return RCP_OK;
+}
+
+int rcp_neighbor_build(rcp_ctx *c, int k, int64_t *n_pairs)
+{
+    CHK(check_k(c, k));
+    CHK(pull_state(c));
+    CHK(rebuild(c, k, c->h_state[k].kappa));
+    if (n_pairs) *n_pairs = c->segs[k].npairs;
+    return RCP_OK;
+}
+
+int rcp_get_pairs(rcp_ctx *c, int k, int32_t *pi, int32_t *pj, int64_t cap, int64_t *count)
+{
+    CHK(check_k(c, k));
+    Seg &s = c->segs[k];
+    if (!s.built) return fail(RCP_ESTATE, "no neighbour list built");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const int64_t n = s.n;
+    std::vector<int32_t> rp(n + 1), orig(n), col(s.nnz);
+    HIPCHK(hipMemcpy(rp.data(), s.rp, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(orig.data(), s.ORIG[s.set], sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    if (s.nnz) HIPCHK(hipMemcpy(col.data(), s.col, sizeof(int32_t) * s.nnz, hipMemcpyDeviceToHost));
+    std::vector<std::pair<int32_t, int32_t>> pr;
+    pr.reserve(s.npairs);
+    for (int64_t i = 0; i < n; ++i)
+        for (int32_t q = rp[i]; q < rp[i + 1]; ++q) {
+            const int32_t a = orig[i], b = orig[col[q]];
+            if (a < b) pr.emplace_back(a, b);
+        }
+    std::sort(pr.begin(), pr.end());
+    const int64_t m = (int64_t)pr.size();
+    for (int64_t q = 0; q < m && q < cap; ++q) {
+        pi[q] = pr[q].first;
+        pj[q] = pr[q].second;
+    }
+    if (count) *count = m;
+    return RCP_OK;
+}
+
+static int eval_current(rcp_ctx *c, int k, const double *xu, double kappa, double mu,
+                        double *gu_dev, hipStream_t st)
+{
+    Seg &s = c->segs[k];
+    const int nb = (int)std::max<int64_t>(1, (s.n + kBlock - 1) / kBlock);
+    CHK(dgrow(&c->part, &c->part_cap, 4 * (int64_t)nb + 8));
+    EvalOut o;
+    o.part = c->part;
+    o.gu = gu_dev;
+    launch_eval(c->d_ptrs, c->d_state, k, s.n, xu, kappa, o, nb, st);
+    launch_eval_finish(c->part, nb, kappa, mu, c->d_state, k, c->out, st);
+    return RCP_OK;
+}
+
+int rcp_energy_grad(rcp_ctx *c, int k, double mu, rcp_energy *e, double *grad_x)
+{
+    CHK(check_k(c, k));
+    if (!e) return fail(RCP_EINVAL, "null output");
+    CHK(pull_state(c));
+    if (c->h_state[k].flags & (F_REBUILD | F_STALE)) {
+        CHK(rebuild(c, k, c->h_state[k].kappa));
+        CHK(pull_state(c));
+    }
+    Seg &s = c->segs[k];
+    double *gdev = nullptr;
+    if (grad_x) {
+        CHK(dgrow(&c->xtmp, &c->xtmp_cap, 3 * s.n));
+        gdev = c->xtmp;
+    }
+    CHK(eval_current(c, k, nullptr, c->h_state[k].kappa, mu, gdev, c->stream));
+    double o[6];
+    HIPCHK(hipMemcpyAsync(o, c->out, sizeof o, hipMemcpyDeviceToHost, c->stream));
+    if (grad_x)
+        HIPCHK(hipMemcpyAsync(grad_x, gdev, sizeof(double) * 3 * s.n, hipMemcpyDeviceToHost,
+                              c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    e->E_overlap = o[0];
+    e->E_growth = o[1];
+    e->dE_dkappa_overlap = o[2];
+    e->dE_dkappa_growth = o[3];
+    e->max_overlap = o[4];
+    e->n_overlap = (int64_t)std::llround(o[5]);
+    return RCP_OK;
+}
+
+static int start_schedule(rcp_ctx *c, const rcp_schedule *sched, int per_packing,
+                          int64_t max_iters)
+{
+    CHK(pull_state(c));
+    for (size_t k = 0; k < c->segs.size(); ++k) {
+        SchedDev q;
+        CHK(to_sched(per_packing ? sched + k : sched, q));
+        CHK(reset_moments(c, (int)k));
+        launch_sched_start(c->d_state, (int)k, q, 1, max_iters, c->stream);
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return RCP_OK;
+}
+
+int rcp_adam_step(rcp_ctx *c, double mu, double eta_x, double eta_k, int64_t n_steps)
+{
+    if (!c) return fail(RCP_EINVAL, "null context");
+    if (n_steps < 1 || !std::isfinite(mu) || !(eta_x >= 0) || !(eta_k >= 0))
+        return fail(RCP_EINVAL, "bad adam_step arguments");
+    rcp_schedule q;
+    std::memset(&q, 0, sizeof q);
+    q.size = sizeof q;
+    q.n_rungs = 1;
+    q.absolute = 1;
+    q.tol = -1.0;
+    q.mu[0] = mu;
+    q.eta_x[0] = eta_x;
+    q.eta_k[0] = eta_k;
+    q.decay[0] = 1.0;
+    q.budget[0] = n_steps;
+    CHK(start_schedule(c, &q, 0, 0));
+    CHK(run_loop(c));
+    CHK(pull_state(c));
+    for (size_t k = 0; k < c->segs.size(); ++k)
+        if (c->h_state[k].flags & F_NONFINITE)
+            return fail(RCP_ENONFINITE, "packing %zu: non-finite energy or gradient", k);
+    return RCP_OK;
+}
+
+int rcp_inflate_run(rcp_ctx *c, const rcp_schedule *sched, int per_packing, int64_t max_iters,
+                    rcp_result *results)
+{
+    if (!c || !sched || !results) return fail(RCP_EINVAL, "null argument");
+    if (max_iters < 0) return fail(RCP_EINVAL, "max_iters < 0");
+    CHK(start_schedule(c, sched, per_packing, max_iters));
+    CHK(run_loop(c));
+    CHK(pull_state(c));
+    int rc = RCP_OK;
+    std::vector<SegState> fin(c->h_state, c->h_state + c->segs.size());
+    for (size_t k = 0; k < c->segs.size(); ++k) {
+        const SegState &st = fin[k];
+        rcp_result &r = results[k];
+        std::memset(&r, 0, sizeof r);
+        r.kappa_before_shrink = st.kappa;
+        r.max_overlap = st.max_delta;
+        r.energy = st.E_ov;
+        r.iterations = st.iters;
+        r.rebuilds = c->segs[k].rebuilds;
+        r.rung = st.rung;
+        if (st.flags & F_NONFINITE) {
+            r.status = RCP_ENONFINITE;
+            rc = RCP_ENONFINITE;
+            continue;
+        }
+        if (st.flags & F_STOP) r.status = 0;
+        else if (st.flags & F_CAP) {
+            r.status = RCP_ENOTCONV;
+            if (rc == RCP_OK) rc = RCP_ENOTCONV;
+        } else r.status = 1;
+        if (!(st.flags & F_STOP)) {
+            // the returned state is the one after the last update: evaluate it
+            rcp_energy e;
+            CHK(rcp_energy_grad(c, (int)k, st.mu, &e, nullptr));
+            r.max_overlap = e.max_overlap;
+            r.energy = e.E_overlap;
+        }
+        CHK(shrink_seg(c, (int)k, &r.kappa, &r.phi));
+        r.rebuilds = c->segs[k].rebuilds;
+    }
+    if (rc == RCP_ENOTCONV) fail(RCP_ENOTCONV, "iteration cap reached before the stop test held");
+    if (rc == RCP_ENONFINITE) fail(RCP_ENONFINITE, "non-finite energy or gradient");
+    return rc;
+}
+
+int rcp_census_run(rcp_ctx *c, const rcp_schedule *sched, int per_packing, int64_t max_iters,
+                   rcp_result *results)
+{
+    return rcp_inflate_run(c, sched, per_packing, max_iters, results);
+}
+
+int rcp_shrink(rcp_ctx *c, int k, double *kappa_shrunk, double *phi)
+{
+    CHK(check_k(c, k));
+    double kp, ph;
+    CHK(shrink_seg(c, k, &kp, &ph));
+    if (kappa_shrunk) *kappa_shrunk = kp;
+    if (phi) *phi = ph;
+    return RCP_OK;
+}
+
+// Make the list valid for user-order device positions x_dev at kappa.
+static int ensure_valid_at(rcp_ctx *c, const double *x_dev, double kappa, hipStream_t st)
+{
+    if (st != c->stream) HIPCHK(hipStreamSynchronize(c->stream));
+    CHK(pull_state(c));
+    Seg &s = c->segs[0];
+    SegState &h = c->h_state[0];
+    bool ok = s.built && !(h.flags & (F_REBUILD | F_STALE)) && kappa <= h.kappa_lim;
+    if (ok) {
+        const int nb = (int)std::max<int64_t>(1, (s.n + kBlock - 1) / kBlock);
+        CHK(dgrow(&c->part, &c->part_cap, 4 * (int64_t)nb + 8));
+        launch_disp(c->d_ptrs, c->d_state, 0, s.n, x_dev, c->part, nb, st);
+        launch_max_finish(c->part, nb, c->out + 8, st);
+        double d2 = 0;
+        HIPCHK(hipMemcpyAsync(&d2, c->out + 8, sizeof d2, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        ok = d2 <= h.disp_lim2;
+    }
+    if (!ok) {
+        HIPCHK(hipStreamSynchronize(st));
+        CHK(rcp_set_state(c, 0, x_dev, kappa, 1));
+        CHK(rebuild(c, 0, kappa));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    }
+    return RCP_OK;
+}
+
+__global__ void k_energy_out(const double *o, double *E)
+{
+    E[0] = o[0] + o[1];
+    E[1] = o[4];
+}
+
+__global__ void k_gk_out(const double *o, double *gk) { gk[0] = o[2] + o[3]; }
+
+int rcp_energy_dev(rcp_ctx *c, const double *x_dev, double kappa, double mu, double *E_dev,
+                   void *stream)
+{
+    if (!c || !x_dev || !E_dev) return fail(RCP_EINVAL, "null argument");
+    hipStream_t st = stream ? (hipStream_t)stream : c->stream;
+    CHK(ensure_valid_at(c, x_dev, kappa, st));
+    CHK(eval_current(c, 0, x_dev, kappa, mu, nullptr, st));
+    hipLaunchKernelGGL(k_energy_out, dim3(1), dim3(1), 0, st, c->out, E_dev);
+    HIPCHK(hipGetLastError());
+    return RCP_OK;
+}
+
+int rcp_adjoint_dev(rcp_ctx *c, const double *x_dev, double kappa, double mu, double *gx_dev,
+                    double *gk_dev, void *stream)
+{
+    if (!c || !x_dev || !gx_dev || !gk_dev) return fail(RCP_EINVAL, "null argument");
+    hipStream_t st = stream ? (hipStream_t)stream : c->stream;
+    CHK(ensure_valid_at(c, x_dev, kappa, st));
+    CHK(eval_current(c, 0, x_dev, kappa, mu, gx_dev, st));
+    hipLaunchKernelGGL(k_gk_out, dim3(1), dim3(1), 0, st, c->out, gk_dev);
+    HIPCHK(hipGetLastError());
+    return RCP_OK;
+}
+
+int rcp_get_stats(rcp_ctx *c, rcp_stats *s)
+{
+    if (!c || !s) return fail(RCP_EINVAL, "null argument");
+    *s = c->stats;
+    s->nnz = 0;
+    s->n_heavy = 0;
+    for (auto &g : c->segs) {
+        s->nnz += g.nnz;
+        s->n_heavy += g.hcnt;
+    }
+    return RCP_OK;
+}
+
+int rcp_reset_stats(rcp_ctx *c)
+{
+    if (!c) return fail(RCP_EINVAL, "null context");
+    std::memset(&c->stats, 0, sizeof c->stats);
+    return RCP_OK;
+}
+
+int rcp_num_packings(rcp_ctx *c) { return c ? (int)c->segs.size() : 0; }
+
+int64_t rcp_num_particles(rcp_ctx *c, int k)
+{
+    if (!c || k < 0 || k >= (int)c->segs.size()) return -1;
+    return c->segs[k].n;
+}
+
+void rcp_destroy(rcp_ctx *c) { destroy_ctx(c); }
+
+}  // extern "C"

@@ -1,0 +1,313 @@
+"""GPU path (through the C ABI) against the FP64 CPU oracle.
+
+Bars: pair sets and placements bit for bit; shrink scale bit for bit;
+energy terms and gradients within 1e-10 of the oracle, per component
+relative to the sum of absolute pair contributions (guards against
+cancellation); stepwise Adam trajectories within 1e-9 of the step size per
+step; whole runs statistically (mean phi over 8 seeds within 0.002).
+"""
+import numpy as np
+import pytest
+
+import rcp_inputs as ri
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def rcp():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2608_12235_amd as m
+    m.lib()
+    return m
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _grad_ok(g, go, scale):
+    err = np.abs(g - go)
+    bad = err > TOL * scale
+    return not bad.any(), float(np.max(err / (scale + 1e-300)))
+
+
+def _oracle_energy(orc, x, d0, L, kappa, mu):
+    pi, pj = (orc.pairs_brute if len(d0) <= 4096 else orc.pairs_cells)(x, d0, L, kappa, 0.0, 0.0)
+    return orc.energy_grad(x, d0, L, kappa, mu, pi, pj)
+
+
+def _dense_c1_state(orc, seed=0, iters=2000, s=0.3, g=0.02):
+    w = ri.c1_lognormal(seed)
+    x0 = orc.rsa(w.d0, w.L, 1.0, w.seed)
+    st = orc.RunState(x0, w.d0, w.L, 1.0)
+    orc.run(st, orc.default_params(w.d0, s=s, g=g), orc.default_schedule(w.n), max_iters=iters)
+    return w, st.x.copy(), float(st.kappa[0])
+
+
+# --------------------------------------------------------------- placement
+@pytest.mark.parametrize("seed", [0, 3])
+def test_rsa_placement_bit_exact(rcp, orc, seed):
+    w = ri.c1_lognormal(seed)
+    _say("rsa C1 seed", seed)
+    p = rcp.Packing(w.d0, w.L, 1.0, w.seed, init="rsa")
+    x, k = p.get_state()
+    assert k == 1.0
+    assert np.array_equal(x, orc.rsa(w.d0, w.L, 1.0, w.seed))
+
+
+def test_rsa_placement_polydisperse_bit_exact(rcp, orc):
+    d0 = ri.lognormal_quantiles(3000, 0.7, 60.0)
+    L = ri.box_for_phi(d0, 0.08)
+    _say("rsa lognormal S=60 N=3000")
+    p = rcp.Packing(d0, L, 1.0, 11, init="rsa")
+    x, _ = p.get_state()
+    assert np.array_equal(x, orc.rsa(d0, L, 1.0, 11))
+
+
+def test_uniform_placement_matches_generator(rcp):
+    w = ri.small_polydisperse(5000, 10.0, 0.3, seed=9)
+    p = rcp.Packing(w.d0, w.L, 1.0, w.seed, init="uniform")
+    x, _ = p.get_state()
+    assert np.array_equal(x, w.x)
+
+
+# --------------------------------------------------------------- pair sets
+PAIR_CASES = [
+    ("lognormal", 100.0, 0.5, 1.0, 0.1, 0.02),
+    ("powerlaw", 20.0, 0.4, 1.0, 0.3, 0.02),
+    ("powerlaw", 300.0, 0.02, 1.0, 0.3, 0.02),
+    ("weibull", 300.0, 0.5, 1.1, 0.1, 0.002),
+    ("lognormal", 8.0, 0.6, 1.0, 2.0, 0.0),
+]
+
+
+@pytest.mark.parametrize("fam,S,phi,kb,s,g", PAIR_CASES)
+@pytest.mark.parametrize("n", [4096, 2049])
+def test_pairs_bit_exact_random(rcp, orc, fam, S, phi, kb, s, g, n):
+    w = ri.small_polydisperse(n, S, phi, seed=17, family=fam)
+    _say("pairs", fam, S, phi, n)
+    p = rcp.Packing(w.d0, w.L, kb, 0, init="none", params=rcp.make_params(skin_s=s, skin_g=g))
+    p.set_state(w.x, kb)
+    npairs = p.neighbor_build()
+    gi, gj = p.pairs()
+    oi, oj = orc.pairs_brute(w.x, w.d0, w.L, kb, s, g)
+    assert npairs == len(oi)
+    assert np.array_equal(gi, oi) and np.array_equal(gj, oj)
+
+
+def test_pairs_bit_exact_c1_states(rcp, orc):
+    w, x, k = _dense_c1_state(orc)
+    _say("pairs C1 dense kappa", k)
+    for (s, g) in [(0.3, 0.02), (0.0, 0.0), (1.0, 0.1)]:
+        p = rcp.Packing(w.d0, w.L, k, 0, init="none",
+                        params=rcp.make_params(skin_s=s, skin_g=g))
+        p.set_state(x, k)
+        p.neighbor_build()
+        gi, gj = p.pairs()
+        oi, oj = orc.pairs_brute(x, w.d0, w.L, k, s, g)
+        assert np.array_equal(gi, oi) and np.array_equal(gj, oj), (s, g)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 40])
+def test_pairs_tiny_and_coarse_grids(rcp, orc, n):
+    # few spheres in a small box: class grids with fewer than 3 cells per axis
+    d0 = np.linspace(1.0, 2.0, n)
+    L = 9.0
+    rng = np.random.default_rng(n)
+    x = rng.uniform(0, L, (n, 3))
+    p = rcp.Packing(d0, L, 1.5, 0, init="none", params=rcp.make_params(skin_s=0.2, skin_g=0.02))
+    p.set_state(x, 1.5)
+    p.neighbor_build()
+    gi, gj = p.pairs()
+    oi, oj = orc.pairs_brute(x, d0, L, 1.5, 0.2, 0.02)
+    assert np.array_equal(gi, oi) and np.array_equal(gj, oj)
+
+
+def test_pairs_bit_exact_c2_full(rcp, orc):
+    w = ri.c2_powerlaw(seed=0)
+    x = ri.uniform_positions(w.n, w.L, 5)
+    _say("pairs C2 N", w.n)
+    p = rcp.Packing(w.d0, w.L, 1.0, 0, init="none", params=rcp.make_params(skin_s=0.5, skin_g=0.02))
+    p.set_state(x, 1.0)
+    p.neighbor_build()
+    gi, gj = p.pairs()
+    oi, oj = orc.pairs_cells(x, w.d0, w.L, 1.0, 0.5, 0.02)
+    assert len(oi) > 10000
+    assert np.array_equal(gi, oi) and np.array_equal(gj, oj)
+
+
+@pytest.fixture(scope="module")
+def c3(rcp):
+    w = ri.c3_lognormal_dense(seed=0)
+    p = rcp.Packing(w.d0, w.L, 1.0, 0, init="none",
+                    params=rcp.make_params(skin_s=2.0, skin_g=0.02))
+    p.set_state(w.x, 1.0)
+    p.neighbor_build()
+    return w, p
+
+
+def test_pairs_c3_sampled_rows(rcp, orc, c3):
+    w, p = c3
+    _say("pairs C3 sampled rows")
+    gi, gj = p.pairs()
+    rows = np.sort(np.random.default_rng(1).choice(w.n, 1500, replace=False))
+    nb = orc.rows_pairs(w.x, w.d0, w.L, 1.0, rows, 2.0, 0.02)
+    # GPU partners of the sampled rows from the canonical half set
+    full_i = np.concatenate([gi, gj])
+    full_j = np.concatenate([gj, gi])
+    order = np.lexsort((full_j, full_i))
+    full_i, full_j = full_i[order], full_j[order]
+    lo = np.searchsorted(full_i, rows, "left")
+    hi = np.searchsorted(full_i, rows, "right")
+    for r, a, b, want in zip(rows, lo, hi, nb):
+        assert np.array_equal(full_j[a:b], want), int(r)
+
+
+# -------------------------------------------------------- energy / gradient
+def _check_energy(p, orc, x, d0, L, kappa, mu):
+    e = p.energy_grad(mu=mu)
+    r = _oracle_energy(orc, x, d0, L, kappa, mu)
+    ok, err = _grad_ok(e["g"], r["g"], r["gscale"])
+    assert ok, "gradient error %g" % err
+    assert e["E_overlap"] == pytest.approx(r["E_ov"], rel=TOL, abs=1e-300)
+    assert e["E_growth"] == pytest.approx(r["E_growth"], rel=TOL)
+    assert e["dE_dkappa_overlap"] == pytest.approx(r["gk_ov"], rel=TOL, abs=1e-300)
+    assert e["dE_dkappa_growth"] == pytest.approx(r["gk_growth"], rel=TOL)
+    assert e["max_overlap"] == pytest.approx(r["max_delta"], rel=1e-13, abs=1e-300)
+    assert e["n_overlap"] == r["n_overlap"]
+    return err
+
+
+def test_energy_grad_c1_dense(rcp, orc):
+    w, x, k = _dense_c1_state(orc)
+    p = rcp.Packing(w.d0, w.L, k, 0, init="none", params=rcp.make_params(skin_s=0.3))
+    p.set_state(x, k)
+    _check_energy(p, orc, x, w.d0, w.L, k, 0.37)
+
+
+@pytest.mark.parametrize("fam,S,phi", [("lognormal", 100.0, 0.5), ("powerlaw", 20.0, 0.4),
+                                       ("weibull", 300.0, 0.5)])
+def test_energy_grad_random(rcp, orc, fam, S, phi):
+    w = ri.small_polydisperse(4096, S, phi, seed=23, family=fam)
+    p = rcp.Packing(w.d0, w.L, 1.0, 0, init="none", params=rcp.make_params(skin_s=0.2))
+    p.set_state(w.x, 1.0)
+    _check_energy(p, orc, w.x, w.d0, w.L, 1.0, 1e-3)
+
+
+def test_energy_grad_c3(rcp, orc, c3):
+    w, p = c3
+    _say("energy C3")
+    e = p.energy_grad(mu=2e-3)
+    rows = np.sort(np.random.default_rng(2).choice(w.n, 2000, replace=False))
+    g, gs, st = orc.rows_grad(w.x, w.d0, w.L, 1.0, rows)
+    ok, err = _grad_ok(e["g"][rows], g, gs)
+    assert ok, "C3 sampled gradient error %g" % err
+    r = _oracle_energy(orc, w.x, w.d0, w.L, 1.0, 2e-3)
+    assert e["E_overlap"] == pytest.approx(r["E_ov"], rel=TOL)
+    assert e["dE_dkappa_overlap"] == pytest.approx(r["gk_ov"], rel=TOL)
+    assert e["n_overlap"] == r["n_overlap"]
+    ok, err = _grad_ok(e["g"], r["g"], r["gscale"])
+    assert ok, "C3 full gradient error %g" % err
+
+
+# ------------------------------------------------------------- Adam steps
+@pytest.mark.parametrize("steps", [1, 10])
+def test_adam_steps_match_oracle(rcp, orc, steps):
+    w, x, k = _dense_c1_state(orc, iters=1500)
+    mu, ex, ek = 2e-3, 2e-3, 2e-4
+    P = orc.default_params(w.d0, s=0.3, g=0.02)
+    p = rcp.Packing(w.d0, w.L, k, 0, init="none",
+                    params=rcp.make_params(skin_s=0.3, skin_g=0.02, eps_x=P.eps_x))
+    p.set_state(x, k)
+    p.adam_step(mu, ex, ek, steps)
+    xg, kg = p.get_state()
+    st = orc.RunState(x, w.d0, w.L, k)
+    orc.run(st, P, orc.oracle.absolute_schedule(mu, ex, ek, steps))
+    d = np.abs(xg - st.x)
+    d = np.minimum(d, w.L - d)
+    assert d.max() <= 1e-9 * ex * steps + 4e-16 * w.L, d.max()
+    assert kg == pytest.approx(st.kappa[0], rel=1e-12)
+
+
+def test_schedule_rungs_match_oracle(rcp, orc):
+    # relative rungs, decays and rung changes over 30 iterations
+    w, x, k = _dense_c1_state(orc, iters=1200)
+    rungs = [(1e-2, 1e-2, 1e-3, 1.0, 8), (1e-3, 5e-3, 5e-4, 0.97, 7), (1e-5, 2e-3, 1e-4, 0.99, 15)]
+    P = orc.default_params(w.d0, s=0.3, g=0.02)
+    S = orc.Schedule()
+    S.n_rungs, S.absolute, S.tol = 3, 0, -1.0
+    for r, (mu, e1, e2, dc, b) in enumerate(rungs):
+        S.mu[r], S.eta_x[r], S.eta_k[r], S.decay[r], S.budget[r] = mu, e1, e2, dc, b
+    st = orc.RunState(x, w.d0, w.L, k)
+    status, res, _ = orc.run(st, P, S)
+    p = rcp.Packing(w.d0, w.L, k, 0, init="none",
+                    params=rcp.make_params(skin_s=0.3, skin_g=0.02, eps_x=P.eps_x))
+    p.set_state(x, k)
+    out = p.inflate_run(rcp.schedule_from_rungs(rungs, tol=-1.0))
+    assert out[0]["iterations"] == res.iterations == 30
+    xg, kg = p.get_state()
+    d = np.abs(xg - st.x)
+    d = np.minimum(d, w.L - d)
+    assert d.max() <= 1e-9 * 1e-2 * k * 30
+    assert kg == pytest.approx(st.kappa[0], rel=1e-11)
+
+
+def test_trajectory_independent_of_skin(rcp, orc):
+    w, x, k = _dense_c1_state(orc, iters=1500)
+    states = []
+    for s in (0.05, 1.0):
+        p = rcp.Packing(w.d0, w.L, k, 0, init="none", params=rcp.make_params(skin_s=s))
+        p.set_state(x, k)
+        p.adam_step(2e-3, 2e-3, 2e-4, 40)
+        states.append(p.get_state())
+    d = np.abs(states[0][0] - states[1][0])
+    d = np.minimum(d, w.L - d)
+    assert d.max() <= 1e-9 * 2e-3 * 40
+
+
+# ---------------------------------------------------------------- shrink
+def test_shrink_bit_exact(rcp, orc):
+    w, x, k = _dense_c1_state(orc, iters=3000)
+    p = rcp.Packing(w.d0, w.L, k, 0, init="none", params=rcp.make_params(skin_s=0.3))
+    p.set_state(x, k)
+    kp, phi = p.shrink()
+    pi, pj = orc.pairs_brute(x, w.d0, w.L, k, 0.0, 0.0)
+    assert len(pi) > 0
+    assert kp == orc.shrink(x, w.d0, w.L, k, pi, pj)
+    assert phi == pytest.approx(orc.phi(w.d0, w.L, kp), rel=1e-14)
+
+
+# -------------------------------------------------------------- whole runs
+def test_inflate_run_deterministic(rcp, orc):
+    w = ri.c1_lognormal(1)
+    out = []
+    for _ in range(2):
+        p = rcp.Packing(w.d0, w.L, 1.0, w.seed, init="rsa", params=rcp.make_params(skin_s=0.3))
+        out.append(p.inflate_run()[0])
+        p.close()
+    assert out[0]["phi"] == out[1]["phi"] and out[0]["iterations"] == out[1]["iterations"]
+
+
+def test_inflate_run_c1_statistics(rcp, orc):
+    phis_g, phis_o = [], []
+    for seed in range(8):
+        w = ri.c1_lognormal(seed)
+        p = rcp.Packing(w.d0, w.L, 1.0, w.seed, init="rsa", params=rcp.make_params(skin_s=0.3))
+        r = p.inflate_run()[0]
+        _say("C1 seed", seed, r)
+        assert r["status"] == 0 and r["max_overlap"] < 5e-4
+        x, _ = p.get_state()
+        none, _ = orc.pairs_brute(x, w.d0, w.L, r["kappa"], 0.0, 0.0)
+        assert len(none) == 0
+        phis_g.append(r["phi"])
+        st = orc.RunState(orc.rsa(w.d0, w.L, 1.0, w.seed), w.d0, w.L, 1.0)
+        status, ro, _ = orc.run(st, orc.default_params(w.d0, s=0.3), orc.default_schedule(w.n))
+        assert status == 0
+        phis_o.append(ro.phi)
+    _say("phi gpu", np.mean(phis_g), np.std(phis_g), "oracle", np.mean(phis_o), np.std(phis_o))
+    assert abs(np.mean(phis_g) - np.mean(phis_o)) <= 0.002
