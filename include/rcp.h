@@ -86,13 +86,17 @@ typedef struct {
  *     one wavefront per row, the rest one thread per row;
  *   graph_iters: iterations captured per HIP graph launch (1 = no graph);
  *   heavy_blocks: blocks reserved per packing for heavy rows (0 = auto);
- *   xcd_remap: 1 = map consecutive row blocks to the same XCD. */
+ *   xcd_remap: 1 = map consecutive row blocks to the same XCD;
+ *   fused_tail: 1 = the last block of a packing to finish an iteration
+ *     reduces the partial sums and updates kappa and the schedule (one
+ *     kernel per iteration), 0 = a separate one-block kernel does it. */
 typedef struct {
     uint32_t size;
     int32_t heavy_threshold;
     int32_t graph_iters;
     int32_t heavy_blocks;
     int32_t xcd_remap;
+    int32_t fused_tail;
 } rcp_tuning;
 
 /* Annealing schedule: a table of rungs run in order (App. A).  Rung r lasts
@@ -227,6 +231,17 @@ int rcp_adam_step(rcp_ctx *ctx, double mu, double eta_x, double eta_k,
  * RCP_ENONFINITE if any packing ended that way. */
 int rcp_inflate_run(rcp_ctx *ctx, const rcp_schedule *sched, int per_packing,
                     int64_t max_iters, rcp_result *results);
+
+/* The run of rcp_inflate_run in steps: rcp_run_start loads the schedule(s)
+ * and resets the optimiser state of every packing without iterating;
+ * rcp_run_continue then advances every active packing by up to n_iters
+ * iterations (0: until each has stopped or reached its cap) and reports
+ * in *active how many packings can still continue.  No shrink is done;
+ * rcp_run_result fills a result for packing k from its current state
+ * (shrink included) without changing that state. */
+int rcp_run_start(rcp_ctx *ctx, const rcp_schedule *sched, int per_packing);
+int rcp_run_continue(rcp_ctx *ctx, int64_t n_iters, int32_t *active);
+int rcp_run_result(rcp_ctx *ctx, int k, rcp_result *result);
 
 /* Census entry point: rcp_inflate_run over every packing of a context made
  * by rcp_census_init, one launch per iteration for the whole batch. */

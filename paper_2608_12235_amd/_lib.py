@@ -34,7 +34,7 @@ class Params(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("size", C.c_uint32), ("heavy_threshold", C.c_int32),
                 ("graph_iters", C.c_int32), ("heavy_blocks", C.c_int32),
-                ("xcd_remap", C.c_int32)]
+                ("xcd_remap", C.c_int32), ("fused_tail", C.c_int32)]
 
 
 class Schedule(C.Structure):
@@ -95,6 +95,9 @@ SIGNATURES = {
                                   C.POINTER(Result)]),
     "rcp_census_run": (C.c_int, [vp, C.POINTER(Schedule), C.c_int, C.c_int64,
                                  C.POINTER(Result)]),
+    "rcp_run_start": (C.c_int, [vp, C.POINTER(Schedule), C.c_int]),
+    "rcp_run_continue": (C.c_int, [vp, C.c_int64, i32p]),
+    "rcp_run_result": (C.c_int, [vp, C.c_int, C.POINTER(Result)]),
     "rcp_shrink": (C.c_int, [vp, C.c_int, dp, dp]),
     "rcp_energy_dev": (C.c_int, [vp, vp, C.c_double, C.c_double, vp, vp]),
     "rcp_adjoint_dev": (C.c_int, [vp, vp, C.c_double, C.c_double, vp, vp, vp]),

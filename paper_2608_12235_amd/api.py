@@ -166,6 +166,27 @@ class Packing:
             check(rc)
         return [_result_dict(r) for r in res]
 
+    def run_start(self, schedule=None):
+        P = self.n_packings
+        if schedule is None:
+            schedule = [default_schedule(n) for n in self.n]
+        per = isinstance(schedule, (list, tuple))
+        if per:
+            arr = (Schedule * P)(*schedule)
+            check(lib().rcp_run_start(self._h, C.cast(arr, C.POINTER(Schedule)), 1))
+        else:
+            check(lib().rcp_run_start(self._h, C.byref(schedule), 0))
+
+    def run_continue(self, n_iters=0):
+        act = C.c_int32()
+        check(lib().rcp_run_continue(self._h, int(n_iters), C.byref(act)))
+        return act.value
+
+    def run_result(self, k=0):
+        r = Result()
+        check(lib().rcp_run_result(self._h, k, C.byref(r)))
+        return _result_dict(r)
+
     def shrink(self, k=0):
         kp, ph = C.c_double(), C.c_double()
         check(lib().rcp_shrink(self._h, k, C.byref(kp), C.byref(ph)))

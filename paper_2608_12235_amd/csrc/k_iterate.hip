@@ -72,26 +72,64 @@ __device__ __forceinline__ double adam_coord(double th, double g, double &m, dou
 
 struct IterScalars {
     double kappa, L, hL, b1, b2, bc1, bc2, eta, eps;
-    int cur;
 };
 
+// Pointers of one segment with the ping-pong buffers already selected
+// (uniform selects keep them in scalar registers; indexing the pointer
+// table with the runtime buffer index would spill it to scratch).
+struct IterPtrs {
+    const double *x, *y, *z, *d0;
+    double *xo, *yo, *zo;
+    double *m0, *m1, *m2, *v0, *v1, *v2, *r0, *r1, *r2;
+    const int32_t *rp, *col, *heavy;
+};
+
+__device__ __forceinline__ IterPtrs select_ptrs(const SegPtrs *__restrict__ P, int seg, int cur)
+{
+    const SegPtrs &q = P[seg];
+    IterPtrs p;
+    p.x = cur ? q.x[1][0] : q.x[0][0];
+    p.y = cur ? q.x[1][1] : q.x[0][1];
+    p.z = cur ? q.x[1][2] : q.x[0][2];
+    p.xo = cur ? q.x[0][0] : q.x[1][0];
+    p.yo = cur ? q.x[0][1] : q.x[1][1];
+    p.zo = cur ? q.x[0][2] : q.x[1][2];
+    p.d0 = q.d0;
+    p.m0 = q.m[0];
+    p.m1 = q.m[1];
+    p.m2 = q.m[2];
+    p.v0 = q.v[0];
+    p.v1 = q.v[1];
+    p.v2 = q.v[2];
+    p.r0 = q.xref[0];
+    p.r1 = q.xref[1];
+    p.r2 = q.xref[2];
+    p.rp = q.rp;
+    p.col = q.col;
+    p.heavy = q.heavy;
+    return p;
+}
+
+__device__ __forceinline__ double update_coord(const double *xin, double *xout, double *mm,
+                                               double *vv, const double *xr,
+                                               const IterScalars &c, int64_t i, double g)
+{
+    double m = mm[i], v = vv[i];
+    const double xn = adam_coord(xin[i], g, m, v, c.b1, c.b2, c.bc1, c.bc2, c.eta, c.eps, c.L);
+    xout[i] = xn;
+    mm[i] = m;
+    vv[i] = v;
+    const double dd = min_image(xn - xr[i], c.L, c.hL);
+    return dd * dd;
+}
+
 // Adam on particle i's coordinates; returns |x_new - x_ref|^2 (min image).
-__device__ __forceinline__ double update_particle(const SegPtrs &p, const IterScalars &c,
+__device__ __forceinline__ double update_particle(const IterPtrs &p, const IterScalars &c,
                                                   int64_t i, double gx, double gy, double gz)
 {
-    const double g[3] = {gx, gy, gz};
-    double d2 = 0.0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        double m = p.m[a][i], v = p.v[a][i];
-        const double xn = adam_coord(p.x[c.cur][a][i], g[a], m, v, c.b1, c.b2, c.bc1, c.bc2,
-                                     c.eta, c.eps, c.L);
-        p.x[c.cur ^ 1][a][i] = xn;
-        p.m[a][i] = m;
-        p.v[a][i] = v;
-        const double dd = min_image(xn - p.xref[a][i], c.L, c.hL);
-        d2 += dd * dd;
-    }
+    double d2 = update_coord(p.x, p.xo, p.m0, p.v0, p.r0, c, i, gx);
+    d2 += update_coord(p.y, p.yo, p.m1, p.v1, p.r1, c, i, gy);
+    d2 += update_coord(p.z, p.zo, p.m2, p.v2, p.r2, c, i, gz);
     return d2;
 }
 
@@ -186,7 +224,6 @@ __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ 
     const WorkItem w = W[b];
     SegState *s = S + w.seg;
     if (s->flags & F_IDLE) return;
-    const SegPtrs p = P[w.seg];
     IterScalars c;
     c.kappa = s->kappa;
     c.L = s->L;
@@ -197,8 +234,8 @@ __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ 
     c.bc2 = 1.0 - s->b2t * c.b2;
     c.eta = s->eta_x;
     c.eps = s->eps_x;
-    c.cur = s->cur;
-    const double *X = p.x[c.cur][0], *Y = p.x[c.cur][1], *Z = p.x[c.cur][2], *D = p.d0;
+    const IterPtrs p = select_ptrs(P, w.seg, s->cur);
+    const double *X = p.x, *Y = p.y, *Z = p.z, *D = p.d0;
 
     double be = 0, bs = 0, bm = 0, bd = 0;
     const int lane = threadIdx.x & (kWave - 1);
@@ -384,15 +421,15 @@ __global__ __launch_bounds__(kBlock) void k_eval(const SegPtrs *__restrict__ P,
                                                 double kappa, double *__restrict__ part,
                                                 double *__restrict__ gu)
 {
-    const SegPtrs p = P[seg];
     const SegState *s = S + seg;
+    const IterPtrs p = select_ptrs(P, seg, s->cur);
+    const int32_t *orig = P[seg].orig;
     const double L = s->L, hL = s->hL;
-    const int cur = s->cur;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double be = 0, bs = 0, bm = 0, bn = 0;
     if (i < n) {
         auto pos = [&](int64_t k, int a) -> double {
-            return xu ? xu[3 * (int64_t)p.orig[k] + a] : p.x[cur][a][k];
+            return xu ? xu[3 * (int64_t)orig[k] + a] : (a == 0 ? p.x[k] : (a == 1 ? p.y[k] : p.z[k]));
         };
         const double xi = pos(i, 0), yi = pos(i, 1), zi = pos(i, 2), di = p.d0[i];
         Acc a = {0, 0, 0, 0, 0, 0, 0};
@@ -405,7 +442,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(const SegPtrs *__restrict__ P,
         bm = a.m;
         bn = a.c;
         if (gu) {
-            const int64_t u = p.orig[i];
+            const int64_t u = orig[i];
             gu[3 * u] = a.gx;
             gu[3 * u + 1] = a.gy;
             gu[3 * u + 2] = a.gz;
@@ -520,12 +557,14 @@ __global__ __launch_bounds__(kBlock) void k_set_positions(const SegPtrs *__restr
                                                          int seg, int64_t n,
                                                          const double *__restrict__ xu, int cur)
 {
-    const SegPtrs p = P[seg];
+    const IterPtrs p = select_ptrs(P, seg, cur);
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
-    const int64_t u = p.orig[i];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) p.x[cur][a][i] = xu[3 * u + a];
+    const int64_t u = P[seg].orig[i];
+    double *X = (double *)p.x, *Y = (double *)p.y, *Z = (double *)p.z;
+    X[i] = xu[3 * u];
+    Y[i] = xu[3 * u + 1];
+    Z[i] = xu[3 * u + 2];
 }
 
 void launch_set_positions(const SegPtrs *P, SegState *S, int seg, int64_t n, const double *xu,

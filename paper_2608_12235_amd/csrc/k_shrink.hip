@@ -45,7 +45,9 @@ __global__ __launch_bounds__(kBlock) void k_shrink(const SegPtrs *__restrict__ P
     const SegState *s = S + seg;
     const double L = s->L, hL = s->hL;
     const int cur = s->cur;
-    const double *X = p.x[cur][0], *Y = p.x[cur][1], *Z = p.x[cur][2];
+    const double *X = cur ? p.x[1][0] : p.x[0][0];
+    const double *Y = cur ? p.x[1][1] : p.x[0][1];
+    const double *Z = cur ? p.x[1][2] : p.x[0][2];
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double kmin = INFINITY;
     if (i < n) {

@@ -422,20 +422,22 @@ static int rebuild(rcp_ctx *c, int k, double kappa)
 }
 
 // ------------------------------------------------------------ iteration loop
+static void launch_one_iteration(rcp_ctx *c)
+{
+    const int flags = (c->tuning.xcd_remap ? 1 : 0) | (c->tuning.fused_tail ? 2 : 0);
+    launch_iterate(c->d_ptrs, c->d_state, c->d_work, c->d_partials, c->nitems, flags, c->stream);
+    if (!c->tuning.fused_tail) launch_tail(c->d_state, c->d_partials, (int)c->segs.size(), c->stream);
+}
+
 static int capture_graph(rcp_ctx *c, int K)
 {
     if (c->gexec) {
         (void)hipGraphExecDestroy(c->gexec);
         c->gexec = nullptr;
     }
-    const int flags = (c->tuning.xcd_remap ? 1 : 0);
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
-    for (int it = 0; it < K; ++it) {
-        launch_iterate(c->d_ptrs, c->d_state, c->d_work, c->d_partials, c->nitems, flags,
-                       c->stream);
-        launch_tail(c->d_state, c->d_partials, (int)c->segs.size(), c->stream);
-    }
+    for (int it = 0; it < K; ++it) launch_one_iteration(c);
     HIPCHK(hipStreamEndCapture(c->stream, &g));
     hipError_t e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
@@ -474,9 +476,7 @@ static int run_loop(rcp_ctx *c)
             HIPCHK(hipGraphLaunch(c->gexec, c->stream));
             c->stats.graph_launches += 1;
         } else {
-            launch_iterate(c->d_ptrs, c->d_state, c->d_work, c->d_partials, c->nitems,
-                           c->tuning.xcd_remap ? 1 : 0, c->stream);
-            launch_tail(c->d_state, c->d_partials, (int)c->segs.size(), c->stream);
+            launch_one_iteration(c);
         }
         HIPCHK(hipEventRecord(c->e1, c->stream));
         std::vector<int64_t> prev(c->segs.size());
@@ -761,6 +761,7 @@ void rcp_tuning_default(rcp_tuning *t)
     t->graph_iters = 16;
     t->heavy_blocks = 0;
     t->xcd_remap = 1;
+    t->fused_tail = 0;
 }
 
 // Default rung table (our reading of App. A; the paper does not list its
@@ -1085,6 +1086,79 @@ int rcp_adam_step(rcp_ctx *c, double mu, double eta_x, double eta_k, int64_t n_s
     return RCP_OK;
 }
 
+// Result of packing k from its current state (shrink included).
+static int seg_result(rcp_ctx *c, int k, rcp_result &r)
+{
+    CHK(pull_state(c));
+    const SegState st = c->h_state[k];
+    std::memset(&r, 0, sizeof r);
+    r.kappa_before_shrink = st.kappa;
+    r.max_overlap = st.max_delta;
+    r.energy = st.E_ov;
+    r.iterations = st.iters;
+    r.rung = st.rung;
+    if (st.flags & F_NONFINITE) {
+        r.status = RCP_ENONFINITE;
+        r.rebuilds = c->segs[k].rebuilds;
+        return RCP_OK;
+    }
+    if (st.flags & F_STOP) r.status = 0;
+    else if (st.flags & F_CAP) r.status = RCP_ENOTCONV;
+    else r.status = 1;
+    if (!(st.flags & F_STOP)) {
+        // the state is the one after the last update: evaluate it
+        rcp_energy e;
+        CHK(rcp_energy_grad(c, k, st.mu, &e, nullptr));
+        r.max_overlap = e.max_overlap;
+        r.energy = e.E_overlap;
+    }
+    CHK(shrink_seg(c, k, &r.kappa, &r.phi));
+    r.rebuilds = c->segs[k].rebuilds;
+    return RCP_OK;
+}
+
+__global__ void k_extend(SegState *S, int nseg, int64_t n_more)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nseg) return;
+    S[k].iter_limit = n_more > 0 ? S[k].iters + n_more : 0;
+    S[k].flags &= ~F_HOLD;
+}
+
+int rcp_run_start(rcp_ctx *c, const rcp_schedule *sched, int per_packing)
+{
+    if (!c || !sched) return fail(RCP_EINVAL, "null argument");
+    CHK(start_schedule(c, sched, per_packing, 0));
+    // hold every packing until rcp_run_continue
+    for (size_t k = 0; k < c->segs.size(); ++k)
+        launch_set_flags(c->d_state, (int)k, 0, F_HOLD, c->stream);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return RCP_OK;
+}
+
+int rcp_run_continue(rcp_ctx *c, int64_t n_iters, int32_t *active)
+{
+    if (!c) return fail(RCP_EINVAL, "null context");
+    if (n_iters < 0) return fail(RCP_EINVAL, "n_iters < 0");
+    const int ns = (int)c->segs.size();
+    hipLaunchKernelGGL(k_extend, dim3((ns + 63) / 64), dim3(64), 0, c->stream, c->d_state, ns,
+                       n_iters);
+    CHK(run_loop(c));
+    CHK(pull_state(c));
+    int32_t a = 0;
+    for (int k = 0; k < ns; ++k)
+        if (!(c->h_state[k].flags & (F_STOP | F_CAP | F_NONFINITE))) ++a;
+    if (active) *active = a;
+    return RCP_OK;
+}
+
+int rcp_run_result(rcp_ctx *c, int k, rcp_result *r)
+{
+    CHK(check_k(c, k));
+    if (!r) return fail(RCP_EINVAL, "null result");
+    return seg_result(c, k, *r);
+}
+
 int rcp_inflate_run(rcp_ctx *c, const rcp_schedule *sched, int per_packing, int64_t max_iters,
                     rcp_result *results)
 {
@@ -1092,38 +1166,12 @@ int rcp_inflate_run(rcp_ctx *c, const rcp_schedule *sched, int per_packing, int6
     if (max_iters < 0) return fail(RCP_EINVAL, "max_iters < 0");
     CHK(start_schedule(c, sched, per_packing, max_iters));
     CHK(run_loop(c));
-    CHK(pull_state(c));
     int rc = RCP_OK;
-    std::vector<SegState> fin(c->h_state, c->h_state + c->segs.size());
     for (size_t k = 0; k < c->segs.size(); ++k) {
-        const SegState &st = fin[k];
-        rcp_result &r = results[k];
-        std::memset(&r, 0, sizeof r);
-        r.kappa_before_shrink = st.kappa;
-        r.max_overlap = st.max_delta;
-        r.energy = st.E_ov;
-        r.iterations = st.iters;
-        r.rebuilds = c->segs[k].rebuilds;
-        r.rung = st.rung;
-        if (st.flags & F_NONFINITE) {
-            r.status = RCP_ENONFINITE;
-            rc = RCP_ENONFINITE;
-            continue;
-        }
-        if (st.flags & F_STOP) r.status = 0;
-        else if (st.flags & F_CAP) {
-            r.status = RCP_ENOTCONV;
-            if (rc == RCP_OK) rc = RCP_ENOTCONV;
-        } else r.status = 1;
-        if (!(st.flags & F_STOP)) {
-            // the returned state is the one after the last update: evaluate it
-            rcp_energy e;
-            CHK(rcp_energy_grad(c, (int)k, st.mu, &e, nullptr));
-            r.max_overlap = e.max_overlap;
-            r.energy = e.E_overlap;
-        }
-        CHK(shrink_seg(c, (int)k, &r.kappa, &r.phi));
-        r.rebuilds = c->segs[k].rebuilds;
+        CHK(seg_result(c, (int)k, results[k]));
+        const int st = results[k].status;
+        if (st == RCP_ENONFINITE) rc = RCP_ENONFINITE;
+        else if (st == RCP_ENOTCONV && rc == RCP_OK) rc = RCP_ENOTCONV;
     }
     if (rc == RCP_ENOTCONV) fail(RCP_ENOTCONV, "iteration cap reached before the stop test held");
     if (rc == RCP_ENONFINITE) fail(RCP_ENONFINITE, "non-finite energy or gradient");

@@ -216,13 +216,15 @@ def test_energy_grad_c3(rcp, orc, c3):
 
 
 # ------------------------------------------------------------- Adam steps
-@pytest.mark.parametrize("steps", [1, 10])
-def test_adam_steps_match_oracle(rcp, orc, steps):
+@pytest.mark.parametrize("steps,fused,graph", [(1, 0, 16), (10, 0, 16), (10, 1, 16),
+                                               (25, 1, 1), (25, 0, 4)])
+def test_adam_steps_match_oracle(rcp, orc, steps, fused, graph):
     w, x, k = _dense_c1_state(orc, iters=1500)
     mu, ex, ek = 2e-3, 2e-3, 2e-4
     P = orc.default_params(w.d0, s=0.3, g=0.02)
     p = rcp.Packing(w.d0, w.L, k, 0, init="none",
-                    params=rcp.make_params(skin_s=0.3, skin_g=0.02, eps_x=P.eps_x))
+                    params=rcp.make_params(skin_s=0.3, skin_g=0.02, eps_x=P.eps_x),
+                    tuning=rcp.make_tuning(fused_tail=fused, graph_iters=graph))
     p.set_state(x, k)
     p.adam_step(mu, ex, ek, steps)
     xg, kg = p.get_state()
@@ -284,13 +286,17 @@ def test_shrink_bit_exact(rcp, orc):
 
 # -------------------------------------------------------------- whole runs
 def test_inflate_run_deterministic(rcp, orc):
+    # bit-identical reruns; the fused tail and the graph length change
+    # nothing but launch structure, so they give the same bits too
     w = ri.c1_lognormal(1)
     out = []
-    for _ in range(2):
-        p = rcp.Packing(w.d0, w.L, 1.0, w.seed, init="rsa", params=rcp.make_params(skin_s=0.3))
+    for fused, graph in [(0, 16), (0, 16), (1, 16), (1, 3)]:
+        p = rcp.Packing(w.d0, w.L, 1.0, w.seed, init="rsa", params=rcp.make_params(skin_s=0.3),
+                        tuning=rcp.make_tuning(fused_tail=fused, graph_iters=graph))
         out.append(p.inflate_run()[0])
         p.close()
-    assert out[0]["phi"] == out[1]["phi"] and out[0]["iterations"] == out[1]["iterations"]
+    for o in out[1:]:
+        assert o["phi"] == out[0]["phi"] and o["iterations"] == out[0]["iterations"]
 
 
 def test_inflate_run_c1_statistics(rcp, orc):
