@@ -110,26 +110,47 @@ __device__ __forceinline__ IterPtrs select_ptrs(const SegPtrs *__restrict__ P, i
     return p;
 }
 
-__device__ __forceinline__ double update_coord(const double *xin, double *xout, double *mm,
-                                               double *vv, const double *xr,
-                                               const IterScalars &c, int64_t i, double g)
+// One coordinate's Adam update from preloaded operands; returns the squared
+// (minimum image) displacement from the list reference along that axis.
+__device__ __forceinline__ double update_coord(double xi, double g, double m, double v, double r,
+                                               double *xout, double *mm, double *vv,
+                                               const IterScalars &c, int64_t i)
 {
-    double m = mm[i], v = vv[i];
-    const double xn = adam_coord(xin[i], g, m, v, c.b1, c.b2, c.bc1, c.bc2, c.eta, c.eps, c.L);
+    const double xn = adam_coord(xi, g, m, v, c.b1, c.b2, c.bc1, c.bc2, c.eta, c.eps, c.L);
     xout[i] = xn;
     mm[i] = m;
     vv[i] = v;
-    const double dd = min_image(xn - xr[i], c.L, c.hL);
+    const double dd = min_image(xn - r, c.L, c.hL);
     return dd * dd;
+}
+
+struct Pre {
+    double m0, m1, m2, v0, v1, v2, r0, r1, r2;
+};
+
+__device__ __forceinline__ Pre preload(const IterPtrs &p, int64_t i)
+{
+    Pre q;
+    q.m0 = p.m0[i];
+    q.m1 = p.m1[i];
+    q.m2 = p.m2[i];
+    q.v0 = p.v0[i];
+    q.v1 = p.v1[i];
+    q.v2 = p.v2[i];
+    q.r0 = p.r0[i];
+    q.r1 = p.r1[i];
+    q.r2 = p.r2[i];
+    return q;
 }
 
 // Adam on particle i's coordinates; returns |x_new - x_ref|^2 (min image).
 __device__ __forceinline__ double update_particle(const IterPtrs &p, const IterScalars &c,
-                                                  int64_t i, double gx, double gy, double gz)
+                                                  int64_t i, double xi, double yi, double zi,
+                                                  const Pre &q, double gx, double gy, double gz)
 {
-    double d2 = update_coord(p.x, p.xo, p.m0, p.v0, p.r0, c, i, gx);
-    d2 += update_coord(p.y, p.yo, p.m1, p.v1, p.r1, c, i, gy);
-    d2 += update_coord(p.z, p.zo, p.m2, p.v2, p.r2, c, i, gz);
+    double d2 = update_coord(xi, gx, q.m0, q.v0, q.r0, p.xo, p.m0, p.v0, c, i);
+    d2 += update_coord(yi, gy, q.m1, q.v1, q.r1, p.yo, p.m1, p.v1, c, i);
+    d2 += update_coord(zi, gz, q.m2, q.v2, q.r2, p.zo, p.m2, p.v2, c, i);
     return d2;
 }
 
@@ -194,14 +215,15 @@ __device__ void tail_logic(SegState *s, double E, double S, double md, double md
     if (s->iter_limit > 0 && s->iters >= s->iter_limit) s->flags |= F_HOLD;
 }
 
-// Deterministic reduction of a segment's block partials by one wavefront;
-// lane 0 then runs the tail.
+// Deterministic reduction of a segment's block partials by one block (fixed
+// assignment of partials to threads, fixed combining order); thread 0 then
+// runs the tail.  Every thread of the block must call it.
 __device__ void reduce_and_tail(SegState *s, const double *partials)
 {
-    const int lane = threadIdx.x;
     double e = 0, sd = 0, m = 0, d = 0;
-    for (int64_t b = lane; b < s->nblocks; b += kWave) {
-        const double *p = partials + 4 * (s->bfirst + b);
+    const int64_t nb = s->nblocks, b0 = s->bfirst;
+    for (int64_t b = threadIdx.x; b < nb; b += kBlock) {
+        const double *p = partials + 4 * (b0 + b);
         e += p[0];
         sd += p[1];
         m = fmax(m, p[2]);
@@ -211,7 +233,25 @@ __device__ void reduce_and_tail(SegState *s, const double *partials)
     sd = wave_sum(sd);
     m = wave_max(m);
     d = wave_max(d);
-    if (lane == 0) tail_logic(s, e, sd, m, d);
+    __shared__ double red[kWavesPerBlock][4];
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+    if (lane == 0) {
+        red[wv][0] = e;
+        red[wv][1] = sd;
+        red[wv][2] = m;
+        red[wv][3] = d;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        e = 0, sd = 0, m = 0, d = 0;
+        for (int k = 0; k < kWavesPerBlock; ++k) {
+            e += red[k][0];
+            sd += red[k][1];
+            m = fmax(m, red[k][2]);
+            d = fmax(d, red[k][3]);
+        }
+        tail_logic(s, e, sd, m, d);
+    }
 }
 
 template <bool kFusedTail>
@@ -245,15 +285,29 @@ __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ 
             const int32_t q0 = p.rp[i], q1 = p.rp[i + 1];
             if (q1 - q0 <= s->heavy_T) {
                 const double xi = X[i], yi = Y[i], zi = Z[i], di = D[i];
+                const Pre pre = preload(p, i);   // overlaps the neighbour gathers
                 Acc a = {0, 0, 0, 0, 0, 0, 0};
-                for (int32_t q = q0; q < q1; ++q) {
+                int32_t q = q0;
+                for (; q + 4 <= q1; q += 4) {
+                    const int32_t j0 = p.col[q], j1 = p.col[q + 1], j2 = p.col[q + 2],
+                                  j3 = p.col[q + 3];
+                    const double x0 = X[j0], y0 = Y[j0], z0 = Z[j0], e0 = D[j0];
+                    const double x1 = X[j1], y1 = Y[j1], z1 = Z[j1], e1 = D[j1];
+                    const double x2 = X[j2], y2 = Y[j2], z2 = Z[j2], e2 = D[j2];
+                    const double x3 = X[j3], y3 = Y[j3], z3 = Z[j3], e3 = D[j3];
+                    pair_term(a, xi, yi, zi, di, x0, y0, z0, e0, c.kappa, c.L, c.hL);
+                    pair_term(a, xi, yi, zi, di, x1, y1, z1, e1, c.kappa, c.L, c.hL);
+                    pair_term(a, xi, yi, zi, di, x2, y2, z2, e2, c.kappa, c.L, c.hL);
+                    pair_term(a, xi, yi, zi, di, x3, y3, z3, e3, c.kappa, c.L, c.hL);
+                }
+                for (; q < q1; ++q) {
                     const int32_t j = p.col[q];
                     pair_term(a, xi, yi, zi, di, X[j], Y[j], Z[j], D[j], c.kappa, c.L, c.hL);
                 }
                 be = a.e;
                 bs = a.s;
                 bm = a.m;
-                bd = update_particle(p, c, i, a.gx, a.gy, a.gz);
+                bd = update_particle(p, c, i, xi, yi, zi, pre, a.gx, a.gy, a.gz);
             }
         }
     } else {
@@ -279,7 +333,8 @@ __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ 
                 be += a.e;
                 bs += a.s;
                 bm = fmax(bm, a.m);
-                bd = fmax(bd, update_particle(p, c, i, a.gx, a.gy, a.gz));
+                bd = fmax(bd, update_particle(p, c, i, xi, yi, zi, preload(p, i), a.gx, a.gy,
+                                              a.gz));
             }
         }
     }
@@ -321,14 +376,14 @@ __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ 
         __syncthreads();
         if (last) {
             __threadfence();
-            if (threadIdx.x < kWave) reduce_and_tail(s, partials);
+            reduce_and_tail(s, partials);
             if (threadIdx.x == 0) s->ticket = 0;
         }
     }
 }
 
-__global__ __launch_bounds__(kWave) void k_tail(SegState *__restrict__ S,
-                                               const double *__restrict__ partials)
+__global__ __launch_bounds__(kBlock) void k_tail(SegState *__restrict__ S,
+                                                const double *__restrict__ partials)
 {
     SegState *s = S + blockIdx.x;
     if (s->flags & F_IDLE) return;
@@ -351,7 +406,7 @@ void launch_iterate(const SegPtrs *P, SegState *S, const WorkItem *W, double *pa
 
 void launch_tail(SegState *S, const double *partials, int nseg, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_tail, dim3(nseg), dim3(kWave), 0, st, S, partials);
+    hipLaunchKernelGGL(k_tail, dim3(nseg), dim3(kBlock), 0, st, S, partials);
 }
 
 // ------------------------------------------------------- small updates

@@ -21,12 +21,13 @@
 
 namespace rcp {
 
-__device__ __forceinline__ int64_t cell_coord(double v, double w, int32_t nc)
+// Cell of coordinate v in a class grid; the same expression is used when
+// keys are made and when a particle looks up its stencil, so the two agree.
+__device__ __forceinline__ int32_t cell_coord(double v, double inv_w, int32_t nc)
 {
-    int64_t c = (int64_t)(v / w);
-    if (c < 0) c = 0;
-    if (c >= nc) c = nc - 1;
-    return c;
+    int32_t c = (int32_t)(v * inv_w);
+    c = c < 0 ? 0 : c;
+    return c >= nc ? nc - 1 : c;
 }
 
 __global__ __launch_bounds__(kBlock) void k_keys(BuildArgs a, uint64_t *__restrict__ keys,
@@ -36,9 +37,9 @@ __global__ __launch_bounds__(kBlock) void k_keys(BuildArgs a, uint64_t *__restri
     if (i >= a.n) return;
     const int l = a.lev[i];
     const LevelGrid g = a.lv[l];
-    uint64_t cx = cell_coord(a.x[i], g.w, g.nc);
-    uint64_t cy = cell_coord(a.y[i], g.w, g.nc);
-    uint64_t cz = cell_coord(a.z[i], g.w, g.nc);
+    uint64_t cx = (uint64_t)cell_coord(a.x[i], g.inv_w, g.nc);
+    uint64_t cy = (uint64_t)cell_coord(a.y[i], g.inv_w, g.nc);
+    uint64_t cz = (uint64_t)cell_coord(a.z[i], g.inv_w, g.nc);
     keys[i] = ((uint64_t)l << a.mb) | morton3(cx, cy, cz);
     vals[i] = (uint32_t)i;
 }
@@ -76,12 +77,6 @@ void launch_permute(const PermArgs &p, hipStream_t s)
 }
 
 // ------------------------------------------------------------- hashing
-__global__ void k_fill_u64(uint64_t *__restrict__ p, int64_t n, uint64_t v)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-
 __global__ void k_fill_u32(uint32_t *__restrict__ p, int64_t n, uint32_t v)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -108,6 +103,12 @@ void launch_fill_f64(double *p, int64_t n, double v, hipStream_t s)
                        p, n, v);
 }
 
+__global__ void k_hash_clear(HashSlot *__restrict__ h, int64_t cap)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cap) h[i].key = kEmptyKey;
+}
+
 __global__ __launch_bounds__(kBlock) void k_hash_starts(BuildArgs a)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -116,11 +117,11 @@ __global__ __launch_bounds__(kBlock) void k_hash_starts(BuildArgs a)
     if (i > 0 && a.skey[i - 1] == key) return;
     uint64_t slot = hash64(key) & a.hmask;
     for (;;) {
-        unsigned long long prev = atomicCAS((unsigned long long *)&a.hkey[slot],
+        unsigned long long prev = atomicCAS((unsigned long long *)&a.hash[slot].key,
                                             (unsigned long long)kEmptyKey,
                                             (unsigned long long)key);
         if (prev == kEmptyKey || prev == key) {
-            a.hval[slot].x = (int)i;
+            a.hash[slot].start = (int32_t)i;
             return;
         }
         slot = (slot + 1) & a.hmask;
@@ -131,9 +132,9 @@ __device__ __forceinline__ int2 hash_find(const BuildArgs &a, uint64_t key)
 {
     uint64_t slot = hash64(key) & a.hmask;
     for (;;) {
-        const uint64_t k = a.hkey[slot];
-        if (k == key) return a.hval[slot];
-        if (k == kEmptyKey) return make_int2(0, 0);
+        const HashSlot e = a.hash[slot];
+        if (e.key == key) return make_int2(e.start, e.count);
+        if (e.key == kEmptyKey) return make_int2(0, 0);
         slot = (slot + 1) & a.hmask;
     }
 }
@@ -145,14 +146,14 @@ __global__ __launch_bounds__(kBlock) void k_hash_counts(BuildArgs a)
     const uint64_t key = a.skey[i];
     if (i + 1 < a.n && a.skey[i + 1] == key) return;
     uint64_t slot = hash64(key) & a.hmask;
-    while (a.hkey[slot] != key) slot = (slot + 1) & a.hmask;
-    a.hval[slot].y = (int)(i - a.hval[slot].x + 1);
+    while (a.hash[slot].key != key) slot = (slot + 1) & a.hmask;
+    a.hash[slot].count = (int32_t)(i - a.hash[slot].start + 1);
 }
 
 void launch_hash_build(const BuildArgs &a, int64_t cap, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((cap + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                       s, a.hkey, cap, kEmptyKey);
+    hipLaunchKernelGGL(k_hash_clear, dim3((unsigned)((cap + kBlock - 1) / kBlock)), dim3(kBlock),
+                       0, s, a.hash, cap);
     if (a.n <= 0) return;
     const dim3 g((unsigned)((a.n + kBlock - 1) / kBlock));
     hipLaunchKernelGGL(k_hash_starts, g, dim3(kBlock), 0, s, a);
@@ -160,141 +161,142 @@ void launch_hash_build(const BuildArgs &a, int64_t cap, hipStream_t s)
 }
 
 // ------------------------------------------------------- pair search
-// Half partners of particle i: same class with a larger sorted index, and
-// every larger class.  fill == 0 counts, fill == 1 writes.
-__global__ __launch_bounds__(kBlock) void k_half(BuildArgs a, uint32_t *__restrict__ cnt,
-                                                const uint32_t *__restrict__ ptr,
-                                                int32_t *__restrict__ col, int fill)
+constexpr int kSearchBuf = 3072;   // entries staged per block in LDS (24 KB)
+
+// Half partners of particle i are searched: same class with a larger sorted
+// index, and every larger class.  Each listed pair is appended in both
+// directions; a block stages its entries in LDS and reserves global space
+// with one atomic (entries that do not fit in LDS go straight to global
+// memory).  The order of the list is arbitrary; it is sorted afterwards.
+__global__ __launch_bounds__(kBlock) void k_search(BuildArgs a, uint64_t *__restrict__ list,
+                                                  uint32_t *__restrict__ counter, int64_t cap,
+                                                  int row_bits)
 {
+    __shared__ uint64_t buf[kSearchBuf];
+    __shared__ uint32_t nbuf;
+    __shared__ uint32_t gbase;
+    if (threadIdx.x == 0) nbuf = 0;
+    __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= a.n) return;
-    const double xi = a.x[i], yi = a.y[i], zi = a.z[i], di = a.d0[i];
-    const int li = a.lev[i];
-    uint32_t c = 0;
-    int32_t *out = fill ? col + ptr[i] : nullptr;
-    for (int L = li; L < a.nlev; ++L) {
-        const LevelGrid g = a.lv[L];
-        if (g.count == 0) continue;
-        const int64_t nc = g.nc;
-        const int64_t cx = cell_coord(xi, g.w, g.nc), cy = cell_coord(yi, g.w, g.nc),
-                      cz = cell_coord(zi, g.w, g.nc);
-        const int64_t lo = nc >= 3 ? -1 : 0, hi = nc >= 3 ? 1 : nc - 1;
-        for (int64_t ox = lo; ox <= hi; ++ox) {
-            const int64_t ax = nc >= 3 ? (cx + ox + nc) % nc : ox;
-            for (int64_t oy = lo; oy <= hi; ++oy) {
-                const int64_t ay = nc >= 3 ? (cy + oy + nc) % nc : oy;
-                for (int64_t oz = lo; oz <= hi; ++oz) {
-                    const int64_t az = nc >= 3 ? (cz + oz + nc) % nc : oz;
-                    const uint64_t key = ((uint64_t)L << a.mb) |
-                                         morton3((uint64_t)ax, (uint64_t)ay, (uint64_t)az);
-                    const int2 r = hash_find(a, key);
-                    for (int64_t j = r.x; j < (int64_t)r.x + r.y; ++j) {
-                        if (L == li && j <= i) continue;
-                        const double dx = min_image(a.x[j] - xi, a.L, a.hL);
-                        const double dy = min_image(a.y[j] - yi, a.L, a.hL);
-                        const double dz = min_image(a.z[j] - zi, a.L, a.hL);
-                        const double r2 = (dx * dx + dy * dy) + dz * dz;
-                        const double cc = a.kb * (a.opg * (0.5 * (di + a.d0[j])) + a.sk2);
-                        if (r2 < cc * cc) {
-                            if (fill) out[c] = (int32_t)j;
-                            ++c;
+    if (i < a.n) {
+        const double xi = a.x[i], yi = a.y[i], zi = a.z[i], di = a.d0[i];
+        const int li = a.lev[i];
+        const uint64_t rowi = (uint64_t)i << row_bits;
+        for (int L = li; L < a.nlev; ++L) {
+            const LevelGrid g = a.lv[L];
+            if (g.count == 0) continue;
+            const int32_t nc = g.nc;
+            // Stencil cells per axis.  With nc >= 3 the cell on one side is
+            // needed only if the particle is closer to that face than the
+            // largest cutoff it can have with a class-L partner (bound in cell
+            // units, with a margin far above the rounding of x * inv_w); with
+            // nc < 3 every cell is searched once.  Skipping a cell is exact.
+            const double cb =
+                a.kb * (a.opg * (0.5 * (di + g.dmax)) + a.sk2) * g.inv_w * (1.0 + 1e-9) + 1e-9;
+            uint64_t m[3][3];   // [axis][slot]: Morton parts of the lower, own, upper cell
+            bool use[3][3];
+            const double pos[3] = {xi, yi, zi};
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                const double fp = pos[ax] * g.inv_w;
+                const int32_t c = cell_coord(pos[ax], g.inv_w, nc);
+                if (nc >= 3) {
+                    const double f = fp - (double)c;
+                    const int32_t lo = c == 0 ? nc - 1 : c - 1, hi = c == nc - 1 ? 0 : c + 1;
+                    m[ax][0] = spread3((uint64_t)lo) << ax;
+                    m[ax][1] = spread3((uint64_t)c) << ax;
+                    m[ax][2] = spread3((uint64_t)hi) << ax;
+                    use[ax][0] = f < cb;
+                    use[ax][1] = true;
+                    use[ax][2] = 1.0 - f < cb;
+                } else {
+                    m[ax][0] = 0;
+                    m[ax][1] = spread3(1) << ax;
+                    m[ax][2] = 0;
+                    use[ax][0] = true;
+                    use[ax][1] = nc == 2;
+                    use[ax][2] = false;
+                }
+            }
+            const uint64_t base = (uint64_t)L << a.mb;
+#pragma unroll
+            for (int ox = 0; ox < 3; ++ox) {
+#pragma unroll
+                for (int oy = 0; oy < 3; ++oy) {
+#pragma unroll
+                    for (int oz = 0; oz < 3; ++oz) {
+                        if (!(use[0][ox] && use[1][oy] && use[2][oz])) continue;
+                        const uint64_t key = base | m[0][ox] | m[1][oy] | m[2][oz];
+                        const int2 r = hash_find(a, key);
+                        for (int64_t j = r.x; j < (int64_t)r.x + r.y; ++j) {
+                            if (L == li && j <= i) continue;
+                            const double dx = min_image(a.x[j] - xi, a.L, a.hL);
+                            const double dy = min_image(a.y[j] - yi, a.L, a.hL);
+                            const double dz = min_image(a.z[j] - zi, a.L, a.hL);
+                            const double r2 = (dx * dx + dy * dy) + dz * dz;
+                            const double cc = a.kb * (a.opg * (0.5 * (di + a.d0[j])) + a.sk2);
+                            if (r2 < cc * cc) {
+                                const uint64_t e0 = rowi | (uint64_t)j;
+                                const uint64_t e1 = ((uint64_t)j << row_bits) | (uint64_t)i;
+                                const uint32_t k = atomicAdd(&nbuf, 2u);
+                                if (k + 1 < (uint32_t)kSearchBuf) {
+                                    buf[k] = e0;
+                                    buf[k + 1] = e1;
+                                } else {
+                                    const uint32_t gi = atomicAdd(counter, 2u);
+                                    if ((int64_t)gi + 1 < cap) {
+                                        list[gi] = e0;
+                                        list[gi + 1] = e1;
+                                    }
+                                }
+                            }
                         }
                     }
                 }
             }
         }
     }
-    if (!fill) cnt[i] = c;
+    __syncthreads();
+    const uint32_t mm = nbuf < (uint32_t)kSearchBuf ? nbuf : (uint32_t)kSearchBuf;
+    if (threadIdx.x == 0) gbase = mm ? atomicAdd(counter, mm) : 0u;
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < mm; k += kBlock)
+        if ((int64_t)gbase + k < cap) list[gbase + k] = buf[k];
 }
 
-void launch_half(const BuildArgs &a, uint32_t *cnt, const uint32_t *ptr, int32_t *col, int fill,
-                 hipStream_t s)
+void launch_search(const BuildArgs &a, uint64_t *list, uint32_t *counter, int64_t cap,
+                   int row_bits, hipStream_t s)
 {
     if (a.n <= 0) return;
-    hipLaunchKernelGGL(k_half, dim3((unsigned)((a.n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                       a, cnt, ptr, col, fill);
+    hipLaunchKernelGGL(k_search, dim3((unsigned)((a.n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       s, a, list, counter, cap, row_bits);
 }
 
-// ------------------------------------------------------- full rows
-__global__ __launch_bounds__(kBlock) void k_in_count(int64_t n, const uint32_t *__restrict__ hp,
-                                                    const int32_t *__restrict__ hcol,
-                                                    uint32_t *__restrict__ in_cnt)
+// Row pointers and partners from the sorted entry list.  Entry q starts row
+// r = key >> row_bits; rows between the previous entry's row and r start at
+// q (empty rows included).  Thread m closes the rows after the last entry.
+__global__ __launch_bounds__(kBlock) void k_csr_from_sorted(const uint64_t *__restrict__ srt,
+                                                           int64_t m, int row_bits, int64_t n,
+                                                           int32_t *__restrict__ rp,
+                                                           int32_t *__restrict__ col)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    for (uint32_t q = hp[i]; q < hp[i + 1]; ++q) atomicAdd(&in_cnt[hcol[q]], 1u);
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q > m) return;
+    const uint64_t mask = (1ull << row_bits) - 1ull;
+    const int64_t prev = q == 0 ? -1 : (int64_t)(srt[q - 1] >> row_bits);
+    const int64_t r = q == m ? n : (int64_t)(srt[q] >> row_bits);
+    if (q < m) col[q] = (int32_t)(srt[q] & mask);
+    for (int64_t rr = prev + 1; rr <= r; ++rr) rp[rr] = (int32_t)q;
 }
 
-void launch_in_count(int64_t n, const uint32_t *hp, const int32_t *hcol, uint32_t *in_cnt,
-                     hipStream_t s)
+void launch_csr_from_sorted(const uint64_t *sorted, int64_t m, int row_bits, int64_t n,
+                            int32_t *rp, int32_t *col, hipStream_t s)
 {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_in_count, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                       s, n, hp, hcol, in_cnt);
+    hipLaunchKernelGGL(k_csr_from_sorted, dim3((unsigned)((m + 1 + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, s, sorted, m, row_bits, n, rp, col);
 }
 
-__global__ __launch_bounds__(kBlock) void k_pair_keys(int64_t n, const uint32_t *__restrict__ hp,
-                                                     const int32_t *__restrict__ hcol,
-                                                     uint64_t *__restrict__ keys,
-                                                     uint32_t *__restrict__ vals)
-{
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    for (uint32_t q = hp[i]; q < hp[i + 1]; ++q) {
-        keys[q] = (uint64_t)(uint32_t)hcol[q];
-        vals[q] = (uint32_t)i;
-    }
-}
-
-void launch_pair_keys(int64_t n, const uint32_t *hp, const int32_t *hcol, uint64_t *keys,
-                      uint32_t *vals, hipStream_t s)
-{
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_pair_keys, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                       s, n, hp, hcol, keys, vals);
-}
-
-__global__ __launch_bounds__(kBlock) void k_add_counts(int64_t n, const uint32_t *__restrict__ hp,
-                                                      const uint32_t *__restrict__ in_cnt,
-                                                      uint32_t *__restrict__ out)
-{
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    out[i] = (hp[i + 1] - hp[i]) + in_cnt[i];
-}
-
-void launch_add_counts(int64_t n, const uint32_t *hp, const uint32_t *in_cnt, uint32_t *out,
-                       hipStream_t s)
-{
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_add_counts, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                       s, n, hp, in_cnt, out);
-}
-
-// Row i = its half partners (search order) followed by the particles that
-// listed i (ascending index, from the stable sort by partner).
-__global__ __launch_bounds__(kBlock) void k_full_fill(int64_t n, const uint32_t *__restrict__ hp,
-                                                     const int32_t *__restrict__ hcol,
-                                                     const uint32_t *__restrict__ ip,
-                                                     const uint32_t *__restrict__ src,
-                                                     const uint32_t *__restrict__ rp,
-                                                     int32_t *__restrict__ col)
-{
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    uint32_t o = rp[i];
-    for (uint32_t q = hp[i]; q < hp[i + 1]; ++q) col[o++] = hcol[q];
-    for (uint32_t q = ip[i]; q < ip[i + 1]; ++q) col[o++] = (int32_t)src[q];
-}
-
-void launch_full_fill(int64_t n, const uint32_t *hp, const int32_t *hcol, const uint32_t *ip,
-                      const uint32_t *src, const uint32_t *rp, int32_t *col, hipStream_t s)
-{
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_full_fill, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                       s, n, hp, hcol, ip, src, rp, col);
-}
-
+// ------------------------------------------------------- heavy rows
 __global__ __launch_bounds__(kBlock) void k_heavy_mark(int64_t n, const uint32_t *__restrict__ rp,
                                                       int32_t T, uint32_t *__restrict__ flag)
 {

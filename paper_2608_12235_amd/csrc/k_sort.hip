@@ -134,6 +134,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint64_t *__restric
     hist[(int64_t)threadIdx.x * nt + blockIdx.x] = cnt[threadIdx.x];
 }
 
+template <bool kVals>
 __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint64_t *__restrict__ kin,
                                                          const uint32_t *__restrict__ vin,
                                                          uint64_t *__restrict__ kout,
@@ -154,7 +155,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint64_t *__rest
         const int64_t i = tile + r * kBlock + threadIdx.x;
         const bool valid = i < n;
         uint64_t key = valid ? kin[i] : 0ull;
-        uint32_t val = valid ? vin[i] : 0u;
+        uint32_t val = (kVals && valid) ? vin[i] : 0u;
         uint32_t d = valid ? (uint32_t)((key >> shift) & 255u) : 256u;
         uint64_t peers = ~0ull;
 #pragma unroll
@@ -170,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint64_t *__rest
             uint32_t pos = base[d] + rank;
             for (int k = 0; k < w; ++k) pos += wcnt[k][d];
             kout[pos] = key;
-            vout[pos] = val;
+            if (kVals) vout[pos] = val;
         }
         __syncthreads();
         uint32_t add = 0;
@@ -194,8 +195,28 @@ int radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nt), dim3(kBlock), 0, s, ki, n, shift,
                            nt, hist);
         scan_exclusive(hist, hist, 256 * nt, tile_tmp, total, s);
-        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nt), dim3(kBlock), 0, s, ki, vi, ko,
-                           vo, n, shift, nt, hist);
+        hipLaunchKernelGGL(k_radix_scatter<true>, dim3((unsigned)nt), dim3(kBlock), 0, s, ki, vi,
+                           ko, vo, n, shift, nt, hist);
+        parity ^= 1;
+    }
+    return parity;
+}
+
+int radix_sort_keys(uint64_t *k0, uint64_t *k1, int64_t n, int nbits, uint32_t *hist,
+                    uint32_t *tile_tmp, uint32_t *total, hipStream_t s)
+{
+    if (n <= 1) return 0;
+    const int64_t nt = (n + kTile - 1) / kTile;
+    int parity = 0;
+    for (int shift = 0; shift < nbits; shift += 8) {
+        const uint64_t *ki = parity ? k1 : k0;
+        uint64_t *ko = parity ? k0 : k1;
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nt), dim3(kBlock), 0, s, ki, n, shift,
+                           nt, hist);
+        scan_exclusive(hist, hist, 256 * nt, tile_tmp, total, s);
+        hipLaunchKernelGGL(k_radix_scatter<false>, dim3((unsigned)nt), dim3(kBlock), 0, s, ki,
+                           (const uint32_t *)nullptr, ko, (uint32_t *)nullptr, n, shift, nt,
+                           hist);
         parity ^= 1;
     }
     return parity;

@@ -14,10 +14,56 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
-#include <unordered_map>
 #include <vector>
 
 namespace rcp {
+
+// Open-addressing map from a cell key to the most recently placed sphere in
+// that cell (the rest of the cell's spheres follow through `next`).
+struct CellHeads {
+    std::vector<uint64_t> key;
+    std::vector<int64_t> head;
+    uint64_t mask = 0;
+    static constexpr uint64_t kEmpty = ~0ull;
+    void init(int64_t expected)
+    {
+        uint64_t cap = 16;
+        while (cap < (uint64_t)(2 * expected + 2)) cap <<= 1;
+        key.assign(cap, kEmpty);
+        head.assign(cap, -1);
+        mask = cap - 1;
+    }
+    static uint64_t mix(uint64_t k)
+    {
+        k ^= k >> 33;
+        k *= 0xff51afd7ed558ccdull;
+        k ^= k >> 33;
+        return k;
+    }
+    int64_t find(uint64_t k) const
+    {
+        for (uint64_t s = mix(k) & mask;; s = (s + 1) & mask) {
+            if (key[s] == k) return head[s];
+            if (key[s] == kEmpty) return -1;
+        }
+    }
+    // returns the previous head of the cell (or -1) and makes i the head
+    int64_t push(uint64_t k, int64_t i)
+    {
+        for (uint64_t s = mix(k) & mask;; s = (s + 1) & mask) {
+            if (key[s] == k) {
+                const int64_t prev = head[s];
+                head[s] = i;
+                return prev;
+            }
+            if (key[s] == kEmpty) {
+                key[s] = k;
+                head[s] = i;
+                return -1;
+            }
+        }
+    }
+};
 
 static inline uint64_t sm64_mix(uint64_t seed, uint64_t k)
 {
@@ -83,7 +129,12 @@ int place_rsa(int64_t n, const double *d0, double L, double kappa0, uint64_t see
         nc[c] = k;
         w[c] = L / (double)k;
     }
-    std::vector<std::unordered_map<uint64_t, int64_t>> head(ncls);
+    std::vector<CellHeads> head(ncls);
+    {
+        std::vector<int64_t> per(ncls, 0);
+        for (int64_t i = 0; i < n; ++i) per[cls[i]]++;
+        for (int c = 0; c < ncls; ++c) head[c].init(per[c]);
+    }
     std::vector<int64_t> next(n, -1);
     std::vector<int64_t> placed_in(ncls, 0);
     auto cell = [&](double v, int c) {
@@ -111,12 +162,11 @@ int place_rsa(int64_t n, const double *d0, double L, double kappa0, uint64_t see
                 for (int64_t ox = lo; ox <= hi && ok; ++ox)
                     for (int64_t oy = lo; oy <= hi && ok; ++oy)
                         for (int64_t oz = lo; oz <= hi && ok; ++oz) {
-                            const int64_t ax = m >= 3 ? (cx + ox + m) % m : ox;
-                            const int64_t ay = m >= 3 ? (cy + oy + m) % m : oy;
-                            const int64_t az = m >= 3 ? (cz + oz + m) % m : oz;
-                            auto it = head[c].find(key(ax, ay, az, c));
-                            if (it == head[c].end()) continue;
-                            for (int64_t j = it->second; j >= 0; j = next[j]) {
+                            auto wrap = [m](int64_t v) { return v < 0 ? v + m : (v >= m ? v - m : v); };
+                            const int64_t ax = m >= 3 ? wrap(cx + ox) : ox;
+                            const int64_t ay = m >= 3 ? wrap(cy + oy) : oy;
+                            const int64_t az = m >= 3 ? wrap(cz + oz) : oz;
+                            for (int64_t j = head[c].find(key(ax, ay, az, c)); j >= 0; j = next[j]) {
                                 const double dx = mimage(x[3 * j] - p[0], L, hL);
                                 const double dy = mimage(x[3 * j + 1] - p[1], L, hL);
                                 const double dz = mimage(x[3 * j + 2] - p[2], L, hL);
@@ -137,9 +187,7 @@ int place_rsa(int64_t n, const double *d0, double L, double kappa0, uint64_t see
         if (a == max_attempts) return -1;
         const int c = cls[i];
         const uint64_t kk = key(cell(x[3 * i], c), cell(x[3 * i + 1], c), cell(x[3 * i + 2], c), c);
-        auto it = head[c].find(kk);
-        next[i] = it == head[c].end() ? -1 : it->second;
-        head[c][kk] = i;
+        next[i] = head[c].push(kk, i);
         placed_in[c]++;
     }
     return 0;

@@ -14,12 +14,23 @@ void scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tile
 // + 1 entries.
 int radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, int nbits,
                uint32_t *hist, uint32_t *tile_tmp, uint32_t *total, hipStream_t s);
+// Same, keys only.
+int radix_sort_keys(uint64_t *k0, uint64_t *k1, int64_t n, int nbits, uint32_t *hist,
+                    uint32_t *tile_tmp, uint32_t *total, hipStream_t s);
 
 // -------------------------------------------------------- k_neighbor.hip
 struct LevelGrid {
-    double w;        // cell width (L / nc)
+    double inv_w;    // cells per unit length (nc / L); cell = floor(x * inv_w)
+    double dmax;     // largest D0 in the class
     int32_t nc;      // cells per axis
     int32_t count;   // particles in the class
+};
+
+// One occupied cell: its key and the run [start, start + count) of sorted
+// particles in it; 16 bytes so a probe is one load.
+struct alignas(16) HashSlot {
+    uint64_t key;
+    int32_t start, count;
 };
 
 // Everything one segment's list build needs, passed by value.
@@ -30,8 +41,7 @@ struct BuildArgs {
     const double *x, *y, *z, *d0;
     const uint8_t *lev;
     const uint64_t *skey;   // sorted keys (after the sort)
-    uint64_t *hkey;         // hash table of occupied cells
-    int2 *hval;             // (first particle, count)
+    struct HashSlot *hash;  // open-addressing table of occupied cells
     uint64_t hmask;
     LevelGrid lv[kMaxLevels];
 };
@@ -53,18 +63,15 @@ struct PermArgs {
 void launch_permute(const PermArgs &p, hipStream_t s);
 
 void launch_hash_build(const BuildArgs &a, int64_t cap, hipStream_t s);
-// fill == 0: cnt[i] = number of half partners; fill == 1: partners written
-// at col[ptr[i]..]
-void launch_half(const BuildArgs &a, uint32_t *cnt, const uint32_t *ptr, int32_t *col,
-                 int fill, hipStream_t s);
-void launch_in_count(int64_t n, const uint32_t *hp, const int32_t *hcol, uint32_t *in_cnt,
-                     hipStream_t s);
-void launch_pair_keys(int64_t n, const uint32_t *hp, const int32_t *hcol, uint64_t *keys,
-                      uint32_t *vals, hipStream_t s);
-void launch_add_counts(int64_t n, const uint32_t *hp, const uint32_t *in_cnt, uint32_t *out,
-                       hipStream_t s);
-void launch_full_fill(int64_t n, const uint32_t *hp, const int32_t *hcol, const uint32_t *ip,
-                      const uint32_t *src, const uint32_t *rp, int32_t *col, hipStream_t s);
+// One pass over the particles: every listed pair (i, j) is appended twice
+// to `list` as (row << row_bits) | col, rows and cols in sorted order, in an
+// arbitrary order; *counter (zeroed by the caller) receives the number of
+// entries, which may exceed cap (then only cap were stored).
+void launch_search(const BuildArgs &a, uint64_t *list, uint32_t *counter, int64_t cap,
+                   int row_bits, hipStream_t s);
+// Full rows from the sorted entry list: rp[0..n] and col[0..m).
+void launch_csr_from_sorted(const uint64_t *sorted, int64_t m, int row_bits, int64_t n,
+                            int32_t *rp, int32_t *col, hipStream_t s);
 void launch_heavy_mark(int64_t n, const uint32_t *rp, int32_t T, uint32_t *flag,
                        hipStream_t s);
 void launch_heavy_compact(int64_t n, const uint32_t *flag, const uint32_t *pos,

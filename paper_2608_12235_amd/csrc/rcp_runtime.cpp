@@ -91,6 +91,7 @@ struct Seg {
     uint64_t seed = 0;
     int nlev = 1;
     std::vector<double> dmax_upto;   // max D0 over classes <= l
+    std::vector<double> dmax_lev;    // max D0 in class l
     std::vector<int64_t> lev_count;
     // device arrays; D0, M, V, ORIG, LEV are double-buffered for the
     // Morton permutation (live set `set`), positions ping-pong through X
@@ -104,7 +105,7 @@ struct Seg {
     int64_t col_cap = 0;
     int set = 0;
     int cur = 0;          // host copy of the live position buffer
-    int64_t npairs = 0, nnz = 0, hcnt = 0;
+    int64_t npairs = 0, nnz = 0, hcnt = 0, list_est = 0;
     int heavy_blocks = 1, light_blocks = 0;
     int64_t rebuilds = 0;
     bool built = false;
@@ -128,13 +129,10 @@ struct rcp_ctx {
     int64_t kcap = 0, kcapB = 0, vcap = 0, vcapB = 0;
     uint32_t *hist = nullptr, *tiles = nullptr, *totals = nullptr;
     int64_t hist_cap = 0, tiles_cap = 0;
-    uint32_t *c0 = nullptr, *c1 = nullptr, *c2 = nullptr, *c3 = nullptr;
-    int64_t c0cap = 0, c1cap = 0, c2cap = 0, c3cap = 0;
-    int32_t *hcol = nullptr;
-    int64_t hcol_cap = 0;
-    uint64_t *hkey = nullptr;
-    int2 *hval = nullptr;
-    int64_t hkcap = 0, hvcap = 0;
+    uint32_t *c0 = nullptr, *c2 = nullptr;
+    int64_t c0cap = 0, c2cap = 0;
+    HashSlot *hash = nullptr;
+    int64_t hcap = 0;
     double *part = nullptr;          // evaluation partials
     int64_t part_cap = 0;
     double *out = nullptr;           // small device results
@@ -286,29 +284,30 @@ static int rebuild(rcp_ctx *c, int k, double kappa)
         int64_t nc = (int64_t)std::floor(s.L / h);
         nc = std::max<int64_t>(1, std::min<int64_t>(nc, (int64_t)1 << 19));
         a.lv[l].nc = (int32_t)nc;
-        a.lv[l].w = s.L / (double)nc;
+        a.lv[l].inv_w = (double)nc / s.L;
+        a.lv[l].dmax = s.dmax_lev[l];
         a.lv[l].count = (int32_t)s.lev_count[l];
         maxbits = std::max(maxbits, bits_for(nc - 1));
     }
     a.mb = 3 * maxbits;
     const int nbits = a.mb + bits_for(s.nlev - 1);
 
-    // scratch sized for the particle count (pairs are sized below)
-    CHK(dgrow(&c->kA, &c->kcap, n));
-    CHK(dgrow(&c->kB, &c->kcapB, n));
+    // scratch sized for the particle count and the expected pair-list length
+    const int row_bits = std::max(1, bits_for(n - 1));
+    int64_t lcap = std::max<int64_t>({n, s.list_est + s.list_est / 4, 8 * n, 1024});
+    CHK(dgrow(&c->kA, &c->kcap, lcap));
+    CHK(dgrow(&c->kB, &c->kcapB, lcap));
+    lcap = std::min(c->kcap, c->kcapB);
     CHK(dgrow(&c->vA, &c->vcap, n));
     CHK(dgrow(&c->vB, &c->vcapB, n));
-    const int64_t tiles = (n + 2047) / 2048 + 1;
+    const int64_t tiles = (lcap + 2047) / 2048 + 1;
     CHK(dgrow(&c->hist, &c->hist_cap, 256 * tiles + 1));
     CHK(dgrow(&c->tiles, &c->tiles_cap, 256 * tiles + 1));
     CHK(dgrow(&c->c0, &c->c0cap, n + 1));
-    CHK(dgrow(&c->c1, &c->c1cap, n + 1));
     CHK(dgrow(&c->c2, &c->c2cap, n + 1));
-    CHK(dgrow(&c->c3, &c->c3cap, n + 1));
     int64_t hcap = 64;
     while (hcap < 2 * n) hcap <<= 1;
-    CHK(dgrow(&c->hkey, &c->hkcap, hcap));
-    CHK(dgrow(&c->hval, &c->hvcap, hcap));
+    CHK(dgrow(&c->hash, &c->hcap, hcap));
 
     // 1. keys at the current positions, stable sort, permutation
     const int cur = s.cur, ncur = cur ^ 1, set = s.set, nset = set ^ 1;
@@ -351,45 +350,48 @@ static int rebuild(rcp_ctx *c, int k, double kappa)
     a.d0 = s.D0[nset];
     a.lev = s.LEV[nset];
     a.skey = skey;
-    a.hkey = c->hkey;
-    a.hval = c->hval;
+    a.hash = c->hash;
     a.hmask = (uint64_t)hcap - 1;
     launch_hash_build(a, hcap, st);
 
-    // 3. half partners: count, scan, fill
-    launch_half(a, c->c0, nullptr, nullptr, 0, st);
-    scan_exclusive(c->c0, c->c1, n, c->tiles, c->totals, st);
-    uint32_t tot = 0;
-    HIPCHK(hipMemcpyAsync(&tot, c->totals, sizeof tot, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    const int64_t P = tot;
-    if (2 * P >= (int64_t)INT32_MAX) return fail(RCP_ENOMEM, "pair count %lld too large", (long long)P);
-    CHK(dgrow(&c->hcol, &c->hcol_cap, P));
-    CHK(dgrow(&c->kA, &c->kcap, std::max<int64_t>(P, n)));
-    CHK(dgrow(&c->kB, &c->kcapB, std::max<int64_t>(P, n)));
-    CHK(dgrow(&c->vA, &c->vcap, std::max<int64_t>(P, n)));
-    CHK(dgrow(&c->vB, &c->vcapB, std::max<int64_t>(P, n)));
-    const int64_t ptiles = (P + 2047) / 2048 + 1;
-    CHK(dgrow(&c->hist, &c->hist_cap, 256 * ptiles + 1));
-    CHK(dgrow(&c->tiles, &c->tiles_cap, 256 * ptiles + 1));
-    if (2 * P > s.col_cap) {
+    // 3. one search pass appends every pair in both directions; the list
+    //    lives in whichever key buffer the Morton keys do not occupy
+    uint64_t *list = par ? c->kA : c->kB;
+    uint64_t *other = par ? c->kB : c->kA;
+    uint32_t total = 0;
+    for (int attempt = 0;; ++attempt) {
+        launch_fill_u32(c->totals + 2, 1, 0u, st);
+        launch_search(a, list, c->totals + 2, lcap, row_bits, st);
+        HIPCHK(hipMemcpyAsync(&total, c->totals + 2, sizeof total, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if ((int64_t)total <= lcap) break;
+        if (attempt > 0) return fail(RCP_ENOMEM, "pair list overflow after regrowth");
+        // grow both key buffers (the Morton keys in `other` are no longer needed
+        // once the hash is built) and search again
+        const bool list_is_A = (list == c->kA);
+        CHK(dgrow(&c->kA, &c->kcap, (int64_t)total));
+        CHK(dgrow(&c->kB, &c->kcapB, (int64_t)total));
+        lcap = std::min(c->kcap, c->kcapB);
+        const int64_t t2 = (lcap + 2047) / 2048 + 1;
+        CHK(dgrow(&c->hist, &c->hist_cap, 256 * t2 + 1));
+        CHK(dgrow(&c->tiles, &c->tiles_cap, 256 * t2 + 1));
+        list = list_is_A ? c->kA : c->kB;
+        other = list_is_A ? c->kB : c->kA;
+    }
+    const int64_t m = total;
+    const int64_t P = m / 2;
+    s.list_est = m;
+
+    // 4. sort the entries by (row, col): full rows, partners ascending
+    const int lp = radix_sort_keys(list, other, m, 2 * row_bits, c->hist, c->tiles, c->totals,
+                                   st);
+    const uint64_t *sorted = lp ? other : list;
+    if (m > s.col_cap) {
         dfree(s.col);
-        s.col_cap = std::max<int64_t>(2 * P + P / 2, 1024);
+        s.col_cap = std::max<int64_t>(m + m / 4, 1024);
         CHK(dalloc(&s.col, (size_t)s.col_cap));
     }
-    launch_half(a, nullptr, c->c1, c->hcol, 1, st);
-
-    // 4. transpose: in-degrees, partners sorted by target (stable), full rows
-    launch_fill_u32(c->c2, n, 0u, st);
-    launch_in_count(n, c->c1, c->hcol, c->c2, st);
-    launch_pair_keys(n, c->c1, c->hcol, c->kA, c->vA, st);
-    const int pp = radix_sort(c->kA, c->vA, c->kB, c->vB, P, std::max(1, bits_for(n - 1)),
-                              c->hist, c->tiles, c->totals, st);
-    const uint32_t *src = pp ? c->vB : c->vA;
-    scan_exclusive(c->c2, c->c3, n, c->tiles, c->totals, st);          // in pointers
-    launch_add_counts(n, c->c1, c->c2, c->c0, st);                     // full counts
-    scan_exclusive(c->c0, (uint32_t *)s.rp, n, c->tiles, c->totals, st);
-    launch_full_fill(n, c->c1, c->hcol, c->c3, src, (const uint32_t *)s.rp, s.col, st);
+    launch_csr_from_sorted(sorted, m, row_bits, n, s.rp, s.col, st);
 
     // 5. heavy rows
     launch_heavy_mark(n, (const uint32_t *)s.rp, c->tuning.heavy_threshold, c->c0, st);
@@ -612,6 +614,7 @@ static int seg_setup(rcp_ctx *c, int k, int64_t n, const double *d0, double L, d
         s.dmax_upto[lev[i]] = std::max(s.dmax_upto[lev[i]], d0[i]);
         s.lev_count[lev[i]]++;
     }
+    s.dmax_lev = s.dmax_upto;
     for (int l = 1; l < nlev; ++l) s.dmax_upto[l] = std::max(s.dmax_upto[l], s.dmax_upto[l - 1]);
     // placement
     std::vector<double> x(3 * n, 0.0);
@@ -714,12 +717,8 @@ static void destroy_ctx(rcp_ctx *c)
     dfree(c->tiles);
     dfree(c->totals);
     dfree(c->c0);
-    dfree(c->c1);
     dfree(c->c2);
-    dfree(c->c3);
-    dfree(c->hcol);
-    dfree(c->hkey);
-    dfree(c->hval);
+    dfree(c->hash);
     dfree(c->part);
     dfree(c->out);
     dfree(c->xtmp);
