@@ -58,7 +58,7 @@ def main():
     ap.add_argument("--skin-g", type=float, default=0.02)
     ap.add_argument("--graph-iters", type=int, default=None)
     ap.add_argument("--fused-tail", type=int, default=None)
-    ap.add_argument("--heavy", type=int, default=None)
+    ap.add_argument("--heavy-first", type=int, default=None)
     ap.add_argument("--xcd-remap", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -83,8 +83,8 @@ def main():
         tun.graph_iters = args.graph_iters
     if args.fused_tail is not None:
         tun.fused_tail = args.fused_tail
-    if args.heavy is not None:
-        tun.heavy_threshold = args.heavy
+    if args.heavy_first is not None:
+        tun.heavy_first = args.heavy_first
     if args.xcd_remap is not None:
         tun.xcd_remap = args.xcd_remap
     params = rcp.make_params(skin_s=args.skin, skin_g=args.skin_g)
@@ -134,13 +134,13 @@ def main():
             "skin_g": args.skin_g,
             "graph_iters": tun.graph_iters,
             "fused_tail": tun.fused_tail,
-            "heavy_threshold": tun.heavy_threshold,
+            "heavy_first": tun.heavy_first,
             "xcd_remap": tun.xcd_remap,
             "rebuilds_in_timed_region": st["rebuilds"],
             "rebuild_ms": st["rebuild_ms"],
             "iterate_ms": st["iterate_ms"],
             "nnz": nnz,
-            "n_heavy": st["n_heavy"],
+            "max_degree": st["max_degree"],
             "kernel_rate": w.n / kern_s,
         },
         "roofline": {

@@ -81,22 +81,21 @@ typedef struct {
 } rcp_params;
 
 /* Launch tuning (performance only; results do not depend on it except
- * through summation order).  size must be sizeof(rcp_tuning).
- *   heavy_threshold: rows with more listed partners than this are handled
- *     one wavefront per row, the rest one thread per row;
+ * through summation order, which is fixed for a given tuning).  size must
+ * be sizeof(rcp_tuning).
  *   graph_iters: iterations captured per HIP graph launch (1 = no graph);
- *   heavy_blocks: blocks reserved per packing for heavy rows (0 = auto);
  *   xcd_remap: 1 = map consecutive row blocks to the same XCD;
  *   fused_tail: 1 = the last block of a packing to finish an iteration
  *     reduces the partial sums and updates kappa and the schedule (one
- *     kernel per iteration), 0 = a separate one-block kernel does it. */
+ *     kernel per iteration), 0 = a separate one-block kernel does it;
+ *   heavy_first: 1 = dispatch the row blocks of the largest particles
+ *     (highest size classes, the longest rows) first. */
 typedef struct {
     uint32_t size;
-    int32_t heavy_threshold;
     int32_t graph_iters;
-    int32_t heavy_blocks;
     int32_t xcd_remap;
     int32_t fused_tail;
+    int32_t heavy_first;
 } rcp_tuning;
 
 /* Annealing schedule: a table of rungs run in order (App. A).  Rung r lasts
@@ -152,7 +151,7 @@ typedef struct {
     int64_t rebuilds;
     int64_t graph_launches;
     int64_t nnz;                /* listed partners (both directions) now        */
-    int64_t n_heavy;            /* rows handled one wavefront per row now       */
+    int64_t max_degree;         /* longest row of the current lists             */
     double iterate_ms;          /* time in iteration launches                   */
     double rebuild_ms;          /* time in neighbour-list builds                */
     double shrink_ms;

@@ -32,9 +32,8 @@ class Params(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("size", C.c_uint32), ("heavy_threshold", C.c_int32),
-                ("graph_iters", C.c_int32), ("heavy_blocks", C.c_int32),
-                ("xcd_remap", C.c_int32), ("fused_tail", C.c_int32)]
+    _fields_ = [("size", C.c_uint32), ("graph_iters", C.c_int32), ("xcd_remap", C.c_int32),
+                ("fused_tail", C.c_int32), ("heavy_first", C.c_int32)]
 
 
 class Schedule(C.Structure):
@@ -60,7 +59,7 @@ class Result(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("iterations", C.c_int64), ("particle_updates", C.c_int64),
                 ("rebuilds", C.c_int64), ("graph_launches", C.c_int64),
-                ("nnz", C.c_int64), ("n_heavy", C.c_int64), ("iterate_ms", C.c_double),
+                ("nnz", C.c_int64), ("max_degree", C.c_int64), ("iterate_ms", C.c_double),
                 ("rebuild_ms", C.c_double), ("shrink_ms", C.c_double)]
 
 

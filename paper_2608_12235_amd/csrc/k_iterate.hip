@@ -1,7 +1,6 @@
 // One inflation iteration on the device, for every active packing at once.
 //
-// k_iterate: for each particle i (light rows: one thread per row; heavy
-// rows: one wavefront per row) evaluate the overlap gradient of Eq. (energy)
+// k_iterate: for each particle i evaluate the overlap gradient of Eq. (energy)
 //     dE/dx_i = sum_j delta_ij / (d_ij r_ij) (x_j - x_i)_mi,
 //     delta = 1 - r/d,  d = kappa (D0_i + D0_j)/2,
 // over the listed partners with delta > 0, apply Adam (Kingma and Ba, bias
@@ -81,7 +80,7 @@ struct IterPtrs {
     const double *x, *y, *z, *d0;
     double *xo, *yo, *zo;
     double *m0, *m1, *m2, *v0, *v1, *v2, *r0, *r1, *r2;
-    const int32_t *rp, *col, *heavy;
+    const int32_t *rp, *col;
 };
 
 __device__ __forceinline__ IterPtrs select_ptrs(const SegPtrs *__restrict__ P, int seg, int cur)
@@ -106,7 +105,6 @@ __device__ __forceinline__ IterPtrs select_ptrs(const SegPtrs *__restrict__ P, i
     p.r2 = q.xref[2];
     p.rp = q.rp;
     p.col = q.col;
-    p.heavy = q.heavy;
     return p;
 }
 
@@ -254,13 +252,59 @@ __device__ void reduce_and_tail(SegState *s, const double *partials)
     }
 }
 
+// Entry loop of one row segment [q, qe): four partners per step so that
+// their gathers are in flight together.
+__device__ __forceinline__ void segment_terms(Acc &a, const int32_t *__restrict__ col,
+                                              const double *__restrict__ X,
+                                              const double *__restrict__ Y,
+                                              const double *__restrict__ Z,
+                                              const double *__restrict__ D, int32_t q, int32_t qe,
+                                              double xi, double yi, double zi, double di,
+                                              const IterScalars &c)
+{
+    for (; q + 4 <= qe; q += 4) {
+        const int32_t j0 = col[q], j1 = col[q + 1], j2 = col[q + 2], j3 = col[q + 3];
+        const double x0 = X[j0], y0 = Y[j0], z0 = Z[j0], e0 = D[j0];
+        const double x1 = X[j1], y1 = Y[j1], z1 = Z[j1], e1 = D[j1];
+        const double x2 = X[j2], y2 = Y[j2], z2 = Z[j2], e2 = D[j2];
+        const double x3 = X[j3], y3 = Y[j3], z3 = Z[j3], e3 = D[j3];
+        pair_term(a, xi, yi, zi, di, x0, y0, z0, e0, c.kappa, c.L, c.hL);
+        pair_term(a, xi, yi, zi, di, x1, y1, z1, e1, c.kappa, c.L, c.hL);
+        pair_term(a, xi, yi, zi, di, x2, y2, z2, e2, c.kappa, c.L, c.hL);
+        pair_term(a, xi, yi, zi, di, x3, y3, z3, e3, c.kappa, c.L, c.hL);
+    }
+    for (; q < qe; ++q) {
+        const int32_t j = col[q];
+        pair_term(a, xi, yi, zi, di, X[j], Y[j], Z[j], D[j], c.kappa, c.L, c.hL);
+    }
+}
+
+__device__ __forceinline__ void store6(double (*M)[kBlock], int k, const Acc &a)
+{
+    M[0][k] = a.gx;
+    M[1][k] = a.gy;
+    M[2][k] = a.gz;
+    M[3][k] = a.e;
+    M[4][k] = a.s;
+    M[5][k] = a.m;
+}
+
+// One iteration for a block of up to 256 consecutive rows of one packing.
+// Phase 1: the block's partner entries (contiguous in the CSR) are split in
+// equal chunks over the 256 threads, so a row with thousands of partners is
+// shared by many threads instead of serialising one.  A row lying inside one
+// chunk is summed by that thread alone; a row spanning chunks is summed as
+// (its piece in the chunk where it starts) + (the leading piece of every
+// later chunk it covers), in chunk order, so the result does not depend on
+// timing.  Phase 2: one thread per row applies Adam (coalesced).
 template <bool kFusedTail>
 __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ P,
                                                    SegState *__restrict__ S,
                                                    const WorkItem *__restrict__ W,
-                                                   double *__restrict__ partials, int xcd_remap)
+                                                   double *__restrict__ partials, int flags)
 {
-    const int b = xcd_remap ? remap_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+    int b = (flags & 1) ? remap_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+    if (flags & 4) b = (int)gridDim.x - 1 - b;   // largest particles (last rows) first
     const WorkItem w = W[b];
     SegState *s = S + w.seg;
     if (s->flags & F_IDLE) return;
@@ -277,74 +321,91 @@ __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ 
     const IterPtrs p = select_ptrs(P, w.seg, s->cur);
     const double *X = p.x, *Y = p.y, *Z = p.z, *D = p.d0;
 
-    double be = 0, bs = 0, bm = 0, bd = 0;
-    const int lane = threadIdx.x & (kWave - 1);
-    if (w.kind == 0) {
-        const int64_t i = w.begin + threadIdx.x;
-        if (i < w.end) {
-            const int32_t q0 = p.rp[i], q1 = p.rp[i + 1];
-            if (q1 - q0 <= s->heavy_T) {
-                const double xi = X[i], yi = Y[i], zi = Z[i], di = D[i];
-                const Pre pre = preload(p, i);   // overlaps the neighbour gathers
-                Acc a = {0, 0, 0, 0, 0, 0, 0};
-                int32_t q = q0;
-                for (; q + 4 <= q1; q += 4) {
-                    const int32_t j0 = p.col[q], j1 = p.col[q + 1], j2 = p.col[q + 2],
-                                  j3 = p.col[q + 3];
-                    const double x0 = X[j0], y0 = Y[j0], z0 = Z[j0], e0 = D[j0];
-                    const double x1 = X[j1], y1 = Y[j1], z1 = Z[j1], e1 = D[j1];
-                    const double x2 = X[j2], y2 = Y[j2], z2 = Z[j2], e2 = D[j2];
-                    const double x3 = X[j3], y3 = Y[j3], z3 = Z[j3], e3 = D[j3];
-                    pair_term(a, xi, yi, zi, di, x0, y0, z0, e0, c.kappa, c.L, c.hL);
-                    pair_term(a, xi, yi, zi, di, x1, y1, z1, e1, c.kappa, c.L, c.hL);
-                    pair_term(a, xi, yi, zi, di, x2, y2, z2, e2, c.kappa, c.L, c.hL);
-                    pair_term(a, xi, yi, zi, di, x3, y3, z3, e3, c.kappa, c.L, c.hL);
-                }
-                for (; q < q1; ++q) {
-                    const int32_t j = p.col[q];
-                    pair_term(a, xi, yi, zi, di, X[j], Y[j], Z[j], D[j], c.kappa, c.L, c.hL);
-                }
-                be = a.e;
-                bs = a.s;
-                bm = a.m;
-                bd = update_particle(p, c, i, xi, yi, zi, pre, a.gx, a.gy, a.gz);
-            }
+    __shared__ int32_t srp[kBlock + 1];
+    __shared__ double G[6][kBlock];   // complete rows
+    __shared__ double A[6][kBlock];   // leading piece of chunk t (row began earlier)
+    __shared__ double B[6][kBlock];   // trailing piece of chunk t (row goes on)
+    const int t = threadIdx.x;
+    const int64_t r0 = w.begin;
+    const int nrow = (int)(w.end - w.begin);
+    // phase-2 operands first: their latency hides behind phase 1
+    const int64_t io = r0 + t;
+    const bool own = t < nrow;
+    double oxi = 0, oyi = 0, ozi = 0;
+    Pre pre = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (own) {
+        oxi = X[io];
+        oyi = Y[io];
+        ozi = Z[io];
+        pre = preload(p, io);
+        srp[t] = p.rp[io];
+    }
+    if (t == 0) srp[nrow] = p.rp[r0 + nrow];
+    __syncthreads();
+
+    const int32_t e0 = srp[0], e1 = srp[nrow];
+    const int32_t chunk = max(1, (e1 - e0 + kBlock - 1) / kBlock);
+    const int32_t cs = e0 + t * chunk, ce = min(cs + chunk, e1);
+    if (cs < ce) {
+        int lo = 0, hi = nrow - 1;   // the row holding entry cs
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (srp[mid] <= cs) lo = mid;
+            else hi = mid - 1;
         }
-    } else {
-        const int wave = threadIdx.x / kWave;
-        const int64_t nw = w.end * kWavesPerBlock;
-        const int32_t hcnt = s->hcnt;
-        for (int64_t h = w.begin * kWavesPerBlock + wave; h < hcnt; h += nw) {
-            const int64_t i = p.heavy[h];
-            const int32_t q0 = p.rp[i], q1 = p.rp[i + 1];
+        int r = lo;
+        int32_t q = cs;
+        for (;;) {
+            const int64_t i = r0 + r;
             const double xi = X[i], yi = Y[i], zi = Z[i], di = D[i];
+            const int32_t rend = srp[r + 1], qe = min(rend, ce);
             Acc a = {0, 0, 0, 0, 0, 0, 0};
-            for (int32_t q = q0 + lane; q < q1; q += kWave) {
-                const int32_t j = p.col[q];
-                pair_term(a, xi, yi, zi, di, X[j], Y[j], Z[j], D[j], c.kappa, c.L, c.hL);
-            }
-            a.gx = wave_sum(a.gx);
-            a.gy = wave_sum(a.gy);
-            a.gz = wave_sum(a.gz);
-            a.e = wave_sum(a.e);
-            a.s = wave_sum(a.s);
-            a.m = wave_max(a.m);
-            if (lane == 0) {
-                be += a.e;
-                bs += a.s;
-                bm = fmax(bm, a.m);
-                bd = fmax(bd, update_particle(p, c, i, xi, yi, zi, preload(p, i), a.gx, a.gy,
-                                              a.gz));
-            }
+            segment_terms(a, p.col, X, Y, Z, D, q, qe, xi, yi, zi, di, c);
+            const bool began_before = srp[r] < cs, goes_on = rend > ce;
+            if (began_before) store6(A, t, a);
+            else if (goes_on) store6(B, t, a);
+            else store6(G, r, a);
+            q = qe;
+            if (q >= ce) break;
+            do {
+                ++r;
+            } while (srp[r + 1] <= q);   // skip rows without partners
         }
     }
+    __syncthreads();
+
+    double be = 0, bs = 0, bm = 0, bd = 0;
+    if (own) {
+        const int32_t qb = srp[t], qe = srp[t + 1];
+        double g[6] = {0, 0, 0, 0, 0, 0};
+        if (qb < qe) {
+            const int tf = (qb - e0) / chunk, tl = (qe - 1 - e0) / chunk;
+            if (tf == tl) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) g[k] = G[k][t];
+            } else {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) g[k] = B[k][tf];
+                for (int u = tf + 1; u <= tl; ++u) {
+#pragma unroll
+                    for (int k = 0; k < 5; ++k) g[k] += A[k][u];
+                    g[5] = fmax(g[5], A[5][u]);
+                }
+            }
+        }
+        be = g[3];
+        bs = g[4];
+        bm = g[5];
+        bd = update_particle(p, c, io, oxi, oyi, ozi, pre, g[0], g[1], g[2]);
+    }
     // block reduction of the four partials
+    const int lane = t & (kWave - 1);
     be = wave_sum(be);
     bs = wave_sum(bs);
     bm = wave_max(bm);
     bd = wave_max(bd);
     __shared__ double red[kWavesPerBlock][4];
-    const int wv = threadIdx.x / kWave;
+    const int wv = t / kWave;
     if (lane == 0) {
         red[wv][0] = be;
         red[wv][1] = bs;
@@ -352,7 +413,7 @@ __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ 
         red[wv][3] = bd;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (t == 0) {
         double e = 0, sd = 0, m = 0, d = 0;
         for (int k = 0; k < kWavesPerBlock; ++k) {
             e += red[k][0];
@@ -369,7 +430,7 @@ __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ 
     if (kFusedTail) {
         __shared__ int last;
         __threadfence();
-        if (threadIdx.x == 0) {
+        if (t == 0) {
             const uint32_t prev = atomicAdd(&s->ticket, 1u);
             last = (prev == (uint32_t)s->nblocks - 1u);
         }
@@ -377,7 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ 
         if (last) {
             __threadfence();
             reduce_and_tail(s, partials);
-            if (threadIdx.x == 0) s->ticket = 0;
+            if (t == 0) s->ticket = 0;
         }
     }
 }
@@ -391,16 +452,16 @@ __global__ __launch_bounds__(kBlock) void k_tail(SegState *__restrict__ S,
 }
 
 void launch_iterate(const SegPtrs *P, SegState *S, const WorkItem *W, double *partials,
-                    int nitems, int xcd_remap, hipStream_t st)
+                    int nitems, int flags, hipStream_t st)
 {
-    // xcd_remap bit 1 selects the fused tail (last block of a packing runs it)
-    const int remap = xcd_remap & 1;
-    if (xcd_remap & 2) {
+    // bit 0: XCD-aware order; bit 1: fused tail; bit 2: last rows first
+    const int f = flags & 5;
+    if (flags & 2) {
         hipLaunchKernelGGL(k_iterate<true>, dim3(nitems), dim3(kBlock), 0, st, P, S, W,
-                           partials, remap);
+                           partials, f);
     } else {
         hipLaunchKernelGGL(k_iterate<false>, dim3(nitems), dim3(kBlock), 0, st, P, S, W,
-                           partials, remap);
+                           partials, f);
     }
 }
 
@@ -411,22 +472,22 @@ void launch_tail(SegState *S, const double *partials, int nseg, hipStream_t st)
 
 // ------------------------------------------------------- small updates
 __global__ void k_after_build(SegState *S, int seg, double kb, double disp_lim2,
-                              double kappa_lim, int cur, const uint32_t *hcnt)
+                              double kappa_lim, int cur, const uint32_t *maxdeg)
 {
     SegState *s = S + seg;
     s->kb = kb;
     s->disp_lim2 = disp_lim2;
     s->kappa_lim = kappa_lim;
     s->cur = cur;
-    s->hcnt = (int32_t)*hcnt;
+    s->maxdeg = (int32_t)*maxdeg;
     s->flags &= ~(F_REBUILD | F_STALE);
 }
 
 void launch_after_build(SegState *S, int seg, double kb, double disp_lim2, double kappa_lim,
-                        int cur, const uint32_t *hcnt_dev, hipStream_t st)
+                        int cur, const uint32_t *maxdeg_dev, hipStream_t st)
 {
     hipLaunchKernelGGL(k_after_build, dim3(1), dim3(1), 0, st, S, seg, kb, disp_lim2, kappa_lim,
-                       cur, hcnt_dev);
+                       cur, maxdeg_dev);
 }
 
 __global__ void k_sched_start(SegState *S, int seg, SchedDev q, int reset_adam,
@@ -467,7 +528,7 @@ void launch_set_flags(SegState *S, int seg, int32_t clear, int32_t set, hipStrea
 }
 
 // ------------------------------------------------------- evaluation
-// Thread per row over the whole list (every row, heavy or not); positions
+// Thread per row over the whole list (not on the iteration path); positions
 // from the user-order array xu (gathered through orig) or from the current
 // buffer.  Partials per block: E_ov, S, max delta, overlapping pairs.
 __global__ __launch_bounds__(kBlock) void k_eval(const SegPtrs *__restrict__ P,

@@ -109,13 +109,22 @@ __global__ void k_hash_clear(HashSlot *__restrict__ h, int64_t cap)
     if (i < cap) h[i].key = kEmptyKey;
 }
 
+// Home slot of a cell key.  The low three Morton bits (a 2x2x2 block of
+// cells) stay together in one 8-slot group (one 128-byte line); the groups
+// themselves are scattered by hashing the remaining bits, so a 27-cell
+// stencil touches about eight lines and Morton-adjacent particles share them.
+__device__ __forceinline__ uint64_t hash_slot(uint64_t key, uint64_t mask)
+{
+    return ((hash64(key >> 3) << 3) | (key & 7ull)) & mask;
+}
+
 __global__ __launch_bounds__(kBlock) void k_hash_starts(BuildArgs a)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= a.n) return;
     const uint64_t key = a.skey[i];
     if (i > 0 && a.skey[i - 1] == key) return;
-    uint64_t slot = hash64(key) & a.hmask;
+    uint64_t slot = hash_slot(key, a.hmask);
     for (;;) {
         unsigned long long prev = atomicCAS((unsigned long long *)&a.hash[slot].key,
                                             (unsigned long long)kEmptyKey,
@@ -130,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_hash_starts(BuildArgs a)
 
 __device__ __forceinline__ int2 hash_find(const BuildArgs &a, uint64_t key)
 {
-    uint64_t slot = hash64(key) & a.hmask;
+    uint64_t slot = hash_slot(key, a.hmask);
     for (;;) {
         const HashSlot e = a.hash[slot];
         if (e.key == key) return make_int2(e.start, e.count);
@@ -145,7 +154,7 @@ __global__ __launch_bounds__(kBlock) void k_hash_counts(BuildArgs a)
     if (i >= a.n) return;
     const uint64_t key = a.skey[i];
     if (i + 1 < a.n && a.skey[i + 1] == key) return;
-    uint64_t slot = hash64(key) & a.hmask;
+    uint64_t slot = hash_slot(key, a.hmask);
     while (a.hash[slot].key != key) slot = (slot + 1) & a.hmask;
     a.hash[slot].count = (int32_t)(i - a.hash[slot].start + 1);
 }
@@ -296,38 +305,21 @@ void launch_csr_from_sorted(const uint64_t *sorted, int64_t m, int row_bits, int
                        dim3(kBlock), 0, s, sorted, m, row_bits, n, rp, col);
 }
 
-// ------------------------------------------------------- heavy rows
-__global__ __launch_bounds__(kBlock) void k_heavy_mark(int64_t n, const uint32_t *__restrict__ rp,
-                                                      int32_t T, uint32_t *__restrict__ flag)
+// ------------------------------------------------------- statistics
+__global__ __launch_bounds__(kBlock) void k_max_degree(int64_t n, const int32_t *__restrict__ rp,
+                                                      uint32_t *__restrict__ out)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    flag[i] = (rp[i + 1] - rp[i]) > (uint32_t)T ? 1u : 0u;
+    uint32_t d = i < n ? (uint32_t)(rp[i + 1] - rp[i]) : 0u;
+    for (int o = kWave / 2; o > 0; o >>= 1) d = max(d, (uint32_t)__shfl_xor(d, o, kWave));
+    if ((threadIdx.x & (kWave - 1)) == 0 && d) atomicMax(out, d);
 }
 
-void launch_heavy_mark(int64_t n, const uint32_t *rp, int32_t T, uint32_t *flag, hipStream_t s)
+void launch_max_degree(int64_t n, const int32_t *rp, uint32_t *out, hipStream_t s)
 {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_heavy_mark, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                       s, n, rp, T, flag);
-}
-
-__global__ __launch_bounds__(kBlock) void k_heavy_compact(int64_t n,
-                                                         const uint32_t *__restrict__ flag,
-                                                         const uint32_t *__restrict__ pos,
-                                                         int32_t *__restrict__ heavy)
-{
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    if (flag[i]) heavy[pos[i]] = (int32_t)i;
-}
-
-void launch_heavy_compact(int64_t n, const uint32_t *flag, const uint32_t *pos, int32_t *heavy,
-                          hipStream_t s)
-{
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_heavy_compact, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
-                       0, s, n, flag, pos, heavy);
+    hipLaunchKernelGGL(k_max_degree, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       s, n, rp, out);
 }
 
 }  // namespace rcp

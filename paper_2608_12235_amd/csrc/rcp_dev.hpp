@@ -46,7 +46,6 @@ struct SegPtrs {
     uint8_t *lev;         // size class
     int32_t *rp;          // row pointers (n + 1) into col
     int32_t *col;         // partners (segment-local sorted indices)
-    int32_t *heavy;       // rows with more than heavy_T partners
 };
 
 // Scalars of one segment.  "host" fields are set by the host; the rest are
@@ -56,12 +55,12 @@ struct SegState {
     int64_t n;
     double L, hL, d0min, sumd0;
     double beta1, beta2, eps_x, eps_k;
-    int32_t heavy_T;
+    int32_t pad_h;
     int32_t nblocks;      // iteration-grid blocks of this segment
     int64_t bfirst;       // first of them (index into the work table)
     // set at each list build (k_after_build)
     double kb, disp_lim2, kappa_lim;
-    int32_t hcnt, pad0;
+    int32_t maxdeg, pad0;
     // optimiser and schedule state
     double kappa, mk, vk, b1t, b2t, mu, eta_x, eta_k;
     int64_t t, it_rung, iters, iter_limit;
@@ -72,11 +71,10 @@ struct SegState {
     SchedDev sched;
 };
 
-// One block of the iteration grid.
+// One block of the iteration grid: rows [begin, end) of packing seg.
 struct WorkItem {
     int32_t seg;
-    int32_t kind;         // 0: rows [begin, end) one thread per row;
-                          // 1: heavy rows, block `begin` of `end` heavy blocks
+    int32_t pad;
     int64_t begin, end;
 };
 

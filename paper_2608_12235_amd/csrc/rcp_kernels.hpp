@@ -72,23 +72,22 @@ void launch_search(const BuildArgs &a, uint64_t *list, uint32_t *counter, int64_
 // Full rows from the sorted entry list: rp[0..n] and col[0..m).
 void launch_csr_from_sorted(const uint64_t *sorted, int64_t m, int row_bits, int64_t n,
                             int32_t *rp, int32_t *col, hipStream_t s);
-void launch_heavy_mark(int64_t n, const uint32_t *rp, int32_t T, uint32_t *flag,
-                       hipStream_t s);
-void launch_heavy_compact(int64_t n, const uint32_t *flag, const uint32_t *pos,
-                          int32_t *heavy, hipStream_t s);
+// *out = longest row (max rp[i+1] - rp[i]); out must be zeroed first.
+void launch_max_degree(int64_t n, const int32_t *rp, uint32_t *out, hipStream_t s);
 void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 void launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 
 // -------------------------------------------------------- k_iterate.hip
 // flags bit 0: XCD-aware block order; bit 1: the last block of each packing
-// runs its tail (otherwise launch_tail must follow).
+// runs its tail (otherwise launch_tail must follow); bit 2: blocks of the
+// last rows (largest particles) first.
 void launch_iterate(const SegPtrs *P, SegState *S, const WorkItem *W, double *partials,
                     int nitems, int flags, hipStream_t s);
 void launch_tail(SegState *S, const double *partials, int nseg, hipStream_t s);
 // After a list build of segment seg: kb, validity limits, current buffer,
-// heavy count (read from hcnt_dev), clear REBUILD / STALE.
+// longest row (read from maxdeg_dev), clear REBUILD / STALE.
 void launch_after_build(SegState *S, int seg, double kb, double disp_lim2, double kappa_lim,
-                        int cur, const uint32_t *hcnt_dev, hipStream_t s);
+                        int cur, const uint32_t *maxdeg_dev, hipStream_t s);
 // Start a schedule on segment seg: copy the table, reset the position in it,
 // set the first rung's parameters from the current kappa.
 void launch_sched_start(SegState *S, int seg, const SchedDev &q, int reset_adam,

@@ -101,12 +101,12 @@ struct Seg {
     int32_t *ORIG[2] = {};
     uint8_t *LEV[2] = {};
     double *XREF[3] = {};
-    int32_t *rp = nullptr, *col = nullptr, *heavy = nullptr;
+    int32_t *rp = nullptr, *col = nullptr;
     int64_t col_cap = 0;
     int set = 0;
     int cur = 0;          // host copy of the live position buffer
-    int64_t npairs = 0, nnz = 0, hcnt = 0, list_est = 0;
-    int heavy_blocks = 1, light_blocks = 0;
+    int64_t npairs = 0, nnz = 0, maxdeg = 0, list_est = 0;
+    int blocks = 0;
     int64_t rebuilds = 0;
     bool built = false;
 };
@@ -129,8 +129,6 @@ struct rcp_ctx {
     int64_t kcap = 0, kcapB = 0, vcap = 0, vcapB = 0;
     uint32_t *hist = nullptr, *tiles = nullptr, *totals = nullptr;
     int64_t hist_cap = 0, tiles_cap = 0;
-    uint32_t *c0 = nullptr, *c2 = nullptr;
-    int64_t c0cap = 0, c2cap = 0;
     HashSlot *hash = nullptr;
     int64_t hcap = 0;
     double *part = nullptr;          // evaluation partials
@@ -161,7 +159,6 @@ static void ptrs_of(const Seg &s, SegPtrs &p)
     p.lev = s.LEV[s.set];
     p.rp = s.rp;
     p.col = s.col;
-    p.heavy = s.heavy;
 }
 
 static int upload_ptrs(rcp_ctx *c, int k)
@@ -193,36 +190,19 @@ static int put_field(rcp_ctx *c, int k, size_t offset, const T &v)
 }
 
 // ------------------------------------------------------------ work table
-static int auto_heavy_blocks(const rcp_ctx *c, const Seg &s)
-{
-    if (c->tuning.heavy_blocks > 0) return c->tuning.heavy_blocks;
-    // two heavy rows per wavefront on average, at least one block
-    int64_t hb = (s.hcnt + 2 * kWavesPerBlock - 1) / (2 * kWavesPerBlock);
-    return (int)std::max<int64_t>(1, std::min<int64_t>(hb, 2048));
-}
-
 static int build_work(rcp_ctx *c)
 {
     std::vector<WorkItem> items;
     for (size_t k = 0; k < c->segs.size(); ++k) {
         Seg &s = c->segs[k];
         const int64_t first = (int64_t)items.size();
-        s.light_blocks = (int)((s.n + kBlock - 1) / kBlock);
-        for (int64_t b = 0; b < s.light_blocks; ++b) {
+        s.blocks = (int)((s.n + kBlock - 1) / kBlock);
+        for (int64_t b = 0; b < s.blocks; ++b) {
             WorkItem w;
             w.seg = (int)k;
-            w.kind = 0;
+            w.pad = 0;
             w.begin = b * kBlock;
             w.end = std::min<int64_t>(s.n, (b + 1) * kBlock);
-            items.push_back(w);
-        }
-        s.heavy_blocks = auto_heavy_blocks(c, s);
-        for (int b = 0; b < s.heavy_blocks; ++b) {
-            WorkItem w;
-            w.seg = (int)k;
-            w.kind = 1;
-            w.begin = b;
-            w.end = s.heavy_blocks;
             items.push_back(w);
         }
         const int32_t nb = (int32_t)(items.size() - first);
@@ -303,8 +283,6 @@ static int rebuild(rcp_ctx *c, int k, double kappa)
     const int64_t tiles = (lcap + 2047) / 2048 + 1;
     CHK(dgrow(&c->hist, &c->hist_cap, 256 * tiles + 1));
     CHK(dgrow(&c->tiles, &c->tiles_cap, 256 * tiles + 1));
-    CHK(dgrow(&c->c0, &c->c0cap, n + 1));
-    CHK(dgrow(&c->c2, &c->c2cap, n + 1));
     int64_t hcap = 64;
     while (hcap < 2 * n) hcap <<= 1;
     CHK(dgrow(&c->hash, &c->hcap, hcap));
@@ -393,40 +371,35 @@ static int rebuild(rcp_ctx *c, int k, double kappa)
     }
     launch_csr_from_sorted(sorted, m, row_bits, n, s.rp, s.col, st);
 
-    // 5. heavy rows
-    launch_heavy_mark(n, (const uint32_t *)s.rp, c->tuning.heavy_threshold, c->c0, st);
-    scan_exclusive(c->c0, c->c2, n, c->tiles, c->totals + 1, st);
-    launch_heavy_compact(n, c->c0, c->c2, s.heavy, st);
+    // 5. longest row (statistics)
+    launch_fill_u32(c->totals + 1, 1, 0u, st);
+    launch_max_degree(n, s.rp, c->totals + 1, st);
 
     const double lim = sk * kappa * s.d0min * (1.0 - 1e-9);
     launch_after_build(c->d_state, k, kappa, lim * lim, opg * kappa * (1.0 - 1e-12), ncur,
                        c->totals + 1, st);
     HIPCHK(hipEventRecord(c->e1, st));
-    uint32_t hc = 0;
-    HIPCHK(hipMemcpyAsync(&hc, c->totals + 1, sizeof hc, hipMemcpyDeviceToHost, st));
+    uint32_t md = 0;
+    HIPCHK(hipMemcpyAsync(&md, c->totals + 1, sizeof md, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, c->e0, c->e1));
     c->stats.rebuild_ms += ms;
     c->stats.rebuilds += 1;
-    const int64_t old_hb = auto_heavy_blocks(c, s);
-    s.hcnt = hc;
+    s.maxdeg = md;
     s.npairs = P;
     s.nnz = 2 * P;
     s.rebuilds += 1;
     s.built = true;
     CHK(upload_ptrs(c, k));
-    // re-plan the heavy blocks when the heavy-row count moved a lot
-    const int64_t new_hb = auto_heavy_blocks(c, s);
-    if (new_hb > 2 * s.heavy_blocks || 4 * new_hb < s.heavy_blocks) CHK(build_work(c));
-    (void)old_hb;
     return RCP_OK;
 }
 
 // ------------------------------------------------------------ iteration loop
 static void launch_one_iteration(rcp_ctx *c)
 {
-    const int flags = (c->tuning.xcd_remap ? 1 : 0) | (c->tuning.fused_tail ? 2 : 0);
+    const int flags = (c->tuning.xcd_remap ? 1 : 0) | (c->tuning.fused_tail ? 2 : 0) |
+                      (c->tuning.heavy_first ? 4 : 0);
     launch_iterate(c->d_ptrs, c->d_state, c->d_work, c->d_partials, c->nitems, flags, c->stream);
     if (!c->tuning.fused_tail) launch_tail(c->d_state, c->d_partials, (int)c->segs.size(), c->stream);
 }
@@ -639,7 +612,6 @@ static int seg_setup(rcp_ctx *c, int k, int64_t n, const double *d0, double L, d
     }
     for (int a = 0; a < 3; ++a) CHK(dalloc(&s.XREF[a], n));
     CHK(dalloc(&s.rp, n + 1));
-    CHK(dalloc(&s.heavy, n));
     s.col_cap = std::max<int64_t>(8 * n, 1024);
     CHK(dalloc(&s.col, s.col_cap));
     std::vector<double> soa(n);
@@ -671,7 +643,6 @@ static int seg_setup(rcp_ctx *c, int k, int64_t n, const double *d0, double L, d
     st.beta2 = c->params.beta2;
     st.eps_x = c->params.eps_x > 0 ? c->params.eps_x : 1e-12 / (kappa0 * s.d0max);
     st.eps_k = c->params.eps_k;
-    st.heavy_T = c->tuning.heavy_threshold;
     st.kappa = kappa0;
     st.b1t = 1.0;
     st.b2t = 1.0;
@@ -703,7 +674,6 @@ static void destroy_ctx(rcp_ctx *c)
         for (int a = 0; a < 3; ++a) dfree(s.XREF[a]);
         dfree(s.rp);
         dfree(s.col);
-        dfree(s.heavy);
     }
     dfree(c->d_ptrs);
     dfree(c->d_state);
@@ -716,8 +686,6 @@ static void destroy_ctx(rcp_ctx *c)
     dfree(c->hist);
     dfree(c->tiles);
     dfree(c->totals);
-    dfree(c->c0);
-    dfree(c->c2);
     dfree(c->hash);
     dfree(c->part);
     dfree(c->out);
@@ -756,11 +724,10 @@ void rcp_tuning_default(rcp_tuning *t)
     if (!t) return;
     std::memset(t, 0, sizeof *t);
     t->size = sizeof(rcp_tuning);
-    t->heavy_threshold = 48;
     t->graph_iters = 16;
-    t->heavy_blocks = 0;
     t->xcd_remap = 1;
     t->fused_tail = 0;
+    t->heavy_first = 1;
 }
 
 // Default rung table (our reading of App. A; the paper does not list its
@@ -876,19 +843,9 @@ int rcp_pack_init(int dim, const double *box, int64_t n, const double *d0, doubl
 int rcp_set_tuning(rcp_ctx *c, const rcp_tuning *t)
 {
     if (!c || !t || t->size != sizeof(rcp_tuning)) return fail(RCP_EINVAL, "bad tuning");
-    if (t->heavy_threshold < 0 || t->graph_iters < 1 || t->heavy_blocks < 0)
-        return fail(RCP_EINVAL, "bad tuning values");
-    const bool replan = t->heavy_threshold != c->tuning.heavy_threshold ||
-                        t->heavy_blocks != c->tuning.heavy_blocks;
+    if (t->graph_iters < 1 || t->graph_iters > 4096) return fail(RCP_EINVAL, "bad tuning values");
     c->tuning = *t;
     c->graph_valid = false;
-    if (replan) {
-        for (size_t k = 0; k < c->segs.size(); ++k) {
-            CHK(put_field(c, (int)k, offsetof(SegState, heavy_T), (int32_t)t->heavy_threshold));
-            launch_set_flags(c->d_state, (int)k, 0, F_STALE, c->stream);
-        }
-        CHK(build_work(c));
-    }
     return RCP_OK;
 }
 
@@ -1257,10 +1214,10 @@ int rcp_get_stats(rcp_ctx *c, rcp_stats *s)
     if (!c || !s) return fail(RCP_EINVAL, "null argument");
     *s = c->stats;
     s->nnz = 0;
-    s->n_heavy = 0;
+    s->max_degree = 0;
     for (auto &g : c->segs) {
         s->nnz += g.nnz;
-        s->n_heavy += g.hcnt;
+        s->max_degree = std::max(s->max_degree, g.maxdeg);
     }
     return RCP_OK;
 }
