@@ -2,25 +2,31 @@
 """Throughput of the inflation hot path on one MI355X.
 
 Workload: N = 1e6 relative diameters from the truncated lognormal with
-sigma_lnD = 1.0 and S = 1e3 (equal-probability quantiles), i.i.d. uniform
-positions at phi = 0.6 in a periodic cube, FP64 throughout.  One step is one
-inflation iteration of the default schedule's densification rung: energy
-gradient over the neighbour list, Adam on positions and kappa, the tail
-(schedule, stop and validity tests), and a list rebuild whenever the
-validity test asks for one.  value = N x iterations / wall time.
+sigma_lnD = 1.0 and S = 1e3 (equal-probability quantiles), placed by random
+sequential addition at phi0 = 0.05 in a periodic cube (the paper's dilute,
+non-overlapping start), FP64 throughout, the default schedule for that size
+ratio.  One step is one inflation iteration: energy gradient over the
+neighbour list, Adam on positions and kappa, the tail (schedule, stop and
+validity tests), and a list rebuild whenever the validity test asks for
+one.  After W untimed iterations, K iterations are timed;
+value = N x K / wall time.
 
 The roofline entry is for the fused gradient + Adam kernel (k_iterate):
-algorithmic bytes per launch = 180 N + 4 nnz (read x, D0, m, v, x_ref and
-one row pointer, write x, m, v; 4 bytes per listed partner), divided by the
-launch's average duration from HIP events recorded by the library on its
-stream over the timed region.  The CPU baseline is the FP64 oracle
-(OpenMP over rows) on the same state, gradient + Adam only.
+algorithmic bytes per launch = 188 N + 4 nnz (read x, y, z, D0 as one
+32-byte record, m, v, x_ref and a row pointer; write the position record,
+m and v; 4 bytes per listed partner; partner gathers are assumed
+cache-served), divided by its mean duration from HIP events recorded by
+the library on its stream around each launch over 256 iterations that
+follow the timed region.  The CPU baseline is the FP64 oracle (OpenMP over
+rows) on the same diameters in the same box, gradient + Adam only.
 """
 import argparse
 import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -33,33 +39,45 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, skin_s, skin_g, target_s=12.0):
-    """Oracle gradient + Adam iterations on the host cores (bounded sample)."""
+def cpu_baseline(d0, L, phi, skin_s, skin_g, target_s=12.0):
+    """Oracle gradient + Adam iterations on the host cores (bounded sample).
+
+    State: the same diameters in the same box, i.i.d. uniform positions
+    (seeded generator) at the scale kappa that gives the volume fraction the
+    GPU run had reached, so the list density is comparable.
+    """
     import oracle
+    import rcp_inputs as ri
     oracle.lib()
     threads = oracle.num_threads()
-    t, npairs = oracle.time_iterations(w.x, w.d0, w.L, 1.0, 1e-2, 2, s=skin_s, g=skin_g)
+    n = d0.shape[0]
+    kappa = float((phi * L ** 3 / (np.pi / 6.0 * np.sum(d0 ** 3))) ** (1.0 / 3.0))
+    x = ri.uniform_positions(n, L, 7)
+    t, npairs = oracle.time_iterations(x, d0, L, kappa, 1e-2, 2, s=skin_s, g=skin_g)
     per = max(t / 2, 1e-6)
     iters = int(max(3, min(500, target_s / per)))
-    t, npairs = oracle.time_iterations(w.x, w.d0, w.L, 1.0, 1e-2, iters, s=skin_s, g=skin_g)
-    return {"value": w.n * iters / t, "unit": "particle-updates/s", "cores": threads,
+    t, npairs = oracle.time_iterations(x, d0, L, kappa, 1e-2, iters, s=skin_s, g=skin_g)
+    return {"value": n * iters / t, "unit": "particle-updates/s", "cores": threads,
             "kind": "oracle",
-            "sample": "%d gradient+Adam iterations of the FP64 oracle on the same N=%d state "
-                      "(list build excluded), %.1f s" % (iters, w.n, t)}
+            "sample": "%d gradient+Adam iterations of the FP64 oracle, N=%d, same diameters and "
+                      "box, uniform positions at phi=%.3f (%d listed pairs; list build "
+                      "excluded), %.1f s" % (iters, n, phi, npairs, t)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=300)
+    ap.add_argument("--steps", type=int, default=40000)
+    ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--n", type=int, default=1_000_000)
-    ap.add_argument("--skin", type=float, default=2.0)
+    ap.add_argument("--phi0", type=float, default=0.05)
+    ap.add_argument("--skin", type=float, default=4.0)
     ap.add_argument("--skin-g", type=float, default=0.02)
     ap.add_argument("--graph-iters", type=int, default=None)
     ap.add_argument("--fused-tail", type=int, default=None)
     ap.add_argument("--heavy-first", type=int, default=None)
     ap.add_argument("--xcd-remap", type=int, default=None)
+    ap.add_argument("--variant", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -77,7 +95,9 @@ def main():
     import rcp_inputs as ri
     import paper_2608_12235_amd as rcp
 
-    w = ri.c3_lognormal_dense(seed=0, n=args.n)
+    d0 = ri.lognormal_quantiles(args.n, 1.0, 1e3)
+    L = ri.box_for_phi(d0, args.phi0)
+    S = float(d0.max() / d0.min())
     tun = rcp.make_tuning()
     if args.graph_iters is not None:
         tun.graph_iters = args.graph_iters
@@ -87,12 +107,15 @@ def main():
         tun.heavy_first = args.heavy_first
     if args.xcd_remap is not None:
         tun.xcd_remap = args.xcd_remap
+    if args.variant is not None:
+        tun.variant = args.variant
     params = rcp.make_params(skin_s=args.skin, skin_g=args.skin_g)
-    p = rcp.Packing(w.d0, w.L, 1.0, 0, init="none", params=params, tuning=tun)
-    p.set_state(w.x, 1.0)
-    p.run_start(rcp.default_schedule(w.n))
+    log("placement (random sequential addition, N=%d)" % args.n)
+    p = rcp.Packing(d0, L, 1.0, 0, init="rsa", params=params, tuning=tun)
+    p.run_start(rcp.default_schedule(args.n, S=S))
     log("warmup %d iterations" % args.warmup)
-    p.run_continue(args.warmup)
+    if args.warmup:
+        p.run_continue(args.warmup)
     torch.cuda.synchronize()
     p.reset_stats()
     log("timed %d iterations" % args.steps)
@@ -104,15 +127,20 @@ def main():
     st = p.stats()
     iters = st["iterations"]
     wall = t1 - t0
-    value = w.n * iters / wall
-    kern_s = st["iterate_ms"] * 1e-3 / max(iters, 1)
-    nnz = st["nnz"]
-    alg_bytes = 180.0 * w.n + 4.0 * nnz
-    achieved = alg_bytes / kern_s / 1e9
+    value = args.n * iters / wall
+    log("kernel timing (256 iterations, one launch each)")
+    it_us, tail_us, ndone = p.time_iterations(256)
+    st2 = p.stats()
+    nnz = st2["nnz"]
+    alg_bytes = 188.0 * args.n + 4.0 * nnz
+    achieved = alg_bytes / (it_us * 1e-6) / 1e9 if it_us > 0 else 0.0
     res = p.run_result()
     log("stats", st)
-    log("state after timed region: kappa %.6f max_overlap %.3e rung %d" %
-        (res["kappa_before_shrink"], res["max_overlap"], res["rung"]))
+    phi_now = float(np.pi / 6.0 * res["kappa_before_shrink"] ** 3 * np.sum(d0 ** 3) / L ** 3)
+    log("state after the timed region: kappa %.6f phi %.4f max_overlap %.3e rung %d; "
+        "k_iterate %.1f us, tail %.1f us over %d launches" %
+        (res["kappa_before_shrink"], phi_now, res["max_overlap"], res["rung"], it_us, tail_us,
+         ndone))
     out = {
         "metric": METRIC,
         "value": value,
@@ -127,21 +155,25 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "lognormal sigma_lnD=1.0 S=1e3 N=%d i.i.d. uniform at phi=0.6, "
-                        "3-D periodic, densification rung of the default schedule" % w.n,
-            "n": w.n,
+            "workload": "lognormal sigma_lnD=1.0 S=1e3 N=%d, RSA start at phi0=%g, 3-D "
+                        "periodic, default schedule, iterations %d..%d" %
+                        (args.n, args.phi0, args.warmup, args.warmup + iters),
+            "n": args.n,
+            "phi_after_timed_region": phi_now,
             "skin_s": args.skin,
             "skin_g": args.skin_g,
             "graph_iters": tun.graph_iters,
             "fused_tail": tun.fused_tail,
             "heavy_first": tun.heavy_first,
             "xcd_remap": tun.xcd_remap,
+            "variant": tun.variant,
             "rebuilds_in_timed_region": st["rebuilds"],
             "rebuild_ms": st["rebuild_ms"],
             "iterate_ms": st["iterate_ms"],
             "nnz": nnz,
-            "max_degree": st["max_degree"],
-            "kernel_rate": w.n / kern_s,
+            "max_degree": st2["max_degree"],
+            "tail_us": tail_us,
+            "kernel_rate": args.n / (it_us * 1e-6) if it_us > 0 else None,
         },
         "roofline": {
             "bound": "hbm",
@@ -152,13 +184,13 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None,
             "bytes_per_launch": alg_bytes,
-            "avg_launch_us": kern_s * 1e6,
+            "avg_launch_us": it_us,
         },
     }
     p.close()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(w, args.skin, args.skin_g)
+        out["cpu_baseline"] = cpu_baseline(d0, L, phi_now, args.skin, args.skin_g)
     print(json.dumps(out), flush=True)
 
 

@@ -88,21 +88,26 @@ typedef struct {
  *   fused_tail: 1 = the last block of a packing to finish an iteration
  *     reduces the partial sums and updates kappa and the schedule (one
  *     kernel per iteration), 0 = a separate one-block kernel does it;
- *   heavy_first: 1 = dispatch the row blocks of the largest particles
- *     (highest size classes, the longest rows) first. */
+ *   heavy_first: 1 = dispatch the last row blocks first;
+ *   variant: gradient + Adam kernel variant, bit 0 = four partner gathers in
+ *     flight per thread instead of two, bit 1 = the Adam operands are loaded
+ *     before the partner loop (more latency hidden, more registers), bit 2 =
+ *     streamed operands (moments, reference positions, list) are loaded and
+ *     stored non-temporally so gathered positions stay in the L2. */
 typedef struct {
     uint32_t size;
     int32_t graph_iters;
     int32_t xcd_remap;
     int32_t fused_tail;
     int32_t heavy_first;
+    int32_t variant;
 } rcp_tuning;
 
 /* Annealing schedule: a table of rungs run in order (App. A).  Rung r lasts
  * budget[r] iterations; the last rung is the final relaxation, where the
  * stop test max delta < tol is applied before each update, and budget of the
- * last rung is its iteration cap.  decay[r] multiplies both step sizes after
- * every iteration of rung r.  When absolute == 0, at the start of rung r:
+ * last rung is its iteration cap.  decay[r] multiplies mu and both step
+ * sizes after every iteration of rung r.  When absolute == 0, at the start of rung r:
  *     mu    = (mu[r] * N) / (kappa * sum D0)
  *     eta_x = eta_x[r] * (kappa * D0_min)
  *     eta_k = eta_k[r] * kappa
@@ -162,10 +167,19 @@ const char *rcp_last_error(void);
 void rcp_params_default(rcp_params *p);
 void rcp_tuning_default(rcp_tuning *t);
 
-/* Default rung table for a packing of n spheres in dimension dim, with the
- * principal budget of Eq. (trigger), n_trig = ceil(4000 Y + X sqrt(n dim)
- * - 2000), floored at n_min.  Returns RCP_EINVAL for n <= 0 or dim < 1. */
-int rcp_schedule_default(int64_t n, int dim, int Y, int X, int64_t n_min,
+/* Default rung table for a packing of n spheres in dimension dim with size
+ * ratio S = max D0 / min D0, with the principal budget of Eq. (trigger),
+ * n_trig = ceil(4000 Y + X sqrt(n dim) - 2000), floored at n_min.  The rung
+ * values are our reading (App. A does not list them): densify at mu~ = 1e-2
+ * for n_trig updates, rungs at 1e-3 and 1e-4 (n_trig/4 each), two cycles
+ * 1e-3 <-> 1e-4 (n_trig/8 each), final relaxation from 1e-5 with mu and
+ * both step sizes halving every 1/16 of its cap (cap 2 n_trig), so mu is
+ * annealed towards 0; stop tolerance 5e-4.  For broad
+ * distributions the position steps are multiplied by max(1, sqrt(S/10)),
+ * the kappa steps by min(1, 160/S) and the densification budget by
+ * 1 + max(0, log10(S/10)), so that small spheres can move out of the way
+ * of growing large ones.  Returns RCP_EINVAL for n <= 0 or dim < 1. */
+int rcp_schedule_default(int64_t n, int dim, double S, int Y, int X, int64_t n_min,
                          rcp_schedule *out);
 
 /* Create a context for n_prob independent packings (1 for a plain solve;
@@ -263,6 +277,15 @@ int rcp_energy_dev(rcp_ctx *ctx, const double *x_dev, double kappa, double mu,
                    double *E_dev, void *stream);
 int rcp_adjoint_dev(rcp_ctx *ctx, const double *x_dev, double kappa, double mu,
                     double *gx_dev, double *gk_dev, void *stream);
+
+/* Kernel timing of the running schedule: like rcp_run_continue(ctx,
+ * n_iters) but each iteration is launched on its own, with HIP events
+ * recorded on the context's stream around the gradient + Adam kernel and
+ * around the tail kernel.  Writes the mean durations (microseconds) over
+ * the iterations that did work, and how many those were (*done).  Rebuilds
+ * that fall in the window run as usual and are not timed here. */
+int rcp_time_iterations(rcp_ctx *ctx, int64_t n_iters, double *iterate_us, double *tail_us,
+                        int64_t *done);
 
 int rcp_get_stats(rcp_ctx *ctx, rcp_stats *s);
 int rcp_reset_stats(rcp_ctx *ctx);

@@ -244,6 +244,8 @@ def n_trig(N, d=3, Y=2, X=9):
 
 # Rung table (our reading of App. A; values are unstated in the paper):
 # (mu~, eta_x~, eta_k~, half-life as a fraction of the rung, budget fraction)
+# The half-life applies to mu and both step sizes; only the final rung
+# decays, so mu is annealed towards 0 there (the dense endpoint of App. A).
 # mu = mu~ N / (kappa sum D0) sets the equilibrium summed overlap to mu~ N;
 # eta_x = eta_x~ kappa D0_min, eta_k = eta_k~ kappa at the rung start.
 DEFAULT_RUNGS = [
@@ -254,22 +256,40 @@ DEFAULT_RUNGS = [
     (1e-4, 2.5e-3, 2.5e-4, 0.0, 0.125),
     (1e-3, 2.5e-3, 2.5e-4, 0.0, 0.125),
     (1e-4, 2.5e-3, 2.5e-4, 0.0, 0.125),
-    (1e-5, 1.25e-3, 1.25e-4, 0.25, 2.0),  # final relaxation (cap)
+    (1e-5, 1.25e-3, 1.25e-4, 1.0 / 16, 2.0),  # final relaxation (cap), mu -> 0
 ]
 
 
-def default_schedule(N, d=3, Y=2, X=9, n_min=5000, tol=5e-4, rungs=None):
+def size_ratio_factors(S):
+    """Step-size and budget factors for a size ratio S = max D0 / min D0.
+
+    Our reading for broad distributions (the paper does not list its rung
+    values): a large sphere's radius grows by about eta_k D_max / 2 per
+    update, and small spheres must be able to move away from it, so the
+    kappa step shrinks as 1/S beyond S = 160, the position step grows as
+    sqrt(S / 10), and the densification rung is lengthened by
+    1 + log10(S / 10).  All three are 1 for S <= 10.
+    """
+    S = max(float(S), 1.0)
+    fx = max(1.0, math.sqrt(S / 10.0))
+    fk = min(1.0, 160.0 / S)
+    fb = 1.0 + max(0.0, math.log10(S / 10.0))
+    return fx, fk, fb
+
+
+def default_schedule(N, d=3, Y=2, X=9, n_min=5000, tol=5e-4, rungs=None, S=1.0):
     nt = max(n_trig(N, d, Y, X), n_min)
-    S = Schedule()
+    fx, fk, fb = size_ratio_factors(S)
+    Sc = Schedule()
     rungs = DEFAULT_RUNGS if rungs is None else rungs
-    S.n_rungs = len(rungs)
-    S.absolute = 0
-    S.tol = tol
+    Sc.n_rungs = len(rungs)
+    Sc.absolute = 0
+    Sc.tol = tol
     for r, (mu, ex, ek, hl, bf) in enumerate(rungs):
-        S.mu[r], S.eta_x[r], S.eta_k[r] = mu, ex, ek
-        S.budget[r] = max(1, int(math.ceil(bf * nt)))
-        S.decay[r] = 1.0 if hl <= 0 else 2.0 ** (-1.0 / (hl * S.budget[r]))
-    return S
+        Sc.mu[r], Sc.eta_x[r], Sc.eta_k[r] = mu, ex * fx, ek * fk
+        Sc.budget[r] = max(1, int(math.ceil(bf * (fb if r == 0 else 1.0) * nt)))
+        Sc.decay[r] = 1.0 if hl <= 0 else 2.0 ** (-1.0 / (hl * Sc.budget[r]))
+    return Sc
 
 
 def absolute_schedule(mu, eta_x, eta_k, n_steps):

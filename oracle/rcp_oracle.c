@@ -594,7 +594,7 @@ typedef struct {
     double mu[ORC_MAX_RUNGS];
     double eta_x[ORC_MAX_RUNGS];
     double eta_k[ORC_MAX_RUNGS];
-    double decay[ORC_MAX_RUNGS];
+    double decay[ORC_MAX_RUNGS];    /* per-iteration factor on mu, eta_x, eta_k */
     int64_t budget[ORC_MAX_RUNGS];
 } orc_sched;
 
@@ -745,7 +745,7 @@ static inline double adam(double th, double g, double *m, double *v, double b1,
  *   2. evaluate the energy terms and gradients at (x_t, kappa_t);
  *   3. in the final rung, stop if max delta < tol (state x_t is returned);
  *   4. t += 1, Adam on every coordinate and on kappa, wrap positions;
- *   5. decay the step sizes, advance the rung counter; at the end of a
+ *   5. decay mu and the step sizes, advance the rung counter; at the end of a
  *      rung start the next one (its mu and etas from the new kappa); at the
  *      end of the final rung stop with status 1;
  *   6. test the list validity for the next iteration.
@@ -809,6 +809,7 @@ int orc_run(int64_t n, double *x, const double *d0, double L, double *kappa,
             x[q] = th;
         }
         *kappa = adam(*kappa, gk, &mk, &vk, b1, b2, b1t, b2t, ek, P->eps_k);
+        mu *= S->decay[r];
         ex *= S->decay[r];
         ek *= S->decay[r];
         itr += 1;

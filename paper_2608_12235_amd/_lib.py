@@ -33,7 +33,8 @@ class Params(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("size", C.c_uint32), ("graph_iters", C.c_int32), ("xcd_remap", C.c_int32),
-                ("fused_tail", C.c_int32), ("heavy_first", C.c_int32)]
+                ("fused_tail", C.c_int32), ("heavy_first", C.c_int32),
+                ("variant", C.c_int32)]
 
 
 class Schedule(C.Structure):
@@ -76,8 +77,8 @@ SIGNATURES = {
     "rcp_last_error": (C.c_char_p, []),
     "rcp_params_default": (None, [C.POINTER(Params)]),
     "rcp_tuning_default": (None, [C.POINTER(Tuning)]),
-    "rcp_schedule_default": (C.c_int, [C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int64,
-                                       C.POINTER(Schedule)]),
+    "rcp_schedule_default": (C.c_int, [C.c_int64, C.c_int, C.c_double, C.c_int, C.c_int,
+                                       C.c_int64, C.POINTER(Schedule)]),
     "rcp_census_init": (C.c_int, [C.c_int, C.c_int, i64p, C.POINTER(dp), dp, dp,
                                   C.POINTER(C.c_uint64), C.c_int, C.POINTER(Params), vp,
                                   C.POINTER(vp)]),
@@ -100,6 +101,7 @@ SIGNATURES = {
     "rcp_shrink": (C.c_int, [vp, C.c_int, dp, dp]),
     "rcp_energy_dev": (C.c_int, [vp, vp, C.c_double, C.c_double, vp, vp]),
     "rcp_adjoint_dev": (C.c_int, [vp, vp, C.c_double, C.c_double, vp, vp, vp]),
+    "rcp_time_iterations": (C.c_int, [vp, C.c_int64, dp, dp, i64p]),
     "rcp_get_stats": (C.c_int, [vp, C.POINTER(Stats)]),
     "rcp_reset_stats": (C.c_int, [vp]),
     "rcp_num_packings": (C.c_int, [vp]),

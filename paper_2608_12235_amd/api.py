@@ -33,9 +33,10 @@ def make_tuning(**kw):
     return t
 
 
-def default_schedule(n, dim=3, Y=2, X=9, n_min=5000):
+def default_schedule(n, dim=3, Y=2, X=9, n_min=5000, S=1.0):
+    """Default rung table for n spheres with size ratio S (max D0 / min D0)."""
     s = Schedule()
-    check(lib().rcp_schedule_default(n, dim, Y, X, n_min, C.byref(s)))
+    check(lib().rcp_schedule_default(n, dim, float(S), Y, X, n_min, C.byref(s)))
     return s
 
 
@@ -153,7 +154,7 @@ class Packing:
     def inflate_run(self, schedule=None, max_iters=0, allow_notconv=True):
         P = self.n_packings
         if schedule is None:
-            schedule = [default_schedule(n) for n in self.n]
+            schedule = self.default_schedules()
         per = isinstance(schedule, (list, tuple))
         if per:
             arr = (Schedule * P)(*schedule)
@@ -166,10 +167,13 @@ class Packing:
             check(rc)
         return [_result_dict(r) for r in res]
 
+    def default_schedules(self):
+        return [default_schedule(n, S=float(d.max() / d.min())) for n, d in zip(self.n, self._d0)]
+
     def run_start(self, schedule=None):
         P = self.n_packings
         if schedule is None:
-            schedule = [default_schedule(n) for n in self.n]
+            schedule = self.default_schedules()
         per = isinstance(schedule, (list, tuple))
         if per:
             arr = (Schedule * P)(*schedule)
@@ -191,6 +195,14 @@ class Packing:
         kp, ph = C.c_double(), C.c_double()
         check(lib().rcp_shrink(self._h, k, C.byref(kp), C.byref(ph)))
         return kp.value, ph.value
+
+    def time_iterations(self, n_iters):
+        """Mean duration (us) of the gradient + Adam kernel and of the tail
+        kernel over up to n_iters further iterations, from HIP events."""
+        a, t, d = C.c_double(), C.c_double(), C.c_int64()
+        check(lib().rcp_time_iterations(self._h, int(n_iters), C.byref(a), C.byref(t),
+                                        C.byref(d)))
+        return a.value, t.value, d.value
 
     def stats(self):
         s = Stats()

@@ -12,7 +12,7 @@
 // k_tail (one block per packing) reduces those partials in a fixed order
 // (so runs are bit-reproducible), forms dE/dkappa = S/kappa - mu sum D0,
 // applies the stop test of App. A (final rung, max delta < tol, evaluated
-// before the update), Adam on kappa, the step-size decay and the rung
+// before the update), Adam on kappa, the decay of mu and the step sizes, the rung
 // advance, and the list-validity test that requests a rebuild.
 #include "rcp_kernels.hpp"
 
@@ -31,15 +31,14 @@ struct Acc {
     double gx, gy, gz, e, s, m, c;
 };
 
-__device__ __forceinline__ void pair_term(Acc &a, double xi, double yi, double zi, double di,
-                                          double xj, double yj, double zj, double dj,
-                                          double kappa, double L, double hL)
+__device__ __forceinline__ void pair_term(Acc &a, const P4 &qi, const P4 &qj, double kappa,
+                                          double L, double hL)
 {
-    const double dx = min_image(xj - xi, L, hL);
-    const double dy = min_image(yj - yi, L, hL);
-    const double dz = min_image(zj - zi, L, hL);
+    const double dx = min_image(qj.x - qi.x, L, hL);
+    const double dy = min_image(qj.y - qi.y, L, hL);
+    const double dz = min_image(qj.z - qi.z, L, hL);
     const double r2 = (dx * dx + dy * dy) + dz * dz;
-    const double d = kappa * (0.5 * (di + dj));
+    const double d = kappa * (0.5 * (qi.d + qj.d));
     if (r2 < d * d) {
         const double r = sqrt(r2);
         const double delta = 1.0 - r / d;
@@ -77,78 +76,101 @@ struct IterScalars {
 // (uniform selects keep them in scalar registers; indexing the pointer
 // table with the runtime buffer index would spill it to scratch).
 struct IterPtrs {
-    const double *x, *y, *z, *d0;
-    double *xo, *yo, *zo;
+    const P4 *q;        // current (x, y, z, D0)
+    P4 *qo;             // next positions
     double *m0, *m1, *m2, *v0, *v1, *v2, *r0, *r1, *r2;
     const int32_t *rp, *col;
 };
 
 __device__ __forceinline__ IterPtrs select_ptrs(const SegPtrs *__restrict__ P, int seg, int cur)
 {
-    const SegPtrs &q = P[seg];
+    const SegPtrs &s = P[seg];
     IterPtrs p;
-    p.x = cur ? q.x[1][0] : q.x[0][0];
-    p.y = cur ? q.x[1][1] : q.x[0][1];
-    p.z = cur ? q.x[1][2] : q.x[0][2];
-    p.xo = cur ? q.x[0][0] : q.x[1][0];
-    p.yo = cur ? q.x[0][1] : q.x[1][1];
-    p.zo = cur ? q.x[0][2] : q.x[1][2];
-    p.d0 = q.d0;
-    p.m0 = q.m[0];
-    p.m1 = q.m[1];
-    p.m2 = q.m[2];
-    p.v0 = q.v[0];
-    p.v1 = q.v[1];
-    p.v2 = q.v[2];
-    p.r0 = q.xref[0];
-    p.r1 = q.xref[1];
-    p.r2 = q.xref[2];
-    p.rp = q.rp;
-    p.col = q.col;
+    p.q = cur ? s.p[1] : s.p[0];
+    p.qo = cur ? s.p[0] : s.p[1];
+    p.m0 = s.m[0];
+    p.m1 = s.m[1];
+    p.m2 = s.m[2];
+    p.v0 = s.v[0];
+    p.v1 = s.v[1];
+    p.v2 = s.v[2];
+    p.r0 = s.xref[0];
+    p.r1 = s.xref[1];
+    p.r2 = s.xref[2];
+    p.rp = s.rp;
+    p.col = s.col;
     return p;
 }
 
-// One coordinate's Adam update from preloaded operands; returns the squared
-// (minimum image) displacement from the list reference along that axis.
+// One coordinate's Adam update from preloaded operands; returns the new
+// coordinate and adds its squared (minimum image) displacement from the
+// list reference to d2.
+template <bool kNT>
 __device__ __forceinline__ double update_coord(double xi, double g, double m, double v, double r,
-                                               double *xout, double *mm, double *vv,
-                                               const IterScalars &c, int64_t i)
+                                               double *mm, double *vv, const IterScalars &c,
+                                               int64_t i, double &d2)
 {
     const double xn = adam_coord(xi, g, m, v, c.b1, c.b2, c.bc1, c.bc2, c.eta, c.eps, c.L);
-    xout[i] = xn;
-    mm[i] = m;
-    vv[i] = v;
+    if (kNT) {
+        __builtin_nontemporal_store(m, mm + i);
+        __builtin_nontemporal_store(v, vv + i);
+    } else {
+        mm[i] = m;
+        vv[i] = v;
+    }
     const double dd = min_image(xn - r, c.L, c.hL);
-    return dd * dd;
+    d2 += dd * dd;
+    return xn;
 }
 
 struct Pre {
     double m0, m1, m2, v0, v1, v2, r0, r1, r2;
 };
 
+template <bool kNT>
+__device__ __forceinline__ double ld(const double *p)
+{
+    return kNT ? __builtin_nontemporal_load(p) : *p;
+}
+
+template <bool kNT>
+__device__ __forceinline__ int32_t ldi(const int32_t *p)
+{
+    return kNT ? __builtin_nontemporal_load(p) : *p;
+}
+
+// Streamed operands (read once per iteration); with kNT they are loaded
+// non-temporally so they do not push gathered positions out of the L2.
+template <bool kNT = false>
 __device__ __forceinline__ Pre preload(const IterPtrs &p, int64_t i)
 {
     Pre q;
-    q.m0 = p.m0[i];
-    q.m1 = p.m1[i];
-    q.m2 = p.m2[i];
-    q.v0 = p.v0[i];
-    q.v1 = p.v1[i];
-    q.v2 = p.v2[i];
-    q.r0 = p.r0[i];
-    q.r1 = p.r1[i];
-    q.r2 = p.r2[i];
+    q.m0 = ld<kNT>(p.m0 + i);
+    q.m1 = ld<kNT>(p.m1 + i);
+    q.m2 = ld<kNT>(p.m2 + i);
+    q.v0 = ld<kNT>(p.v0 + i);
+    q.v1 = ld<kNT>(p.v1 + i);
+    q.v2 = ld<kNT>(p.v2 + i);
+    q.r0 = ld<kNT>(p.r0 + i);
+    q.r1 = ld<kNT>(p.r1 + i);
+    q.r2 = ld<kNT>(p.r2 + i);
     return q;
 }
 
-// Adam on particle i's coordinates; returns |x_new - x_ref|^2 (min image).
+// Adam on particle i's coordinates, new position (and its D0) stored;
+// returns |x_new - x_ref|^2 (min image).
+template <bool kNT = false>
 __device__ __forceinline__ double update_particle(const IterPtrs &p, const IterScalars &c,
-                                                  int64_t i, double xi, double yi, double zi,
-                                                  const Pre &q, double gx, double gy, double gz)
+                                                  int64_t i, const P4 &qi, const Pre &q,
+                                                  double gx, double gy, double gz)
 {
-    double d2 = update_coord(xi, gx, q.m0, q.v0, q.r0, p.xo, p.m0, p.v0, c, i);
-    d2 += update_coord(yi, gy, q.m1, q.v1, q.r1, p.yo, p.m1, p.v1, c, i);
-    d2 += update_coord(zi, gz, q.m2, q.v2, q.r2, p.zo, p.m2, p.v2, c, i);
+    double d2 = 0.0;
+    P4 o;
+    o.x = update_coord<kNT>(qi.x, gx, q.m0, q.v0, q.r0, p.m0, p.v0, c, i, d2);
+    o.y = update_coord<kNT>(qi.y, gy, q.m1, q.v1, q.r1, p.m1, p.v1, c, i, d2);
+    o.z = update_coord<kNT>(qi.z, gz, q.m2, q.v2, q.r2, p.m2, p.v2, c, i, d2);
+    o.d = qi.d;
+    p.qo[i] = o;
     return d2;
 }
 
@@ -195,6 +217,7 @@ __device__ void tail_logic(SegState *s, double E, double S, double md, double md
     s->mk = mk;
     s->vk = vk;
     s->cur ^= 1;
+    s->mu *= q.decay[r];
     s->eta_x *= q.decay[r];
     s->eta_k *= q.decay[r];
     s->it_rung += 1;
@@ -252,41 +275,38 @@ __device__ void reduce_and_tail(SegState *s, const double *partials)
     }
 }
 
-// Entry loop of one row segment [q, qe): four partners per step so that
-// their gathers are in flight together.
+// Entry loop of one row segment [q, qe): kU partners per step so that
+// their gathers are in flight together (kU = 2 or 4).
+template <int kU, bool kNT>
 __device__ __forceinline__ void segment_terms(Acc &a, const int32_t *__restrict__ col,
-                                              const double *__restrict__ X,
-                                              const double *__restrict__ Y,
-                                              const double *__restrict__ Z,
-                                              const double *__restrict__ D, int32_t q, int32_t qe,
-                                              double xi, double yi, double zi, double di,
-                                              const IterScalars &c)
+                                              const P4 *__restrict__ Q, int32_t q, int32_t qe,
+                                              const P4 &qi, const IterScalars &c)
 {
-    for (; q + 4 <= qe; q += 4) {
-        const int32_t j0 = col[q], j1 = col[q + 1], j2 = col[q + 2], j3 = col[q + 3];
-        const double x0 = X[j0], y0 = Y[j0], z0 = Z[j0], e0 = D[j0];
-        const double x1 = X[j1], y1 = Y[j1], z1 = Z[j1], e1 = D[j1];
-        const double x2 = X[j2], y2 = Y[j2], z2 = Z[j2], e2 = D[j2];
-        const double x3 = X[j3], y3 = Y[j3], z3 = Z[j3], e3 = D[j3];
-        pair_term(a, xi, yi, zi, di, x0, y0, z0, e0, c.kappa, c.L, c.hL);
-        pair_term(a, xi, yi, zi, di, x1, y1, z1, e1, c.kappa, c.L, c.hL);
-        pair_term(a, xi, yi, zi, di, x2, y2, z2, e2, c.kappa, c.L, c.hL);
-        pair_term(a, xi, yi, zi, di, x3, y3, z3, e3, c.kappa, c.L, c.hL);
+    if (kU == 4) {
+        for (; q + 4 <= qe; q += 4) {
+            const int32_t j0 = ldi<kNT>(col + q), j1 = ldi<kNT>(col + q + 1),
+                          j2 = ldi<kNT>(col + q + 2), j3 = ldi<kNT>(col + q + 3);
+            const P4 q0 = Q[j0], q1 = Q[j1], q2 = Q[j2], q3 = Q[j3];
+            pair_term(a, qi, q0, c.kappa, c.L, c.hL);
+            pair_term(a, qi, q1, c.kappa, c.L, c.hL);
+            pair_term(a, qi, q2, c.kappa, c.L, c.hL);
+            pair_term(a, qi, q3, c.kappa, c.L, c.hL);
+        }
     }
-    for (; q < qe; ++q) {
-        const int32_t j = col[q];
-        pair_term(a, xi, yi, zi, di, X[j], Y[j], Z[j], D[j], c.kappa, c.L, c.hL);
+    for (; q + 2 <= qe; q += 2) {
+        const int32_t j0 = ldi<kNT>(col + q), j1 = ldi<kNT>(col + q + 1);
+        const P4 q0 = Q[j0], q1 = Q[j1];
+        pair_term(a, qi, q0, c.kappa, c.L, c.hL);
+        pair_term(a, qi, q1, c.kappa, c.L, c.hL);
     }
+    if (q < qe) pair_term(a, qi, Q[ldi<kNT>(col + q)], c.kappa, c.L, c.hL);
 }
 
-__device__ __forceinline__ void store6(double (*M)[kBlock], int k, const Acc &a)
+__device__ __forceinline__ void store3(double (*M)[kBlock], int k, const Acc &a)
 {
     M[0][k] = a.gx;
     M[1][k] = a.gy;
     M[2][k] = a.gz;
-    M[3][k] = a.e;
-    M[4][k] = a.s;
-    M[5][k] = a.m;
 }
 
 // One iteration for a block of up to 256 consecutive rows of one packing.
@@ -297,7 +317,7 @@ __device__ __forceinline__ void store6(double (*M)[kBlock], int k, const Acc &a)
 // (its piece in the chunk where it starts) + (the leading piece of every
 // later chunk it covers), in chunk order, so the result does not depend on
 // timing.  Phase 2: one thread per row applies Adam (coalesced).
-template <bool kFusedTail>
+template <bool kFusedTail, int kU, bool kEarly, bool kNT>
 __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ P,
                                                    SegState *__restrict__ S,
                                                    const WorkItem *__restrict__ W,
@@ -319,30 +339,35 @@ __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ 
     c.eta = s->eta_x;
     c.eps = s->eps_x;
     const IterPtrs p = select_ptrs(P, w.seg, s->cur);
-    const double *X = p.x, *Y = p.y, *Z = p.z, *D = p.d0;
+    const P4 *Q = p.q;
 
     __shared__ int32_t srp[kBlock + 1];
-    __shared__ double G[6][kBlock];   // complete rows
-    __shared__ double A[6][kBlock];   // leading piece of chunk t (row began earlier)
-    __shared__ double B[6][kBlock];   // trailing piece of chunk t (row goes on)
+    __shared__ double G[3][kBlock];   // gradient of complete rows
+    __shared__ double A[3][kBlock];   // leading piece of chunk t (row began earlier)
+    __shared__ double B[3][kBlock];   // trailing piece of chunk t (row goes on)
     const int t = threadIdx.x;
     const int64_t r0 = w.begin;
     const int nrow = (int)(w.end - w.begin);
-    // phase-2 operands first: their latency hides behind phase 1
+    // phase-2 operands either first (their latency hides behind phase 1)
+    // or after it (fewer registers live through phase 1)
     const int64_t io = r0 + t;
     const bool own = t < nrow;
-    double oxi = 0, oyi = 0, ozi = 0;
+    P4 oq = {0, 0, 0, 0};
     Pre pre = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (own) {
-        oxi = X[io];
-        oyi = Y[io];
-        ozi = Z[io];
-        pre = preload(p, io);
+        if (kEarly) {
+            oq = Q[io];
+            pre = preload<kNT>(p, io);
+        }
         srp[t] = p.rp[io];
     }
     if (t == 0) srp[nrow] = p.rp[r0 + nrow];
     __syncthreads();
 
+    // energy, kappa-gradient and max-overlap terms are block totals: each
+    // thread keeps its own sums over its chunk (fixed assignment, so fixed
+    // order); only the gradient needs per-row bookkeeping
+    double be = 0, bs = 0, bm = 0, bd = 0;
     const int32_t e0 = srp[0], e1 = srp[nrow];
     const int32_t chunk = max(1, (e1 - e0 + kBlock - 1) / kBlock);
     const int32_t cs = e0 + t * chunk, ce = min(cs + chunk, e1);
@@ -356,15 +381,17 @@ __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ 
         int r = lo;
         int32_t q = cs;
         for (;;) {
-            const int64_t i = r0 + r;
-            const double xi = X[i], yi = Y[i], zi = Z[i], di = D[i];
+            const P4 qi = Q[r0 + r];
             const int32_t rend = srp[r + 1], qe = min(rend, ce);
             Acc a = {0, 0, 0, 0, 0, 0, 0};
-            segment_terms(a, p.col, X, Y, Z, D, q, qe, xi, yi, zi, di, c);
+            segment_terms<kU, kNT>(a, p.col, Q, q, qe, qi, c);
+            be += a.e;
+            bs += a.s;
+            bm = fmax(bm, a.m);
             const bool began_before = srp[r] < cs, goes_on = rend > ce;
-            if (began_before) store6(A, t, a);
-            else if (goes_on) store6(B, t, a);
-            else store6(G, r, a);
+            if (began_before) store3(A, t, a);
+            else if (goes_on) store3(B, t, a);
+            else store3(G, r, a);
             q = qe;
             if (q >= ce) break;
             do {
@@ -374,29 +401,28 @@ __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ 
     }
     __syncthreads();
 
-    double be = 0, bs = 0, bm = 0, bd = 0;
     if (own) {
+        if (!kEarly) {
+            oq = Q[io];
+            pre = preload<kNT>(p, io);
+        }
         const int32_t qb = srp[t], qe = srp[t + 1];
-        double g[6] = {0, 0, 0, 0, 0, 0};
+        double g[3] = {0, 0, 0};
         if (qb < qe) {
             const int tf = (qb - e0) / chunk, tl = (qe - 1 - e0) / chunk;
             if (tf == tl) {
 #pragma unroll
-                for (int k = 0; k < 6; ++k) g[k] = G[k][t];
+                for (int k = 0; k < 3; ++k) g[k] = G[k][t];
             } else {
 #pragma unroll
-                for (int k = 0; k < 6; ++k) g[k] = B[k][tf];
+                for (int k = 0; k < 3; ++k) g[k] = B[k][tf];
                 for (int u = tf + 1; u <= tl; ++u) {
 #pragma unroll
-                    for (int k = 0; k < 5; ++k) g[k] += A[k][u];
-                    g[5] = fmax(g[5], A[5][u]);
+                    for (int k = 0; k < 3; ++k) g[k] += A[k][u];
                 }
             }
         }
-        be = g[3];
-        bs = g[4];
-        bm = g[5];
-        bd = update_particle(p, c, io, oxi, oyi, ozi, pre, g[0], g[1], g[2]);
+        bd = update_particle<kNT>(p, c, io, oq, pre, g[0], g[1], g[2]);
     }
     // block reduction of the four partials
     const int lane = t & (kWave - 1);
@@ -451,18 +477,40 @@ __global__ __launch_bounds__(kBlock) void k_tail(SegState *__restrict__ S,
     reduce_and_tail(s, partials);
 }
 
+template <bool kF, int kU, bool kE, bool kNT>
+static void launch_one(const SegPtrs *P, SegState *S, const WorkItem *W, double *partials,
+                       int nitems, int f, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_iterate<kF, kU, kE, kNT>), dim3(nitems), dim3(kBlock), 0, st, P, S, W,
+                       partials, f);
+}
+
+template <bool kF>
+static void launch_variant(const SegPtrs *P, SegState *S, const WorkItem *W, double *partials,
+                           int nitems, int f, int variant, hipStream_t st)
+{
+    switch (variant & 7) {
+    case 0: launch_one<kF, 2, false, false>(P, S, W, partials, nitems, f, st); break;
+    case 1: launch_one<kF, 4, false, false>(P, S, W, partials, nitems, f, st); break;
+    case 2: launch_one<kF, 2, true, false>(P, S, W, partials, nitems, f, st); break;
+    case 3: launch_one<kF, 4, true, false>(P, S, W, partials, nitems, f, st); break;
+    case 4: launch_one<kF, 2, false, true>(P, S, W, partials, nitems, f, st); break;
+    case 5: launch_one<kF, 4, false, true>(P, S, W, partials, nitems, f, st); break;
+    case 6: launch_one<kF, 2, true, true>(P, S, W, partials, nitems, f, st); break;
+    default: launch_one<kF, 4, true, true>(P, S, W, partials, nitems, f, st); break;
+    }
+}
+
 void launch_iterate(const SegPtrs *P, SegState *S, const WorkItem *W, double *partials,
                     int nitems, int flags, hipStream_t st)
 {
-    // bit 0: XCD-aware order; bit 1: fused tail; bit 2: last rows first
-    const int f = flags & 5;
-    if (flags & 2) {
-        hipLaunchKernelGGL(k_iterate<true>, dim3(nitems), dim3(kBlock), 0, st, P, S, W,
-                           partials, f);
-    } else {
-        hipLaunchKernelGGL(k_iterate<false>, dim3(nitems), dim3(kBlock), 0, st, P, S, W,
-                           partials, f);
-    }
+    // bit 0: XCD-aware order; bit 1: fused tail; bit 2: last rows first;
+    // bits 8-10: kernel variant (bit 8: four gathers in flight instead of two,
+    // bit 9: Adam operands loaded before the partner loop, bit 10: streamed
+    // operands loaded and stored non-temporally)
+    const int f = flags & 5, variant = (flags >> 8) & 7;
+    if (flags & 2) launch_variant<true>(P, S, W, partials, nitems, f, variant, st);
+    else launch_variant<false>(P, S, W, partials, nitems, f, variant, st);
 }
 
 void launch_tail(SegState *S, const double *partials, int nseg, hipStream_t st)
@@ -544,15 +592,20 @@ __global__ __launch_bounds__(kBlock) void k_eval(const SegPtrs *__restrict__ P,
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double be = 0, bs = 0, bm = 0, bn = 0;
     if (i < n) {
-        auto pos = [&](int64_t k, int a) -> double {
-            return xu ? xu[3 * (int64_t)orig[k] + a] : (a == 0 ? p.x[k] : (a == 1 ? p.y[k] : p.z[k]));
+        // position from the user-order array when given, D0 from the list
+        auto pos = [&](int64_t k) -> P4 {
+            P4 q = p.q[k];
+            if (xu) {
+                const int64_t u = orig[k];
+                q.x = xu[3 * u];
+                q.y = xu[3 * u + 1];
+                q.z = xu[3 * u + 2];
+            }
+            return q;
         };
-        const double xi = pos(i, 0), yi = pos(i, 1), zi = pos(i, 2), di = p.d0[i];
+        const P4 qi = pos(i);
         Acc a = {0, 0, 0, 0, 0, 0, 0};
-        for (int32_t q = p.rp[i]; q < p.rp[i + 1]; ++q) {
-            const int32_t j = p.col[q];
-            pair_term(a, xi, yi, zi, di, pos(j, 0), pos(j, 1), pos(j, 2), p.d0[j], kappa, L, hL);
-        }
+        for (int32_t q = p.rp[i]; q < p.rp[i + 1]; ++q) pair_term(a, qi, pos(p.col[q]), kappa, L, hL);
         be = a.e;
         bs = a.s;
         bm = a.m;
@@ -673,14 +726,15 @@ __global__ __launch_bounds__(kBlock) void k_set_positions(const SegPtrs *__restr
                                                          int seg, int64_t n,
                                                          const double *__restrict__ xu, int cur)
 {
-    const IterPtrs p = select_ptrs(P, seg, cur);
+    P4 *Q = cur ? P[seg].p[1] : P[seg].p[0];
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     const int64_t u = P[seg].orig[i];
-    double *X = (double *)p.x, *Y = (double *)p.y, *Z = (double *)p.z;
-    X[i] = xu[3 * u];
-    Y[i] = xu[3 * u + 1];
-    Z[i] = xu[3 * u + 2];
+    P4 q = Q[i];
+    q.x = xu[3 * u];
+    q.y = xu[3 * u + 1];
+    q.z = xu[3 * u + 2];
+    Q[i] = q;
 }
 
 void launch_set_positions(const SegPtrs *P, SegState *S, int seg, int64_t n, const double *xu,

@@ -9,8 +9,13 @@
 // for the largest sphere (the size ratio reaches 5e5 in the paper's
 // lognormal study, Sec. 1).
 //
-// Keys are (class << mb) | Morton(cell) so one stable sort orders particles
-// by class, then spatially; occupied cells are located through an
+// Keys are (tile << tshift) | (class << mb) | Morton(cell): one stable sort
+// orders particles by spatial tile (a T x T x T split of the box, tiles in
+// Morton order), then by class, then by cell.  A tile holds every class of
+// its region, so the blocks an XCD runs (a contiguous range) cover a compact
+// region and the partners they gather, of any class, stay in that XCD's L2.
+// A cell's tile is a function of its integer coordinates, so all particles
+// of a cell share it.  Occupied cells are located through an
 // open-addressing hash of their keys.  The listing predicate is evaluated
 // with a fixed operation order and no contraction so that the pair set is
 // reproducible bit for bit:
@@ -30,6 +35,12 @@ __device__ __forceinline__ int32_t cell_coord(double v, double inv_w, int32_t nc
     return c >= nc ? nc - 1 : c;
 }
 
+// Tile coordinate of cell c of a grid with nc cells per axis.
+__device__ __forceinline__ uint64_t tile_of(int64_t c, int32_t nc, int32_t tiles)
+{
+    return (uint64_t)((c * tiles) / nc);
+}
+
 __global__ __launch_bounds__(kBlock) void k_keys(BuildArgs a, uint64_t *__restrict__ keys,
                                                 uint32_t *__restrict__ vals)
 {
@@ -37,10 +48,13 @@ __global__ __launch_bounds__(kBlock) void k_keys(BuildArgs a, uint64_t *__restri
     if (i >= a.n) return;
     const int l = a.lev[i];
     const LevelGrid g = a.lv[l];
-    uint64_t cx = (uint64_t)cell_coord(a.x[i], g.inv_w, g.nc);
-    uint64_t cy = (uint64_t)cell_coord(a.y[i], g.inv_w, g.nc);
-    uint64_t cz = (uint64_t)cell_coord(a.z[i], g.inv_w, g.nc);
-    keys[i] = ((uint64_t)l << a.mb) | morton3(cx, cy, cz);
+    const P4 q = a.pos[i];
+    uint64_t cx = (uint64_t)cell_coord(q.x, g.inv_w, g.nc);
+    uint64_t cy = (uint64_t)cell_coord(q.y, g.inv_w, g.nc);
+    uint64_t cz = (uint64_t)cell_coord(q.z, g.inv_w, g.nc);
+    const uint64_t tile = morton3(tile_of(cx, g.nc, a.tiles), tile_of(cy, g.nc, a.tiles),
+                                  tile_of(cz, g.nc, a.tiles));
+    keys[i] = (tile << a.tshift) | ((uint64_t)l << a.mb) | morton3(cx, cy, cz);
     vals[i] = (uint32_t)i;
 }
 
@@ -56,15 +70,16 @@ __global__ __launch_bounds__(kBlock) void k_permute(PermArgs p)
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= p.n) return;
     const int64_t s = p.perm[k];
+    const P4 q = p.ps[s];
+    p.pd[k] = q;
+    p.xref[0][k] = q.x;
+    p.xref[1][k] = q.y;
+    p.xref[2][k] = q.z;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        double xv = p.xs[a][s];
-        p.xd[a][k] = xv;
-        p.xref[a][k] = xv;
         p.md[a][k] = p.ms[a][s];
         p.vd[a][k] = p.vs[a][s];
     }
-    p.d0d[k] = p.d0s[s];
     p.od[k] = p.os[s];
     p.ld[k] = p.ls[s];
 }
@@ -177,32 +192,45 @@ constexpr int kSearchBuf = 3072;   // entries staged per block in LDS (24 KB)
 // directions; a block stages its entries in LDS and reserves global space
 // with one atomic (entries that do not fit in LDS go straight to global
 // memory).  The order of the list is arbitrary; it is sorted afterwards.
+__device__ __forceinline__ int remap_xcd(int b, int G)
+{
+    // workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+    // contiguous range of particles (one spatial region, tile-major order)
+    const int nx = 8, per = G / nx, rem = G % nx;
+    const int xcd = b % nx, loc = b / nx;
+    return (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + loc;
+}
+
 __global__ __launch_bounds__(kBlock) void k_search(BuildArgs a, uint64_t *__restrict__ list,
                                                   uint32_t *__restrict__ counter, int64_t cap,
-                                                  int row_bits)
+                                                  int row_bits, int xcd_remap)
 {
     __shared__ uint64_t buf[kSearchBuf];
     __shared__ uint32_t nbuf;
     __shared__ uint32_t gbase;
     if (threadIdx.x == 0) nbuf = 0;
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int blk = xcd_remap ? remap_xcd((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+    const int64_t i = (int64_t)blk * kBlock + threadIdx.x;
     if (i < a.n) {
-        const double xi = a.x[i], yi = a.y[i], zi = a.z[i], di = a.d0[i];
+        const P4 qi = a.pos[i];
+        const double xi = qi.x, yi = qi.y, zi = qi.z, di = qi.d;
         const int li = a.lev[i];
         const uint64_t rowi = (uint64_t)i << row_bits;
         for (int L = li; L < a.nlev; ++L) {
             const LevelGrid g = a.lv[L];
             if (g.count == 0) continue;
             const int32_t nc = g.nc;
-            // Stencil cells per axis.  With nc >= 3 the cell on one side is
-            // needed only if the particle is closer to that face than the
-            // largest cutoff it can have with a class-L partner (bound in cell
-            // units, with a margin far above the rounding of x * inv_w); with
-            // nc < 3 every cell is searched once.  Skipping a cell is exact.
+            // Stencil cells.  With nc >= 3 a neighbour cell is searched only
+            // if its nearest point is closer to the particle than the largest
+            // cutoff the particle can have with a class-L partner (bound in
+            // cell units, with a margin far above the rounding of x * inv_w);
+            // with nc < 3 every cell is searched once.  Skipping is exact.
             const double cb =
                 a.kb * (a.opg * (0.5 * (di + g.dmax)) + a.sk2) * g.inv_w * (1.0 + 1e-9) + 1e-9;
             uint64_t m[3][3];   // [axis][slot]: Morton parts of the lower, own, upper cell
+            uint64_t tp[3][3];  // the same for the tile field
+            double gap[3][3];   // distance (cell units) from the particle to that slab
             bool use[3][3];
             const double pos[3] = {xi, yi, zi};
 #pragma unroll
@@ -215,6 +243,12 @@ __global__ __launch_bounds__(kBlock) void k_search(BuildArgs a, uint64_t *__rest
                     m[ax][0] = spread3((uint64_t)lo) << ax;
                     m[ax][1] = spread3((uint64_t)c) << ax;
                     m[ax][2] = spread3((uint64_t)hi) << ax;
+                    tp[ax][0] = spread3(tile_of(lo, nc, a.tiles)) << ax;
+                    tp[ax][1] = spread3(tile_of(c, nc, a.tiles)) << ax;
+                    tp[ax][2] = spread3(tile_of(hi, nc, a.tiles)) << ax;
+                    gap[ax][0] = f;
+                    gap[ax][1] = 0.0;
+                    gap[ax][2] = 1.0 - f;
                     use[ax][0] = f < cb;
                     use[ax][1] = true;
                     use[ax][2] = 1.0 - f < cb;
@@ -222,6 +256,10 @@ __global__ __launch_bounds__(kBlock) void k_search(BuildArgs a, uint64_t *__rest
                     m[ax][0] = 0;
                     m[ax][1] = spread3(1) << ax;
                     m[ax][2] = 0;
+                    tp[ax][0] = spread3(tile_of(0, nc, a.tiles)) << ax;
+                    tp[ax][1] = spread3(tile_of(1, nc, a.tiles)) << ax;
+                    tp[ax][2] = 0;
+                    gap[ax][0] = gap[ax][1] = gap[ax][2] = 0.0;
                     use[ax][0] = true;
                     use[ax][1] = nc == 2;
                     use[ax][2] = false;
@@ -235,15 +273,22 @@ __global__ __launch_bounds__(kBlock) void k_search(BuildArgs a, uint64_t *__rest
 #pragma unroll
                     for (int oz = 0; oz < 3; ++oz) {
                         if (!(use[0][ox] && use[1][oy] && use[2][oz])) continue;
-                        const uint64_t key = base | m[0][ox] | m[1][oy] | m[2][oz];
+                        // a cell whose nearest point is beyond the cutoff bound
+                        // cannot hold a partner (corners and edges of the stencil)
+                        const double g2 = (gap[0][ox] * gap[0][ox] + gap[1][oy] * gap[1][oy]) +
+                                          gap[2][oz] * gap[2][oz];
+                        if (!(g2 < cb * cb)) continue;
+                        const uint64_t key = base | m[0][ox] | m[1][oy] | m[2][oz] |
+                                             ((tp[0][ox] | tp[1][oy] | tp[2][oz]) << a.tshift);
                         const int2 r = hash_find(a, key);
                         for (int64_t j = r.x; j < (int64_t)r.x + r.y; ++j) {
                             if (L == li && j <= i) continue;
-                            const double dx = min_image(a.x[j] - xi, a.L, a.hL);
-                            const double dy = min_image(a.y[j] - yi, a.L, a.hL);
-                            const double dz = min_image(a.z[j] - zi, a.L, a.hL);
+                            const P4 qj = a.pos[j];
+                            const double dx = min_image(qj.x - xi, a.L, a.hL);
+                            const double dy = min_image(qj.y - yi, a.L, a.hL);
+                            const double dz = min_image(qj.z - zi, a.L, a.hL);
                             const double r2 = (dx * dx + dy * dy) + dz * dz;
-                            const double cc = a.kb * (a.opg * (0.5 * (di + a.d0[j])) + a.sk2);
+                            const double cc = a.kb * (a.opg * (0.5 * (di + qj.d)) + a.sk2);
                             if (r2 < cc * cc) {
                                 const uint64_t e0 = rowi | (uint64_t)j;
                                 const uint64_t e1 = ((uint64_t)j << row_bits) | (uint64_t)i;
@@ -274,11 +319,11 @@ __global__ __launch_bounds__(kBlock) void k_search(BuildArgs a, uint64_t *__rest
 }
 
 void launch_search(const BuildArgs &a, uint64_t *list, uint32_t *counter, int64_t cap,
-                   int row_bits, hipStream_t s)
+                   int row_bits, int xcd_remap, hipStream_t s)
 {
     if (a.n <= 0) return;
     hipLaunchKernelGGL(k_search, dim3((unsigned)((a.n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                       s, a, list, counter, cap, row_bits);
+                       s, a, list, counter, cap, row_bits, xcd_remap);
 }
 
 // Row pointers and partners from the sorted entry list.  Entry q starts row
@@ -309,10 +354,17 @@ void launch_csr_from_sorted(const uint64_t *sorted, int64_t m, int row_bits, int
 __global__ __launch_bounds__(kBlock) void k_max_degree(int64_t n, const int32_t *__restrict__ rp,
                                                       uint32_t *__restrict__ out)
 {
+    __shared__ uint32_t wm[kWavesPerBlock];
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     uint32_t d = i < n ? (uint32_t)(rp[i + 1] - rp[i]) : 0u;
     for (int o = kWave / 2; o > 0; o >>= 1) d = max(d, (uint32_t)__shfl_xor(d, o, kWave));
-    if ((threadIdx.x & (kWave - 1)) == 0 && d) atomicMax(out, d);
+    if ((threadIdx.x & (kWave - 1)) == 0) wm[threadIdx.x / kWave] = d;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t m = 0;
+        for (int k = 0; k < kWavesPerBlock; ++k) m = max(m, wm[k]);
+        if (m) atomicMax(out, m);
+    }
 }
 
 void launch_max_degree(int64_t n, const int32_t *rp, uint32_t *out, hipStream_t s)

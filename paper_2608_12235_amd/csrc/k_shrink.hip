@@ -44,21 +44,18 @@ __global__ __launch_bounds__(kBlock) void k_shrink(const SegPtrs *__restrict__ P
     const SegPtrs p = P[seg];
     const SegState *s = S + seg;
     const double L = s->L, hL = s->hL;
-    const int cur = s->cur;
-    const double *X = cur ? p.x[1][0] : p.x[0][0];
-    const double *Y = cur ? p.x[1][1] : p.x[0][1];
-    const double *Z = cur ? p.x[1][2] : p.x[0][2];
+    const P4 *Q = s->cur ? p.p[1] : p.p[0];
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double kmin = INFINITY;
     if (i < n) {
-        const double xi = X[i], yi = Y[i], zi = Z[i], di = p.d0[i];
+        const P4 qi = Q[i];
         for (int32_t q = p.rp[i]; q < p.rp[i + 1]; ++q) {
-            const int32_t j = p.col[q];
-            const double dx = min_image(X[j] - xi, L, hL);
-            const double dy = min_image(Y[j] - yi, L, hL);
-            const double dz = min_image(Z[j] - zi, L, hL);
+            const P4 qj = Q[p.col[q]];
+            const double dx = min_image(qj.x - qi.x, L, hL);
+            const double dy = min_image(qj.y - qi.y, L, hL);
+            const double dz = min_image(qj.z - qi.z, L, hL);
             const double r2 = (dx * dx + dy * dy) + dz * dz;
-            kmin = fmin(kmin, contact_scale(r2, 0.5 * (di + p.d0[j])));
+            kmin = fmin(kmin, contact_scale(r2, 0.5 * (qi.d + qj.d)));
         }
     }
     kmin = wave_min(kmin);

@@ -36,11 +36,16 @@ struct SchedDev {
     int64_t budget[kMaxRungs];
 };
 
+// Position and relative diameter of one particle, 32 bytes: a neighbour
+// gather touches a single cache line.
+struct alignas(32) P4 {
+    double x, y, z, d;
+};
+
 // Array pointers of one segment (host-owned; uploaded whole).
 struct SegPtrs {
-    double *x[2][3];      // ping-pong positions, SoA
-    double *d0;           // relative diameters
-    double *m[3], *v[3];  // Adam moments
+    P4 *p[2];             // ping-pong (x, y, z, D0)
+    double *m[3], *v[3];  // Adam moments, SoA
     double *xref[3];      // positions at the last list build
     int32_t *orig;        // sorted index -> user index
     uint8_t *lev;         // size class

@@ -37,8 +37,9 @@ struct alignas(16) HashSlot {
 struct BuildArgs {
     int64_t n;
     int32_t nlev, mb;       // classes; Morton bits below the class field
+    int32_t tshift, tiles;  // key bit of the tile field; tiles per axis (power of 2)
     double L, hL, kb, opg, sk2;
-    const double *x, *y, *z, *d0;
+    const P4 *pos;
     const uint8_t *lev;
     const uint64_t *skey;   // sorted keys (after the sort)
     struct HashSlot *hash;  // open-addressing table of occupied cells
@@ -51,10 +52,9 @@ void launch_keys(const BuildArgs &a, uint64_t *keys, uint32_t *vals, hipStream_t
 struct PermArgs {
     int64_t n;
     const uint32_t *perm;
-    const double *xs[3];
-    double *xd[3];
+    const P4 *ps;
+    P4 *pd;
     double *xref[3];
-    const double *d0s; double *d0d;
     const double *ms[3]; double *md[3];
     const double *vs[3]; double *vd[3];
     const int32_t *os; int32_t *od;
@@ -68,7 +68,7 @@ void launch_hash_build(const BuildArgs &a, int64_t cap, hipStream_t s);
 // arbitrary order; *counter (zeroed by the caller) receives the number of
 // entries, which may exceed cap (then only cap were stored).
 void launch_search(const BuildArgs &a, uint64_t *list, uint32_t *counter, int64_t cap,
-                   int row_bits, hipStream_t s);
+                   int row_bits, int xcd_remap, hipStream_t s);
 // Full rows from the sorted entry list: rp[0..n] and col[0..m).
 void launch_csr_from_sorted(const uint64_t *sorted, int64_t m, int row_bits, int64_t n,
                             int32_t *rp, int32_t *col, hipStream_t s);

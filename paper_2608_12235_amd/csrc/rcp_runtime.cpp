@@ -93,10 +93,9 @@ struct Seg {
     std::vector<double> dmax_upto;   // max D0 over classes <= l
     std::vector<double> dmax_lev;    // max D0 in class l
     std::vector<int64_t> lev_count;
-    // device arrays; D0, M, V, ORIG, LEV are double-buffered for the
-    // Morton permutation (live set `set`), positions ping-pong through X
-    double *X[2][3] = {};
-    double *D0[2] = {};
+    // device arrays; M, V, ORIG, LEV are double-buffered for the Morton
+    // permutation (live set `set`); positions with D0 ping-pong through Q
+    P4 *Q[2] = {};
     double *M[2][3] = {}, *V[2][3] = {};
     int32_t *ORIG[2] = {};
     uint8_t *LEV[2] = {};
@@ -147,9 +146,7 @@ struct rcp_ctx {
 
 static void ptrs_of(const Seg &s, SegPtrs &p)
 {
-    for (int b = 0; b < 2; ++b)
-        for (int a = 0; a < 3; ++a) p.x[b][a] = s.X[b][a];
-    p.d0 = s.D0[s.set];
+    for (int b = 0; b < 2; ++b) p.p[b] = s.Q[b];
     for (int a = 0; a < 3; ++a) {
         p.m[a] = s.M[s.set][a];
         p.v[a] = s.V[s.set][a];
@@ -270,7 +267,13 @@ static int rebuild(rcp_ctx *c, int k, double kappa)
         maxbits = std::max(maxbits, bits_for(nc - 1));
     }
     a.mb = 3 * maxbits;
-    const int nbits = a.mb + bits_for(s.nlev - 1);
+    // spatial tiles ahead of the class field (see k_neighbor.hip): 4 x 4 x 4
+    // when the key has room, else 2 x 2 x 2, else none
+    const int lb = bits_for(s.nlev - 1);
+    a.tshift = a.mb + lb;
+    a.tiles = (a.tshift + 6 <= 63) ? 4 : ((a.tshift + 3 <= 63) ? 2 : 1);
+    const int tbits = a.tiles == 4 ? 6 : (a.tiles == 2 ? 3 : 0);
+    const int nbits = a.tshift + tbits;
 
     // scratch sized for the particle count and the expected pair-list length
     const int row_bits = std::max(1, bits_for(n - 1));
@@ -289,10 +292,7 @@ static int rebuild(rcp_ctx *c, int k, double kappa)
 
     // 1. keys at the current positions, stable sort, permutation
     const int cur = s.cur, ncur = cur ^ 1, set = s.set, nset = set ^ 1;
-    a.x = s.X[cur][0];
-    a.y = s.X[cur][1];
-    a.z = s.X[cur][2];
-    a.d0 = s.D0[set];
+    a.pos = s.Q[cur];
     a.lev = s.LEV[set];
     launch_keys(a, c->kA, c->vA, st);
     const int par = radix_sort(c->kA, c->vA, c->kB, c->vB, n, nbits, c->hist, c->tiles,
@@ -302,17 +302,15 @@ static int rebuild(rcp_ctx *c, int k, double kappa)
     PermArgs pa;
     pa.n = n;
     pa.perm = perm;
+    pa.ps = s.Q[cur];
+    pa.pd = s.Q[ncur];
     for (int ax = 0; ax < 3; ++ax) {
-        pa.xs[ax] = s.X[cur][ax];
-        pa.xd[ax] = s.X[ncur][ax];
         pa.xref[ax] = s.XREF[ax];
         pa.ms[ax] = s.M[set][ax];
         pa.md[ax] = s.M[nset][ax];
         pa.vs[ax] = s.V[set][ax];
         pa.vd[ax] = s.V[nset][ax];
     }
-    pa.d0s = s.D0[set];
-    pa.d0d = s.D0[nset];
     pa.os = s.ORIG[set];
     pa.od = s.ORIG[nset];
     pa.ls = s.LEV[set];
@@ -322,10 +320,7 @@ static int rebuild(rcp_ctx *c, int k, double kappa)
     s.cur = ncur;
 
     // 2. occupied-cell hash on the sorted keys
-    a.x = s.X[ncur][0];
-    a.y = s.X[ncur][1];
-    a.z = s.X[ncur][2];
-    a.d0 = s.D0[nset];
+    a.pos = s.Q[ncur];
     a.lev = s.LEV[nset];
     a.skey = skey;
     a.hash = c->hash;
@@ -339,7 +334,7 @@ static int rebuild(rcp_ctx *c, int k, double kappa)
     uint32_t total = 0;
     for (int attempt = 0;; ++attempt) {
         launch_fill_u32(c->totals + 2, 1, 0u, st);
-        launch_search(a, list, c->totals + 2, lcap, row_bits, st);
+        launch_search(a, list, c->totals + 2, lcap, row_bits, c->tuning.xcd_remap, st);
         HIPCHK(hipMemcpyAsync(&total, c->totals + 2, sizeof total, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         if ((int64_t)total <= lcap) break;
@@ -399,7 +394,7 @@ static int rebuild(rcp_ctx *c, int k, double kappa)
 static void launch_one_iteration(rcp_ctx *c)
 {
     const int flags = (c->tuning.xcd_remap ? 1 : 0) | (c->tuning.fused_tail ? 2 : 0) |
-                      (c->tuning.heavy_first ? 4 : 0);
+                      (c->tuning.heavy_first ? 4 : 0) | ((c->tuning.variant & 7) << 8);
     launch_iterate(c->d_ptrs, c->d_state, c->d_work, c->d_partials, c->nitems, flags, c->stream);
     if (!c->tuning.fused_tail) launch_tail(c->d_state, c->d_partials, (int)c->segs.size(), c->stream);
 }
@@ -602,11 +597,10 @@ static int seg_setup(rcp_ctx *c, int k, int64_t n, const double *d0, double L, d
     // device arrays
     for (int b = 0; b < 2; ++b) {
         for (int a = 0; a < 3; ++a) {
-            CHK(dalloc(&s.X[b][a], n));
             CHK(dalloc(&s.M[b][a], n));
             CHK(dalloc(&s.V[b][a], n));
         }
-        CHK(dalloc(&s.D0[b], n));
+        CHK(dalloc(&s.Q[b], n));
         CHK(dalloc(&s.ORIG[b], n));
         CHK(dalloc(&s.LEV[b], n));
     }
@@ -617,12 +611,16 @@ static int seg_setup(rcp_ctx *c, int k, int64_t n, const double *d0, double L, d
     std::vector<double> soa(n);
     for (int a = 0; a < 3; ++a) {
         for (int64_t i = 0; i < n; ++i) soa[i] = x[3 * i + a];
-        HIPCHK(hipMemcpy(s.X[0][a], soa.data(), sizeof(double) * n, hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(s.XREF[a], soa.data(), sizeof(double) * n, hipMemcpyHostToDevice));
         HIPCHK(hipMemset(s.M[0][a], 0, sizeof(double) * n));
         HIPCHK(hipMemset(s.V[0][a], 0, sizeof(double) * n));
     }
-    HIPCHK(hipMemcpy(s.D0[0], d0, sizeof(double) * n, hipMemcpyHostToDevice));
+    {
+        std::vector<P4> q(n);
+        for (int64_t i = 0; i < n; ++i) q[i] = P4{x[3 * i], x[3 * i + 1], x[3 * i + 2], d0[i]};
+        HIPCHK(hipMemcpy(s.Q[0], q.data(), sizeof(P4) * n, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(s.Q[1], q.data(), sizeof(P4) * n, hipMemcpyHostToDevice));
+    }
     std::vector<int32_t> orig(n);
     for (int64_t i = 0; i < n; ++i) orig[i] = (int32_t)i;
     HIPCHK(hipMemcpy(s.ORIG[0], orig.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
@@ -663,11 +661,10 @@ static void destroy_ctx(rcp_ctx *c)
     for (auto &s : c->segs) {
         for (int b = 0; b < 2; ++b) {
             for (int a = 0; a < 3; ++a) {
-                dfree(s.X[b][a]);
                 dfree(s.M[b][a]);
                 dfree(s.V[b][a]);
             }
-            dfree(s.D0[b]);
+            dfree(s.Q[b]);
             dfree(s.ORIG[b]);
             dfree(s.LEV[b]);
         }
@@ -727,36 +724,39 @@ void rcp_tuning_default(rcp_tuning *t)
     t->graph_iters = 16;
     t->xcd_remap = 1;
     t->fused_tail = 0;
-    t->heavy_first = 1;
+    t->heavy_first = 0;
+    t->variant = 3;
 }
 
-// Default rung table (our reading of App. A; the paper does not list its
-// values): a densification rung at mu~ = 1e-2 for n_trig iterations, two
-// rungs at 1e-3 and 1e-4 (n_trig/4 each), two mu cycles 1e-3 <-> 1e-4
-// (n_trig/8 each) and the final relaxation at 1e-5 with a step-size
-// half-life of a quarter of its cap (cap 2 n_trig); stop tolerance 5e-4.
-int rcp_schedule_default(int64_t n, int dim, int Y, int X, int64_t n_min, rcp_schedule *out)
+// Default rung table; see include/rcp.h for the reading it encodes.
+int rcp_schedule_default(int64_t n, int dim, double S, int Y, int X, int64_t n_min,
+                         rcp_schedule *out)
 {
     if (!out || n <= 0 || dim < 1) return fail(RCP_EINVAL, "bad arguments to rcp_schedule_default");
     std::memset(out, 0, sizeof *out);
     out->size = sizeof(rcp_schedule);
     const double nt_d = std::ceil(4000.0 * Y + X * std::sqrt((double)n * dim) - 2000.0);
     const int64_t nt = std::max<int64_t>((int64_t)nt_d, n_min);
+    const double Sr = std::max(S, 1.0);
+    const double fx = std::max(1.0, std::sqrt(Sr / 10.0));
+    const double fk = std::min(1.0, 160.0 / Sr);
+    const double fb = 1.0 + std::max(0.0, std::log10(Sr / 10.0));
     struct R { double mu, ex, ek, hl, bf; };
     const R rungs[] = {
         {1e-2, 1e-2, 1e-3, 0.0, 1.0},      {1e-3, 5e-3, 5e-4, 0.0, 0.25},
         {1e-4, 2.5e-3, 2.5e-4, 0.0, 0.25}, {1e-3, 2.5e-3, 2.5e-4, 0.0, 0.125},
         {1e-4, 2.5e-3, 2.5e-4, 0.0, 0.125}, {1e-3, 2.5e-3, 2.5e-4, 0.0, 0.125},
-        {1e-4, 2.5e-3, 2.5e-4, 0.0, 0.125}, {1e-5, 1.25e-3, 1.25e-4, 0.25, 2.0},
+        {1e-4, 2.5e-3, 2.5e-4, 0.0, 0.125}, {1e-5, 1.25e-3, 1.25e-4, 1.0 / 16, 2.0},
     };
     out->n_rungs = (int32_t)(sizeof rungs / sizeof rungs[0]);
     out->absolute = 0;
     out->tol = 5e-4;
     for (int r = 0; r < out->n_rungs; ++r) {
         out->mu[r] = rungs[r].mu;
-        out->eta_x[r] = rungs[r].ex;
-        out->eta_k[r] = rungs[r].ek;
-        out->budget[r] = std::max<int64_t>(1, (int64_t)std::ceil(rungs[r].bf * (double)nt));
+        out->eta_x[r] = rungs[r].ex * fx;
+        out->eta_k[r] = rungs[r].ek * fk;
+        const double bf = rungs[r].bf * (r == 0 ? fb : 1.0);
+        out->budget[r] = std::max<int64_t>(1, (int64_t)std::ceil(bf * (double)nt));
         out->decay[r] = rungs[r].hl <= 0 ? 1.0
                                          : std::pow(2.0, -1.0 / (rungs[r].hl * (double)out->budget[r]));
     }
@@ -843,7 +843,8 @@ int rcp_pack_init(int dim, const double *box, int64_t n, const double *d0, doubl
 int rcp_set_tuning(rcp_ctx *c, const rcp_tuning *t)
 {
     if (!c || !t || t->size != sizeof(rcp_tuning)) return fail(RCP_EINVAL, "bad tuning");
-    if (t->graph_iters < 1 || t->graph_iters > 4096) return fail(RCP_EINVAL, "bad tuning values");
+    if (t->graph_iters < 1 || t->graph_iters > 4096 || t->variant < 0 || t->variant > 7)
+        return fail(RCP_EINVAL, "bad tuning values");
     c->tuning = *t;
     c->graph_valid = false;
     return RCP_OK;
@@ -903,21 +904,21 @@ int rcp_get_state(rcp_ctx *c, int k, double *x, double *kappa, double *diam)
     CHK(pull_state(c));
     Seg &s = c->segs[k];
     const int64_t n = s.n;
-    std::vector<double> a(n);
+    std::vector<P4> q(n);
     std::vector<int32_t> orig(n);
     HIPCHK(hipMemcpy(orig.data(), s.ORIG[s.set], sizeof(int32_t) * n, hipMemcpyDeviceToHost));
-    if (x) {
-        for (int ax = 0; ax < 3; ++ax) {
-            HIPCHK(hipMemcpy(a.data(), s.X[s.cur][ax], sizeof(double) * n, hipMemcpyDeviceToHost));
-            for (int64_t i = 0; i < n; ++i) x[3 * (int64_t)orig[i] + ax] = a[i];
-        }
-    }
+    HIPCHK(hipMemcpy(q.data(), s.Q[s.cur], sizeof(P4) * n, hipMemcpyDeviceToHost));
     const double kap = c->h_state[k].kappa;
-    if (kappa) *kappa = kap;
-    if (diam) {
-        HIPCHK(hipMemcpy(a.data(), s.D0[s.set], sizeof(double) * n, hipMemcpyDeviceToHost));
-        for (int64_t i = 0; i < n; ++i) diam[orig[i]] = kap * a[i];
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t u = orig[i];
+        if (x) {
+            x[3 * u] = q[i].x;
+            x[3 * u + 1] = q[i].y;
+            x[3 * u + 2] = q[i].z;
+        }
+        if (diam) diam[u] = kap * q[i].d;
     }
+    if (kappa) *kappa = kap;
     return RCP_OK;
 }
 
@@ -1206,6 +1207,67 @@ int rcp_adjoint_dev(rcp_ctx *c, const double *x_dev, double kappa, double mu, do
     CHK(eval_current(c, 0, x_dev, kappa, mu, gx_dev, st));
     hipLaunchKernelGGL(k_gk_out, dim3(1), dim3(1), 0, st, c->out, gk_dev);
     HIPCHK(hipGetLastError());
+    return RCP_OK;
+}
+
+int rcp_time_iterations(rcp_ctx *c, int64_t n_iters, double *iterate_us, double *tail_us,
+                        int64_t *done)
+{
+    if (!c || n_iters < 1) return fail(RCP_EINVAL, "bad arguments");
+    const int ns = (int)c->segs.size();
+    hipLaunchKernelGGL(k_extend, dim3((ns + 63) / 64), dim3(64), 0, c->stream, c->d_state, ns,
+                       n_iters);
+    constexpr int kBatch = 32;
+    std::vector<hipEvent_t> ev(3 * kBatch);
+    for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+    double it_ms = 0, tl_ms = 0;
+    int64_t n_done = 0;
+    int rc = RCP_OK;
+    const int flags = (c->tuning.xcd_remap ? 1 : 0) | (c->tuning.heavy_first ? 4 : 0) |
+                      ((c->tuning.variant & 7) << 8);
+    for (;;) {
+        if ((rc = pull_state(c)) != RCP_OK) break;
+        bool any = false;
+        for (int k = 0; k < ns && rc == RCP_OK; ++k) {
+            const int32_t f = c->h_state[k].flags;
+            if (seg_done(f)) continue;
+            if (f & (F_REBUILD | F_STALE)) rc = rebuild(c, k, c->h_state[k].kappa);
+            any = true;
+        }
+        if (rc != RCP_OK || !any) break;
+        if ((rc = pull_state(c)) != RCP_OK) break;
+        int64_t before = 0;
+        for (int k = 0; k < ns; ++k) before += c->h_state[k].iters;
+        for (int b = 0; b < kBatch; ++b) {
+            (void)hipEventRecord(ev[3 * b], c->stream);
+            launch_iterate(c->d_ptrs, c->d_state, c->d_work, c->d_partials, c->nitems, flags,
+                           c->stream);
+            (void)hipEventRecord(ev[3 * b + 1], c->stream);
+            launch_tail(c->d_state, c->d_partials, ns, c->stream);
+            (void)hipEventRecord(ev[3 * b + 2], c->stream);
+        }
+        if ((rc = pull_state(c)) != RCP_OK) break;
+        int64_t after = 0;
+        for (int k = 0; k < ns; ++k) after += c->h_state[k].iters;
+        // a packing runs consecutive launches until it goes idle, so the
+        // first (after - before) launches of a one-packing context did work
+        const int64_t worked = std::min<int64_t>(after - before, kBatch);
+        for (int64_t b = 0; b < worked; ++b) {
+            float a = 0, t = 0;
+            (void)hipEventElapsedTime(&a, ev[3 * b], ev[3 * b + 1]);
+            (void)hipEventElapsedTime(&t, ev[3 * b + 1], ev[3 * b + 2]);
+            it_ms += a;
+            tl_ms += t;
+        }
+        n_done += worked;
+        c->stats.iterations += after - before;
+        if (after == before) break;
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (rc != RCP_OK) return rc;
+    if (iterate_us) *iterate_us = n_done ? 1e3 * it_ms / (double)n_done : 0.0;
+    if (tail_us) *tail_us = n_done ? 1e3 * tl_ms / (double)n_done : 0.0;
+    if (done) *done = n_done;
     return RCP_OK;
 }
 

@@ -216,15 +216,17 @@ def test_energy_grad_c3(rcp, orc, c3):
 
 
 # ------------------------------------------------------------- Adam steps
-@pytest.mark.parametrize("steps,fused,graph", [(1, 0, 16), (10, 0, 16), (10, 1, 16),
-                                               (25, 1, 1), (25, 0, 4)])
-def test_adam_steps_match_oracle(rcp, orc, steps, fused, graph):
+@pytest.mark.parametrize("steps,fused,graph,variant", [(1, 0, 16, 3), (10, 0, 16, 0),
+                                                       (10, 1, 16, 1), (25, 1, 1, 2),
+                                                       (25, 0, 4, 3)])
+def test_adam_steps_match_oracle(rcp, orc, steps, fused, graph, variant):
     w, x, k = _dense_c1_state(orc, iters=1500)
     mu, ex, ek = 2e-3, 2e-3, 2e-4
     P = orc.default_params(w.d0, s=0.3, g=0.02)
     p = rcp.Packing(w.d0, w.L, k, 0, init="none",
                     params=rcp.make_params(skin_s=0.3, skin_g=0.02, eps_x=P.eps_x),
-                    tuning=rcp.make_tuning(fused_tail=fused, graph_iters=graph))
+                    tuning=rcp.make_tuning(fused_tail=fused, graph_iters=graph,
+                                           variant=variant))
     p.set_state(x, k)
     p.adam_step(mu, ex, ek, steps)
     xg, kg = p.get_state()
@@ -287,12 +289,14 @@ def test_shrink_bit_exact(rcp, orc):
 # -------------------------------------------------------------- whole runs
 def test_inflate_run_deterministic(rcp, orc):
     # bit-identical reruns; the fused tail and the graph length change
-    # nothing but launch structure, so they give the same bits too
+    # nothing but launch structure, so they give the same bits too (the
+    # kernel variant is kept fixed: it may change the summation order)
     w = ri.c1_lognormal(1)
     out = []
-    for fused, graph in [(0, 16), (0, 16), (1, 16), (1, 3)]:
+    for fused, graph, variant in [(0, 16, 3), (0, 16, 3), (1, 16, 3), (1, 3, 3)]:
         p = rcp.Packing(w.d0, w.L, 1.0, w.seed, init="rsa", params=rcp.make_params(skin_s=0.3),
-                        tuning=rcp.make_tuning(fused_tail=fused, graph_iters=graph))
+                        tuning=rcp.make_tuning(fused_tail=fused, graph_iters=graph,
+                                               variant=variant))
         out.append(p.inflate_run()[0])
         p.close()
     for o in out[1:]:

@@ -400,6 +400,7 @@ def test_table_cap_sanity(orc, alpha, S, phi_paper):
     L = ri.box_for_phi(d0, 0.1)
     x = orc.rsa(d0, L, 1.0, 1)
     st = orc.RunState(x, d0, L, 1.0)
-    status, res, _ = orc.run(st, orc.default_params(d0, s=1.0), orc.default_schedule(2000))
+    S = float(d0.max() / d0.min())
+    status, res, _ = orc.run(st, orc.default_params(d0, s=1.0), orc.default_schedule(2000, S=S))
     assert status == 0
     assert abs(res.phi - phi_paper) < 0.03
