@@ -64,6 +64,18 @@ def cpu_baseline(d0, L, phi, skin_s, skin_g, target_s=12.0):
                       "excluded), %.1f s" % (iters, n, phi, npairs, t)}
 
 
+def copy_reference(torch, mib):
+    """Plain copy of a known size: each launch reads and writes mib MiB."""
+    a = torch.empty(mib * 131072, dtype=torch.float64, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_reference_mib": mib, "launches": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,7 +83,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--phi0", type=float, default=0.05)
-    ap.add_argument("--skin", type=float, default=4.0)
+    ap.add_argument("--skin", type=float, default=16.0)
     ap.add_argument("--skin-g", type=float, default=0.02)
     ap.add_argument("--graph-iters", type=int, default=None)
     ap.add_argument("--fused-tail", type=int, default=None)
@@ -79,6 +91,9 @@ def main():
     ap.add_argument("--xcd-remap", type=int, default=None)
     ap.add_argument("--variant", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB three times "
+                         "(the known-size reference for hardware byte counters) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -92,6 +107,9 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_reference > 0:
+        copy_reference(torch, args.copy_reference)
+        return
     import rcp_inputs as ri
     import paper_2608_12235_amd as rcp
 

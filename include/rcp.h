@@ -108,10 +108,11 @@ typedef struct {
  * stop test max delta < tol is applied before each update, and budget of the
  * last rung is its iteration cap.  decay[r] multiplies mu and both step
  * sizes after every iteration of rung r.  When absolute == 0, at the start of rung r:
- *     mu    = (mu[r] * N) / (kappa * sum D0)
+ *     mu    = (mu[r] * N_v) / (kappa * sum D0),  N_v = (sum D0^3)^2 / sum D0^6
  *     eta_x = eta_x[r] * (kappa * D0_min)
  *     eta_k = eta_k[r] * kappa
- * with kappa its value at that moment; when absolute != 0 the three numbers
+ * with kappa its value at that moment (N_v is formed with compensated
+ * sums in index order); when absolute != 0 the three numbers
  * are used as given.  size must be sizeof(rcp_schedule). */
 typedef struct {
     uint32_t size;
@@ -176,9 +177,14 @@ void rcp_tuning_default(rcp_tuning *t);
  * both step sizes halving every 1/16 of its cap (cap 2 n_trig), so mu is
  * annealed towards 0; stop tolerance 5e-4.  For broad
  * distributions the position steps are multiplied by max(1, sqrt(S/10)),
- * the kappa steps by min(1, 160/S) and the densification budget by
+ * the kappa steps by min(1, sqrt(160/S)) and the densification budget by
  * 1 + max(0, log10(S/10)), so that small spheres can move out of the way
- * of growing large ones.  Returns RCP_EINVAL for n <= 0 or dim < 1. */
+ * of growing large ones.  In relative schedules mu~ is turned into
+ * mu = mu~ N_v / (kappa sum D0) at each rung start, N_v = (sum D0^3)^2 /
+ * sum D0^6 (the volume participation number: N for equal spheres, about the
+ * number of volume-carrying spheres for a broad distribution), so the
+ * equilibrium summed overlap is mu~ N_v.  Returns RCP_EINVAL for n <= 0 or
+ * dim < 1. */
 int rcp_schedule_default(int64_t n, int dim, double S, int Y, int X, int64_t n_min,
                          rcp_schedule *out);
 

@@ -246,7 +246,8 @@ def n_trig(N, d=3, Y=2, X=9):
 # (mu~, eta_x~, eta_k~, half-life as a fraction of the rung, budget fraction)
 # The half-life applies to mu and both step sizes; only the final rung
 # decays, so mu is annealed towards 0 there (the dense endpoint of App. A).
-# mu = mu~ N / (kappa sum D0) sets the equilibrium summed overlap to mu~ N;
+# mu = mu~ N_v / (kappa sum D0) sets the equilibrium summed overlap to mu~ N_v,
+# N_v = (sum D0^3)^2 / sum D0^6 (volume participation number);
 # eta_x = eta_x~ kappa D0_min, eta_k = eta_k~ kappa at the rung start.
 DEFAULT_RUNGS = [
     (1e-2, 1e-2, 1e-3, 0.0, 1.0),        # densify
@@ -266,13 +267,13 @@ def size_ratio_factors(S):
     Our reading for broad distributions (the paper does not list its rung
     values): a large sphere's radius grows by about eta_k D_max / 2 per
     update, and small spheres must be able to move away from it, so the
-    kappa step shrinks as 1/S beyond S = 160, the position step grows as
-    sqrt(S / 10), and the densification rung is lengthened by
+    kappa step shrinks as sqrt(160 / S) beyond S = 160, the position step
+    grows as sqrt(S / 10), and the densification rung is lengthened by
     1 + log10(S / 10).  All three are 1 for S <= 10.
     """
     S = max(float(S), 1.0)
     fx = max(1.0, math.sqrt(S / 10.0))
-    fk = min(1.0, 160.0 / S)
+    fk = min(1.0, math.sqrt(160.0 / S))
     fb = 1.0 + max(0.0, math.log10(S / 10.0))
     return fx, fk, fb
 

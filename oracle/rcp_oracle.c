@@ -712,16 +712,19 @@ static void run_grad(run_t *R, double kappa, double *Eov, double *Sdrd,
 
 /* Rung parameters at the start of rung r, from kappa at that moment.
  * Relative schedules scale mu so that the equilibrium summed overlap is
- * mu~ N (from dE/dkappa = 0), and the step sizes by the current length and
+ * mu~ N_v (from dE/dkappa = 0), where N_v = (sum D0^3)^2 / sum D0^6 is the
+ * volume participation number (N for equal spheres; for a broad
+ * distribution about the number of spheres that carry the solid volume and
+ * hence the contact network), and the step sizes by the current length and
  * kappa scales; absolute schedules take the numbers as they are. */
-static void rung_start(const orc_sched *S, int r, double kappa, int64_t n,
+static void rung_start(const orc_sched *S, int r, double kappa, double nvol,
                        double sumd0, double d0min, double *mu, double *ex,
                        double *ek)
 {
     if (S->absolute) {
         *mu = S->mu[r]; *ex = S->eta_x[r]; *ek = S->eta_k[r];
     } else {
-        *mu = (S->mu[r] * (double)n) / (kappa * sumd0);
+        *mu = (S->mu[r] * nvol) / (kappa * sumd0);
         *ex = S->eta_x[r] * (kappa * d0min);
         *ek = S->eta_k[r] * kappa;
     }
@@ -767,19 +770,23 @@ int orc_run(int64_t n, double *x, const double *d0, double L, double *kappa,
     R.xref = malloc(sizeof(double) * 3 * (size_t)n);
     R.g = malloc(sizeof(double) * 3 * (size_t)n);
     R.d0min = d0[0];
-    nsum_t sd = {0, 0};
+    nsum_t sd = {0, 0}, s3 = {0, 0}, s6 = {0, 0};
     for (int64_t i = 0; i < n; ++i) {
         if (d0[i] < R.d0min) R.d0min = d0[i];
         nadd(&sd, d0[i]);
+        const double c3 = d0[i] * d0[i] * d0[i];
+        nadd(&s3, c3);
+        nadd(&s6, c3 * c3);
     }
     R.sumd0 = nval(&sd);
+    const double nvol = (nval(&s3) * nval(&s3)) / nval(&s6);
     const double b1 = P->beta1, b2 = P->beta2;
     int64_t t = ctl[0];
     int r = (int)ctl[1];
     int64_t itr = ctl[2];
     double mu = etas[0], ex = etas[1], ek = etas[2];
     if (ctl[3]) {
-        rung_start(S, r, *kappa, n, R.sumd0, R.d0min, &mu, &ex, &ek);
+        rung_start(S, r, *kappa, nvol, R.sumd0, R.d0min, &mu, &ex, &ek);
         ctl[3] = 0;
     }
     /* beta powers as repeated products (the same rounding on every side) */
@@ -817,7 +824,7 @@ int orc_run(int64_t n, double *x, const double *d0, double L, double *kappa,
             if (r == S->n_rungs - 1) { status = 1; ++it; break; }
             r += 1;
             itr = 0;
-            rung_start(S, r, *kappa, n, R.sumd0, R.d0min, &mu, &ex, &ek);
+            rung_start(S, r, *kappa, nvol, R.sumd0, R.d0min, &mu, &ex, &ek);
         }
         /* list validity for the next iteration */
         double lim = P->skin_s * R.kb * R.d0min;

@@ -182,7 +182,7 @@ __device__ __forceinline__ void rung_start(SegState *s, int r)
         s->eta_x = q.eta_x[r];
         s->eta_k = q.eta_k[r];
     } else {
-        s->mu = (q.mu[r] * (double)s->n) / (s->kappa * s->sumd0);
+        s->mu = (q.mu[r] * s->nvol) / (s->kappa * s->sumd0);
         s->eta_x = q.eta_x[r] * (s->kappa * s->d0min);
         s->eta_k = q.eta_k[r] * s->kappa;
     }

@@ -59,6 +59,7 @@ struct SegState {
     // host: constants
     int64_t n;
     double L, hL, d0min, sumd0;
+    double nvol;          // (sum D0^3)^2 / sum D0^6, the pressure normaliser
     double beta1, beta2, eps_x, eps_k;
     int32_t pad_h;
     int32_t nblocks;      // iteration-grid blocks of this segment

@@ -87,7 +87,7 @@ static int dgrow(T **p, int64_t *cap, int64_t need)
 // ------------------------------------------------------------ context
 struct Seg {
     int64_t n = 0;
-    double L = 0, d0min = 0, d0max = 0, sumd0 = 0, sumd03 = 0, kappa0 = 1;
+    double L = 0, d0min = 0, d0max = 0, sumd0 = 0, sumd03 = 0, nvol = 0, kappa0 = 1;
     uint64_t seed = 0;
     int nlev = 1;
     std::vector<double> dmax_upto;   // max D0 over classes <= l
@@ -545,7 +545,7 @@ static int seg_setup(rcp_ctx *c, int k, int64_t n, const double *d0, double L, d
     s.seed = seed;
     s.d0min = d0[0];
     s.d0max = d0[0];
-    double sum = 0, cs = 0, sum3 = 0, cs3 = 0;   // Neumaier sums
+    double sum = 0, cs = 0, sum3 = 0, cs3 = 0, sum6 = 0, cs6 = 0;   // Neumaier sums
     auto nadd = [](double &acc, double &comp, double v) {
         double t = acc + v;
         if (std::fabs(acc) >= std::fabs(v)) comp += (acc - t) + v;
@@ -556,10 +556,13 @@ static int seg_setup(rcp_ctx *c, int k, int64_t n, const double *d0, double L, d
         s.d0min = std::min(s.d0min, d0[i]);
         s.d0max = std::max(s.d0max, d0[i]);
         nadd(sum, cs, d0[i]);
-        nadd(sum3, cs3, d0[i] * d0[i] * d0[i]);
+        const double c3 = d0[i] * d0[i] * d0[i];
+        nadd(sum3, cs3, c3);
+        nadd(sum6, cs6, c3 * c3);
     }
     s.sumd0 = sum + cs;
     s.sumd03 = sum3 + cs3;
+    s.nvol = (s.sumd03 * s.sumd03) / (sum6 + cs6);
     const double opg = 1.0 + c->params.skin_g, sk2 = (2.0 * c->params.skin_s) * s.d0min;
     if (!(kappa0 * (opg * s.d0max + sk2) < 0.5 * L))
         return fail(RCP_EBOX, "packing %d: listing cutoff at kappa0 is not below L/2", k);
@@ -637,6 +640,7 @@ static int seg_setup(rcp_ctx *c, int k, int64_t n, const double *d0, double L, d
     st.hL = 0.5 * L;
     st.d0min = s.d0min;
     st.sumd0 = s.sumd0;
+    st.nvol = s.nvol;
     st.beta1 = c->params.beta1;
     st.beta2 = c->params.beta2;
     st.eps_x = c->params.eps_x > 0 ? c->params.eps_x : 1e-12 / (kappa0 * s.d0max);
@@ -725,7 +729,7 @@ void rcp_tuning_default(rcp_tuning *t)
     t->xcd_remap = 1;
     t->fused_tail = 0;
     t->heavy_first = 0;
-    t->variant = 3;
+    t->variant = 1;
 }
 
 // Default rung table; see include/rcp.h for the reading it encodes.
@@ -739,7 +743,7 @@ int rcp_schedule_default(int64_t n, int dim, double S, int Y, int X, int64_t n_m
     const int64_t nt = std::max<int64_t>((int64_t)nt_d, n_min);
     const double Sr = std::max(S, 1.0);
     const double fx = std::max(1.0, std::sqrt(Sr / 10.0));
-    const double fk = std::min(1.0, 160.0 / Sr);
+    const double fk = std::min(1.0, std::sqrt(160.0 / Sr));
     const double fb = 1.0 + std::max(0.0, std::log10(Sr / 10.0));
     struct R { double mu, ex, ek, hl, bf; };
     const R rungs[] = {
