@@ -87,7 +87,8 @@ def main():
     ap.add_argument("--skin-g", type=float, default=0.02)
     ap.add_argument("--graph-iters", type=int, default=None)
     ap.add_argument("--fused-tail", type=int, default=None)
-    ap.add_argument("--heavy-first", type=int, default=None)
+    ap.add_argument("--row-cost", type=int, default=None)
+    ap.add_argument("--item-work", type=int, default=None)
     ap.add_argument("--xcd-remap", type=int, default=None)
     ap.add_argument("--variant", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -121,8 +122,10 @@ def main():
         tun.graph_iters = args.graph_iters
     if args.fused_tail is not None:
         tun.fused_tail = args.fused_tail
-    if args.heavy_first is not None:
-        tun.heavy_first = args.heavy_first
+    if args.row_cost is not None:
+        tun.row_cost = args.row_cost
+    if args.item_work is not None:
+        tun.item_work = args.item_work
     if args.xcd_remap is not None:
         tun.xcd_remap = args.xcd_remap
     if args.variant is not None:
@@ -182,7 +185,8 @@ def main():
             "skin_g": args.skin_g,
             "graph_iters": tun.graph_iters,
             "fused_tail": tun.fused_tail,
-            "heavy_first": tun.heavy_first,
+            "row_cost": tun.row_cost,
+            "item_work": tun.item_work,
             "xcd_remap": tun.xcd_remap,
             "variant": tun.variant,
             "rebuilds_in_timed_region": st["rebuilds"],

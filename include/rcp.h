@@ -84,23 +84,29 @@ typedef struct {
  * through summation order, which is fixed for a given tuning).  size must
  * be sizeof(rcp_tuning).
  *   graph_iters: iterations captured per HIP graph launch (1 = no graph);
- *   xcd_remap: 1 = map consecutive row blocks to the same XCD;
+ *   xcd_remap: 1 = map consecutive work items to the same XCD;
  *   fused_tail: 1 = the last block of a packing to finish an iteration
  *     reduces the partial sums and updates kappa and the schedule (one
  *     kernel per iteration), 0 = a separate one-block kernel does it;
- *   heavy_first: 1 = dispatch the last row blocks first;
  *   variant: gradient + Adam kernel variant, bit 0 = four partner gathers in
  *     flight per thread instead of two, bit 1 = the Adam operands are loaded
  *     before the partner loop (more latency hidden, more registers), bit 2 =
  *     streamed operands (moments, reference positions, list) are loaded and
- *     stored non-temporally so gathered positions stay in the L2. */
+ *     stored non-temporally so gathered positions stay in the L2;
+ *   row_cost, item_work: the rows of a packing (in list order) are cut into
+ *     work items of item_work units, a row costing row_cost units plus one
+ *     per listed partner, so each 256-thread block gets about the same
+ *     gather work whether its rows are small spheres or large ones; 1 <=
+ *     row_cost <= 65536 and 1 <= item_work <= 256 * row_cost (an item then
+ *     never holds more than 256 rows). */
 typedef struct {
     uint32_t size;
     int32_t graph_iters;
     int32_t xcd_remap;
     int32_t fused_tail;
-    int32_t heavy_first;
     int32_t variant;
+    int32_t row_cost;
+    int32_t item_work;
 } rcp_tuning;
 
 /* Annealing schedule: a table of rungs run in order (App. A).  Rung r lasts

@@ -33,8 +33,8 @@ class Params(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("size", C.c_uint32), ("graph_iters", C.c_int32), ("xcd_remap", C.c_int32),
-                ("fused_tail", C.c_int32), ("heavy_first", C.c_int32),
-                ("variant", C.c_int32)]
+                ("fused_tail", C.c_int32), ("variant", C.c_int32), ("row_cost", C.c_int32),
+                ("item_work", C.c_int32)]
 
 
 class Schedule(C.Structure):

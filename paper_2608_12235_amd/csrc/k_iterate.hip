@@ -323,8 +323,7 @@ __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ 
                                                    const WorkItem *__restrict__ W,
                                                    double *__restrict__ partials, int flags)
 {
-    int b = (flags & 1) ? remap_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
-    if (flags & 4) b = (int)gridDim.x - 1 - b;   // largest particles (last rows) first
+    const int b = (flags & 1) ? remap_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
     const WorkItem w = W[b];
     SegState *s = S + w.seg;
     if (s->flags & F_IDLE) return;
@@ -504,13 +503,60 @@ static void launch_variant(const SegPtrs *P, SegState *S, const WorkItem *W, dou
 void launch_iterate(const SegPtrs *P, SegState *S, const WorkItem *W, double *partials,
                     int nitems, int flags, hipStream_t st)
 {
-    // bit 0: XCD-aware order; bit 1: fused tail; bit 2: last rows first;
-    // bits 8-10: kernel variant (bit 8: four gathers in flight instead of two,
+    // bit 0: XCD-aware order; bit 1: fused tail; bits 8-10: kernel variant (bit 8: four gathers in flight instead of two,
     // bit 9: Adam operands loaded before the partner loop, bit 10: streamed
     // operands loaded and stored non-temporally)
-    const int f = flags & 5, variant = (flags >> 8) & 7;
+    const int f = flags & 1, variant = (flags >> 8) & 7;
     if (flags & 2) launch_variant<true>(P, S, W, partials, nitems, f, variant, st);
     else launch_variant<false>(P, S, W, partials, nitems, f, variant, st);
+}
+
+// Work items.  Row i of a packing has work coordinate w(i) = rc * i + rp[i]
+// (strictly increasing, w(0) = 0); item b holds the rows with w(i) in
+// [b * wk, (b + 1) * wk), i.e. it begins at the first row with w(i) >= b * wk.
+// Row i is that first row for the items b with w(i - 1) < b * wk <= w(i),
+// so one thread per row writes every boundary exactly once; items past the
+// last row keep begin = end = n from the fill.  With wk <= 256 rc no item
+// holds more than 256 rows.
+__global__ __launch_bounds__(kBlock) void k_items_fill(WorkItem *__restrict__ W, int64_t nslots,
+                                                      int seg, int64_t n)
+{
+    const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (b >= nslots) return;
+    WorkItem w;
+    w.seg = seg;
+    w.pad = 0;
+    w.begin = n;
+    w.end = n;
+    W[b] = w;
+}
+
+__global__ __launch_bounds__(kBlock) void k_items(const int32_t *__restrict__ rp, int64_t n,
+                                                 int64_t rc, int64_t wk,
+                                                 WorkItem *__restrict__ W, int64_t nslots)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int64_t hi = rc * i + (int64_t)rp[i];
+    const int64_t bl = i == 0 ? 0 : (rc * (i - 1) + (int64_t)rp[i - 1]) / wk + 1;
+    const int64_t bh = min(hi / wk, nslots - 1);
+    for (int64_t b = bl; b <= bh; ++b) {
+        W[b].begin = i;
+        if (b > 0) W[b - 1].end = i;
+    }
+}
+
+void launch_items(const int32_t *rp, int64_t n, int seg, int row_cost, int item_work,
+                  WorkItem *W, int64_t nslots, hipStream_t st)
+{
+    if (nslots <= 0) return;
+    const unsigned gf = (unsigned)((nslots + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_items_fill, dim3(gf), dim3(kBlock), 0, st, W, nslots, seg,
+                       rp ? n : (int64_t)0);
+    if (!rp || n <= 0) return;
+    const unsigned gi = (unsigned)((n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_items, dim3(gi), dim3(kBlock), 0, st, rp, n, (int64_t)row_cost,
+                       (int64_t)item_work, W, nslots);
 }
 
 void launch_tail(SegState *S, const double *partials, int nseg, hipStream_t st)

@@ -81,6 +81,11 @@ void launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 // flags bit 0: XCD-aware block order; bit 1: the last block of each packing
 // runs its tail (otherwise launch_tail must follow); bit 2: blocks of the
 // last rows (largest particles) first.
+// Work items of packing seg (nslots slots at W): rows are cut so that an
+// item covers item_work units of row_cost * row + row pointer; rp == nullptr
+// leaves every slot empty.
+void launch_items(const int32_t *rp, int64_t n, int seg, int row_cost, int item_work,
+                  WorkItem *W, int64_t nslots, hipStream_t st);
 void launch_iterate(const SegPtrs *P, SegState *S, const WorkItem *W, double *partials,
                     int nitems, int flags, hipStream_t s);
 void launch_tail(SegState *S, const double *partials, int nseg, hipStream_t s);

@@ -105,7 +105,9 @@ struct Seg {
     int set = 0;
     int cur = 0;          // host copy of the live position buffer
     int64_t npairs = 0, nnz = 0, maxdeg = 0, list_est = 0;
-    int blocks = 0;
+    int blocks = 0;              // work-item slots of this packing
+    int64_t first_item = 0;      // its first slot in the work table
+    int64_t slot_entries = 0;    // list length the slots are sized for
     int64_t rebuilds = 0;
     bool built = false;
 };
@@ -121,6 +123,7 @@ struct rcp_ctx {
     SegState *h_state = nullptr;    // pinned mirror of d_state
     WorkItem *d_work = nullptr;
     int nitems = 0;
+    int64_t items_cap = 0;
     double *d_partials = nullptr;
     // build scratch, shared by all segments
     uint64_t *kA = nullptr, *kB = nullptr;
@@ -187,34 +190,54 @@ static int put_field(rcp_ctx *c, int k, size_t offset, const T &v)
 }
 
 // ------------------------------------------------------------ work table
+// Work-item slots for packing k: enough for row_cost * n + slot_entries
+// units of item_work each (see rcp_tuning), plus one.
+static int64_t slots_for(const rcp_ctx *c, int64_t n, int64_t entries)
+{
+    const int64_t rc = c->tuning.row_cost, wk = c->tuning.item_work;
+    return (rc * n + entries) / wk + 2;
+}
+
+// Cut the rows of a built packing into work items (device kernel on its
+// row pointers); items of an unbuilt packing are left empty.
+static void fill_items(rcp_ctx *c, int k)
+{
+    Seg &s = c->segs[k];
+    WorkItem *w = c->d_work + s.first_item;
+    launch_items(s.built ? s.rp : nullptr, s.n, k, c->tuning.row_cost, c->tuning.item_work, w,
+                 s.blocks, c->stream);
+}
+
+// Lay out the work-item slots of all packings (a graph captured before is
+// invalid afterwards) and fill them.
 static int build_work(rcp_ctx *c)
 {
-    std::vector<WorkItem> items;
+    int64_t total = 0;
     for (size_t k = 0; k < c->segs.size(); ++k) {
         Seg &s = c->segs[k];
-        const int64_t first = (int64_t)items.size();
-        s.blocks = (int)((s.n + kBlock - 1) / kBlock);
-        for (int64_t b = 0; b < s.blocks; ++b) {
-            WorkItem w;
-            w.seg = (int)k;
-            w.pad = 0;
-            w.begin = b * kBlock;
-            w.end = std::min<int64_t>(s.n, (b + 1) * kBlock);
-            items.push_back(w);
-        }
-        const int32_t nb = (int32_t)(items.size() - first);
-        CHK(put_field(c, (int)k, offsetof(SegState, nblocks), nb));
-        CHK(put_field(c, (int)k, offsetof(SegState, bfirst), first));
+        const int64_t nb = slots_for(c, s.n, s.slot_entries);
+        if (nb > (int64_t)INT32_MAX / 4 || total + nb > (int64_t)INT32_MAX / 4)
+            return fail(RCP_ENOMEM, "work table too large");
+        s.blocks = (int)nb;
+        s.first_item = total;
+        total += nb;
     }
-    if ((int)items.size() > c->nitems) {
+    if (total > c->items_cap) {
         dfree(c->d_work);
         dfree(c->d_partials);
-        CHK(dalloc(&c->d_work, items.size()));
-        CHK(dalloc(&c->d_partials, 4 * items.size()));
+        c->d_work = nullptr;
+        c->d_partials = nullptr;
+        CHK(dalloc(&c->d_work, (size_t)total));
+        CHK(dalloc(&c->d_partials, 4 * (size_t)total));
+        c->items_cap = total;
     }
-    c->nitems = (int)items.size();
-    HIPCHK(hipMemcpyAsync(c->d_work, items.data(), sizeof(WorkItem) * items.size(),
-                          hipMemcpyHostToDevice, c->stream));
+    c->nitems = (int)total;
+    for (size_t k = 0; k < c->segs.size(); ++k) {
+        Seg &s = c->segs[k];
+        CHK(put_field(c, (int)k, offsetof(SegState, nblocks), (int32_t)s.blocks));
+        CHK(put_field(c, (int)k, offsetof(SegState, bfirst), s.first_item));
+        fill_items(c, (int)k);
+    }
     HIPCHK(hipStreamSynchronize(c->stream));
     c->graph_valid = false;
     return RCP_OK;
@@ -365,6 +388,13 @@ static int rebuild(rcp_ctx *c, int k, double kappa)
         CHK(dalloc(&s.col, (size_t)s.col_cap));
     }
     launch_csr_from_sorted(sorted, m, row_bits, n, s.rp, s.col, st);
+    s.built = true;
+    if (slots_for(c, n, m) > s.blocks) {
+        s.slot_entries = m + m / 4;
+        CHK(build_work(c));
+    } else {
+        fill_items(c, k);
+    }
 
     // 5. longest row (statistics)
     launch_fill_u32(c->totals + 1, 1, 0u, st);
@@ -394,7 +424,7 @@ static int rebuild(rcp_ctx *c, int k, double kappa)
 static void launch_one_iteration(rcp_ctx *c)
 {
     const int flags = (c->tuning.xcd_remap ? 1 : 0) | (c->tuning.fused_tail ? 2 : 0) |
-                      (c->tuning.heavy_first ? 4 : 0) | ((c->tuning.variant & 7) << 8);
+                      ((c->tuning.variant & 7) << 8);
     launch_iterate(c->d_ptrs, c->d_state, c->d_work, c->d_partials, c->nitems, flags, c->stream);
     if (!c->tuning.fused_tail) launch_tail(c->d_state, c->d_partials, (int)c->segs.size(), c->stream);
 }
@@ -611,6 +641,7 @@ static int seg_setup(rcp_ctx *c, int k, int64_t n, const double *d0, double L, d
     CHK(dalloc(&s.rp, n + 1));
     s.col_cap = std::max<int64_t>(8 * n, 1024);
     CHK(dalloc(&s.col, s.col_cap));
+    s.slot_entries = s.col_cap;
     std::vector<double> soa(n);
     for (int a = 0; a < 3; ++a) {
         for (int64_t i = 0; i < n; ++i) soa[i] = x[3 * i + a];
@@ -728,8 +759,9 @@ void rcp_tuning_default(rcp_tuning *t)
     t->graph_iters = 16;
     t->xcd_remap = 1;
     t->fused_tail = 0;
-    t->heavy_first = 0;
     t->variant = 1;
+    t->row_cost = 16;
+    t->item_work = 4096;
 }
 
 // Default rung table; see include/rcp.h for the reading it encodes.
@@ -847,10 +879,14 @@ int rcp_pack_init(int dim, const double *box, int64_t n, const double *d0, doubl
 int rcp_set_tuning(rcp_ctx *c, const rcp_tuning *t)
 {
     if (!c || !t || t->size != sizeof(rcp_tuning)) return fail(RCP_EINVAL, "bad tuning");
-    if (t->graph_iters < 1 || t->graph_iters > 4096 || t->variant < 0 || t->variant > 7)
+    if (t->graph_iters < 1 || t->graph_iters > 4096 || t->variant < 0 || t->variant > 7 ||
+        t->row_cost < 1 || t->row_cost > 65536 || t->item_work < 1 ||
+        (int64_t)t->item_work > (int64_t)kBlock * t->row_cost)
         return fail(RCP_EINVAL, "bad tuning values");
+    const bool relayout = t->row_cost != c->tuning.row_cost || t->item_work != c->tuning.item_work;
     c->tuning = *t;
     c->graph_valid = false;
+    if (relayout && !c->segs.empty()) CHK(build_work(c));
     return RCP_OK;
 }
 
@@ -1227,7 +1263,7 @@ int rcp_time_iterations(rcp_ctx *c, int64_t n_iters, double *iterate_us, double 
     double it_ms = 0, tl_ms = 0;
     int64_t n_done = 0;
     int rc = RCP_OK;
-    const int flags = (c->tuning.xcd_remap ? 1 : 0) | (c->tuning.heavy_first ? 4 : 0) |
+    const int flags = (c->tuning.xcd_remap ? 1 : 0) |
                       ((c->tuning.variant & 7) << 8);
     for (;;) {
         if ((rc = pull_state(c)) != RCP_OK) break;
