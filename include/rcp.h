@@ -91,8 +91,8 @@ typedef struct {
  *   variant: gradient + Adam kernel variant, bit 0 = four partner gathers in
  *     flight per thread instead of two, bit 1 = the Adam operands are loaded
  *     before the partner loop (more latency hidden, more registers), bit 2 =
- *     streamed operands (moments, reference positions, list) are loaded and
- *     stored non-temporally so gathered positions stay in the L2;
+ *     a work item's partner indices are staged in LDS in one coalesced pass
+ *     before the partner loop;
  *   row_cost, item_work: the rows of a packing (in list order) are cut into
  *     work items of item_work units, a row costing row_cost units plus one
  *     per listed partner, so each 256-thread block gets about the same
@@ -195,7 +195,8 @@ int rcp_schedule_default(int64_t n, int dim, double S, int Y, int X, int64_t n_m
                          rcp_schedule *out);
 
 /* Create a context for n_prob independent packings (1 for a plain solve;
- * several for a batched census).  Packing k has n[k] spheres with relative
+ * several for a batched census).  Packing k has n[k] spheres (1 <= n[k] <
+ * 2^27) with relative
  * diameters d0[k][0..n[k]) (host), cube edge box[k], starting scale
  * kappa0[k] and placement seed seeds[k] (SplitMix64 counter stream, see
  * rcp_pack_init).  dim must be 3.  stream is a hipStream_t (NULL: the

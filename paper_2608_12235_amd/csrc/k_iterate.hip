@@ -31,19 +31,32 @@ struct Acc {
     double gx, gy, gz, e, s, m, c;
 };
 
-__device__ __forceinline__ void pair_term(Acc &a, const P4 &qi, const P4 &qj, double kappa,
-                                          double L, double hL)
+// Minimum image of the separation of a listed pair: the nearest multiple of
+// L is removed.  Same value as min_image() whenever the imaged separation
+// is below L/2 (true of every listed pair that can be in contact), with
+// three instructions instead of two compares and selects.
+__device__ __forceinline__ double near_image(double d, double L, double iL)
 {
-    const double dx = min_image(qj.x - qi.x, L, hL);
-    const double dy = min_image(qj.y - qi.y, L, hL);
-    const double dz = min_image(qj.z - qi.z, L, hL);
+    return fma(-L, rint(d * iL), d);
+}
+
+// One listed partner's terms (Eq. energy): with q = r/d and delta = 1 - q,
+// E += delta^2 / 4 and S += delta q / 2 (each pair is seen from both ends),
+// and the gradient on x_i gains delta / (d r) (x_j - x_i).
+__device__ __forceinline__ void pair_term(Acc &a, const P4 &qi, const P4 &qj, double kappa,
+                                          double L, double iL)
+{
+    const double dx = near_image(qj.x - qi.x, L, iL);
+    const double dy = near_image(qj.y - qi.y, L, iL);
+    const double dz = near_image(qj.z - qi.z, L, iL);
     const double r2 = (dx * dx + dy * dy) + dz * dz;
     const double d = kappa * (0.5 * (qi.d + qj.d));
     if (r2 < d * d) {
         const double r = sqrt(r2);
-        const double delta = 1.0 - r / d;
+        const double q = r / d;
+        const double delta = 1.0 - q;
         a.e += 0.25 * (delta * delta);
-        a.s += 0.5 * (delta * r / d);
+        a.s += 0.5 * (delta * q);
         a.m = fmax(a.m, delta);
         a.c += 0.5;
         if (r > 0.0) {
@@ -55,13 +68,15 @@ __device__ __forceinline__ void pair_term(Acc &a, const P4 &qi, const P4 &qj, do
     }
 }
 
+// Adam on one coordinate (Kingma and Ba, bias corrected; ib1 = 1 / (1 -
+// beta1^t), ib2 = 1 / (1 - beta2^t)), then wrapped into [0, L).
 __device__ __forceinline__ double adam_coord(double th, double g, double &m, double &v,
-                                             double b1, double b2, double bc1, double bc2,
+                                             double b1, double b2, double ib1, double ib2,
                                              double eta, double eps, double L)
 {
     m = b1 * m + (1.0 - b1) * g;
     v = b2 * v + (1.0 - b2) * (g * g);
-    const double mh = m / bc1, vh = v / bc2;
+    const double mh = m * ib1, vh = v * ib2;
     double t = th - eta * mh / (sqrt(vh) + eps);
     if (t < 0.0) t += L;
     if (t >= L) t -= L;
@@ -69,7 +84,7 @@ __device__ __forceinline__ double adam_coord(double th, double g, double &m, dou
 }
 
 struct IterScalars {
-    double kappa, L, hL, b1, b2, bc1, bc2, eta, eps;
+    double kappa, L, hL, iL, b1, b2, ib1, ib2, eta, eps;
 };
 
 // Pointers of one segment with the ping-pong buffers already selected
@@ -105,19 +120,13 @@ __device__ __forceinline__ IterPtrs select_ptrs(const SegPtrs *__restrict__ P, i
 // One coordinate's Adam update from preloaded operands; returns the new
 // coordinate and adds its squared (minimum image) displacement from the
 // list reference to d2.
-template <bool kNT>
 __device__ __forceinline__ double update_coord(double xi, double g, double m, double v, double r,
                                                double *mm, double *vv, const IterScalars &c,
                                                int64_t i, double &d2)
 {
-    const double xn = adam_coord(xi, g, m, v, c.b1, c.b2, c.bc1, c.bc2, c.eta, c.eps, c.L);
-    if (kNT) {
-        __builtin_nontemporal_store(m, mm + i);
-        __builtin_nontemporal_store(v, vv + i);
-    } else {
-        mm[i] = m;
-        vv[i] = v;
-    }
+    const double xn = adam_coord(xi, g, m, v, c.b1, c.b2, c.ib1, c.ib2, c.eta, c.eps, c.L);
+    gstore(mm, i, m);
+    gstore(vv, i, v);
     const double dd = min_image(xn - r, c.L, c.hL);
     d2 += dd * dd;
     return xn;
@@ -127,50 +136,35 @@ struct Pre {
     double m0, m1, m2, v0, v1, v2, r0, r1, r2;
 };
 
-template <bool kNT>
-__device__ __forceinline__ double ld(const double *p)
-{
-    return kNT ? __builtin_nontemporal_load(p) : *p;
-}
-
-template <bool kNT>
-__device__ __forceinline__ int32_t ldi(const int32_t *p)
-{
-    return kNT ? __builtin_nontemporal_load(p) : *p;
-}
-
-// Streamed operands (read once per iteration); with kNT they are loaded
-// non-temporally so they do not push gathered positions out of the L2.
-template <bool kNT = false>
+// Streamed operands of row i (read once per iteration).
 __device__ __forceinline__ Pre preload(const IterPtrs &p, int64_t i)
 {
     Pre q;
-    q.m0 = ld<kNT>(p.m0 + i);
-    q.m1 = ld<kNT>(p.m1 + i);
-    q.m2 = ld<kNT>(p.m2 + i);
-    q.v0 = ld<kNT>(p.v0 + i);
-    q.v1 = ld<kNT>(p.v1 + i);
-    q.v2 = ld<kNT>(p.v2 + i);
-    q.r0 = ld<kNT>(p.r0 + i);
-    q.r1 = ld<kNT>(p.r1 + i);
-    q.r2 = ld<kNT>(p.r2 + i);
+    q.m0 = gload(p.m0, i);
+    q.m1 = gload(p.m1, i);
+    q.m2 = gload(p.m2, i);
+    q.v0 = gload(p.v0, i);
+    q.v1 = gload(p.v1, i);
+    q.v2 = gload(p.v2, i);
+    q.r0 = gload(p.r0, i);
+    q.r1 = gload(p.r1, i);
+    q.r2 = gload(p.r2, i);
     return q;
 }
 
 // Adam on particle i's coordinates, new position (and its D0) stored;
 // returns |x_new - x_ref|^2 (min image).
-template <bool kNT = false>
 __device__ __forceinline__ double update_particle(const IterPtrs &p, const IterScalars &c,
                                                   int64_t i, const P4 &qi, const Pre &q,
                                                   double gx, double gy, double gz)
 {
     double d2 = 0.0;
     P4 o;
-    o.x = update_coord<kNT>(qi.x, gx, q.m0, q.v0, q.r0, p.m0, p.v0, c, i, d2);
-    o.y = update_coord<kNT>(qi.y, gy, q.m1, q.v1, q.r1, p.m1, p.v1, c, i, d2);
-    o.z = update_coord<kNT>(qi.z, gz, q.m2, q.v2, q.r2, p.m2, p.v2, c, i, d2);
+    o.x = update_coord(qi.x, gx, q.m0, q.v0, q.r0, p.m0, p.v0, c, i, d2);
+    o.y = update_coord(qi.y, gy, q.m1, q.v1, q.r1, p.m1, p.v1, c, i, d2);
+    o.z = update_coord(qi.z, gz, q.m2, q.v2, q.r2, p.m2, p.v2, c, i, d2);
     o.d = qi.d;
-    p.qo[i] = o;
+    store_p4(p.qo, (int32_t)i, o);
     return d2;
 }
 
@@ -236,25 +230,42 @@ __device__ void tail_logic(SegState *s, double E, double S, double md, double md
     if (s->iter_limit > 0 && s->iters >= s->iter_limit) s->flags |= F_HOLD;
 }
 
-// Deterministic reduction of a segment's block partials by one block (fixed
-// assignment of partials to threads, fixed combining order); thread 0 then
-// runs the tail.  Every thread of the block must call it.
+// Per-block partial sums of one iteration: E_ov, S, max delta, max disp^2.
+struct alignas(32) Part4 {
+    double e, s, m, d;
+};
+
+// Deterministic reduction of a segment's block partials by one block of
+// kT threads (fixed assignment of partials to threads, fixed combining
+// order); thread 0 then runs the tail.  Every thread of the block must call
+// it.
+template <int kT>
 __device__ void reduce_and_tail(SegState *s, const double *partials)
 {
+    constexpr int kW = kT / kWave;
     double e = 0, sd = 0, m = 0, d = 0;
     const int64_t nb = s->nblocks, b0 = s->bfirst;
-    for (int64_t b = threadIdx.x; b < nb; b += kBlock) {
-        const double *p = partials + 4 * (b0 + b);
-        e += p[0];
-        sd += p[1];
-        m = fmax(m, p[2]);
-        d = fmax(d, p[3]);
+    const Part4 *P = reinterpret_cast<const Part4 *>(partials) + b0;
+    int64_t b = threadIdx.x;
+    for (; b + 3 * kT < nb; b += 4 * kT) {
+        const Part4 p0 = P[b], p1 = P[b + kT], p2 = P[b + 2 * kT], p3 = P[b + 3 * kT];
+        e += ((p0.e + p1.e) + (p2.e + p3.e));
+        sd += ((p0.s + p1.s) + (p2.s + p3.s));
+        m = fmax(m, fmax(fmax(p0.m, p1.m), fmax(p2.m, p3.m)));
+        d = fmax(d, fmax(fmax(p0.d, p1.d), fmax(p2.d, p3.d)));
+    }
+    for (; b < nb; b += kT) {
+        const Part4 p0 = P[b];
+        e += p0.e;
+        sd += p0.s;
+        m = fmax(m, p0.m);
+        d = fmax(d, p0.d);
     }
     e = wave_sum(e);
     sd = wave_sum(sd);
     m = wave_max(m);
     d = wave_max(d);
-    __shared__ double red[kWavesPerBlock][4];
+    __shared__ double red[kW][4];
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     if (lane == 0) {
         red[wv][0] = e;
@@ -265,7 +276,7 @@ __device__ void reduce_and_tail(SegState *s, const double *partials)
     __syncthreads();
     if (threadIdx.x == 0) {
         e = 0, sd = 0, m = 0, d = 0;
-        for (int k = 0; k < kWavesPerBlock; ++k) {
+        for (int k = 0; k < kW; ++k) {
             e += red[k][0];
             sd += red[k][1];
             m = fmax(m, red[k][2]);
@@ -275,31 +286,61 @@ __device__ void reduce_and_tail(SegState *s, const double *partials)
     }
 }
 
+// Partner indices of a work item, staged in LDS at the start of the item
+// (entries past the stage are read from global memory).
+constexpr int kColStage = 2048;
+
+template <bool kStage>
+__device__ __forceinline__ int32_t col_at(const int32_t *__restrict__ col,
+                                          const int32_t *__restrict__ scol, int32_t q,
+                                          int32_t e0)
+{
+    if (kStage) {
+        const int32_t k = q - e0;
+        return k < kColStage ? scol[k] : gload(col, q);
+    }
+    return gload(col, q);
+}
+
 // Entry loop of one row segment [q, qe): kU partners per step so that
-// their gathers are in flight together (kU = 2 or 4).
-template <int kU, bool kNT>
+// their gathers are in flight together (kU = 2 or 4); with kU = 4 the next
+// step's partner indices are requested before this step's terms are
+// evaluated, so their latency hides behind the arithmetic.
+template <int kU, bool kStage>
 __device__ __forceinline__ void segment_terms(Acc &a, const int32_t *__restrict__ col,
+                                              const int32_t *__restrict__ scol, int32_t e0,
                                               const P4 *__restrict__ Q, int32_t q, int32_t qe,
                                               const P4 &qi, const IterScalars &c)
 {
-    if (kU == 4) {
-        for (; q + 4 <= qe; q += 4) {
-            const int32_t j0 = ldi<kNT>(col + q), j1 = ldi<kNT>(col + q + 1),
-                          j2 = ldi<kNT>(col + q + 2), j3 = ldi<kNT>(col + q + 3);
-            const P4 q0 = Q[j0], q1 = Q[j1], q2 = Q[j2], q3 = Q[j3];
-            pair_term(a, qi, q0, c.kappa, c.L, c.hL);
-            pair_term(a, qi, q1, c.kappa, c.L, c.hL);
-            pair_term(a, qi, q2, c.kappa, c.L, c.hL);
-            pair_term(a, qi, q3, c.kappa, c.L, c.hL);
+    if (kU == 4 && q + 4 <= qe) {
+        int32_t j0 = col_at<kStage>(col, scol, q, e0), j1 = col_at<kStage>(col, scol, q + 1, e0),
+                j2 = col_at<kStage>(col, scol, q + 2, e0), j3 = col_at<kStage>(col, scol, q + 3, e0);
+        for (;;) {
+            const P4 q0 = load_p4(Q, j0), q1 = load_p4(Q, j1), q2 = load_p4(Q, j2),
+                     q3 = load_p4(Q, j3);
+            q += 4;
+            const bool more = q + 4 <= qe;
+            if (more) {
+                j0 = col_at<kStage>(col, scol, q, e0);
+                j1 = col_at<kStage>(col, scol, q + 1, e0);
+                j2 = col_at<kStage>(col, scol, q + 2, e0);
+                j3 = col_at<kStage>(col, scol, q + 3, e0);
+            }
+            pair_term(a, qi, q0, c.kappa, c.L, c.iL);
+            pair_term(a, qi, q1, c.kappa, c.L, c.iL);
+            pair_term(a, qi, q2, c.kappa, c.L, c.iL);
+            pair_term(a, qi, q3, c.kappa, c.L, c.iL);
+            if (!more) break;
         }
     }
     for (; q + 2 <= qe; q += 2) {
-        const int32_t j0 = ldi<kNT>(col + q), j1 = ldi<kNT>(col + q + 1);
-        const P4 q0 = Q[j0], q1 = Q[j1];
-        pair_term(a, qi, q0, c.kappa, c.L, c.hL);
-        pair_term(a, qi, q1, c.kappa, c.L, c.hL);
+        const int32_t j0 = col_at<kStage>(col, scol, q, e0),
+                      j1 = col_at<kStage>(col, scol, q + 1, e0);
+        const P4 q0 = load_p4(Q, j0), q1 = load_p4(Q, j1);
+        pair_term(a, qi, q0, c.kappa, c.L, c.iL);
+        pair_term(a, qi, q1, c.kappa, c.L, c.iL);
     }
-    if (q < qe) pair_term(a, qi, Q[ldi<kNT>(col + q)], c.kappa, c.L, c.hL);
+    if (q < qe) pair_term(a, qi, load_p4(Q, col_at<kStage>(col, scol, q, e0)), c.kappa, c.L, c.iL);
 }
 
 __device__ __forceinline__ void store3(double (*M)[kBlock], int k, const Acc &a)
@@ -317,7 +358,7 @@ __device__ __forceinline__ void store3(double (*M)[kBlock], int k, const Acc &a)
 // (its piece in the chunk where it starts) + (the leading piece of every
 // later chunk it covers), in chunk order, so the result does not depend on
 // timing.  Phase 2: one thread per row applies Adam (coalesced).
-template <bool kFusedTail, int kU, bool kEarly, bool kNT>
+template <bool kFusedTail, int kU, bool kEarly, bool kStage>
 __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ P,
                                                    SegState *__restrict__ S,
                                                    const WorkItem *__restrict__ W,
@@ -333,8 +374,9 @@ __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ 
     c.hL = s->hL;
     c.b1 = s->beta1;
     c.b2 = s->beta2;
-    c.bc1 = 1.0 - s->b1t * c.b1;
-    c.bc2 = 1.0 - s->b2t * c.b2;
+    c.iL = 1.0 / c.L;
+    c.ib1 = 1.0 / (1.0 - s->b1t * c.b1);
+    c.ib2 = 1.0 / (1.0 - s->b2t * c.b2);
     c.eta = s->eta_x;
     c.eps = s->eps_x;
     const IterPtrs p = select_ptrs(P, w.seg, s->cur);
@@ -344,9 +386,17 @@ __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ 
     __shared__ double G[3][kBlock];   // gradient of complete rows
     __shared__ double A[3][kBlock];   // leading piece of chunk t (row began earlier)
     __shared__ double B[3][kBlock];   // trailing piece of chunk t (row goes on)
+    __shared__ int32_t scol[kStage ? kColStage : 1];
     const int t = threadIdx.x;
     const int64_t r0 = w.begin;
     const int nrow = (int)(w.end - w.begin);
+    if (kStage) {
+        // the item's partner indices, one coalesced pass, issued together
+        // with the row pointers below
+        const int32_t f0 = gload(p.rp, r0), f1 = gload(p.rp, r0 + nrow);
+        const int32_t nst = min(f1 - f0, (int32_t)kColStage);
+        for (int k = t; k < nst; k += kBlock) scol[k] = gload(p.col, (int64_t)f0 + k);
+    }
     // phase-2 operands either first (their latency hides behind phase 1)
     // or after it (fewer registers live through phase 1)
     const int64_t io = r0 + t;
@@ -355,12 +405,12 @@ __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ 
     Pre pre = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (own) {
         if (kEarly) {
-            oq = Q[io];
-            pre = preload<kNT>(p, io);
+            oq = load_p4(Q, (int32_t)io);
+            pre = preload(p, io);
         }
-        srp[t] = p.rp[io];
+        srp[t] = gload(p.rp, io);
     }
-    if (t == 0) srp[nrow] = p.rp[r0 + nrow];
+    if (t == 0) srp[nrow] = gload(p.rp, r0 + nrow);
     __syncthreads();
 
     // energy, kappa-gradient and max-overlap terms are block totals: each
@@ -380,10 +430,10 @@ __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ 
         int r = lo;
         int32_t q = cs;
         for (;;) {
-            const P4 qi = Q[r0 + r];
+            const P4 qi = load_p4(Q, (int32_t)(r0 + r));
             const int32_t rend = srp[r + 1], qe = min(rend, ce);
             Acc a = {0, 0, 0, 0, 0, 0, 0};
-            segment_terms<kU, kNT>(a, p.col, Q, q, qe, qi, c);
+            segment_terms<kU, kStage>(a, p.col, scol, e0, Q, q, qe, qi, c);
             be += a.e;
             bs += a.s;
             bm = fmax(bm, a.m);
@@ -402,8 +452,8 @@ __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ 
 
     if (own) {
         if (!kEarly) {
-            oq = Q[io];
-            pre = preload<kNT>(p, io);
+            oq = load_p4(Q, (int32_t)io);
+            pre = preload(p, io);
         }
         const int32_t qb = srp[t], qe = srp[t + 1];
         double g[3] = {0, 0, 0};
@@ -421,7 +471,7 @@ __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ 
                 }
             }
         }
-        bd = update_particle<kNT>(p, c, io, oq, pre, g[0], g[1], g[2]);
+        bd = update_particle(p, c, io, oq, pre, g[0], g[1], g[2]);
     }
     // block reduction of the four partials
     const int lane = t & (kWave - 1);
@@ -446,11 +496,12 @@ __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ 
             m = fmax(m, red[k][2]);
             d = fmax(d, red[k][3]);
         }
-        double *o = partials + 4 * (int64_t)b;
-        o[0] = e;
-        o[1] = sd;
-        o[2] = m;
-        o[3] = d;
+        Part4 o;
+        o.e = e;
+        o.s = sd;
+        o.m = m;
+        o.d = d;
+        reinterpret_cast<Part4 *>(partials)[b] = o;
     }
     if (kFusedTail) {
         __shared__ int last;
@@ -462,18 +513,20 @@ __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ 
         __syncthreads();
         if (last) {
             __threadfence();
-            reduce_and_tail(s, partials);
+            reduce_and_tail<kBlock>(s, partials);
             if (t == 0) s->ticket = 0;
         }
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_tail(SegState *__restrict__ S,
-                                                const double *__restrict__ partials)
+constexpr int kTailBlock = 1024;
+
+__global__ __launch_bounds__(kTailBlock) void k_tail(SegState *__restrict__ S,
+                                                    const double *__restrict__ partials)
 {
     SegState *s = S + blockIdx.x;
     if (s->flags & F_IDLE) return;
-    reduce_and_tail(s, partials);
+    reduce_and_tail<kTailBlock>(s, partials);
 }
 
 template <bool kF, int kU, bool kE, bool kNT>
@@ -488,6 +541,8 @@ template <bool kF>
 static void launch_variant(const SegPtrs *P, SegState *S, const WorkItem *W, double *partials,
                            int nitems, int f, int variant, hipStream_t st)
 {
+    // bit 0: four gathers in flight; bit 1: early Adam operands; bit 2:
+    // partner indices staged in LDS
     switch (variant & 7) {
     case 0: launch_one<kF, 2, false, false>(P, S, W, partials, nitems, f, st); break;
     case 1: launch_one<kF, 4, false, false>(P, S, W, partials, nitems, f, st); break;
@@ -503,9 +558,8 @@ static void launch_variant(const SegPtrs *P, SegState *S, const WorkItem *W, dou
 void launch_iterate(const SegPtrs *P, SegState *S, const WorkItem *W, double *partials,
                     int nitems, int flags, hipStream_t st)
 {
-    // bit 0: XCD-aware order; bit 1: fused tail; bits 8-10: kernel variant (bit 8: four gathers in flight instead of two,
-    // bit 9: Adam operands loaded before the partner loop, bit 10: streamed
-    // operands loaded and stored non-temporally)
+    // bit 0: XCD-aware order; bit 1: fused tail; bits 8-10: kernel variant
+    // (see launch_variant)
     const int f = flags & 1, variant = (flags >> 8) & 7;
     if (flags & 2) launch_variant<true>(P, S, W, partials, nitems, f, variant, st);
     else launch_variant<false>(P, S, W, partials, nitems, f, variant, st);
@@ -561,7 +615,7 @@ void launch_items(const int32_t *rp, int64_t n, int seg, int row_cost, int item_
 
 void launch_tail(SegState *S, const double *partials, int nseg, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_tail, dim3(nseg), dim3(kBlock), 0, st, S, partials);
+    hipLaunchKernelGGL(k_tail, dim3(nseg), dim3(kTailBlock), 0, st, S, partials);
 }
 
 // ------------------------------------------------------- small updates
@@ -634,7 +688,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(const SegPtrs *__restrict__ P,
     const SegState *s = S + seg;
     const IterPtrs p = select_ptrs(P, seg, s->cur);
     const int32_t *orig = P[seg].orig;
-    const double L = s->L, hL = s->hL;
+    const double L = s->L, iL = 1.0 / L;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double be = 0, bs = 0, bm = 0, bn = 0;
     if (i < n) {
@@ -651,7 +705,7 @@ __global__ __launch_bounds__(kBlock) void k_eval(const SegPtrs *__restrict__ P,
         };
         const P4 qi = pos(i);
         Acc a = {0, 0, 0, 0, 0, 0, 0};
-        for (int32_t q = p.rp[i]; q < p.rp[i + 1]; ++q) pair_term(a, qi, pos(p.col[q]), kappa, L, hL);
+        for (int32_t q = p.rp[i]; q < p.rp[i + 1]; ++q) pair_term(a, qi, pos(p.col[q]), kappa, L, iL);
         be = a.e;
         bs = a.s;
         bm = a.m;

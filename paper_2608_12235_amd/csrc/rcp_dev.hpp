@@ -84,6 +84,51 @@ struct WorkItem {
     int64_t begin, end;
 };
 
+// ------------------------------------------------- global-memory access
+// Array pointers come from a table in device memory, so the compiler cannot
+// tell that they address global memory and would emit flat instructions
+// (which also wait on LDS traffic).  These views make the accesses global
+// loads / stores; sphere records are addressed with a 32-bit byte offset
+// from a uniform base (n < 2^27).
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ P4 load_p4(const P4 *base, int32_t j)
+{
+    const gptr<const char> b = (gptr<const char>)base;
+    const dbl4 v = *(gptr<const dbl4>)(b + ((uint32_t)j << 5));
+    P4 r;
+    r.x = v.x;
+    r.y = v.y;
+    r.z = v.z;
+    r.d = v.w;
+    return r;
+}
+
+__device__ __forceinline__ void store_p4(P4 *base, int32_t j, const P4 &r)
+{
+    const gptr<char> b = (gptr<char>)base;
+    dbl4 v;
+    v.x = r.x;
+    v.y = r.y;
+    v.z = r.z;
+    v.w = r.d;
+    *(gptr<dbl4>)(b + ((uint32_t)j << 5)) = v;
+}
+
+template <class T>
+__device__ __forceinline__ T gload(const T *base, int64_t i)
+{
+    return ((gptr<const T>)base)[i];
+}
+
+template <class T>
+__device__ __forceinline__ void gstore(T *base, int64_t i, T v)
+{
+    ((gptr<T>)base)[i] = v;
+}
+
 // ------------------------------------------------------------------ math
 // Minimum image of a separation of two coordinates in [0, L): one box
 // length is removed when the separation exceeds half a box; exactly at

@@ -555,7 +555,8 @@ static int shrink_seg(rcp_ctx *c, int k, double *kp_out, double *phi_out)
 static int validate_seg(int64_t n, const double *d0, double L, double kappa0)
 {
     if (n <= 0) return fail(RCP_EINVAL, "n must be positive");
-    if (n >= (int64_t)1 << 30) return fail(RCP_EINVAL, "n too large");
+    // positions are gathered with 32-bit byte offsets (32 bytes a sphere)
+    if (n >= (int64_t)1 << 27) return fail(RCP_EINVAL, "n too large (limit 2^27 - 1)");
     if (!d0) return fail(RCP_EINVAL, "null diameter list");
     if (!(L > 0) || !std::isfinite(L)) return fail(RCP_EINVAL, "box edge must be positive");
     if (!(kappa0 > 0) || !std::isfinite(kappa0)) return fail(RCP_EINVAL, "kappa0 must be positive");
