@@ -68,10 +68,14 @@ typedef struct rcp_ctx rcp_ctx;
  *     kappa; eps_x <= 0 selects 1e-12 / (kappa0 * max D0).
  *   skin_s, skin_g: a pair is listed at scale kb when
  *       r^2 < c^2,  c = kb ((1 + g)(D0_i + D0_j)/2 + 2 s D0_min),
- *     and the list stays valid while every particle moved less than
- *     s kb D0_min and kappa <= (1 + g) kb (App. A rebuilds on accumulated
- *     displacement; the skin form is ours).
- *   level_ratio_pow2: size classes are floor(log2(D0/D0_min) / p), p >= 1.
+ *     and the list stays valid while
+ *       2 max|x - x_build| + max(0, kappa - (1 + g) kb) max D0 <= 2 s kb D0_min
+ *     (App. A rebuilds on accumulated displacement; the skin form is ours:
+ *     kappa may grow by the factor 1 + g for free, and beyond that at the
+ *     expense of the displacement allowance).
+ *   level_ratio_pow2: size classes are floor(log2(D0/D0_min) / p), p >= 1;
+ *     consecutive classes share one cell grid while its cell width stays
+ *     within twice that of the first of them.
  */
 typedef struct {
     uint32_t size;

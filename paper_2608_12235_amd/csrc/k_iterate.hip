@@ -226,7 +226,12 @@ __device__ void tail_logic(SegState *s, double E, double S, double md, double md
         }
     }
     if (!(s->kappa > 0.0) || !isfinite(s->kappa)) s->flags |= F_NONFINITE;
-    if (mdisp2 > s->disp_lim2 || s->kappa > s->kappa_lim) s->flags |= F_REBUILD;
+    // list validity: an unlisted pair had r >= kb ((1 + g) d0_ij + 2 s D0_min)
+    // at the build, so it cannot touch while 2 max|dx| + max(0, kappa - (1 +
+    // g) kb) D0_max <= 2 s kb D0_min (growth beyond the g allowance is paid
+    // from the displacement skin)
+    const double excess = fmax(0.0, s->kappa - s->kappa_lim);
+    if (!(2.0 * sqrt(mdisp2) + excess * s->d0max_k <= 2.0 * s->disp_lim)) s->flags |= F_REBUILD;
     if (s->iter_limit > 0 && s->iters >= s->iter_limit) s->flags |= F_HOLD;
 }
 
@@ -619,22 +624,22 @@ void launch_tail(SegState *S, const double *partials, int nseg, hipStream_t st)
 }
 
 // ------------------------------------------------------- small updates
-__global__ void k_after_build(SegState *S, int seg, double kb, double disp_lim2,
+__global__ void k_after_build(SegState *S, int seg, double kb, double disp_lim,
                               double kappa_lim, int cur, const uint32_t *maxdeg)
 {
     SegState *s = S + seg;
     s->kb = kb;
-    s->disp_lim2 = disp_lim2;
+    s->disp_lim = disp_lim;
     s->kappa_lim = kappa_lim;
     s->cur = cur;
     s->maxdeg = (int32_t)*maxdeg;
     s->flags &= ~(F_REBUILD | F_STALE);
 }
 
-void launch_after_build(SegState *S, int seg, double kb, double disp_lim2, double kappa_lim,
+void launch_after_build(SegState *S, int seg, double kb, double disp_lim, double kappa_lim,
                         int cur, const uint32_t *maxdeg_dev, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_after_build, dim3(1), dim3(1), 0, st, S, seg, kb, disp_lim2, kappa_lim,
+    hipLaunchKernelGGL(k_after_build, dim3(1), dim3(1), 0, st, S, seg, kb, disp_lim, kappa_lim,
                        cur, maxdeg_dev);
 }
 

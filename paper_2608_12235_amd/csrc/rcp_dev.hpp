@@ -60,12 +60,13 @@ struct SegState {
     int64_t n;
     double L, hL, d0min, sumd0;
     double nvol;          // (sum D0^3)^2 / sum D0^6, the pressure normaliser
+    double d0max_k;       // max D0 (1 + 1e-9), for the list-validity test
     double beta1, beta2, eps_x, eps_k;
     int32_t pad_h;
     int32_t nblocks;      // iteration-grid blocks of this segment
     int64_t bfirst;       // first of them (index into the work table)
     // set at each list build (k_after_build)
-    double kb, disp_lim2, kappa_lim;
+    double kb, disp_lim, kappa_lim;
     int32_t maxdeg, pad0;
     // optimiser and schedule state
     double kappa, mk, vk, b1t, b2t, mu, eta_x, eta_k;

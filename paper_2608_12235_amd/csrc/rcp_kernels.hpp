@@ -91,7 +91,7 @@ void launch_iterate(const SegPtrs *P, SegState *S, const WorkItem *W, double *pa
 void launch_tail(SegState *S, const double *partials, int nseg, hipStream_t s);
 // After a list build of segment seg: kb, validity limits, current buffer,
 // longest row (read from maxdeg_dev), clear REBUILD / STALE.
-void launch_after_build(SegState *S, int seg, double kb, double disp_lim2, double kappa_lim,
+void launch_after_build(SegState *S, int seg, double kb, double disp_lim, double kappa_lim,
                         int cur, const uint32_t *maxdeg_dev, hipStream_t s);
 // Start a schedule on segment seg: copy the table, reset the position in it,
 // set the first rung's parameters from the current kappa.

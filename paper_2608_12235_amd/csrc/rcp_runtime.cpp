@@ -401,7 +401,7 @@ static int rebuild(rcp_ctx *c, int k, double kappa)
     launch_max_degree(n, s.rp, c->totals + 1, st);
 
     const double lim = sk * kappa * s.d0min * (1.0 - 1e-9);
-    launch_after_build(c->d_state, k, kappa, lim * lim, opg * kappa * (1.0 - 1e-12), ncur,
+    launch_after_build(c->d_state, k, kappa, lim, opg * kappa * (1.0 - 1e-12), ncur,
                        c->totals + 1, st);
     HIPCHK(hipEventRecord(c->e1, st));
     uint32_t md = 0;
@@ -597,18 +597,39 @@ static int seg_setup(rcp_ctx *c, int k, int64_t n, const double *d0, double L, d
     const double opg = 1.0 + c->params.skin_g, sk2 = (2.0 * c->params.skin_s) * s.d0min;
     if (!(kappa0 * (opg * s.d0max + sk2) < 0.5 * L))
         return fail(RCP_EBOX, "packing %d: listing cutoff at kappa0 is not below L/2", k);
-    // size classes
+    // size classes: class floor(log2(D0 / D0_min) / p); consecutive classes
+    // share a level (one grid) while the level's cell width, kappa ((1 + g)
+    // max D0 + 2 s D0_min), stays within twice that of its first class, so a
+    // skin that dominates the small classes' cutoffs does not leave several
+    // nearly identical, sparsely filled grids to be searched
     const int p = std::max(1, c->params.level_ratio_pow2);
-    std::vector<uint8_t> lev(n);
-    int nlev = 1;
+    std::vector<int> cls(n);
+    int ncls = 1;
     for (int64_t i = 0; i < n; ++i) {
         int e;
         std::frexp(d0[i] / s.d0min, &e);
-        int l = std::max(0, e - 1) / p;
-        if (l >= kMaxLevels) return fail(RCP_EINVAL, "more than %d size classes", kMaxLevels);
-        lev[i] = (uint8_t)l;
-        nlev = std::max(nlev, l + 1);
+        cls[i] = std::max(0, e - 1) / p;
+        if (cls[i] >= 4 * kMaxLevels) return fail(RCP_EINVAL, "size ratio too large");
+        ncls = std::max(ncls, cls[i] + 1);
     }
+    std::vector<double> cmax(ncls, 0.0);
+    for (int64_t i = 0; i < n; ++i) cmax[cls[i]] = std::max(cmax[cls[i]], d0[i]);
+    for (int q = 1; q < ncls; ++q) cmax[q] = std::max(cmax[q], cmax[q - 1]);
+    const double opg0 = 1.0 + c->params.skin_g, sk0 = (2.0 * c->params.skin_s) * s.d0min;
+    std::vector<uint8_t> level_of(ncls);
+    int nlev = 0;
+    double h0 = 0.0;
+    for (int q = 0; q < ncls; ++q) {
+        const double h = opg0 * cmax[q] + sk0;
+        if (q == 0 || h > 2.0 * h0) {
+            if (nlev >= kMaxLevels) return fail(RCP_EINVAL, "more than %d size levels", kMaxLevels);
+            ++nlev;
+            h0 = h;
+        }
+        level_of[q] = (uint8_t)(nlev - 1);
+    }
+    std::vector<uint8_t> lev(n);
+    for (int64_t i = 0; i < n; ++i) lev[i] = level_of[cls[i]];
     s.nlev = nlev;
     s.dmax_upto.assign(nlev, 0.0);
     s.lev_count.assign(nlev, 0);
@@ -673,6 +694,7 @@ static int seg_setup(rcp_ctx *c, int k, int64_t n, const double *d0, double L, d
     st.d0min = s.d0min;
     st.sumd0 = s.sumd0;
     st.nvol = s.nvol;
+    st.d0max_k = s.d0max * (1.0 + 1e-9);
     st.beta1 = c->params.beta1;
     st.beta2 = c->params.beta2;
     st.eps_x = c->params.eps_x > 0 ? c->params.eps_x : 1e-12 / (kappa0 * s.d0max);
@@ -1199,7 +1221,7 @@ static int ensure_valid_at(rcp_ctx *c, const double *x_dev, double kappa, hipStr
     CHK(pull_state(c));
     Seg &s = c->segs[0];
     SegState &h = c->h_state[0];
-    bool ok = s.built && !(h.flags & (F_REBUILD | F_STALE)) && kappa <= h.kappa_lim;
+    bool ok = s.built && !(h.flags & (F_REBUILD | F_STALE));
     if (ok) {
         const int nb = (int)std::max<int64_t>(1, (s.n + kBlock - 1) / kBlock);
         CHK(dgrow(&c->part, &c->part_cap, 4 * (int64_t)nb + 8));
@@ -1208,7 +1230,9 @@ static int ensure_valid_at(rcp_ctx *c, const double *x_dev, double kappa, hipStr
         double d2 = 0;
         HIPCHK(hipMemcpyAsync(&d2, c->out + 8, sizeof d2, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        ok = d2 <= h.disp_lim2;
+        // the test the iteration tail applies (see k_iterate.hip)
+        const double excess = std::max(0.0, kappa - h.kappa_lim);
+        ok = 2.0 * std::sqrt(d2) + excess * h.d0max_k <= 2.0 * h.disp_lim;
     }
     if (!ok) {
         HIPCHK(hipStreamSynchronize(st));
