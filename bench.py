@@ -15,12 +15,20 @@ The roofline entry is for the fused gradient + Adam kernel (k_iterate):
 algorithmic bytes per launch = 188 N + 4 nnz (read x, y, z, D0 as one
 32-byte record, m, v, x_ref and a row pointer; write the position record,
 m and v; 4 bytes per listed partner; partner gathers are assumed
-cache-served), divided by its mean duration from HIP events recorded by
-the library on its stream around each launch over 256 iterations that
-follow the timed region.  The CPU baseline is the FP64 oracle (OpenMP over
+cache-served), with nnz averaged over the timed launches, divided by the
+kernel's mean duration from HIP events the library records on its stream
+around the middle launch of every graph of the timed region (one launch in
+graph_iters, a uniform sample: event nodes cost a few microseconds each;
+--kernel-timing 2 brackets every launch, 0 none and omits the roofline
+entry).
+traffic is the HBM bytes per launch from the hardware counters committed
+under profiles/ (FETCH_SIZE x 2 + WRITE_SIZE x 1, the scales measured with
+a plain copy); it is null when the kernel sources differ from the ones the
+counters were taken on.  The CPU baseline is the FP64 oracle (OpenMP over
 rows) on the same diameters in the same box, gradient + Adam only.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -33,6 +41,32 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle-updates/s (Adam iters/s × N) and % HBM peak; batched vs plain loop"
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2608_12235_amd/csrc/k_iterate.hip", "paper_2608_12235_amd/csrc/rcp_dev.hpp",
+                  "paper_2608_12235_amd/csrc/rcp_kernels.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_iterate_traffic.json")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic():
+    """HBM bytes per k_iterate launch from the committed counter summary,
+    or None when the kernel has changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None, None
+    if t.get("source_sha256") != kernel_source_hash():
+        return None, t
+    b = 1024.0 * (t["fetch_kib_per_launch"] * t["fetch_scale"] +
+                  t["write_kib_per_launch"] * t["write_scale"])
+    return b, t
 
 
 def log(*a):
@@ -80,7 +114,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40000)
-    ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--phi0", type=float, default=0.05)
     ap.add_argument("--skin", type=float, default=16.0)
@@ -92,6 +126,9 @@ def main():
     ap.add_argument("--xcd-remap", type=int, default=None)
     ap.add_argument("--variant", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-timing", type=int, default=1, choices=(0, 1, 2),
+                    help="HIP events around 0: no launch (no roofline entry), 1: the first "
+                         "launch of every graph, 2: every launch")
     ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times "
                          "(the known-size reference for hardware byte counters) and exit")
@@ -118,6 +155,7 @@ def main():
     L = ri.box_for_phi(d0, args.phi0)
     S = float(d0.max() / d0.min())
     tun = rcp.make_tuning()
+    tun.time_kernels = args.kernel_timing
     if args.graph_iters is not None:
         tun.graph_iters = args.graph_iters
     if args.fused_tail is not None:
@@ -149,19 +187,20 @@ def main():
     iters = st["iterations"]
     wall = t1 - t0
     value = args.n * iters / wall
-    log("kernel timing (256 iterations, one launch each)")
-    it_us, tail_us, ndone = p.time_iterations(256)
-    st2 = p.stats()
-    nnz = st2["nnz"]
-    alg_bytes = 188.0 * args.n + 4.0 * nnz
-    achieved = alg_bytes / (it_us * 1e-6) / 1e9 if it_us > 0 else 0.0
     res = p.run_result()
     log("stats", st)
+    nl = max(st["kernel_launches"], 1)
+    it_us = 1e3 * st["kernel_ms"] / nl
+    tail_us = 1e3 * st["tail_kernel_ms"] / nl
+    nnz_mean = st["kernel_nnz"] / nl
+    alg_bytes = 188.0 * args.n + 4.0 * nnz_mean
+    achieved = alg_bytes / (it_us * 1e-6) / 1e9 if it_us > 0 else 0.0
+    traffic, tinfo = counter_traffic()
     phi_now = float(np.pi / 6.0 * res["kappa_before_shrink"] ** 3 * np.sum(d0 ** 3) / L ** 3)
     log("state after the timed region: kappa %.6f phi %.4f max_overlap %.3e rung %d; "
-        "k_iterate %.1f us, tail %.1f us over %d launches" %
+        "k_iterate %.1f us, tail %.1f us (mean over %d timed launches)" %
         (res["kappa_before_shrink"], phi_now, res["max_overlap"], res["rung"], it_us, tail_us,
-         ndone))
+         st["kernel_launches"]))
     out = {
         "metric": METRIC,
         "value": value,
@@ -192,8 +231,8 @@ def main():
             "rebuilds_in_timed_region": st["rebuilds"],
             "rebuild_ms": st["rebuild_ms"],
             "iterate_ms": st["iterate_ms"],
-            "nnz": nnz,
-            "max_degree": st2["max_degree"],
+            "nnz_mean_per_launch": nnz_mean,
+            "max_degree": st["max_degree"],
             "tail_us": tail_us,
             "kernel_rate": args.n / (it_us * 1e-6) if it_us > 0 else None,
         },
@@ -204,11 +243,15 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
             "bytes_per_launch": alg_bytes,
             "avg_launch_us": it_us,
+            "launches_timed": st["kernel_launches"],
+            "traffic_source": (tinfo or {}).get("summary") if traffic is not None else None,
         },
     }
+    if args.kernel_timing == 0:
+        del out["roofline"]
     p.close()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

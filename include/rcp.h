@@ -97,6 +97,11 @@ typedef struct {
  *     before the partner loop (more latency hidden, more registers), bit 2 =
  *     a work item's partner indices are staged in LDS in one coalesced pass
  *     before the partner loop;
+ *   time_kernels: 0 = no timing; 1 = HIP events around the gradient + Adam
+ *     and tail launches of the middle iteration (graph_iters / 2) of every
+ *     batch of graph_iters (a uniform sample of one launch in graph_iters;
+ *     event nodes cost a few microseconds each); 2 = around every launch
+ *     (rcp_stats.kernel_ms and friends);
  *   row_cost, item_work: the rows of a packing (in list order) are cut into
  *     work items of item_work units, a row costing row_cost units plus one
  *     per listed partner, so each 256-thread block gets about the same
@@ -111,6 +116,7 @@ typedef struct {
     int32_t variant;
     int32_t row_cost;
     int32_t item_work;
+    int32_t time_kernels;
 } rcp_tuning;
 
 /* Annealing schedule: a table of rungs run in order (App. A).  Rung r lasts
@@ -171,6 +177,14 @@ typedef struct {
     double iterate_ms;          /* time in iteration launches                   */
     double rebuild_ms;          /* time in neighbour-list builds                */
     double shrink_ms;
+    /* with rcp_tuning.time_kernels > 0: HIP events on the context's stream
+     * around the sampled launches of the gradient + Adam kernel and of the
+     * tail kernel, counted for launches in which some packing iterated */
+    double kernel_ms;           /* summed gradient + Adam kernel durations       */
+    double tail_kernel_ms;      /* summed tail kernel durations                  */
+    int64_t kernel_launches;    /* launches timed                                */
+    int64_t kernel_nnz;         /* sum over timed launches of the listed
+                                   partners (all packings) at that launch        */
 } rcp_stats;
 
 int rcp_version(void);

@@ -34,7 +34,7 @@ class Params(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("size", C.c_uint32), ("graph_iters", C.c_int32), ("xcd_remap", C.c_int32),
                 ("fused_tail", C.c_int32), ("variant", C.c_int32), ("row_cost", C.c_int32),
-                ("item_work", C.c_int32)]
+                ("item_work", C.c_int32), ("time_kernels", C.c_int32)]
 
 
 class Schedule(C.Structure):
@@ -61,7 +61,9 @@ class Stats(C.Structure):
     _fields_ = [("iterations", C.c_int64), ("particle_updates", C.c_int64),
                 ("rebuilds", C.c_int64), ("graph_launches", C.c_int64),
                 ("nnz", C.c_int64), ("max_degree", C.c_int64), ("iterate_ms", C.c_double),
-                ("rebuild_ms", C.c_double), ("shrink_ms", C.c_double)]
+                ("rebuild_ms", C.c_double), ("shrink_ms", C.c_double), ("kernel_ms", C.c_double),
+                ("tail_kernel_ms", C.c_double), ("kernel_launches", C.c_int64),
+                ("kernel_nnz", C.c_int64)]
 
 
 _lib = None

@@ -144,6 +144,7 @@ struct rcp_ctx {
     int graph_k = 0;
     bool graph_valid = false;
     hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::vector<hipEvent_t> kev;     // per-launch kernel timing events (3 per iteration)
     rcp_stats stats{};
 };
 
@@ -421,12 +422,79 @@ static int rebuild(rcp_ctx *c, int k, double kappa)
 }
 
 // ------------------------------------------------------------ iteration loop
-static void launch_one_iteration(rcp_ctx *c)
+static int ensure_kernel_events(rcp_ctx *c, int K);
+
+// Record event e on the context's stream.  While the stream is being
+// captured, a plain hipEventRecord leaves no node in the graph, so the event
+// node is added to the capture graph explicitly after the current capture
+// dependencies, and becomes the new dependency.
+static int record_event(rcp_ctx *c, hipEvent_t e)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    unsigned long long id = 0;
+    hipGraph_t cg = nullptr;
+    const hipGraphNode_t *deps = nullptr;
+    size_t nd = 0;
+    HIPCHK(hipStreamGetCaptureInfo_v2(c->stream, &cs, &id, &cg, &deps, &nd));
+    if (cs != hipStreamCaptureStatusActive) {
+        HIPCHK(hipEventRecord(e, c->stream));
+        return RCP_OK;
+    }
+    hipGraphNode_t node;
+    HIPCHK(hipGraphAddEventRecordNode(&node, cg, deps, nd, e));
+    HIPCHK(hipStreamUpdateCaptureDependencies(c->stream, &node, 1,
+                                              hipStreamSetCaptureDependencies));
+    return RCP_OK;
+}
+
+// Launches that carry timing events: the middle one of every batch of
+// graph_iters (time_kernels = 1; away from the host synchronisation that
+// precedes a batch) or all of them (time_kernels = 2).
+static bool slot_timed(const rcp_ctx *c, int64_t slot)
+{
+    const int64_t mid = std::max(1, c->tuning.graph_iters) / 2;
+    return slot >= 0 && (c->tuning.time_kernels == 2 || (c->tuning.time_kernels == 1 && slot == mid));
+}
+
+// One iteration: gradient + Adam kernel and tail kernel, bracketed by the
+// slot's three events when the slot is timed.
+static int launch_one_iteration(rcp_ctx *c, int slot)
 {
     const int flags = (c->tuning.xcd_remap ? 1 : 0) | (c->tuning.fused_tail ? 2 : 0) |
                       ((c->tuning.variant & 7) << 8);
+    const bool timed = slot_timed(c, slot) && 3 * slot + 2 < (int)c->kev.size();
+    if (timed) CHK(record_event(c, c->kev[3 * slot]));
     launch_iterate(c->d_ptrs, c->d_state, c->d_work, c->d_partials, c->nitems, flags, c->stream);
+    if (timed) CHK(record_event(c, c->kev[3 * slot + 1]));
     if (!c->tuning.fused_tail) launch_tail(c->d_state, c->d_partials, (int)c->segs.size(), c->stream);
+    if (timed) CHK(record_event(c, c->kev[3 * slot + 2]));
+    return RCP_OK;
+}
+
+// Events for timing K launches (created once, reused by every graph).
+static int ensure_kernel_events(rcp_ctx *c, int K)
+{
+    while ((int)c->kev.size() < 3 * K) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        c->kev.push_back(e);
+    }
+    return RCP_OK;
+}
+
+// Accumulate the durations of the timed launches among the first `worked`.
+static void add_kernel_times(rcp_ctx *c, int64_t worked, int64_t nnz)
+{
+    for (int64_t b = 0; b < worked && 3 * b + 2 < (int64_t)c->kev.size(); ++b) {
+        if (!slot_timed(c, b)) continue;
+        float a = 0, t = 0;
+        (void)hipEventElapsedTime(&a, c->kev[3 * b], c->kev[3 * b + 1]);
+        (void)hipEventElapsedTime(&t, c->kev[3 * b + 1], c->kev[3 * b + 2]);
+        c->stats.kernel_ms += a;
+        c->stats.tail_kernel_ms += t;
+        c->stats.kernel_launches += 1;
+        c->stats.kernel_nnz += nnz;
+    }
 }
 
 static int capture_graph(rcp_ctx *c, int K)
@@ -435,10 +503,17 @@ static int capture_graph(rcp_ctx *c, int K)
         (void)hipGraphExecDestroy(c->gexec);
         c->gexec = nullptr;
     }
+    if (c->tuning.time_kernels) CHK(ensure_kernel_events(c, K));
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
-    for (int it = 0; it < K; ++it) launch_one_iteration(c);
-    HIPCHK(hipStreamEndCapture(c->stream, &g));
+    int rc = RCP_OK;
+    for (int it = 0; it < K && rc == RCP_OK; ++it) rc = launch_one_iteration(c, it);
+    const hipError_t ee = hipStreamEndCapture(c->stream, &g);
+    if (rc != RCP_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (ee != hipSuccess) return fail(RCP_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ee));
     hipError_t e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(RCP_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
@@ -470,13 +545,14 @@ static int run_loop(rcp_ctx *c)
         if (!any) break;
         int64_t before = 0;
         for (size_t k = 0; k < c->segs.size(); ++k) before += c->h_state[k].iters;
+        if (c->tuning.time_kernels) CHK(ensure_kernel_events(c, K));
         HIPCHK(hipEventRecord(c->e0, c->stream));
         if (K > 1) {
             if (!c->graph_valid || c->graph_k != K) CHK(capture_graph(c, K));
             HIPCHK(hipGraphLaunch(c->gexec, c->stream));
             c->stats.graph_launches += 1;
         } else {
-            launch_one_iteration(c);
+            CHK(launch_one_iteration(c, 0));
         }
         HIPCHK(hipEventRecord(c->e1, c->stream));
         std::vector<int64_t> prev(c->segs.size());
@@ -485,11 +561,17 @@ static int run_loop(rcp_ctx *c)
         float ms = 0;
         HIPCHK(hipEventElapsedTime(&ms, c->e0, c->e1));
         c->stats.iterate_ms += ms;
+        int64_t worked = 0, nnz = 0;
         for (size_t k = 0; k < c->segs.size(); ++k) {
             const int64_t d = c->h_state[k].iters - prev[k];
             c->stats.iterations += d;
             c->stats.particle_updates += d * c->segs[k].n;
+            worked = std::max(worked, d);
+            if (d > 0) nnz += c->segs[k].nnz;
         }
+        // a packing runs consecutive launches until it goes idle, so the
+        // first `worked` launches of this batch did work
+        if (c->tuning.time_kernels) add_kernel_times(c, std::min<int64_t>(worked, K), nnz);
         (void)before;
     }
     return RCP_OK;
@@ -747,6 +829,8 @@ static void destroy_ctx(rcp_ctx *c)
     dfree(c->xtmp);
     if (c->h_state) (void)hipHostFree(c->h_state);
     if (c->h_out) (void)hipHostFree(c->h_out);
+    for (auto &e : c->kev) (void)hipEventDestroy(e);
+    c->kev.clear();
     if (c->e0) (void)hipEventDestroy(c->e0);
     if (c->e1) (void)hipEventDestroy(c->e1);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -782,9 +866,10 @@ void rcp_tuning_default(rcp_tuning *t)
     t->graph_iters = 16;
     t->xcd_remap = 1;
     t->fused_tail = 0;
-    t->variant = 1;
+    t->variant = 0;
     t->row_cost = 16;
     t->item_work = 4096;
+    t->time_kernels = 0;
 }
 
 // Default rung table; see include/rcp.h for the reading it encodes.
@@ -906,6 +991,7 @@ int rcp_set_tuning(rcp_ctx *c, const rcp_tuning *t)
         t->row_cost < 1 || t->row_cost > 65536 || t->item_work < 1 ||
         (int64_t)t->item_work > (int64_t)kBlock * t->row_cost)
         return fail(RCP_EINVAL, "bad tuning values");
+    if (t->time_kernels < 0 || t->time_kernels > 2) return fail(RCP_EINVAL, "bad tuning values");
     const bool relayout = t->row_cost != c->tuning.row_cost || t->item_work != c->tuning.item_work;
     c->tuning = *t;
     c->graph_valid = false;

@@ -36,10 +36,10 @@ def test_every_declared_symbol_is_exported(L):
 def test_struct_sizes_match_header_layout(L):
     # sizes follow from the field lists in include/rcp.h (x86-64 alignment)
     assert C.sizeof(L.Params) == 8 + 6 * 8 + 8
-    assert C.sizeof(L.Tuning) == 7 * 4
+    assert C.sizeof(L.Tuning) == 8 * 4
     assert C.sizeof(L.Schedule) == 16 + 8 + 5 * 16 * 8
     assert C.sizeof(L.Result) == 5 * 8 + 2 * 8 + 2 * 4
-    assert C.sizeof(L.Stats) == 6 * 8 + 3 * 8
+    assert C.sizeof(L.Stats) == 6 * 8 + 3 * 8 + 2 * 8 + 2 * 8
 
 
 def test_version_and_defaults(L):
