@@ -298,12 +298,15 @@ int rcp_census_run(rcp_ctx *ctx, const rcp_schedule *sched, int per_packing,
  * fraction at kappa'. */
 int rcp_shrink(rcp_ctx *ctx, int k, double *kappa_shrunk, double *phi);
 
-/* Raw device entry points for torch.autograd.Function (packing 0).
- * x_dev: (n, 3) row-major positions in user order on the device; the list
- * is rebuilt at (x_dev, kappa) if it is not valid there (this synchronises
- * the stream).  rcp_energy_dev writes E = E_overlap + E_growth to E_dev[0]
- * and max overlap to E_dev[1].  rcp_adjoint_dev writes dE/dx (n, 3, user
- * order) to gx_dev and dE/dkappa to gk_dev[0]. */
+/* Raw device entry points for torch.autograd.Function (packing 0; App. A,
+ * Eq. (energy) and its gradient).  x_dev: (n, 3) row-major positions in user
+ * order on the device, borrowed until the work on `stream` completes.
+ * stream is the caller's hipStream_t and NULL means the null stream (not
+ * the context's own): reads of x_dev and writes of the outputs are ordered
+ * on it.  The list is rebuilt at (x_dev, kappa) if it is not valid there
+ * (this synchronises the stream).  rcp_energy_dev writes E = E_overlap +
+ * E_growth to E_dev[0] and max overlap to E_dev[1].  rcp_adjoint_dev writes
+ * dE/dx (n, 3, user order) to gx_dev and dE/dkappa to gk_dev[0]. */
 int rcp_energy_dev(rcp_ctx *ctx, const double *x_dev, double kappa, double mu,
                    double *E_dev, void *stream);
 int rcp_adjoint_dev(rcp_ctx *ctx, const double *x_dev, double kappa, double mu,

@@ -11,5 +11,12 @@ from ._lib import lib, RcpError, LIB_PATH
 from .api import (Packing, make_params, make_tuning, default_schedule,
                   absolute_schedule, schedule_from_rungs)
 
+
+def overlap_energy(x, kappa, packing, mu=0.0):
+    """See autograd.overlap_energy (imports torch on first use)."""
+    from .autograd import overlap_energy as f
+    return f(x, kappa, packing, mu)
+
+
 __all__ = ["lib", "RcpError", "LIB_PATH", "Packing", "make_params", "make_tuning",
-           "default_schedule", "absolute_schedule", "schedule_from_rungs"]
+           "default_schedule", "absolute_schedule", "schedule_from_rungs", "overlap_energy"]

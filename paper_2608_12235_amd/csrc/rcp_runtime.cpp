@@ -1341,7 +1341,7 @@ int rcp_energy_dev(rcp_ctx *c, const double *x_dev, double kappa, double mu, dou
                    void *stream)
 {
     if (!c || !x_dev || !E_dev) return fail(RCP_EINVAL, "null argument");
-    hipStream_t st = stream ? (hipStream_t)stream : c->stream;
+    hipStream_t st = (hipStream_t)stream;   // NULL: the null stream
     CHK(ensure_valid_at(c, x_dev, kappa, st));
     CHK(eval_current(c, 0, x_dev, kappa, mu, nullptr, st));
     hipLaunchKernelGGL(k_energy_out, dim3(1), dim3(1), 0, st, c->out, E_dev);
@@ -1353,7 +1353,7 @@ int rcp_adjoint_dev(rcp_ctx *c, const double *x_dev, double kappa, double mu, do
                     double *gk_dev, void *stream)
 {
     if (!c || !x_dev || !gx_dev || !gk_dev) return fail(RCP_EINVAL, "null argument");
-    hipStream_t st = stream ? (hipStream_t)stream : c->stream;
+    hipStream_t st = (hipStream_t)stream;   // NULL: the null stream
     CHK(ensure_valid_at(c, x_dev, kappa, st));
     CHK(eval_current(c, 0, x_dev, kappa, mu, gx_dev, st));
     hipLaunchKernelGGL(k_gk_out, dim3(1), dim3(1), 0, st, c->out, gk_dev);

@@ -83,6 +83,10 @@ PAIR_CASES = [
     ("powerlaw", 300.0, 0.02, 1.0, 0.3, 0.02),
     ("weibull", 300.0, 0.5, 1.1, 0.1, 0.002),
     ("lognormal", 8.0, 0.6, 1.0, 2.0, 0.0),
+    # skins that dominate the small classes' cutoffs: classes share grids
+    ("lognormal", 300.0, 0.05, 1.0, 6.0, 0.02),
+    ("powerlaw", 300.0, 0.02, 1.0, 8.0, 0.02),
+    ("lognormal", 1000.0, 0.02, 1.3, 12.0, 0.02),
 ]
 
 
@@ -236,6 +240,43 @@ def test_adam_steps_match_oracle(rcp, orc, steps, fused, graph, variant):
     d = np.minimum(d, w.L - d)
     assert d.max() <= 1e-9 * ex * steps + 4e-16 * w.L, d.max()
     assert kg == pytest.approx(st.kappa[0], rel=1e-12)
+
+
+@pytest.mark.parametrize("row_cost,item_work", [(1, 1), (1, 256), (4, 64), (64, 8192)])
+def test_work_item_cuts_agree(rcp, orc, row_cost, item_work):
+    # the cut of the rows into work items changes only the summation order
+    # of the gradient pieces
+    w, x, k = _dense_c1_state(orc, iters=1500)
+    mu, ex, ek, steps = 2e-3, 2e-3, 2e-4, 10
+    P = orc.default_params(w.d0, s=0.3, g=0.02)
+    p = rcp.Packing(w.d0, w.L, k, 0, init="none",
+                    params=rcp.make_params(skin_s=0.3, skin_g=0.02, eps_x=P.eps_x),
+                    tuning=rcp.make_tuning(row_cost=row_cost, item_work=item_work))
+    p.set_state(x, k)
+    p.adam_step(mu, ex, ek, steps)
+    xg, kg = p.get_state()
+    st = orc.RunState(x, w.d0, w.L, k)
+    orc.run(st, P, orc.oracle.absolute_schedule(mu, ex, ek, steps))
+    d = np.abs(xg - st.x)
+    d = np.minimum(d, w.L - d)
+    assert d.max() <= 1e-9 * ex * steps + 4e-16 * w.L, d.max()
+    assert kg == pytest.approx(st.kappa[0], rel=1e-12)
+
+
+def test_kernel_timing_changes_nothing(rcp, orc):
+    # per-launch event nodes in the graphs leave the trajectory bit-identical
+    w = ri.c1_lognormal(2)
+    out = []
+    for tk in (0, 1, 2):
+        p = rcp.Packing(w.d0, w.L, 1.0, w.seed, init="rsa", params=rcp.make_params(skin_s=0.3),
+                        tuning=rcp.make_tuning(time_kernels=tk))
+        out.append(p.inflate_run()[0])
+        st = p.stats()
+        if tk:
+            assert st["kernel_launches"] > 0 and st["kernel_ms"] > 0
+        p.close()
+    for o in out[1:]:
+        assert o["phi"] == out[0]["phi"] and o["iterations"] == out[0]["iterations"]
 
 
 def test_schedule_rungs_match_oracle(rcp, orc):
