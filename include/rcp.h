@@ -233,7 +233,17 @@ int rcp_pack_init(int dim, const double *box, int64_t n, const double *d0,
                   double kappa0, uint64_t seed, int init_mode,
                   const rcp_params *params, void *stream, rcp_ctx **out);
 
+/* Replace the launch tuning (see rcp_tuning); RCP_EINVAL for values out of
+ * range.  A captured graph is re-captured at the next iteration. */
 int rcp_set_tuning(rcp_ctx *ctx, const rcp_tuning *t);
+
+/* Replace the listing skin (skin_s, skin_g of rcp_params) of every packing
+ * of the context, e.g. by an autotuner between iterations of a run; every
+ * built list is rebuilt before the next iteration.  The trajectory does not
+ * depend on the skin beyond summation order.  RCP_EINVAL for a negative or
+ * non-finite value, RCP_EBOX if a packing's largest cutoff at its current
+ * kappa would not be below L/2 (nothing is changed then). */
+int rcp_set_skin(rcp_ctx *ctx, double skin_s, double skin_g);
 
 /* Replace positions (row-major (n, 3), user order, wrapped into [0, L)) and
  * kappa of packing k; host or device pointer.  Resets the Adam moments and
@@ -272,7 +282,10 @@ int rcp_adam_step(rcp_ctx *ctx, double mu, double eta_x, double eta_k,
  * per_packing == 0) until every packing has stopped, hit its cap, or
  * max_iters iterations were taken (0: no limit); then shrink each packing
  * to contact.  results has n_prob entries.  Returns 0, or RCP_ENOTCONV /
- * RCP_ENONFINITE if any packing ended that way. */
+ * RCP_ENONFINITE / RCP_EBOX if any packing ended that way (its result's
+ * status says which).  In a context with several packings, a packing whose
+ * listing cutoff reaches L/2 is stopped with status RCP_EBOX and the others
+ * run on; with one packing the call fails at that point. */
 int rcp_inflate_run(rcp_ctx *ctx, const rcp_schedule *sched, int per_packing,
                     int64_t max_iters, rcp_result *results);
 

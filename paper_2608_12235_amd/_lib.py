@@ -87,6 +87,7 @@ SIGNATURES = {
     "rcp_pack_init": (C.c_int, [C.c_int, dp, C.c_int64, dp, C.c_double, C.c_uint64, C.c_int,
                                 C.POINTER(Params), vp, C.POINTER(vp)]),
     "rcp_set_tuning": (C.c_int, [vp, C.POINTER(Tuning)]),
+    "rcp_set_skin": (C.c_int, [vp, C.c_double, C.c_double]),
     "rcp_set_state": (C.c_int, [vp, C.c_int, vp, C.c_double, C.c_int]),
     "rcp_get_state": (C.c_int, [vp, C.c_int, dp, dp, dp]),
     "rcp_neighbor_build": (C.c_int, [vp, C.c_int, i64p]),

@@ -85,6 +85,7 @@ class Packing:
         check(lib().rcp_census_init(3, P, ns, ptrs, box, kap, sd, _INIT[init],
                                     C.byref(self.params), stream, C.byref(h)))
         self._h = h
+        self.tuning = make_tuning()
         if tuning is not None:
             self.set_tuning(tuning)
 
@@ -110,6 +111,12 @@ class Packing:
 
     def set_tuning(self, t):
         check(lib().rcp_set_tuning(self._h, C.byref(t)))
+        self.tuning = t
+
+    def set_skin(self, skin_s, skin_g):
+        check(lib().rcp_set_skin(self._h, float(skin_s), float(skin_g)))
+        self.params.skin_s = float(skin_s)
+        self.params.skin_g = float(skin_g)
 
     def set_state(self, x, kappa, k=0):
         x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
@@ -151,7 +158,7 @@ class Packing:
     def adam_step(self, mu, eta_x, eta_k, n_steps):
         check(lib().rcp_adam_step(self._h, float(mu), float(eta_x), float(eta_k), int(n_steps)))
 
-    def inflate_run(self, schedule=None, max_iters=0, allow_notconv=True):
+    def inflate_run(self, schedule=None, max_iters=0, allow_notconv=True, allow_fail=False):
         P = self.n_packings
         if schedule is None:
             schedule = self.default_schedules()
@@ -163,7 +170,7 @@ class Packing:
             sp = C.byref(schedule)
         res = (Result * P)()
         rc = lib().rcp_inflate_run(self._h, sp, 1 if per else 0, int(max_iters), res)
-        if rc != 0 and not (allow_notconv and rc == -5):
+        if rc != 0 and not (allow_notconv and rc == -5) and not (allow_fail and rc in (-2, -5, -6)):
             check(rc)
         return [_result_dict(r) for r in res]
 

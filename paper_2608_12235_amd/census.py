@@ -1,0 +1,92 @@
+"""Batched census: many independent packings in one context.
+
+Every iteration of a census is one launch of the gradient + Adam kernel over
+the work items of all packings that are still running, and one tail launch
+with a block per packing (each packing keeps its own kappa, Adam state,
+schedule and flags), captured in HIP graphs; lists are rebuilt per packing
+when its validity test asks for it.  A packing's trajectory depends only on
+its own data, so the results equal those of plain solves bit for bit.
+"""
+import time
+
+import numpy as np
+
+from .api import Packing, make_params
+
+
+def _sync():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.synchronize()
+    except ImportError:
+        pass
+
+
+def run_batched(workloads, params=None, tuning=None, schedules=None, max_iters=0):
+    """One context for all workloads (objects with d0, L, seed); returns
+    (results, seconds of the inflation run, stats)."""
+    params = params if params is not None else make_params()
+    p = Packing([w.d0 for w in workloads], [w.L for w in workloads], 1.0,
+                [w.seed for w in workloads], init="rsa", params=params, tuning=tuning)
+    try:
+        _sync()
+        t0 = time.perf_counter()
+        res = p.inflate_run(schedules, max_iters=max_iters, allow_fail=True)
+        _sync()
+        dt = time.perf_counter() - t0
+        return res, dt, p.stats()
+    finally:
+        p.close()
+
+
+def run_loop(workloads, params=None, tuning=None, schedules=None, max_iters=0, log=None):
+    """The same workloads as one plain solve each; returns (results, summed
+    seconds of the inflation runs)."""
+    params = params if params is not None else make_params()
+    out, total = [], 0.0
+    for k, w in enumerate(workloads):
+        p = Packing(w.d0, w.L, 1.0, w.seed, init="rsa", params=params, tuning=tuning)
+        try:
+            _sync()
+            t0 = time.perf_counter()
+            r = p.inflate_run(None if schedules is None else schedules[k], max_iters=max_iters,
+                              allow_fail=True)[0]
+            _sync()
+            total += time.perf_counter() - t0
+        finally:
+            p.close()
+        out.append(r)
+        if log:
+            log("plain solve %d/%d: N=%d phi=%.4f its=%d" % (k + 1, len(workloads), w.n,
+                                                              r["phi"], r["iterations"]))
+    return out, total
+
+
+def particle_updates(results, workloads):
+    return float(sum(r["iterations"] * w.n for r, w in zip(results, workloads)))
+
+
+def run_autotuned(workloads, params=None, warmup=1000, trial_iters=400, log=None):
+    """One context for all workloads: warm-up iterations, autotuner trials
+    (which continue the run), then the rest of the run.  Returns (results,
+    seconds of the whole run including the trials, chosen settings)."""
+    from . import autotune
+    params = params if params is not None else make_params()
+    p = Packing([w.d0 for w in workloads], [w.L for w in workloads], 1.0,
+                [w.seed for w in workloads], init="rsa", params=params)
+    try:
+        _sync()
+        t0 = time.perf_counter()
+        p.run_start(None)
+        if warmup:
+            p.run_continue(warmup)
+        best, trials = autotune.tune(p, trial_iters=trial_iters, log=log)
+        p.run_continue(0)
+        _sync()
+        res = [p.run_result(k) for k in range(p.n_packings)]
+        _sync()
+        dt = time.perf_counter() - t0
+        return res, dt, {"best": best, "trials": trials}
+    finally:
+        p.close()

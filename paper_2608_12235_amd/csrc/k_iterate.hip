@@ -659,7 +659,7 @@ __global__ void k_sched_start(SegState *S, int seg, SchedDev q, int reset_adam,
         s->mk = 0.0;
         s->vk = 0.0;
     }
-    s->flags &= ~(F_STOP | F_CAP | F_HOLD | F_NONFINITE);
+    s->flags &= ~(F_STOP | F_CAP | F_HOLD | F_NONFINITE | F_ABORT);
     rung_start(s, 0);
 }
 

@@ -26,7 +26,8 @@ enum : int32_t {
     F_NONFINITE = 8,   // NaN / Inf met
     F_HOLD = 16,       // iteration limit of the current call reached
     F_STALE = 32,      // no valid list (host has to build one first)
-    F_IDLE = F_STOP | F_CAP | F_REBUILD | F_NONFINITE | F_HOLD | F_STALE,
+    F_ABORT = 64,      // the host gave up on this packing (census: others go on)
+    F_IDLE = F_STOP | F_CAP | F_REBUILD | F_NONFINITE | F_HOLD | F_STALE | F_ABORT,
 };
 
 struct SchedDev {

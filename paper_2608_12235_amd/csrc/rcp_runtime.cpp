@@ -109,6 +109,7 @@ struct Seg {
     int64_t first_item = 0;      // its first slot in the work table
     int64_t slot_entries = 0;    // list length the slots are sized for
     int64_t rebuilds = 0;
+    int err = 0;                 // error that stopped this packing (census)
     bool built = false;
 };
 
@@ -524,7 +525,7 @@ static int capture_graph(rcp_ctx *c, int K)
 
 static bool seg_done(int32_t f)
 {
-    return (f & (F_STOP | F_CAP | F_NONFINITE | F_HOLD)) != 0;
+    return (f & (F_STOP | F_CAP | F_NONFINITE | F_HOLD | F_ABORT)) != 0;
 }
 
 // Iterate every packing until each is done (stop, cap, non-finite, limit).
@@ -538,7 +539,15 @@ static int run_loop(rcp_ctx *c)
             const int32_t f = c->h_state[k].flags;
             if (seg_done(f)) continue;
             if (f & (F_REBUILD | F_STALE)) {
-                CHK(rebuild(c, (int)k, c->h_state[k].kappa));
+                const int rc = rebuild(c, (int)k, c->h_state[k].kappa);
+                if (rc == RCP_EBOX && c->segs.size() > 1) {
+                    // one packing outgrew its box: stop it, let the others run
+                    c->segs[k].err = rc;
+                    launch_set_flags(c->d_state, (int)k, 0, F_ABORT, c->stream);
+                    c->h_state[k].flags |= F_ABORT;
+                    continue;
+                }
+                CHK(rc);
             }
             any = true;
         }
@@ -984,6 +993,27 @@ int rcp_pack_init(int dim, const double *box, int64_t n, const double *d0, doubl
     return rcp_census_init(dim, 1, &n, dl, &L, &kappa0, &seed, init_mode, params, stream, out);
 }
 
+int rcp_set_skin(rcp_ctx *c, double skin_s, double skin_g)
+{
+    if (!c) return fail(RCP_EINVAL, "null context");
+    if (!(skin_s >= 0) || !(skin_g >= 0) || !std::isfinite(skin_s) || !std::isfinite(skin_g))
+        return fail(RCP_EINVAL, "bad skin");
+    CHK(pull_state(c));
+    for (size_t k = 0; k < c->segs.size(); ++k) {
+        const Seg &s = c->segs[k];
+        const double kap = c->h_state[k].kappa;
+        if (!(kap * ((1.0 + skin_g) * s.d0max + (2.0 * skin_s) * s.d0min) < 0.5 * s.L))
+            return fail(RCP_EBOX, "packing %d: listing cutoff with this skin is not below L/2",
+                        (int)k);
+    }
+    c->params.skin_s = skin_s;
+    c->params.skin_g = skin_g;
+    for (size_t k = 0; k < c->segs.size(); ++k)
+        if (c->segs[k].built) launch_set_flags(c->d_state, (int)k, 0, F_REBUILD, c->stream);
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return pull_state(c);
+}
+
 int rcp_set_tuning(rcp_ctx *c, const rcp_tuning *t)
 {
     if (!c || !t || t->size != sizeof(rcp_tuning)) return fail(RCP_EINVAL, "bad tuning");
@@ -1161,6 +1191,7 @@ static int start_schedule(rcp_ctx *c, const rcp_schedule *sched, int per_packing
         SchedDev q;
         CHK(to_sched(per_packing ? sched + k : sched, q));
         CHK(reset_moments(c, (int)k));
+        c->segs[k].err = 0;
         launch_sched_start(c->d_state, (int)k, q, 1, max_iters, c->stream);
     }
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -1203,6 +1234,11 @@ static int seg_result(rcp_ctx *c, int k, rcp_result &r)
     r.energy = st.E_ov;
     r.iterations = st.iters;
     r.rung = st.rung;
+    if (c->segs[k].err) {
+        r.status = c->segs[k].err;
+        r.rebuilds = c->segs[k].rebuilds;
+        return RCP_OK;
+    }
     if (st.flags & F_NONFINITE) {
         r.status = RCP_ENONFINITE;
         r.rebuilds = c->segs[k].rebuilds;
@@ -1276,11 +1312,14 @@ int rcp_inflate_run(rcp_ctx *c, const rcp_schedule *sched, int per_packing, int6
     for (size_t k = 0; k < c->segs.size(); ++k) {
         CHK(seg_result(c, (int)k, results[k]));
         const int st = results[k].status;
-        if (st == RCP_ENONFINITE) rc = RCP_ENONFINITE;
+        if (st == RCP_EBOX) rc = RCP_EBOX;
+        else if (st == RCP_ENONFINITE && rc != RCP_EBOX) rc = RCP_ENONFINITE;
         else if (st == RCP_ENOTCONV && rc == RCP_OK) rc = RCP_ENOTCONV;
     }
     if (rc == RCP_ENOTCONV) fail(RCP_ENOTCONV, "iteration cap reached before the stop test held");
     if (rc == RCP_ENONFINITE) fail(RCP_ENONFINITE, "non-finite energy or gradient");
+    if (rc == RCP_EBOX)
+        fail(RCP_EBOX, "a packing's listing cutoff reached L/2 (its result status is RCP_EBOX)");
     return rc;
 }
 

@@ -81,32 +81,42 @@ def small_polydisperse(n, S, phi, seed, family="lognormal", uniform=True):
                family, {"S": S}, uniform=uniform)
 
 
-def census_draw(n_prob=64, seed=2026, n_lo=1_000, n_hi=200_000, phi0=0.05):
+def census_draw(n_prob=64, seed=2026, n_lo=1_000, n_hi=200_000, phi0=0.05, span_max=0.4):
     """Seeded parameter draw over the three families.
 
     Packing k uses family k mod 3: lognormal alpha ~ U[0.2, 1.5]; power law
     exponent p ~ U[-4, -2]; Weibull modulus k ~ logU[0.5, 3].  S ~ logU[2,
     100] and N ~ logU[n_lo, n_hi]; each packing gets its own placement seed.
+    As in the paper's studies, where N is chosen so that the largest sphere
+    spans a fixed fraction of the box (Sec. 3), a draw whose largest sphere
+    would span more than span_max of the box edge at phi = 0.8 is drawn
+    again (attempt a uses counters k * 8 + j + a * 2^20).
     """
     out = []
-    u = lambda k, j: float((splitmix64(seed, k * 8 + j) >> np.uint64(11))
-                           .astype(np.float64) * 2.0 ** -53)
     for k in range(n_prob):
-        S = float(np.exp(np.log(2.0) + u(k, 0) * (np.log(100.0) - np.log(2.0))))
-        n = int(np.exp(np.log(n_lo) + u(k, 1) * (np.log(n_hi) - np.log(n_lo))))
-        fam = k % 3
-        if fam == 0:
-            a = 0.2 + 1.3 * u(k, 2)
-            d0 = lognormal_quantiles(n, a, S)
-            name, params = "lognormal", {"alpha": a, "S": S}
-        elif fam == 1:
-            p = -4.0 + 2.0 * u(k, 2)
-            d0 = powerlaw_quantiles(n, p, S)
-            name, params = "powerlaw", {"p": p, "S": S}
+        for a in range(1000):
+            u = lambda j: float((splitmix64(seed, k * 8 + j + a * (1 << 20)) >> np.uint64(11))
+                                .astype(np.float64) * 2.0 ** -53)
+            S = float(np.exp(np.log(2.0) + u(0) * (np.log(100.0) - np.log(2.0))))
+            n = int(np.exp(np.log(n_lo) + u(1) * (np.log(n_hi) - np.log(n_lo))))
+            fam = k % 3
+            if fam == 0:
+                al = 0.2 + 1.3 * u(2)
+                d0 = lognormal_quantiles(n, al, S)
+                name, params = "lognormal", {"alpha": al, "S": S}
+            elif fam == 1:
+                p = -4.0 + 2.0 * u(2)
+                d0 = powerlaw_quantiles(n, p, S)
+                name, params = "powerlaw", {"p": p, "S": S}
+            else:
+                kk = float(np.exp(np.log(0.5) + u(2) * (np.log(3.0) - np.log(0.5))))
+                d0 = weibull_quantiles(n, kk, S)
+                name, params = "weibull", {"k": kk, "S": S}
+            L = box_for_phi(d0, phi0)
+            if (0.8 / phi0) ** (1.0 / 3.0) * float(d0.max()) <= span_max * L:
+                break
         else:
-            kk = float(np.exp(np.log(0.5) + u(k, 2) * (np.log(3.0) - np.log(0.5))))
-            d0 = weibull_quantiles(n, kk, S)
-            name, params = "weibull", {"k": kk, "S": S}
+            raise RuntimeError("census draw %d: no admissible parameters" % k)
         wseed = int(splitmix64(seed, 10_000 + k) & np.uint64(0xFFFFFFFF))
         out.append(_wl("%s #%d N=%d S=%.3g" % (name, k, n, S), d0, phi0, wseed,
                        name, params, uniform=False))
