@@ -625,22 +625,29 @@ void launch_tail(SegState *S, const double *partials, int nseg, hipStream_t st)
 
 // ------------------------------------------------------- small updates
 __global__ void k_after_build(SegState *S, int seg, double kb, double disp_lim,
-                              double kappa_lim, int cur, const uint32_t *maxdeg)
+                              double kappa_lim, int cur)
 {
     SegState *s = S + seg;
     s->kb = kb;
     s->disp_lim = disp_lim;
     s->kappa_lim = kappa_lim;
     s->cur = cur;
-    s->maxdeg = (int32_t)*maxdeg;
     s->flags &= ~(F_REBUILD | F_STALE);
 }
 
 void launch_after_build(SegState *S, int seg, double kb, double disp_lim, double kappa_lim,
-                        int cur, const uint32_t *maxdeg_dev, hipStream_t st)
+                        int cur, hipStream_t st)
 {
     hipLaunchKernelGGL(k_after_build, dim3(1), dim3(1), 0, st, S, seg, kb, disp_lim, kappa_lim,
-                       cur, maxdeg_dev);
+                       cur);
+}
+
+// Host-side pointer table entry written in stream order (no host staging).
+__global__ void k_put_ptrs(SegPtrs *P, int seg, SegPtrs v) { P[seg] = v; }
+
+void launch_put_ptrs(SegPtrs *P, int seg, const SegPtrs &v, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_put_ptrs, dim3(1), dim3(1), 0, st, P, seg, v);
 }
 
 __global__ void k_sched_start(SegState *S, int seg, SchedDev q, int reset_adam,

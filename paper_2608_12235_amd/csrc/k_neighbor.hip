@@ -137,6 +137,7 @@ __global__ __launch_bounds__(kBlock) void k_hash_starts(BuildArgs a)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= a.n) return;
+    if (a.lv[a.lev[i]].dbase >= 0) return;
     const uint64_t key = a.skey[i];
     if (i > 0 && a.skey[i - 1] == key) return;
     uint64_t slot = hash_slot(key, a.hmask);
@@ -167,6 +168,7 @@ __global__ __launch_bounds__(kBlock) void k_hash_counts(BuildArgs a)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= a.n) return;
+    if (a.lv[a.lev[i]].dbase >= 0) return;
     const uint64_t key = a.skey[i];
     if (i + 1 < a.n && a.skey[i + 1] == key) return;
     uint64_t slot = hash_slot(key, a.hmask);
@@ -174,14 +176,51 @@ __global__ __launch_bounds__(kBlock) void k_hash_counts(BuildArgs a)
     a.hash[slot].count = (int32_t)(i - a.hash[slot].start + 1);
 }
 
-void launch_hash_build(const BuildArgs &a, int64_t cap, hipStream_t s)
+// Dense cell index of sorted particle i (its level must be dense).
+__device__ __forceinline__ int64_t dense_index(const BuildArgs &a, int64_t i)
+{
+    const LevelGrid g = a.lv[a.lev[i]];
+    const P4 q = a.pos[i];
+    const int64_t cx = cell_coord(q.x, g.inv_w, g.nc), cy = cell_coord(q.y, g.inv_w, g.nc),
+                  cz = cell_coord(q.z, g.inv_w, g.nc);
+    return g.dbase + (cx * g.nc + cy) * g.nc + cz;
+}
+
+// A cell's sorted particles are contiguous (same key): the first one writes
+// the start (k_dense_starts), then the last one the count (k_dense_counts).
+__global__ __launch_bounds__(kBlock) void k_dense_starts(BuildArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.n) return;
+    if (a.lv[a.lev[i]].dbase < 0) return;
+    if (i > 0 && a.skey[i - 1] == a.skey[i]) return;
+    a.dense[dense_index(a, i)].x = (int32_t)i;
+}
+
+__global__ __launch_bounds__(kBlock) void k_dense_counts(BuildArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.n) return;
+    if (a.lv[a.lev[i]].dbase < 0) return;
+    if (i + 1 < a.n && a.skey[i + 1] == a.skey[i]) return;
+    int2 *cell = a.dense + dense_index(a, i);
+    cell->y = (int32_t)(i - cell->x + 1);
+}
+
+void launch_hash_build(const BuildArgs &a, int64_t cap, int64_t ndense, hipStream_t s)
 {
     hipLaunchKernelGGL(k_hash_clear, dim3((unsigned)((cap + kBlock - 1) / kBlock)), dim3(kBlock),
                        0, s, a.hash, cap);
+    if (ndense > 0)
+        launch_fill_u32(reinterpret_cast<uint32_t *>(a.dense), 2 * ndense, 0u, s);
     if (a.n <= 0) return;
     const dim3 g((unsigned)((a.n + kBlock - 1) / kBlock));
     hipLaunchKernelGGL(k_hash_starts, g, dim3(kBlock), 0, s, a);
     hipLaunchKernelGGL(k_hash_counts, g, dim3(kBlock), 0, s, a);
+    if (ndense > 0) {
+        hipLaunchKernelGGL(k_dense_starts, g, dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(k_dense_counts, g, dim3(kBlock), 0, s, a);
+    }
 }
 
 // ------------------------------------------------------- pair search
@@ -228,8 +267,10 @@ __global__ __launch_bounds__(kBlock) void k_search(BuildArgs a, uint64_t *__rest
             // with nc < 3 every cell is searched once.  Skipping is exact.
             const double cb =
                 a.kb * (a.opg * (0.5 * (di + g.dmax)) + a.sk2) * g.inv_w * (1.0 + 1e-9) + 1e-9;
+            const bool dense = g.dbase >= 0;
             uint64_t m[3][3];   // [axis][slot]: Morton parts of the lower, own, upper cell
             uint64_t tp[3][3];  // the same for the tile field
+            int32_t cc[3][3];   // the cell coordinates themselves (dense levels)
             double gap[3][3];   // distance (cell units) from the particle to that slab
             bool use[3][3];
             const double pos[3] = {xi, yi, zi};
@@ -240,6 +281,9 @@ __global__ __launch_bounds__(kBlock) void k_search(BuildArgs a, uint64_t *__rest
                 if (nc >= 3) {
                     const double f = fp - (double)c;
                     const int32_t lo = c == 0 ? nc - 1 : c - 1, hi = c == nc - 1 ? 0 : c + 1;
+                    cc[ax][0] = lo;
+                    cc[ax][1] = c;
+                    cc[ax][2] = hi;
                     m[ax][0] = spread3((uint64_t)lo) << ax;
                     m[ax][1] = spread3((uint64_t)c) << ax;
                     m[ax][2] = spread3((uint64_t)hi) << ax;
@@ -253,6 +297,9 @@ __global__ __launch_bounds__(kBlock) void k_search(BuildArgs a, uint64_t *__rest
                     use[ax][1] = true;
                     use[ax][2] = 1.0 - f < cb;
                 } else {
+                    cc[ax][0] = 0;
+                    cc[ax][1] = 1;
+                    cc[ax][2] = 0;
                     m[ax][0] = 0;
                     m[ax][1] = spread3(1) << ax;
                     m[ax][2] = 0;
@@ -278,9 +325,15 @@ __global__ __launch_bounds__(kBlock) void k_search(BuildArgs a, uint64_t *__rest
                         const double g2 = (gap[0][ox] * gap[0][ox] + gap[1][oy] * gap[1][oy]) +
                                           gap[2][oz] * gap[2][oz];
                         if (!(g2 < cb * cb)) continue;
-                        const uint64_t key = base | m[0][ox] | m[1][oy] | m[2][oz] |
-                                             ((tp[0][ox] | tp[1][oy] | tp[2][oz]) << a.tshift);
-                        const int2 r = hash_find(a, key);
+                        int2 r;
+                        if (dense) {
+                            r = a.dense[g.dbase + ((int64_t)cc[0][ox] * nc + cc[1][oy]) * nc +
+                                        cc[2][oz]];
+                        } else {
+                            const uint64_t key = base | m[0][ox] | m[1][oy] | m[2][oz] |
+                                                 ((tp[0][ox] | tp[1][oy] | tp[2][oz]) << a.tshift);
+                            r = hash_find(a, key);
+                        }
                         for (int64_t j = r.x; j < (int64_t)r.x + r.y; ++j) {
                             if (L == li && j <= i) continue;
                             const P4 qj = a.pos[j];

@@ -68,7 +68,7 @@ struct SegState {
     int64_t bfirst;       // first of them (index into the work table)
     // set at each list build (k_after_build)
     double kb, disp_lim, kappa_lim;
-    int32_t maxdeg, pad0;
+    int32_t pad0, pad0b;
     // optimiser and schedule state
     double kappa, mk, vk, b1t, b2t, mu, eta_x, eta_k;
     int64_t t, it_rung, iters, iter_limit;

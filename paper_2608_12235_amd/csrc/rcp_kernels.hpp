@@ -24,6 +24,7 @@ struct LevelGrid {
     double dmax;     // largest D0 in the class
     int32_t nc;      // cells per axis
     int32_t count;   // particles in the class
+    int64_t dbase;   // first entry of the level's dense cell table, -1: hashed
 };
 
 // One occupied cell: its key and the run [start, start + count) of sorted
@@ -44,6 +45,7 @@ struct BuildArgs {
     const uint64_t *skey;   // sorted keys (after the sort)
     struct HashSlot *hash;  // open-addressing table of occupied cells
     uint64_t hmask;
+    int2 *dense;            // (start, count) per cell of the dense levels
     LevelGrid lv[kMaxLevels];
 };
 
@@ -62,7 +64,9 @@ struct PermArgs {
 };
 void launch_permute(const PermArgs &p, hipStream_t s);
 
-void launch_hash_build(const BuildArgs &a, int64_t cap, hipStream_t s);
+// Cell tables on the sorted particles: the hash for levels with dbase < 0,
+// the dense (start, count) arrays (ndense entries, cleared here) otherwise.
+void launch_hash_build(const BuildArgs &a, int64_t cap, int64_t ndense, hipStream_t s);
 // One pass over the particles: every listed pair (i, j) is appended twice
 // to `list` as (row << row_bits) | col, rows and cols in sorted order, in an
 // arbitrary order; *counter (zeroed by the caller) receives the number of
@@ -90,9 +94,11 @@ void launch_iterate(const SegPtrs *P, SegState *S, const WorkItem *W, double *pa
                     int nitems, int flags, hipStream_t s);
 void launch_tail(SegState *S, const double *partials, int nseg, hipStream_t s);
 // After a list build of segment seg: kb, validity limits, current buffer,
-// longest row (read from maxdeg_dev), clear REBUILD / STALE.
+// clear REBUILD / STALE.
 void launch_after_build(SegState *S, int seg, double kb, double disp_lim, double kappa_lim,
-                        int cur, const uint32_t *maxdeg_dev, hipStream_t s);
+                        int cur, hipStream_t st);
+// Write entry seg of the device pointer table in stream order.
+void launch_put_ptrs(SegPtrs *P, int seg, const SegPtrs &v, hipStream_t st);
 // Start a schedule on segment seg: copy the table, reset the position in it,
 // set the first rung's parameters from the current kappa.
 void launch_sched_start(SegState *S, int seg, const SchedDev &q, int reset_adam,

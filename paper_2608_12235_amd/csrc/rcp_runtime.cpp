@@ -134,6 +134,8 @@ struct rcp_ctx {
     int64_t hist_cap = 0, tiles_cap = 0;
     HashSlot *hash = nullptr;
     int64_t hcap = 0;
+    int2 *dense = nullptr;           // dense cell tables
+    int64_t dense_cap = 0;
     double *part = nullptr;          // evaluation partials
     int64_t part_cap = 0;
     double *out = nullptr;           // small device results
@@ -146,6 +148,9 @@ struct rcp_ctx {
     bool graph_valid = false;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     std::vector<hipEvent_t> kev;     // per-launch kernel timing events (3 per iteration)
+    // rebuild timing: event pairs recorded around list builds, read (and
+    // returned to the pool) at the next point where the stream is idle
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> rb_pending, rb_pool;
     rcp_stats stats{};
 };
 
@@ -167,9 +172,32 @@ static int upload_ptrs(rcp_ctx *c, int k)
 {
     SegPtrs p;
     ptrs_of(c->segs[k], p);
-    HIPCHK(hipMemcpyAsync(c->d_ptrs + k, &p, sizeof p, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    launch_put_ptrs(c->d_ptrs, k, p, c->stream);   // in stream order, no sync
+    HIPCHK(hipGetLastError());
     return RCP_OK;
+}
+
+static int rebuild_events(rcp_ctx *c, std::pair<hipEvent_t, hipEvent_t> &ev)
+{
+    if (!c->rb_pool.empty()) {
+        ev = c->rb_pool.back();
+        c->rb_pool.pop_back();
+        return RCP_OK;
+    }
+    HIPCHK(hipEventCreate(&ev.first));
+    HIPCHK(hipEventCreate(&ev.second));
+    return RCP_OK;
+}
+
+// Add the durations of completed list builds to the statistics.
+static void flush_rebuild_times(rcp_ctx *c)
+{
+    for (auto &ev : c->rb_pending) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, ev.first, ev.second) == hipSuccess) c->stats.rebuild_ms += ms;
+        c->rb_pool.push_back(ev);
+    }
+    c->rb_pending.clear();
 }
 
 static int pull_state(rcp_ctx *c)
@@ -177,6 +205,7 @@ static int pull_state(rcp_ctx *c)
     HIPCHK(hipMemcpyAsync(c->h_state, c->d_state, sizeof(SegState) * c->segs.size(),
                           hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    flush_rebuild_times(c);
     for (size_t k = 0; k < c->segs.size(); ++k) c->segs[k].cur = c->h_state[k].cur;
     return RCP_OK;
 }
@@ -269,7 +298,9 @@ static int rebuild(rcp_ctx *c, int k, double kappa)
     if (!(cmax < 0.5 * s.L))
         return fail(RCP_EBOX, "packing %d: listing cutoff %.17g is not below L/2 = %.17g", k,
                     cmax, 0.5 * s.L);
-    HIPCHK(hipEventRecord(c->e0, st));
+    std::pair<hipEvent_t, hipEvent_t> ev;
+    CHK(rebuild_events(c, ev));
+    HIPCHK(hipEventRecord(ev.first, st));
 
     BuildArgs a;
     std::memset(&a, 0, sizeof a);
@@ -289,6 +320,7 @@ static int rebuild(rcp_ctx *c, int k, double kappa)
         a.lv[l].inv_w = (double)nc / s.L;
         a.lv[l].dmax = s.dmax_lev[l];
         a.lv[l].count = (int32_t)s.lev_count[l];
+        a.lv[l].dbase = -1;
         maxbits = std::max(maxbits, bits_for(nc - 1));
     }
     a.mb = 3 * maxbits;
@@ -311,8 +343,23 @@ static int rebuild(rcp_ctx *c, int k, double kappa)
     const int64_t tiles = (lcap + 2047) / 2048 + 1;
     CHK(dgrow(&c->hist, &c->hist_cap, 256 * tiles + 1));
     CHK(dgrow(&c->tiles, &c->tiles_cap, 256 * tiles + 1));
+    // levels whose grid fits a budget of 8 cells a particle get a dense
+    // (start, count) table, looked up without hashing; the rest are hashed
+    int64_t ndense = 0;
+    const int64_t dense_budget = 8 * n + 65536;
+    int64_t nhashed = 0;
+    for (int l = 0; l < s.nlev; ++l) {
+        const int64_t nc = a.lv[l].nc, cells = nc * nc * nc;
+        if (a.lv[l].count > 0 && ndense + cells <= dense_budget) {
+            a.lv[l].dbase = ndense;
+            ndense += cells;
+        } else {
+            nhashed += a.lv[l].count;
+        }
+    }
+    if (ndense > 0) CHK(dgrow(&c->dense, &c->dense_cap, ndense));
     int64_t hcap = 64;
-    while (hcap < 2 * n) hcap <<= 1;
+    while (hcap < 2 * nhashed) hcap <<= 1;
     CHK(dgrow(&c->hash, &c->hcap, hcap));
 
     // 1. keys at the current positions, stable sort, permutation
@@ -350,7 +397,8 @@ static int rebuild(rcp_ctx *c, int k, double kappa)
     a.skey = skey;
     a.hash = c->hash;
     a.hmask = (uint64_t)hcap - 1;
-    launch_hash_build(a, hcap, st);
+    a.dense = c->dense;
+    launch_hash_build(a, hcap, ndense, st);
 
     // 3. one search pass appends every pair in both directions; the list
     //    lives in whichever key buffer the Morton keys do not occupy
@@ -398,22 +446,11 @@ static int rebuild(rcp_ctx *c, int k, double kappa)
         fill_items(c, k);
     }
 
-    // 5. longest row (statistics)
-    launch_fill_u32(c->totals + 1, 1, 0u, st);
-    launch_max_degree(n, s.rp, c->totals + 1, st);
-
     const double lim = sk * kappa * s.d0min * (1.0 - 1e-9);
-    launch_after_build(c->d_state, k, kappa, lim, opg * kappa * (1.0 - 1e-12), ncur,
-                       c->totals + 1, st);
-    HIPCHK(hipEventRecord(c->e1, st));
-    uint32_t md = 0;
-    HIPCHK(hipMemcpyAsync(&md, c->totals + 1, sizeof md, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    float ms = 0;
-    HIPCHK(hipEventElapsedTime(&ms, c->e0, c->e1));
-    c->stats.rebuild_ms += ms;
+    launch_after_build(c->d_state, k, kappa, lim, opg * kappa * (1.0 - 1e-12), ncur, st);
+    HIPCHK(hipEventRecord(ev.second, st));
+    c->rb_pending.push_back(ev);
     c->stats.rebuilds += 1;
-    s.maxdeg = md;
     s.npairs = P;
     s.nnz = 2 * P;
     s.rebuilds += 1;
@@ -833,6 +870,7 @@ static void destroy_ctx(rcp_ctx *c)
     dfree(c->tiles);
     dfree(c->totals);
     dfree(c->hash);
+    dfree(c->dense);
     dfree(c->part);
     dfree(c->out);
     dfree(c->xtmp);
@@ -840,6 +878,11 @@ static void destroy_ctx(rcp_ctx *c)
     if (c->h_out) (void)hipHostFree(c->h_out);
     for (auto &e : c->kev) (void)hipEventDestroy(e);
     c->kev.clear();
+    for (auto *v : {&c->rb_pending, &c->rb_pool})
+        for (auto &ev : *v) {
+            (void)hipEventDestroy(ev.first);
+            (void)hipEventDestroy(ev.second);
+        }
     if (c->e0) (void)hipEventDestroy(c->e0);
     if (c->e1) (void)hipEventDestroy(c->e1);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -1464,12 +1507,20 @@ int rcp_time_iterations(rcp_ctx *c, int64_t n_iters, double *iterate_us, double 
 int rcp_get_stats(rcp_ctx *c, rcp_stats *s)
 {
     if (!c || !s) return fail(RCP_EINVAL, "null argument");
+    CHK(pull_state(c));   // completes and counts pending list-build timings
     *s = c->stats;
     s->nnz = 0;
     s->max_degree = 0;
     for (auto &g : c->segs) {
         s->nnz += g.nnz;
-        s->max_degree = std::max(s->max_degree, g.maxdeg);
+        if (!g.built || g.n <= 0) continue;
+        // longest row of the current list, computed on request
+        launch_fill_u32(c->totals + 1, 1, 0u, c->stream);
+        launch_max_degree(g.n, g.rp, c->totals + 1, c->stream);
+        uint32_t md = 0;
+        HIPCHK(hipMemcpyAsync(&md, c->totals + 1, sizeof md, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        s->max_degree = std::max<int64_t>(s->max_degree, md);
     }
     return RCP_OK;
 }
