@@ -110,6 +110,89 @@ def copy_reference(torch, mib):
     print(json.dumps({"copy_reference_mib": mib, "launches": 3}), flush=True)
 
 
+def _kernel_roofline(st, n):
+    nl = max(st["kernel_launches"], 1)
+    it_us = 1e3 * st["kernel_ms"] / nl
+    nnz = st["kernel_nnz"] / nl
+    b = 188.0 * n + 4.0 * nnz
+    a = b / (it_us * 1e-6) / 1e9 if it_us > 0 else 0.0
+    return {"bound": "hbm", "kernel": "k_iterate", "achieved": a, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": a / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": b,
+            "avg_launch_us": it_us, "launches_timed": st["kernel_launches"]}
+
+
+def run_c5(torch, args):
+    """Extreme size ratio: one whole run to the stop criterion."""
+    import rcp_inputs as ri
+    import paper_2608_12235_amd as rcp
+    n = 3_000_000 if args.n == 1_000_000 else args.n
+    w = ri.c5_extreme(n=n)
+    S = float(w.d0.max() / w.d0.min())
+    skin = 256.0 if args.skin == 16.0 else args.skin
+    log("placement (random sequential addition, N=%d, S=%.3g)" % (n, S))
+    p = rcp.Packing(w.d0, w.L, 1.0, w.seed, init="rsa", params=rcp.make_params(skin_s=skin),
+                    tuning=rcp.make_tuning(time_kernels=1))
+    p.run_start(rcp.default_schedule(n, S=S))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while True:
+        act = p.run_continue(25000)
+        torch.cuda.synchronize()
+        log("  %d iterations, %.1f s" % (p.run_result()["iterations"], time.perf_counter() - t0))
+        if act == 0:
+            break
+    wall = time.perf_counter() - t0
+    st = p.stats()
+    res = p.run_result()
+    p.close()
+    out = {"metric": METRIC, "value": n * res["iterations"] / wall, "unit": "particle-updates/s",
+           "n_gpus": 1, "steps": res["iterations"], "warmup": 0,
+           "ms_per_step": wall * 1e3 / max(res["iterations"], 1), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "lognormal sigma_lnD=2.5 S=5e5 N=%d, RSA start at phi0=0.05, "
+                                  "3-D periodic, default schedule, whole run" % n,
+                      "phi_final": res["phi"], "status": res["status"],
+                      "max_overlap_before_shrink": res["max_overlap"], "skin_s": skin,
+                      "rebuilds": st["rebuilds"], "rebuild_ms": st["rebuild_ms"],
+                      "iterate_ms": st["iterate_ms"]},
+           "roofline": _kernel_roofline(st, n)}
+    print(json.dumps(out), flush=True)
+
+
+def run_census(torch, args):
+    """C4: 64 packings in one context against a loop of plain solves."""
+    import rcp_inputs as ri
+    from paper_2608_12235_amd import census
+    wl = ri.census_draw(64)
+    ntot = sum(w.n for w in wl)
+    log("census: 64 packings, sum N = %d; batched" % ntot)
+    res_b, tb, st = census.run_batched(wl)
+    log("batched %.1f s; loop of plain solves" % tb)
+    res_l, tl = census.run_loop(wl)
+    log("loop %.1f s; autotuned" % tl)
+    res_a, ta, info = census.run_autotuned(wl)
+    ub = census.particle_updates(res_b, wl)
+    phib = np.array([r["phi"] for r in res_b])
+    phil = np.array([r["phi"] for r in res_l])
+    phia = np.array([r["phi"] for r in res_a])
+    out = {"metric": METRIC, "value": ub / tb, "unit": "particle-updates/s", "n_gpus": 1,
+           "steps": int(max(r["iterations"] for r in res_b)), "warmup": 0,
+           "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "census of 64 packings (lognormal / power law / Weibull, "
+                                  "S 2..100, N 1e3..2e5, sum N %d), whole runs" % ntot,
+                      "batched_s": tb, "loop_s": tl, "autotuned_s": ta,
+                      "speedup_batched": tl / tb, "speedup_autotuned": tl / ta,
+                      "loop_value": census.particle_updates(res_l, wl) / tl,
+                      "bit_identical_batched_vs_loop": bool(np.array_equal(phib, phil)),
+                      "mean_phi_batched": float(phib.mean()),
+                      "mean_phi_autotuned": float(phia.mean()),
+                      "autotune_choice": info["best"],
+                      "statuses": sorted(set(int(r["status"]) for r in res_b)),
+                      "rebuilds_batched": st["rebuilds"], "rebuild_ms_batched": st["rebuild_ms"]}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,8 +210,12 @@ def main():
     ap.add_argument("--variant", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-timing", type=int, default=1, choices=(0, 1, 2),
-                    help="HIP events around 0: no launch (no roofline entry), 1: the first "
+                    help="HIP events around 0: no launch (no roofline entry), 1: the middle "
                          "launch of every graph, 2: every launch")
+    ap.add_argument("--workload", default="lognormal", choices=("lognormal", "c5", "census"),
+                    help="lognormal: the default line; c5: lognormal sigma_lnD=2.5, S=5e5, "
+                         "N=3e6 run to the stop criterion; census: 64 packings batched vs a loop "
+                         "of plain solves")
     ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times "
                          "(the known-size reference for hardware byte counters) and exit")
@@ -147,6 +234,12 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_reference > 0:
         copy_reference(torch, args.copy_reference)
+        return
+    if args.workload == "c5":
+        run_c5(torch, args)
+        return
+    if args.workload == "census":
+        run_census(torch, args)
         return
     import rcp_inputs as ri
     import paper_2608_12235_amd as rcp

@@ -201,9 +201,9 @@ void rcp_tuning_default(rcp_tuning *t);
  * both step sizes halving every 1/16 of its cap (cap 2 n_trig), so mu is
  * annealed towards 0; stop tolerance 5e-4.  For broad
  * distributions the position steps are multiplied by max(1, sqrt(S/10)),
- * the kappa steps by min(1, sqrt(160/S)) and the densification budget by
- * 1 + max(0, log10(S/10)), so that small spheres can move out of the way
- * of growing large ones.  In relative schedules mu~ is turned into
+ * the kappa steps by min(1, sqrt(160/S)) min(1, (1e4/S)^(1/4)) and the
+ * densification budget by 1 + max(0, log10(S/10)) + 1.7 max(0, log10(S/1e4)),
+ * so that small spheres can move out of the way of growing large ones.  In relative schedules mu~ is turned into
  * mu = mu~ N_v / (kappa sum D0) at each rung start, N_v = (sum D0^3)^2 /
  * sum D0^6 (the volume participation number: N for equal spheres, about the
  * number of volume-carrying spheres for a broad distribution), so the

@@ -269,12 +269,16 @@ def size_ratio_factors(S):
     update, and small spheres must be able to move away from it, so the
     kappa step shrinks as sqrt(160 / S) beyond S = 160, the position step
     grows as sqrt(S / 10), and the densification rung is lengthened by
-    1 + log10(S / 10).  All three are 1 for S <= 10.
+    1 + log10(S / 10).  All three are 1 for S <= 10.  Beyond S = 1e4 the
+    kappa step shrinks by a further (1e4 / S)^(1/4) and the densification
+    rung grows by a further 1.7 log10(S / 1e4), so the largest spheres do
+    not outrun the smallest ones at S ~ 1e5 (a run at S = 5e5 engulfed
+    small spheres and did not converge without it).
     """
     S = max(float(S), 1.0)
     fx = max(1.0, math.sqrt(S / 10.0))
-    fk = min(1.0, math.sqrt(160.0 / S))
-    fb = 1.0 + max(0.0, math.log10(S / 10.0))
+    fk = min(1.0, math.sqrt(160.0 / S)) * min(1.0, (1e4 / S) ** 0.25)
+    fb = 1.0 + max(0.0, math.log10(S / 10.0)) + 1.7 * max(0.0, math.log10(S / 1e4))
     return fx, fk, fb
 
 

@@ -935,8 +935,9 @@ int rcp_schedule_default(int64_t n, int dim, double S, int Y, int X, int64_t n_m
     const int64_t nt = std::max<int64_t>((int64_t)nt_d, n_min);
     const double Sr = std::max(S, 1.0);
     const double fx = std::max(1.0, std::sqrt(Sr / 10.0));
-    const double fk = std::min(1.0, std::sqrt(160.0 / Sr));
-    const double fb = 1.0 + std::max(0.0, std::log10(Sr / 10.0));
+    const double fk = std::min(1.0, std::sqrt(160.0 / Sr)) * std::min(1.0, std::pow(1e4 / Sr, 0.25));
+    const double fb = 1.0 + std::max(0.0, std::log10(Sr / 10.0)) +
+                      1.7 * std::max(0.0, std::log10(Sr / 1e4));
     struct R { double mu, ex, ek, hl, bf; };
     const R rungs[] = {
         {1e-2, 1e-2, 1e-3, 0.0, 1.0},      {1e-3, 5e-3, 5e-4, 0.0, 0.25},
