@@ -96,7 +96,9 @@ typedef struct {
  *     flight per thread instead of two, bit 1 = the Adam operands are loaded
  *     before the partner loop (more latency hidden, more registers), bit 2 =
  *     a work item's partner indices are staged in LDS in one coalesced pass
- *     before the partner loop;
+ *     before the partner loop, bit 3 = persistent blocks that each take a
+ *     sequence of work items and prefetch the next item's descriptor and row
+ *     pointers (bits 1, 2 and fused_tail do not apply with bit 3);
  *   time_kernels: 0 = no timing; 1 = HIP events around the gradient + Adam
  *     and tail launches of the middle iteration (graph_iters / 2) of every
  *     batch of graph_iters (a uniform sample of one launch in graph_iters;

@@ -308,9 +308,9 @@ __device__ __forceinline__ int32_t col_at(const int32_t *__restrict__ col,
 }
 
 // Entry loop of one row segment [q, qe): kU partners per step so that
-// their gathers are in flight together (kU = 2 or 4); with kU = 4 the next
-// step's partner indices are requested before this step's terms are
-// evaluated, so their latency hides behind the arithmetic.
+// their gathers are in flight together (kU = 2 or 4); the next step's
+// partner indices are requested before this step's terms are evaluated, so
+// their latency hides behind the arithmetic.
 template <int kU, bool kStage>
 __device__ __forceinline__ void segment_terms(Acc &a, const int32_t *__restrict__ col,
                                               const int32_t *__restrict__ scol, int32_t e0,
@@ -338,6 +338,21 @@ __device__ __forceinline__ void segment_terms(Acc &a, const int32_t *__restrict_
             if (!more) break;
         }
     }
+    if (kU == 2 && q + 2 <= qe) {
+        int32_t j0 = col_at<kStage>(col, scol, q, e0), j1 = col_at<kStage>(col, scol, q + 1, e0);
+        for (;;) {
+            const P4 q0 = load_p4(Q, j0), q1 = load_p4(Q, j1);
+            q += 2;
+            const bool more = q + 2 <= qe;
+            if (more) {
+                j0 = col_at<kStage>(col, scol, q, e0);
+                j1 = col_at<kStage>(col, scol, q + 1, e0);
+            }
+            pair_term(a, qi, q0, c.kappa, c.L, c.iL);
+            pair_term(a, qi, q1, c.kappa, c.L, c.iL);
+            if (!more) break;
+        }
+    }
     for (; q + 2 <= qe; q += 2) {
         const int32_t j0 = col_at<kStage>(col, scol, q, e0),
                       j1 = col_at<kStage>(col, scol, q + 1, e0);
@@ -355,53 +370,37 @@ __device__ __forceinline__ void store3(double (*M)[kBlock], int k, const Acc &a)
     M[2][k] = a.gz;
 }
 
-// One iteration for a block of up to 256 consecutive rows of one packing.
-// Phase 1: the block's partner entries (contiguous in the CSR) are split in
+// LDS of one work item.
+struct ItemLds {
+    int32_t srp[kBlock + 1];
+    double G[3][kBlock];   // gradient of complete rows
+    double A[3][kBlock];   // leading piece of chunk t (row began earlier)
+    double B[3][kBlock];   // trailing piece of chunk t (row goes on)
+    double red[kWavesPerBlock][4];
+};
+
+struct NoHook {
+    __device__ void operator()() const {}
+};
+
+// One work item: up to 256 consecutive rows [r0, r0 + nrow) of one packing;
+// rp_t = rp[r0 + t] (t < nrow) and rp_end = rp[r0 + nrow] are given.
+// Phase 1: the item's partner entries (contiguous in the CSR) are split in
 // equal chunks over the 256 threads, so a row with thousands of partners is
 // shared by many threads instead of serialising one.  A row lying inside one
 // chunk is summed by that thread alone; a row spanning chunks is summed as
 // (its piece in the chunk where it starts) + (the leading piece of every
 // later chunk it covers), in chunk order, so the result does not depend on
-// timing.  Phase 2: one thread per row applies Adam (coalesced).
-template <bool kFusedTail, int kU, bool kEarly, bool kStage>
-__global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ P,
-                                                   SegState *__restrict__ S,
-                                                   const WorkItem *__restrict__ W,
-                                                   double *__restrict__ partials, int flags)
+// timing.  Phase 2: one thread per row applies Adam (coalesced).  hook() runs
+// between the phases (the persistent kernel prefetches there).  Thread 0
+// writes the item's partial sums to *out.  Every thread must call it.
+template <int kU, bool kEarly, bool kStage, class Hook>
+__device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &c, int64_t r0,
+                                          int nrow, int32_t rp_t, int32_t rp_end, ItemLds &L,
+                                          int32_t *scol, Part4 *out, Hook hook)
 {
-    const int b = (flags & 1) ? remap_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
-    const WorkItem w = W[b];
-    SegState *s = S + w.seg;
-    if (s->flags & F_IDLE) return;
-    IterScalars c;
-    c.kappa = s->kappa;
-    c.L = s->L;
-    c.hL = s->hL;
-    c.b1 = s->beta1;
-    c.b2 = s->beta2;
-    c.iL = 1.0 / c.L;
-    c.ib1 = 1.0 / (1.0 - s->b1t * c.b1);
-    c.ib2 = 1.0 / (1.0 - s->b2t * c.b2);
-    c.eta = s->eta_x;
-    c.eps = s->eps_x;
-    const IterPtrs p = select_ptrs(P, w.seg, s->cur);
     const P4 *Q = p.q;
-
-    __shared__ int32_t srp[kBlock + 1];
-    __shared__ double G[3][kBlock];   // gradient of complete rows
-    __shared__ double A[3][kBlock];   // leading piece of chunk t (row began earlier)
-    __shared__ double B[3][kBlock];   // trailing piece of chunk t (row goes on)
-    __shared__ int32_t scol[kStage ? kColStage : 1];
     const int t = threadIdx.x;
-    const int64_t r0 = w.begin;
-    const int nrow = (int)(w.end - w.begin);
-    if (kStage) {
-        // the item's partner indices, one coalesced pass, issued together
-        // with the row pointers below
-        const int32_t f0 = gload(p.rp, r0), f1 = gload(p.rp, r0 + nrow);
-        const int32_t nst = min(f1 - f0, (int32_t)kColStage);
-        for (int k = t; k < nst; k += kBlock) scol[k] = gload(p.col, (int64_t)f0 + k);
-    }
     // phase-2 operands either first (their latency hides behind phase 1)
     // or after it (fewer registers live through phase 1)
     const int64_t io = r0 + t;
@@ -413,46 +412,53 @@ __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ 
             oq = load_p4(Q, (int32_t)io);
             pre = preload(p, io);
         }
-        srp[t] = gload(p.rp, io);
+        L.srp[t] = rp_t;
     }
-    if (t == 0) srp[nrow] = gload(p.rp, r0 + nrow);
+    if (t == 0) L.srp[nrow] = rp_end;
+    if (kStage) {
+        // the item's partner indices, one coalesced pass
+        const int32_t nst = min(rp_end - gload(p.rp, r0), (int32_t)kColStage);
+        const int32_t f0 = gload(p.rp, r0);
+        for (int k = t; k < nst; k += kBlock) scol[k] = gload(p.col, (int64_t)f0 + k);
+    }
     __syncthreads();
 
     // energy, kappa-gradient and max-overlap terms are block totals: each
     // thread keeps its own sums over its chunk (fixed assignment, so fixed
     // order); only the gradient needs per-row bookkeeping
     double be = 0, bs = 0, bm = 0, bd = 0;
-    const int32_t e0 = srp[0], e1 = srp[nrow];
+    const int32_t e0 = L.srp[0], e1 = L.srp[nrow];
     const int32_t chunk = max(1, (e1 - e0 + kBlock - 1) / kBlock);
     const int32_t cs = e0 + t * chunk, ce = min(cs + chunk, e1);
     if (cs < ce) {
         int lo = 0, hi = nrow - 1;   // the row holding entry cs
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (srp[mid] <= cs) lo = mid;
+            if (L.srp[mid] <= cs) lo = mid;
             else hi = mid - 1;
         }
         int r = lo;
         int32_t q = cs;
         for (;;) {
             const P4 qi = load_p4(Q, (int32_t)(r0 + r));
-            const int32_t rend = srp[r + 1], qe = min(rend, ce);
+            const int32_t rend = L.srp[r + 1], qe = min(rend, ce);
             Acc a = {0, 0, 0, 0, 0, 0, 0};
             segment_terms<kU, kStage>(a, p.col, scol, e0, Q, q, qe, qi, c);
             be += a.e;
             bs += a.s;
             bm = fmax(bm, a.m);
-            const bool began_before = srp[r] < cs, goes_on = rend > ce;
-            if (began_before) store3(A, t, a);
-            else if (goes_on) store3(B, t, a);
-            else store3(G, r, a);
+            const bool began_before = L.srp[r] < cs, goes_on = rend > ce;
+            if (began_before) store3(L.A, t, a);
+            else if (goes_on) store3(L.B, t, a);
+            else store3(L.G, r, a);
             q = qe;
             if (q >= ce) break;
             do {
                 ++r;
-            } while (srp[r + 1] <= q);   // skip rows without partners
+            } while (L.srp[r + 1] <= q);   // skip rows without partners
         }
     }
+    hook();
     __syncthreads();
 
     if (own) {
@@ -460,19 +466,19 @@ __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ 
             oq = load_p4(Q, (int32_t)io);
             pre = preload(p, io);
         }
-        const int32_t qb = srp[t], qe = srp[t + 1];
+        const int32_t qb = L.srp[t], qe = L.srp[t + 1];
         double g[3] = {0, 0, 0};
         if (qb < qe) {
             const int tf = (qb - e0) / chunk, tl = (qe - 1 - e0) / chunk;
             if (tf == tl) {
 #pragma unroll
-                for (int k = 0; k < 3; ++k) g[k] = G[k][t];
+                for (int k = 0; k < 3; ++k) g[k] = L.G[k][t];
             } else {
 #pragma unroll
-                for (int k = 0; k < 3; ++k) g[k] = B[k][tf];
+                for (int k = 0; k < 3; ++k) g[k] = L.B[k][tf];
                 for (int u = tf + 1; u <= tl; ++u) {
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) g[k] += A[k][u];
+                    for (int k = 0; k < 3; ++k) g[k] += L.A[k][u];
                 }
             }
         }
@@ -484,30 +490,68 @@ __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ 
     bs = wave_sum(bs);
     bm = wave_max(bm);
     bd = wave_max(bd);
-    __shared__ double red[kWavesPerBlock][4];
     const int wv = t / kWave;
     if (lane == 0) {
-        red[wv][0] = be;
-        red[wv][1] = bs;
-        red[wv][2] = bm;
-        red[wv][3] = bd;
+        L.red[wv][0] = be;
+        L.red[wv][1] = bs;
+        L.red[wv][2] = bm;
+        L.red[wv][3] = bd;
     }
     __syncthreads();
     if (t == 0) {
         double e = 0, sd = 0, m = 0, d = 0;
         for (int k = 0; k < kWavesPerBlock; ++k) {
-            e += red[k][0];
-            sd += red[k][1];
-            m = fmax(m, red[k][2]);
-            d = fmax(d, red[k][3]);
+            e += L.red[k][0];
+            sd += L.red[k][1];
+            m = fmax(m, L.red[k][2]);
+            d = fmax(d, L.red[k][3]);
         }
         Part4 o;
         o.e = e;
         o.s = sd;
         o.m = m;
         o.d = d;
-        reinterpret_cast<Part4 *>(partials)[b] = o;
+        *out = o;
     }
+}
+
+__device__ __forceinline__ void load_scalars(const SegState *s, IterScalars &c)
+{
+    c.kappa = s->kappa;
+    c.L = s->L;
+    c.hL = s->hL;
+    c.b1 = s->beta1;
+    c.b2 = s->beta2;
+    c.iL = 1.0 / c.L;
+    c.ib1 = 1.0 / (1.0 - s->b1t * c.b1);
+    c.ib2 = 1.0 / (1.0 - s->b2t * c.b2);
+    c.eta = s->eta_x;
+    c.eps = s->eps_x;
+}
+
+// One block per work item.
+template <bool kFusedTail, int kU, bool kEarly, bool kStage>
+__global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ P,
+                                                   SegState *__restrict__ S,
+                                                   const WorkItem *__restrict__ W,
+                                                   double *__restrict__ partials, int flags)
+{
+    const int b = (flags & 1) ? remap_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+    const WorkItem w = W[b];
+    SegState *s = S + w.seg;
+    if (s->flags & F_IDLE) return;
+    IterScalars c;
+    load_scalars(s, c);
+    const IterPtrs p = select_ptrs(P, w.seg, s->cur);
+    __shared__ ItemLds L;
+    __shared__ int32_t scol[kStage ? kColStage : 1];
+    const int t = threadIdx.x;
+    const int64_t r0 = w.begin;
+    const int nrow = (int)(w.end - w.begin);
+    const int32_t rp_t = t < nrow ? gload(p.rp, r0 + t) : 0;
+    const int32_t rp_end = gload(p.rp, r0 + nrow);
+    item_body<kU, kEarly, kStage>(p, c, r0, nrow, rp_t, rp_end, L, scol,
+                                  reinterpret_cast<Part4 *>(partials) + b, NoHook());
     if (kFusedTail) {
         __shared__ int last;
         __threadfence();
@@ -524,14 +568,84 @@ __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ 
     }
 }
 
-constexpr int kTailBlock = 1024;
+// resident blocks of the persistent form: 256 CUs x 5 blocks (the occupancy
+// of the two-gather variant)
+constexpr int kPersistBlocks = 256 * 5;
 
-__global__ __launch_bounds__(kTailBlock) void k_tail(SegState *__restrict__ S,
-                                                    const double *__restrict__ partials)
+// Persistent form: a grid of resident blocks, each taking the work items
+// lo + slot, lo + slot + nbx, ... of its XCD's contiguous range (blocks are
+// dispatched round-robin over the 8 XCDs).  The next item's descriptor is
+// requested at the top of an item and its row pointers between the item's
+// two phases, so they are in registers when the item starts.
+template <int kU>
+__global__ __launch_bounds__(kBlock) void k_iterate_persist(const SegPtrs *__restrict__ P,
+                                                           SegState *__restrict__ S,
+                                                           const WorkItem *__restrict__ W,
+                                                           double *__restrict__ partials,
+                                                           int nitems, int flags)
 {
-    SegState *s = S + blockIdx.x;
-    if (s->flags & F_IDLE) return;
-    reduce_and_tail<kTailBlock>(s, partials);
+    constexpr int nx = 8;
+    const int G = (int)gridDim.x;
+    int lo = 0, hi = nitems, slot = (int)blockIdx.x, nbx = G;
+    if ((flags & 1) && G >= nx) {
+        const int xcd = (int)blockIdx.x % nx;
+        slot = (int)blockIdx.x / nx;
+        nbx = (G - xcd + nx - 1) / nx;
+        const int per = nitems / nx, rem = nitems % nx;
+        lo = xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per;
+        hi = lo + per + (xcd < rem ? 1 : 0);
+    }
+    int item = lo + slot;
+    if (item >= hi) return;
+    __shared__ ItemLds L;
+    const int t = threadIdx.x;
+    WorkItem wn = W[item];
+    int cseg = -1;
+    bool idle = true;
+    IterScalars c;
+    IterPtrs p;
+    int32_t rpn_t = 0, rpn_e = 0;
+    bool have = false;
+    for (;;) {
+        const WorkItem w = wn;
+        const int next = item + nbx;
+        if (next < hi) wn = W[next];
+        if (w.seg != cseg) {
+            cseg = w.seg;
+            const SegState *s = S + cseg;
+            idle = (s->flags & F_IDLE) != 0;
+            if (!idle) {
+                load_scalars(s, c);
+                p = select_ptrs(P, cseg, s->cur);
+            }
+            have = false;
+        }
+        if (!idle) {
+            const int nrow = (int)(w.end - w.begin);
+            int32_t rp_t, rp_end;
+            if (have) {
+                rp_t = rpn_t;
+                rp_end = rpn_e;
+            } else {
+                rp_t = t < nrow ? gload(p.rp, w.begin + t) : 0;
+                rp_end = gload(p.rp, w.begin + nrow);
+            }
+            have = false;
+            auto hook = [&]() {
+                if (next < hi && wn.seg == cseg) {
+                    const int nr = (int)(wn.end - wn.begin);
+                    rpn_t = t < nr ? gload(p.rp, wn.begin + t) : 0;
+                    rpn_e = gload(p.rp, wn.begin + nr);
+                    have = true;
+                }
+            };
+            item_body<kU, false, false>(p, c, w.begin, nrow, rp_t, rp_end, L, nullptr,
+                                        reinterpret_cast<Part4 *>(partials) + item, hook);
+        }
+        item = next;
+        if (item >= hi) break;
+        __syncthreads();   // the item's LDS is reused
+    }
 }
 
 template <bool kF, int kU, bool kE, bool kNT>
@@ -547,7 +661,18 @@ static void launch_variant(const SegPtrs *P, SegState *S, const WorkItem *W, dou
                            int nitems, int f, int variant, hipStream_t st)
 {
     // bit 0: four gathers in flight; bit 1: early Adam operands; bit 2:
-    // partner indices staged in LDS
+    // partner indices staged in LDS; bit 3: persistent blocks (bits 1, 2 and
+    // the fused tail do not apply to it)
+    if (variant & 8) {
+        const int grid = std::min(nitems, kPersistBlocks);
+        if (variant & 1)
+            hipLaunchKernelGGL(k_iterate_persist<4>, dim3(grid), dim3(kBlock), 0, st, P, S, W,
+                               partials, nitems, f);
+        else
+            hipLaunchKernelGGL(k_iterate_persist<2>, dim3(grid), dim3(kBlock), 0, st, P, S, W,
+                               partials, nitems, f);
+        return;
+    }
     switch (variant & 7) {
     case 0: launch_one<kF, 2, false, false>(P, S, W, partials, nitems, f, st); break;
     case 1: launch_one<kF, 4, false, false>(P, S, W, partials, nitems, f, st); break;
@@ -563,11 +688,22 @@ static void launch_variant(const SegPtrs *P, SegState *S, const WorkItem *W, dou
 void launch_iterate(const SegPtrs *P, SegState *S, const WorkItem *W, double *partials,
                     int nitems, int flags, hipStream_t st)
 {
-    // bit 0: XCD-aware order; bit 1: fused tail; bits 8-10: kernel variant
+    // bit 0: XCD-aware order; bit 1: fused tail; bits 8-11: kernel variant
     // (see launch_variant)
-    const int f = flags & 1, variant = (flags >> 8) & 7;
-    if (flags & 2) launch_variant<true>(P, S, W, partials, nitems, f, variant, st);
+    const int f = flags & 1, variant = (flags >> 8) & 15;
+    if (variant & 8) launch_variant<false>(P, S, W, partials, nitems, f, variant, st);
+    else if (flags & 2) launch_variant<true>(P, S, W, partials, nitems, f, variant, st);
     else launch_variant<false>(P, S, W, partials, nitems, f, variant, st);
+}
+
+constexpr int kTailBlock = 1024;
+
+__global__ __launch_bounds__(kTailBlock) void k_tail(SegState *__restrict__ S,
+                                                    const double *__restrict__ partials)
+{
+    SegState *s = S + blockIdx.x;
+    if (s->flags & F_IDLE) return;
+    reduce_and_tail<kTailBlock>(s, partials);
 }
 
 // Work items.  Row i of a packing has work coordinate w(i) = rc * i + rp[i]

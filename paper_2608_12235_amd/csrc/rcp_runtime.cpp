@@ -499,7 +499,7 @@ static bool slot_timed(const rcp_ctx *c, int64_t slot)
 static int launch_one_iteration(rcp_ctx *c, int slot)
 {
     const int flags = (c->tuning.xcd_remap ? 1 : 0) | (c->tuning.fused_tail ? 2 : 0) |
-                      ((c->tuning.variant & 7) << 8);
+                      ((c->tuning.variant & 15) << 8);
     const bool timed = slot_timed(c, slot) && 3 * slot + 2 < (int)c->kev.size();
     if (timed) CHK(record_event(c, c->kev[3 * slot]));
     launch_iterate(c->d_ptrs, c->d_state, c->d_work, c->d_partials, c->nitems, flags, c->stream);
@@ -1061,7 +1061,7 @@ int rcp_set_skin(rcp_ctx *c, double skin_s, double skin_g)
 int rcp_set_tuning(rcp_ctx *c, const rcp_tuning *t)
 {
     if (!c || !t || t->size != sizeof(rcp_tuning)) return fail(RCP_EINVAL, "bad tuning");
-    if (t->graph_iters < 1 || t->graph_iters > 4096 || t->variant < 0 || t->variant > 7 ||
+    if (t->graph_iters < 1 || t->graph_iters > 4096 || t->variant < 0 || t->variant > 15 ||
         t->row_cost < 1 || t->row_cost > 65536 || t->item_work < 1 ||
         (int64_t)t->item_work > (int64_t)kBlock * t->row_cost)
         return fail(RCP_EINVAL, "bad tuning values");
@@ -1458,7 +1458,7 @@ int rcp_time_iterations(rcp_ctx *c, int64_t n_iters, double *iterate_us, double 
     int64_t n_done = 0;
     int rc = RCP_OK;
     const int flags = (c->tuning.xcd_remap ? 1 : 0) |
-                      ((c->tuning.variant & 7) << 8);
+                      ((c->tuning.variant & 15) << 8);
     for (;;) {
         if ((rc = pull_state(c)) != RCP_OK) break;
         bool any = false;

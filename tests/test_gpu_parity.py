@@ -222,7 +222,8 @@ def test_energy_grad_c3(rcp, orc, c3):
 # ------------------------------------------------------------- Adam steps
 @pytest.mark.parametrize("steps,fused,graph,variant", [(1, 0, 16, 3), (10, 0, 16, 0),
                                                        (10, 1, 16, 1), (25, 1, 1, 2),
-                                                       (25, 0, 4, 3)])
+                                                       (25, 0, 4, 3), (10, 0, 16, 8),
+                                                       (25, 0, 1, 9), (10, 0, 16, 12)])
 def test_adam_steps_match_oracle(rcp, orc, steps, fused, graph, variant):
     w, x, k = _dense_c1_state(orc, iters=1500)
     mu, ex, ek = 2e-3, 2e-3, 2e-4
