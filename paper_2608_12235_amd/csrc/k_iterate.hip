@@ -698,12 +698,24 @@ void launch_iterate(const SegPtrs *P, SegState *S, const WorkItem *W, double *pa
 
 constexpr int kTailBlock = 1024;
 
+// One block per packing.  The packing's record is copied to LDS in one
+// parallel pass, the tail works on the copy (its many dependent reads and
+// writes then cost LDS latency, not memory latency) and the block writes the
+// record back.
 __global__ __launch_bounds__(kTailBlock) void k_tail(SegState *__restrict__ S,
                                                     const double *__restrict__ partials)
 {
-    SegState *s = S + blockIdx.x;
-    if (s->flags & F_IDLE) return;
-    reduce_and_tail<kTailBlock>(s, partials);
+    static_assert(sizeof(SegState) % 8 == 0, "SegState is copied in 8-byte words");
+    constexpr int kWords = (int)(sizeof(SegState) / 8);
+    __shared__ SegState ls;
+    uint64_t *src = reinterpret_cast<uint64_t *>(S + blockIdx.x);
+    uint64_t *dst = reinterpret_cast<uint64_t *>(&ls);
+    for (int k = threadIdx.x; k < kWords; k += kTailBlock) dst[k] = src[k];
+    __syncthreads();
+    if (ls.flags & F_IDLE) return;
+    reduce_and_tail<kTailBlock>(&ls, partials);
+    __syncthreads();
+    for (int k = threadIdx.x; k < kWords; k += kTailBlock) src[k] = dst[k];
 }
 
 // Work items.  Row i of a packing has work coordinate w(i) = rc * i + rp[i]
