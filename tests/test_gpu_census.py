@@ -1,0 +1,79 @@
+"""Batched census (many packings in one context) against plain solves and
+against the FP64 oracle.
+
+A packing's trajectory in a census depends only on its own data, so the
+batched results must equal the plain solves bit for bit.  phi accuracy:
+the smallest packings of the census draw, 8 placement seeds each, batched on
+the GPU and run by the oracle; mean phi within 0.002 (the whole-run bar),
+every GPU run stopped by the criterion with no overlap left after shrink."""
+import numpy as np
+import pytest
+
+import rcp_inputs as ri
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rcp():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2608_12235_amd as m
+    m.lib()
+    return m
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _smallest(k):
+    wl = ri.census_draw(64)
+    return sorted(wl, key=lambda w: w.n)[:k]
+
+
+def test_census_equals_plain_solves(rcp):
+    from paper_2608_12235_amd import census
+    wl = _smallest(6)
+    _say("census of", [w.n for w in wl])
+    rb, _, _ = census.run_batched(wl)
+    rl, _ = census.run_loop(wl)
+    for a, b in zip(rb, rl):
+        assert a == b
+
+
+def test_census_phi_matches_oracle(rcp, orc):
+    from paper_2608_12235_amd import census
+    base = _smallest(4)
+    wl = []
+    for w in base:
+        for seed in range(8):
+            wl.append(type(w)(w.name, w.d0, w.L, w.phi0, 1000 + seed, w.family, w.params))
+    _say("census phi check:", len(wl), "packings, N", [w.n for w in base])
+    res, _, _ = census.run_batched(wl)
+    pg, po = [], []
+    for w, r in zip(wl, res):
+        assert r["status"] == 0 and r["max_overlap"] < 5e-4, r
+        pg.append(r["phi"])
+        st = orc.RunState(orc.rsa(w.d0, w.L, 1.0, w.seed), w.d0, w.L, 1.0)
+        S = float(w.d0.max() / w.d0.min())
+        status, ro, _ = orc.run(st, orc.default_params(w.d0, s=0.5), orc.default_schedule(w.n, S=S))
+        assert status == 0
+        po.append(ro.phi)
+    _say("phi gpu %.5f +- %.5f oracle %.5f +- %.5f" % (np.mean(pg), np.std(pg), np.mean(po),
+                                                       np.std(po)))
+    assert abs(np.mean(pg) - np.mean(po)) <= 0.002
+
+
+def test_census_box_failure_isolated(rcp):
+    # a packing whose largest sphere cannot fit its box at the reached scale
+    # is stopped with RCP_EBOX while the others finish
+    from paper_2608_12235_amd import census
+    ok = _smallest(2)
+    d0 = np.array([10.0] + [1.0] * 29)
+    L = ri.box_for_phi(d0, 0.03)   # fits at kappa = 1, not once phi nears jamming
+    bad = type(ok[0])("tight", d0, L, 0.03, 7, "lognormal", {})
+    res, _, _ = census.run_batched(ok + [bad])
+    assert res[0]["status"] == 0 and res[1]["status"] == 0
+    assert res[2]["status"] == -2
