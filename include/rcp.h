@@ -98,7 +98,13 @@ typedef struct {
  *     a work item's partner indices are staged in LDS in one coalesced pass
  *     before the partner loop, bit 3 = persistent blocks that each take a
  *     sequence of work items and prefetch the next item's descriptor and row
- *     pointers (bits 1, 2 and fused_tail do not apply with bit 3);
+ *     pointers (bits 1, 2 and fused_tail do not apply with bit 3), bit 4 =
+ *     compiled for seven waves per SIMD (fewer registers, some spilling),
+ *     bit 5 = work items of up to 512 rows, two per thread in the Adam phase
+ *     (bits 1-4 and fused_tail do not apply with it); bit 6 selects the
+ *     wave-cooperative pair search of the list build (the 64 lanes of a
+ *     wave test the flattened candidates of all their cells together; the
+ *     same pairs are listed);
  *   time_kernels: 0 = no timing; 1 = HIP events around the gradient + Adam
  *     and tail launches of the middle iteration (graph_iters / 2) of every
  *     batch of graph_iters (a uniform sample of one launch in graph_iters;
@@ -108,8 +114,9 @@ typedef struct {
  *     work items of item_work units, a row costing row_cost units plus one
  *     per listed partner, so each 256-thread block gets about the same
  *     gather work whether its rows are small spheres or large ones; 1 <=
- *     row_cost <= 65536 and 1 <= item_work <= 256 * row_cost (an item then
- *     never holds more than 256 rows). */
+ *     row_cost <= 65536 and 1 <= item_work <= R * row_cost, R = 512 with
+ *     variant bit 5 and 256 otherwise (an item then never holds more than R
+ *     rows). */
 typedef struct {
     uint32_t size;
     int32_t graph_iters;
@@ -192,6 +199,9 @@ typedef struct {
 int rcp_version(void);
 const char *rcp_last_error(void);
 void rcp_params_default(rcp_params *p);
+/* Defaults: graph_iters 16, xcd_remap 1, fused_tail 0, variant 64 (the
+ * cooperative pair search, the two-gather gradient + Adam kernel), row_cost
+ * 16, item_work 4096, time_kernels 0. */
 void rcp_tuning_default(rcp_tuning *t);
 
 /* Default rung table for a packing of n spheres in dimension dim with size

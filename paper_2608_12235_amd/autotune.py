@@ -14,7 +14,7 @@ import time
 from .api import make_tuning
 
 SKINS = (0.5, 1.0, 2.0, 4.0, 8.0)
-VARIANTS = (0, 1)
+VARIANTS = (64, 65, 0, 1)
 WORK_CUTS = ((16, 4096), (8, 2048), (4, 512))
 GRAPH_ITERS = (16, 32)
 

@@ -27,6 +27,10 @@ __device__ __forceinline__ int remap_block(int b, int G)
     return (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + loc;
 }
 
+// Running sums of pair terms: the gradient of the current row, and the
+// energy, kappa-gradient and max-overlap terms (per thread in the iteration
+// kernel, per row in the evaluation kernel); c counts overlapping pairs
+// (evaluation only).
 struct Acc {
     double gx, gy, gz, e, s, m, c;
 };
@@ -43,6 +47,7 @@ __device__ __forceinline__ double near_image(double d, double L, double iL)
 // One listed partner's terms (Eq. energy): with q = r/d and delta = 1 - q,
 // E += delta^2 / 4 and S += delta q / 2 (each pair is seen from both ends),
 // and the gradient on x_i gains delta / (d r) (x_j - x_i).
+template <bool kCount = true>
 __device__ __forceinline__ void pair_term(Acc &a, const P4 &qi, const P4 &qj, double kappa,
                                           double L, double iL)
 {
@@ -58,7 +63,7 @@ __device__ __forceinline__ void pair_term(Acc &a, const P4 &qi, const P4 &qj, do
         a.e += 0.25 * (delta * delta);
         a.s += 0.5 * (delta * q);
         a.m = fmax(a.m, delta);
-        a.c += 0.5;
+        if (kCount) a.c += 0.5;
         if (r > 0.0) {
             const double f = delta / (d * r);
             a.gx += f * dx;
@@ -244,7 +249,25 @@ struct alignas(32) Part4 {
 // kT threads (fixed assignment of partials to threads, fixed combining
 // order); thread 0 then runs the tail.  Every thread of the block must call
 // it.
-template <int kT>
+// A block partial read past the caches (system-scope relaxed atomic loads):
+// used when the partials were written in the same kernel by other XCDs.
+__device__ __forceinline__ Part4 load_part_coherent(const Part4 *p)
+{
+    Part4 r;
+    r.e = __hip_atomic_load(&p->e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    r.s = __hip_atomic_load(&p->s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    r.m = __hip_atomic_load(&p->m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    r.d = __hip_atomic_load(&p->d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    return r;
+}
+
+template <bool kCoherent>
+__device__ __forceinline__ Part4 load_part(const Part4 *p)
+{
+    return kCoherent ? load_part_coherent(p) : *p;
+}
+
+template <int kT, bool kCoherent = false>
 __device__ void reduce_and_tail(SegState *s, const double *partials)
 {
     constexpr int kW = kT / kWave;
@@ -253,14 +276,16 @@ __device__ void reduce_and_tail(SegState *s, const double *partials)
     const Part4 *P = reinterpret_cast<const Part4 *>(partials) + b0;
     int64_t b = threadIdx.x;
     for (; b + 3 * kT < nb; b += 4 * kT) {
-        const Part4 p0 = P[b], p1 = P[b + kT], p2 = P[b + 2 * kT], p3 = P[b + 3 * kT];
+        const Part4 p0 = load_part<kCoherent>(P + b), p1 = load_part<kCoherent>(P + b + kT),
+                    p2 = load_part<kCoherent>(P + b + 2 * kT),
+                    p3 = load_part<kCoherent>(P + b + 3 * kT);
         e += ((p0.e + p1.e) + (p2.e + p3.e));
         sd += ((p0.s + p1.s) + (p2.s + p3.s));
         m = fmax(m, fmax(fmax(p0.m, p1.m), fmax(p2.m, p3.m)));
         d = fmax(d, fmax(fmax(p0.d, p1.d), fmax(p2.d, p3.d)));
     }
     for (; b < nb; b += kT) {
-        const Part4 p0 = P[b];
+        const Part4 p0 = load_part<kCoherent>(P + b);
         e += p0.e;
         sd += p0.s;
         m = fmax(m, p0.m);
@@ -331,10 +356,10 @@ __device__ __forceinline__ void segment_terms(Acc &a, const int32_t *__restrict_
                 j2 = col_at<kStage>(col, scol, q + 2, e0);
                 j3 = col_at<kStage>(col, scol, q + 3, e0);
             }
-            pair_term(a, qi, q0, c.kappa, c.L, c.iL);
-            pair_term(a, qi, q1, c.kappa, c.L, c.iL);
-            pair_term(a, qi, q2, c.kappa, c.L, c.iL);
-            pair_term(a, qi, q3, c.kappa, c.L, c.iL);
+            pair_term<false>(a, qi, q0, c.kappa, c.L, c.iL);
+            pair_term<false>(a, qi, q1, c.kappa, c.L, c.iL);
+            pair_term<false>(a, qi, q2, c.kappa, c.L, c.iL);
+            pair_term<false>(a, qi, q3, c.kappa, c.L, c.iL);
             if (!more) break;
         }
     }
@@ -348,8 +373,8 @@ __device__ __forceinline__ void segment_terms(Acc &a, const int32_t *__restrict_
                 j0 = col_at<kStage>(col, scol, q, e0);
                 j1 = col_at<kStage>(col, scol, q + 1, e0);
             }
-            pair_term(a, qi, q0, c.kappa, c.L, c.iL);
-            pair_term(a, qi, q1, c.kappa, c.L, c.iL);
+            pair_term<false>(a, qi, q0, c.kappa, c.L, c.iL);
+            pair_term<false>(a, qi, q1, c.kappa, c.L, c.iL);
             if (!more) break;
         }
     }
@@ -357,13 +382,14 @@ __device__ __forceinline__ void segment_terms(Acc &a, const int32_t *__restrict_
         const int32_t j0 = col_at<kStage>(col, scol, q, e0),
                       j1 = col_at<kStage>(col, scol, q + 1, e0);
         const P4 q0 = load_p4(Q, j0), q1 = load_p4(Q, j1);
-        pair_term(a, qi, q0, c.kappa, c.L, c.iL);
-        pair_term(a, qi, q1, c.kappa, c.L, c.iL);
+        pair_term<false>(a, qi, q0, c.kappa, c.L, c.iL);
+        pair_term<false>(a, qi, q1, c.kappa, c.L, c.iL);
     }
-    if (q < qe) pair_term(a, qi, load_p4(Q, col_at<kStage>(col, scol, q, e0)), c.kappa, c.L, c.iL);
+    if (q < qe) pair_term<false>(a, qi, load_p4(Q, col_at<kStage>(col, scol, q, e0)), c.kappa, c.L, c.iL);
 }
 
-__device__ __forceinline__ void store3(double (*M)[kBlock], int k, const Acc &a)
+template <int kN>
+__device__ __forceinline__ void store3(double (*M)[kN], int k, const Acc &a)
 {
     M[0][k] = a.gx;
     M[1][k] = a.gy;
@@ -371,20 +397,23 @@ __device__ __forceinline__ void store3(double (*M)[kBlock], int k, const Acc &a)
 }
 
 // LDS of one work item.
-struct ItemLds {
-    int32_t srp[kBlock + 1];
-    double G[3][kBlock];   // gradient of complete rows
+template <int kR>
+struct ItemLdsR {
+    int32_t srp[kR + 1];
+    double G[3][kR];       // gradient of complete rows
     double A[3][kBlock];   // leading piece of chunk t (row began earlier)
     double B[3][kBlock];   // trailing piece of chunk t (row goes on)
     double red[kWavesPerBlock][4];
 };
+using ItemLds = ItemLdsR<kBlock>;
 
 struct NoHook {
     __device__ void operator()() const {}
 };
 
-// One work item: up to 256 consecutive rows [r0, r0 + nrow) of one packing;
-// rp_t = rp[r0 + t] (t < nrow) and rp_end = rp[r0 + nrow] are given.
+// One work item: up to kR (256 or 512) consecutive rows [r0, r0 + nrow) of
+// one packing; rp_own[k] = rp[r0 + t + 256 k] for the rows this thread owns
+// and rp_end = rp[r0 + nrow] are given.
 // Phase 1: the item's partner entries (contiguous in the CSR) are split in
 // equal chunks over the 256 threads, so a row with thousands of partners is
 // shared by many threads instead of serialising one.  A row lying inside one
@@ -394,26 +423,26 @@ struct NoHook {
 // timing.  Phase 2: one thread per row applies Adam (coalesced).  hook() runs
 // between the phases (the persistent kernel prefetches there).  Thread 0
 // writes the item's partial sums to *out.  Every thread must call it.
-template <int kU, bool kEarly, bool kStage, class Hook>
+template <int kU, bool kEarly, bool kStage, int kR, class Hook, bool kCoherentOut = false>
 __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &c, int64_t r0,
-                                          int nrow, int32_t rp_t, int32_t rp_end, ItemLds &L,
-                                          int32_t *scol, Part4 *out, Hook hook)
+                                          int nrow, const int32_t *rp_own, int32_t rp_end,
+                                          ItemLdsR<kR> &L, int32_t *scol, Part4 *out, Hook hook)
 {
+    static_assert(kR == kBlock || (kR == 2 * kBlock && !kEarly), "rows per item");
+    constexpr int kOwn = kR / kBlock;
     const P4 *Q = p.q;
     const int t = threadIdx.x;
     // phase-2 operands either first (their latency hides behind phase 1)
     // or after it (fewer registers live through phase 1)
-    const int64_t io = r0 + t;
-    const bool own = t < nrow;
     P4 oq = {0, 0, 0, 0};
     Pre pre = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (own) {
-        if (kEarly) {
-            oq = load_p4(Q, (int32_t)io);
-            pre = preload(p, io);
-        }
-        L.srp[t] = rp_t;
+    if (kEarly && t < nrow) {
+        oq = load_p4(Q, (int32_t)(r0 + t));
+        pre = preload(p, r0 + t);
     }
+#pragma unroll
+    for (int k = 0; k < kOwn; ++k)
+        if (t + k * kBlock < nrow) L.srp[t + k * kBlock] = rp_own[k];
     if (t == 0) L.srp[nrow] = rp_end;
     if (kStage) {
         // the item's partner indices, one coalesced pass
@@ -426,7 +455,8 @@ __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &
     // energy, kappa-gradient and max-overlap terms are block totals: each
     // thread keeps its own sums over its chunk (fixed assignment, so fixed
     // order); only the gradient needs per-row bookkeeping
-    double be = 0, bs = 0, bm = 0, bd = 0;
+    Acc a = {0, 0, 0, 0, 0, 0, 0};   // e, s, m: this thread's totals
+    double bd = 0;
     const int32_t e0 = L.srp[0], e1 = L.srp[nrow];
     const int32_t chunk = max(1, (e1 - e0 + kBlock - 1) / kBlock);
     const int32_t cs = e0 + t * chunk, ce = min(cs + chunk, e1);
@@ -442,15 +472,12 @@ __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &
         for (;;) {
             const P4 qi = load_p4(Q, (int32_t)(r0 + r));
             const int32_t rend = L.srp[r + 1], qe = min(rend, ce);
-            Acc a = {0, 0, 0, 0, 0, 0, 0};
+            a.gx = a.gy = a.gz = 0.0;
             segment_terms<kU, kStage>(a, p.col, scol, e0, Q, q, qe, qi, c);
-            be += a.e;
-            bs += a.s;
-            bm = fmax(bm, a.m);
             const bool began_before = L.srp[r] < cs, goes_on = rend > ce;
-            if (began_before) store3(L.A, t, a);
-            else if (goes_on) store3(L.B, t, a);
-            else store3(L.G, r, a);
+            if (began_before) store3<kBlock>(L.A, t, a);
+            else if (goes_on) store3<kBlock>(L.B, t, a);
+            else store3<kR>(L.G, r, a);
             q = qe;
             if (q >= ce) break;
             do {
@@ -461,34 +488,38 @@ __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &
     hook();
     __syncthreads();
 
-    if (own) {
+#pragma unroll
+    for (int k = 0; k < kOwn; ++k) {
+        const int row = t + k * kBlock;
+        if (row >= nrow) break;
+        const int64_t io = r0 + row;
         if (!kEarly) {
             oq = load_p4(Q, (int32_t)io);
             pre = preload(p, io);
         }
-        const int32_t qb = L.srp[t], qe = L.srp[t + 1];
+        const int32_t qb = L.srp[row], qe = L.srp[row + 1];
         double g[3] = {0, 0, 0};
         if (qb < qe) {
             const int tf = (qb - e0) / chunk, tl = (qe - 1 - e0) / chunk;
             if (tf == tl) {
 #pragma unroll
-                for (int k = 0; k < 3; ++k) g[k] = L.G[k][t];
+                for (int d = 0; d < 3; ++d) g[d] = L.G[d][row];
             } else {
 #pragma unroll
-                for (int k = 0; k < 3; ++k) g[k] = L.B[k][tf];
+                for (int d = 0; d < 3; ++d) g[d] = L.B[d][tf];
                 for (int u = tf + 1; u <= tl; ++u) {
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) g[k] += L.A[k][u];
+                    for (int d = 0; d < 3; ++d) g[d] += L.A[d][u];
                 }
             }
         }
-        bd = update_particle(p, c, io, oq, pre, g[0], g[1], g[2]);
+        bd = fmax(bd, update_particle(p, c, io, oq, pre, g[0], g[1], g[2]));
     }
     // block reduction of the four partials
     const int lane = t & (kWave - 1);
-    be = wave_sum(be);
-    bs = wave_sum(bs);
-    bm = wave_max(bm);
+    const double be = wave_sum(a.e);
+    const double bs = wave_sum(a.s);
+    const double bm = wave_max(a.m);
     bd = wave_max(bd);
     const int wv = t / kWave;
     if (lane == 0) {
@@ -506,12 +537,20 @@ __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &
             m = fmax(m, L.red[k][2]);
             d = fmax(d, L.red[k][3]);
         }
-        Part4 o;
-        o.e = e;
-        o.s = sd;
-        o.m = m;
-        o.d = d;
-        *out = o;
+        if (kCoherentOut) {
+            // written through to memory: the tail may run on another XCD
+            __hip_atomic_store(&out->e, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&out->s, sd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&out->m, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(&out->d, d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        } else {
+            Part4 o;
+            o.e = e;
+            o.s = sd;
+            o.m = m;
+            o.d = d;
+            *out = o;
+        }
     }
 }
 
@@ -529,9 +568,10 @@ __device__ __forceinline__ void load_scalars(const SegState *s, IterScalars &c)
     c.eps = s->eps_x;
 }
 
-// One block per work item.
-template <bool kFusedTail, int kU, bool kEarly, bool kStage>
-__global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ P,
+// One block per work item; kWaves > 1 asks the compiler for that many
+// waves per SIMD (fewer registers, a little spilling).
+template <bool kFusedTail, int kU, bool kEarly, bool kStage, int kWaves>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))) void k_iterate(const SegPtrs *__restrict__ P,
                                                    SegState *__restrict__ S,
                                                    const WorkItem *__restrict__ W,
                                                    double *__restrict__ partials, int flags)
@@ -550,22 +590,55 @@ __global__ __launch_bounds__(kBlock) void k_iterate(const SegPtrs *__restrict__ 
     const int nrow = (int)(w.end - w.begin);
     const int32_t rp_t = t < nrow ? gload(p.rp, r0 + t) : 0;
     const int32_t rp_end = gload(p.rp, r0 + nrow);
-    item_body<kU, kEarly, kStage>(p, c, r0, nrow, rp_t, rp_end, L, scol,
-                                  reinterpret_cast<Part4 *>(partials) + b, NoHook());
+    item_body<kU, kEarly, kStage, kBlock, NoHook, kFusedTail>(
+        p, c, r0, nrow, &rp_t, rp_end, L, scol, reinterpret_cast<Part4 *>(partials) + b,
+        NoHook());
     if (kFusedTail) {
+        // the last block of the packing to finish reduces the partials and
+        // runs the tail.  Partials are written through to memory and read
+        // past the caches; the ticket is taken only after this block's
+        // partial stores have completed (no release fence: on this part a
+        // fence writes back the whole L2 of the XCD).
         __shared__ int last;
-        __threadfence();
         if (t == 0) {
-            const uint32_t prev = atomicAdd(&s->ticket, 1u);
+            __builtin_amdgcn_s_waitcnt(0);
+            const uint32_t prev = __hip_atomic_fetch_add(&s->ticket, 1u, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_SYSTEM);
             last = (prev == (uint32_t)s->nblocks - 1u);
         }
         __syncthreads();
         if (last) {
-            __threadfence();
-            reduce_and_tail<kBlock>(s, partials);
-            if (t == 0) s->ticket = 0;
+            reduce_and_tail<kBlock, true>(s, partials);
+            if (t == 0) __hip_atomic_store(&s->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         }
     }
+}
+
+// Items of up to 512 rows: two rows per thread in the Adam phase, so half as
+// many blocks carry the per-item set-up, synchronisation and reduction.
+template <int kU>
+__global__ __launch_bounds__(kBlock) void k_iterate512(const SegPtrs *__restrict__ P,
+                                                      SegState *__restrict__ S,
+                                                      const WorkItem *__restrict__ W,
+                                                      double *__restrict__ partials, int flags)
+{
+    const int b = (flags & 1) ? remap_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+    const WorkItem w = W[b];
+    SegState *s = S + w.seg;
+    if (s->flags & F_IDLE) return;
+    IterScalars c;
+    load_scalars(s, c);
+    const IterPtrs p = select_ptrs(P, w.seg, s->cur);
+    __shared__ ItemLdsR<2 * kBlock> L;
+    const int t = threadIdx.x;
+    const int64_t r0 = w.begin;
+    const int nrow = (int)(w.end - w.begin);
+    int32_t rp_own[2];
+    rp_own[0] = t < nrow ? gload(p.rp, r0 + t) : 0;
+    rp_own[1] = t + kBlock < nrow ? gload(p.rp, r0 + t + kBlock) : 0;
+    const int32_t rp_end = gload(p.rp, r0 + nrow);
+    item_body<kU, false, false, 2 * kBlock>(p, c, r0, nrow, rp_own, rp_end, L, nullptr,
+                                            reinterpret_cast<Part4 *>(partials) + b, NoHook());
 }
 
 // resident blocks of the persistent form: 256 CUs x 5 blocks (the occupancy
@@ -639,8 +712,9 @@ __global__ __launch_bounds__(kBlock) void k_iterate_persist(const SegPtrs *__res
                     have = true;
                 }
             };
-            item_body<kU, false, false>(p, c, w.begin, nrow, rp_t, rp_end, L, nullptr,
-                                        reinterpret_cast<Part4 *>(partials) + item, hook);
+            item_body<kU, false, false, kBlock>(p, c, w.begin, nrow, &rp_t, rp_end, L, nullptr,
+                                                reinterpret_cast<Part4 *>(partials) + item,
+                                                hook);
         }
         item = next;
         if (item >= hi) break;
@@ -648,12 +722,28 @@ __global__ __launch_bounds__(kBlock) void k_iterate_persist(const SegPtrs *__res
     }
 }
 
-template <bool kF, int kU, bool kE, bool kNT>
+template <bool kF, int kU, bool kE, bool kNT, int kW>
 static void launch_one(const SegPtrs *P, SegState *S, const WorkItem *W, double *partials,
                        int nitems, int f, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_iterate<kF, kU, kE, kNT>), dim3(nitems), dim3(kBlock), 0, st, P, S, W,
-                       partials, f);
+    hipLaunchKernelGGL((k_iterate<kF, kU, kE, kNT, kW>), dim3(nitems), dim3(kBlock), 0, st, P, S,
+                       W, partials, f);
+}
+
+template <bool kF, int kW>
+static void launch_basic(const SegPtrs *P, SegState *S, const WorkItem *W, double *partials,
+                         int nitems, int f, int variant, hipStream_t st)
+{
+    switch (variant & 7) {
+    case 0: launch_one<kF, 2, false, false, kW>(P, S, W, partials, nitems, f, st); break;
+    case 1: launch_one<kF, 4, false, false, kW>(P, S, W, partials, nitems, f, st); break;
+    case 2: launch_one<kF, 2, true, false, kW>(P, S, W, partials, nitems, f, st); break;
+    case 3: launch_one<kF, 4, true, false, kW>(P, S, W, partials, nitems, f, st); break;
+    case 4: launch_one<kF, 2, false, true, kW>(P, S, W, partials, nitems, f, st); break;
+    case 5: launch_one<kF, 4, false, true, kW>(P, S, W, partials, nitems, f, st); break;
+    case 6: launch_one<kF, 2, true, true, kW>(P, S, W, partials, nitems, f, st); break;
+    default: launch_one<kF, 4, true, true, kW>(P, S, W, partials, nitems, f, st); break;
+    }
 }
 
 template <bool kF>
@@ -662,7 +752,9 @@ static void launch_variant(const SegPtrs *P, SegState *S, const WorkItem *W, dou
 {
     // bit 0: four gathers in flight; bit 1: early Adam operands; bit 2:
     // partner indices staged in LDS; bit 3: persistent blocks (bits 1, 2 and
-    // the fused tail do not apply to it)
+    // the fused tail do not apply to it); bit 4: seven waves per SIMD asked
+    // of the compiler; bit 5: items of up to 512 rows (bits 1-4 and the
+    // fused tail do not apply)
     if (variant & 8) {
         const int grid = std::min(nitems, kPersistBlocks);
         if (variant & 1)
@@ -673,25 +765,26 @@ static void launch_variant(const SegPtrs *P, SegState *S, const WorkItem *W, dou
                                partials, nitems, f);
         return;
     }
-    switch (variant & 7) {
-    case 0: launch_one<kF, 2, false, false>(P, S, W, partials, nitems, f, st); break;
-    case 1: launch_one<kF, 4, false, false>(P, S, W, partials, nitems, f, st); break;
-    case 2: launch_one<kF, 2, true, false>(P, S, W, partials, nitems, f, st); break;
-    case 3: launch_one<kF, 4, true, false>(P, S, W, partials, nitems, f, st); break;
-    case 4: launch_one<kF, 2, false, true>(P, S, W, partials, nitems, f, st); break;
-    case 5: launch_one<kF, 4, false, true>(P, S, W, partials, nitems, f, st); break;
-    case 6: launch_one<kF, 2, true, true>(P, S, W, partials, nitems, f, st); break;
-    default: launch_one<kF, 4, true, true>(P, S, W, partials, nitems, f, st); break;
+    if (variant & 32) {
+        if (variant & 1)
+            hipLaunchKernelGGL(k_iterate512<4>, dim3(nitems), dim3(kBlock), 0, st, P, S, W,
+                               partials, f);
+        else
+            hipLaunchKernelGGL(k_iterate512<2>, dim3(nitems), dim3(kBlock), 0, st, P, S, W,
+                               partials, f);
+        return;
     }
+    if (variant & 16) launch_basic<kF, 7>(P, S, W, partials, nitems, f, variant, st);
+    else launch_basic<kF, 1>(P, S, W, partials, nitems, f, variant, st);
 }
 
 void launch_iterate(const SegPtrs *P, SegState *S, const WorkItem *W, double *partials,
                     int nitems, int flags, hipStream_t st)
 {
-    // bit 0: XCD-aware order; bit 1: fused tail; bits 8-11: kernel variant
+    // bit 0: XCD-aware order; bit 1: fused tail; bits 8-13: kernel variant
     // (see launch_variant)
-    const int f = flags & 1, variant = (flags >> 8) & 15;
-    if (variant & 8) launch_variant<false>(P, S, W, partials, nitems, f, variant, st);
+    const int f = flags & 1, variant = (flags >> 8) & 63;
+    if (variant & 40) launch_variant<false>(P, S, W, partials, nitems, f, variant, st);
     else if (flags & 2) launch_variant<true>(P, S, W, partials, nitems, f, variant, st);
     else launch_variant<false>(P, S, W, partials, nitems, f, variant, st);
 }

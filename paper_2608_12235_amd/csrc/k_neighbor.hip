@@ -371,12 +371,249 @@ __global__ __launch_bounds__(kBlock) void k_search(BuildArgs a, uint64_t *__rest
         if ((int64_t)gbase + k < cap) list[gbase + k] = buf[k];
 }
 
+// ------------------------------------------------ wave-cooperative search
+// The same search with the candidates of a wave flattened: for one level
+// and one stencil slot, every lane contributes the run [start, start +
+// count) of its cell (restricted to larger indices in its own level), a
+// wave prefix sum numbers the candidates, and the 64 lanes test
+// consecutive candidates together, each lane finding the candidate's owner
+// by a binary search over the prefix.  A particle's candidate set and the
+// pair test are those of k_search, so the listed pairs are the same; only
+// the order in which entries are appended differs (the list is sorted
+// afterwards).
+struct Stencil {
+    uint64_t m[3][3];    // [axis][slot]: Morton parts of the lower, own, upper cell
+    uint64_t tp[3][3];   // the same for the tile field
+    int32_t cc[3][3];    // cell coordinates (dense levels)
+    double gap[3][3];    // distance (cell units) from the particle to that slab
+    bool use[3][3];
+    double cb;           // largest cutoff with a partner of the level, in cell units
+};
+
+__device__ __forceinline__ void stencil_setup(const BuildArgs &a, const LevelGrid &g,
+                                              const double pos[3], double di, Stencil &S)
+{
+    const int32_t nc = g.nc;
+    S.cb = a.kb * (a.opg * (0.5 * (di + g.dmax)) + a.sk2) * g.inv_w * (1.0 + 1e-9) + 1e-9;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const double fp = pos[ax] * g.inv_w;
+        const int32_t c = cell_coord(pos[ax], g.inv_w, nc);
+        if (nc >= 3) {
+            const double f = fp - (double)c;
+            const int32_t lo = c == 0 ? nc - 1 : c - 1, hi = c == nc - 1 ? 0 : c + 1;
+            S.cc[ax][0] = lo;
+            S.cc[ax][1] = c;
+            S.cc[ax][2] = hi;
+            S.m[ax][0] = spread3((uint64_t)lo) << ax;
+            S.m[ax][1] = spread3((uint64_t)c) << ax;
+            S.m[ax][2] = spread3((uint64_t)hi) << ax;
+            S.tp[ax][0] = spread3(tile_of(lo, nc, a.tiles)) << ax;
+            S.tp[ax][1] = spread3(tile_of(c, nc, a.tiles)) << ax;
+            S.tp[ax][2] = spread3(tile_of(hi, nc, a.tiles)) << ax;
+            S.gap[ax][0] = f;
+            S.gap[ax][1] = 0.0;
+            S.gap[ax][2] = 1.0 - f;
+            S.use[ax][0] = f < S.cb;
+            S.use[ax][1] = true;
+            S.use[ax][2] = 1.0 - f < S.cb;
+        } else {
+            S.cc[ax][0] = 0;
+            S.cc[ax][1] = 1;
+            S.cc[ax][2] = 0;
+            S.m[ax][0] = 0;
+            S.m[ax][1] = spread3(1) << ax;
+            S.m[ax][2] = 0;
+            S.tp[ax][0] = spread3(tile_of(0, nc, a.tiles)) << ax;
+            S.tp[ax][1] = spread3(tile_of(1, nc, a.tiles)) << ax;
+            S.tp[ax][2] = 0;
+            S.gap[ax][0] = S.gap[ax][1] = S.gap[ax][2] = 0.0;
+            S.use[ax][0] = true;
+            S.use[ax][1] = nc == 2;
+            S.use[ax][2] = false;
+        }
+    }
+}
+
+// Stencil slot sl (0..26, x slowest) of a particle: whether it is searched
+// (the cell's nearest point within the cutoff bound) and its cell.
+__device__ __forceinline__ bool slot_used(const Stencil &S, int sl)
+{
+    const int ox = sl / 9, oy = (sl / 3) % 3, oz = sl % 3;
+    const double g2 = (S.gap[0][ox] * S.gap[0][ox] + S.gap[1][oy] * S.gap[1][oy]) +
+                      S.gap[2][oz] * S.gap[2][oz];
+    return S.use[0][ox] && S.use[1][oy] && S.use[2][oz] && g2 < S.cb * S.cb;
+}
+
+__device__ __forceinline__ int64_t slot_dense_index(const LevelGrid &g, const Stencil &S, int sl)
+{
+    const int ox = sl / 9, oy = (sl / 3) % 3, oz = sl % 3;
+    return ((int64_t)S.cc[0][ox] * g.nc + S.cc[1][oy]) * g.nc + S.cc[2][oz];
+}
+
+__device__ __forceinline__ uint64_t slot_key(const BuildArgs &a, const Stencil &S, uint64_t base,
+                                             int sl)
+{
+    const int ox = sl / 9, oy = (sl / 3) % 3, oz = sl % 3;
+    return base | S.m[0][ox] | S.m[1][oy] | S.m[2][oz] |
+           ((S.tp[0][ox] | S.tp[1][oy] | S.tp[2][oz]) << a.tshift);
+}
+
+// Per-block output staging of k_search_coop.
+struct SearchOut {
+    uint64_t *buf;      // LDS, kSearchBuf entries
+    uint32_t *nbuf;     // LDS counter
+    uint64_t *list;
+    uint32_t *counter;
+    int64_t cap;
+    int row_bits;
+};
+
+// Test, with the whole wave, the candidates of one stencil slot: lane t
+// contributes the run [st, st + ct) of its cell; a wave prefix sum numbers
+// the candidates and each round tests 64 consecutive ones, a lane finding
+// its candidate's owner by binary search over the prefix.  Listed pairs
+// take one LDS reservation per wave and round.
+__device__ __forceinline__ void test_slot(const BuildArgs &a, const SearchOut &out, int lane,
+                                          uint64_t below, int64_t wbase, int32_t st, int32_t ct,
+                                          double xi, double yi, double zi, double di)
+{
+    int32_t inc = ct;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int32_t u = __shfl_up(inc, o, kWave);
+        if (lane >= o) inc += u;
+    }
+    const int32_t T = __shfl(inc, kWave - 1, kWave);
+    if (T == 0) return;
+    const int32_t ex = inc - ct;
+    for (int32_t r0 = 0; r0 < T; r0 += kWave) {
+        const int32_t q = r0 + lane;
+        // owner: number of lanes whose inclusive prefix is <= q
+        int o = 0;
+#pragma unroll
+        for (int step = kWave / 2; step > 0; step >>= 1) {
+            const int32_t v = __shfl(inc, o + step - 1, kWave);
+            if (v <= q) o += step;
+        }
+        const bool has = q < T;
+        o = has ? o : 0;
+        const int32_t jst = __shfl(st, o, kWave);
+        const int32_t jex = __shfl(ex, o, kWave);
+        const double ox_ = __shfl(xi, o, kWave);
+        const double oy_ = __shfl(yi, o, kWave);
+        const double oz_ = __shfl(zi, o, kWave);
+        const double od_ = __shfl(di, o, kWave);
+        const int64_t j = (int64_t)jst + (q - jex);
+        bool hit = false;
+        if (has) {
+            const P4 qj = a.pos[j];
+            const double dx = min_image(qj.x - ox_, a.L, a.hL);
+            const double dy = min_image(qj.y - oy_, a.L, a.hL);
+            const double dz = min_image(qj.z - oz_, a.L, a.hL);
+            const double r2 = (dx * dx + dy * dy) + dz * dz;
+            const double cc = a.kb * (a.opg * (0.5 * (od_ + qj.d)) + a.sk2);
+            hit = r2 < cc * cc;
+        }
+        const uint64_t bal = __ballot(hit);
+        if (bal == 0ull) continue;
+        const int lead = __ffsll((unsigned long long)bal) - 1;
+        uint32_t k0 = 0;
+        if (lane == lead) k0 = atomicAdd(out.nbuf, 2u * (uint32_t)__popcll(bal));
+        k0 = __shfl(k0, lead, kWave);
+        if (hit) {
+            const int64_t io = wbase + o;
+            const uint64_t e0 = ((uint64_t)io << out.row_bits) | (uint64_t)j;
+            const uint64_t e1 = ((uint64_t)j << out.row_bits) | (uint64_t)io;
+            const uint32_t k = k0 + 2u * (uint32_t)__popcll(bal & below);
+            if (k + 1 < (uint32_t)kSearchBuf) {
+                out.buf[k] = e0;
+                out.buf[k + 1] = e1;
+            } else {
+                const uint32_t gi = atomicAdd(out.counter, 2u);
+                if ((int64_t)gi + 1 < out.cap) {
+                    out.list[gi] = e0;
+                    out.list[gi + 1] = e1;
+                }
+            }
+        }
+    }
+}
+
+// Restrict a cell run to sorted indices above i (a particle's own level:
+// each pair is found once; a cell's particles are one contiguous run).
+__device__ __forceinline__ int2 above(int2 r, int64_t i)
+{
+    const int64_t s2 = (int64_t)r.x > i + 1 ? (int64_t)r.x : i + 1;
+    const int64_t e = (int64_t)r.x + r.y;
+    return make_int2((int32_t)s2, e > s2 ? (int32_t)(e - s2) : 0);
+}
+
+__global__ __launch_bounds__(kBlock) void k_search_coop(BuildArgs a, uint64_t *__restrict__ list,
+                                                       uint32_t *__restrict__ counter,
+                                                       int64_t cap, int row_bits, int xcd_remap)
+{
+    __shared__ uint64_t buf[kSearchBuf];
+    __shared__ uint32_t nbuf;
+    __shared__ uint32_t gbase;
+    if (threadIdx.x == 0) nbuf = 0;
+    __syncthreads();
+    const int blk = xcd_remap ? remap_xcd((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+    const int64_t wbase = (int64_t)blk * kBlock + (threadIdx.x & ~(kWave - 1));
+    const int64_t i = wbase + lane;
+    const bool valid = i < a.n;
+    const SearchOut out{buf, &nbuf, list, counter, cap, row_bits};
+    double xi = 0.0, yi = 0.0, zi = 0.0, di = 0.0;
+    int li = kMaxLevels;
+    if (valid) {
+        const P4 qi = a.pos[i];
+        xi = qi.x;
+        yi = qi.y;
+        zi = qi.z;
+        di = qi.d;
+        li = a.lev[i];
+    }
+    for (int L = 0; L < a.nlev; ++L) {
+        const LevelGrid g = a.lv[L];
+        if (g.count == 0) continue;
+        const bool act = li <= L;
+        if (__ballot(act) == 0ull) continue;
+        Stencil S;
+        const double pos[3] = {xi, yi, zi};
+        stencil_setup(a, g, pos, di, S);
+        const bool same = L == li;
+        const uint64_t base = (uint64_t)L << a.mb;
+#pragma unroll
+        for (int sl = 0; sl < 27; ++sl) {
+            int2 r = make_int2(0, 0);
+            if (act && slot_used(S, sl))
+                r = g.dbase >= 0 ? a.dense[g.dbase + slot_dense_index(g, S, sl)]
+                                 : hash_find(a, slot_key(a, S, base, sl));
+            if (same) r = above(r, i);
+            test_slot(a, out, lane, below, wbase, r.x, r.y, xi, yi, zi, di);
+        }
+    }
+    __syncthreads();
+    const uint32_t mm = nbuf < (uint32_t)kSearchBuf ? nbuf : (uint32_t)kSearchBuf;
+    if (threadIdx.x == 0) gbase = mm ? atomicAdd(counter, mm) : 0u;
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < mm; k += kBlock)
+        if ((int64_t)gbase + k < cap) list[gbase + k] = buf[k];
+}
+
 void launch_search(const BuildArgs &a, uint64_t *list, uint32_t *counter, int64_t cap,
-                   int row_bits, int xcd_remap, hipStream_t s)
+                   int row_bits, int xcd_remap, int coop, hipStream_t s)
 {
     if (a.n <= 0) return;
-    hipLaunchKernelGGL(k_search, dim3((unsigned)((a.n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                       s, a, list, counter, cap, row_bits, xcd_remap);
+    const dim3 grid((unsigned)((a.n + kBlock - 1) / kBlock));
+    if (coop)
+        hipLaunchKernelGGL(k_search_coop, grid, dim3(kBlock), 0, s, a, list, counter, cap,
+                           row_bits, xcd_remap);
+    else
+        hipLaunchKernelGGL(k_search, grid, dim3(kBlock), 0, s, a, list, counter, cap, row_bits,
+                           xcd_remap);
 }
 
 // Row pointers and partners from the sorted entry list.  Entry q starts row

@@ -101,12 +101,62 @@ __global__ void k_write_total(uint32_t *__restrict__ out, int64_t n,
     out[n] = *total;
 }
 
+// One block of 1024 threads scans up to kScanSingle values in rounds of
+// 8192 (8 consecutive values a thread), so a short scan is one launch.
+constexpr int kScanThreads = 1024;
+constexpr int64_t kScanSingle = 32768;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_single(const uint32_t *__restrict__ in,
+                                                             uint32_t *__restrict__ out,
+                                                             int64_t n,
+                                                             uint32_t *__restrict__ total)
+{
+    constexpr int kW = kScanThreads / kWave;
+    __shared__ uint32_t ws[kW];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < n; base += 8 * kScanThreads) {
+        const int64_t i0 = base + (int64_t)threadIdx.x * 8;
+        uint32_t v[8], sum = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            v[k] = (i0 + k < n) ? in[i0 + k] : 0u;
+            sum += v[k];
+        }
+        uint32_t inc = sum;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const uint32_t u = __shfl_up(inc, o, kWave);
+            if (lane >= o) inc += u;
+        }
+        if (lane == kWave - 1) ws[w] = inc;
+        __syncthreads();
+        uint32_t off = 0, tot = 0;
+        for (int q = 0; q < kW; ++q) {
+            if (q < w) off += ws[q];
+            tot += ws[q];
+        }
+        __syncthreads();   // ws is rewritten in the next round
+        uint32_t run = carry + off + inc - sum;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (i0 + k < n) out[i0 + k] = run;
+            run += v[k];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        out[n] = carry;
+        if (total) *total = carry;
+    }
+}
+
 void scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tile_tmp,
                     uint32_t *total, hipStream_t s)
 {
-    if (n <= 0) {
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, tile_tmp, (int64_t)0, total);
-        hipLaunchKernelGGL(k_write_total, dim3(1), dim3(1), 0, s, out, (int64_t)0, total);
+    if (n <= kScanSingle) {
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kScanThreads), 0, s, in, out,
+                           n < 0 ? (int64_t)0 : n, total);
         return;
     }
     const int64_t nt = (n + kTile - 1) / kTile;

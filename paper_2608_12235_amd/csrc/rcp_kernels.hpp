@@ -70,9 +70,10 @@ void launch_hash_build(const BuildArgs &a, int64_t cap, int64_t ndense, hipStrea
 // One pass over the particles: every listed pair (i, j) is appended twice
 // to `list` as (row << row_bits) | col, rows and cols in sorted order, in an
 // arbitrary order; *counter (zeroed by the caller) receives the number of
-// entries, which may exceed cap (then only cap were stored).
+// entries, which may exceed cap (then only cap were stored).  coop selects
+// the wave-cooperative form (same pairs, other append order).
 void launch_search(const BuildArgs &a, uint64_t *list, uint32_t *counter, int64_t cap,
-                   int row_bits, int xcd_remap, hipStream_t s);
+                   int row_bits, int xcd_remap, int coop, hipStream_t s);
 // Full rows from the sorted entry list: rp[0..n] and col[0..m).
 void launch_csr_from_sorted(const uint64_t *sorted, int64_t m, int row_bits, int64_t n,
                             int32_t *rp, int32_t *col, hipStream_t s);

@@ -113,6 +113,26 @@ struct Seg {
     bool built = false;
 };
 
+// Scratch of one list build in flight (sort buffers, cell tables) and the
+// stream it is queued on.
+struct BuildLane {
+    hipStream_t st = nullptr;
+    bool own = false;
+    hipEvent_t ev = nullptr;
+    uint64_t *kA = nullptr, *kB = nullptr;
+    uint32_t *vA = nullptr, *vB = nullptr;
+    int64_t kcap = 0, kcapB = 0, vcap = 0, vcapB = 0;
+    uint32_t *hist = nullptr, *tiles = nullptr, *totals = nullptr;
+    int64_t hist_cap = 0, tiles_cap = 0, totals_cap = 0;
+    HashSlot *hash = nullptr;
+    int64_t hcap = 0;
+    int2 *dense = nullptr;           // dense cell tables
+    int64_t dense_cap = 0;
+    int64_t load = 0;                // particles assigned in the current batch
+};
+
+constexpr int kBuildLanes = 4;
+
 struct rcp_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -126,16 +146,17 @@ struct rcp_ctx {
     int nitems = 0;
     int64_t items_cap = 0;
     double *d_partials = nullptr;
-    // build scratch, shared by all segments
-    uint64_t *kA = nullptr, *kB = nullptr;
-    uint32_t *vA = nullptr, *vB = nullptr;
-    int64_t kcap = 0, kcapB = 0, vcap = 0, vcapB = 0;
-    uint32_t *hist = nullptr, *tiles = nullptr, *totals = nullptr;
-    int64_t hist_cap = 0, tiles_cap = 0;
-    HashSlot *hash = nullptr;
-    int64_t hcap = 0;
-    int2 *dense = nullptr;           // dense cell tables
-    int64_t dense_cap = 0;
+    uint32_t *totals = nullptr;      // small device counters
+    // list builds: lane 0 runs on the context's stream, further lanes (for
+    // builds of several packings at once) on streams of their own
+    std::vector<BuildLane> lanes;
+    hipEvent_t fork_ev = nullptr;
+    uint64_t *larena = nullptr;      // list regions of the builds in flight
+    int64_t larena_cap = 0;
+    uint32_t *bcount = nullptr;      // their entry counts (device, pinned host)
+    int64_t bcount_cap = 0;
+    uint32_t *h_bcount = nullptr;
+    int64_t h_bcount_cap = 0;
     double *part = nullptr;          // evaluation partials
     int64_t part_cap = 0;
     double *out = nullptr;           // small device results
@@ -168,11 +189,11 @@ static void ptrs_of(const Seg &s, SegPtrs &p)
     p.col = s.col;
 }
 
-static int upload_ptrs(rcp_ctx *c, int k)
+static int upload_ptrs(rcp_ctx *c, int k, hipStream_t st)
 {
     SegPtrs p;
     ptrs_of(c->segs[k], p);
-    launch_put_ptrs(c->d_ptrs, k, p, c->stream);   // in stream order, no sync
+    launch_put_ptrs(c->d_ptrs, k, p, st);   // in stream order, no sync
     HIPCHK(hipGetLastError());
     return RCP_OK;
 }
@@ -231,12 +252,12 @@ static int64_t slots_for(const rcp_ctx *c, int64_t n, int64_t entries)
 
 // Cut the rows of a built packing into work items (device kernel on its
 // row pointers); items of an unbuilt packing are left empty.
-static void fill_items(rcp_ctx *c, int k)
+static void fill_items(rcp_ctx *c, int k, hipStream_t st)
 {
     Seg &s = c->segs[k];
     WorkItem *w = c->d_work + s.first_item;
     launch_items(s.built ? s.rp : nullptr, s.n, k, c->tuning.row_cost, c->tuning.item_work, w,
-                 s.blocks, c->stream);
+                 s.blocks, st);
 }
 
 // Lay out the work-item slots of all packings (a graph captured before is
@@ -267,7 +288,7 @@ static int build_work(rcp_ctx *c)
         Seg &s = c->segs[k];
         CHK(put_field(c, (int)k, offsetof(SegState, nblocks), (int32_t)s.blocks));
         CHK(put_field(c, (int)k, offsetof(SegState, bfirst), s.first_item));
-        fill_items(c, (int)k);
+        fill_items(c, (int)k, c->stream);
     }
     HIPCHK(hipStreamSynchronize(c->stream));
     c->graph_valid = false;
@@ -285,11 +306,28 @@ static int bits_for(int64_t v)   // bits needed to hold values 0..v
     return b;
 }
 
-// Build the list of segment k at its current positions with kb = kappa.
-static int rebuild(rcp_ctx *c, int k, double kappa)
+// A list build is split at its one host round trip, the entry count of the
+// search: the front half (keys, sort, permutation, cell tables, search into
+// the packing's region of the list arena) of every packing that needs a
+// build is queued, the counts come back in one copy, and the back halves
+// (entry sort, rows, work items) follow.  Builds are spread over up to
+// kBuildLanes streams, each with its own sort buffers and cell tables, so
+// the builds of small packings run side by side.
+struct BuildJob {
+    int k = 0;
+    int lane = 0;
+    double kappa = 0.0;
+    BuildArgs a;
+    int nbits = 0, row_bits = 0;
+    int64_t ndense = 0, hcap = 0;
+    int64_t lcap = 0, loff = 0;   // list region: entries and offset in the arena
+};
+
+// Host arithmetic of a build of packing k at kb = kappa: grid levels, key
+// layout, dense / hashed levels, list capacity (at least min_entries).
+static int build_plan(rcp_ctx *c, int k, double kappa, int64_t min_entries, BuildJob &j)
 {
-    Seg &s = c->segs[k];
-    hipStream_t st = c->stream;
+    const Seg &s = c->segs[k];
     const int64_t n = s.n;
     const double g = c->params.skin_g, sk = c->params.skin_s;
     const double opg = 1.0 + g, sk2 = (2.0 * sk) * s.d0min;
@@ -298,11 +336,9 @@ static int rebuild(rcp_ctx *c, int k, double kappa)
     if (!(cmax < 0.5 * s.L))
         return fail(RCP_EBOX, "packing %d: listing cutoff %.17g is not below L/2 = %.17g", k,
                     cmax, 0.5 * s.L);
-    std::pair<hipEvent_t, hipEvent_t> ev;
-    CHK(rebuild_events(c, ev));
-    HIPCHK(hipEventRecord(ev.first, st));
-
-    BuildArgs a;
+    j.k = k;
+    j.kappa = kappa;
+    BuildArgs &a = j.a;
     std::memset(&a, 0, sizeof a);
     a.n = n;
     a.nlev = s.nlev;
@@ -330,50 +366,113 @@ static int rebuild(rcp_ctx *c, int k, double kappa)
     a.tshift = a.mb + lb;
     a.tiles = (a.tshift + 6 <= 63) ? 4 : ((a.tshift + 3 <= 63) ? 2 : 1);
     const int tbits = a.tiles == 4 ? 6 : (a.tiles == 2 ? 3 : 0);
-    const int nbits = a.tshift + tbits;
-
-    // scratch sized for the particle count and the expected pair-list length
-    const int row_bits = std::max(1, bits_for(n - 1));
-    int64_t lcap = std::max<int64_t>({n, s.list_est + s.list_est / 4, 8 * n, 1024});
-    CHK(dgrow(&c->kA, &c->kcap, lcap));
-    CHK(dgrow(&c->kB, &c->kcapB, lcap));
-    lcap = std::min(c->kcap, c->kcapB);
-    CHK(dgrow(&c->vA, &c->vcap, n));
-    CHK(dgrow(&c->vB, &c->vcapB, n));
-    const int64_t tiles = (lcap + 2047) / 2048 + 1;
-    CHK(dgrow(&c->hist, &c->hist_cap, 256 * tiles + 1));
-    CHK(dgrow(&c->tiles, &c->tiles_cap, 256 * tiles + 1));
+    j.nbits = a.tshift + tbits;
+    j.row_bits = std::max(1, bits_for(n - 1));
     // levels whose grid fits a budget of 8 cells a particle get a dense
     // (start, count) table, looked up without hashing; the rest are hashed
-    int64_t ndense = 0;
+    j.ndense = 0;
     const int64_t dense_budget = 8 * n + 65536;
     int64_t nhashed = 0;
     for (int l = 0; l < s.nlev; ++l) {
         const int64_t nc = a.lv[l].nc, cells = nc * nc * nc;
-        if (a.lv[l].count > 0 && ndense + cells <= dense_budget) {
-            a.lv[l].dbase = ndense;
-            ndense += cells;
+        if (a.lv[l].count > 0 && j.ndense + cells <= dense_budget) {
+            a.lv[l].dbase = j.ndense;
+            j.ndense += cells;
         } else {
             nhashed += a.lv[l].count;
         }
     }
-    if (ndense > 0) CHK(dgrow(&c->dense, &c->dense_cap, ndense));
-    int64_t hcap = 64;
-    while (hcap < 2 * nhashed) hcap <<= 1;
-    CHK(dgrow(&c->hash, &c->hcap, hcap));
+    j.hcap = 64;
+    while (j.hcap < 2 * nhashed) j.hcap <<= 1;
+    // the expected list length with room to spare
+    j.lcap = std::max<int64_t>({s.list_est + s.list_est / 4, 8 * n, 1024, min_entries});
+    return RCP_OK;
+}
 
-    // 1. keys at the current positions, stable sort, permutation
+// Lanes 0..nl-1 exist (lane 0 is the context's stream).
+static int ensure_lanes(rcp_ctx *c, int nl)
+{
+    if (!c->fork_ev) HIPCHK(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+    while ((int)c->lanes.size() < nl) {
+        BuildLane L;
+        if (c->lanes.empty()) {
+            L.st = c->stream;
+        } else {
+            HIPCHK(hipStreamCreateWithFlags(&L.st, hipStreamNonBlocking));
+            L.own = true;
+        }
+        const hipError_t e = hipEventCreateWithFlags(&L.ev, hipEventDisableTiming);
+        c->lanes.push_back(L);
+        HIPCHK(e);
+    }
+    return RCP_OK;
+}
+
+// Grow each lane's scratch for the builds assigned to it and the list
+// arena for all of them (their streams are idle: buffers may be
+// reallocated).
+static int build_grow(rcp_ctx *c, std::vector<BuildJob> &jobs, int nl)
+{
+    int64_t ltot = 0;
+    for (auto &j : jobs) {
+        j.loff = ltot;
+        ltot += j.lcap;
+    }
+    for (int l = 0; l < nl; ++l) {
+        BuildLane &L = c->lanes[l];
+        int64_t nmax = 0, lmax = 0, dmax = 0, hmax = 64;
+        for (auto &j : jobs) {
+            if (j.lane != l) continue;
+            nmax = std::max(nmax, j.a.n);
+            lmax = std::max(lmax, j.lcap);
+            dmax = std::max(dmax, j.ndense);
+            hmax = std::max(hmax, j.hcap);
+        }
+        // kA: Morton keys, then the second buffer of the entry sort; kB: keys
+        CHK(dgrow(&L.kA, &L.kcap, std::max(nmax, lmax)));
+        CHK(dgrow(&L.kB, &L.kcapB, nmax));
+        CHK(dgrow(&L.vA, &L.vcap, nmax));
+        CHK(dgrow(&L.vB, &L.vcapB, nmax));
+        const int64_t tiles = (std::max(nmax, lmax) + 2047) / 2048 + 1;
+        CHK(dgrow(&L.hist, &L.hist_cap, 256 * tiles + 1));
+        CHK(dgrow(&L.tiles, &L.tiles_cap, 256 * tiles + 1));
+        CHK(dgrow(&L.totals, &L.totals_cap, 16));
+        if (dmax > 0) CHK(dgrow(&L.dense, &L.dense_cap, dmax));
+        CHK(dgrow(&L.hash, &L.hcap, hmax));
+    }
+    CHK(dgrow(&c->larena, &c->larena_cap, ltot));
+    CHK(dgrow(&c->bcount, &c->bcount_cap, (int64_t)jobs.size()));
+    if ((int64_t)jobs.size() > c->h_bcount_cap) {
+        if (c->h_bcount) (void)hipHostFree(c->h_bcount);
+        c->h_bcount = nullptr;
+        c->h_bcount_cap = 0;
+        const int64_t cap = std::max<int64_t>(64, 2 * (int64_t)jobs.size());
+        const hipError_t e = hipHostMalloc((void **)&c->h_bcount, sizeof(uint32_t) * cap, 0);
+        if (e != hipSuccess) return fail(RCP_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+        c->h_bcount_cap = cap;
+    }
+    return RCP_OK;
+}
+
+// Front half of a build: keys at the current positions, stable sort,
+// permutation of every per-particle array, cell tables, and one search pass
+// appending every pair in both directions to the job's list region; the
+// entry count goes to *counter.
+static void build_front(rcp_ctx *c, BuildJob &j, uint32_t *counter)
+{
+    Seg &s = c->segs[j.k];
+    BuildLane &B = c->lanes[j.lane];
+    hipStream_t st = B.st;
+    BuildArgs &a = j.a;
+    const int64_t n = s.n;
     const int cur = s.cur, ncur = cur ^ 1, set = s.set, nset = set ^ 1;
     a.pos = s.Q[cur];
     a.lev = s.LEV[set];
-    launch_keys(a, c->kA, c->vA, st);
-    const int par = radix_sort(c->kA, c->vA, c->kB, c->vB, n, nbits, c->hist, c->tiles,
-                               c->totals, st);
-    const uint64_t *skey = par ? c->kB : c->kA;
-    const uint32_t *perm = par ? c->vB : c->vA;
+    launch_keys(a, B.kA, B.vA, st);
+    const int par = radix_sort(B.kA, B.vA, B.kB, B.vB, n, j.nbits, B.hist, B.tiles, B.totals, st);
     PermArgs pa;
     pa.n = n;
-    pa.perm = perm;
+    pa.perm = par ? B.vB : B.vA;
     pa.ps = s.Q[cur];
     pa.pd = s.Q[ncur];
     for (int ax = 0; ax < 3; ++ax) {
@@ -390,73 +489,164 @@ static int rebuild(rcp_ctx *c, int k, double kappa)
     launch_permute(pa, st);
     s.set = nset;
     s.cur = ncur;
-
-    // 2. occupied-cell hash on the sorted keys
     a.pos = s.Q[ncur];
     a.lev = s.LEV[nset];
-    a.skey = skey;
-    a.hash = c->hash;
-    a.hmask = (uint64_t)hcap - 1;
-    a.dense = c->dense;
-    launch_hash_build(a, hcap, ndense, st);
+    a.skey = par ? B.kB : B.kA;
+    a.hash = B.hash;
+    a.hmask = (uint64_t)j.hcap - 1;
+    a.dense = B.dense;
+    launch_hash_build(a, j.hcap, j.ndense, st);
+    launch_fill_u32(counter, 1, 0u, st);
+    launch_search(a, c->larena + j.loff, counter, j.lcap, j.row_bits, c->tuning.xcd_remap,
+                  (c->tuning.variant >> 6) & 1, st);
+}
 
-    // 3. one search pass appends every pair in both directions; the list
-    //    lives in whichever key buffer the Morton keys do not occupy
-    uint64_t *list = par ? c->kA : c->kB;
-    uint64_t *other = par ? c->kB : c->kA;
-    uint32_t total = 0;
-    for (int attempt = 0;; ++attempt) {
-        launch_fill_u32(c->totals + 2, 1, 0u, st);
-        launch_search(a, list, c->totals + 2, lcap, row_bits, c->tuning.xcd_remap, st);
-        HIPCHK(hipMemcpyAsync(&total, c->totals + 2, sizeof total, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if ((int64_t)total <= lcap) break;
-        if (attempt > 0) return fail(RCP_ENOMEM, "pair list overflow after regrowth");
-        // grow both key buffers (the Morton keys in `other` are no longer needed
-        // once the hash is built) and search again
-        const bool list_is_A = (list == c->kA);
-        CHK(dgrow(&c->kA, &c->kcap, (int64_t)total));
-        CHK(dgrow(&c->kB, &c->kcapB, (int64_t)total));
-        lcap = std::min(c->kcap, c->kcapB);
-        const int64_t t2 = (lcap + 2047) / 2048 + 1;
-        CHK(dgrow(&c->hist, &c->hist_cap, 256 * t2 + 1));
-        CHK(dgrow(&c->tiles, &c->tiles_cap, 256 * t2 + 1));
-        list = list_is_A ? c->kA : c->kB;
-        other = list_is_A ? c->kB : c->kA;
-    }
-    const int64_t m = total;
-    const int64_t P = m / 2;
+// Back half, m entries in the job's list region: sort them by (row, col)
+// into full rows with partners ascending, row pointers and columns, work
+// items (*relayout when the packing's slots are too few: the caller lays
+// out the work table again), validity limits.
+static int build_back(rcp_ctx *c, BuildJob &j, int64_t m, bool *relayout)
+{
+    Seg &s = c->segs[j.k];
+    BuildLane &B = c->lanes[j.lane];
+    hipStream_t st = B.st;
+    const int64_t n = s.n;
+    uint64_t *list = c->larena + j.loff;
     s.list_est = m;
-
-    // 4. sort the entries by (row, col): full rows, partners ascending
-    const int lp = radix_sort_keys(list, other, m, 2 * row_bits, c->hist, c->tiles, c->totals,
-                                   st);
-    const uint64_t *sorted = lp ? other : list;
-    if (m > s.col_cap) {
-        dfree(s.col);
-        s.col_cap = std::max<int64_t>(m + m / 4, 1024);
-        CHK(dalloc(&s.col, (size_t)s.col_cap));
-    }
-    launch_csr_from_sorted(sorted, m, row_bits, n, s.rp, s.col, st);
+    const int lp = radix_sort_keys(list, B.kA, m, 2 * j.row_bits, B.hist, B.tiles, B.totals, st);
+    launch_csr_from_sorted(lp ? B.kA : list, m, j.row_bits, n, s.rp, s.col, st);
     s.built = true;
     if (slots_for(c, n, m) > s.blocks) {
         s.slot_entries = m + m / 4;
-        CHK(build_work(c));
+        *relayout = true;
     } else {
-        fill_items(c, k);
+        fill_items(c, j.k, st);
     }
-
-    const double lim = sk * kappa * s.d0min * (1.0 - 1e-9);
-    launch_after_build(c->d_state, k, kappa, lim, opg * kappa * (1.0 - 1e-12), ncur, st);
-    HIPCHK(hipEventRecord(ev.second, st));
-    c->rb_pending.push_back(ev);
-    c->stats.rebuilds += 1;
-    s.npairs = P;
-    s.nnz = 2 * P;
+    const double sk = c->params.skin_s, opg = 1.0 + c->params.skin_g;
+    const double lim = sk * j.kappa * s.d0min * (1.0 - 1e-9);
+    launch_after_build(c->d_state, j.k, j.kappa, lim, opg * j.kappa * (1.0 - 1e-12), s.cur, st);
+    s.npairs = m / 2;
+    s.nnz = m;
     s.rebuilds += 1;
-    s.built = true;
-    CHK(upload_ptrs(c, k));
+    c->stats.rebuilds += 1;
+    CHK(upload_ptrs(c, j.k, st));
     return RCP_OK;
+}
+
+// Make the context's stream wait for lanes 1..nl-1.
+static int join_lanes(rcp_ctx *c, int nl)
+{
+    for (int l = 1; l < nl; ++l) {
+        HIPCHK(hipEventRecord(c->lanes[l].ev, c->lanes[l].st));
+        HIPCHK(hipStreamWaitEvent(c->stream, c->lanes[l].ev, 0));
+    }
+    return RCP_OK;
+}
+
+// Build the lists of packings ks[i] at kb = kappas[i], sharing one host
+// round trip.  rcs[i] receives each packing's status (RCP_EBOX leaves that
+// packing untouched); the return value is the first error that is not a
+// per-packing RCP_EBOX.
+static int rebuild_batch(rcp_ctx *c, const std::vector<int> &ks, const std::vector<double> &kappas,
+                         std::vector<int> &rcs)
+{
+    rcs.assign(ks.size(), RCP_OK);
+    std::vector<BuildJob> jobs;
+    for (size_t i = 0; i < ks.size(); ++i) {
+        BuildJob j;
+        const int rc = build_plan(c, ks[i], kappas[i], 0, j);
+        if (rc == RCP_EBOX) {
+            rcs[i] = rc;
+            continue;
+        }
+        CHK(rc);
+        jobs.push_back(j);
+    }
+    if (jobs.empty()) return RCP_OK;
+    // lanes: largest packings first, each to the least loaded lane
+    const int nl = (int)std::min<size_t>(kBuildLanes, jobs.size());
+    CHK(ensure_lanes(c, nl));
+    std::vector<int> order(jobs.size());
+    for (size_t q = 0; q < jobs.size(); ++q) order[q] = (int)q;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return jobs[x].a.n > jobs[y].a.n; });
+    for (int l = 0; l < nl; ++l) c->lanes[l].load = 0;
+    for (int q : order) {
+        int best = 0;
+        for (int l = 1; l < nl; ++l)
+            if (c->lanes[l].load < c->lanes[best].load) best = l;
+        jobs[q].lane = best;
+        c->lanes[best].load += jobs[q].a.n;
+    }
+    CHK(build_grow(c, jobs, nl));
+    std::pair<hipEvent_t, hipEvent_t> ev;
+    CHK(rebuild_events(c, ev));
+    HIPCHK(hipEventRecord(ev.first, c->stream));
+    if (nl > 1) {
+        HIPCHK(hipEventRecord(c->fork_ev, c->stream));
+        for (int l = 1; l < nl; ++l) HIPCHK(hipStreamWaitEvent(c->lanes[l].st, c->fork_ev, 0));
+    }
+    for (int q : order) build_front(c, jobs[q], c->bcount + q);
+    CHK(join_lanes(c, nl));
+    HIPCHK(hipMemcpyAsync(c->h_bcount, c->bcount, sizeof(uint32_t) * jobs.size(),
+                          hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipGetLastError());
+    // columns sized before any back half is queued
+    std::vector<int64_t> ms(jobs.size());
+    std::vector<int> redo;
+    for (size_t q = 0; q < jobs.size(); ++q) {
+        ms[q] = (int64_t)c->h_bcount[q];
+        if (ms[q] > jobs[q].lcap) {
+            redo.push_back((int)q);
+            continue;
+        }
+        Seg &s = c->segs[jobs[q].k];
+        if (ms[q] > s.col_cap) {
+            dfree(s.col);
+            s.col_cap = std::max<int64_t>(ms[q] + ms[q] / 4, 1024);
+            CHK(dalloc(&s.col, (size_t)s.col_cap));
+        }
+    }
+    bool relayout = false;
+    for (int q : order)
+        if (ms[q] <= jobs[q].lcap) CHK(build_back(c, jobs[q], ms[q], &relayout));
+    CHK(join_lanes(c, nl));
+    // a list that outgrew its region is built again on its own, sized for
+    // the count just seen (its particles are already in list order, so the
+    // second sort keeps that order and the list is the same)
+    for (int q : redo) {
+        std::vector<BuildJob> one(1);
+        CHK(build_plan(c, jobs[q].k, jobs[q].kappa, ms[q], one[0]));
+        one[0].lane = 0;
+        HIPCHK(hipStreamSynchronize(c->stream));
+        CHK(build_grow(c, one, 1));
+        build_front(c, one[0], c->bcount);
+        HIPCHK(hipMemcpyAsync(c->h_bcount, c->bcount, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                              c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        const int64_t m = (int64_t)c->h_bcount[0];
+        if (m > one[0].lcap) return fail(RCP_ENOMEM, "pair list overflow after regrowth");
+        Seg &s = c->segs[jobs[q].k];
+        if (m > s.col_cap) {
+            dfree(s.col);
+            s.col_cap = std::max<int64_t>(m + m / 4, 1024);
+            CHK(dalloc(&s.col, (size_t)s.col_cap));
+        }
+        CHK(build_back(c, one[0], m, &relayout));
+    }
+    HIPCHK(hipEventRecord(ev.second, c->stream));
+    c->rb_pending.push_back(ev);
+    if (relayout) CHK(build_work(c));
+    return RCP_OK;
+}
+
+// Build the list of segment k at its current positions with kb = kappa.
+static int rebuild(rcp_ctx *c, int k, double kappa)
+{
+    std::vector<int> rcs;
+    CHK(rebuild_batch(c, {k}, {kappa}, rcs));
+    return rcs[0];
 }
 
 // ------------------------------------------------------------ iteration loop
@@ -499,7 +689,7 @@ static bool slot_timed(const rcp_ctx *c, int64_t slot)
 static int launch_one_iteration(rcp_ctx *c, int slot)
 {
     const int flags = (c->tuning.xcd_remap ? 1 : 0) | (c->tuning.fused_tail ? 2 : 0) |
-                      ((c->tuning.variant & 15) << 8);
+                      ((c->tuning.variant & 63) << 8);
     const bool timed = slot_timed(c, slot) && 3 * slot + 2 < (int)c->kev.size();
     if (timed) CHK(record_event(c, c->kev[3 * slot]));
     launch_iterate(c->d_ptrs, c->d_state, c->d_work, c->d_partials, c->nitems, flags, c->stream);
@@ -572,23 +762,35 @@ static int run_loop(rcp_ctx *c)
     CHK(pull_state(c));
     for (;;) {
         bool any = false;
+        std::vector<int> ks;
+        std::vector<double> kap;
         for (size_t k = 0; k < c->segs.size(); ++k) {
             const int32_t f = c->h_state[k].flags;
             if (seg_done(f)) continue;
             if (f & (F_REBUILD | F_STALE)) {
-                const int rc = rebuild(c, (int)k, c->h_state[k].kappa);
-                if (rc == RCP_EBOX && c->segs.size() > 1) {
-                    // one packing outgrew its box: stop it, let the others run
-                    c->segs[k].err = rc;
-                    launch_set_flags(c->d_state, (int)k, 0, F_ABORT, c->stream);
-                    c->h_state[k].flags |= F_ABORT;
-                    continue;
-                }
-                CHK(rc);
+                ks.push_back((int)k);
+                kap.push_back(c->h_state[k].kappa);
             }
             any = true;
         }
         if (!any) break;
+        if (!ks.empty()) {
+            std::vector<int> rcs;
+            CHK(rebuild_batch(c, ks, kap, rcs));
+            for (size_t i = 0; i < ks.size(); ++i) {
+                if (rcs[i] == RCP_OK) continue;
+                if (c->segs.size() == 1) return rcs[i];
+                // one packing outgrew its box: stop it, let the others run
+                const int k = ks[i];
+                c->segs[k].err = rcs[i];
+                launch_set_flags(c->d_state, k, 0, F_ABORT, c->stream);
+                c->h_state[k].flags |= F_ABORT;
+            }
+            any = false;
+            for (size_t k = 0; k < c->segs.size(); ++k)
+                if (!seg_done(c->h_state[k].flags)) any = true;
+            if (!any) break;
+        }
         int64_t before = 0;
         for (size_t k = 0; k < c->segs.size(); ++k) before += c->h_state[k].iters;
         if (c->tuning.time_kernels) CHK(ensure_kernel_events(c, K));
@@ -862,15 +1064,26 @@ static void destroy_ctx(rcp_ctx *c)
     dfree(c->d_state);
     dfree(c->d_work);
     dfree(c->d_partials);
-    dfree(c->kA);
-    dfree(c->kB);
-    dfree(c->vA);
-    dfree(c->vB);
-    dfree(c->hist);
-    dfree(c->tiles);
+    for (auto &L : c->lanes) {
+        if (L.own && L.st) (void)hipStreamSynchronize(L.st);
+        dfree(L.kA);
+        dfree(L.kB);
+        dfree(L.vA);
+        dfree(L.vB);
+        dfree(L.hist);
+        dfree(L.tiles);
+        dfree(L.totals);
+        dfree(L.hash);
+        dfree(L.dense);
+        if (L.ev) (void)hipEventDestroy(L.ev);
+        if (L.own && L.st) (void)hipStreamDestroy(L.st);
+    }
+    c->lanes.clear();
+    if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
     dfree(c->totals);
-    dfree(c->hash);
-    dfree(c->dense);
+    dfree(c->larena);
+    dfree(c->bcount);
+    if (c->h_bcount) (void)hipHostFree(c->h_bcount);
     dfree(c->part);
     dfree(c->out);
     dfree(c->xtmp);
@@ -918,7 +1131,7 @@ void rcp_tuning_default(rcp_tuning *t)
     t->graph_iters = 16;
     t->xcd_remap = 1;
     t->fused_tail = 0;
-    t->variant = 0;
+    t->variant = 64;   // cooperative pair search
     t->row_cost = 16;
     t->item_work = 4096;
     t->time_kernels = 0;
@@ -1061,9 +1274,10 @@ int rcp_set_skin(rcp_ctx *c, double skin_s, double skin_g)
 int rcp_set_tuning(rcp_ctx *c, const rcp_tuning *t)
 {
     if (!c || !t || t->size != sizeof(rcp_tuning)) return fail(RCP_EINVAL, "bad tuning");
-    if (t->graph_iters < 1 || t->graph_iters > 4096 || t->variant < 0 || t->variant > 15 ||
+    const int64_t max_rows = (t->variant & 32) ? 2 * kBlock : kBlock;
+    if (t->graph_iters < 1 || t->graph_iters > 4096 || t->variant < 0 || t->variant > 127 ||
         t->row_cost < 1 || t->row_cost > 65536 || t->item_work < 1 ||
-        (int64_t)t->item_work > (int64_t)kBlock * t->row_cost)
+        (int64_t)t->item_work > max_rows * t->row_cost)
         return fail(RCP_EINVAL, "bad tuning values");
     if (t->time_kernels < 0 || t->time_kernels > 2) return fail(RCP_EINVAL, "bad tuning values");
     const bool relayout = t->row_cost != c->tuning.row_cost || t->item_work != c->tuning.item_work;
@@ -1458,17 +1672,29 @@ int rcp_time_iterations(rcp_ctx *c, int64_t n_iters, double *iterate_us, double 
     int64_t n_done = 0;
     int rc = RCP_OK;
     const int flags = (c->tuning.xcd_remap ? 1 : 0) |
-                      ((c->tuning.variant & 15) << 8);
+                      ((c->tuning.variant & 63) << 8);
     for (;;) {
         if ((rc = pull_state(c)) != RCP_OK) break;
         bool any = false;
-        for (int k = 0; k < ns && rc == RCP_OK; ++k) {
+        std::vector<int> ks;
+        std::vector<double> kap;
+        for (int k = 0; k < ns; ++k) {
             const int32_t f = c->h_state[k].flags;
             if (seg_done(f)) continue;
-            if (f & (F_REBUILD | F_STALE)) rc = rebuild(c, k, c->h_state[k].kappa);
+            if (f & (F_REBUILD | F_STALE)) {
+                ks.push_back(k);
+                kap.push_back(c->h_state[k].kappa);
+            }
             any = true;
         }
-        if (rc != RCP_OK || !any) break;
+        if (!any) break;
+        if (!ks.empty()) {
+            std::vector<int> rcs;
+            if ((rc = rebuild_batch(c, ks, kap, rcs)) != RCP_OK) break;
+            for (int r : rcs)
+                if (r != RCP_OK) rc = r;
+            if (rc != RCP_OK) break;
+        }
         if ((rc = pull_state(c)) != RCP_OK) break;
         int64_t before = 0;
         for (int k = 0; k < ns; ++k) before += c->h_state[k].iters;

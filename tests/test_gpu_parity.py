@@ -92,10 +92,12 @@ PAIR_CASES = [
 
 @pytest.mark.parametrize("fam,S,phi,kb,s,g", PAIR_CASES)
 @pytest.mark.parametrize("n", [4096, 2049])
-def test_pairs_bit_exact_random(rcp, orc, fam, S, phi, kb, s, g, n):
+@pytest.mark.parametrize("search", [0, 64])
+def test_pairs_bit_exact_random(rcp, orc, fam, S, phi, kb, s, g, n, search):
     w = ri.small_polydisperse(n, S, phi, seed=17, family=fam)
-    _say("pairs", fam, S, phi, n)
+    _say("pairs", fam, S, phi, n, "search variant", search)
     p = rcp.Packing(w.d0, w.L, kb, 0, init="none", params=rcp.make_params(skin_s=s, skin_g=g))
+    p.set_tuning(rcp.make_tuning(variant=search))
     p.set_state(w.x, kb)
     npairs = p.neighbor_build()
     gi, gj = p.pairs()
@@ -118,13 +120,15 @@ def test_pairs_bit_exact_c1_states(rcp, orc):
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 40])
-def test_pairs_tiny_and_coarse_grids(rcp, orc, n):
+@pytest.mark.parametrize("search", [0, 64])
+def test_pairs_tiny_and_coarse_grids(rcp, orc, n, search):
     # few spheres in a small box: class grids with fewer than 3 cells per axis
     d0 = np.linspace(1.0, 2.0, n)
     L = 9.0
     rng = np.random.default_rng(n)
     x = rng.uniform(0, L, (n, 3))
     p = rcp.Packing(d0, L, 1.5, 0, init="none", params=rcp.make_params(skin_s=0.2, skin_g=0.02))
+    p.set_tuning(rcp.make_tuning(variant=search))
     p.set_state(x, 1.5)
     p.neighbor_build()
     gi, gj = p.pairs()
@@ -132,11 +136,13 @@ def test_pairs_tiny_and_coarse_grids(rcp, orc, n):
     assert np.array_equal(gi, oi) and np.array_equal(gj, oj)
 
 
-def test_pairs_bit_exact_c2_full(rcp, orc):
+@pytest.mark.parametrize("search", [0, 64])
+def test_pairs_bit_exact_c2_full(rcp, orc, search):
     w = ri.c2_powerlaw(seed=0)
     x = ri.uniform_positions(w.n, w.L, 5)
-    _say("pairs C2 N", w.n)
+    _say("pairs C2 N", w.n, "search variant", search)
     p = rcp.Packing(w.d0, w.L, 1.0, 0, init="none", params=rcp.make_params(skin_s=0.5, skin_g=0.02))
+    p.set_tuning(rcp.make_tuning(variant=search))
     p.set_state(x, 1.0)
     p.neighbor_build()
     gi, gj = p.pairs()
@@ -223,7 +229,8 @@ def test_energy_grad_c3(rcp, orc, c3):
 @pytest.mark.parametrize("steps,fused,graph,variant", [(1, 0, 16, 3), (10, 0, 16, 0),
                                                        (10, 1, 16, 1), (25, 1, 1, 2),
                                                        (25, 0, 4, 3), (10, 0, 16, 8),
-                                                       (25, 0, 1, 9), (10, 0, 16, 12)])
+                                                       (25, 0, 1, 9), (10, 0, 16, 12),
+                                                       (10, 0, 16, 16), (10, 1, 4, 17)])
 def test_adam_steps_match_oracle(rcp, orc, steps, fused, graph, variant):
     w, x, k = _dense_c1_state(orc, iters=1500)
     mu, ex, ek = 2e-3, 2e-3, 2e-4
@@ -243,8 +250,10 @@ def test_adam_steps_match_oracle(rcp, orc, steps, fused, graph, variant):
     assert kg == pytest.approx(st.kappa[0], rel=1e-12)
 
 
-@pytest.mark.parametrize("row_cost,item_work", [(1, 1), (1, 256), (4, 64), (64, 8192)])
-def test_work_item_cuts_agree(rcp, orc, row_cost, item_work):
+@pytest.mark.parametrize("row_cost,item_work,variant", [(1, 1, 0), (1, 256, 0), (4, 64, 0),
+                                                        (64, 8192, 0), (4, 2048, 32),
+                                                        (1, 512, 33)])
+def test_work_item_cuts_agree(rcp, orc, row_cost, item_work, variant):
     # the cut of the rows into work items changes only the summation order
     # of the gradient pieces
     w, x, k = _dense_c1_state(orc, iters=1500)
@@ -252,7 +261,8 @@ def test_work_item_cuts_agree(rcp, orc, row_cost, item_work):
     P = orc.default_params(w.d0, s=0.3, g=0.02)
     p = rcp.Packing(w.d0, w.L, k, 0, init="none",
                     params=rcp.make_params(skin_s=0.3, skin_g=0.02, eps_x=P.eps_x),
-                    tuning=rcp.make_tuning(row_cost=row_cost, item_work=item_work))
+                    tuning=rcp.make_tuning(row_cost=row_cost, item_work=item_work,
+                                           variant=variant))
     p.set_state(x, k)
     p.adam_step(mu, ex, ek, steps)
     xg, kg = p.get_state()
