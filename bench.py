@@ -41,8 +41,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle-updates/s (Adam iters/s × N) and % HBM peak; batched vs plain loop"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_2608_12235_amd/csrc/k_iterate.hip", "paper_2608_12235_amd/csrc/rcp_dev.hpp",
-                  "paper_2608_12235_amd/csrc/rcp_kernels.hpp"]
+KERNEL_SOURCES = ["paper_2608_12235_amd/csrc/k_iterate.hip", "paper_2608_12235_amd/csrc/rcp_dev.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_iterate_traffic.json")
 
 
