@@ -65,7 +65,9 @@ typedef struct rcp_ctx rcp_ctx;
 
 /* Optimiser and neighbour-list parameters.  size must be sizeof(rcp_params).
  *   beta1, beta2, eps_x, eps_k: Adam (Kingma and Ba) for positions and for
- *     kappa; eps_x <= 0 selects 1e-12 / (kappa0 * max D0).
+ *     kappa; eps_x <= 0 selects 1e-12 / (kappa0 * max D0), an explicit
+ *     eps_x must be at least 1e-100 (RCP_EINVAL otherwise: the position
+ *     update neglects sqrt(v) below 1e-100 next to it).
  *   skin_s, skin_g: a pair is listed at scale kb when
  *       r^2 < c^2,  c = kb ((1 + g)(D0_i + D0_j)/2 + 2 s D0_min),
  *     and the list stays valid while

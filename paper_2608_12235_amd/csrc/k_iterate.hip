@@ -44,6 +44,33 @@ __device__ __forceinline__ double near_image(double d, double L, double iL)
     return fma(-L, rint(d * iL), d);
 }
 
+// Reciprocal and reciprocal square root from the hardware estimates
+// (v_rcp_f64, v_rsq_f64), each refined by two Newton steps: within two
+// units in the last place of the correctly rounded values for normal
+// positive arguments, at a third of the cost of an IEEE division or root.
+__device__ __forceinline__ double fast_rcp(double d)
+{
+    double y = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-d, y, 1.0);
+    return fma(y, e, y);
+}
+
+__device__ __forceinline__ double fast_rsq(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    double t = fma(-(h * y), y, 0.5);
+    y = fma(y, t, y);
+    t = fma(-(h * y), y, 0.5);
+    return fma(y, t, y);
+}
+
+// Squared distances below this use the IEEE root (the estimates lose range
+// near the bottom of the exponent range).
+constexpr double kTinyR2 = 1e-200;
+
 // One listed partner's terms (Eq. energy): with q = r/d and delta = 1 - q,
 // E += delta^2 / 4 and S += delta q / 2 (each pair is seen from both ends),
 // and the gradient on x_i gains delta / (d r) (x_j - x_i).
@@ -57,15 +84,23 @@ __device__ __forceinline__ void pair_term(Acc &a, const P4 &qi, const P4 &qj, do
     const double r2 = (dx * dx + dy * dy) + dz * dz;
     const double d = kappa * (0.5 * (qi.d + qj.d));
     if (r2 < d * d) {
-        const double r = sqrt(r2);
-        const double q = r / d;
+        const double id = fast_rcp(d);
+        double r, ir;
+        if (r2 >= kTinyR2) {
+            ir = fast_rsq(r2);
+            r = r2 * ir;
+        } else {
+            r = sqrt(r2);
+            ir = r > 0.0 ? 1.0 / r : 0.0;
+        }
+        const double q = r * id;
         const double delta = 1.0 - q;
         a.e += 0.25 * (delta * delta);
         a.s += 0.5 * (delta * q);
         a.m = fmax(a.m, delta);
         if (kCount) a.c += 0.5;
         if (r > 0.0) {
-            const double f = delta / (d * r);
+            const double f = (delta * id) * ir;
             a.gx += f * dx;
             a.gy += f * dy;
             a.gz += f * dz;
@@ -82,7 +117,10 @@ __device__ __forceinline__ double adam_coord(double th, double g, double &m, dou
     m = b1 * m + (1.0 - b1) * g;
     v = b2 * v + (1.0 - b2) * (g * g);
     const double mh = m * ib1, vh = v * ib2;
-    double t = th - eta * mh / (sqrt(vh) + eps);
+    // sqrt(vh) as vh / sqrt(vh); below 1e-200 the root is negligible next
+    // to eps (>= 1e-100 is required) and is taken as vh * 1e100 (0 at 0)
+    const double sv = vh * fast_rsq(fmax(vh, 1e-200));
+    double t = th - (eta * mh) * fast_rcp(sv + eps);
     if (t < 0.0) t += L;
     if (t >= L) t -= L;
     return t;

@@ -1187,7 +1187,7 @@ int rcp_census_init(int dim, int n_prob, const int64_t *n, const double *const *
     if (params) P = *params;
     else rcp_params_default(&P);
     if (!(P.beta1 >= 0 && P.beta1 < 1) || !(P.beta2 >= 0 && P.beta2 < 1) || !(P.skin_s >= 0) ||
-        !(P.skin_g >= 0) || !(P.eps_k > 0))
+        !(P.skin_g >= 0) || !(P.eps_k > 0) || (P.eps_x > 0 && !(P.eps_x >= 1e-100)))
         return fail(RCP_EINVAL, "bad rcp_params values");
     for (int k = 0; k < n_prob; ++k) CHK(validate_seg(n[k], d0[k], box[k], kappa0[k]));
     if (init_mode < RCP_INIT_NONE || init_mode > RCP_INIT_UNIFORM)
