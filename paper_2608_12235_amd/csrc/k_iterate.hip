@@ -246,6 +246,7 @@ __device__ void tail_logic(SegState *s, double E, double S, double md, double md
     s->t += 1;
     s->b1t *= s->beta1;
     s->b2t *= s->beta2;
+    seg_bias_terms(*s);
     double mk = s->mk, vk = s->vk;
     mk = s->beta1 * mk + (1.0 - s->beta1) * gk;
     vk = s->beta2 * vk + (1.0 - s->beta2) * (gk * gk);
@@ -555,10 +556,10 @@ __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &
     }
     // block reduction of the four partials
     const int lane = t & (kWave - 1);
-    const double be = wave_sum(a.e);
-    const double bs = wave_sum(a.s);
-    const double bm = wave_max(a.m);
-    bd = wave_max(bd);
+    const double be = wave_sum_dpp(a.e);
+    const double bs = wave_sum_dpp(a.s);
+    const double bm = wave_max_dpp(a.m);
+    bd = wave_max_dpp(bd);
     const int wv = t / kWave;
     if (lane == 0) {
         L.red[wv][0] = be;
@@ -599,9 +600,9 @@ __device__ __forceinline__ void load_scalars(const SegState *s, IterScalars &c)
     c.hL = s->hL;
     c.b1 = s->beta1;
     c.b2 = s->beta2;
-    c.iL = 1.0 / c.L;
-    c.ib1 = 1.0 / (1.0 - s->b1t * c.b1);
-    c.ib2 = 1.0 / (1.0 - s->b2t * c.b2);
+    c.iL = s->iL;
+    c.ib1 = s->ib1n;
+    c.ib2 = s->ib2n;
     c.eta = s->eta_x;
     c.eps = s->eps_x;
 }
@@ -942,6 +943,7 @@ __global__ void k_sched_start(SegState *S, int seg, SchedDev q, int reset_adam,
         s->t = 0;
         s->b1t = 1.0;
         s->b2t = 1.0;
+        seg_bias_terms(*s);
         s->mk = 0.0;
         s->vk = 0.0;
     }

@@ -69,6 +69,10 @@ struct SegState {
     // set at each list build (k_after_build)
     double kb, disp_lim, kappa_lim;
     int32_t pad0, pad0b;
+    // reciprocals the iteration kernel would otherwise divide for in every
+    // wave: 1 / L, and the bias corrections of the next position step,
+    // 1 / (1 - beta1^(t+1)) and 1 / (1 - beta2^(t+1))
+    double iL, ib1n, ib2n;
     // optimiser and schedule state
     double kappa, mk, vk, b1t, b2t, mu, eta_x, eta_k;
     int64_t t, it_rung, iters, iter_limit;
@@ -78,6 +82,13 @@ struct SegState {
     uint32_t ticket, pad2;
     SchedDev sched;
 };
+
+// Refresh ib1n, ib2n after b1t = beta1^t or b2t = beta2^t changed.
+__host__ __device__ inline void seg_bias_terms(SegState &s)
+{
+    s.ib1n = 1.0 / (1.0 - s.b1t * s.beta1);
+    s.ib2n = 1.0 / (1.0 - s.b2t * s.beta2);
+}
 
 // One block of the iteration grid: rows [begin, end) of packing seg.
 struct WorkItem {
@@ -153,6 +164,60 @@ __device__ __forceinline__ double wave_max(double v)
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
     return v;
+}
+
+// A double moved across lanes by a DPP control (both halves); lanes that
+// the row mask leaves out receive `old`.
+template <int kCtrl, int kRowMask = 0xf>
+__device__ __forceinline__ double dpp_f64(double old, double v)
+{
+    union {
+        double d;
+        int i[2];
+    } a, b, r;
+    a.d = old;
+    b.d = v;
+    r.i[0] = __builtin_amdgcn_update_dpp(a.i[0], b.i[0], kCtrl, kRowMask, 0xf, false);
+    r.i[1] = __builtin_amdgcn_update_dpp(a.i[1], b.i[1], kCtrl, kRowMask, 0xf, false);
+    return r.d;
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane)
+{
+    union {
+        double d;
+        int i[2];
+    } a;
+    a.d = v;
+    a.i[0] = __builtin_amdgcn_readlane(a.i[0], lane);
+    a.i[1] = __builtin_amdgcn_readlane(a.i[1], lane);
+    return a.d;
+}
+
+// Wave-wide sum / maximum (of values >= 0) with DPP moves only, no LDS
+// traffic: quad butterflies, rotations within rows of 16, then the row
+// broadcasts; the total ends in lane 63 and is returned to every lane.
+// The combining order is fixed.
+__device__ __forceinline__ double wave_sum_dpp(double v)
+{
+    v += dpp_f64<0xb1>(0.0, v);          // quad_perm [1, 0, 3, 2]
+    v += dpp_f64<0x4e>(0.0, v);          // quad_perm [2, 3, 0, 1]
+    v += dpp_f64<0x124>(0.0, v);         // row_ror:4
+    v += dpp_f64<0x128>(0.0, v);         // row_ror:8
+    v += dpp_f64<0x142, 0xa>(0.0, v);    // row_bcast:15 into rows 1, 3
+    v += dpp_f64<0x143, 0xc>(0.0, v);    // row_bcast:31 into rows 2, 3
+    return readlane_f64(v, kWave - 1);
+}
+
+__device__ __forceinline__ double wave_max_dpp(double v)
+{
+    v = fmax(v, dpp_f64<0xb1>(0.0, v));
+    v = fmax(v, dpp_f64<0x4e>(0.0, v));
+    v = fmax(v, dpp_f64<0x124>(0.0, v));
+    v = fmax(v, dpp_f64<0x128>(0.0, v));
+    v = fmax(v, dpp_f64<0x142, 0xa>(0.0, v));
+    v = fmax(v, dpp_f64<0x143, 0xc>(0.0, v));
+    return readlane_f64(v, kWave - 1);
 }
 
 __device__ __forceinline__ double wave_min(double v)

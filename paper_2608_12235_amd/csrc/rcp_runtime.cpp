@@ -1032,6 +1032,8 @@ static int seg_setup(rcp_ctx *c, int k, int64_t n, const double *d0, double L, d
     st.kappa = kappa0;
     st.b1t = 1.0;
     st.b2t = 1.0;
+    st.iL = 1.0 / L;
+    seg_bias_terms(st);
     st.flags = F_STALE | F_HOLD;
     st.cur = 0;
     HIPCHK(hipMemcpy(c->d_state + k, &st, sizeof st, hipMemcpyHostToDevice));
@@ -1323,6 +1325,7 @@ int rcp_set_state(rcp_ctx *c, int k, const double *x, double kappa, int is_devic
     st.t = 0;
     st.b1t = 1.0;
     st.b2t = 1.0;
+    seg_bias_terms(st);
     st.mk = 0;
     st.vk = 0;
     st.it_rung = 0;
