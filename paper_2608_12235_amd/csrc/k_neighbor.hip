@@ -463,6 +463,7 @@ __device__ __forceinline__ uint64_t slot_key(const BuildArgs &a, const Stencil &
 struct SearchOut {
     uint64_t *buf;      // LDS, kSearchBuf entries
     uint32_t *nbuf;     // LDS counter
+    const P4 *own;      // LDS, this wave's 64 particles
     uint64_t *list;
     uint32_t *counter;
     int64_t cap;
@@ -475,18 +476,12 @@ struct SearchOut {
 // its candidate's owner by binary search over the prefix.  Listed pairs
 // take one LDS reservation per wave and round.
 __device__ __forceinline__ void test_slot(const BuildArgs &a, const SearchOut &out, int lane,
-                                          uint64_t below, int64_t wbase, int32_t st, int32_t ct,
-                                          double xi, double yi, double zi, double di)
+                                          uint64_t below, int64_t wbase, int32_t st, int32_t ct)
 {
-    int32_t inc = ct;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const int32_t u = __shfl_up(inc, o, kWave);
-        if (lane >= o) inc += u;
-    }
-    const int32_t T = __shfl(inc, kWave - 1, kWave);
+    const int32_t inc = wave_scan_incl_dpp(ct);
+    const int32_t T = __builtin_amdgcn_readlane(inc, kWave - 1);
     if (T == 0) return;
-    const int32_t ex = inc - ct;
+    const int32_t jb = st - (inc - ct);   // candidate q of this lane's run is j = q + jb
     for (int32_t r0 = 0; r0 < T; r0 += kWave) {
         const int32_t q = r0 + lane;
         // owner: number of lanes whose inclusive prefix is <= q
@@ -498,21 +493,16 @@ __device__ __forceinline__ void test_slot(const BuildArgs &a, const SearchOut &o
         }
         const bool has = q < T;
         o = has ? o : 0;
-        const int32_t jst = __shfl(st, o, kWave);
-        const int32_t jex = __shfl(ex, o, kWave);
-        const double ox_ = __shfl(xi, o, kWave);
-        const double oy_ = __shfl(yi, o, kWave);
-        const double oz_ = __shfl(zi, o, kWave);
-        const double od_ = __shfl(di, o, kWave);
-        const int64_t j = (int64_t)jst + (q - jex);
+        const int64_t j = (int64_t)q + __shfl(jb, o, kWave);
         bool hit = false;
         if (has) {
+            const P4 oq = out.own[o];
             const P4 qj = a.pos[j];
-            const double dx = min_image(qj.x - ox_, a.L, a.hL);
-            const double dy = min_image(qj.y - oy_, a.L, a.hL);
-            const double dz = min_image(qj.z - oz_, a.L, a.hL);
+            const double dx = min_image(qj.x - oq.x, a.L, a.hL);
+            const double dy = min_image(qj.y - oq.y, a.L, a.hL);
+            const double dz = min_image(qj.z - oq.z, a.L, a.hL);
             const double r2 = (dx * dx + dy * dy) + dz * dz;
-            const double cc = a.kb * (a.opg * (0.5 * (od_ + qj.d)) + a.sk2);
+            const double cc = a.kb * (a.opg * (0.5 * (oq.d + qj.d)) + a.sk2);
             hit = r2 < cc * cc;
         }
         const uint64_t bal = __ballot(hit);
@@ -554,17 +544,17 @@ __global__ __launch_bounds__(kBlock) void k_search_coop(BuildArgs a, uint64_t *_
                                                        int64_t cap, int row_bits, int xcd_remap)
 {
     __shared__ uint64_t buf[kSearchBuf];
+    __shared__ P4 own[kBlock];
     __shared__ uint32_t nbuf;
     __shared__ uint32_t gbase;
-    if (threadIdx.x == 0) nbuf = 0;
-    __syncthreads();
     const int blk = xcd_remap ? remap_xcd((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
     const int lane = (int)(threadIdx.x & (kWave - 1));
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
     const int64_t wbase = (int64_t)blk * kBlock + (threadIdx.x & ~(kWave - 1));
     const int64_t i = wbase + lane;
     const bool valid = i < a.n;
-    const SearchOut out{buf, &nbuf, list, counter, cap, row_bits};
+    const SearchOut out{buf, &nbuf, own + (threadIdx.x & ~(kWave - 1)), list, counter, cap,
+                        row_bits};
     double xi = 0.0, yi = 0.0, zi = 0.0, di = 0.0;
     int li = kMaxLevels;
     if (valid) {
@@ -575,6 +565,9 @@ __global__ __launch_bounds__(kBlock) void k_search_coop(BuildArgs a, uint64_t *_
         di = qi.d;
         li = a.lev[i];
     }
+    own[threadIdx.x] = P4{xi, yi, zi, di};
+    if (threadIdx.x == 0) nbuf = 0;
+    __syncthreads();
     for (int L = 0; L < a.nlev; ++L) {
         const LevelGrid g = a.lv[L];
         if (g.count == 0) continue;
@@ -592,7 +585,7 @@ __global__ __launch_bounds__(kBlock) void k_search_coop(BuildArgs a, uint64_t *_
                 r = g.dbase >= 0 ? a.dense[g.dbase + slot_dense_index(g, S, sl)]
                                  : hash_find(a, slot_key(a, S, base, sl));
             if (same) r = above(r, i);
-            test_slot(a, out, lane, below, wbase, r.x, r.y, xi, yi, zi, di);
+            test_slot(a, out, lane, below, wbase, r.x, r.y);
         }
     }
     __syncthreads();

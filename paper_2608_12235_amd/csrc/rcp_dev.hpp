@@ -194,6 +194,20 @@ __device__ __forceinline__ double readlane_f64(double v, int lane)
     return a.d;
 }
 
+// Inclusive prefix sum of an int over the 64 lanes with DPP only:
+// Kogge-Stone shifts within rows of 16, then the row broadcasts carry the
+// totals of rows 0 and 0..1 (2) forward.
+__device__ __forceinline__ int32_t wave_scan_incl_dpp(int32_t v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);   // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);   // row_bcast:31
+    return v;
+}
+
 // Wave-wide sum / maximum (of values >= 0) with DPP moves only, no LDS
 // traffic: quad butterflies, rotations within rows of 16, then the row
 // broadcasts; the total ends in lane 63 and is returned to every lane.
