@@ -568,7 +568,16 @@ __global__ __launch_bounds__(kBlock) void k_search_coop(BuildArgs a, uint64_t *_
     own[threadIdx.x] = P4{xi, yi, zi, di};
     if (threadIdx.x == 0) nbuf = 0;
     __syncthreads();
-    for (int L = 0; L < a.nlev; ++L) {
+    // a grid with gridDim.y > 1 gives each block one level and one plane
+    // (fixed x offset) of the stencil: shorter chains of dependent lookups
+    // for packings too small to fill the GPU otherwise
+    int Lb = 0, Le = a.nlev, plane = -1;
+    if (gridDim.y > 1) {
+        Lb = (int)blockIdx.y / 3;
+        Le = Lb + 1;
+        plane = (int)blockIdx.y % 3;
+    }
+    for (int L = Lb; L < Le; ++L) {
         const LevelGrid g = a.lv[L];
         if (g.count == 0) continue;
         const bool act = li <= L;
@@ -580,6 +589,7 @@ __global__ __launch_bounds__(kBlock) void k_search_coop(BuildArgs a, uint64_t *_
         const uint64_t base = (uint64_t)L << a.mb;
 #pragma unroll
         for (int sl = 0; sl < 27; ++sl) {
+            if (plane >= 0 && sl / 9 != plane) continue;
             int2 r = make_int2(0, 0);
             if (act && slot_used(S, sl))
                 r = g.dbase >= 0 ? a.dense[g.dbase + slot_dense_index(g, S, sl)]
@@ -601,9 +611,12 @@ void launch_search(const BuildArgs &a, uint64_t *list, uint32_t *counter, int64_
 {
     if (a.n <= 0) return;
     const dim3 grid((unsigned)((a.n + kBlock - 1) / kBlock));
-    if (coop)
-        hipLaunchKernelGGL(k_search_coop, grid, dim3(kBlock), 0, s, a, list, counter, cap,
-                           row_bits, xcd_remap);
+    if (coop) {
+        // fewer than 8 blocks per CU: split the work by level and plane
+        const unsigned ny = grid.x < 2048u ? 3u * (unsigned)a.nlev : 1u;
+        hipLaunchKernelGGL(k_search_coop, dim3(grid.x, ny), dim3(kBlock), 0, s, a, list,
+                           counter, cap, row_bits, xcd_remap);
+    }
     else
         hipLaunchKernelGGL(k_search, grid, dim3(kBlock), 0, s, a, list, counter, cap, row_bits,
                            xcd_remap);
