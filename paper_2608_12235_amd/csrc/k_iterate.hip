@@ -306,34 +306,39 @@ __device__ __forceinline__ Part4 load_part(const Part4 *p)
     return kCoherent ? load_part_coherent(p) : *p;
 }
 
-template <int kT, bool kCoherent = false>
-__device__ void reduce_and_tail(SegState *s, const double *partials)
+// This thread's share of a packing's block partials: partials t, t + kT,
+// t + 2 kT, ... in rounds of eight whose loads are all in flight together,
+// combined in a fixed order.
+template <int kT, bool kCoherent>
+__device__ __forceinline__ Part4 thread_partials(int64_t nb, int64_t b0, const double *partials)
+{
+    const Part4 *P = reinterpret_cast<const Part4 *>(partials) + b0;
+    Part4 a = {0, 0, 0, 0};
+    for (int64_t b = threadIdx.x; b < nb; b += 8 * kT) {
+        Part4 p[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            p[k] = b + k * kT < nb ? load_part<kCoherent>(P + b + k * kT) : Part4{0, 0, 0, 0};
+        a.e += ((p[0].e + p[1].e) + (p[2].e + p[3].e)) + ((p[4].e + p[5].e) + (p[6].e + p[7].e));
+        a.s += ((p[0].s + p[1].s) + (p[2].s + p[3].s)) + ((p[4].s + p[5].s) + (p[6].s + p[7].s));
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            a.m = fmax(a.m, p[k].m);
+            a.d = fmax(a.d, p[k].d);
+        }
+    }
+    return a;
+}
+
+// Block reduction of the threads' shares (DPP within waves, then the waves
+// in order by thread 0), then thread 0 runs the tail.  Every thread of the
+// block must call it.
+template <int kT>
+__device__ __forceinline__ void block_tail(SegState *s, const Part4 &mine)
 {
     constexpr int kW = kT / kWave;
-    double e = 0, sd = 0, m = 0, d = 0;
-    const int64_t nb = s->nblocks, b0 = s->bfirst;
-    const Part4 *P = reinterpret_cast<const Part4 *>(partials) + b0;
-    int64_t b = threadIdx.x;
-    for (; b + 3 * kT < nb; b += 4 * kT) {
-        const Part4 p0 = load_part<kCoherent>(P + b), p1 = load_part<kCoherent>(P + b + kT),
-                    p2 = load_part<kCoherent>(P + b + 2 * kT),
-                    p3 = load_part<kCoherent>(P + b + 3 * kT);
-        e += ((p0.e + p1.e) + (p2.e + p3.e));
-        sd += ((p0.s + p1.s) + (p2.s + p3.s));
-        m = fmax(m, fmax(fmax(p0.m, p1.m), fmax(p2.m, p3.m)));
-        d = fmax(d, fmax(fmax(p0.d, p1.d), fmax(p2.d, p3.d)));
-    }
-    for (; b < nb; b += kT) {
-        const Part4 p0 = load_part<kCoherent>(P + b);
-        e += p0.e;
-        sd += p0.s;
-        m = fmax(m, p0.m);
-        d = fmax(d, p0.d);
-    }
-    e = wave_sum(e);
-    sd = wave_sum(sd);
-    m = wave_max(m);
-    d = wave_max(d);
+    const double e = wave_sum_dpp(mine.e), sd = wave_sum_dpp(mine.s);
+    const double m = wave_max_dpp(mine.m), d = wave_max_dpp(mine.d);
     __shared__ double red[kW][4];
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
     if (lane == 0) {
@@ -344,15 +349,23 @@ __device__ void reduce_and_tail(SegState *s, const double *partials)
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        e = 0, sd = 0, m = 0, d = 0;
+        double te = 0, ts = 0, tm = 0, td = 0;
         for (int k = 0; k < kW; ++k) {
-            e += red[k][0];
-            sd += red[k][1];
-            m = fmax(m, red[k][2]);
-            d = fmax(d, red[k][3]);
+            te += red[k][0];
+            ts += red[k][1];
+            tm = fmax(tm, red[k][2]);
+            td = fmax(td, red[k][3]);
         }
-        tail_logic(s, e, sd, m, d);
+        tail_logic(s, te, ts, tm, td);
     }
+}
+
+// Deterministic reduction of a segment's block partials by one block of kT
+// threads, then the tail (see thread_partials, block_tail).
+template <int kT, bool kCoherent = false>
+__device__ void reduce_and_tail(SegState *s, const double *partials)
+{
+    block_tail<kT>(s, thread_partials<kT, kCoherent>(s->nblocks, s->bfirst, partials));
 }
 
 // Partner indices of a work item, staged in LDS at the start of the item
@@ -840,12 +853,16 @@ __global__ __launch_bounds__(kTailBlock) void k_tail(SegState *__restrict__ S,
     static_assert(sizeof(SegState) % 8 == 0, "SegState is copied in 8-byte words");
     constexpr int kWords = (int)(sizeof(SegState) / 8);
     __shared__ SegState ls;
-    uint64_t *src = reinterpret_cast<uint64_t *>(S + blockIdx.x);
+    SegState *gs = S + blockIdx.x;
+    // the partials are loaded before the record is copied, so the two
+    // latencies overlap (an idle packing's stale partials are then dropped)
+    const Part4 mine = thread_partials<kTailBlock, false>(gs->nblocks, gs->bfirst, partials);
+    uint64_t *src = reinterpret_cast<uint64_t *>(gs);
     uint64_t *dst = reinterpret_cast<uint64_t *>(&ls);
     for (int k = threadIdx.x; k < kWords; k += kTailBlock) dst[k] = src[k];
     __syncthreads();
     if (ls.flags & F_IDLE) return;
-    reduce_and_tail<kTailBlock>(&ls, partials);
+    block_tail<kTailBlock>(&ls, mine);
     __syncthreads();
     for (int k = threadIdx.x; k < kWords; k += kTailBlock) src[k] = dst[k];
 }
