@@ -203,7 +203,7 @@ const char *rcp_last_error(void);
 void rcp_params_default(rcp_params *p);
 /* Defaults: graph_iters 16, xcd_remap 1, fused_tail 0, variant 64 (the
  * cooperative pair search, the two-gather gradient + Adam kernel), row_cost
- * 16, item_work 4096, time_kernels 0. */
+ * 10, item_work 2560, time_kernels 0. */
 void rcp_tuning_default(rcp_tuning *t);
 
 /* Default rung table for a packing of n spheres in dimension dim with size

@@ -1134,8 +1134,8 @@ void rcp_tuning_default(rcp_tuning *t)
     t->xcd_remap = 1;
     t->fused_tail = 0;
     t->variant = 64;   // cooperative pair search
-    t->row_cost = 16;
-    t->item_work = 4096;
+    t->row_cost = 10;
+    t->item_work = 2560;
     t->time_kernels = 0;
 }
 
