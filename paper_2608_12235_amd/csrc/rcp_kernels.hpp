@@ -5,18 +5,14 @@
 namespace rcp {
 
 // ------------------------------------------------------------ k_sort.hip
-// Exclusive scan of n u32 counts into out[0..n]; out[n] and *total get the
-// sum.  tile_tmp needs ceil(n / 2048) entries.  in may equal out.
-void scan_exclusive(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tile_tmp,
-                    uint32_t *total, hipStream_t s);
 // Stable LSD radix sort on the low nbits of the keys; returns 0 if the
 // result is in (k0, v0), 1 if in (k1, v1).  hist needs 256 * ceil(n/2048)
-// + 1 entries.
+// entries, totals 256.
 int radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, int nbits,
-               uint32_t *hist, uint32_t *tile_tmp, uint32_t *total, hipStream_t s);
+               uint32_t *hist, uint32_t *totals, hipStream_t s);
 // Same, keys only.
 int radix_sort_keys(uint64_t *k0, uint64_t *k1, int64_t n, int nbits, uint32_t *hist,
-                    uint32_t *tile_tmp, uint32_t *total, hipStream_t s);
+                    uint32_t *totals, hipStream_t s);
 
 // -------------------------------------------------------- k_neighbor.hip
 struct LevelGrid {

@@ -122,8 +122,8 @@ struct BuildLane {
     uint64_t *kA = nullptr, *kB = nullptr;
     uint32_t *vA = nullptr, *vB = nullptr;
     int64_t kcap = 0, kcapB = 0, vcap = 0, vcapB = 0;
-    uint32_t *hist = nullptr, *tiles = nullptr, *totals = nullptr;
-    int64_t hist_cap = 0, tiles_cap = 0, totals_cap = 0;
+    uint32_t *hist = nullptr, *tiles = nullptr;   // radix histograms, digit totals
+    int64_t hist_cap = 0, tiles_cap = 0;
     HashSlot *hash = nullptr;
     int64_t hcap = 0;
     int2 *dense = nullptr;           // dense cell tables
@@ -435,8 +435,7 @@ static int build_grow(rcp_ctx *c, std::vector<BuildJob> &jobs, int nl)
         CHK(dgrow(&L.vB, &L.vcapB, nmax));
         const int64_t tiles = (std::max(nmax, lmax) + 2047) / 2048 + 1;
         CHK(dgrow(&L.hist, &L.hist_cap, 256 * tiles + 1));
-        CHK(dgrow(&L.tiles, &L.tiles_cap, 256 * tiles + 1));
-        CHK(dgrow(&L.totals, &L.totals_cap, 16));
+        CHK(dgrow(&L.tiles, &L.tiles_cap, 256));
         if (dmax > 0) CHK(dgrow(&L.dense, &L.dense_cap, dmax));
         CHK(dgrow(&L.hash, &L.hcap, hmax));
     }
@@ -469,7 +468,7 @@ static void build_front(rcp_ctx *c, BuildJob &j, uint32_t *counter)
     a.pos = s.Q[cur];
     a.lev = s.LEV[set];
     launch_keys(a, B.kA, B.vA, st);
-    const int par = radix_sort(B.kA, B.vA, B.kB, B.vB, n, j.nbits, B.hist, B.tiles, B.totals, st);
+    const int par = radix_sort(B.kA, B.vA, B.kB, B.vB, n, j.nbits, B.hist, B.tiles, st);
     PermArgs pa;
     pa.n = n;
     pa.perm = par ? B.vB : B.vA;
@@ -513,7 +512,7 @@ static int build_back(rcp_ctx *c, BuildJob &j, int64_t m, bool *relayout)
     const int64_t n = s.n;
     uint64_t *list = c->larena + j.loff;
     s.list_est = m;
-    const int lp = radix_sort_keys(list, B.kA, m, 2 * j.row_bits, B.hist, B.tiles, B.totals, st);
+    const int lp = radix_sort_keys(list, B.kA, m, 2 * j.row_bits, B.hist, B.tiles, st);
     launch_csr_from_sorted(lp ? B.kA : list, m, j.row_bits, n, s.rp, s.col, st);
     s.built = true;
     if (slots_for(c, n, m) > s.blocks) {
@@ -1074,7 +1073,6 @@ static void destroy_ctx(rcp_ctx *c)
         dfree(L.vB);
         dfree(L.hist);
         dfree(L.tiles);
-        dfree(L.totals);
         dfree(L.hash);
         dfree(L.dense);
         if (L.ev) (void)hipEventDestroy(L.ev);
