@@ -921,8 +921,11 @@ void launch_tail(SegState *S, const double *partials, int nseg, hipStream_t st)
 }
 
 // ------------------------------------------------------- small updates
-__global__ void k_after_build(SegState *S, int seg, double kb, double disp_lim,
-                              double kappa_lim, int cur)
+// After a list build: the packing's list scale and validity limits, its
+// current buffer, the flags cleared, and its pointer table entry (written
+// in stream order, no host staging).
+__global__ void k_after_build(SegState *S, SegPtrs *P, int seg, double kb, double disp_lim,
+                              double kappa_lim, int cur, SegPtrs v)
 {
     SegState *s = S + seg;
     s->kb = kb;
@@ -930,21 +933,14 @@ __global__ void k_after_build(SegState *S, int seg, double kb, double disp_lim,
     s->kappa_lim = kappa_lim;
     s->cur = cur;
     s->flags &= ~(F_REBUILD | F_STALE);
+    P[seg] = v;
 }
 
-void launch_after_build(SegState *S, int seg, double kb, double disp_lim, double kappa_lim,
-                        int cur, hipStream_t st)
+void launch_after_build(SegState *S, SegPtrs *P, int seg, double kb, double disp_lim,
+                        double kappa_lim, int cur, const SegPtrs &v, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_after_build, dim3(1), dim3(1), 0, st, S, seg, kb, disp_lim, kappa_lim,
-                       cur);
-}
-
-// Host-side pointer table entry written in stream order (no host staging).
-__global__ void k_put_ptrs(SegPtrs *P, int seg, SegPtrs v) { P[seg] = v; }
-
-void launch_put_ptrs(SegPtrs *P, int seg, const SegPtrs &v, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_put_ptrs, dim3(1), dim3(1), 0, st, P, seg, v);
+    hipLaunchKernelGGL(k_after_build, dim3(1), dim3(1), 0, st, S, P, seg, kb, disp_lim,
+                       kappa_lim, cur, v);
 }
 
 __global__ void k_sched_start(SegState *S, int seg, SchedDev q, int reset_adam,

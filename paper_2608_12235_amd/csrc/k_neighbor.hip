@@ -118,12 +118,6 @@ void launch_fill_f64(double *p, int64_t n, double v, hipStream_t s)
                        p, n, v);
 }
 
-__global__ void k_hash_clear(HashSlot *__restrict__ h, int64_t cap)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < cap) h[i].key = kEmptyKey;
-}
-
 // Home slot of a cell key.  The low three Morton bits (a 2x2x2 block of
 // cells) stay together in one 8-slot group (one 128-byte line); the groups
 // themselves are scattered by hashing the remaining bits, so a 27-cell
@@ -131,26 +125,6 @@ __global__ void k_hash_clear(HashSlot *__restrict__ h, int64_t cap)
 __device__ __forceinline__ uint64_t hash_slot(uint64_t key, uint64_t mask)
 {
     return ((hash64(key >> 3) << 3) | (key & 7ull)) & mask;
-}
-
-__global__ __launch_bounds__(kBlock) void k_hash_starts(BuildArgs a)
-{
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= a.n) return;
-    if (a.lv[a.lev[i]].dbase >= 0) return;
-    const uint64_t key = a.skey[i];
-    if (i > 0 && a.skey[i - 1] == key) return;
-    uint64_t slot = hash_slot(key, a.hmask);
-    for (;;) {
-        unsigned long long prev = atomicCAS((unsigned long long *)&a.hash[slot].key,
-                                            (unsigned long long)kEmptyKey,
-                                            (unsigned long long)key);
-        if (prev == kEmptyKey || prev == key) {
-            a.hash[slot].start = (int32_t)i;
-            return;
-        }
-        slot = (slot + 1) & a.hmask;
-    }
 }
 
 __device__ __forceinline__ int2 hash_find(const BuildArgs &a, uint64_t key)
@@ -164,18 +138,6 @@ __device__ __forceinline__ int2 hash_find(const BuildArgs &a, uint64_t key)
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_hash_counts(BuildArgs a)
-{
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= a.n) return;
-    if (a.lv[a.lev[i]].dbase >= 0) return;
-    const uint64_t key = a.skey[i];
-    if (i + 1 < a.n && a.skey[i + 1] == key) return;
-    uint64_t slot = hash_slot(key, a.hmask);
-    while (a.hash[slot].key != key) slot = (slot + 1) & a.hmask;
-    a.hash[slot].count = (int32_t)(i - a.hash[slot].start + 1);
-}
-
 // Dense cell index of sorted particle i (its level must be dense).
 __device__ __forceinline__ int64_t dense_index(const BuildArgs &a, int64_t i)
 {
@@ -186,41 +148,56 @@ __device__ __forceinline__ int64_t dense_index(const BuildArgs &a, int64_t i)
     return g.dbase + (cx * g.nc + cy) * g.nc + cz;
 }
 
-// A cell's sorted particles are contiguous (same key): the first one writes
-// the start (k_dense_starts), then the last one the count (k_dense_counts).
-__global__ __launch_bounds__(kBlock) void k_dense_starts(BuildArgs a)
+// A cell's sorted particles are contiguous (same key): the first one finds
+// the end of the run and writes (start, count), into the dense table of its
+// level or into the hash (inserted by compare-and-swap on the key).
+__global__ __launch_bounds__(kBlock) void k_cells(BuildArgs a)
 {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= a.n) return;
-    if (a.lv[a.lev[i]].dbase < 0) return;
-    if (i > 0 && a.skey[i - 1] == a.skey[i]) return;
-    a.dense[dense_index(a, i)].x = (int32_t)i;
-}
-
-__global__ __launch_bounds__(kBlock) void k_dense_counts(BuildArgs a)
-{
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= a.n) return;
-    if (a.lv[a.lev[i]].dbase < 0) return;
-    if (i + 1 < a.n && a.skey[i + 1] == a.skey[i]) return;
-    int2 *cell = a.dense + dense_index(a, i);
-    cell->y = (int32_t)(i - cell->x + 1);
-}
-
-void launch_hash_build(const BuildArgs &a, int64_t cap, int64_t ndense, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_hash_clear, dim3((unsigned)((cap + kBlock - 1) / kBlock)), dim3(kBlock),
-                       0, s, a.hash, cap);
-    if (ndense > 0)
-        launch_fill_u32(reinterpret_cast<uint32_t *>(a.dense), 2 * ndense, 0u, s);
-    if (a.n <= 0) return;
-    const dim3 g((unsigned)((a.n + kBlock - 1) / kBlock));
-    hipLaunchKernelGGL(k_hash_starts, g, dim3(kBlock), 0, s, a);
-    hipLaunchKernelGGL(k_hash_counts, g, dim3(kBlock), 0, s, a);
-    if (ndense > 0) {
-        hipLaunchKernelGGL(k_dense_starts, g, dim3(kBlock), 0, s, a);
-        hipLaunchKernelGGL(k_dense_counts, g, dim3(kBlock), 0, s, a);
+    const uint64_t key = a.skey[i];
+    if (i > 0 && a.skey[i - 1] == key) return;
+    int64_t e = i + 1;
+    while (e < a.n && a.skey[e] == key) ++e;
+    const int32_t start = (int32_t)i, count = (int32_t)(e - i);
+    if (a.lv[a.lev[i]].dbase >= 0) {
+        a.dense[dense_index(a, i)] = make_int2(start, count);
+        return;
     }
+    uint64_t slot = hash_slot(key, a.hmask);
+    for (;;) {
+        const unsigned long long prev = atomicCAS((unsigned long long *)&a.hash[slot].key,
+                                                  (unsigned long long)kEmptyKey,
+                                                  (unsigned long long)key);
+        if (prev == kEmptyKey) {
+            a.hash[slot].start = start;
+            a.hash[slot].count = count;
+            return;
+        }
+        slot = (slot + 1) & a.hmask;
+    }
+}
+
+// Empty hash slots, zero dense cells (2 ndense words), zero *counter.
+__global__ void k_tables_clear(HashSlot *__restrict__ h, int64_t cap, uint32_t *__restrict__ dense,
+                               int64_t nd2, uint32_t *__restrict__ counter)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cap) h[i].key = kEmptyKey;
+    if (i < nd2) dense[i] = 0u;
+    if (i == 0 && counter) *counter = 0u;
+}
+
+void launch_hash_build(const BuildArgs &a, int64_t cap, int64_t ndense, uint32_t *counter,
+                       hipStream_t s)
+{
+    const int64_t m = cap > 2 * ndense ? cap : 2 * ndense;
+    hipLaunchKernelGGL(k_tables_clear, dim3((unsigned)((m + kBlock - 1) / kBlock)), dim3(kBlock),
+                       0, s, a.hash, cap, reinterpret_cast<uint32_t *>(a.dense), 2 * ndense,
+                       counter);
+    if (a.n <= 0) return;
+    hipLaunchKernelGGL(k_cells, dim3((unsigned)((a.n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       a);
 }
 
 // ------------------------------------------------------- pair search

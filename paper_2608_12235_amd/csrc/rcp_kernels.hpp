@@ -61,8 +61,10 @@ struct PermArgs {
 void launch_permute(const PermArgs &p, hipStream_t s);
 
 // Cell tables on the sorted particles: the hash for levels with dbase < 0,
-// the dense (start, count) arrays (ndense entries, cleared here) otherwise.
-void launch_hash_build(const BuildArgs &a, int64_t cap, int64_t ndense, hipStream_t s);
+// the dense (start, count) arrays (ndense entries, cleared here) otherwise;
+// *counter (if given) is zeroed in the same launch.
+void launch_hash_build(const BuildArgs &a, int64_t cap, int64_t ndense, uint32_t *counter,
+                       hipStream_t s);
 // One pass over the particles: every listed pair (i, j) is appended twice
 // to `list` as (row << row_bits) | col, rows and cols in sorted order, in an
 // arbitrary order; *counter (zeroed by the caller) receives the number of
@@ -92,10 +94,8 @@ void launch_iterate(const SegPtrs *P, SegState *S, const WorkItem *W, double *pa
 void launch_tail(SegState *S, const double *partials, int nseg, hipStream_t s);
 // After a list build of segment seg: kb, validity limits, current buffer,
 // clear REBUILD / STALE.
-void launch_after_build(SegState *S, int seg, double kb, double disp_lim, double kappa_lim,
-                        int cur, hipStream_t st);
-// Write entry seg of the device pointer table in stream order.
-void launch_put_ptrs(SegPtrs *P, int seg, const SegPtrs &v, hipStream_t st);
+void launch_after_build(SegState *S, SegPtrs *P, int seg, double kb, double disp_lim,
+                        double kappa_lim, int cur, const SegPtrs &v, hipStream_t st);
 // Start a schedule on segment seg: copy the table, reset the position in it,
 // set the first rung's parameters from the current kappa.
 void launch_sched_start(SegState *S, int seg, const SchedDev &q, int reset_adam,

@@ -189,15 +189,6 @@ static void ptrs_of(const Seg &s, SegPtrs &p)
     p.col = s.col;
 }
 
-static int upload_ptrs(rcp_ctx *c, int k, hipStream_t st)
-{
-    SegPtrs p;
-    ptrs_of(c->segs[k], p);
-    launch_put_ptrs(c->d_ptrs, k, p, st);   // in stream order, no sync
-    HIPCHK(hipGetLastError());
-    return RCP_OK;
-}
-
 static int rebuild_events(rcp_ctx *c, std::pair<hipEvent_t, hipEvent_t> &ev)
 {
     if (!c->rb_pool.empty()) {
@@ -494,8 +485,7 @@ static void build_front(rcp_ctx *c, BuildJob &j, uint32_t *counter)
     a.hash = B.hash;
     a.hmask = (uint64_t)j.hcap - 1;
     a.dense = B.dense;
-    launch_hash_build(a, j.hcap, j.ndense, st);
-    launch_fill_u32(counter, 1, 0u, st);
+    launch_hash_build(a, j.hcap, j.ndense, counter, st);
     launch_search(a, c->larena + j.loff, counter, j.lcap, j.row_bits, c->tuning.xcd_remap,
                   (c->tuning.variant >> 6) & 1, st);
 }
@@ -523,12 +513,15 @@ static int build_back(rcp_ctx *c, BuildJob &j, int64_t m, bool *relayout)
     }
     const double sk = c->params.skin_s, opg = 1.0 + c->params.skin_g;
     const double lim = sk * j.kappa * s.d0min * (1.0 - 1e-9);
-    launch_after_build(c->d_state, j.k, j.kappa, lim, opg * j.kappa * (1.0 - 1e-12), s.cur, st);
+    SegPtrs pp;
+    ptrs_of(s, pp);
+    launch_after_build(c->d_state, c->d_ptrs, j.k, j.kappa, lim, opg * j.kappa * (1.0 - 1e-12),
+                       s.cur, pp, st);
+    HIPCHK(hipGetLastError());
     s.npairs = m / 2;
     s.nnz = m;
     s.rebuilds += 1;
     c->stats.rebuilds += 1;
-    CHK(upload_ptrs(c, j.k, st));
     return RCP_OK;
 }
 
