@@ -201,7 +201,7 @@ typedef struct {
 int rcp_version(void);
 const char *rcp_last_error(void);
 void rcp_params_default(rcp_params *p);
-/* Defaults: graph_iters 16, xcd_remap 1, fused_tail 0, variant 64 (the
+/* Defaults: graph_iters 32, xcd_remap 1, fused_tail 0, variant 64 (the
  * cooperative pair search, the two-gather gradient + Adam kernel), row_cost
  * 10, item_work 2560, time_kernels 0. */
 void rcp_tuning_default(rcp_tuning *t);

@@ -16,7 +16,7 @@ from .api import make_tuning
 SKINS = (0.5, 1.0, 2.0, 4.0, 8.0)
 VARIANTS = (64, 65, 0, 1)
 WORK_CUTS = ((10, 2560), (16, 4096), (8, 2048))
-GRAPH_ITERS = (16, 32)
+GRAPH_ITERS = (32, 16)
 
 
 def _sync():

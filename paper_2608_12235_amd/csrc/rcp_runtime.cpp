@@ -1121,7 +1121,7 @@ void rcp_tuning_default(rcp_tuning *t)
     if (!t) return;
     std::memset(t, 0, sizeof *t);
     t->size = sizeof(rcp_tuning);
-    t->graph_iters = 16;
+    t->graph_iters = 32;
     t->xcd_remap = 1;
     t->fused_tail = 0;
     t->variant = 64;   // cooperative pair search
