@@ -11,7 +11,7 @@ import time
 
 import numpy as np
 
-from .api import Packing, make_params
+from .api import Packing, make_params, make_tuning
 
 
 def _sync():
@@ -23,10 +23,18 @@ def _sync():
         pass
 
 
+def census_tuning():
+    """Library defaults with 16-iteration graphs: small packings ask for a
+    list build every few tens of iterations and sit idle for the rest of the
+    graph once they have asked."""
+    return make_tuning(graph_iters=16)
+
+
 def run_batched(workloads, params=None, tuning=None, schedules=None, max_iters=0):
     """One context for all workloads (objects with d0, L, seed); returns
     (results, seconds of the inflation run, stats)."""
     params = params if params is not None else make_params()
+    tuning = tuning if tuning is not None else census_tuning()
     p = Packing([w.d0 for w in workloads], [w.L for w in workloads], 1.0,
                 [w.seed for w in workloads], init="rsa", params=params, tuning=tuning)
     try:
@@ -44,6 +52,7 @@ def run_loop(workloads, params=None, tuning=None, schedules=None, max_iters=0, l
     """The same workloads as one plain solve each; returns (results, summed
     seconds of the inflation runs)."""
     params = params if params is not None else make_params()
+    tuning = tuning if tuning is not None else census_tuning()
     out, total = [], 0.0
     for k, w in enumerate(workloads):
         p = Packing(w.d0, w.L, 1.0, w.seed, init="rsa", params=params, tuning=tuning)
@@ -74,7 +83,7 @@ def run_autotuned(workloads, params=None, warmup=1000, trial_iters=400, log=None
     from . import autotune
     params = params if params is not None else make_params()
     p = Packing([w.d0 for w in workloads], [w.L for w in workloads], 1.0,
-                [w.seed for w in workloads], init="rsa", params=params)
+                [w.seed for w in workloads], init="rsa", params=params, tuning=census_tuning())
     try:
         _sync()
         t0 = time.perf_counter()

@@ -1,5 +1,6 @@
 // Stable LSD radix sort of (u64 key, u32 value) pairs and of u64 keys, for
-// the neighbour-list build (Morton ordering, entry sort).
+// the neighbour-list build (Morton ordering, entry sort), of several arrays
+// at once.
 //
 // Sort: 8-bit digits, tiles of 2048 keys (256 threads x 8 rounds).  Per pass:
 // per-tile digit histogram -> per digit, an exclusive scan over the tiles
@@ -39,29 +40,63 @@ __device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t *total)
 }
 
 // ---------------------------------------------------------------- sort
-__global__ __launch_bounds__(kBlock) void k_radix_hist(const uint64_t *__restrict__ keys,
-                                                      int64_t n, int shift, int64_t nt,
+// Several independent arrays (segments) are sorted by one sequence of
+// launches: every launch covers the tiles of all segments, a block finding
+// its segment by binary search over the segments' first tiles.  Histograms
+// are laid out per segment, digit-major: hist[256 t0 + d nt + t].
+
+// Segment of tile b: the last segment whose first tile is <= b.
+__device__ __forceinline__ int seg_of_tile(const SortSeg *__restrict__ sg, int nseg, int64_t b)
+{
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sg[mid].t0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_radix_hist(const SortSeg *__restrict__ sg, int nseg,
+                                                      int par, int shift,
                                                       uint32_t *__restrict__ hist)
 {
     __shared__ uint32_t cnt[256];
     cnt[threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const int j = seg_of_tile(sg, nseg, blockIdx.x);
+    const int64_t n = sg[j].n, t0 = sg[j].t0, nt = sg[j].nt;
+    const int64_t t = (int64_t)blockIdx.x - t0;
+    // pointers read from memory: global-address-space views keep the loads
+    // off the flat path (which would also wait on the LDS atomics)
+    const gptr<const uint64_t> keys = (gptr<const uint64_t>)(par ? sg[j].k[1] : sg[j].k[0]);
+    // all eight loads in flight together (clamped indices: a tile holds at
+    // least one key)
+    const int64_t base = t * kTile;
+    uint64_t kk[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        int64_t i = base + k * kBlock + threadIdx.x;
-        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 255u], 1u);
+        const int64_t i = base + k * kBlock + threadIdx.x;
+        kk[k] = keys[i < n ? i : n - 1];
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nt + blockIdx.x] = cnt[threadIdx.x];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int64_t i = base + k * kBlock + threadIdx.x;
+        if (i < n) atomicAdd(&cnt[(kk[k] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[256 * t0 + (int64_t)threadIdx.x * nt + t] = cnt[threadIdx.x];
 }
 
-// Block d: exclusive scan, in place, of digit d's tile counts hist[d * nt
-// .. d * nt + nt) (tile order), and the digit's total to totals[d].
-__global__ __launch_bounds__(kBlock) void k_radix_rowscan(uint32_t *__restrict__ hist, int64_t nt,
+// Block (j, d): exclusive scan, in place, of digit d's tile counts in
+// segment j (tile order), and the digit's total to totals[256 j + d].
+__global__ __launch_bounds__(kBlock) void k_radix_rowscan(const SortSeg *__restrict__ sg,
+                                                         uint32_t *__restrict__ hist,
                                                          uint32_t *__restrict__ totals)
 {
-    uint32_t *row = hist + (int64_t)blockIdx.x * nt;
+    const int j = (int)(blockIdx.x >> 8), d = (int)(blockIdx.x & 255u);
+    const int64_t nt = sg[j].nt;
+    uint32_t *row = hist + 256 * sg[j].t0 + (int64_t)d * nt;
     uint32_t carry = 0;
     for (int64_t base = 0; base < nt; base += 4 * kBlock) {
         const int64_t i0 = base + (int64_t)threadIdx.x * 4;
@@ -84,32 +119,48 @@ __global__ __launch_bounds__(kBlock) void k_radix_rowscan(uint32_t *__restrict__
 }
 
 template <bool kVals>
-__global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint64_t *__restrict__ kin,
-                                                         const uint32_t *__restrict__ vin,
-                                                         uint64_t *__restrict__ kout,
-                                                         uint32_t *__restrict__ vout,
-                                                         int64_t n, int shift, int64_t nt,
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(const SortSeg *__restrict__ sg, int nseg,
+                                                         int par, int shift,
                                                          const uint32_t *__restrict__ off,
                                                          const uint32_t *__restrict__ totals)
 {
     __shared__ uint32_t base[256];
     __shared__ uint32_t wcnt[kWavesPerBlock][257];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    // first position of digit threadIdx.x: the totals of smaller digits plus
-    // this digit's count in earlier tiles
+    const int j = seg_of_tile(sg, nseg, blockIdx.x);
+    const int64_t n = sg[j].n, t0 = sg[j].t0, nt = sg[j].nt;
+    const int64_t t = (int64_t)blockIdx.x - t0;
+    const gptr<const uint64_t> kin = (gptr<const uint64_t>)(par ? sg[j].k[1] : sg[j].k[0]);
+    const gptr<uint64_t> kout = (gptr<uint64_t>)(par ? sg[j].k[0] : sg[j].k[1]);
+    const gptr<const uint32_t> vin = (gptr<const uint32_t>)(par ? sg[j].v[1] : sg[j].v[0]);
+    const gptr<uint32_t> vout = (gptr<uint32_t>)(par ? sg[j].v[0] : sg[j].v[1]);
+    // the tile's keys (and values) are loaded up front, all in flight
+    // together (clamped indices: a tile holds at least one key)
+    const int64_t tile = t * kTile;
+    uint64_t kk[8];
+    uint32_t vv[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int64_t i = tile + r * kBlock + threadIdx.x;
+        const int64_t ic = i < n ? i : n - 1;
+        kk[r] = kin[ic];
+        vv[r] = kVals ? vin[ic] : 0u;
+    }
+    // first position of digit threadIdx.x: the segment's totals of smaller
+    // digits plus this digit's count in its earlier tiles
     uint32_t all;
-    const uint32_t dbase = block_exclusive(totals[threadIdx.x], &all);
-    base[threadIdx.x] = dbase + off[(int64_t)threadIdx.x * nt + blockIdx.x];
+    const uint32_t dbase = block_exclusive(totals[256 * j + threadIdx.x], &all);
+    base[threadIdx.x] = dbase + off[256 * t0 + (int64_t)threadIdx.x * nt + t];
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-    const int64_t tile = (int64_t)blockIdx.x * kTile;
+#pragma unroll
     for (int r = 0; r < 8; ++r) {
         for (int k = threadIdx.x; k < kWavesPerBlock * 257; k += kBlock)
             (&wcnt[0][0])[k] = 0;
         __syncthreads();
         const int64_t i = tile + r * kBlock + threadIdx.x;
         const bool valid = i < n;
-        uint64_t key = valid ? kin[i] : 0ull;
-        uint32_t val = (kVals && valid) ? vin[i] : 0u;
+        uint64_t key = kk[r];
+        uint32_t val = vv[r];
         uint32_t d = valid ? (uint32_t)((key >> shift) & 255u) : 256u;
         uint64_t peers = ~0ull;
 #pragma unroll
@@ -135,45 +186,47 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint64_t *__rest
     }
 }
 
-int radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, int nbits,
-               uint32_t *hist, uint32_t *totals, hipStream_t s)
+// Segment descriptors travel as kernel arguments (no copy engine, no host
+// staging that must outlive the call), kSegChunk per launch.
+constexpr int kSegChunk = 32;
+struct SegChunk {
+    SortSeg s[kSegChunk];
+};
+
+__global__ void k_put_segs(SortSeg *__restrict__ dst, SegChunk c, int n)
 {
-    if (n <= 1) return 0;
-    const int64_t nt = (n + kTile - 1) / kTile;
-    int parity = 0;
-    for (int shift = 0; shift < nbits; shift += 8) {
-        const uint64_t *ki = parity ? k1 : k0;
-        const uint32_t *vi = parity ? v1 : v0;
-        uint64_t *ko = parity ? k0 : k1;
-        uint32_t *vo = parity ? v0 : v1;
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nt), dim3(kBlock), 0, s, ki, n, shift,
-                           nt, hist);
-        hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(kBlock), 0, s, hist, nt, totals);
-        hipLaunchKernelGGL(k_radix_scatter<true>, dim3((unsigned)nt), dim3(kBlock), 0, s, ki, vi,
-                           ko, vo, n, shift, nt, hist, totals);
-        parity ^= 1;
-    }
-    return parity;
+    if ((int)threadIdx.x < n) dst[threadIdx.x] = c.s[threadIdx.x];
 }
 
-int radix_sort_keys(uint64_t *k0, uint64_t *k1, int64_t n, int nbits, uint32_t *hist,
-                    uint32_t *totals, hipStream_t s)
+void launch_put_segs(SortSeg *dst, const SortSeg *src, int nseg, hipStream_t s)
 {
-    if (n <= 1) return 0;
-    const int64_t nt = (n + kTile - 1) / kTile;
-    int parity = 0;
-    for (int shift = 0; shift < nbits; shift += 8) {
-        const uint64_t *ki = parity ? k1 : k0;
-        uint64_t *ko = parity ? k0 : k1;
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nt), dim3(kBlock), 0, s, ki, n, shift,
-                           nt, hist);
-        hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(kBlock), 0, s, hist, nt, totals);
-        hipLaunchKernelGGL(k_radix_scatter<false>, dim3((unsigned)nt), dim3(kBlock), 0, s, ki,
-                           (const uint32_t *)nullptr, ko, (uint32_t *)nullptr, n, shift, nt,
-                           hist, totals);
-        parity ^= 1;
+    for (int b = 0; b < nseg; b += kSegChunk) {
+        SegChunk c;
+        const int n = nseg - b < kSegChunk ? nseg - b : kSegChunk;
+        for (int q = 0; q < n; ++q) c.s[q] = src[b + q];
+        hipLaunchKernelGGL(k_put_segs, dim3(1), dim3(kSegChunk), 0, s, dst + b, c, n);
     }
-    return parity;
+}
+
+int radix_sort_segs(const SortSeg *sg, int nseg, int64_t ntiles, int nbits, bool vals,
+                    uint32_t *hist, uint32_t *totals, hipStream_t s)
+{
+    if (nseg <= 0 || ntiles <= 0) return 0;
+    int par = 0;
+    for (int shift = 0; shift < nbits; shift += 8) {
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)ntiles), dim3(kBlock), 0, s, sg, nseg,
+                           par, shift, hist);
+        hipLaunchKernelGGL(k_radix_rowscan, dim3((unsigned)(256 * nseg)), dim3(kBlock), 0, s, sg,
+                           hist, totals);
+        if (vals)
+            hipLaunchKernelGGL(k_radix_scatter<true>, dim3((unsigned)ntiles), dim3(kBlock), 0, s,
+                               sg, nseg, par, shift, hist, totals);
+        else
+            hipLaunchKernelGGL(k_radix_scatter<false>, dim3((unsigned)ntiles), dim3(kBlock), 0, s,
+                               sg, nseg, par, shift, hist, totals);
+        par ^= 1;
+    }
+    return par;
 }
 
 }  // namespace rcp

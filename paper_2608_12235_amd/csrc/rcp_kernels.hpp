@@ -5,14 +5,23 @@
 namespace rcp {
 
 // ------------------------------------------------------------ k_sort.hip
-// Stable LSD radix sort on the low nbits of the keys; returns 0 if the
-// result is in (k0, v0), 1 if in (k1, v1).  hist needs 256 * ceil(n/2048)
-// entries, totals 256.
-int radix_sort(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, int nbits,
-               uint32_t *hist, uint32_t *totals, hipStream_t s);
-// Same, keys only.
-int radix_sort_keys(uint64_t *k0, uint64_t *k1, int64_t n, int nbits, uint32_t *hist,
-                    uint32_t *totals, hipStream_t s);
+// One array of a segmented sort (device descriptor): keys k[0] (values
+// v[0], or nullptr) and the second buffers k[1], v[1]; n items in nt =
+// ceil(n / 2048) tiles, t0 = tiles of the segments before it.
+struct SortSeg {
+    uint64_t *k[2];
+    uint32_t *v[2];
+    int64_t n, t0, nt;
+};
+constexpr int64_t kSortTile = 2048;
+// Stable LSD radix sort of every segment sg[0..nseg) (device memory) on the
+// low nbits of its keys, by one sequence of launches over all ntiles
+// tiles; returns the buffer index (the same for all segments) that holds
+// the result.  hist needs 256 * ntiles entries, totals 256 * nseg.
+int radix_sort_segs(const SortSeg *sg, int nseg, int64_t ntiles, int nbits, bool vals,
+                    uint32_t *hist, uint32_t *totals, hipStream_t s);
+// Write nseg host descriptors to dst (device) in stream order.
+void launch_put_segs(SortSeg *dst, const SortSeg *src, int nseg, hipStream_t s);
 
 // -------------------------------------------------------- k_neighbor.hip
 struct LevelGrid {

@@ -113,17 +113,12 @@ struct Seg {
     bool built = false;
 };
 
-// Scratch of one list build in flight (sort buffers, cell tables) and the
-// stream it is queued on.
+// A stream for the per-packing steps of list builds and the cell tables
+// of the build running on it.
 struct BuildLane {
     hipStream_t st = nullptr;
     bool own = false;
     hipEvent_t ev = nullptr;
-    uint64_t *kA = nullptr, *kB = nullptr;
-    uint32_t *vA = nullptr, *vB = nullptr;
-    int64_t kcap = 0, kcapB = 0, vcap = 0, vcapB = 0;
-    uint32_t *hist = nullptr, *tiles = nullptr;   // radix histograms, digit totals
-    int64_t hist_cap = 0, tiles_cap = 0;
     HashSlot *hash = nullptr;
     int64_t hcap = 0;
     int2 *dense = nullptr;           // dense cell tables
@@ -151,6 +146,19 @@ struct rcp_ctx {
     // builds of several packings at once) on streams of their own
     std::vector<BuildLane> lanes;
     hipEvent_t fork_ev = nullptr;
+    // batch sort buffers: Morton keys and permutations of all packings being
+    // built (key and value ping-pong), the second buffer of the entry sort,
+    // histograms, digit totals, segment descriptors (device, pinned host)
+    uint64_t *skA = nullptr, *skB = nullptr;
+    uint32_t *svA = nullptr, *svB = nullptr;
+    int64_t skA_cap = 0, skB_cap = 0, svA_cap = 0, svB_cap = 0;
+    uint64_t *ltmp = nullptr;
+    int64_t ltmp_cap = 0;
+    uint32_t *shist = nullptr, *stot = nullptr;
+    int64_t shist_cap = 0, stot_cap = 0;
+    SortSeg *d_segs = nullptr;
+    int64_t segs_cap = 0;
+    std::vector<SortSeg> h_segs;
     uint64_t *larena = nullptr;      // list regions of the builds in flight
     int64_t larena_cap = 0;
     uint32_t *bcount = nullptr;      // their entry counts (device, pinned host)
@@ -298,12 +306,13 @@ static int bits_for(int64_t v)   // bits needed to hold values 0..v
 }
 
 // A list build is split at its one host round trip, the entry count of the
-// search: the front half (keys, sort, permutation, cell tables, search into
-// the packing's region of the list arena) of every packing that needs a
-// build is queued, the counts come back in one copy, and the back halves
-// (entry sort, rows, work items) follow.  Builds are spread over up to
-// kBuildLanes streams, each with its own sort buffers and cell tables, so
-// the builds of small packings run side by side.
+// search.  All packings that need a build are built as one batch: their
+// Morton keys are sorted by one segmented radix sort (one sequence of
+// launches for the batch), then each packing's permutation, cell tables and
+// search run on one of up to kBuildLanes streams (each with its own cell
+// tables, so small packings' builds run side by side); the entry counts
+// come back in one copy; one segmented sort orders every list by (row,
+// col), and the rows, work items and validity limits follow per packing.
 struct BuildJob {
     int k = 0;
     int lane = 0;
@@ -312,6 +321,7 @@ struct BuildJob {
     int nbits = 0, row_bits = 0;
     int64_t ndense = 0, hcap = 0;
     int64_t lcap = 0, loff = 0;   // list region: entries and offset in the arena
+    int64_t koff = 0;             // offset of the packing's keys in the batch key buffers
 };
 
 // Host arithmetic of a build of packing k at kb = kappa: grid levels, key
@@ -399,44 +409,48 @@ static int ensure_lanes(rcp_ctx *c, int nl)
     return RCP_OK;
 }
 
-// Grow each lane's scratch for the builds assigned to it and the list
-// arena for all of them (their streams are idle: buffers may be
-// reallocated).
+// Grow the lanes' cell tables, the batch key buffers, the list arena and
+// the sort scratch for the planned builds (every stream involved is idle:
+// buffers may be reallocated).
 static int build_grow(rcp_ctx *c, std::vector<BuildJob> &jobs, int nl)
 {
-    int64_t ltot = 0;
+    int64_t ltot = 0, ntot = 0, tiles = 0, ltiles = 0;
     for (auto &j : jobs) {
         j.loff = ltot;
         ltot += j.lcap;
+        j.koff = ntot;
+        ntot += j.a.n;
+        tiles += (j.a.n + kSortTile - 1) / kSortTile;
+        ltiles += (j.lcap + kSortTile - 1) / kSortTile;
     }
     for (int l = 0; l < nl; ++l) {
         BuildLane &L = c->lanes[l];
-        int64_t nmax = 0, lmax = 0, dmax = 0, hmax = 64;
+        int64_t dmax = 0, hmax = 64;
         for (auto &j : jobs) {
             if (j.lane != l) continue;
-            nmax = std::max(nmax, j.a.n);
-            lmax = std::max(lmax, j.lcap);
             dmax = std::max(dmax, j.ndense);
             hmax = std::max(hmax, j.hcap);
         }
-        // kA: Morton keys, then the second buffer of the entry sort; kB: keys
-        CHK(dgrow(&L.kA, &L.kcap, std::max(nmax, lmax)));
-        CHK(dgrow(&L.kB, &L.kcapB, nmax));
-        CHK(dgrow(&L.vA, &L.vcap, nmax));
-        CHK(dgrow(&L.vB, &L.vcapB, nmax));
-        const int64_t tiles = (std::max(nmax, lmax) + 2047) / 2048 + 1;
-        CHK(dgrow(&L.hist, &L.hist_cap, 256 * tiles + 1));
-        CHK(dgrow(&L.tiles, &L.tiles_cap, 256));
         if (dmax > 0) CHK(dgrow(&L.dense, &L.dense_cap, dmax));
         CHK(dgrow(&L.hash, &L.hcap, hmax));
     }
+    const int64_t J = (int64_t)jobs.size();
+    CHK(dgrow(&c->skA, &c->skA_cap, ntot));
+    CHK(dgrow(&c->skB, &c->skB_cap, ntot));
+    CHK(dgrow(&c->svA, &c->svA_cap, ntot));
+    CHK(dgrow(&c->svB, &c->svB_cap, ntot));
     CHK(dgrow(&c->larena, &c->larena_cap, ltot));
-    CHK(dgrow(&c->bcount, &c->bcount_cap, (int64_t)jobs.size()));
-    if ((int64_t)jobs.size() > c->h_bcount_cap) {
+    CHK(dgrow(&c->ltmp, &c->ltmp_cap, ltot));
+    CHK(dgrow(&c->shist, &c->shist_cap, 256 * std::max(tiles, ltiles)));
+    CHK(dgrow(&c->stot, &c->stot_cap, 256 * J));
+    CHK(dgrow(&c->d_segs, &c->segs_cap, J));
+    CHK(dgrow(&c->bcount, &c->bcount_cap, J));
+    if ((int64_t)c->h_segs.size() < J) c->h_segs.resize(J);
+    if (J > c->h_bcount_cap) {
         if (c->h_bcount) (void)hipHostFree(c->h_bcount);
         c->h_bcount = nullptr;
         c->h_bcount_cap = 0;
-        const int64_t cap = std::max<int64_t>(64, 2 * (int64_t)jobs.size());
+        const int64_t cap = std::max<int64_t>(64, 2 * J);
         const hipError_t e = hipHostMalloc((void **)&c->h_bcount, sizeof(uint32_t) * cap, 0);
         if (e != hipSuccess) return fail(RCP_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
         c->h_bcount_cap = cap;
@@ -444,84 +458,29 @@ static int build_grow(rcp_ctx *c, std::vector<BuildJob> &jobs, int nl)
     return RCP_OK;
 }
 
-// Front half of a build: keys at the current positions, stable sort,
-// permutation of every per-particle array, cell tables, and one search pass
-// appending every pair in both directions to the job's list region; the
-// entry count goes to *counter.
-static void build_front(rcp_ctx *c, BuildJob &j, uint32_t *counter)
+// Sort the segments h_segs[0..J) (host descriptors: t0 and nt are filled
+// in here; they are passed to the device as kernel arguments) on the
+// context's stream; *par receives the buffer index holding the results.
+static int sort_segments(rcp_ctx *c, int J, int nbits, bool vals, int *par)
 {
-    Seg &s = c->segs[j.k];
-    BuildLane &B = c->lanes[j.lane];
-    hipStream_t st = B.st;
-    BuildArgs &a = j.a;
-    const int64_t n = s.n;
-    const int cur = s.cur, ncur = cur ^ 1, set = s.set, nset = set ^ 1;
-    a.pos = s.Q[cur];
-    a.lev = s.LEV[set];
-    launch_keys(a, B.kA, B.vA, st);
-    const int par = radix_sort(B.kA, B.vA, B.kB, B.vB, n, j.nbits, B.hist, B.tiles, st);
-    PermArgs pa;
-    pa.n = n;
-    pa.perm = par ? B.vB : B.vA;
-    pa.ps = s.Q[cur];
-    pa.pd = s.Q[ncur];
-    for (int ax = 0; ax < 3; ++ax) {
-        pa.xref[ax] = s.XREF[ax];
-        pa.ms[ax] = s.M[set][ax];
-        pa.md[ax] = s.M[nset][ax];
-        pa.vs[ax] = s.V[set][ax];
-        pa.vd[ax] = s.V[nset][ax];
+    int64_t t = 0;
+    for (int q = 0; q < J; ++q) {
+        c->h_segs[q].t0 = t;
+        c->h_segs[q].nt = (c->h_segs[q].n + kSortTile - 1) / kSortTile;
+        t += c->h_segs[q].nt;
     }
-    pa.os = s.ORIG[set];
-    pa.od = s.ORIG[nset];
-    pa.ls = s.LEV[set];
-    pa.ld = s.LEV[nset];
-    launch_permute(pa, st);
-    s.set = nset;
-    s.cur = ncur;
-    a.pos = s.Q[ncur];
-    a.lev = s.LEV[nset];
-    a.skey = par ? B.kB : B.kA;
-    a.hash = B.hash;
-    a.hmask = (uint64_t)j.hcap - 1;
-    a.dense = B.dense;
-    launch_hash_build(a, j.hcap, j.ndense, counter, st);
-    launch_search(a, c->larena + j.loff, counter, j.lcap, j.row_bits, c->tuning.xcd_remap,
-                  (c->tuning.variant >> 6) & 1, st);
+    launch_put_segs(c->d_segs, c->h_segs.data(), J, c->stream);
+    *par = radix_sort_segs(c->d_segs, J, t, nbits, vals, c->shist, c->stot, c->stream);
+    HIPCHK(hipGetLastError());
+    return RCP_OK;
 }
 
-// Back half, m entries in the job's list region: sort them by (row, col)
-// into full rows with partners ascending, row pointers and columns, work
-// items (*relayout when the packing's slots are too few: the caller lays
-// out the work table again), validity limits.
-static int build_back(rcp_ctx *c, BuildJob &j, int64_t m, bool *relayout)
+// Lanes 1..nl-1 wait for the context's stream.
+static int fork_lanes(rcp_ctx *c, int nl)
 {
-    Seg &s = c->segs[j.k];
-    BuildLane &B = c->lanes[j.lane];
-    hipStream_t st = B.st;
-    const int64_t n = s.n;
-    uint64_t *list = c->larena + j.loff;
-    s.list_est = m;
-    const int lp = radix_sort_keys(list, B.kA, m, 2 * j.row_bits, B.hist, B.tiles, st);
-    launch_csr_from_sorted(lp ? B.kA : list, m, j.row_bits, n, s.rp, s.col, st);
-    s.built = true;
-    if (slots_for(c, n, m) > s.blocks) {
-        s.slot_entries = m + m / 4;
-        *relayout = true;
-    } else {
-        fill_items(c, j.k, st);
-    }
-    const double sk = c->params.skin_s, opg = 1.0 + c->params.skin_g;
-    const double lim = sk * j.kappa * s.d0min * (1.0 - 1e-9);
-    SegPtrs pp;
-    ptrs_of(s, pp);
-    launch_after_build(c->d_state, c->d_ptrs, j.k, j.kappa, lim, opg * j.kappa * (1.0 - 1e-12),
-                       s.cur, pp, st);
-    HIPCHK(hipGetLastError());
-    s.npairs = m / 2;
-    s.nnz = m;
-    s.rebuilds += 1;
-    c->stats.rebuilds += 1;
+    if (nl <= 1) return RCP_OK;
+    HIPCHK(hipEventRecord(c->fork_ev, c->stream));
+    for (int l = 1; l < nl; ++l) HIPCHK(hipStreamWaitEvent(c->lanes[l].st, c->fork_ev, 0));
     return RCP_OK;
 }
 
@@ -532,6 +491,126 @@ static int join_lanes(rcp_ctx *c, int nl)
         HIPCHK(hipEventRecord(c->lanes[l].ev, c->lanes[l].st));
         HIPCHK(hipStreamWaitEvent(c->stream, c->lanes[l].ev, 0));
     }
+    return RCP_OK;
+}
+
+// Front half of a batch of builds: Morton keys at the current positions,
+// one segmented sort, then per packing (on its lane) the permutation of
+// every per-particle array, the cell tables, and one search pass appending
+// every pair in both directions to its list region; the entry count of
+// jobs[q] goes to bcount[q].  Leaves the lanes forked.
+static int build_fronts(rcp_ctx *c, std::vector<BuildJob> &jobs, int nl)
+{
+    const int J = (int)jobs.size();
+    int nbits = 1;
+    for (int q = 0; q < J; ++q) {
+        BuildJob &j = jobs[q];
+        Seg &s = c->segs[j.k];
+        j.a.pos = s.Q[s.cur];
+        j.a.lev = s.LEV[s.set];
+        launch_keys(j.a, c->skA + j.koff, c->svA + j.koff, c->stream);
+        SortSeg &g = c->h_segs[q];
+        g.k[0] = c->skA + j.koff;
+        g.k[1] = c->skB + j.koff;
+        g.v[0] = c->svA + j.koff;
+        g.v[1] = c->svB + j.koff;
+        g.n = j.a.n;
+        nbits = std::max(nbits, j.nbits);
+    }
+    int par = 0;
+    CHK(sort_segments(c, J, nbits, true, &par));
+    CHK(fork_lanes(c, nl));
+    for (int q = 0; q < J; ++q) {
+        BuildJob &j = jobs[q];
+        Seg &s = c->segs[j.k];
+        BuildLane &B = c->lanes[j.lane];
+        hipStream_t st = B.st;
+        BuildArgs &a = j.a;
+        const int cur = s.cur, ncur = cur ^ 1, set = s.set, nset = set ^ 1;
+        PermArgs pa;
+        pa.n = s.n;
+        pa.perm = (par ? c->svB : c->svA) + j.koff;
+        pa.ps = s.Q[cur];
+        pa.pd = s.Q[ncur];
+        for (int ax = 0; ax < 3; ++ax) {
+            pa.xref[ax] = s.XREF[ax];
+            pa.ms[ax] = s.M[set][ax];
+            pa.md[ax] = s.M[nset][ax];
+            pa.vs[ax] = s.V[set][ax];
+            pa.vd[ax] = s.V[nset][ax];
+        }
+        pa.os = s.ORIG[set];
+        pa.od = s.ORIG[nset];
+        pa.ls = s.LEV[set];
+        pa.ld = s.LEV[nset];
+        launch_permute(pa, st);
+        s.set = nset;
+        s.cur = ncur;
+        a.pos = s.Q[ncur];
+        a.lev = s.LEV[nset];
+        a.skey = (par ? c->skB : c->skA) + j.koff;
+        a.hash = B.hash;
+        a.hmask = (uint64_t)j.hcap - 1;
+        a.dense = B.dense;
+        launch_hash_build(a, j.hcap, j.ndense, c->bcount + q, st);
+        launch_search(a, c->larena + j.loff, c->bcount + q, j.lcap, j.row_bits,
+                      c->tuning.xcd_remap, (c->tuning.variant >> 6) & 1, st);
+    }
+    HIPCHK(hipGetLastError());
+    return RCP_OK;
+}
+
+// Back half for the jobs listed in qs, ms[q] entries in each list region:
+// one segmented sort by (row, col) (full rows, partners ascending), then
+// per packing (on its lane) row pointers and columns, work items
+// (*relayout when a packing's slots are too few: the caller lays out the
+// work table again) and the validity limits.  Leaves the lanes forked.
+static int build_backs(rcp_ctx *c, std::vector<BuildJob> &jobs, const std::vector<int> &qs,
+                       const std::vector<int64_t> &ms, int nl, bool *relayout)
+{
+    const int J = (int)qs.size();
+    if (J == 0) return RCP_OK;
+    int nbits = 1;
+    for (int r = 0; r < J; ++r) {
+        const BuildJob &j = jobs[qs[r]];
+        SortSeg &g = c->h_segs[r];
+        g.k[0] = c->larena + j.loff;
+        g.k[1] = c->ltmp + j.loff;
+        g.v[0] = g.v[1] = nullptr;
+        g.n = ms[qs[r]];
+        nbits = std::max(nbits, 2 * j.row_bits);
+    }
+    int par = 0;
+    CHK(sort_segments(c, J, nbits, false, &par));
+    CHK(fork_lanes(c, nl));
+    const double sk = c->params.skin_s, opg = 1.0 + c->params.skin_g;
+    for (int r = 0; r < J; ++r) {
+        BuildJob &j = jobs[qs[r]];
+        const int64_t m = ms[qs[r]];
+        Seg &s = c->segs[j.k];
+        hipStream_t st = c->lanes[j.lane].st;
+        const int64_t n = s.n;
+        s.list_est = m;
+        launch_csr_from_sorted((par ? c->ltmp : c->larena) + j.loff, m, j.row_bits, n, s.rp, s.col,
+                               st);
+        s.built = true;
+        if (slots_for(c, n, m) > s.blocks) {
+            s.slot_entries = m + m / 4;
+            *relayout = true;
+        } else {
+            fill_items(c, j.k, st);
+        }
+        const double lim = sk * j.kappa * s.d0min * (1.0 - 1e-9);
+        SegPtrs pp;
+        ptrs_of(s, pp);
+        launch_after_build(c->d_state, c->d_ptrs, j.k, j.kappa, lim,
+                           opg * j.kappa * (1.0 - 1e-12), s.cur, pp, st);
+        s.npairs = m / 2;
+        s.nnz = m;
+        s.rebuilds += 1;
+        c->stats.rebuilds += 1;
+    }
+    HIPCHK(hipGetLastError());
     return RCP_OK;
 }
 
@@ -574,11 +653,7 @@ static int rebuild_batch(rcp_ctx *c, const std::vector<int> &ks, const std::vect
     std::pair<hipEvent_t, hipEvent_t> ev;
     CHK(rebuild_events(c, ev));
     HIPCHK(hipEventRecord(ev.first, c->stream));
-    if (nl > 1) {
-        HIPCHK(hipEventRecord(c->fork_ev, c->stream));
-        for (int l = 1; l < nl; ++l) HIPCHK(hipStreamWaitEvent(c->lanes[l].st, c->fork_ev, 0));
-    }
-    for (int q : order) build_front(c, jobs[q], c->bcount + q);
+    CHK(build_fronts(c, jobs, nl));
     CHK(join_lanes(c, nl));
     HIPCHK(hipMemcpyAsync(c->h_bcount, c->bcount, sizeof(uint32_t) * jobs.size(),
                           hipMemcpyDeviceToHost, c->stream));
@@ -586,13 +661,14 @@ static int rebuild_batch(rcp_ctx *c, const std::vector<int> &ks, const std::vect
     HIPCHK(hipGetLastError());
     // columns sized before any back half is queued
     std::vector<int64_t> ms(jobs.size());
-    std::vector<int> redo;
+    std::vector<int> ok, redo;
     for (size_t q = 0; q < jobs.size(); ++q) {
         ms[q] = (int64_t)c->h_bcount[q];
         if (ms[q] > jobs[q].lcap) {
             redo.push_back((int)q);
             continue;
         }
+        ok.push_back((int)q);
         Seg &s = c->segs[jobs[q].k];
         if (ms[q] > s.col_cap) {
             dfree(s.col);
@@ -601,8 +677,7 @@ static int rebuild_batch(rcp_ctx *c, const std::vector<int> &ks, const std::vect
         }
     }
     bool relayout = false;
-    for (int q : order)
-        if (ms[q] <= jobs[q].lcap) CHK(build_back(c, jobs[q], ms[q], &relayout));
+    CHK(build_backs(c, jobs, ok, ms, nl, &relayout));
     CHK(join_lanes(c, nl));
     // a list that outgrew its region is built again on its own, sized for
     // the count just seen (its particles are already in list order, so the
@@ -613,19 +688,19 @@ static int rebuild_batch(rcp_ctx *c, const std::vector<int> &ks, const std::vect
         one[0].lane = 0;
         HIPCHK(hipStreamSynchronize(c->stream));
         CHK(build_grow(c, one, 1));
-        build_front(c, one[0], c->bcount);
+        CHK(build_fronts(c, one, 1));
         HIPCHK(hipMemcpyAsync(c->h_bcount, c->bcount, sizeof(uint32_t), hipMemcpyDeviceToHost,
                               c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
-        const int64_t m = (int64_t)c->h_bcount[0];
-        if (m > one[0].lcap) return fail(RCP_ENOMEM, "pair list overflow after regrowth");
+        std::vector<int64_t> m1(1, (int64_t)c->h_bcount[0]);
+        if (m1[0] > one[0].lcap) return fail(RCP_ENOMEM, "pair list overflow after regrowth");
         Seg &s = c->segs[jobs[q].k];
-        if (m > s.col_cap) {
+        if (m1[0] > s.col_cap) {
             dfree(s.col);
-            s.col_cap = std::max<int64_t>(m + m / 4, 1024);
+            s.col_cap = std::max<int64_t>(m1[0] + m1[0] / 4, 1024);
             CHK(dalloc(&s.col, (size_t)s.col_cap));
         }
-        CHK(build_back(c, one[0], m, &relayout));
+        CHK(build_backs(c, one, std::vector<int>{0}, m1, 1, &relayout));
     }
     HIPCHK(hipEventRecord(ev.second, c->stream));
     c->rb_pending.push_back(ev);
@@ -1060,12 +1135,6 @@ static void destroy_ctx(rcp_ctx *c)
     dfree(c->d_partials);
     for (auto &L : c->lanes) {
         if (L.own && L.st) (void)hipStreamSynchronize(L.st);
-        dfree(L.kA);
-        dfree(L.kB);
-        dfree(L.vA);
-        dfree(L.vB);
-        dfree(L.hist);
-        dfree(L.tiles);
         dfree(L.hash);
         dfree(L.dense);
         if (L.ev) (void)hipEventDestroy(L.ev);
@@ -1074,6 +1143,14 @@ static void destroy_ctx(rcp_ctx *c)
     c->lanes.clear();
     if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
     dfree(c->totals);
+    dfree(c->skA);
+    dfree(c->skB);
+    dfree(c->svA);
+    dfree(c->svB);
+    dfree(c->ltmp);
+    dfree(c->shist);
+    dfree(c->stot);
+    dfree(c->d_segs);
     dfree(c->larena);
     dfree(c->bcount);
     if (c->h_bcount) (void)hipHostFree(c->h_bcount);
