@@ -76,7 +76,7 @@ def particle_updates(results, workloads):
     return float(sum(r["iterations"] * w.n for r, w in zip(results, workloads)))
 
 
-def run_autotuned(workloads, params=None, warmup=1000, trial_iters=400, log=None):
+def run_autotuned(workloads, params=None, warmup=1000, trial_iters=200, log=None):
     """One context for all workloads: warm-up iterations, autotuner trials
     (which continue the run), then the rest of the run.  Returns (results,
     seconds of the whole run including the trials, chosen settings)."""
