@@ -148,7 +148,9 @@ __device__ __forceinline__ void gstore(T *base, int64_t i, T v)
 // +-L/2 no shift is applied.
 __device__ __forceinline__ double min_image(double d, double L, double hL)
 {
-    return d > hL ? d - L : (d < -hL ? d + L : d);
+    // d > hL gives d - L and d < -hL gives d - (-L) = d + L exactly: one
+    // compare on |d| and one select instead of two of each
+    return fabs(d) > hL ? d - copysign(L, d) : d;
 }
 
 // ------------------------------------------------------------ reductions
