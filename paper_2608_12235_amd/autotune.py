@@ -18,7 +18,7 @@ from .api import make_tuning
 SKINS = (1.0, 2.0, 4.0)
 VARIANTS = (64, 65)
 WORK_CUTS = ((10, 2560), (16, 4096))
-GRAPH_ITERS = (16, 32)
+GRAPH_ITERS = (8, 16, 32)
 
 
 def _sync():
