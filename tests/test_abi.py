@@ -83,6 +83,24 @@ def test_invalid_arguments_rejected_without_device(L):
     assert lib.rcp_pack_init(3, box, 3, dp, 1.0, 0, 9, None, None, C.byref(h)) == L.RCP_EINVAL
     s = L.Schedule()
     assert lib.rcp_schedule_default(0, 3, 1.0, 2, 9, 5000, C.byref(s)) == L.RCP_EINVAL
+    # an explicit eps_x below 1e-100 is refused (the position update neglects
+    # sqrt(v) below 1e-100 next to eps_x)
+    pr = L.Params()
+    lib.rcp_params_default(C.byref(pr))
+    pr.eps_x = 1e-120
+    assert lib.rcp_pack_init(3, box, 3, dp, 1.0, 0, 1, C.byref(pr), None, C.byref(h)) == L.RCP_EINVAL
+    assert b"rcp_params" in lib.rcp_last_error()
+
+
+def test_tuning_defaults(L):
+    lib = L.lib()
+    t = L.Tuning()
+    lib.rcp_tuning_default(C.byref(t))
+    assert t.size == C.sizeof(L.Tuning)
+    assert (t.graph_iters, t.xcd_remap, t.fused_tail, t.variant) == (32, 1, 0, 64)
+    assert (t.row_cost, t.item_work, t.time_kernels) == (10, 2560, 0)
+    # every item holds at most 256 rows: item_work <= 256 row_cost
+    assert t.item_work <= 256 * t.row_cost
 
 
 def test_oracle_not_reachable_from_package():
