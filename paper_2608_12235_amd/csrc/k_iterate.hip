@@ -915,32 +915,80 @@ void launch_items(const int32_t *rp, int64_t n, int seg, int row_cost, int item_
                        (int64_t)item_work, W, nslots);
 }
 
+// Segmented forms for a batch of list builds: block b of a grid belongs
+// to the last job whose first block is <= b.
+__device__ __forceinline__ int back_job_of(const BackJob *__restrict__ jobs, int J, int64_t b,
+                                           int64_t BackJob::*first)
+{
+    int lo = 0, hi = J - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].*first <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_items_fill_seg(const BackJob *__restrict__ jobs, int J)
+{
+    const BackJob &B = jobs[back_job_of(jobs, J, blockIdx.x, &BackJob::bs0)];
+    const int64_t b = ((int64_t)blockIdx.x - B.bs0) * kBlock + threadIdx.x;
+    if (!B.fill || b >= B.nslots) return;
+    WorkItem w;
+    w.seg = B.seg;
+    w.pad = 0;
+    w.begin = B.n;
+    w.end = B.n;
+    B.W[b] = w;
+}
+
+__global__ __launch_bounds__(kBlock) void k_items_seg(const BackJob *__restrict__ jobs, int J)
+{
+    const BackJob &B = jobs[back_job_of(jobs, J, blockIdx.x, &BackJob::br0)];
+    const int64_t i = ((int64_t)blockIdx.x - B.br0) * kBlock + threadIdx.x;
+    if (!B.fill || i >= B.n) return;
+    const int64_t rc = B.row_cost, wk = B.item_work;
+    const int64_t hi = rc * i + (int64_t)B.rp[i];
+    const int64_t bl = i == 0 ? 0 : (rc * (i - 1) + (int64_t)B.rp[i - 1]) / wk + 1;
+    const int64_t bh = min(hi / wk, B.nslots - 1);
+    for (int64_t b = bl; b <= bh; ++b) {
+        B.W[b].begin = i;
+        if (b > 0) B.W[b - 1].end = i;
+    }
+}
+
+__global__ void k_after_seg(const BackJob *__restrict__ jobs, int J, SegState *S, SegPtrs *P)
+{
+    const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (j >= J) return;
+    const BackJob &B = jobs[j];
+    SegState *s = S + B.seg;
+    s->kb = B.kb;
+    s->disp_lim = B.disp_lim;
+    s->kappa_lim = B.kappa_lim;
+    s->cur = B.cur;
+    s->flags &= ~(F_REBUILD | F_STALE);
+    P[B.seg] = B.ptrs;
+}
+
+void launch_items_seg(const BackJob *jobs, int J, int64_t nbs, int64_t nbr, hipStream_t st)
+{
+    if (nbs > 0)
+        hipLaunchKernelGGL(k_items_fill_seg, dim3((unsigned)nbs), dim3(kBlock), 0, st, jobs, J);
+    if (nbr > 0)
+        hipLaunchKernelGGL(k_items_seg, dim3((unsigned)nbr), dim3(kBlock), 0, st, jobs, J);
+}
+
+void launch_after_seg(const BackJob *jobs, int J, SegState *S, SegPtrs *P, hipStream_t st)
+{
+    if (J > 0)
+        hipLaunchKernelGGL(k_after_seg, dim3((unsigned)((J + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                           st, jobs, J, S, P);
+}
+
 void launch_tail(SegState *S, const double *partials, int nseg, hipStream_t st)
 {
     hipLaunchKernelGGL(k_tail, dim3(nseg), dim3(kTailBlock), 0, st, S, partials);
-}
-
-// ------------------------------------------------------- small updates
-// After a list build: the packing's list scale and validity limits, its
-// current buffer, the flags cleared, and its pointer table entry (written
-// in stream order, no host staging).
-__global__ void k_after_build(SegState *S, SegPtrs *P, int seg, double kb, double disp_lim,
-                              double kappa_lim, int cur, SegPtrs v)
-{
-    SegState *s = S + seg;
-    s->kb = kb;
-    s->disp_lim = disp_lim;
-    s->kappa_lim = kappa_lim;
-    s->cur = cur;
-    s->flags &= ~(F_REBUILD | F_STALE);
-    P[seg] = v;
-}
-
-void launch_after_build(SegState *S, SegPtrs *P, int seg, double kb, double disp_lim,
-                        double kappa_lim, int cur, const SegPtrs &v, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_after_build, dim3(1), dim3(1), 0, st, S, P, seg, kb, disp_lim,
-                       kappa_lim, cur, v);
 }
 
 __global__ void k_sched_start(SegState *S, int seg, SchedDev q, int reset_adam,

@@ -41,14 +41,13 @@ __device__ __forceinline__ uint64_t tile_of(int64_t c, int32_t nc, int32_t tiles
     return (uint64_t)((c * tiles) / nc);
 }
 
-__global__ __launch_bounds__(kBlock) void k_keys(BuildArgs a, uint64_t *__restrict__ keys,
-                                                uint32_t *__restrict__ vals)
+__device__ __forceinline__ void key_of(const BuildArgs &a, const P4 *__restrict__ pos,
+                                       const uint8_t *__restrict__ lev, int64_t i,
+                                       uint64_t *__restrict__ keys, uint32_t *__restrict__ vals)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= a.n) return;
-    const int l = a.lev[i];
+    const int l = lev[i];
     const LevelGrid g = a.lv[l];
-    const P4 q = a.pos[i];
+    const P4 q = pos[i];
     uint64_t cx = (uint64_t)cell_coord(q.x, g.inv_w, g.nc);
     uint64_t cy = (uint64_t)cell_coord(q.y, g.inv_w, g.nc);
     uint64_t cz = (uint64_t)cell_coord(q.z, g.inv_w, g.nc);
@@ -58,17 +57,8 @@ __global__ __launch_bounds__(kBlock) void k_keys(BuildArgs a, uint64_t *__restri
     vals[i] = (uint32_t)i;
 }
 
-void launch_keys(const BuildArgs &a, uint64_t *keys, uint32_t *vals, hipStream_t s)
+__device__ __forceinline__ void permute_one(const PermArgs &p, int64_t k)
 {
-    if (a.n <= 0) return;
-    hipLaunchKernelGGL(k_keys, dim3((unsigned)((a.n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                       a, keys, vals);
-}
-
-__global__ __launch_bounds__(kBlock) void k_permute(PermArgs p)
-{
-    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (k >= p.n) return;
     const int64_t s = p.perm[k];
     const P4 q = p.ps[s];
     p.pd[k] = q;
@@ -82,13 +72,6 @@ __global__ __launch_bounds__(kBlock) void k_permute(PermArgs p)
     }
     p.od[k] = p.os[s];
     p.ld[k] = p.ls[s];
-}
-
-void launch_permute(const PermArgs &p, hipStream_t s)
-{
-    if (p.n <= 0) return;
-    hipLaunchKernelGGL(k_permute, dim3((unsigned)((p.n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                       s, p);
 }
 
 // ------------------------------------------------------------- hashing
@@ -151,10 +134,8 @@ __device__ __forceinline__ int64_t dense_index(const BuildArgs &a, int64_t i)
 // A cell's sorted particles are contiguous (same key): the first one finds
 // the end of the run and writes (start, count), into the dense table of its
 // level or into the hash (inserted by compare-and-swap on the key).
-__global__ __launch_bounds__(kBlock) void k_cells(BuildArgs a)
+__device__ __forceinline__ void cells_one(const BuildArgs &a, int64_t i)
 {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= a.n) return;
     const uint64_t key = a.skey[i];
     if (i > 0 && a.skey[i - 1] == key) return;
     int64_t e = i + 1;
@@ -176,28 +157,6 @@ __global__ __launch_bounds__(kBlock) void k_cells(BuildArgs a)
         }
         slot = (slot + 1) & a.hmask;
     }
-}
-
-// Empty hash slots, zero dense cells (2 ndense words), zero *counter.
-__global__ void k_tables_clear(HashSlot *__restrict__ h, int64_t cap, uint32_t *__restrict__ dense,
-                               int64_t nd2, uint32_t *__restrict__ counter)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < cap) h[i].key = kEmptyKey;
-    if (i < nd2) dense[i] = 0u;
-    if (i == 0 && counter) *counter = 0u;
-}
-
-void launch_hash_build(const BuildArgs &a, int64_t cap, int64_t ndense, uint32_t *counter,
-                       hipStream_t s)
-{
-    const int64_t m = cap > 2 * ndense ? cap : 2 * ndense;
-    hipLaunchKernelGGL(k_tables_clear, dim3((unsigned)((m + kBlock - 1) / kBlock)), dim3(kBlock),
-                       0, s, a.hash, cap, reinterpret_cast<uint32_t *>(a.dense), 2 * ndense,
-                       counter);
-    if (a.n <= 0) return;
-    hipLaunchKernelGGL(k_cells, dim3((unsigned)((a.n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                       a);
 }
 
 // ------------------------------------------------------- pair search
@@ -602,13 +561,10 @@ void launch_search(const BuildArgs &a, uint64_t *list, uint32_t *counter, int64_
 // Row pointers and partners from the sorted entry list.  Entry q starts row
 // r = key >> row_bits; rows between the previous entry's row and r start at
 // q (empty rows included).  Thread m closes the rows after the last entry.
-__global__ __launch_bounds__(kBlock) void k_csr_from_sorted(const uint64_t *__restrict__ srt,
-                                                           int64_t m, int row_bits, int64_t n,
-                                                           int32_t *__restrict__ rp,
-                                                           int32_t *__restrict__ col)
+__device__ __forceinline__ void csr_one(const uint64_t *__restrict__ srt, int64_t m, int row_bits,
+                                        int64_t n, int32_t *__restrict__ rp,
+                                        int32_t *__restrict__ col, int64_t q)
 {
-    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (q > m) return;
     const uint64_t mask = (1ull << row_bits) - 1ull;
     const int64_t prev = q == 0 ? -1 : (int64_t)(srt[q - 1] >> row_bits);
     const int64_t r = q == m ? n : (int64_t)(srt[q] >> row_bits);
@@ -616,11 +572,79 @@ __global__ __launch_bounds__(kBlock) void k_csr_from_sorted(const uint64_t *__re
     for (int64_t rr = prev + 1; rr <= r; ++rr) rp[rr] = (int32_t)q;
 }
 
-void launch_csr_from_sorted(const uint64_t *sorted, int64_t m, int row_bits, int64_t n,
-                            int32_t *rp, int32_t *col, hipStream_t s)
+// ------------------------------------------- segmented build steps
+// Block b of a batch grid belongs to the last job whose first block is <= b.
+template <class T>
+__device__ __forceinline__ int job_of(const T *__restrict__ jobs, int J, int64_t b,
+                                      int64_t T::*first)
 {
-    hipLaunchKernelGGL(k_csr_from_sorted, dim3((unsigned)((m + 1 + kBlock - 1) / kBlock)),
-                       dim3(kBlock), 0, s, sorted, m, row_bits, n, rp, col);
+    int lo = 0, hi = J - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].*first <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_keys_seg(const FrontJob *__restrict__ jobs, int J)
+{
+    const FrontJob &F = jobs[job_of(jobs, J, blockIdx.x, &FrontJob::b0)];
+    const int64_t i = ((int64_t)blockIdx.x - F.b0) * kBlock + threadIdx.x;
+    if (i < F.a.n) key_of(F.a, F.pos0, F.lev0, i, F.keys, F.vals);
+}
+
+__global__ __launch_bounds__(kBlock) void k_permute_seg(const FrontJob *__restrict__ jobs, int J)
+{
+    const FrontJob &F = jobs[job_of(jobs, J, blockIdx.x, &FrontJob::b0)];
+    const int64_t k = ((int64_t)blockIdx.x - F.b0) * kBlock + threadIdx.x;
+    if (k < F.pa.n) permute_one(F.pa, k);
+}
+
+__global__ __launch_bounds__(kBlock) void k_tables_clear_seg(const FrontJob *__restrict__ jobs,
+                                                            int J)
+{
+    const FrontJob &F = jobs[job_of(jobs, J, blockIdx.x, &FrontJob::bt0)];
+    const int64_t i = ((int64_t)blockIdx.x - F.bt0) * kBlock + threadIdx.x;
+    if (i < F.hcap) F.a.hash[i].key = kEmptyKey;
+    if (i < F.nd2) reinterpret_cast<uint32_t *>(F.a.dense)[i] = 0u;
+    if (i == 0) *F.counter = 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cells_seg(const FrontJob *__restrict__ jobs, int J)
+{
+    const FrontJob &F = jobs[job_of(jobs, J, blockIdx.x, &FrontJob::b0)];
+    const int64_t i = ((int64_t)blockIdx.x - F.b0) * kBlock + threadIdx.x;
+    if (i < F.a.n) cells_one(F.a, i);
+}
+
+__global__ __launch_bounds__(kBlock) void k_csr_seg(const BackJob *__restrict__ jobs, int J)
+{
+    const BackJob &B = jobs[job_of(jobs, J, blockIdx.x, &BackJob::bc0)];
+    const int64_t q = ((int64_t)blockIdx.x - B.bc0) * kBlock + threadIdx.x;
+    if (q <= B.m) csr_one(B.srt, B.m, B.row_bits, B.n, B.rp, B.col, q);
+}
+
+void launch_keys_seg(const FrontJob *jobs, int J, int64_t nb, hipStream_t s)
+{
+    if (nb > 0) hipLaunchKernelGGL(k_keys_seg, dim3((unsigned)nb), dim3(kBlock), 0, s, jobs, J);
+}
+
+void launch_permute_seg(const FrontJob *jobs, int J, int64_t nb, hipStream_t s)
+{
+    if (nb > 0) hipLaunchKernelGGL(k_permute_seg, dim3((unsigned)nb), dim3(kBlock), 0, s, jobs, J);
+}
+
+void launch_tables_seg(const FrontJob *jobs, int J, int64_t nbt, int64_t nb, hipStream_t s)
+{
+    if (nbt > 0)
+        hipLaunchKernelGGL(k_tables_clear_seg, dim3((unsigned)nbt), dim3(kBlock), 0, s, jobs, J);
+    if (nb > 0) hipLaunchKernelGGL(k_cells_seg, dim3((unsigned)nb), dim3(kBlock), 0, s, jobs, J);
+}
+
+void launch_csr_seg(const BackJob *jobs, int J, int64_t nbc, hipStream_t s)
+{
+    if (nbc > 0) hipLaunchKernelGGL(k_csr_seg, dim3((unsigned)nbc), dim3(kBlock), 0, s, jobs, J);
 }
 
 // ------------------------------------------------------- statistics

@@ -66,7 +66,7 @@ struct SegState {
     int32_t pad_h;
     int32_t nblocks;      // iteration-grid blocks of this segment
     int64_t bfirst;       // first of them (index into the work table)
-    // set at each list build (k_after_build)
+    // set at each list build (k_after_seg)
     double kb, disp_lim, kappa_lim;
     int32_t pad0, pad0b;
     // reciprocals the iteration kernel would otherwise divide for in every

@@ -54,8 +54,6 @@ struct BuildArgs {
     LevelGrid lv[kMaxLevels];
 };
 
-void launch_keys(const BuildArgs &a, uint64_t *keys, uint32_t *vals, hipStream_t s);
-
 struct PermArgs {
     int64_t n;
     const uint32_t *perm;
@@ -67,13 +65,50 @@ struct PermArgs {
     const int32_t *os; int32_t *od;
     const uint8_t *ls; uint8_t *ld;
 };
-void launch_permute(const PermArgs &p, hipStream_t s);
 
-// Cell tables on the sorted particles: the hash for levels with dbase < 0,
-// the dense (start, count) arrays (ndense entries, cleared here) otherwise;
-// *counter (if given) is zeroed in the same launch.
-void launch_hash_build(const BuildArgs &a, int64_t cap, int64_t ndense, uint32_t *counter,
-                       hipStream_t s);
+// One packing of a batch of list builds as the segmented build kernels see
+// it (device table, one entry per packing; block ranges are prefixes over
+// the batch).
+struct FrontJob {
+    BuildArgs a;            // geometry, permuted positions / levels, sorted keys, tables
+    PermArgs pa;            // the permutation (pa.perm: sorted local indices)
+    const P4 *pos0;         // positions before the permutation (keys)
+    const uint8_t *lev0;
+    uint64_t *keys;         // Morton keys out
+    uint32_t *vals;         // local indices out
+    uint32_t *counter;      // search entry count, zeroed with the tables
+    int64_t hcap, nd2;      // hash slots and dense words to clear
+    int64_t b0;             // first block in the per-particle grids
+    int64_t bt0;            // first block in the table-clear grid
+};
+struct BackJob {
+    const uint64_t *srt;    // entries sorted by (row, col)
+    int64_t m, n;
+    int32_t row_bits, seg;
+    int32_t *rp, *col;
+    WorkItem *W;            // the packing's work-item slots
+    int64_t nslots;
+    int32_t row_cost, item_work;
+    int32_t fill;           // 1: cut the rows into the slots here
+    int32_t cur;
+    double kb, disp_lim, kappa_lim;
+    SegPtrs ptrs;
+    int64_t bc0;            // first block in the entry grid (m + 1 threads a packing)
+    int64_t bs0;            // first block in the slot grid
+    int64_t br0;            // first block in the row grid
+};
+// Front steps for all packings of a batch (jobs in device memory): Morton
+// keys (nb = blocks of the per-particle grid), permutation, cell tables
+// (nbt = blocks of the clear grid; clears the counters too).
+void launch_keys_seg(const FrontJob *jobs, int J, int64_t nb, hipStream_t s);
+void launch_permute_seg(const FrontJob *jobs, int J, int64_t nb, hipStream_t s);
+void launch_tables_seg(const FrontJob *jobs, int J, int64_t nbt, int64_t nb, hipStream_t s);
+// Back steps: rows and columns (nbc blocks), work items (nbs slot blocks,
+// nbr row blocks), validity limits and pointer entries.
+void launch_csr_seg(const BackJob *jobs, int J, int64_t nbc, hipStream_t s);
+void launch_items_seg(const BackJob *jobs, int J, int64_t nbs, int64_t nbr, hipStream_t s);
+void launch_after_seg(const BackJob *jobs, int J, SegState *S, SegPtrs *P, hipStream_t s);
+
 // One pass over the particles: every listed pair (i, j) is appended twice
 // to `list` as (row << row_bits) | col, rows and cols in sorted order, in an
 // arbitrary order; *counter (zeroed by the caller) receives the number of
@@ -81,9 +116,6 @@ void launch_hash_build(const BuildArgs &a, int64_t cap, int64_t ndense, uint32_t
 // the wave-cooperative form (same pairs, other append order).
 void launch_search(const BuildArgs &a, uint64_t *list, uint32_t *counter, int64_t cap,
                    int row_bits, int xcd_remap, int coop, hipStream_t s);
-// Full rows from the sorted entry list: rp[0..n] and col[0..m).
-void launch_csr_from_sorted(const uint64_t *sorted, int64_t m, int row_bits, int64_t n,
-                            int32_t *rp, int32_t *col, hipStream_t s);
 // *out = longest row (max rp[i+1] - rp[i]); out must be zeroed first.
 void launch_max_degree(int64_t n, const int32_t *rp, uint32_t *out, hipStream_t s);
 void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
@@ -101,10 +133,6 @@ void launch_items(const int32_t *rp, int64_t n, int seg, int row_cost, int item_
 void launch_iterate(const SegPtrs *P, SegState *S, const WorkItem *W, double *partials,
                     int nitems, int flags, hipStream_t s);
 void launch_tail(SegState *S, const double *partials, int nseg, hipStream_t s);
-// After a list build of segment seg: kb, validity limits, current buffer,
-// clear REBUILD / STALE.
-void launch_after_build(SegState *S, SegPtrs *P, int seg, double kb, double disp_lim,
-                        double kappa_lim, int cur, const SegPtrs &v, hipStream_t st);
 // Start a schedule on segment seg: copy the table, reset the position in it,
 // set the first rung's parameters from the current kappa.
 void launch_sched_start(SegState *S, int seg, const SchedDev &q, int reset_adam,

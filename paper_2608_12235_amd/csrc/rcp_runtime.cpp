@@ -113,16 +113,11 @@ struct Seg {
     bool built = false;
 };
 
-// A stream for the per-packing steps of list builds and the cell tables
-// of the build running on it.
+// A stream for the pair searches of a batch of list builds.
 struct BuildLane {
     hipStream_t st = nullptr;
     bool own = false;
     hipEvent_t ev = nullptr;
-    HashSlot *hash = nullptr;
-    int64_t hcap = 0;
-    int2 *dense = nullptr;           // dense cell tables
-    int64_t dense_cap = 0;
     int64_t load = 0;                // particles assigned in the current batch
 };
 
@@ -161,6 +156,13 @@ struct rcp_ctx {
     std::vector<SortSeg> h_segs;
     uint64_t *larena = nullptr;      // list regions of the builds in flight
     int64_t larena_cap = 0;
+    HashSlot *harena = nullptr;      // their cell hashes and dense cell tables
+    int64_t harena_cap = 0;
+    int2 *darena = nullptr;
+    int64_t darena_cap = 0;
+    FrontJob *d_fj = nullptr, *h_fj = nullptr;   // batch job tables (device, pinned host)
+    BackJob *d_bj = nullptr, *h_bj = nullptr;
+    int64_t fj_cap = 0, bj_cap = 0, hj_cap = 0;
     uint32_t *bcount = nullptr;      // their entry counts (device, pinned host)
     int64_t bcount_cap = 0;
     uint32_t *h_bcount = nullptr;
@@ -322,6 +324,7 @@ struct BuildJob {
     int64_t ndense = 0, hcap = 0;
     int64_t lcap = 0, loff = 0;   // list region: entries and offset in the arena
     int64_t koff = 0;             // offset of the packing's keys in the batch key buffers
+    int64_t hoff = 0, doff = 0;   // offsets of its hash and dense tables in their arenas
 };
 
 // Host arithmetic of a build of packing k at kb = kappa: grid levels, key
@@ -414,27 +417,37 @@ static int ensure_lanes(rcp_ctx *c, int nl)
 // buffers may be reallocated).
 static int build_grow(rcp_ctx *c, std::vector<BuildJob> &jobs, int nl)
 {
-    int64_t ltot = 0, ntot = 0, tiles = 0, ltiles = 0;
+    (void)nl;
+    int64_t ltot = 0, ntot = 0, tiles = 0, ltiles = 0, htot = 0, dtot = 0;
     for (auto &j : jobs) {
         j.loff = ltot;
         ltot += j.lcap;
         j.koff = ntot;
         ntot += j.a.n;
+        j.hoff = htot;
+        htot += j.hcap;
+        j.doff = dtot;
+        dtot += j.ndense;
         tiles += (j.a.n + kSortTile - 1) / kSortTile;
         ltiles += (j.lcap + kSortTile - 1) / kSortTile;
     }
-    for (int l = 0; l < nl; ++l) {
-        BuildLane &L = c->lanes[l];
-        int64_t dmax = 0, hmax = 64;
-        for (auto &j : jobs) {
-            if (j.lane != l) continue;
-            dmax = std::max(dmax, j.ndense);
-            hmax = std::max(hmax, j.hcap);
-        }
-        if (dmax > 0) CHK(dgrow(&L.dense, &L.dense_cap, dmax));
-        CHK(dgrow(&L.hash, &L.hcap, hmax));
-    }
     const int64_t J = (int64_t)jobs.size();
+    CHK(dgrow(&c->harena, &c->harena_cap, htot));
+    CHK(dgrow(&c->darena, &c->darena_cap, std::max<int64_t>(dtot, 1)));
+    CHK(dgrow(&c->d_fj, &c->fj_cap, J));
+    CHK(dgrow(&c->d_bj, &c->bj_cap, J));
+    if (J > c->hj_cap) {
+        if (c->h_fj) (void)hipHostFree(c->h_fj);
+        if (c->h_bj) (void)hipHostFree(c->h_bj);
+        c->h_fj = nullptr;
+        c->h_bj = nullptr;
+        c->hj_cap = 0;
+        const int64_t cap = std::max<int64_t>(16, 2 * J);
+        hipError_t e = hipHostMalloc((void **)&c->h_fj, sizeof(FrontJob) * cap, 0);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&c->h_bj, sizeof(BackJob) * cap, 0);
+        if (e != hipSuccess) return fail(RCP_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+        c->hj_cap = cap;
+    }
     CHK(dgrow(&c->skA, &c->skA_cap, ntot));
     CHK(dgrow(&c->skB, &c->skB_cap, ntot));
     CHK(dgrow(&c->svA, &c->svA_cap, ntot));
@@ -494,42 +507,35 @@ static int join_lanes(rcp_ctx *c, int nl)
     return RCP_OK;
 }
 
-// Front half of a batch of builds: Morton keys at the current positions,
-// one segmented sort, then per packing (on its lane) the permutation of
-// every per-particle array, the cell tables, and one search pass appending
-// every pair in both directions to its list region; the entry count of
-// jobs[q] goes to bcount[q].  Leaves the lanes forked.
+// Front half of a batch of builds: Morton keys at the current positions
+// and one segmented sort, the permutation of every per-particle array and
+// the cell tables, each as one launch over all packings (job table
+// jobs -> c->h_fj, copied to the device), then the pair searches, one per
+// packing on its lane, appending every pair in both directions to the
+// packing's list region (entry count of jobs[q] in bcount[q]).  Leaves the
+// lanes forked.
 static int build_fronts(rcp_ctx *c, std::vector<BuildJob> &jobs, int nl)
 {
     const int J = (int)jobs.size();
     int nbits = 1;
+    for (auto &j : jobs) nbits = std::max(nbits, j.nbits);
+    const int spar = ((nbits + 7) / 8) & 1;   // buffer of the sorted keys (n >= 1 always)
+    int64_t nb = 0, nbt = 0;
     for (int q = 0; q < J; ++q) {
         BuildJob &j = jobs[q];
         Seg &s = c->segs[j.k];
-        j.a.pos = s.Q[s.cur];
-        j.a.lev = s.LEV[s.set];
-        launch_keys(j.a, c->skA + j.koff, c->svA + j.koff, c->stream);
-        SortSeg &g = c->h_segs[q];
-        g.k[0] = c->skA + j.koff;
-        g.k[1] = c->skB + j.koff;
-        g.v[0] = c->svA + j.koff;
-        g.v[1] = c->svB + j.koff;
-        g.n = j.a.n;
-        nbits = std::max(nbits, j.nbits);
-    }
-    int par = 0;
-    CHK(sort_segments(c, J, nbits, true, &par));
-    CHK(fork_lanes(c, nl));
-    for (int q = 0; q < J; ++q) {
-        BuildJob &j = jobs[q];
-        Seg &s = c->segs[j.k];
-        BuildLane &B = c->lanes[j.lane];
-        hipStream_t st = B.st;
-        BuildArgs &a = j.a;
+        FrontJob &F = c->h_fj[q];
         const int cur = s.cur, ncur = cur ^ 1, set = s.set, nset = set ^ 1;
-        PermArgs pa;
+        j.a.pos = s.Q[ncur];
+        j.a.lev = s.LEV[nset];
+        j.a.skey = (spar ? c->skB : c->skA) + j.koff;
+        j.a.hash = c->harena + j.hoff;
+        j.a.hmask = (uint64_t)j.hcap - 1;
+        j.a.dense = c->darena + j.doff;
+        F.a = j.a;
+        PermArgs &pa = F.pa;
         pa.n = s.n;
-        pa.perm = (par ? c->svB : c->svA) + j.koff;
+        pa.perm = (spar ? c->svB : c->svA) + j.koff;
         pa.ps = s.Q[cur];
         pa.pd = s.Q[ncur];
         for (int ax = 0; ax < 3; ++ax) {
@@ -543,18 +549,39 @@ static int build_fronts(rcp_ctx *c, std::vector<BuildJob> &jobs, int nl)
         pa.od = s.ORIG[nset];
         pa.ls = s.LEV[set];
         pa.ld = s.LEV[nset];
-        launch_permute(pa, st);
+        F.pos0 = s.Q[cur];
+        F.lev0 = s.LEV[set];
+        F.keys = c->skA + j.koff;
+        F.vals = c->svA + j.koff;
+        F.counter = c->bcount + q;
+        F.hcap = j.hcap;
+        F.nd2 = 2 * j.ndense;
+        F.b0 = nb;
+        nb += (s.n + kBlock - 1) / kBlock;
+        F.bt0 = nbt;
+        nbt += (std::max(F.hcap, F.nd2) + kBlock - 1) / kBlock;
+        SortSeg &g = c->h_segs[q];
+        g.k[0] = c->skA + j.koff;
+        g.k[1] = c->skB + j.koff;
+        g.v[0] = c->svA + j.koff;
+        g.v[1] = c->svB + j.koff;
+        g.n = s.n;
         s.set = nset;
         s.cur = ncur;
-        a.pos = s.Q[ncur];
-        a.lev = s.LEV[nset];
-        a.skey = (par ? c->skB : c->skA) + j.koff;
-        a.hash = B.hash;
-        a.hmask = (uint64_t)j.hcap - 1;
-        a.dense = B.dense;
-        launch_hash_build(a, j.hcap, j.ndense, c->bcount + q, st);
-        launch_search(a, c->larena + j.loff, c->bcount + q, j.lcap, j.row_bits,
-                      c->tuning.xcd_remap, (c->tuning.variant >> 6) & 1, st);
+    }
+    HIPCHK(hipMemcpyAsync(c->d_fj, c->h_fj, sizeof(FrontJob) * J, hipMemcpyHostToDevice,
+                          c->stream));
+    launch_keys_seg(c->d_fj, J, nb, c->stream);
+    int par = 0;
+    CHK(sort_segments(c, J, nbits, true, &par));
+    if (par != spar) return fail(RCP_EDEVICE, "internal: key sort parity");
+    launch_permute_seg(c->d_fj, J, nb, c->stream);
+    launch_tables_seg(c->d_fj, J, nbt, nb, c->stream);
+    CHK(fork_lanes(c, nl));
+    for (int q = 0; q < J; ++q) {
+        const BuildJob &j = jobs[q];
+        launch_search(j.a, c->larena + j.loff, c->bcount + q, j.lcap, j.row_bits,
+                      c->tuning.xcd_remap, (c->tuning.variant >> 6) & 1, c->lanes[j.lane].st);
     }
     HIPCHK(hipGetLastError());
     return RCP_OK;
@@ -562,54 +589,76 @@ static int build_fronts(rcp_ctx *c, std::vector<BuildJob> &jobs, int nl)
 
 // Back half for the jobs listed in qs, ms[q] entries in each list region:
 // one segmented sort by (row, col) (full rows, partners ascending), then
-// per packing (on its lane) row pointers and columns, work items
-// (*relayout when a packing's slots are too few: the caller lays out the
-// work table again) and the validity limits.  Leaves the lanes forked.
+// row pointers and columns, work items (*relayout when a packing's slots
+// are too few: the caller lays out the work table again) and the validity
+// limits and pointer entries, each as one launch over the batch (job table
+// -> c->h_bj, copied to the device).
 static int build_backs(rcp_ctx *c, std::vector<BuildJob> &jobs, const std::vector<int> &qs,
-                       const std::vector<int64_t> &ms, int nl, bool *relayout)
+                       const std::vector<int64_t> &ms, bool *relayout)
 {
     const int J = (int)qs.size();
     if (J == 0) return RCP_OK;
     int nbits = 1;
+    int64_t ltiles = 0;
+    for (int r = 0; r < J; ++r) {
+        nbits = std::max(nbits, 2 * jobs[qs[r]].row_bits);
+        ltiles += (ms[qs[r]] + kSortTile - 1) / kSortTile;
+    }
+    const int spar = ltiles > 0 ? ((nbits + 7) / 8) & 1 : 0;
+    const double sk = c->params.skin_s, opg = 1.0 + c->params.skin_g;
+    int64_t nbc = 0, nbs = 0, nbr = 0;
     for (int r = 0; r < J; ++r) {
         const BuildJob &j = jobs[qs[r]];
+        const int64_t m = ms[qs[r]];
+        Seg &s = c->segs[j.k];
+        BackJob &B = c->h_bj[r];
         SortSeg &g = c->h_segs[r];
         g.k[0] = c->larena + j.loff;
         g.k[1] = c->ltmp + j.loff;
         g.v[0] = g.v[1] = nullptr;
-        g.n = ms[qs[r]];
-        nbits = std::max(nbits, 2 * j.row_bits);
-    }
-    int par = 0;
-    CHK(sort_segments(c, J, nbits, false, &par));
-    CHK(fork_lanes(c, nl));
-    const double sk = c->params.skin_s, opg = 1.0 + c->params.skin_g;
-    for (int r = 0; r < J; ++r) {
-        BuildJob &j = jobs[qs[r]];
-        const int64_t m = ms[qs[r]];
-        Seg &s = c->segs[j.k];
-        hipStream_t st = c->lanes[j.lane].st;
-        const int64_t n = s.n;
+        g.n = m;
+        B.srt = (spar ? c->ltmp : c->larena) + j.loff;
+        B.m = m;
+        B.n = s.n;
+        B.row_bits = j.row_bits;
+        B.seg = j.k;
+        B.rp = s.rp;
+        B.col = s.col;
+        B.W = c->d_work + s.first_item;
+        B.nslots = s.blocks;
+        B.row_cost = c->tuning.row_cost;
+        B.item_work = c->tuning.item_work;
         s.list_est = m;
-        launch_csr_from_sorted((par ? c->ltmp : c->larena) + j.loff, m, j.row_bits, n, s.rp, s.col,
-                               st);
         s.built = true;
-        if (slots_for(c, n, m) > s.blocks) {
+        B.fill = slots_for(c, s.n, m) <= s.blocks ? 1 : 0;
+        if (!B.fill) {
             s.slot_entries = m + m / 4;
             *relayout = true;
-        } else {
-            fill_items(c, j.k, st);
         }
-        const double lim = sk * j.kappa * s.d0min * (1.0 - 1e-9);
-        SegPtrs pp;
-        ptrs_of(s, pp);
-        launch_after_build(c->d_state, c->d_ptrs, j.k, j.kappa, lim,
-                           opg * j.kappa * (1.0 - 1e-12), s.cur, pp, st);
+        B.cur = s.cur;
+        B.kb = j.kappa;
+        B.disp_lim = sk * j.kappa * s.d0min * (1.0 - 1e-9);
+        B.kappa_lim = opg * j.kappa * (1.0 - 1e-12);
+        ptrs_of(s, B.ptrs);
+        B.bc0 = nbc;
+        nbc += (m + 1 + kBlock - 1) / kBlock;
+        B.bs0 = nbs;
+        nbs += (s.blocks + kBlock - 1) / kBlock;
+        B.br0 = nbr;
+        nbr += (s.n + kBlock - 1) / kBlock;
         s.npairs = m / 2;
         s.nnz = m;
         s.rebuilds += 1;
         c->stats.rebuilds += 1;
     }
+    HIPCHK(hipMemcpyAsync(c->d_bj, c->h_bj, sizeof(BackJob) * J, hipMemcpyHostToDevice,
+                          c->stream));
+    int par = 0;
+    CHK(sort_segments(c, J, nbits, false, &par));
+    if (par != spar) return fail(RCP_EDEVICE, "internal: entry sort parity");
+    launch_csr_seg(c->d_bj, J, nbc, c->stream);
+    launch_items_seg(c->d_bj, J, nbs, nbr, c->stream);
+    launch_after_seg(c->d_bj, J, c->d_state, c->d_ptrs, c->stream);
     HIPCHK(hipGetLastError());
     return RCP_OK;
 }
@@ -677,8 +726,7 @@ static int rebuild_batch(rcp_ctx *c, const std::vector<int> &ks, const std::vect
         }
     }
     bool relayout = false;
-    CHK(build_backs(c, jobs, ok, ms, nl, &relayout));
-    CHK(join_lanes(c, nl));
+    CHK(build_backs(c, jobs, ok, ms, &relayout));
     // a list that outgrew its region is built again on its own, sized for
     // the count just seen (its particles are already in list order, so the
     // second sort keeps that order and the list is the same)
@@ -700,7 +748,7 @@ static int rebuild_batch(rcp_ctx *c, const std::vector<int> &ks, const std::vect
             s.col_cap = std::max<int64_t>(m1[0] + m1[0] / 4, 1024);
             CHK(dalloc(&s.col, (size_t)s.col_cap));
         }
-        CHK(build_backs(c, one, std::vector<int>{0}, m1, 1, &relayout));
+        CHK(build_backs(c, one, std::vector<int>{0}, m1, &relayout));
     }
     HIPCHK(hipEventRecord(ev.second, c->stream));
     c->rb_pending.push_back(ev);
@@ -1135,8 +1183,6 @@ static void destroy_ctx(rcp_ctx *c)
     dfree(c->d_partials);
     for (auto &L : c->lanes) {
         if (L.own && L.st) (void)hipStreamSynchronize(L.st);
-        dfree(L.hash);
-        dfree(L.dense);
         if (L.ev) (void)hipEventDestroy(L.ev);
         if (L.own && L.st) (void)hipStreamDestroy(L.st);
     }
@@ -1152,6 +1198,12 @@ static void destroy_ctx(rcp_ctx *c)
     dfree(c->stot);
     dfree(c->d_segs);
     dfree(c->larena);
+    dfree(c->harena);
+    dfree(c->darena);
+    dfree(c->d_fj);
+    dfree(c->d_bj);
+    if (c->h_fj) (void)hipHostFree(c->h_fj);
+    if (c->h_bj) (void)hipHostFree(c->h_bj);
     dfree(c->bcount);
     if (c->h_bcount) (void)hipHostFree(c->h_bcount);
     dfree(c->part);
