@@ -50,10 +50,10 @@ def run_batched(workloads, params=None, tuning=None, schedules=None, max_iters=0
 
 
 def run_loop(workloads, params=None, tuning=None, schedules=None, max_iters=0, log=None):
-    """The same workloads as one plain solve each; returns (results, summed
-    seconds of the inflation runs)."""
+    """The same workloads as one plain solve each (library default tuning
+    unless given); returns (results, summed seconds of the inflation
+    runs)."""
     params = params if params is not None else make_params()
-    tuning = tuning if tuning is not None else census_tuning()
     out, total = [], 0.0
     for k, w in enumerate(workloads):
         p = Packing(w.d0, w.L, 1.0, w.seed, init="rsa", params=params, tuning=tuning)
