@@ -159,6 +159,20 @@ __device__ __forceinline__ void cells_one(const BuildArgs &a, int64_t i)
     }
 }
 
+// Block b of a batch grid belongs to the last job whose first block is <= b.
+template <class T>
+__device__ __forceinline__ int job_of(const T *__restrict__ jobs, int J, int64_t b,
+                                      int64_t T::*first)
+{
+    int lo = 0, hi = J - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].*first <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // ------------------------------------------------------- pair search
 constexpr int kSearchBuf = 3072;   // entries staged per block in LDS (24 KB)
 
@@ -475,15 +489,23 @@ __device__ __forceinline__ int2 above(int2 r, int64_t i)
     return make_int2((int32_t)s2, e > s2 ? (int32_t)(e - s2) : 0);
 }
 
-__global__ __launch_bounds__(kBlock) void k_search_coop(BuildArgs a, uint64_t *__restrict__ list,
-                                                       uint32_t *__restrict__ counter,
-                                                       int64_t cap, int row_bits, int xcd_remap)
+// One launch searches every packing of a batch (job table; block ranges
+// F.b0 per packing).
+__global__ __launch_bounds__(kBlock) void k_search_coop(const FrontJob *__restrict__ jobs, int J,
+                                                       int xcd_remap)
 {
     __shared__ uint64_t buf[kSearchBuf];
     __shared__ P4 own[kBlock];
     __shared__ uint32_t nbuf;
     __shared__ uint32_t gbase;
-    const int blk = xcd_remap ? remap_xcd((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+    const int gb = xcd_remap ? remap_xcd((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+    const FrontJob &F = jobs[job_of(jobs, J, gb, &FrontJob::b0)];
+    const BuildArgs &a = F.a;
+    uint64_t *const list = F.list;
+    uint32_t *const counter = F.counter;
+    const int64_t cap = F.lcap;
+    const int row_bits = F.row_bits;
+    const int64_t blk = (int64_t)gb - F.b0;
     const int lane = (int)(threadIdx.x & (kWave - 1));
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
     const int64_t wbase = (int64_t)blk * kBlock + (threadIdx.x & ~(kWave - 1));
@@ -510,7 +532,7 @@ __global__ __launch_bounds__(kBlock) void k_search_coop(BuildArgs a, uint64_t *_
     int Lb = 0, Le = a.nlev, plane = -1;
     if (gridDim.y > 1) {
         Lb = (int)blockIdx.y / 3;
-        Le = Lb + 1;
+        Le = Lb + 1 < a.nlev ? Lb + 1 : a.nlev;
         plane = (int)blockIdx.y % 3;
     }
     for (int L = Lb; L < Le; ++L) {
@@ -543,19 +565,22 @@ __global__ __launch_bounds__(kBlock) void k_search_coop(BuildArgs a, uint64_t *_
 }
 
 void launch_search(const BuildArgs &a, uint64_t *list, uint32_t *counter, int64_t cap,
-                   int row_bits, int xcd_remap, int coop, hipStream_t s)
+                   int row_bits, int xcd_remap, hipStream_t s)
 {
     if (a.n <= 0) return;
     const dim3 grid((unsigned)((a.n + kBlock - 1) / kBlock));
-    if (coop) {
-        // fewer than 8 blocks per CU: split the work by level and plane
-        const unsigned ny = grid.x < 2048u ? 3u * (unsigned)a.nlev : 1u;
-        hipLaunchKernelGGL(k_search_coop, dim3(grid.x, ny), dim3(kBlock), 0, s, a, list,
-                           counter, cap, row_bits, xcd_remap);
-    }
-    else
-        hipLaunchKernelGGL(k_search, grid, dim3(kBlock), 0, s, a, list, counter, cap, row_bits,
-                           xcd_remap);
+    hipLaunchKernelGGL(k_search, grid, dim3(kBlock), 0, s, a, list, counter, cap, row_bits,
+                       xcd_remap);
+}
+
+void launch_search_seg(const FrontJob *jobs, int J, int64_t nb, int max_nlev, int xcd_remap,
+                       hipStream_t s)
+{
+    if (nb <= 0) return;
+    // fewer than 8 blocks per CU: split the work by level and plane
+    const unsigned ny = nb < 2048 ? 3u * (unsigned)max_nlev : 1u;
+    hipLaunchKernelGGL(k_search_coop, dim3((unsigned)nb, ny), dim3(kBlock), 0, s, jobs, J,
+                       xcd_remap);
 }
 
 // Row pointers and partners from the sorted entry list.  Entry q starts row
@@ -573,20 +598,6 @@ __device__ __forceinline__ void csr_one(const uint64_t *__restrict__ srt, int64_
 }
 
 // ------------------------------------------- segmented build steps
-// Block b of a batch grid belongs to the last job whose first block is <= b.
-template <class T>
-__device__ __forceinline__ int job_of(const T *__restrict__ jobs, int J, int64_t b,
-                                      int64_t T::*first)
-{
-    int lo = 0, hi = J - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (jobs[mid].*first <= b) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
 __global__ __launch_bounds__(kBlock) void k_keys_seg(const FrontJob *__restrict__ jobs, int J)
 {
     const FrontJob &F = jobs[job_of(jobs, J, blockIdx.x, &FrontJob::b0)];

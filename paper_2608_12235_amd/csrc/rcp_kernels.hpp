@@ -77,6 +77,9 @@ struct FrontJob {
     uint64_t *keys;         // Morton keys out
     uint32_t *vals;         // local indices out
     uint32_t *counter;      // search entry count, zeroed with the tables
+    uint64_t *list;         // search output: the list region and its capacity
+    int64_t lcap;
+    int32_t row_bits, pad;
     int64_t hcap, nd2;      // hash slots and dense words to clear
     int64_t b0;             // first block in the per-particle grids
     int64_t bt0;            // first block in the table-clear grid
@@ -112,10 +115,14 @@ void launch_after_seg(const BackJob *jobs, int J, SegState *S, SegPtrs *P, hipSt
 // One pass over the particles: every listed pair (i, j) is appended twice
 // to `list` as (row << row_bits) | col, rows and cols in sorted order, in an
 // arbitrary order; *counter (zeroed by the caller) receives the number of
-// entries, which may exceed cap (then only cap were stored).  coop selects
-// the wave-cooperative form (same pairs, other append order).
+// entries, which may exceed cap (then only cap were stored).
 void launch_search(const BuildArgs &a, uint64_t *list, uint32_t *counter, int64_t cap,
-                   int row_bits, int xcd_remap, int coop, hipStream_t s);
+                   int row_bits, int xcd_remap, hipStream_t s);
+// The same for every packing of a batch in one launch, wave-cooperative
+// (the same pairs, another append order; nb = blocks of the per-particle
+// grid, the jobs' list, lcap, row_bits and counter fields say where).
+void launch_search_seg(const FrontJob *jobs, int J, int64_t nb, int max_nlev, int xcd_remap,
+                       hipStream_t s);
 // *out = longest row (max rp[i+1] - rp[i]); out must be zeroed first.
 void launch_max_degree(int64_t n, const int32_t *rp, uint32_t *out, hipStream_t s);
 void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);

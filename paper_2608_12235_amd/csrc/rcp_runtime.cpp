@@ -510,10 +510,10 @@ static int join_lanes(rcp_ctx *c, int nl)
 // Front half of a batch of builds: Morton keys at the current positions
 // and one segmented sort, the permutation of every per-particle array and
 // the cell tables, each as one launch over all packings (job table
-// jobs -> c->h_fj, copied to the device), then the pair searches, one per
-// packing on its lane, appending every pair in both directions to the
-// packing's list region (entry count of jobs[q] in bcount[q]).  Leaves the
-// lanes forked.
+// jobs -> c->h_fj, copied to the device), then the pair search (one launch
+// for the batch; the lane-per-packing form for the non-cooperative search),
+// appending every pair in both directions to each packing's list region
+// (entry count of jobs[q] in bcount[q]).  May leave the lanes forked.
 static int build_fronts(rcp_ctx *c, std::vector<BuildJob> &jobs, int nl)
 {
     const int J = (int)jobs.size();
@@ -554,6 +554,10 @@ static int build_fronts(rcp_ctx *c, std::vector<BuildJob> &jobs, int nl)
         F.keys = c->skA + j.koff;
         F.vals = c->svA + j.koff;
         F.counter = c->bcount + q;
+        F.list = c->larena + j.loff;
+        F.lcap = j.lcap;
+        F.row_bits = j.row_bits;
+        F.pad = 0;
         F.hcap = j.hcap;
         F.nd2 = 2 * j.ndense;
         F.b0 = nb;
@@ -577,11 +581,17 @@ static int build_fronts(rcp_ctx *c, std::vector<BuildJob> &jobs, int nl)
     if (par != spar) return fail(RCP_EDEVICE, "internal: key sort parity");
     launch_permute_seg(c->d_fj, J, nb, c->stream);
     launch_tables_seg(c->d_fj, J, nbt, nb, c->stream);
-    CHK(fork_lanes(c, nl));
-    for (int q = 0; q < J; ++q) {
-        const BuildJob &j = jobs[q];
-        launch_search(j.a, c->larena + j.loff, c->bcount + q, j.lcap, j.row_bits,
-                      c->tuning.xcd_remap, (c->tuning.variant >> 6) & 1, c->lanes[j.lane].st);
+    if ((c->tuning.variant >> 6) & 1) {
+        int max_nlev = 1;
+        for (auto &j : jobs) max_nlev = std::max(max_nlev, j.a.nlev);
+        launch_search_seg(c->d_fj, J, nb, max_nlev, c->tuning.xcd_remap, c->stream);
+    } else {
+        CHK(fork_lanes(c, nl));
+        for (int q = 0; q < J; ++q) {
+            const BuildJob &j = jobs[q];
+            launch_search(j.a, c->larena + j.loff, c->bcount + q, j.lcap, j.row_bits,
+                          c->tuning.xcd_remap, c->lanes[j.lane].st);
+        }
     }
     HIPCHK(hipGetLastError());
     return RCP_OK;
