@@ -492,13 +492,14 @@ __device__ __forceinline__ int2 above(int2 r, int64_t i)
 // One launch searches every packing of a batch (job table; block ranges
 // F.b0 per packing).
 __global__ __launch_bounds__(kBlock) void k_search_coop(const FrontJob *__restrict__ jobs, int J,
-                                                       int xcd_remap)
+                                                       int xcd_remap, int64_t b_base)
 {
     __shared__ uint64_t buf[kSearchBuf];
     __shared__ P4 own[kBlock];
     __shared__ uint32_t nbuf;
     __shared__ uint32_t gbase;
-    const int gb = xcd_remap ? remap_xcd((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+    const int64_t gb =
+        b_base + (xcd_remap ? remap_xcd((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x);
     const FrontJob &F = jobs[job_of(jobs, J, gb, &FrontJob::b0)];
     const BuildArgs &a = F.a;
     uint64_t *const list = F.list;
@@ -506,6 +507,9 @@ __global__ __launch_bounds__(kBlock) void k_search_coop(const FrontJob *__restri
     const int64_t cap = F.lcap;
     const int row_bits = F.row_bits;
     const int64_t blk = (int64_t)gb - F.b0;
+    // split grids give every packing 3 * (the batch's deepest) levels; the
+    // slices past this packing's levels have nothing to do
+    if (gridDim.y > 1 && (int)blockIdx.y / 3 >= a.nlev) return;
     const int lane = (int)(threadIdx.x & (kWave - 1));
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
     const int64_t wbase = (int64_t)blk * kBlock + (threadIdx.x & ~(kWave - 1));
@@ -574,13 +578,13 @@ void launch_search(const BuildArgs &a, uint64_t *list, uint32_t *counter, int64_
 }
 
 void launch_search_seg(const FrontJob *jobs, int J, int64_t nb, int max_nlev, int xcd_remap,
-                       hipStream_t s)
+                       int64_t b_base, hipStream_t s)
 {
     if (nb <= 0) return;
     // fewer than 8 blocks per CU: split the work by level and plane
     const unsigned ny = nb < 2048 ? 3u * (unsigned)max_nlev : 1u;
     hipLaunchKernelGGL(k_search_coop, dim3((unsigned)nb, ny), dim3(kBlock), 0, s, jobs, J,
-                       xcd_remap);
+                       xcd_remap, b_base);
 }
 
 // Row pointers and partners from the sorted entry list.  Entry q starts row

@@ -118,11 +118,11 @@ void launch_after_seg(const BackJob *jobs, int J, SegState *S, SegPtrs *P, hipSt
 // entries, which may exceed cap (then only cap were stored).
 void launch_search(const BuildArgs &a, uint64_t *list, uint32_t *counter, int64_t cap,
                    int row_bits, int xcd_remap, hipStream_t s);
-// The same for every packing of a batch in one launch, wave-cooperative
-// (the same pairs, another append order; nb = blocks of the per-particle
-// grid, the jobs' list, lcap, row_bits and counter fields say where).
+// The same, wave-cooperative (the same pairs, another append order), for
+// jobs[0..J) (their list, lcap, row_bits and counter fields say where) over
+// nb blocks of the per-particle grid starting at block b_base of the batch.
 void launch_search_seg(const FrontJob *jobs, int J, int64_t nb, int max_nlev, int xcd_remap,
-                       hipStream_t s);
+                       int64_t b_base, hipStream_t s);
 // *out = longest row (max rp[i+1] - rp[i]); out must be zeroed first.
 void launch_max_degree(int64_t n, const int32_t *rp, uint32_t *out, hipStream_t s);
 void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);

@@ -510,10 +510,10 @@ static int join_lanes(rcp_ctx *c, int nl)
 // Front half of a batch of builds: Morton keys at the current positions
 // and one segmented sort, the permutation of every per-particle array and
 // the cell tables, each as one launch over all packings (job table
-// jobs -> c->h_fj, copied to the device), then the pair search (one launch
-// for the batch; the lane-per-packing form for the non-cooperative search),
-// appending every pair in both directions to each packing's list region
-// (entry count of jobs[q] in bcount[q]).  May leave the lanes forked.
+// jobs -> c->h_fj, copied to the device), then the pair searches, one per
+// packing on its lane, appending every pair in both directions to each
+// packing's list region (entry count of jobs[q] in bcount[q]).  Leaves the
+// lanes forked.
 static int build_fronts(rcp_ctx *c, std::vector<BuildJob> &jobs, int nl)
 {
     const int J = (int)jobs.size();
@@ -581,17 +581,20 @@ static int build_fronts(rcp_ctx *c, std::vector<BuildJob> &jobs, int nl)
     if (par != spar) return fail(RCP_EDEVICE, "internal: key sort parity");
     launch_permute_seg(c->d_fj, J, nb, c->stream);
     launch_tables_seg(c->d_fj, J, nbt, nb, c->stream);
-    if ((c->tuning.variant >> 6) & 1) {
-        int max_nlev = 1;
-        for (auto &j : jobs) max_nlev = std::max(max_nlev, j.a.nlev);
-        launch_search_seg(c->d_fj, J, nb, max_nlev, c->tuning.xcd_remap, c->stream);
-    } else {
-        CHK(fork_lanes(c, nl));
-        for (int q = 0; q < J; ++q) {
-            const BuildJob &j = jobs[q];
+    // one search launch per packing, spread over the lanes: each packing's
+    // grid is split by level and plane when it is small, which a single
+    // launch over a large batch would not be
+    CHK(fork_lanes(c, nl));
+    const bool coop = (c->tuning.variant >> 6) & 1;
+    for (int q = 0; q < J; ++q) {
+        const BuildJob &j = jobs[q];
+        hipStream_t st = c->lanes[j.lane].st;
+        if (coop)
+            launch_search_seg(c->d_fj + q, 1, (j.a.n + kBlock - 1) / kBlock, j.a.nlev,
+                              c->tuning.xcd_remap, c->h_fj[q].b0, st);
+        else
             launch_search(j.a, c->larena + j.loff, c->bcount + q, j.lcap, j.row_bits,
-                          c->tuning.xcd_remap, c->lanes[j.lane].st);
-        }
+                          c->tuning.xcd_remap, st);
     }
     HIPCHK(hipGetLastError());
     return RCP_OK;
