@@ -3,10 +3,12 @@
 Trials continue a running schedule, so no iteration is wasted: for each
 candidate the skin (rcp_set_skin) and the tuning (rcp_set_tuning) are
 applied and `trial_iters` iterations of every active packing are timed,
-list rebuilds included; the candidate with the highest particle-update rate
-wins.  The search is coordinate-wise: the skin first (it trades list length
-against rebuild frequency), then the iteration kernel variant, the work-item
-cut, and the graph length.  Results do not depend on any of these beyond
+list rebuilds included.  The current settings are timed first; a candidate
+replaces the best only if its particle-update rate is higher by the factor
+MARGIN (trial rates are noisy and the run drifts from trial to trial).  The
+search is coordinate-wise: the skin first (it trades list length against
+rebuild frequency), then the iteration kernel variant, the work-item cut,
+and the graph length.  Results do not depend on any of these beyond
 summation order.
 """
 import time
@@ -19,6 +21,7 @@ SKINS = (1.0, 2.0, 4.0)
 VARIANTS = (64, 65)
 WORK_CUTS = ((10, 2560), (16, 4096))
 GRAPH_ITERS = (8, 16, 32)
+MARGIN = 1.05
 
 
 def _sync():
@@ -74,9 +77,15 @@ def tune(packing, trial_iters=200, skins=SKINS, variants=VARIANTS, work_cuts=WOR
         trials.append((dict(settings), rate))
         if log:
             log("autotune: %s -> %.4g updates/s" % (settings, rate))
-        if rate > best_rate:
+        # a candidate must beat the best so far by a margin: trial rates
+        # are noisy and the run's conditions drift from trial to trial
+        if best_rate < 0 or rate > MARGIN * best_rate:
             best_rate, best = rate, dict(settings)
         return active > 0
+
+    # the current settings first: the baseline every candidate must beat
+    if not run(dict(best)):
+        return best, trials
 
     axes = [("skin_s", [(s,) for s in skins]), ("variant", [(v,) for v in variants]),
             ("work", list(work_cuts)), ("graph_iters", [(k,) for k in graph_iters])]
