@@ -331,82 +331,150 @@ __global__ __launch_bounds__(kBlock) void k_search(BuildArgs a, uint64_t *__rest
 // pair test are those of k_search, so the listed pairs are the same; only
 // the order in which entries are appended differs (the list is sorted
 // afterwards).
-struct Stencil {
-    uint64_t m[3][3];    // [axis][slot]: Morton parts of the lower, own, upper cell
-    uint64_t tp[3][3];   // the same for the tile field
-    int32_t cc[3][3];    // cell coordinates (dense levels)
-    double gap[3][3];    // distance (cell units) from the particle to that slab
-    bool use[3][3];
-    double cb;           // largest cutoff with a partner of the level, in cell units
+// Loads through global-address-space views (global rather than flat
+// instructions, so waiting for LDS results does not also wait for them).
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ int2 load_run(const int2 *t, uint64_t k)
+{
+    const uint64_t v = ((gptr<const uint64_t>)t)[k];
+    return make_int2((int32_t)(uint32_t)v, (int32_t)(uint32_t)(v >> 32));
+}
+
+__device__ __forceinline__ HashSlot load_hslot(const HashSlot *t, uint64_t k)
+{
+    const u64x2 v = ((gptr<const u64x2>)t)[k];
+    HashSlot h;
+    h.key = v.x;
+    h.start = (int32_t)(uint32_t)v.y;
+    h.count = (int32_t)(uint32_t)(v.y >> 32);
+    return h;
+}
+
+__device__ __forceinline__ P4 load_pos(const P4 *t, int64_t k)
+{
+    const dbl4 v = ((gptr<const dbl4>)t)[k];
+    P4 r;
+    r.x = v.x;
+    r.y = v.y;
+    r.z = v.z;
+    r.d = v.w;
+    return r;
+}
+
+// A particle's stencil in one level grid, as the cooperative search keeps
+// it in registers: a mask of the searched slots (sphere-distance pruning of
+// the 27 cells, as in k_search) and, per axis and offset, the part of the
+// cell's table position that axis contributes.  For a hashed level the
+// parts are the Morton and tile bits of the key; for a dense level they are
+// the strides of the (x, y, z) cell index.  The parts of a key occupy
+// disjoint bits, so in both cases the position is base + px + py + pz.
+struct CoopStencil {
+    uint32_t mask;       // bit sl (slot sl = 9 ox + 3 oy + oz) set if searched
+    uint64_t p[3][3];    // [axis][lower, own, upper cell]
 };
 
-__device__ __forceinline__ void stencil_setup(const BuildArgs &a, const LevelGrid &g,
-                                              const double pos[3], double di, Stencil &S)
+__device__ __forceinline__ void coop_stencil(const BuildArgs &a, const LevelGrid &g,
+                                             const double pos[3], double di, bool act,
+                                             CoopStencil &S)
 {
     const int32_t nc = g.nc;
-    S.cb = a.kb * (a.opg * (0.5 * (di + g.dmax)) + a.sk2) * g.inv_w * (1.0 + 1e-9) + 1e-9;
+    const bool dense = g.dbase >= 0;
+    const double cb = a.kb * (a.opg * (0.5 * (di + g.dmax)) + a.sk2) * g.inv_w * (1.0 + 1e-9) + 1e-9;
+    double gap[3][3];
+    bool use[3][3];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-        const double fp = pos[ax] * g.inv_w;
-        const int32_t c = cell_coord(pos[ax], g.inv_w, nc);
+        int32_t cc[3];
         if (nc >= 3) {
+            const double fp = pos[ax] * g.inv_w;
+            const int32_t c = cell_coord(pos[ax], g.inv_w, nc);
             const double f = fp - (double)c;
-            const int32_t lo = c == 0 ? nc - 1 : c - 1, hi = c == nc - 1 ? 0 : c + 1;
-            S.cc[ax][0] = lo;
-            S.cc[ax][1] = c;
-            S.cc[ax][2] = hi;
-            S.m[ax][0] = spread3((uint64_t)lo) << ax;
-            S.m[ax][1] = spread3((uint64_t)c) << ax;
-            S.m[ax][2] = spread3((uint64_t)hi) << ax;
-            S.tp[ax][0] = spread3(tile_of(lo, nc, a.tiles)) << ax;
-            S.tp[ax][1] = spread3(tile_of(c, nc, a.tiles)) << ax;
-            S.tp[ax][2] = spread3(tile_of(hi, nc, a.tiles)) << ax;
-            S.gap[ax][0] = f;
-            S.gap[ax][1] = 0.0;
-            S.gap[ax][2] = 1.0 - f;
-            S.use[ax][0] = f < S.cb;
-            S.use[ax][1] = true;
-            S.use[ax][2] = 1.0 - f < S.cb;
+            cc[0] = c == 0 ? nc - 1 : c - 1;
+            cc[1] = c;
+            cc[2] = c == nc - 1 ? 0 : c + 1;
+            gap[ax][0] = f;
+            gap[ax][1] = 0.0;
+            gap[ax][2] = 1.0 - f;
+            use[ax][0] = f < cb;
+            use[ax][1] = true;
+            use[ax][2] = 1.0 - f < cb;
         } else {
-            S.cc[ax][0] = 0;
-            S.cc[ax][1] = 1;
-            S.cc[ax][2] = 0;
-            S.m[ax][0] = 0;
-            S.m[ax][1] = spread3(1) << ax;
-            S.m[ax][2] = 0;
-            S.tp[ax][0] = spread3(tile_of(0, nc, a.tiles)) << ax;
-            S.tp[ax][1] = spread3(tile_of(1, nc, a.tiles)) << ax;
-            S.tp[ax][2] = 0;
-            S.gap[ax][0] = S.gap[ax][1] = S.gap[ax][2] = 0.0;
-            S.use[ax][0] = true;
-            S.use[ax][1] = nc == 2;
-            S.use[ax][2] = false;
+            cc[0] = 0;
+            cc[1] = 1;
+            cc[2] = 0;
+            gap[ax][0] = gap[ax][1] = gap[ax][2] = 0.0;
+            use[ax][0] = true;
+            use[ax][1] = nc == 2;
+            use[ax][2] = false;
+        }
+        const int64_t stride = ax == 0 ? (int64_t)nc * nc : (ax == 1 ? (int64_t)nc : 1);
+#pragma unroll
+        for (int o = 0; o < 3; ++o)
+            S.p[ax][o] = dense ? (uint64_t)((int64_t)cc[o] * stride)
+                               : (spread3((uint64_t)cc[o]) << ax) |
+                                     ((spread3(tile_of(cc[o], nc, a.tiles)) << ax) << a.tshift);
+    }
+    uint32_t m = 0;
+#pragma unroll
+    for (int sl = 0; sl < 27; ++sl) {
+        const int ox = sl / 9, oy = (sl / 3) % 3, oz = sl % 3;
+        const double g2 = (gap[0][ox] * gap[0][ox] + gap[1][oy] * gap[1][oy]) +
+                          gap[2][oz] * gap[2][oz];
+        if (use[0][ox] && use[1][oy] && use[2][oz] && g2 < cb * cb) m |= 1u << sl;
+    }
+    S.mask = act ? m : 0u;
+}
+
+// Cell runs (start, count) of the nine slots of stencil plane ox.  Every
+// table read of the plane is issued before any is used, so a wave has nine
+// lookups in flight instead of one; lanes that do not search a slot read the
+// level's first entry (one shared line) and discard it.  A hash probe that
+// meets another key (a collision) continues along the probe sequence.
+__device__ __forceinline__ void lookup_plane(const BuildArgs &a, const CoopStencil &S,
+                                             bool dense, uint64_t base, int ox, int2 r[9])
+{
+    if (dense) {
+        int2 v[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const bool u = (S.mask >> (ox * 9 + k)) & 1u;
+            const uint64_t at = base + S.p[0][ox] + S.p[1][k / 3] + S.p[2][k % 3];
+            v[k] = load_run(a.dense, u ? at : base);
+        }
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const bool u = (S.mask >> (ox * 9 + k)) & 1u;
+            r[k] = u ? v[k] : make_int2(0, 0);
+        }
+        return;
+    }
+    HashSlot e[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const bool u = (S.mask >> (ox * 9 + k)) & 1u;
+        const uint64_t key = base + S.p[0][ox] + S.p[1][k / 3] + S.p[2][k % 3];
+        e[k] = load_hslot(a.hash, u ? hash_slot(key, a.hmask) : 0ull);
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const bool u = (S.mask >> (ox * 9 + k)) & 1u;
+        const uint64_t key = base + S.p[0][ox] + S.p[1][k / 3] + S.p[2][k % 3];
+        r[k] = make_int2(0, 0);
+        if (u && e[k].key == key) r[k] = make_int2(e[k].start, e[k].count);
+        if (u && e[k].key != key && e[k].key != kEmptyKey) {
+            uint64_t slot = hash_slot(key, a.hmask);
+            for (;;) {
+                slot = (slot + 1) & a.hmask;
+                const HashSlot f = load_hslot(a.hash, slot);
+                if (f.key == key) {
+                    r[k] = make_int2(f.start, f.count);
+                    break;
+                }
+                if (f.key == kEmptyKey) break;
+            }
         }
     }
-}
-
-// Stencil slot sl (0..26, x slowest) of a particle: whether it is searched
-// (the cell's nearest point within the cutoff bound) and its cell.
-__device__ __forceinline__ bool slot_used(const Stencil &S, int sl)
-{
-    const int ox = sl / 9, oy = (sl / 3) % 3, oz = sl % 3;
-    const double g2 = (S.gap[0][ox] * S.gap[0][ox] + S.gap[1][oy] * S.gap[1][oy]) +
-                      S.gap[2][oz] * S.gap[2][oz];
-    return S.use[0][ox] && S.use[1][oy] && S.use[2][oz] && g2 < S.cb * S.cb;
-}
-
-__device__ __forceinline__ int64_t slot_dense_index(const LevelGrid &g, const Stencil &S, int sl)
-{
-    const int ox = sl / 9, oy = (sl / 3) % 3, oz = sl % 3;
-    return ((int64_t)S.cc[0][ox] * g.nc + S.cc[1][oy]) * g.nc + S.cc[2][oz];
-}
-
-__device__ __forceinline__ uint64_t slot_key(const BuildArgs &a, const Stencil &S, uint64_t base,
-                                             int sl)
-{
-    const int ox = sl / 9, oy = (sl / 3) % 3, oz = sl % 3;
-    return base | S.m[0][ox] | S.m[1][oy] | S.m[2][oz] |
-           ((S.tp[0][ox] | S.tp[1][oy] | S.tp[2][oz]) << a.tshift);
 }
 
 // Per-block output staging of k_search_coop.
@@ -447,7 +515,7 @@ __device__ __forceinline__ void test_slot(const BuildArgs &a, const SearchOut &o
         bool hit = false;
         if (has) {
             const P4 oq = out.own[o];
-            const P4 qj = a.pos[j];
+            const P4 qj = load_pos(a.pos, j);
             const double dx = min_image(qj.x - oq.x, a.L, a.hL);
             const double dy = min_image(qj.y - oq.y, a.L, a.hL);
             const double dz = min_image(qj.z - oq.z, a.L, a.hL);
@@ -472,8 +540,8 @@ __device__ __forceinline__ void test_slot(const BuildArgs &a, const SearchOut &o
             } else {
                 const uint32_t gi = atomicAdd(out.counter, 2u);
                 if ((int64_t)gi + 1 < out.cap) {
-                    out.list[gi] = e0;
-                    out.list[gi + 1] = e1;
+                    gstore(out.list, (int64_t)gi, e0);
+                    gstore(out.list, (int64_t)gi + 1, e1);
                 }
             }
         }
@@ -491,7 +559,7 @@ __device__ __forceinline__ int2 above(int2 r, int64_t i)
 
 // One launch searches every packing of a batch (job table; block ranges
 // F.b0 per packing).
-__global__ __launch_bounds__(kBlock) void k_search_coop(const FrontJob *__restrict__ jobs, int J,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_search_coop(const FrontJob *__restrict__ jobs, int J,
                                                        int xcd_remap, int64_t b_base)
 {
     __shared__ uint64_t buf[kSearchBuf];
@@ -520,12 +588,12 @@ __global__ __launch_bounds__(kBlock) void k_search_coop(const FrontJob *__restri
     double xi = 0.0, yi = 0.0, zi = 0.0, di = 0.0;
     int li = kMaxLevels;
     if (valid) {
-        const P4 qi = a.pos[i];
+        const P4 qi = load_pos(a.pos, i);
         xi = qi.x;
         yi = qi.y;
         zi = qi.z;
         di = qi.d;
-        li = a.lev[i];
+        li = gload(a.lev, i);
     }
     own[threadIdx.x] = P4{xi, yi, zi, di};
     if (threadIdx.x == 0) nbuf = 0;
@@ -544,20 +612,22 @@ __global__ __launch_bounds__(kBlock) void k_search_coop(const FrontJob *__restri
         if (g.count == 0) continue;
         const bool act = li <= L;
         if (__ballot(act) == 0ull) continue;
-        Stencil S;
+        CoopStencil S;
         const double pos[3] = {xi, yi, zi};
-        stencil_setup(a, g, pos, di, S);
+        coop_stencil(a, g, pos, di, act, S);
         const bool same = L == li;
-        const uint64_t base = (uint64_t)L << a.mb;
+        const bool dense = g.dbase >= 0;
+        const uint64_t base = dense ? (uint64_t)g.dbase : (uint64_t)L << a.mb;
 #pragma unroll
-        for (int sl = 0; sl < 27; ++sl) {
-            if (plane >= 0 && sl / 9 != plane) continue;
-            int2 r = make_int2(0, 0);
-            if (act && slot_used(S, sl))
-                r = g.dbase >= 0 ? a.dense[g.dbase + slot_dense_index(g, S, sl)]
-                                 : hash_find(a, slot_key(a, S, base, sl));
-            if (same) r = above(r, i);
-            test_slot(a, out, lane, below, wbase, r.x, r.y);
+        for (int ox = 0; ox < 3; ++ox) {
+            if (plane >= 0 && ox != plane) continue;
+            int2 r[9];
+            lookup_plane(a, S, dense, base, ox, r);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const int2 rk = same ? above(r[k], i) : r[k];
+                test_slot(a, out, lane, below, wbase, rk.x, rk.y);
+            }
         }
     }
     __syncthreads();
@@ -565,7 +635,7 @@ __global__ __launch_bounds__(kBlock) void k_search_coop(const FrontJob *__restri
     if (threadIdx.x == 0) gbase = mm ? atomicAdd(counter, mm) : 0u;
     __syncthreads();
     for (uint32_t k = threadIdx.x; k < mm; k += kBlock)
-        if ((int64_t)gbase + k < cap) list[gbase + k] = buf[k];
+        if ((int64_t)gbase + k < cap) gstore(list, (int64_t)gbase + k, buf[k]);
 }
 
 void launch_search(const BuildArgs &a, uint64_t *list, uint32_t *counter, int64_t cap,
