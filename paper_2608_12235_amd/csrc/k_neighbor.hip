@@ -174,7 +174,7 @@ __device__ __forceinline__ int job_of(const T *__restrict__ jobs, int J, int64_t
 }
 
 // ------------------------------------------------------- pair search
-constexpr int kSearchBuf = 3072;   // entries staged per block in LDS (24 KB)
+constexpr int kSearchBuf = 2304;   // entries staged per block in LDS (18 KB)
 
 // Half partners of particle i are searched: same class with a larger sorted
 // index, and every larger class.  Each listed pair is appended in both
@@ -477,44 +477,108 @@ __device__ __forceinline__ void lookup_plane(const BuildArgs &a, const CoopStenc
     }
 }
 
-// Per-block output staging of k_search_coop.
+// Inclusive running maximum of a non-negative int over the 64 lanes (DPP
+// only; the same shifts and row broadcasts as the prefix sum).
+__device__ __forceinline__ int32_t wave_scan_max_dpp(int32_t v)
+{
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false));   // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false));   // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false));   // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false));   // row_shr:8
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false));   // row_bcast:15
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false));   // row_bcast:31
+    return v;
+}
+
+// Per-wave LDS table of one stencil plane's runs.  The candidates of the
+// plane are numbered lane by lane and, within a lane, slot by slot; row t
+// holds, for lane t's nine runs, the end E_k of run k in that numbering and
+// the offset J_k with sorted index j = J_k + q for candidate q of the run.
+// Row layout (int32, 16-byte rows): E_0..7, J_0..7, E_8, J_8, 2 unused.
+constexpr int kTabRow = 20;
+
+__device__ __forceinline__ int tab_e(int k) { return k < 8 ? k : 16; }
+__device__ __forceinline__ int tab_j(int k) { return k < 8 ? 8 + k : 17; }
+
+// Per-block output staging of k_search_coop, and the wave's plane table.
 struct SearchOut {
     uint64_t *buf;      // LDS, kSearchBuf entries
     uint32_t *nbuf;     // LDS counter
-    const P4 *own;      // LDS, this wave's 64 particles
+    int32_t *tab;       // LDS, this wave's 64 rows of kTabRow
+    int32_t *mark;      // LDS, this wave's 64 owner marks
     uint64_t *list;
     uint32_t *counter;
     int64_t cap;
     int row_bits;
 };
 
-// Test, with the whole wave, the candidates of one stencil slot: lane t
-// contributes the run [st, st + ct) of its cell; a wave prefix sum numbers
-// the candidates and each round tests 64 consecutive ones, a lane finding
-// its candidate's owner by binary search over the prefix.  Listed pairs
-// take one LDS reservation per wave and round.
-__device__ __forceinline__ void test_slot(const BuildArgs &a, const SearchOut &out, int lane,
-                                          uint64_t below, int64_t wbase, int32_t st, int32_t ct)
+// Test, with the whole wave, the candidates of one stencil plane: lane t
+// contributes the runs r[0..8] of its nine cells.  A wave prefix sum of
+// the lanes' totals numbers the candidates and each round tests 64
+// consecutive ones, so a round is full whichever cells the candidates come
+// from.  The owner of candidate q is the number of lanes whose prefix is
+// <= q: each lane whose prefix ends inside the round's window marks its
+// position there (the last such lane of a position), and a running maximum
+// over the window gives every candidate its owner.  The owner's table row
+// then gives the run and the sorted index.  Listed pairs take one LDS
+// reservation per wave and round.
+__device__ __forceinline__ void test_plane(const BuildArgs &a, const SearchOut &out, int lane,
+                                           uint64_t below, int64_t wbase, const int2 r[9])
 {
-    const int32_t inc = wave_scan_incl_dpp(ct);
+    int32_t cum[9];
+    int32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        c += r[k].y;
+        cum[k] = c;
+    }
+    const int32_t inc = wave_scan_incl_dpp(c);
     const int32_t T = __builtin_amdgcn_readlane(inc, kWave - 1);
     if (T == 0) return;
-    const int32_t jb = st - (inc - ct);   // candidate q of this lane's run is j = q + jb
+    const int32_t excl = inc - c;
+    int32_t *row = out.tab + lane * kTabRow;
+    {
+        int32_t E[9], J[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            E[k] = excl + cum[k];
+            J[k] = r[k].x - (E[k] - r[k].y);
+        }
+        *(int4 *)(row + 0) = make_int4(E[0], E[1], E[2], E[3]);
+        *(int4 *)(row + 4) = make_int4(E[4], E[5], E[6], E[7]);
+        *(int4 *)(row + 8) = make_int4(J[0], J[1], J[2], J[3]);
+        *(int4 *)(row + 12) = make_int4(J[4], J[5], J[6], J[7]);
+        *(int2 *)(row + 16) = make_int2(E[8], J[8]);
+    }
+    // the next lane's prefix (past the last lane: beyond every window).  The
+    // shuffle runs on every lane: a lane outside the active mask would
+    // supply 0 instead of its value.
+    int32_t nxt = __shfl(inc, (lane + 1) & (kWave - 1), kWave);
+    if (lane == kWave - 1) nxt = 0x7fffffff;
+    __builtin_amdgcn_wave_barrier();
     for (int32_t r0 = 0; r0 < T; r0 += kWave) {
         const int32_t q = r0 + lane;
-        // owner: number of lanes whose inclusive prefix is <= q
-        int o = 0;
-#pragma unroll
-        for (int step = kWave / 2; step > 0; step >>= 1) {
-            const int32_t v = __shfl(inc, o + step - 1, kWave);
-            if (v <= q) o += step;
-        }
+        out.mark[lane] = 0;
+        const int32_t P = max(inc - r0, 0), Pn = max(nxt - r0, 0);
+        if (P < kWave && Pn != P) out.mark[P] = lane + 1;
+        __builtin_amdgcn_wave_barrier();
         const bool has = q < T;
+        int o = wave_scan_max_dpp(out.mark[lane]);
         o = has ? o : 0;
-        const int64_t j = (int64_t)q + __shfl(jb, o, kWave);
+        const int32_t *ro = out.tab + o * kTabRow;
+        const int4 e0 = *(const int4 *)(ro + 0);
+        const int4 e1 = *(const int4 *)(ro + 4);
+        const int32_t e8 = ro[16];
+        const int k = (int)(e0.x <= q) + (int)(e0.y <= q) + (int)(e0.z <= q) + (int)(e0.w <= q) +
+                      (int)(e1.x <= q) + (int)(e1.y <= q) + (int)(e1.z <= q) + (int)(e1.w <= q) +
+                      (int)(e8 <= q);
+        const int64_t j = (int64_t)ro[tab_j(k < 8 ? k : 8)] + q;
+        __builtin_amdgcn_wave_barrier();
         bool hit = false;
-        if (has) {
-            const P4 oq = out.own[o];
+        // (the index checks hold by construction; they keep a wrong owner
+        // from reading outside the positions)
+        if (has && (uint64_t)j < (uint64_t)a.n && wbase + o < a.n) {
+            const P4 oq = load_pos(a.pos, wbase + o);
             const P4 qj = load_pos(a.pos, j);
             const double dx = min_image(qj.x - oq.x, a.L, a.hL);
             const double dy = min_image(qj.y - oq.y, a.L, a.hL);
@@ -533,10 +597,10 @@ __device__ __forceinline__ void test_slot(const BuildArgs &a, const SearchOut &o
             const int64_t io = wbase + o;
             const uint64_t e0 = ((uint64_t)io << out.row_bits) | (uint64_t)j;
             const uint64_t e1 = ((uint64_t)j << out.row_bits) | (uint64_t)io;
-            const uint32_t k = k0 + 2u * (uint32_t)__popcll(bal & below);
-            if (k + 1 < (uint32_t)kSearchBuf) {
-                out.buf[k] = e0;
-                out.buf[k + 1] = e1;
+            const uint32_t kk = k0 + 2u * (uint32_t)__popcll(bal & below);
+            if (kk + 1 < (uint32_t)kSearchBuf) {
+                out.buf[kk] = e0;
+                out.buf[kk + 1] = e1;
             } else {
                 const uint32_t gi = atomicAdd(out.counter, 2u);
                 if ((int64_t)gi + 1 < out.cap) {
@@ -546,6 +610,7 @@ __device__ __forceinline__ void test_slot(const BuildArgs &a, const SearchOut &o
             }
         }
     }
+    __builtin_amdgcn_wave_barrier();
 }
 
 // Restrict a cell run to sorted indices above i (a particle's own level:
@@ -563,7 +628,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                                                        int xcd_remap, int64_t b_base)
 {
     __shared__ uint64_t buf[kSearchBuf];
-    __shared__ P4 own[kBlock];
+    __shared__ __align__(16) int32_t tab[kBlock * kTabRow];
+    __shared__ int32_t mark[kBlock];
     __shared__ uint32_t nbuf;
     __shared__ uint32_t gbase;
     const int64_t gb =
@@ -583,7 +649,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const int64_t wbase = (int64_t)blk * kBlock + (threadIdx.x & ~(kWave - 1));
     const int64_t i = wbase + lane;
     const bool valid = i < a.n;
-    const SearchOut out{buf, &nbuf, own + (threadIdx.x & ~(kWave - 1)), list, counter, cap,
+    const int wofs = (int)(threadIdx.x & ~(kWave - 1));
+    const SearchOut out{buf, &nbuf, tab + wofs * kTabRow, mark + wofs, list, counter, cap,
                         row_bits};
     double xi = 0.0, yi = 0.0, zi = 0.0, di = 0.0;
     int li = kMaxLevels;
@@ -595,7 +662,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         di = qi.d;
         li = gload(a.lev, i);
     }
-    own[threadIdx.x] = P4{xi, yi, zi, di};
     if (threadIdx.x == 0) nbuf = 0;
     __syncthreads();
     // a grid with gridDim.y > 1 gives each block one level and one plane
@@ -623,11 +689,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             if (plane >= 0 && ox != plane) continue;
             int2 r[9];
             lookup_plane(a, S, dense, base, ox, r);
+            if (same) {
 #pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                const int2 rk = same ? above(r[k], i) : r[k];
-                test_slot(a, out, lane, below, wbase, rk.x, rk.y);
+                for (int k = 0; k < 9; ++k) r[k] = above(r[k], i);
             }
+            test_plane(a, out, lane, below, wbase, r);
         }
     }
     __syncthreads();

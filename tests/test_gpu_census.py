@@ -43,6 +43,7 @@ def test_census_equals_plain_solves(rcp):
         assert a == b
 
 
+@pytest.mark.timeout(600)   # 32 oracle inflations on the host
 def test_census_phi_matches_oracle(rcp, orc):
     from paper_2608_12235_amd import census
     base = _smallest(4)
