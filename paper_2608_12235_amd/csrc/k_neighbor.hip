@@ -103,11 +103,15 @@ void launch_fill_f64(double *p, int64_t n, double v, hipStream_t s)
 
 // Home slot of a cell key.  The low three Morton bits (a 2x2x2 block of
 // cells) stay together in one 8-slot group (one 128-byte line); the groups
-// themselves are scattered by hashing the remaining bits, so a 27-cell
-// stencil touches about eight lines and Morton-adjacent particles share them.
+// themselves are scattered by multiplicative (Fibonacci) hashing of the
+// remaining bits, the group number being the top bits of the product with
+// 2^64 / golden ratio, so a 27-cell stencil touches about eight lines and
+// Morton-adjacent particles share them.  The table size is a power of two,
+// at least 64 slots.
 __device__ __forceinline__ uint64_t hash_slot(uint64_t key, uint64_t mask)
 {
-    return ((hash64(key >> 3) << 3) | (key & 7ull)) & mask;
+    const int gshift = __builtin_clzll(mask) + 3;   // 64 - log2(number of groups)
+    return ((((key >> 3) * 0x9e3779b97f4a7c15ull) >> gshift) << 3) | (key & 7ull);
 }
 
 __device__ __forceinline__ int2 hash_find(const BuildArgs &a, uint64_t key)
@@ -374,6 +378,12 @@ struct CoopStencil {
     uint64_t p[3][3];    // [axis][lower, own, upper cell]
 };
 
+// Two-bit tile coordinate in Morton form (tiles per axis <= 4).
+__device__ __forceinline__ uint64_t spread_tile(uint32_t t)
+{
+    return (uint64_t)((t & 1u) | ((t & 2u) << 2));
+}
+
 __device__ __forceinline__ void coop_stencil(const BuildArgs &a, const LevelGrid &g,
                                              const double pos[3], double di, bool act,
                                              CoopStencil &S)
@@ -381,47 +391,104 @@ __device__ __forceinline__ void coop_stencil(const BuildArgs &a, const LevelGrid
     const int32_t nc = g.nc;
     const bool dense = g.dbase >= 0;
     const double cb = a.kb * (a.opg * (0.5 * (di + g.dmax)) + a.sk2) * g.inv_w * (1.0 + 1e-9) + 1e-9;
-    double gap[3][3];
-    bool use[3][3];
+    uint32_t m = 0;
+    if (nc >= 3) {
+        int32_t c[3];
+        double sq[3][3];
+        bool ok[3][3];
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        int32_t cc[3];
-        if (nc >= 3) {
+        for (int ax = 0; ax < 3; ++ax) {
             const double fp = pos[ax] * g.inv_w;
-            const int32_t c = cell_coord(pos[ax], g.inv_w, nc);
-            const double f = fp - (double)c;
-            cc[0] = c == 0 ? nc - 1 : c - 1;
-            cc[1] = c;
-            cc[2] = c == nc - 1 ? 0 : c + 1;
-            gap[ax][0] = f;
-            gap[ax][1] = 0.0;
-            gap[ax][2] = 1.0 - f;
-            use[ax][0] = f < cb;
-            use[ax][1] = true;
-            use[ax][2] = 1.0 - f < cb;
+            c[ax] = cell_coord(pos[ax], g.inv_w, nc);
+            const double f = fp - (double)c[ax];
+            // squared distance (cell units) to the lower and upper slab
+            sq[ax][0] = f * f;
+            sq[ax][1] = 0.0;
+            sq[ax][2] = (1.0 - f) * (1.0 - f);
+            ok[ax][0] = f < cb;
+            ok[ax][1] = true;
+            ok[ax][2] = 1.0 - f < cb;
+        }
+        // a cell is searched if its nearest point is within the bound; the
+        // zero terms of the own-cell axes are left out of the sums (adding
+        // +0.0 changes nothing), the order is (x + y) + z as in k_search
+        const double cb2 = cb * cb;
+#pragma unroll
+        for (int ox = 0; ox < 3; ++ox) {
+#pragma unroll
+            for (int oy = 0; oy < 3; ++oy) {
+                const double sxy = ox == 1 ? sq[1][oy]
+                                           : (oy == 1 ? sq[0][ox] : sq[0][ox] + sq[1][oy]);
+#pragma unroll
+                for (int oz = 0; oz < 3; ++oz) {
+                    const double s2 = oz == 1 ? sxy
+                                              : (ox == 1 && oy == 1 ? sq[2][oz] : sxy + sq[2][oz]);
+                    if (ok[0][ox] && ok[1][oy] && ok[2][oz] && s2 < cb2)
+                        m |= 1u << (ox * 9 + oy * 3 + oz);
+                }
+            }
+        }
+        if (dense) {
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                const int64_t stride = ax == 0 ? (int64_t)nc * nc : (ax == 1 ? (int64_t)nc : 1);
+                const int32_t lo = c[ax] == 0 ? nc - 1 : c[ax] - 1;
+                const int32_t hi = c[ax] == nc - 1 ? 0 : c[ax] + 1;
+                S.p[ax][0] = (uint64_t)((int64_t)lo * stride);
+                S.p[ax][1] = (uint64_t)((int64_t)c[ax] * stride);
+                S.p[ax][2] = (uint64_t)((int64_t)hi * stride);
+            }
         } else {
-            cc[0] = 0;
-            cc[1] = 1;
-            cc[2] = 0;
-            gap[ax][0] = gap[ax][1] = gap[ax][2] = 0.0;
+            // Morton parts of the neighbour cells by dilated-integer
+            // increment and decrement of the own cell's, and their tiles from
+            // the own cell's tile (tiles per axis T = 1, 2 or 4; tile k starts
+            // at cell ceil(k nc / T)); the periodic wraps are the level's
+            // first and last cell
+            const uint32_t T = (uint32_t)a.tiles, lt = (uint32_t)__builtin_ctz(T);
+            const uint32_t tlast = ((uint32_t)(nc - 1) * T) / (uint32_t)nc;
+            const uint64_t dlast = spread3((uint64_t)(nc - 1));
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                const uint64_t M = 0x1249249249249249ull;
+                const uint32_t cu = (uint32_t)c[ax];
+                const uint64_t d = spread3((uint64_t)cu);
+                const uint64_t dhi = cu == (uint32_t)nc - 1 ? 0ull : ((d | ~M) + 1) & M;
+                const uint64_t dlo = cu == 0 ? dlast : (d - 1) & M;
+                const uint32_t t = (cu * T) / (uint32_t)nc;
+                const uint32_t thi =
+                    cu == (uint32_t)nc - 1
+                        ? 0u
+                        : t + (cu + 1 == (((t + 1) * (uint32_t)nc + T - 1) >> lt) ? 1u : 0u);
+                const uint32_t tlo =
+                    cu == 0 ? tlast : t - (cu == ((t * (uint32_t)nc + T - 1) >> lt) ? 1u : 0u);
+                S.p[ax][0] = (dlo << ax) | ((spread_tile(tlo) << ax) << a.tshift);
+                S.p[ax][1] = (d << ax) | ((spread_tile(t) << ax) << a.tshift);
+                S.p[ax][2] = (dhi << ax) | ((spread_tile(thi) << ax) << a.tshift);
+            }
+        }
+    } else {
+        // one or two cells per axis: each distinct cell is searched once
+        int32_t cc[3][3];
+        bool use[3][3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            cc[ax][0] = 0;
+            cc[ax][1] = 1;
+            cc[ax][2] = 0;
             use[ax][0] = true;
             use[ax][1] = nc == 2;
             use[ax][2] = false;
+            const int64_t stride = ax == 0 ? (int64_t)nc * nc : (ax == 1 ? (int64_t)nc : 1);
+#pragma unroll
+            for (int o = 0; o < 3; ++o)
+                S.p[ax][o] = dense ? (uint64_t)((int64_t)cc[ax][o] * stride)
+                                   : (spread3((uint64_t)cc[ax][o]) << ax) |
+                                         ((spread3(tile_of(cc[ax][o], nc, a.tiles)) << ax)
+                                          << a.tshift);
         }
-        const int64_t stride = ax == 0 ? (int64_t)nc * nc : (ax == 1 ? (int64_t)nc : 1);
 #pragma unroll
-        for (int o = 0; o < 3; ++o)
-            S.p[ax][o] = dense ? (uint64_t)((int64_t)cc[o] * stride)
-                               : (spread3((uint64_t)cc[o]) << ax) |
-                                     ((spread3(tile_of(cc[o], nc, a.tiles)) << ax) << a.tshift);
-    }
-    uint32_t m = 0;
-#pragma unroll
-    for (int sl = 0; sl < 27; ++sl) {
-        const int ox = sl / 9, oy = (sl / 3) % 3, oz = sl % 3;
-        const double g2 = (gap[0][ox] * gap[0][ox] + gap[1][oy] * gap[1][oy]) +
-                          gap[2][oz] * gap[2][oz];
-        if (use[0][ox] && use[1][oy] && use[2][oz] && g2 < cb * cb) m |= 1u << sl;
+        for (int sl = 0; sl < 27; ++sl)
+            if (use[0][sl / 9] && use[1][(sl / 3) % 3] && use[2][sl % 3]) m |= 1u << sl;
     }
     S.mask = act ? m : 0u;
 }
