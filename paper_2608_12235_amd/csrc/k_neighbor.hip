@@ -564,9 +564,6 @@ __device__ __forceinline__ int32_t wave_scan_max_dpp(int32_t v)
 // Row layout (int32, 16-byte rows): E_0..7, J_0..7, E_8, J_8, 2 unused.
 constexpr int kTabRow = 20;
 
-__device__ __forceinline__ int tab_e(int k) { return k < 8 ? k : 16; }
-__device__ __forceinline__ int tab_j(int k) { return k < 8 ? 8 + k : 17; }
-
 // Per-block output staging of k_search_coop, and the wave's plane table.
 struct SearchOut {
     uint64_t *buf;      // LDS, kSearchBuf entries
@@ -632,14 +629,24 @@ __device__ __forceinline__ void test_plane(const BuildArgs &a, const SearchOut &
         const bool has = q < T;
         int o = wave_scan_max_dpp(out.mark[lane]);
         o = has ? o : 0;
+        // the owner's whole row in one batch of reads; the run is the first
+        // whose end exceeds q, its offset picked by selects
         const int32_t *ro = out.tab + o * kTabRow;
         const int4 e0 = *(const int4 *)(ro + 0);
         const int4 e1 = *(const int4 *)(ro + 4);
-        const int32_t e8 = ro[16];
-        const int k = (int)(e0.x <= q) + (int)(e0.y <= q) + (int)(e0.z <= q) + (int)(e0.w <= q) +
-                      (int)(e1.x <= q) + (int)(e1.y <= q) + (int)(e1.z <= q) + (int)(e1.w <= q) +
-                      (int)(e8 <= q);
-        const int64_t j = (int64_t)ro[tab_j(k < 8 ? k : 8)] + q;
+        const int4 j0 = *(const int4 *)(ro + 8);
+        const int4 j1 = *(const int4 *)(ro + 12);
+        const int2 ej8 = *(const int2 *)(ro + 16);
+        int32_t jb = ej8.y;
+        jb = e1.w > q ? j1.w : jb;
+        jb = e1.z > q ? j1.z : jb;
+        jb = e1.y > q ? j1.y : jb;
+        jb = e1.x > q ? j1.x : jb;
+        jb = e0.w > q ? j0.w : jb;
+        jb = e0.z > q ? j0.z : jb;
+        jb = e0.y > q ? j0.y : jb;
+        jb = e0.x > q ? j0.x : jb;
+        const int64_t j = (int64_t)jb + q;
         __builtin_amdgcn_wave_barrier();
         bool hit = false;
         // (the index checks hold by construction; they keep a wrong owner
