@@ -178,7 +178,7 @@ __device__ __forceinline__ int job_of(const T *__restrict__ jobs, int J, int64_t
 }
 
 // ------------------------------------------------------- pair search
-constexpr int kSearchBuf = 2304;   // entries staged per block in LDS (18 KB)
+constexpr int kSearchBuf = 3072;   // entries staged per block in LDS (24 KB)
 
 // Half partners of particle i are searched: same class with a larger sorted
 // index, and every larger class.  Each listed pair is appended in both
@@ -564,17 +564,34 @@ __device__ __forceinline__ int32_t wave_scan_max_dpp(int32_t v)
 // Row layout (int32, 16-byte rows): E_0..7, J_0..7, E_8, J_8, 2 unused.
 constexpr int kTabRow = 20;
 
-// Per-block output staging of k_search_coop, and the wave's plane table.
+// Per-wave state of k_search_coop in LDS: the wave's particles, its plane
+// table and owner marks, and its output staging.  Each wave stages its
+// entries; when its staging is full it reserves global space with one
+// atomic and copies them out without waiting for the other waves, and what
+// remains at the end goes out with one reservation for the whole block.
+constexpr uint32_t kWaveBuf = 256;   // staged entries per wave (2 KB)
+
 struct SearchOut {
-    uint64_t *buf;      // LDS, kSearchBuf entries
-    uint32_t *nbuf;     // LDS counter
+    const P4 *own;      // LDS, this wave's 64 particles
     int32_t *tab;       // LDS, this wave's 64 rows of kTabRow
     int32_t *mark;      // LDS, this wave's 64 owner marks
+    uint64_t *wbuf;     // LDS, this wave's kWaveBuf staged entries
     uint64_t *list;
     uint32_t *counter;
     int64_t cap;
     int row_bits;
 };
+
+// Copy the wave's n staged entries to the list (called by the whole wave).
+__device__ __forceinline__ void flush_wave(const SearchOut &out, int lane, uint32_t n)
+{
+    uint32_t g = 0;
+    if (lane == 0) g = atomicAdd(out.counter, n);
+    g = (uint32_t)__builtin_amdgcn_readfirstlane((int)g);
+    for (uint32_t k = (uint32_t)lane; k < n; k += kWave)
+        if ((int64_t)g + k < out.cap) gstore(out.list, (int64_t)g + k, out.wbuf[k]);
+    __builtin_amdgcn_wave_barrier();
+}
 
 // Test, with the whole wave, the candidates of one stencil plane: lane t
 // contributes the runs r[0..8] of its nine cells.  A wave prefix sum of
@@ -584,10 +601,11 @@ struct SearchOut {
 // <= q: each lane whose prefix ends inside the round's window marks its
 // position there (the last such lane of a position), and a running maximum
 // over the window gives every candidate its owner.  The owner's table row
-// then gives the run and the sorted index.  Listed pairs take one LDS
-// reservation per wave and round.
+// then gives the run and the sorted index.  Listed pairs are staged at the
+// wave's count wn (the same on every lane).
 __device__ __forceinline__ void test_plane(const BuildArgs &a, const SearchOut &out, int lane,
-                                           uint64_t below, int64_t wbase, const int2 r[9])
+                                           uint64_t below, int64_t wbase, const int2 r[9],
+                                           uint32_t &wn)
 {
     int32_t cum[9];
     int32_t c = 0;
@@ -649,10 +667,10 @@ __device__ __forceinline__ void test_plane(const BuildArgs &a, const SearchOut &
         const int64_t j = (int64_t)jb + q;
         __builtin_amdgcn_wave_barrier();
         bool hit = false;
-        // (the index checks hold by construction; they keep a wrong owner
-        // from reading outside the positions)
-        if (has && (uint64_t)j < (uint64_t)a.n && wbase + o < a.n) {
-            const P4 oq = load_pos(a.pos, wbase + o);
+        // (the index check holds by construction; it keeps a wrong owner from
+        // reading outside the positions)
+        if (has && (uint64_t)j < (uint64_t)a.n) {
+            const P4 oq = out.own[o];
             const P4 qj = load_pos(a.pos, j);
             const double dx = min_image(qj.x - oq.x, a.L, a.hL);
             const double dy = min_image(qj.y - oq.y, a.L, a.hL);
@@ -663,26 +681,19 @@ __device__ __forceinline__ void test_plane(const BuildArgs &a, const SearchOut &
         }
         const uint64_t bal = __ballot(hit);
         if (bal == 0ull) continue;
-        const int lead = __ffsll((unsigned long long)bal) - 1;
-        uint32_t k0 = 0;
-        if (lane == lead) k0 = atomicAdd(out.nbuf, 2u * (uint32_t)__popcll(bal));
-        k0 = __shfl(k0, lead, kWave);
+        const uint32_t cnt = 2u * (uint32_t)__popcll(bal);
+        if (wn + cnt > kWaveBuf) {
+            flush_wave(out, lane, wn);
+            wn = 0;
+        }
         if (hit) {
             const int64_t io = wbase + o;
-            const uint64_t e0 = ((uint64_t)io << out.row_bits) | (uint64_t)j;
-            const uint64_t e1 = ((uint64_t)j << out.row_bits) | (uint64_t)io;
-            const uint32_t kk = k0 + 2u * (uint32_t)__popcll(bal & below);
-            if (kk + 1 < (uint32_t)kSearchBuf) {
-                out.buf[kk] = e0;
-                out.buf[kk + 1] = e1;
-            } else {
-                const uint32_t gi = atomicAdd(out.counter, 2u);
-                if ((int64_t)gi + 1 < out.cap) {
-                    gstore(out.list, (int64_t)gi, e0);
-                    gstore(out.list, (int64_t)gi + 1, e1);
-                }
-            }
+            const uint32_t kk = wn + 2u * (uint32_t)__popcll(bal & below);
+            out.wbuf[kk] = ((uint64_t)io << out.row_bits) | (uint64_t)j;
+            out.wbuf[kk + 1] = ((uint64_t)j << out.row_bits) | (uint64_t)io;
         }
+        wn += cnt;
+        __builtin_amdgcn_wave_barrier();
     }
     __builtin_amdgcn_wave_barrier();
 }
@@ -701,19 +712,16 @@ __device__ __forceinline__ int2 above(int2 r, int64_t i)
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_search_coop(const FrontJob *__restrict__ jobs, int J,
                                                        int xcd_remap, int64_t b_base)
 {
-    __shared__ uint64_t buf[kSearchBuf];
+    __shared__ P4 own[kBlock];
     __shared__ __align__(16) int32_t tab[kBlock * kTabRow];
     __shared__ int32_t mark[kBlock];
-    __shared__ uint32_t nbuf;
-    __shared__ uint32_t gbase;
+    __shared__ uint64_t wbuf[kWavesPerBlock * kWaveBuf];
+    __shared__ uint32_t wcount[kWavesPerBlock];
+    __shared__ uint32_t bbase;
     const int64_t gb =
         b_base + (xcd_remap ? remap_xcd((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x);
     const FrontJob &F = jobs[job_of(jobs, J, gb, &FrontJob::b0)];
     const BuildArgs &a = F.a;
-    uint64_t *const list = F.list;
-    uint32_t *const counter = F.counter;
-    const int64_t cap = F.lcap;
-    const int row_bits = F.row_bits;
     const int64_t blk = (int64_t)gb - F.b0;
     // split grids give every packing 3 * (the batch's deepest) levels; the
     // slices past this packing's levels have nothing to do
@@ -724,8 +732,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const int64_t i = wbase + lane;
     const bool valid = i < a.n;
     const int wofs = (int)(threadIdx.x & ~(kWave - 1));
-    const SearchOut out{buf, &nbuf, tab + wofs * kTabRow, mark + wofs, list, counter, cap,
-                        row_bits};
+    const SearchOut out{own + wofs, tab + wofs * kTabRow, mark + wofs,
+                        wbuf + (wofs / kWave) * kWaveBuf, F.list, F.counter, F.lcap, F.row_bits};
     double xi = 0.0, yi = 0.0, zi = 0.0, di = 0.0;
     int li = kMaxLevels;
     if (valid) {
@@ -736,8 +744,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         di = qi.d;
         li = gload(a.lev, i);
     }
-    if (threadIdx.x == 0) nbuf = 0;
-    __syncthreads();
+    own[threadIdx.x] = P4{xi, yi, zi, di};
+    __builtin_amdgcn_wave_barrier();
     // a grid with gridDim.y > 1 gives each block one level and one plane
     // (fixed x offset) of the stencil: shorter chains of dependent lookups
     // for packings too small to fill the GPU otherwise
@@ -747,6 +755,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         Le = Lb + 1 < a.nlev ? Lb + 1 : a.nlev;
         plane = (int)blockIdx.y % 3;
     }
+    uint32_t wn = 0;
     for (int L = Lb; L < Le; ++L) {
         const LevelGrid g = a.lv[L];
         if (g.count == 0) continue;
@@ -767,15 +776,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 #pragma unroll
                 for (int k = 0; k < 9; ++k) r[k] = above(r[k], i);
             }
-            test_plane(a, out, lane, below, wbase, r);
+            test_plane(a, out, lane, below, wbase, r, wn);
         }
     }
+    // what the waves still hold goes out with one reservation per block
+    const int w = (int)threadIdx.x / kWave;
+    if (lane == 0) wcount[w] = wn;
     __syncthreads();
-    const uint32_t mm = nbuf < (uint32_t)kSearchBuf ? nbuf : (uint32_t)kSearchBuf;
-    if (threadIdx.x == 0) gbase = mm ? atomicAdd(counter, mm) : 0u;
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+        for (int k = 0; k < kWavesPerBlock; ++k) tot += wcount[k];
+        bbase = tot ? atomicAdd(F.counter, tot) : 0u;
+    }
     __syncthreads();
-    for (uint32_t k = threadIdx.x; k < mm; k += kBlock)
-        if ((int64_t)gbase + k < cap) gstore(list, (int64_t)gbase + k, buf[k]);
+    uint32_t g = bbase;
+    for (int k = 0; k < w; ++k) g += wcount[k];
+    for (uint32_t k = (uint32_t)lane; k < wn; k += kWave)
+        if ((int64_t)g + k < F.lcap) gstore(F.list, (int64_t)g + k, out.wbuf[k]);
 }
 
 void launch_search(const BuildArgs &a, uint64_t *list, uint32_t *counter, int64_t cap,
