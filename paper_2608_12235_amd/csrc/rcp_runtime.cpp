@@ -386,8 +386,11 @@ static int build_plan(rcp_ctx *c, int k, double kappa, int64_t min_entries, Buil
             nhashed += a.lv[l].count;
         }
     }
+    // at most a quarter of the slots occupied: a lookup of an absent cell
+    // (most lookups on the sparse levels) rarely meets another key and has to
+    // follow a probe chain (each step a dependent load)
     j.hcap = 64;
-    while (j.hcap < 2 * nhashed) j.hcap <<= 1;
+    while (j.hcap < 4 * nhashed) j.hcap <<= 1;
     // the expected list length with room to spare
     j.lcap = std::max<int64_t>({s.list_est + s.list_est / 4, 8 * n, 1024, min_entries});
     return RCP_OK;

@@ -106,6 +106,38 @@ def test_pairs_bit_exact_random(rcp, orc, fam, S, phi, kb, s, g, n, search):
     assert np.array_equal(gi, oi) and np.array_equal(gj, oj)
 
 
+_EXTREME = {}
+
+
+def _extreme_case(orc, n, kb):
+    # C5's size distribution (lognormal sigma_lnD = 2.5, S = 5e5) and skin
+    # (256 D0_min) at a smaller N: many size levels, most of them hashed, the
+    # 4 x 4 x 4 tile split; N = 530000 gives more than 2048 blocks, so the
+    # search runs on the full grid instead of the level/plane split
+    key = (n, kb)
+    if key not in _EXTREME:
+        d0 = ri.lognormal_quantiles(n, 2.5, 5e5)
+        L = ri.box_for_phi(d0, 0.05)
+        x = ri.uniform_positions(n, L, 11)
+        _EXTREME[key] = (d0, L, x, orc.pairs_cells(x, d0, L, kb, 256.0, 0.02))
+    return _EXTREME[key]
+
+
+@pytest.mark.parametrize("n", [20000, 530000])
+@pytest.mark.parametrize("kb", [1.0, 2.0])
+@pytest.mark.parametrize("search", [0, 64])
+def test_pairs_bit_exact_extreme_size_ratio(rcp, orc, n, kb, search):
+    d0, L, x, (oi, oj) = _extreme_case(orc, n, kb)
+    _say("pairs extreme S N", n, "kb", kb, "search variant", search)
+    p = rcp.Packing(d0, L, kb, 0, init="none", params=rcp.make_params(skin_s=256.0, skin_g=0.02))
+    p.set_tuning(rcp.make_tuning(variant=search))
+    p.set_state(x, kb)
+    assert p.neighbor_build() == len(oi)
+    gi, gj = p.pairs()
+    assert len(oi) > 1000
+    assert np.array_equal(gi, oi) and np.array_equal(gj, oj)
+
+
 def test_pairs_bit_exact_c1_states(rcp, orc):
     w, x, k = _dense_c1_state(orc)
     _say("pairs C1 dense kappa", k)
