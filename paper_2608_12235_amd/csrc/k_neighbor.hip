@@ -135,6 +135,37 @@ __device__ __forceinline__ int64_t dense_index(const BuildArgs &a, int64_t i)
     return g.dbase + (cx * g.nc + cy) * g.nc + cz;
 }
 
+// End of the run of sorted keys equal to key that starts at i (the first
+// index past it, at most n).  The eight keys after i are read together
+// (most runs end there); a longer run is bracketed by doubling steps and the
+// end found by bisection, so a run of c keys costs O(log c) dependent reads.
+__device__ __forceinline__ int64_t run_end(const uint64_t *sk, int64_t n, int64_t i, uint64_t key)
+{
+    uint64_t v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = i + 1 + k < n ? gload(sk, i + 1 + k) : ~key;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (v[k] != key) return i + 1 + k;
+    int64_t lo = i + 9, hi = n, step = 8;   // keys [i, lo) equal key
+    for (;;) {
+        const int64_t p = lo + step - 1;
+        if (p >= n) break;
+        if (gload(sk, p) != key) {
+            hi = p;
+            break;
+        }
+        lo = p + 1;
+        step *= 2;
+    }
+    while (lo < hi) {   // the first index in [lo, hi] whose key differs (hi: differs, or n)
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (gload(sk, mid) == key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // A cell's sorted particles are contiguous (same key): the first one finds
 // the end of the run and writes (start, count), into the dense table of its
 // level or into the hash (inserted by compare-and-swap on the key).
@@ -142,8 +173,7 @@ __device__ __forceinline__ void cells_one(const BuildArgs &a, int64_t i)
 {
     const uint64_t key = a.skey[i];
     if (i > 0 && a.skey[i - 1] == key) return;
-    int64_t e = i + 1;
-    while (e < a.n && a.skey[e] == key) ++e;
+    const int64_t e = run_end(a.skey, a.n, i, key);
     const int32_t start = (int32_t)i, count = (int32_t)(e - i);
     if (a.lv[a.lev[i]].dbase >= 0) {
         a.dense[dense_index(a, i)] = make_int2(start, count);
