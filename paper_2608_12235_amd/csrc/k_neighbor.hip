@@ -357,14 +357,15 @@ __global__ __launch_bounds__(kBlock) void k_search(BuildArgs a, uint64_t *__rest
 
 // ------------------------------------------------ wave-cooperative search
 // The same search with the candidates of a wave flattened: for one level
-// and one stencil slot, every lane contributes the run [start, start +
-// count) of its cell (restricted to larger indices in its own level), a
-// wave prefix sum numbers the candidates, and the 64 lanes test
-// consecutive candidates together, each lane finding the candidate's owner
-// by a binary search over the prefix.  A particle's candidate set and the
+// and one stencil plane (the nine cells at one x offset), every lane
+// contributes the runs [start, start + count) of its nine cells
+// (restricted to larger indices in its own level), a wave prefix sum
+// numbers all of them as one sequence, and the 64 lanes test consecutive
+// candidates together (test_plane).  A particle's candidate set and the
 // pair test are those of k_search, so the listed pairs are the same; only
 // the order in which entries are appended differs (the list is sorted
 // afterwards).
+
 // Loads through global-address-space views (global rather than flat
 // instructions, so waiting for LDS results does not also wait for them).
 typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
