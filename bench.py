@@ -109,6 +109,48 @@ def copy_reference(torch, mib):
     print(json.dumps({"copy_reference_mib": mib, "launches": 3}), flush=True)
 
 
+def run_builds(torch, args):
+    """List builds alone: the workload's state after --warmup iterations,
+    then --builds rebuilds of its neighbour list timed one by one (the
+    profiling target for the build kernels; no iteration in between)."""
+    import rcp_inputs as ri
+    import paper_2608_12235_amd as rcp
+    if args.workload == "c5":
+        w = ri.c5_extreme(n=3_000_000 if args.n == 1_000_000 else args.n)
+        d0, L, seed = w.d0, w.L, w.seed
+        skin = 256.0 if args.skin == 16.0 else args.skin
+        tun = rcp.make_tuning(row_cost=16, item_work=4096)
+        name = "lognormal sigma_lnD=2.5 S=5e5 N=%d" % len(d0)
+    else:
+        d0 = ri.lognormal_quantiles(args.n, 1.0, 1e3)
+        L, seed, skin = ri.box_for_phi(d0, args.phi0), 0, args.skin
+        tun = rcp.make_tuning()
+        name = "lognormal sigma_lnD=1.0 S=1e3 N=%d" % len(d0)
+    if args.variant is not None:
+        tun.variant = args.variant
+    S = float(d0.max() / d0.min())
+    p = rcp.Packing(d0, L, 1.0, seed, init="rsa", params=rcp.make_params(skin_s=skin),
+                    tuning=tun)
+    p.run_start(rcp.default_schedule(len(d0), S=S))
+    p.run_continue(args.warmup)
+    torch.cuda.synchronize()
+    it = p.run_result()["iterations"]
+    ms = []
+    npairs = 0
+    for _ in range(args.builds):
+        t0 = time.perf_counter()
+        npairs = p.neighbor_build()
+        torch.cuda.synchronize()
+        ms.append((time.perf_counter() - t0) * 1e3)
+    p.close()
+    out = {"metric": "list build time", "value": float(np.mean(ms)), "unit": "ms",
+           "higher_is_better": False, "builds": args.builds, "median_ms": float(np.median(ms)),
+           "config": {"workload": "%s, RSA start at phi0=0.05, state after %d iterations, "
+                                  "skin %g D0_min" % (name, it, skin),
+                      "listed_pairs": int(npairs), "variant": int(tun.variant)}}
+    print(json.dumps(out), flush=True)
+
+
 def _kernel_roofline(st, n):
     nl = max(st["kernel_launches"], 1)
     it_us = 1e3 * st["kernel_ms"] / nl
@@ -226,6 +268,9 @@ def main():
                     help="lognormal: the default line; c5: lognormal sigma_lnD=2.5, S=5e5, "
                          "N=3e6 run to the stop criterion; census: 64 packings batched vs a loop "
                          "of plain solves")
+    ap.add_argument("--builds", type=int, default=0, metavar="K",
+                    help="only time K neighbour-list builds of the lognormal or c5 workload "
+                         "after --warmup iterations and exit")
     ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times "
                          "(the known-size reference for hardware byte counters) and exit")
@@ -244,6 +289,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_reference > 0:
         copy_reference(torch, args.copy_reference)
+        return
+    if args.builds > 0:
+        run_builds(torch, args)
         return
     if args.workload == "c5":
         run_c5(torch, args)
