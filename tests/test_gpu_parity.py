@@ -138,6 +138,34 @@ def test_pairs_bit_exact_extreme_size_ratio(rcp, orc, n, kb, search):
     assert np.array_equal(gi, oi) and np.array_equal(gj, oj)
 
 
+@pytest.mark.parametrize("spread", [3.0, 1.2])
+@pytest.mark.parametrize("search", [0, 64])
+def test_pairs_bit_exact_dense_cluster(rcp, orc, spread, search):
+    # every sphere inside a ball of radius spread * D_max straddling the
+    # periodic corner of a nearly empty box: crowded cells (long runs of
+    # one key), many candidates and partners per sphere (the search's
+    # staging fills and is flushed), and a list far longer than the one
+    # estimated from the volume fraction (the list capacity grows)
+    n = 3000
+    d0 = ri.lognormal_quantiles(n, 1.0, 4.0)
+    L = ri.box_for_phi(d0, 0.001)
+    rng = np.random.default_rng(3)
+    u = rng.normal(size=(n, 3))
+    u /= np.linalg.norm(u, axis=1)[:, None]
+    r = spread * d0.max() * rng.random(n) ** (1.0 / 3.0)
+    x = np.mod(0.999 * L + u * r[:, None], L)
+    _say("pairs dense cluster spread", spread, "search variant", search)
+    p = rcp.Packing(d0, L, 1.0, 0, init="none", params=rcp.make_params(skin_s=0.5, skin_g=0.02))
+    p.set_tuning(rcp.make_tuning(variant=search))
+    p.set_state(x, 1.0)
+    npairs = p.neighbor_build()
+    gi, gj = p.pairs()
+    oi, oj = orc.pairs_brute(x, d0, L, 1.0, 0.5, 0.02)
+    assert len(oi) > 50000
+    assert npairs == len(oi)
+    assert np.array_equal(gi, oi) and np.array_equal(gj, oj)
+
+
 def test_pairs_bit_exact_c1_states(rcp, orc):
     w, x, k = _dense_c1_state(orc)
     _say("pairs C1 dense kappa", k)
