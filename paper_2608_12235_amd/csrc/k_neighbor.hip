@@ -646,9 +646,9 @@ __device__ __forceinline__ void test_plane(const BuildArgs &a, const SearchOut &
         cum[k] = c;
     }
     // candidate numbers are 32-bit: a plane's total is at most 64 lanes x 9
-    // cells x the largest cell, which exceeds 2^31 only when nearly every
-    // sphere of a packing of millions shares a handful of cells (a list of
-    // ~n^2 pairs, far beyond any list capacity)
+    // cells x the largest cell, which exceeds 2^31 only with more than 3.7
+    // million spheres in one cell (their ~10^13 pairs would not fit any
+    // list)
     const int32_t inc = wave_scan_incl_dpp(c);
     const int32_t T = __builtin_amdgcn_readlane(inc, kWave - 1);
     if (T == 0) return;
