@@ -526,9 +526,10 @@ __device__ __forceinline__ void coop_stencil(const BuildArgs &a, const LevelGrid
 
 // Cell runs (start, count) of the nine slots of stencil plane ox.  Every
 // table read of the plane is issued before any is used, so a wave has nine
-// lookups in flight instead of one; lanes that do not search a slot read the
-// level's first entry (one shared line) and discard it.  A hash probe that
-// meets another key (a collision) continues along the probe sequence.
+// lookups in flight instead of one; lanes that do not search a slot read a
+// fixed entry (the level's first dense cell, or the hash table's first
+// slot: one shared line) and discard it.  A hash probe that meets another
+// key (a collision) continues along the probe sequence.
 __device__ __forceinline__ void lookup_plane(const BuildArgs &a, const CoopStencil &S,
                                              bool dense, uint64_t base, int ox, int2 r[9])
 {
