@@ -177,7 +177,7 @@ def run_c5(torch, args):
     skin = C5_SKIN if args.skin == 16.0 else args.skin
     log("placement (random sequential addition, N=%d, S=%.3g)" % (n, S))
     # work cut 16 / 4096 measured faster than the library default on this
-    # workload (175 against 190 us per iteration launch)
+    # workload (176 against 196 us per iteration launch at skin 2048)
     tun = rcp.make_tuning(time_kernels=1, row_cost=16, item_work=4096)
     if args.row_cost is not None:
         tun.row_cost = args.row_cost
