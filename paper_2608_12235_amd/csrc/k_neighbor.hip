@@ -601,6 +601,10 @@ constexpr int kTabRow = 20;
 // entries; when its staging is full it reserves global space with one
 // atomic and copies them out without waiting for the other waves, and what
 // remains at the end goes out with one reservation for the whole block.
+// Only the wave itself reads and writes these arrays, and the LDS executes
+// a wave's accesses in order, so no block barrier is needed between a
+// write and the reads of other lanes (wave barriers keep the compiler from
+// moving accesses across them).
 constexpr uint32_t kWaveBuf = 256;   // staged entries per wave (2 KB)
 
 struct SearchOut {
