@@ -603,8 +603,8 @@ constexpr int kTabRow = 20;
 // remains at the end goes out with one reservation for the whole block.
 // Only the wave itself reads and writes these arrays, and the LDS executes
 // a wave's accesses in order, so no block barrier is needed between a
-// write and the reads of other lanes (wave barriers keep the compiler from
-// moving accesses across them).
+// write and the reads of other lanes (the compiler keeps a store and a
+// later load of the same array in order, as their addresses may alias).
 constexpr uint32_t kWaveBuf = 256;   // staged entries per wave (2 KB)
 
 struct SearchOut {
