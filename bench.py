@@ -1,36 +1,44 @@
 #!/usr/bin/env python
 """Throughput of the inflation hot path on one MI355X.
 
-Workload: N = 1e6 relative diameters from the truncated lognormal with
-sigma_lnD = 1.0 and S = 1e3 (equal-probability quantiles), placed by random
-sequential addition at phi0 = 0.05 in a periodic cube (the paper's dilute,
-non-overlapping start), FP64 throughout, the default schedule for that size
-ratio.  One step is one inflation iteration: energy gradient over the
-neighbour list, Adam on positions and kappa, the tail (schedule, stop and
-validity tests), and a list rebuild whenever the validity test asks for
-one.  After W untimed iterations, K iterations are timed;
-value = N x K / wall time.
+Primary workload (the one the line's value and roofline are for): the
+dense random state of N = 1e6 spheres, relative diameters from the truncated
+lognormal with sigma_lnD = 1.0 and S = 1e3 (equal-probability quantiles),
+i.i.d. uniform positions at phi = 0.6 in a periodic cube (overlaps
+allowed), FP64 throughout.  One step is one inflation iteration from that
+state: energy gradient over the neighbour list, Adam on positions and kappa,
+the tail (schedule, stop and validity tests), and a list rebuild whenever
+the validity test asks for one.  mu and the step sizes are held at the
+values the default schedule's final relaxation rung takes at this state,
+the listing skin is 4 D0_min.  The list is built during the W untimed
+warm-up iterations; K iterations are then timed with inputs resident in
+device memory; value = N x K / wall time (rebuilds in the window included,
+and reported separately).
 
 The roofline entry is for the fused gradient + Adam kernel (k_iterate):
-algorithmic bytes per launch = 188 N + 4 nnz (read x, y, z, D0 as one
-32-byte record, m, v, x_ref and a row pointer; write the position record,
-m and v; 4 bytes per listed partner; partner gathers are assumed
-cache-served), with nnz averaged over the timed launches, divided by the
-kernel's mean duration from HIP events the library records on its stream
-around the middle launch of every graph of the timed region (one launch in
-graph_iters, a uniform sample: event nodes cost a few microseconds each;
---kernel-timing 2 brackets every launch, 0 none and omits the roofline
-entry).
-traffic is the HBM bytes per launch from the hardware counters committed
-under profiles/ (FETCH_SIZE x 2 + WRITE_SIZE x 1, the scales measured with
-a plain copy); it is null when the kernel sources differ from the ones the
-counters were taken on.  The CPU baseline is the FP64 oracle (OpenMP over
-rows) on the same diameters in the same box, gradient + Adam only.
+algorithmic bytes per launch = (176 + 4) N + 4 nnz (read x, D0, m, v, x_ref
+and a row pointer; write x', m, v; 4 bytes per listed partner; partner
+gathers assumed cache-served), nnz the listed partners (both directions)
+averaged over the timed launches, divided by the kernel's mean duration from
+HIP events the library records on its own stream around every launch of
+the timed region.  traffic is the HBM bytes per launch from the hardware
+counters committed under profiles/ (FETCH_SIZE x 2 + WRITE_SIZE x 1, the
+scales measured with a plain copy), null when the kernel sources differ
+from the ones the counters were taken on.
+
+Secondary legs run first, each in a child process of its own (before this
+process touches the GPU), and are reported as sub-objects: the C2 whole run
+(power law p = -3, S = 20, N = 1e5, RSA start at phi0 = 0.05, to the stop
+criterion), the RSA-start window of the lognormal S = 1e3 workload, and the
+census of 64 packings batched against a loop of plain solves.  The CPU
+baseline is the FP64 oracle (OpenMP over rows) on the primary state itself,
+gradient + Adam only, timed on every host thread and on one.
 """
 import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -42,8 +50,14 @@ sys.path.insert(0, ROOT)
 METRIC = "particle-updates/s (Adam iters/s × N) and % HBM peak; batched vs plain loop"
 HBM_PEAK_GBS = 8000.0
 C5_SKIN = 2048.0   # listing skin of the extreme size-ratio workload, in D0_min
+C3_SKIN = 4.0      # listing skin of the primary workload, in D0_min
 KERNEL_SOURCES = ["paper_2608_12235_amd/csrc/k_iterate.hip", "paper_2608_12235_amd/csrc/rcp_dev.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_iterate_traffic.json")
+# algorithmic bytes per sphere update of the gradient + Adam kernel: read x
+# (24), D0 (8), m (24), v (24), x_ref (24); write x' (24), m (24), v (24); one
+# row pointer (4); plus 4 per listed partner
+BYTES_PER_SPHERE = 176.0 + 4.0
+BYTES_PER_PARTNER = 4.0
 
 
 def kernel_source_hash():
@@ -54,15 +68,16 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def counter_traffic():
-    """HBM bytes per k_iterate launch from the committed counter summary,
-    or None when the kernel has changed since the counters were taken."""
+def counter_traffic(workload):
+    """HBM bytes per k_iterate launch from the committed counter summary of
+    this workload, or None when the kernel has changed since the counters
+    were taken."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None, None
-    if t.get("source_sha256") != kernel_source_hash():
+    if t.get("source_sha256") != kernel_source_hash() or t.get("workload") != workload:
         return None, t
     b = 1024.0 * (t["fetch_kib_per_launch"] * t["fetch_scale"] +
                   t["write_kib_per_launch"] * t["write_scale"])
@@ -73,29 +88,42 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(d0, L, phi, skin_s, skin_g, target_s=12.0):
-    """Oracle gradient + Adam iterations on the host cores (bounded sample).
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    State: the same diameters in the same box, i.i.d. uniform positions
-    (seeded generator) at the scale kappa that gives the volume fraction the
-    GPU run had reached, so the list density is comparable.
-    """
+
+def cpu_baseline(x, d0, L, kappa, eta_x, skin_s, skin_g, target_s=10.0):
+    """Oracle gradient + Adam iterations on the host cores (bounded samples)
+    on the given state: every host thread, then one thread."""
     import oracle
-    import rcp_inputs as ri
     oracle.lib()
     threads = oracle.num_threads()
     n = d0.shape[0]
-    kappa = float((phi * L ** 3 / (np.pi / 6.0 * np.sum(d0 ** 3))) ** (1.0 / 3.0))
-    x = ri.uniform_positions(n, L, 7)
-    t, npairs = oracle.time_iterations(x, d0, L, kappa, 1e-2, 2, s=skin_s, g=skin_g)
-    per = max(t / 2, 1e-6)
-    iters = int(max(3, min(500, target_s / per)))
-    t, npairs = oracle.time_iterations(x, d0, L, kappa, 1e-2, iters, s=skin_s, g=skin_g)
-    return {"value": n * iters / t, "unit": "particle-updates/s", "cores": threads,
-            "kind": "oracle",
-            "sample": "%d gradient+Adam iterations of the FP64 oracle, N=%d, same diameters and "
-                      "box, uniform positions at phi=%.3f (%d listed pairs; list build "
-                      "excluded), %.1f s" % (iters, n, phi, npairs, t)}
+    out = {}
+    for label, th in (("all", 0), ("one", 1)):
+        t, npairs = oracle.time_iterations(x, d0, L, kappa, eta_x, 1, s=skin_s, g=skin_g,
+                                           threads=th)
+        per = max(t, 1e-6)
+        iters = int(max(2, min(500, target_s / per)))
+        t, npairs = oracle.time_iterations(x, d0, L, kappa, eta_x, iters, s=skin_s, g=skin_g,
+                                           threads=th)
+        out[label] = (n * iters / t, iters, t, npairs)
+    v, iters, t, npairs = out["all"]
+    v1, iters1, t1, _ = out["one"]
+    return {"value": v, "unit": "particle-updates/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_threads": os.cpu_count(),
+            "value_1_thread": v1,
+            "sample": "%d gradient+Adam iterations of the FP64 oracle on %d threads (%.1f s) "
+                      "and %d on 1 thread (%.1f s), N=%d, the primary state itself (same "
+                      "diameters, box, positions and kappa; %d listed pairs; list build "
+                      "excluded)" % (iters, threads, t, iters1, t1, n, npairs)}
 
 
 def copy_reference(torch, mib):
@@ -119,12 +147,13 @@ def run_builds(torch, args):
     if args.workload == "c5":
         w = ri.c5_extreme(n=3_000_000 if args.n == 1_000_000 else args.n)
         d0, L, seed = w.d0, w.L, w.seed
-        skin = C5_SKIN if args.skin == 16.0 else args.skin
+        skin = C5_SKIN if args.skin is None else args.skin
         tun = rcp.make_tuning(row_cost=16, item_work=4096)
         name = "lognormal sigma_lnD=2.5 S=5e5 N=%d" % len(d0)
     else:
         d0 = ri.lognormal_quantiles(args.n, 1.0, 1e3)
-        L, seed, skin = ri.box_for_phi(d0, args.phi0), 0, args.skin
+        L, seed = ri.box_for_phi(d0, 0.05), 0
+        skin = 16.0 if args.skin is None else args.skin
         tun = rcp.make_tuning()
         name = "lognormal sigma_lnD=1.0 S=1e3 N=%d" % len(d0)
     if args.variant is not None:
@@ -156,11 +185,20 @@ def _kernel_roofline(st, n):
     nl = max(st["kernel_launches"], 1)
     it_us = 1e3 * st["kernel_ms"] / nl
     nnz = st["kernel_nnz"] / nl
-    b = 188.0 * n + 4.0 * nnz
+    b = BYTES_PER_SPHERE * n + BYTES_PER_PARTNER * nnz
     a = b / (it_us * 1e-6) / 1e9 if it_us > 0 else 0.0
     return {"bound": "hbm", "kernel": "k_iterate", "achieved": a, "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": a / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": b,
-            "avg_launch_us": it_us, "launches_timed": st["kernel_launches"]}
+            "avg_launch_us": it_us, "launches_timed": st["kernel_launches"],
+            "nnz_per_sphere": nnz / n}
+
+
+def _apply_tuning_args(tun, args):
+    for k in ("graph_iters", "fused_tail", "row_cost", "item_work", "xcd_remap", "variant"):
+        v = getattr(args, k)
+        if v is not None:
+            setattr(tun, k, v)
+    return tun
 
 
 def run_c5(torch, args):
@@ -174,17 +212,12 @@ def run_c5(torch, args):
     # slows as the skin grows while rebuilds get rarer (whole runs: 1.18e10
     # updates/s at 256, 1.44e10 at 768, 1.52e10 at 1536, 1.53e10 at 3072,
     # where the kernel starts to slow)
-    skin = C5_SKIN if args.skin == 16.0 else args.skin
+    skin = C5_SKIN if args.skin is None else args.skin
     log("placement (random sequential addition, N=%d, S=%.3g)" % (n, S))
     # work cut 16 / 4096 measured faster than the library default on this
     # workload (176 against 196 us per iteration launch at skin 2048)
     tun = rcp.make_tuning(time_kernels=1, row_cost=16, item_work=4096)
-    if args.row_cost is not None:
-        tun.row_cost = args.row_cost
-    if args.item_work is not None:
-        tun.item_work = args.item_work
-    if args.variant is not None:
-        tun.variant = args.variant
+    _apply_tuning_args(tun, args)
     p = rcp.Packing(w.d0, w.L, 1.0, w.seed, init="rsa", params=rcp.make_params(skin_s=skin),
                     tuning=tun)
     p.run_start(rcp.default_schedule(n, S=S))
@@ -216,118 +249,134 @@ def run_c5(torch, args):
     print(json.dumps(out), flush=True)
 
 
-def run_census(torch, args):
+# ------------------------------------------------------------ secondary legs
+def leg_c2(torch, args):
+    """Power law p = -3 on [1, 20], N = 1e5, RSA at phi0 = 0.05, seed 0, the
+    default schedule run to the stop criterion (whole run, rebuilds and
+    shrink included)."""
+    import rcp_inputs as ri
+    import paper_2608_12235_amd as rcp
+    w = ri.c2_powerlaw(seed=0)
+    p = rcp.Packing(w.d0, w.L, 1.0, w.seed, init="rsa")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = p.inflate_run()[0]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = p.stats()
+    p.close()
+    return {"workload": "powerlaw p=-3 S=20 N=%d, RSA start at phi0=0.05, seed 0, default "
+                        "schedule, whole run to the stop criterion" % w.n,
+            "value": w.n * r["iterations"] / wall, "unit": "particle-updates/s",
+            "seconds": wall, "iterations": r["iterations"], "phi_final": r["phi"],
+            "status": r["status"], "max_overlap_before_shrink": r["max_overlap"],
+            "rebuilds": st["rebuilds"], "rebuild_ms": st["rebuild_ms"]}
+
+
+def leg_rsa(torch, args):
+    """Lognormal S = 1e3, N = 1e6, RSA start at phi0 = 0.05, default
+    schedule, listing skin 16 D0_min: iterations 200..2200 of the run."""
+    import rcp_inputs as ri
+    import paper_2608_12235_amd as rcp
+    n = 1_000_000
+    d0 = ri.lognormal_quantiles(n, 1.0, 1e3)
+    L = ri.box_for_phi(d0, 0.05)
+    tun = rcp.make_tuning(time_kernels=1)
+    p = rcp.Packing(d0, L, 1.0, 0, init="rsa", params=rcp.make_params(skin_s=16.0), tuning=tun)
+    p.run_start(rcp.default_schedule(n, S=float(d0.max() / d0.min())))
+    p.run_continue(200)
+    torch.cuda.synchronize()
+    p.reset_stats()
+    t0 = time.perf_counter()
+    p.run_continue(2000)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = p.stats()
+    p.close()
+    rf = _kernel_roofline(st, n)
+    return {"workload": "lognormal sigma_lnD=1.0 S=1e3 N=1e6, RSA start at phi0=0.05, default "
+                        "schedule, skin 16 D0_min, iterations 200..2200",
+            "value": n * st["iterations"] / wall, "unit": "particle-updates/s",
+            "k_iterate_us": rf["avg_launch_us"], "k_iterate_frac": rf["frac"],
+            "nnz_per_sphere": rf["nnz_per_sphere"], "launches_timed": rf["launches_timed"],
+            "rebuilds": st["rebuilds"], "rebuild_ms": st["rebuild_ms"]}
+
+
+def leg_census(torch, args):
     """C4: 64 packings in one context against a loop of plain solves."""
     import rcp_inputs as ri
     from paper_2608_12235_amd import census
     wl = ri.census_draw(64)
     ntot = sum(w.n for w in wl)
-    log("census: 64 packings, sum N = %d; batched" % ntot)
     res_b, tb, st = census.run_batched(wl)
-    log("batched %.1f s; loop of plain solves" % tb)
     res_l, tl = census.run_loop(wl)
-    log("loop %.1f s; autotuned" % tl)
-    res_a, ta, info = census.run_autotuned(wl)
-    ub = census.particle_updates(res_b, wl)
     phib = np.array([r["phi"] for r in res_b])
     phil = np.array([r["phi"] for r in res_l])
-    phia = np.array([r["phi"] for r in res_a])
-    out = {"metric": METRIC, "value": ub / tb, "unit": "particle-updates/s", "n_gpus": 1,
-           "steps": int(max(r["iterations"] for r in res_b)), "warmup": 0,
-           "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "census of 64 packings (lognormal / power law / Weibull, "
-                                  "S 2..100, N 1e3..2e5, sum N %d), whole runs" % ntot,
-                      "batched_s": tb, "loop_s": tl, "autotuned_s": ta,
-                      "speedup_batched": tl / tb, "speedup_autotuned": tl / ta,
-                      "loop_value": census.particle_updates(res_l, wl) / tl,
-                      "bit_identical_batched_vs_loop": bool(np.array_equal(phib, phil)),
-                      "mean_phi_batched": float(phib.mean()),
-                      "mean_phi_autotuned": float(phia.mean()),
-                      "autotune_choice": info["best"],
-                      "statuses": sorted(set(int(r["status"]) for r in res_b)),
-                      "rebuilds_batched": st["rebuilds"], "rebuild_ms_batched": st["rebuild_ms"]}}
-    print(json.dumps(out), flush=True)
+    ub = census.particle_updates(res_b, wl)
+    return {"workload": "census of 64 packings (lognormal / power law / Weibull, S 2..100, "
+                        "N 1e3..2e5, sum N %d), whole runs" % ntot,
+            "value": ub / tb, "unit": "particle-updates/s",
+            "batched_s": tb, "loop_s": tl, "speedup_batched": tl / tb,
+            "loop_value": census.particle_updates(res_l, wl) / tl,
+            "bit_identical_batched_vs_loop": bool(np.array_equal(phib, phil)),
+            "mean_phi": float(phib.mean()),
+            "statuses": sorted(set(int(r["status"]) for r in res_b)),
+            "rebuilds": st["rebuilds"], "rebuild_ms": st["rebuild_ms"]}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--n", type=int, default=1_000_000)
-    ap.add_argument("--phi0", type=float, default=0.05)
-    ap.add_argument("--skin", type=float, default=16.0)
-    ap.add_argument("--skin-g", type=float, default=0.02)
-    ap.add_argument("--graph-iters", type=int, default=None)
-    ap.add_argument("--fused-tail", type=int, default=None)
-    ap.add_argument("--row-cost", type=int, default=None)
-    ap.add_argument("--item-work", type=int, default=None)
-    ap.add_argument("--xcd-remap", type=int, default=None)
-    ap.add_argument("--variant", type=int, default=None)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel-timing", type=int, default=1, choices=(0, 1, 2),
-                    help="HIP events around 0: no launch (no roofline entry), 1: the middle "
-                         "launch of every graph, 2: every launch")
-    ap.add_argument("--workload", default="lognormal", choices=("lognormal", "c5", "census"),
-                    help="lognormal: the default line; c5: lognormal sigma_lnD=2.5, S=5e5, "
-                         "N=3e6 run to the stop criterion; census: 64 packings batched vs a loop "
-                         "of plain solves")
-    ap.add_argument("--builds", type=int, default=0, metavar="K",
-                    help="only time K neighbour-list builds of the lognormal or c5 workload "
-                         "after --warmup iterations and exit")
-    ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
-                    help="only run a plain device-to-device copy of MIB MiB three times "
-                         "(the known-size reference for hardware byte counters) and exit")
-    args = ap.parse_args()
+LEGS = {"c2": leg_c2, "rsa": leg_rsa, "census": leg_census}
+LEG_KEYS = {"c2": "c2_whole_run", "rsa": "rsa_start_window", "census": "census"}
+LEG_TIMEOUT = {"c2": 300, "rsa": 300, "census": 600}
 
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(packings shard across GPUs without communication; see the design "
-              "notes). Run with --gpus 1.", file=sys.stderr)
-        sys.exit(2)
 
-    import torch
-    if not torch.cuda.is_available():
-        print("bench.py needs a HIP device", file=sys.stderr)
-        sys.exit(1)
-    torch.cuda.set_device(0)
-    if args.copy_reference > 0:
-        copy_reference(torch, args.copy_reference)
-        return
-    if args.builds > 0:
-        run_builds(torch, args)
-        return
-    if args.workload == "c5":
-        run_c5(torch, args)
-        return
-    if args.workload == "census":
-        run_census(torch, args)
-        return
+def run_legs(names):
+    """Each leg in a child process of its own (started before this process
+    initialises the GPU); returns {key: result or error}."""
+    out = {}
+    for name in names:
+        log("leg %s (child process)" % name)
+        t0 = time.perf_counter()
+        try:
+            r = subprocess.run([sys.executable, os.path.abspath(__file__), "--leg", name],
+                               capture_output=True, text=True, timeout=LEG_TIMEOUT[name])
+        except subprocess.TimeoutExpired:
+            out[LEG_KEYS[name]] = {"error": "timed out after %d s" % LEG_TIMEOUT[name]}
+            continue
+        sys.stderr.write(r.stderr)
+        res = None
+        for line in r.stdout.splitlines():
+            if line.startswith("{"):
+                res = json.loads(line)
+        if r.returncode != 0 or res is None:
+            out[LEG_KEYS[name]] = {"error": "exit code %d" % r.returncode}
+        else:
+            out[LEG_KEYS[name]] = res
+        log("leg %s done in %.1f s" % (name, time.perf_counter() - t0))
+    return out
+
+
+# ------------------------------------------------------------ primary
+def run_primary(torch, args):
     import rcp_inputs as ri
     import paper_2608_12235_amd as rcp
 
-    d0 = ri.lognormal_quantiles(args.n, 1.0, 1e3)
-    L = ri.box_for_phi(d0, args.phi0)
+    w = ri.c3_lognormal_dense(seed=0, n=args.n)
+    n, d0, L = w.n, w.d0, w.L
     S = float(d0.max() / d0.min())
+    skin = C3_SKIN if args.skin is None else args.skin
     tun = rcp.make_tuning()
     tun.time_kernels = args.kernel_timing
-    if args.graph_iters is not None:
-        tun.graph_iters = args.graph_iters
-    if args.fused_tail is not None:
-        tun.fused_tail = args.fused_tail
-    if args.row_cost is not None:
-        tun.row_cost = args.row_cost
-    if args.item_work is not None:
-        tun.item_work = args.item_work
-    if args.xcd_remap is not None:
-        tun.xcd_remap = args.xcd_remap
-    if args.variant is not None:
-        tun.variant = args.variant
-    params = rcp.make_params(skin_s=args.skin, skin_g=args.skin_g)
-    log("placement (random sequential addition, N=%d)" % args.n)
-    p = rcp.Packing(d0, L, 1.0, 0, init="rsa", params=params, tuning=tun)
-    p.run_start(rcp.default_schedule(args.n, S=S))
+    _apply_tuning_args(tun, args)
+    params = rcp.make_params(skin_s=skin, skin_g=args.skin_g)
+    # mu and the step sizes of the default schedule's final rung, held fixed
+    ds = rcp.default_schedule(n, S=S)
+    r = ds.n_rungs - 1
+    sched = rcp.schedule_from_rungs(
+        [(ds.mu[r], ds.eta_x[r], ds.eta_k[r], 1.0, args.warmup + args.steps + 1)], tol=-1.0)
+    log("primary: %s, kappa 1, skin %g D0_min" % (w.name, skin))
+    p = rcp.Packing(d0, L, 1.0, 0, init="none", params=params, tuning=tun)
+    p.set_state(w.x, 1.0)
+    p.run_start(sched)
     log("warmup %d iterations" % args.warmup)
     if args.warmup:
         p.run_continue(args.warmup)
@@ -340,23 +389,26 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st = p.stats()
+    _, _, opt = p.get_optimizer(moments=False)
+    res = p.run_result()
+    xs, kap = p.get_state()
+    p.close()
     iters = st["iterations"]
     wall = t1 - t0
-    value = args.n * iters / wall
-    res = p.run_result()
+    value = n * iters / wall
     log("stats", st)
+    rf = _kernel_roofline(st, n)
     nl = max(st["kernel_launches"], 1)
-    it_us = 1e3 * st["kernel_ms"] / nl
     tail_us = 1e3 * st["tail_kernel_ms"] / nl
-    nnz_mean = st["kernel_nnz"] / nl
-    alg_bytes = 188.0 * args.n + 4.0 * nnz_mean
-    achieved = alg_bytes / (it_us * 1e-6) / 1e9 if it_us > 0 else 0.0
-    traffic, tinfo = counter_traffic()
-    phi_now = float(np.pi / 6.0 * res["kappa_before_shrink"] ** 3 * np.sum(d0 ** 3) / L ** 3)
-    log("state after the timed region: kappa %.6f phi %.4f max_overlap %.3e rung %d; "
-        "k_iterate %.1f us, tail %.1f us (mean over %d timed launches)" %
-        (res["kappa_before_shrink"], phi_now, res["max_overlap"], res["rung"], it_us, tail_us,
-         st["kernel_launches"]))
+    wl_name = "c3_lognormal_S1e3_N%d_phi0.6_uniform" % n
+    traffic, tinfo = counter_traffic(wl_name)
+    rf["traffic"] = traffic
+    rf["traffic_source"] = (tinfo or {}).get("summary") if traffic is not None else None
+    phi_now = float(np.pi / 6.0 * kap ** 3 * np.sum(d0 ** 3) / L ** 3)
+    log("after the timed region: kappa %.6f phi %.4f max_overlap %.3e; k_iterate %.2f us, tail "
+        "%.2f us (mean over %d launches), nnz/N %.3f" %
+        (kap, phi_now, res["max_overlap"], rf["avg_launch_us"], tail_us, st["kernel_launches"],
+         rf["nnz_per_sphere"]))
     out = {
         "metric": METRIC,
         "value": value,
@@ -371,12 +423,15 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "lognormal sigma_lnD=1.0 S=1e3 N=%d, RSA start at phi0=%g, 3-D "
-                        "periodic, default schedule, iterations %d..%d" %
-                        (args.n, args.phi0, args.warmup, args.warmup + iters),
-            "n": args.n,
+            "workload": "lognormal sigma_lnD=1.0 S=1e3 N=%d, i.i.d. uniform positions at "
+                        "phi=0.6 (kappa 1), 3-D periodic; Adam iterations %d..%d with mu, "
+                        "eta_x, eta_k of the default schedule's final rung held fixed; "
+                        "listing skin %g D0_min" % (n, args.warmup, args.warmup + iters, skin),
+            "n": n,
+            "nnz_per_sphere": rf["nnz_per_sphere"],
+            "mu": opt["mu"], "eta_x": opt["eta_x"], "eta_k": opt["eta_k"],
             "phi_after_timed_region": phi_now,
-            "skin_s": args.skin,
+            "skin_s": skin,
             "skin_g": args.skin_g,
             "graph_iters": tun.graph_iters,
             "fused_tail": tun.fused_tail,
@@ -387,31 +442,85 @@ def main():
             "rebuilds_in_timed_region": st["rebuilds"],
             "rebuild_ms": st["rebuild_ms"],
             "iterate_ms": st["iterate_ms"],
-            "nnz_mean_per_launch": nnz_mean,
             "max_degree": st["max_degree"],
             "tail_us": tail_us,
-            "kernel_rate": args.n / (it_us * 1e-6) if it_us > 0 else None,
+            "kernel_rate": n / (rf["avg_launch_us"] * 1e-6) if rf["avg_launch_us"] > 0 else None,
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_iterate",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "bytes_per_launch": alg_bytes,
-            "avg_launch_us": it_us,
-            "launches_timed": st["kernel_launches"],
-            "traffic_source": (tinfo or {}).get("summary") if traffic is not None else None,
-        },
+        "roofline": rf,
     }
     if args.kernel_timing == 0:
         del out["roofline"]
-    p.close()
+    return out, (w.x, d0, L, 1.0, opt["eta_x"], skin, args.skin_g)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--skin", type=float, default=None,
+                    help="listing skin in D0_min (default 4; c5: 2048; --builds: 16)")
+    ap.add_argument("--skin-g", type=float, default=0.02)
+    ap.add_argument("--graph-iters", dest="graph_iters", type=int, default=None)
+    ap.add_argument("--fused-tail", dest="fused_tail", type=int, default=None)
+    ap.add_argument("--row-cost", dest="row_cost", type=int, default=None)
+    ap.add_argument("--item-work", dest="item_work", type=int, default=None)
+    ap.add_argument("--xcd-remap", dest="xcd_remap", type=int, default=None)
+    ap.add_argument("--variant", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--legs", default="c2,rsa,census",
+                    help="secondary legs run first in child processes (comma list of c2, rsa, "
+                         "census; empty for none)")
+    ap.add_argument("--leg", default=None, choices=sorted(LEGS), help=argparse.SUPPRESS)
+    ap.add_argument("--kernel-timing", type=int, default=2, choices=(0, 1, 2),
+                    help="HIP events around 0: no launch (no roofline entry), 1: the middle "
+                         "launch of every graph, 2: every launch")
+    ap.add_argument("--workload", default="c3", choices=("c3", "c5"),
+                    help="c3: the default line; c5: lognormal sigma_lnD=2.5, S=5e5, N=3e6 run "
+                         "to the stop criterion")
+    ap.add_argument("--builds", type=int, default=0, metavar="K",
+                    help="only time K neighbour-list builds of the RSA-start lognormal (or c5) "
+                         "workload after --warmup iterations and exit")
+    ap.add_argument("--copy-reference", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB three times "
+                         "(the known-size reference for hardware byte counters) and exit")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(packings shard across GPUs without communication; see the design "
+              "notes). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    legs = {}
+    if args.leg is None and args.copy_reference == 0 and args.builds == 0 and \
+            args.workload == "c3" and args.legs:
+        # before this process initialises the GPU
+        legs = run_legs([s for s in args.legs.split(",") if s])
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    if args.leg is not None:
+        print(json.dumps(LEGS[args.leg](torch, args)), flush=True)
+        return
+    if args.copy_reference > 0:
+        copy_reference(torch, args.copy_reference)
+        return
+    if args.builds > 0:
+        run_builds(torch, args)
+        return
+    if args.workload == "c5":
+        run_c5(torch, args)
+        return
+    out, cpu_state = run_primary(torch, args)
+    out.update(legs)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(d0, L, phi_now, args.skin, args.skin_g)
+        out["cpu_baseline"] = cpu_baseline(*cpu_state)
     print(json.dumps(out), flush=True)
 
 

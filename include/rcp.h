@@ -65,9 +65,9 @@ typedef struct rcp_ctx rcp_ctx;
 
 /* Optimiser and neighbour-list parameters.  size must be sizeof(rcp_params).
  *   beta1, beta2, eps_x, eps_k: Adam (Kingma and Ba) for positions and for
- *     kappa; eps_x <= 0 selects 1e-12 / (kappa0 * max D0), an explicit
- *     eps_x must be at least 1e-100 (RCP_EINVAL otherwise: the position
- *     update neglects sqrt(v) below 1e-100 next to it).
+ *     kappa (App. A), 0 <= beta < 1; eps_x <= 0 selects
+ *     1e-12 / (kappa0 * max D0), an explicit eps_x and eps_k must be
+ *     positive and finite.
  *   skin_s, skin_g: a pair is listed at scale kb when
  *       r^2 < c^2,  c = kb ((1 + g)(D0_i + D0_j)/2 + 2 s D0_min),
  *     and the list stays valid while
@@ -196,6 +196,8 @@ typedef struct {
     int64_t kernel_launches;    /* launches timed                                */
     int64_t kernel_nnz;         /* sum over timed launches of the listed
                                    partners (all packings) at that launch        */
+    int64_t levels;             /* cell-grid levels of the size classes (largest
+                                   over the packings)                            */
 } rcp_stats;
 
 int rcp_version(void);
@@ -248,7 +250,8 @@ int rcp_pack_init(int dim, const double *box, int64_t n, const double *d0,
                   const rcp_params *params, void *stream, rcp_ctx **out);
 
 /* Replace the launch tuning (see rcp_tuning); RCP_EINVAL for values out of
- * range.  A captured graph is re-captured at the next iteration. */
+ * range.  A captured graph is re-captured at the next iteration.  Tuning
+ * changes launch shapes only; the method (App. A) is unchanged. */
 int rcp_set_tuning(rcp_ctx *ctx, const rcp_tuning *t);
 
 /* Replace the listing skin (skin_s, skin_g of rcp_params) of every packing
@@ -259,23 +262,67 @@ int rcp_set_tuning(rcp_ctx *ctx, const rcp_tuning *t);
  * kappa would not be below L/2 (nothing is changed then). */
 int rcp_set_skin(rcp_ctx *ctx, double skin_s, double skin_g);
 
-/* Replace positions (row-major (n, 3), user order, wrapped into [0, L)) and
- * kappa of packing k; host or device pointer.  Resets the Adam moments and
- * the schedule position and marks the neighbour list stale. */
+/* Replace positions (row-major (n, 3), user order) and kappa of packing k
+ * (the state of the optimised energy, Eq. (energy) of App. A); x is a host
+ * pointer (is_device == 0, every value in [-L, 2L), wrapped into [0, L)) or
+ * a device pointer (is_device != 0, values already in [0, L)).  Resets the
+ * Adam moments and step counter (as after placement) and the schedule
+ * position, and marks the neighbour list stale.  RCP_EINVAL for a bad
+ * kappa or a host position outside [-L, 2L). */
 int rcp_set_state(rcp_ctx *ctx, int k, const double *x, double kappa,
                   int is_device);
 
 /* Copy positions (n, 3, user order), kappa and optionally the working
- * diameters kappa D0 (n) of packing k to host memory. */
+ * diameters kappa D0 (n) of packing k to host memory (App. A: the outputs
+ * of a run are the positions and the scaled diameters).  x, kappa and diam
+ * may each be NULL. */
 int rcp_get_state(rcp_ctx *ctx, int k, double *x, double *kappa, double *diam);
 
+/* Optimiser state of one packing beyond its positions and kappa: App. A
+ * applies Adam (Kingma and Ba, bias corrected) to every coordinate and to
+ * kappa with one step counter, and anneals mu through the rungs of a
+ * schedule.  size must be sizeof(rcp_optimizer). */
+typedef struct {
+    uint32_t size;
+    int32_t rung;          /* rung of the loaded schedule in force            */
+    int64_t t;             /* Adam step counter (0 = no step taken)           */
+    int64_t it_rung;       /* iterations taken in the current rung            */
+    int64_t iterations;    /* iterations of the current run                   */
+    double m_kappa, v_kappa;   /* first and second moments of kappa           */
+    double mu, eta_x, eta_k;   /* growth pressure and step sizes in force     */
+} rcp_optimizer;
+
+/* Copy the optimiser state of packing k: the first and second moments of
+ * every coordinate (m, v: (n, 3) row-major, user order, host; either may be
+ * NULL) and the scalars in *opt.  Together with rcp_get_state this is a
+ * complete checkpoint of a run in progress. */
+int rcp_get_optimizer(rcp_ctx *ctx, int k, double *m, double *v, rcp_optimizer *opt);
+
+/* Restore the optimiser state of packing k from a checkpoint (host arrays
+ * as rcp_get_optimizer writes them; m or v NULL leaves that array as it
+ * is).  To resume a run: rcp_set_state (positions, kappa), rcp_run_start
+ * (loads the schedule and resets the optimiser), rcp_set_optimizer, then
+ * rcp_run_continue.  The resumed trajectory equals the uninterrupted one up
+ * to the summation order of the gradient (the neighbour list is rebuilt at
+ * the resume point).  RCP_EINVAL for t < 0, a rung outside the loaded
+ * schedule, v < 0 or non-finite values. */
+int rcp_set_optimizer(rcp_ctx *ctx, int k, const double *m, const double *v,
+                      const rcp_optimizer *opt);
+
 /* Build the neighbour list of packing k at its current (x, kappa), with
- * kb = kappa.  n_pairs (may be NULL) receives the number of listed pairs
- * (each counted once). */
+ * kb = kappa (App. A keeps a neighbour structure that is rebuilt when the
+ * accumulated displacement demands it; the listing rule is that of
+ * rcp_params).  n_pairs (may be NULL) receives the number of listed pairs
+ * (each counted once).  RCP_EBOX if the largest listing cutoff is not below
+ * L/2; RCP_ENOMEM if the list would exceed 2^31 - 1 entries (both
+ * directions counted). */
 int rcp_neighbor_build(rcp_ctx *ctx, int k, int64_t *n_pairs);
 
-/* Canonical pair set of the current list of packing k: i < j in user
- * indices, lexicographic.  Writes min(count, cap) pairs and sets *count. */
+/* Canonical pair set of the current list of packing k: every pair (i, j)
+ * whose separation r (minimum image, Sec. 2) satisfies r^2 < c^2 with the
+ * listing cutoff c of rcp_params, as i < j in user indices, lexicographic.
+ * Writes min(count, cap) pairs to the host arrays i, j (NULL allowed with
+ * cap = 0) and sets *count.  RCP_ESTATE if no list has been built. */
 int rcp_get_pairs(rcp_ctx *ctx, int k, int32_t *i, int32_t *j, int64_t cap,
                   int64_t *count);
 
@@ -285,14 +332,22 @@ int rcp_get_pairs(rcp_ctx *ctx, int k, int32_t *i, int32_t *j, int64_t cap,
 int rcp_energy_grad(rcp_ctx *ctx, int k, double mu, rcp_energy *e,
                     double *grad_x);
 
-/* n_steps Adam updates of every packing with fixed mu, eta_x, eta_k
- * (absolute numbers), the neighbour list rebuilt whenever its validity
- * test fails.  Equivalent to rcp_inflate_run with a one-rung absolute
- * schedule of budget n_steps and no stop test. */
+/* n_steps Adam updates (App. A: Adam on every coordinate and on kappa,
+ * Kingma and Ba with bias correction) of every packing with fixed mu,
+ * eta_x, eta_k (absolute numbers), the neighbour list rebuilt whenever its
+ * validity test fails; no stop test.  The moments and the step counter
+ * carry over from the previous call (adam_step(a) then adam_step(b) is
+ * adam_step(a + b)); they start at zero after placement, rcp_set_state and
+ * rcp_run_start.  RCP_EINVAL for n_steps < 1, a non-finite mu or a negative
+ * step size; RCP_ENONFINITE if a gradient became NaN or Inf. */
 int rcp_adam_step(rcp_ctx *ctx, double mu, double eta_x, double eta_k,
                   int64_t n_steps);
 
-/* Run the schedule (sched[k] for packing k, or sched[0] for all when
+/* Inflation run of App. A: Adam on positions and kappa under the annealing
+ * schedule (rungs of Eq. (trigger) length), stop test in the final rung,
+ * then shrink to contact (Sec. 2).  Starts from the current positions and
+ * kappa with fresh optimiser moments.
+ * Run the schedule (sched[k] for packing k, or sched[0] for all when
  * per_packing == 0) until every packing has stopped, hit its cap, or
  * max_iters iterations were taken (0: no limit); then shrink each packing
  * to contact.  results has n_prob entries.  Returns 0, or RCP_ENOTCONV /
@@ -314,8 +369,11 @@ int rcp_run_start(rcp_ctx *ctx, const rcp_schedule *sched, int per_packing);
 int rcp_run_continue(rcp_ctx *ctx, int64_t n_iters, int32_t *active);
 int rcp_run_result(rcp_ctx *ctx, int k, rcp_result *result);
 
-/* Census entry point: rcp_inflate_run over every packing of a context made
- * by rcp_census_init, one launch per iteration for the whole batch. */
+/* Census entry point (Sec. 3 generates its census of packings one run at a
+ * time; here the runs of a batch share every launch): rcp_inflate_run over
+ * every packing of a context made by rcp_census_init, one launch per
+ * iteration for the whole batch.  Every packing's result is the one a
+ * context of its own would give. */
 int rcp_census_run(rcp_ctx *ctx, const rcp_schedule *sched, int per_packing,
                    int64_t max_iters, rcp_result *results);
 
@@ -331,9 +389,12 @@ int rcp_shrink(rcp_ctx *ctx, int k, double *kappa_shrunk, double *phi);
  * stream is the caller's hipStream_t and NULL means the null stream (not
  * the context's own): reads of x_dev and writes of the outputs are ordered
  * on it.  The list is rebuilt at (x_dev, kappa) if it is not valid there
- * (this synchronises the stream).  rcp_energy_dev writes E = E_overlap +
- * E_growth to E_dev[0] and max overlap to E_dev[1].  rcp_adjoint_dev writes
- * dE/dx (n, 3, user order) to gx_dev and dE/dkappa to gk_dev[0]. */
+ * (this synchronises the stream): packing 0 then takes x_dev and kappa as
+ * its state, exactly as rcp_set_state would (its optimiser state is reset),
+ * so a context used for evaluation should not also carry a run.
+ * rcp_energy_dev writes E = E_overlap + E_growth to E_dev[0] and max overlap
+ * to E_dev[1].  rcp_adjoint_dev writes dE/dx (n, 3, user order) to gx_dev
+ * and dE/dkappa to gk_dev[0]. */
 int rcp_energy_dev(rcp_ctx *ctx, const double *x_dev, double kappa, double mu,
                    double *E_dev, void *stream);
 int rcp_adjoint_dev(rcp_ctx *ctx, const double *x_dev, double kappa, double mu,
@@ -348,10 +409,17 @@ int rcp_adjoint_dev(rcp_ctx *ctx, const double *x_dev, double kappa, double mu,
 int rcp_time_iterations(rcp_ctx *ctx, int64_t n_iters, double *iterate_us, double *tail_us,
                         int64_t *done);
 
+/* Counters and timings accumulated by the context (see rcp_stats; the
+ * particle-update rate of App. A's iterations is particle_updates divided
+ * by the iteration time); rcp_reset_stats zeroes them. */
 int rcp_get_stats(rcp_ctx *ctx, rcp_stats *s);
 int rcp_reset_stats(rcp_ctx *ctx);
+/* Number of packings of a context, and spheres in packing k (-1 for a bad
+ * context or index). */
 int rcp_num_packings(rcp_ctx *ctx);
 int64_t rcp_num_particles(rcp_ctx *ctx, int k);
+/* Release every device and host buffer of the context (waits for its
+ * stream).  NULL is ignored. */
 void rcp_destroy(rcp_ctx *ctx);
 
 #ifdef __cplusplus

@@ -9,12 +9,13 @@ from .oracle import (build, lib, splitmix64, u01, pairs_brute, pairs_cells,
                      rows_pairs, energy_grad, rows_grad, shrink, phi, rsa,
                      run, Params, Schedule, n_trig, default_schedule,
                      time_iterations, set_threads, num_threads, RunState,
-                     default_params, absolute_schedule, Result)
+                     default_params, absolute_schedule, Result, set_list_check,
+                     list_misses)
 from . import oracle
 
 __all__ = [
     "build", "lib", "splitmix64", "u01", "pairs_brute", "pairs_cells",
     "rows_pairs", "energy_grad", "rows_grad", "shrink", "phi", "rsa", "run",
     "Params", "Schedule", "n_trig", "default_schedule", "time_iterations",
-    "set_threads", "num_threads", "RunState",
+    "set_threads", "num_threads", "RunState", "set_list_check", "list_misses",
 ]

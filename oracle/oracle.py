@@ -71,7 +71,11 @@ def lib():
         L.orc_time_iterations.restype = C.c_double
         L.orc_time_iterations.argtypes = [C.c_int64, dp, dp, C.c_double,
                                           C.c_double, C.c_double, C.c_double,
-                                          C.c_double, C.c_double, C.c_int64, lp]
+                                          C.c_double, C.c_double, C.c_int64, lp,
+                                          C.c_int]
+        L.orc_set_list_check.restype = None
+        L.orc_set_list_check.argtypes = [C.c_int, C.c_double]
+        L.orc_list_misses.restype = C.c_int64
         L.orc_num_threads.restype = C.c_int
         L.orc_set_threads.argtypes = [C.c_int]
         _lib = L
@@ -130,6 +134,17 @@ def splitmix64(seed, k):
 
 def u01(seed, i, attempt, axis):
     return lib().orc_u01(seed, i, attempt, axis)
+
+
+def set_list_check(on, trigger_scale=1.0):
+    """Debug mode of run(): count overlapping pairs missing from the list
+    before each gradient (n <= 4096); trigger_scale widens the rebuild
+    test's displacement allowance (1 = as stated)."""
+    lib().orc_set_list_check(1 if on else 0, float(trigger_scale))
+
+
+def list_misses():
+    return int(lib().orc_list_misses())
 
 
 def set_threads(n):
@@ -320,6 +335,11 @@ class RunState:
         self.ctl = np.array([0, 0, 0, 1], np.int64)
         self.etas = np.zeros(3)
 
+    def new_schedule(self):
+        """Start the next call of run() at rung 0 of its schedule while the
+        Adam moments and step counter carry over."""
+        self.ctl[1:] = (0, 0, 1)
+
 
 def default_params(d0, kappa0=1.0, s=0.1, g=0.02):
     P = Params()
@@ -343,11 +363,12 @@ def run(state, params, sched, max_iters=1 << 62, trace_cap=0):
     return st, res, (tr[:ntr] if trace_cap else None)
 
 
-def time_iterations(x, d0, L, kappa, eta_x, iters, s=0.1, g=0.02):
-    """Seconds for `iters` gradient + Adam evaluations on a fixed list."""
+def time_iterations(x, d0, L, kappa, eta_x, iters, s=0.1, g=0.02, threads=0):
+    """Seconds for `iters` gradient + Adam evaluations on a fixed list
+    (timed on `threads` threads, 0 = all)."""
     x = _pos(x).copy()
     d0 = _vec(d0)
     npairs = np.zeros(1, np.int64)
     t = lib().orc_time_iterations(d0.shape[0], _d(x), _d(d0), L, kappa, 0.0,
-                                  eta_x, s, g, iters, _l(npairs))
+                                  eta_x, s, g, iters, _l(npairs), int(threads))
     return t, int(npairs[0])

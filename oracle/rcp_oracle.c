@@ -629,6 +629,24 @@ static void full_rows(int64_t n, int64_t np, const int32_t *pi, const int32_t *p
     *col_out = col;
 }
 
+/* Debug mode of the run: before every gradient evaluation, test by brute
+ * force (n <= 4096) that every overlapping pair (r < d at the current kappa)
+ * is in the current list, and count the pairs that are not.  The
+ * displacement allowance of the rebuild test can be scaled (1 = the rule
+ * as stated; a larger factor plants a mistake the check must catch). */
+static int g_list_check = 0;
+static int64_t g_list_misses = 0;
+static double g_trigger_scale = 1.0;
+
+void orc_set_list_check(int on, double trigger_scale)
+{
+    g_list_check = on;
+    g_list_misses = 0;
+    g_trigger_scale = trigger_scale > 0 ? trigger_scale : 1.0;
+}
+
+int64_t orc_list_misses(void) { return g_list_misses; }
+
 typedef struct {
     int64_t n;
     double L, hL, d0min, sumd0;
@@ -665,6 +683,26 @@ static void run_rebuild(run_t *R, double kappa, const orc_params *P)
     memcpy(R->xref, R->x, sizeof(double) * 3 * (size_t)R->n);
     R->kb = kappa;
     R->rebuilds++;
+}
+
+/* Debug check (see orc_set_list_check): every pair with r < d at kappa
+ * must be one of the listed pairs. */
+static void list_check(const run_t *R, double kappa)
+{
+    const int64_t n = R->n;
+    unsigned char *in = calloc((size_t)(n * n), 1);
+    for (int64_t p = 0; p < R->np; ++p) {
+        in[(int64_t)R->pi[p] * n + R->pj[p]] = 1;
+        in[(int64_t)R->pj[p] * n + R->pi[p]] = 1;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = i + 1; j < n; ++j) {
+            double dx, dy, dz;
+            double r2 = sep2(R->x, i, j, R->L, R->hL, &dx, &dy, &dz);
+            double d = kappa * (0.5 * (R->d0[i] + R->d0[j]));
+            if (r2 < d * d && !in[i * n + j]) ++g_list_misses;
+        }
+    free(in);
 }
 
 /* Gradient over full rows (parallel over rows, each row summed in list
@@ -799,6 +837,7 @@ int orc_run(int64_t n, double *x, const double *d0, double L, double *kappa,
     int64_t it;
     for (it = 0; it < max_iters; ++it) {
         if (need_build) run_rebuild(&R, *kappa, P);
+        if (g_list_check && n <= 4096) list_check(&R, *kappa);
         run_grad(&R, *kappa, &Eov, &Sdrd, &maxd);
         if (trace && it < trace_cap) {
             trace[3 * it] = maxd; trace[3 * it + 1] = *kappa; trace[3 * it + 2] = Eov;
@@ -827,7 +866,7 @@ int orc_run(int64_t n, double *x, const double *d0, double L, double *kappa,
             rung_start(S, r, *kappa, nvol, R.sumd0, R.d0min, &mu, &ex, &ek);
         }
         /* list validity for the next iteration */
-        double lim = P->skin_s * R.kb * R.d0min;
+        double lim = g_trigger_scale * (P->skin_s * R.kb * R.d0min);
         double md2 = 0.0;
         for (int64_t i = 0; i < n; ++i) {
             double dx = mimg(x[3 * i] - R.xref[3 * i], L, R.hL);
@@ -865,10 +904,12 @@ int orc_run(int64_t n, double *x, const double *d0, double L, double *kappa,
 }
 
 /* Timing helper for the CPU baseline: `iters` evaluations of gradient +
- * Adam on a fixed list (no schedule logic, no rebuilds), in place. */
+ * Adam on a fixed list (no schedule logic, no rebuilds), in place.  The
+ * list is built with every thread; the timed loop runs on `threads`
+ * threads (0: every thread). */
 double orc_time_iterations(int64_t n, double *x, const double *d0, double L,
                            double kappa, double mu, double eta_x, double s,
-                           double g, int64_t iters, int64_t *np_out)
+                           double g, int64_t iters, int64_t *np_out, int threads)
 {
     run_t R;
     memset(&R, 0, sizeof R);
@@ -885,8 +926,11 @@ double orc_time_iterations(int64_t n, double *x, const double *d0, double L,
     double b1t = 1.0, b2t = 1.0, Eov, Sdrd, maxd;
     double t0;
 #ifdef _OPENMP
+    const int all = omp_get_max_threads();
+    if (threads > 0) omp_set_num_threads(threads);
     t0 = omp_get_wtime();
 #else
+    (void)threads;
     t0 = 0;
 #endif
     for (int64_t it = 0; it < iters; ++it) {
@@ -905,6 +949,7 @@ double orc_time_iterations(int64_t n, double *x, const double *d0, double L,
     double t1;
 #ifdef _OPENMP
     t1 = omp_get_wtime();
+    omp_set_num_threads(all);
 #else
     t1 = 0;
 #endif

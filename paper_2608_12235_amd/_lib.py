@@ -57,13 +57,20 @@ class Result(C.Structure):
                 ("status", C.c_int32), ("rung", C.c_int32)]
 
 
+class Optimizer(C.Structure):
+    _fields_ = [("size", C.c_uint32), ("rung", C.c_int32), ("t", C.c_int64),
+                ("it_rung", C.c_int64), ("iterations", C.c_int64), ("m_kappa", C.c_double),
+                ("v_kappa", C.c_double), ("mu", C.c_double), ("eta_x", C.c_double),
+                ("eta_k", C.c_double)]
+
+
 class Stats(C.Structure):
     _fields_ = [("iterations", C.c_int64), ("particle_updates", C.c_int64),
                 ("rebuilds", C.c_int64), ("graph_launches", C.c_int64),
                 ("nnz", C.c_int64), ("max_degree", C.c_int64), ("iterate_ms", C.c_double),
                 ("rebuild_ms", C.c_double), ("shrink_ms", C.c_double), ("kernel_ms", C.c_double),
                 ("tail_kernel_ms", C.c_double), ("kernel_launches", C.c_int64),
-                ("kernel_nnz", C.c_int64)]
+                ("kernel_nnz", C.c_int64), ("levels", C.c_int64)]
 
 
 _lib = None
@@ -90,6 +97,8 @@ SIGNATURES = {
     "rcp_set_skin": (C.c_int, [vp, C.c_double, C.c_double]),
     "rcp_set_state": (C.c_int, [vp, C.c_int, vp, C.c_double, C.c_int]),
     "rcp_get_state": (C.c_int, [vp, C.c_int, dp, dp, dp]),
+    "rcp_get_optimizer": (C.c_int, [vp, C.c_int, dp, dp, C.POINTER(Optimizer)]),
+    "rcp_set_optimizer": (C.c_int, [vp, C.c_int, dp, dp, C.POINTER(Optimizer)]),
     "rcp_neighbor_build": (C.c_int, [vp, C.c_int, i64p]),
     "rcp_get_pairs": (C.c_int, [vp, C.c_int, i32p, i32p, C.c_int64, i64p]),
     "rcp_energy_grad": (C.c_int, [vp, C.c_int, C.c_double, C.POINTER(Energy), dp]),

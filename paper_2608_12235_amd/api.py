@@ -3,7 +3,7 @@ import ctypes as C
 
 import numpy as np
 
-from ._lib import (lib, check, Params, Tuning, Schedule, Energy, Result, Stats,
+from ._lib import (lib, check, Params, Tuning, Schedule, Energy, Result, Stats, Optimizer,
                    RCP_INIT_NONE, RCP_INIT_RSA, RCP_INIT_UNIFORM, RcpError)
 
 _INIT = {"none": RCP_INIT_NONE, "rsa": RCP_INIT_RSA, "uniform": RCP_INIT_UNIFORM}
@@ -130,6 +130,28 @@ class Packing:
         check(lib().rcp_get_state(self._h, k, _dp(x), C.byref(kap),
                                   _dp(dm) if diameters else None))
         return (x, kap.value, dm) if diameters else (x, kap.value)
+
+    def get_optimizer(self, k=0, moments=True):
+        """Optimiser state of packing k: (m, v, dict of scalars); m and v are
+        (n, 3) arrays in user order (None when moments is False)."""
+        o = Optimizer()
+        o.size = C.sizeof(Optimizer)
+        m = np.empty((self.n[k], 3)) if moments else None
+        v = np.empty((self.n[k], 3)) if moments else None
+        check(lib().rcp_get_optimizer(self._h, k, _dp(m) if moments else None,
+                                      _dp(v) if moments else None, C.byref(o)))
+        return m, v, {f: getattr(o, f) for f, _ in Optimizer._fields_ if f != "size"}
+
+    def set_optimizer(self, opt, m=None, v=None, k=0):
+        """Restore the optimiser state of packing k (see get_optimizer)."""
+        o = Optimizer()
+        o.size = C.sizeof(Optimizer)
+        for f, val in opt.items():
+            setattr(o, f, val)
+        mm = None if m is None else np.ascontiguousarray(m, np.float64).reshape(self.n[k], 3)
+        vv = None if v is None else np.ascontiguousarray(v, np.float64).reshape(self.n[k], 3)
+        check(lib().rcp_set_optimizer(self._h, k, _dp(mm) if mm is not None else None,
+                                      _dp(vv) if vv is not None else None, C.byref(o)))
 
     def neighbor_build(self, k=0):
         npairs = C.c_int64()

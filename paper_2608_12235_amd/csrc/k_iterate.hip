@@ -117,9 +117,10 @@ __device__ __forceinline__ double adam_coord(double th, double g, double &m, dou
     m = b1 * m + (1.0 - b1) * g;
     v = b2 * v + (1.0 - b2) * (g * g);
     const double mh = m * ib1, vh = v * ib2;
-    // sqrt(vh) as vh / sqrt(vh); below 1e-200 the root is negligible next
-    // to eps (>= 1e-100 is required) and is taken as vh * 1e100 (0 at 0)
-    const double sv = vh * fast_rsq(fmax(vh, 1e-200));
+    // sqrt(vh) as vh / sqrt(vh); below 1e-200 (where the estimate loses
+    // range, a rarely taken branch) the IEEE root
+    double sv = vh * fast_rsq(fmax(vh, 1e-200));
+    if (vh < 1e-200) sv = sqrt(vh);
     double t = th - (eta * mh) * fast_rcp(sv + eps);
     if (t < 0.0) t += L;
     if (t >= L) t -= L;
@@ -1189,6 +1190,36 @@ __global__ __launch_bounds__(kBlock) void k_set_positions(const SegPtrs *__restr
     q.y = xu[3 * u + 1];
     q.z = xu[3 * u + 2];
     Q[i] = q;
+}
+
+// Adam moments of packing seg between list order and user order (mu, vu:
+// n x 3 row-major): dir 0 copies the list's moments out, dir 1 in.
+__global__ __launch_bounds__(kBlock) void k_moments_io(const SegPtrs *__restrict__ P, int seg,
+                                                      int64_t n, double *__restrict__ mu,
+                                                      double *__restrict__ vu, int dir)
+{
+    const SegPtrs &p = P[seg];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int64_t u = p.orig[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (dir == 0) {
+            mu[3 * u + a] = p.m[a][i];
+            vu[3 * u + a] = p.v[a][i];
+        } else {
+            p.m[a][i] = mu[3 * u + a];
+            p.v[a][i] = vu[3 * u + a];
+        }
+    }
+}
+
+void launch_moments_io(const SegPtrs *P, int seg, int64_t n, double *mu, double *vu, int dir,
+                       hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_moments_io, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       st, P, seg, n, mu, vu, dir);
 }
 
 void launch_set_positions(const SegPtrs *P, SegState *S, int seg, int64_t n, const double *xu,

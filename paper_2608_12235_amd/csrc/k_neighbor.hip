@@ -225,12 +225,12 @@ __device__ __forceinline__ int remap_xcd(int b, int G)
 }
 
 __global__ __launch_bounds__(kBlock) void k_search(BuildArgs a, uint64_t *__restrict__ list,
-                                                  uint32_t *__restrict__ counter, int64_t cap,
+                                                  unsigned long long *__restrict__ counter, int64_t cap,
                                                   int row_bits, int xcd_remap)
 {
     __shared__ uint64_t buf[kSearchBuf];
     __shared__ uint32_t nbuf;
-    __shared__ uint32_t gbase;
+    __shared__ unsigned long long gbase;
     if (threadIdx.x == 0) nbuf = 0;
     __syncthreads();
     const int blk = xcd_remap ? remap_xcd((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(kBlock) void k_search(BuildArgs a, uint64_t *__rest
                                     buf[k] = e0;
                                     buf[k + 1] = e1;
                                 } else {
-                                    const uint32_t gi = atomicAdd(counter, 2u);
+                                    const unsigned long long gi = atomicAdd(counter, 2ull);
                                     if ((int64_t)gi + 1 < cap) {
                                         list[gi] = e0;
                                         list[gi + 1] = e1;
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(kBlock) void k_search(BuildArgs a, uint64_t *__rest
     }
     __syncthreads();
     const uint32_t mm = nbuf < (uint32_t)kSearchBuf ? nbuf : (uint32_t)kSearchBuf;
-    if (threadIdx.x == 0) gbase = mm ? atomicAdd(counter, mm) : 0u;
+    if (threadIdx.x == 0) gbase = mm ? atomicAdd(counter, (unsigned long long)mm) : 0ull;
     __syncthreads();
     for (uint32_t k = threadIdx.x; k < mm; k += kBlock)
         if ((int64_t)gbase + k < cap) list[gbase + k] = buf[k];
@@ -613,7 +613,7 @@ struct SearchOut {
     int32_t *mark;      // LDS, this wave's 64 owner marks
     uint64_t *wbuf;     // LDS, this wave's kWaveBuf staged entries
     uint64_t *list;
-    uint32_t *counter;
+    unsigned long long *counter;
     int64_t cap;
     int row_bits;
 };
@@ -621,9 +621,11 @@ struct SearchOut {
 // Copy the wave's n staged entries to the list (called by the whole wave).
 __device__ __forceinline__ void flush_wave(const SearchOut &out, int lane, uint32_t n)
 {
-    uint32_t g = 0;
-    if (lane == 0) g = atomicAdd(out.counter, n);
-    g = (uint32_t)__builtin_amdgcn_readfirstlane((int)g);
+    unsigned long long g = 0;
+    if (lane == 0) g = atomicAdd(out.counter, (unsigned long long)n);
+    g = (unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)g) |
+        ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(g >> 32))
+         << 32);
     for (uint32_t k = (uint32_t)lane; k < n; k += kWave)
         if ((int64_t)g + k < out.cap) gstore(out.list, (int64_t)g + k, out.wbuf[k]);
     __builtin_amdgcn_wave_barrier();
@@ -757,7 +759,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     __shared__ int32_t mark[kBlock];
     __shared__ uint64_t wbuf[kWavesPerBlock * kWaveBuf];
     __shared__ uint32_t wcount[kWavesPerBlock];
-    __shared__ uint32_t bbase;
+    __shared__ unsigned long long bbase;
     const int64_t gb =
         b_base + (xcd_remap ? remap_xcd((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x);
     const FrontJob &F = jobs[job_of(jobs, J, gb, &FrontJob::b0)];
@@ -826,16 +828,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     if (threadIdx.x == 0) {
         uint32_t tot = 0;
         for (int k = 0; k < kWavesPerBlock; ++k) tot += wcount[k];
-        bbase = tot ? atomicAdd(F.counter, tot) : 0u;
+        bbase = tot ? atomicAdd(F.counter, (unsigned long long)tot) : 0ull;
     }
     __syncthreads();
-    uint32_t g = bbase;
+    unsigned long long g = bbase;
     for (int k = 0; k < w; ++k) g += wcount[k];
     for (uint32_t k = (uint32_t)lane; k < wn; k += kWave)
         if ((int64_t)g + k < F.lcap) gstore(F.list, (int64_t)g + k, out.wbuf[k]);
 }
 
-void launch_search(const BuildArgs &a, uint64_t *list, uint32_t *counter, int64_t cap,
+void launch_search(const BuildArgs &a, uint64_t *list, unsigned long long *counter, int64_t cap,
                    int row_bits, int xcd_remap, hipStream_t s)
 {
     if (a.n <= 0) return;
@@ -890,7 +892,7 @@ __global__ __launch_bounds__(kBlock) void k_tables_clear_seg(const FrontJob *__r
     const int64_t i = ((int64_t)blockIdx.x - F.bt0) * kBlock + threadIdx.x;
     if (i < F.hcap) F.a.hash[i].key = kEmptyKey;
     if (i < F.nd2) reinterpret_cast<uint32_t *>(F.a.dense)[i] = 0u;
-    if (i == 0) *F.counter = 0u;
+    if (i == 0) *F.counter = 0ull;
 }
 
 __global__ __launch_bounds__(kBlock) void k_cells_seg(const FrontJob *__restrict__ jobs, int J)

@@ -76,7 +76,8 @@ struct FrontJob {
     const uint8_t *lev0;
     uint64_t *keys;         // Morton keys out
     uint32_t *vals;         // local indices out
-    uint32_t *counter;      // search entry count, zeroed with the tables
+    unsigned long long *counter;   // search entry count (64-bit, so it cannot wrap),
+                                   // zeroed with the tables
     uint64_t *list;         // search output: the list region and its capacity
     int64_t lcap;
     int32_t row_bits, pad;
@@ -116,7 +117,7 @@ void launch_after_seg(const BackJob *jobs, int J, SegState *S, SegPtrs *P, hipSt
 // to `list` as (row << row_bits) | col, rows and cols in sorted order, in an
 // arbitrary order; *counter (zeroed by the caller) receives the number of
 // entries, which may exceed cap (then only cap were stored).
-void launch_search(const BuildArgs &a, uint64_t *list, uint32_t *counter, int64_t cap,
+void launch_search(const BuildArgs &a, uint64_t *list, unsigned long long *counter, int64_t cap,
                    int row_bits, int xcd_remap, hipStream_t s);
 // The same, wave-cooperative (the same pairs, another append order), for
 // jobs[0..J) (their list, lcap, row_bits and counter fields say where) over
@@ -161,6 +162,10 @@ void launch_eval_finish(const double *part, int nblocks, double kappa, double mu
 // Max displacement^2 of xu (user order, n x 3) against the list's xref.
 void launch_disp(const SegPtrs *P, const SegState *S, int seg, int64_t n, const double *xu,
                  double *part, int nblocks, hipStream_t s);
+// Adam moments of segment seg to (dir 0) or from (dir 1) user-order arrays
+// mu, vu (n x 3 row-major, device).
+void launch_moments_io(const SegPtrs *P, int seg, int64_t n, double *mu, double *vu, int dir,
+                       hipStream_t s);
 // Gather user-order positions xu (n x 3) into the current SoA buffer.
 void launch_set_positions(const SegPtrs *P, SegState *S, int seg, int64_t n, const double *xu,
                           int cur, hipStream_t s);

@@ -163,9 +163,9 @@ struct rcp_ctx {
     FrontJob *d_fj = nullptr, *h_fj = nullptr;   // batch job tables (device, pinned host)
     BackJob *d_bj = nullptr, *h_bj = nullptr;
     int64_t fj_cap = 0, bj_cap = 0, hj_cap = 0;
-    uint32_t *bcount = nullptr;      // their entry counts (device, pinned host)
+    unsigned long long *bcount = nullptr;   // their entry counts (device, pinned host)
     int64_t bcount_cap = 0;
-    uint32_t *h_bcount = nullptr;
+    unsigned long long *h_bcount = nullptr;
     int64_t h_bcount_cap = 0;
     double *part = nullptr;          // evaluation partials
     int64_t part_cap = 0;
@@ -467,7 +467,8 @@ static int build_grow(rcp_ctx *c, std::vector<BuildJob> &jobs, int nl)
         c->h_bcount = nullptr;
         c->h_bcount_cap = 0;
         const int64_t cap = std::max<int64_t>(64, 2 * J);
-        const hipError_t e = hipHostMalloc((void **)&c->h_bcount, sizeof(uint32_t) * cap, 0);
+        const hipError_t e =
+            hipHostMalloc((void **)&c->h_bcount, sizeof(unsigned long long) * cap, 0);
         if (e != hipSuccess) return fail(RCP_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
         c->h_bcount_cap = cap;
     }
@@ -679,6 +680,18 @@ static int build_backs(rcp_ctx *c, std::vector<BuildJob> &jobs, const std::vecto
     return RCP_OK;
 }
 
+// A list of m entries (each pair twice) is addressed with 32-bit row
+// pointers and partner indices: longer lists are refused.
+static int check_list_size(int k, int64_t m)
+{
+    if (m > (int64_t)INT32_MAX)
+        return fail(RCP_ENOMEM,
+                    "packing %d: neighbour list of %lld entries exceeds 2^31 - 1 (reduce the "
+                    "listing skin)",
+                    k, (long long)m);
+    return RCP_OK;
+}
+
 // Build the lists of packings ks[i] at kb = kappas[i], sharing one host
 // round trip.  rcs[i] receives each packing's status (RCP_EBOX leaves that
 // packing untouched); the return value is the first error that is not a
@@ -720,7 +733,7 @@ static int rebuild_batch(rcp_ctx *c, const std::vector<int> &ks, const std::vect
     HIPCHK(hipEventRecord(ev.first, c->stream));
     CHK(build_fronts(c, jobs, nl));
     CHK(join_lanes(c, nl));
-    HIPCHK(hipMemcpyAsync(c->h_bcount, c->bcount, sizeof(uint32_t) * jobs.size(),
+    HIPCHK(hipMemcpyAsync(c->h_bcount, c->bcount, sizeof(unsigned long long) * jobs.size(),
                           hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     HIPCHK(hipGetLastError());
@@ -729,6 +742,8 @@ static int rebuild_batch(rcp_ctx *c, const std::vector<int> &ks, const std::vect
     std::vector<int> ok, redo;
     for (size_t q = 0; q < jobs.size(); ++q) {
         ms[q] = (int64_t)c->h_bcount[q];
+        // row pointers, partner indices and work-item offsets are 32-bit
+        CHK(check_list_size(jobs[q].k, ms[q]));
         if (ms[q] > jobs[q].lcap) {
             redo.push_back((int)q);
             continue;
@@ -753,10 +768,11 @@ static int rebuild_batch(rcp_ctx *c, const std::vector<int> &ks, const std::vect
         HIPCHK(hipStreamSynchronize(c->stream));
         CHK(build_grow(c, one, 1));
         CHK(build_fronts(c, one, 1));
-        HIPCHK(hipMemcpyAsync(c->h_bcount, c->bcount, sizeof(uint32_t), hipMemcpyDeviceToHost,
-                              c->stream));
+        HIPCHK(hipMemcpyAsync(c->h_bcount, c->bcount, sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
         std::vector<int64_t> m1(1, (int64_t)c->h_bcount[0]);
+        CHK(check_list_size(jobs[q].k, m1[0]));
         if (m1[0] > one[0].lcap) return fail(RCP_ENOMEM, "pair list overflow after regrowth");
         Seg &s = c->segs[jobs[q].k];
         if (m1[0] > s.col_cap) {
@@ -1325,7 +1341,8 @@ int rcp_census_init(int dim, int n_prob, const int64_t *n, const double *const *
     if (params) P = *params;
     else rcp_params_default(&P);
     if (!(P.beta1 >= 0 && P.beta1 < 1) || !(P.beta2 >= 0 && P.beta2 < 1) || !(P.skin_s >= 0) ||
-        !(P.skin_g >= 0) || !(P.eps_k > 0) || (P.eps_x > 0 && !(P.eps_x >= 1e-100)))
+        !(P.skin_g >= 0) || !(P.eps_k > 0) || !std::isfinite(P.eps_k) ||
+        !std::isfinite(P.eps_x) || !std::isfinite(P.skin_s) || !std::isfinite(P.skin_g))
         return fail(RCP_EINVAL, "bad rcp_params values");
     for (int k = 0; k < n_prob; ++k) CHK(validate_seg(n[k], d0[k], box[k], kappa0[k]));
     if (init_mode < RCP_INIT_NONE || init_mode > RCP_INIT_UNIFORM)
@@ -1498,6 +1515,96 @@ int rcp_get_state(rcp_ctx *c, int k, double *x, double *kappa, double *diam)
     return RCP_OK;
 }
 
+int rcp_get_optimizer(rcp_ctx *c, int k, double *m, double *v, rcp_optimizer *o)
+{
+    CHK(check_k(c, k));
+    if (!o || o->size != sizeof(rcp_optimizer)) return fail(RCP_EINVAL, "rcp_optimizer: bad size");
+    CHK(pull_state(c));
+    const SegState &st = c->h_state[k];
+    o->rung = st.rung;
+    o->t = st.t;
+    o->it_rung = st.it_rung;
+    o->iterations = st.iters;
+    o->m_kappa = st.mk;
+    o->v_kappa = st.vk;
+    o->mu = st.mu;
+    o->eta_x = st.eta_x;
+    o->eta_k = st.eta_k;
+    if (m || v) {
+        const Seg &s = c->segs[k];
+        CHK(dgrow(&c->xtmp, &c->xtmp_cap, 6 * s.n));
+        launch_moments_io(c->d_ptrs, k, s.n, c->xtmp, c->xtmp + 3 * s.n, 0, c->stream);
+        HIPCHK(hipGetLastError());
+        if (m)
+            HIPCHK(hipMemcpyAsync(m, c->xtmp, sizeof(double) * 3 * s.n, hipMemcpyDeviceToHost,
+                                  c->stream));
+        if (v)
+            HIPCHK(hipMemcpyAsync(v, c->xtmp + 3 * s.n, sizeof(double) * 3 * s.n,
+                                  hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+    }
+    return RCP_OK;
+}
+
+int rcp_set_optimizer(rcp_ctx *c, int k, const double *m, const double *v,
+                      const rcp_optimizer *o)
+{
+    CHK(check_k(c, k));
+    if (!o || o->size != sizeof(rcp_optimizer)) return fail(RCP_EINVAL, "rcp_optimizer: bad size");
+    CHK(pull_state(c));
+    const int nr = c->h_state[k].sched.n_rungs;
+    if (o->t < 0 || o->it_rung < 0 || o->iterations < 0 || o->rung < 0 ||
+        (nr > 0 ? o->rung >= nr : o->rung != 0))
+        return fail(RCP_EINVAL, "rcp_optimizer: step counter or schedule position out of range");
+    if (!std::isfinite(o->m_kappa) || !(o->v_kappa >= 0) || !std::isfinite(o->v_kappa) ||
+        !std::isfinite(o->mu) || !(o->eta_x >= 0) || !std::isfinite(o->eta_x) ||
+        !(o->eta_k >= 0) || !std::isfinite(o->eta_k))
+        return fail(RCP_EINVAL, "rcp_optimizer: bad value");
+    const Seg &s = c->segs[k];
+    const int64_t n3 = 3 * s.n;
+    for (int64_t q = 0; m && q < n3; ++q)
+        if (!std::isfinite(m[q])) return fail(RCP_EINVAL, "first moment %lld is not finite", (long long)q);
+    for (int64_t q = 0; v && q < n3; ++q)
+        if (!(v[q] >= 0) || !std::isfinite(v[q]))
+            return fail(RCP_EINVAL, "second moment %lld is negative or not finite", (long long)q);
+    SegState st = c->h_state[k];
+    st.t = o->t;
+    // beta powers as repeated products, as the iteration forms them
+    st.b1t = 1.0;
+    st.b2t = 1.0;
+    for (int64_t q = 0; q < o->t; ++q) {
+        st.b1t *= st.beta1;
+        st.b2t *= st.beta2;
+    }
+    seg_bias_terms(st);
+    st.mk = o->m_kappa;
+    st.vk = o->v_kappa;
+    st.rung = o->rung;
+    st.it_rung = o->it_rung;
+    st.iters = o->iterations;
+    st.mu = o->mu;
+    st.eta_x = o->eta_x;
+    st.eta_k = o->eta_k;
+    if (m || v) {
+        CHK(dgrow(&c->xtmp, &c->xtmp_cap, 6 * s.n));
+        if (!m || !v) {   // keep the array not given
+            launch_moments_io(c->d_ptrs, k, s.n, c->xtmp, c->xtmp + n3, 0, c->stream);
+            HIPCHK(hipGetLastError());
+        }
+        if (m)
+            HIPCHK(hipMemcpyAsync(c->xtmp, m, sizeof(double) * n3, hipMemcpyHostToDevice, c->stream));
+        if (v)
+            HIPCHK(hipMemcpyAsync(c->xtmp + n3, v, sizeof(double) * n3, hipMemcpyHostToDevice,
+                                  c->stream));
+        launch_moments_io(c->d_ptrs, k, s.n, c->xtmp, c->xtmp + n3, 1, c->stream);
+        HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipMemcpyAsync(c->d_state + k, &st, sizeof st, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->h_state[k] = st;
+    return RCP_OK;
+}
+
 int rcp_neighbor_build(rcp_ctx *c, int k, int64_t *n_pairs)
 {
     CHK(check_k(c, k));
@@ -1580,16 +1687,18 @@ int rcp_energy_grad(rcp_ctx *c, int k, double mu, rcp_energy *e, double *grad_x)
     return RCP_OK;
 }
 
+// Load a schedule on every packing and set its first rung; with
+// reset_adam the optimiser starts afresh (moments and step counter zero).
 static int start_schedule(rcp_ctx *c, const rcp_schedule *sched, int per_packing,
-                          int64_t max_iters)
+                          int64_t max_iters, bool reset_adam = true)
 {
     CHK(pull_state(c));
+    std::vector<SchedDev> qs(c->segs.size());
+    for (size_t k = 0; k < c->segs.size(); ++k) CHK(to_sched(per_packing ? sched + k : sched, qs[k]));
     for (size_t k = 0; k < c->segs.size(); ++k) {
-        SchedDev q;
-        CHK(to_sched(per_packing ? sched + k : sched, q));
-        CHK(reset_moments(c, (int)k));
+        if (reset_adam) CHK(reset_moments(c, (int)k));
         c->segs[k].err = 0;
-        launch_sched_start(c->d_state, (int)k, q, 1, max_iters, c->stream);
+        launch_sched_start(c->d_state, (int)k, qs[k], reset_adam ? 1 : 0, max_iters, c->stream);
     }
     HIPCHK(hipStreamSynchronize(c->stream));
     return RCP_OK;
@@ -1611,7 +1720,8 @@ int rcp_adam_step(rcp_ctx *c, double mu, double eta_x, double eta_k, int64_t n_s
     q.eta_k[0] = eta_k;
     q.decay[0] = 1.0;
     q.budget[0] = n_steps;
-    CHK(start_schedule(c, &q, 0, 0));
+    // the optimiser state carries over from the previous call
+    CHK(start_schedule(c, &q, 0, 0, false));
     CHK(run_loop(c));
     CHK(pull_state(c));
     for (size_t k = 0; k < c->segs.size(); ++k)
@@ -1877,8 +1987,10 @@ int rcp_get_stats(rcp_ctx *c, rcp_stats *s)
     *s = c->stats;
     s->nnz = 0;
     s->max_degree = 0;
+    s->levels = 0;
     for (auto &g : c->segs) {
         s->nnz += g.nnz;
+        s->levels = std::max<int64_t>(s->levels, g.nlev);
         if (!g.built || g.n <= 0) continue;
         // longest row of the current list, computed on request
         launch_fill_u32(c->totals + 1, 1, 0u, c->stream);

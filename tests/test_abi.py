@@ -39,7 +39,8 @@ def test_struct_sizes_match_header_layout(L):
     assert C.sizeof(L.Tuning) == 8 * 4
     assert C.sizeof(L.Schedule) == 16 + 8 + 5 * 16 * 8
     assert C.sizeof(L.Result) == 5 * 8 + 2 * 8 + 2 * 4
-    assert C.sizeof(L.Stats) == 6 * 8 + 3 * 8 + 2 * 8 + 2 * 8
+    assert C.sizeof(L.Stats) == 6 * 8 + 3 * 8 + 2 * 8 + 3 * 8
+    assert C.sizeof(L.Optimizer) == 8 + 3 * 8 + 5 * 8
 
 
 def test_version_and_defaults(L):
@@ -83,13 +84,15 @@ def test_invalid_arguments_rejected_without_device(L):
     assert lib.rcp_pack_init(3, box, 3, dp, 1.0, 0, 9, None, None, C.byref(h)) == L.RCP_EINVAL
     s = L.Schedule()
     assert lib.rcp_schedule_default(0, 3, 1.0, 2, 9, 5000, C.byref(s)) == L.RCP_EINVAL
-    # an explicit eps_x below 1e-100 is refused (the position update neglects
-    # sqrt(v) below 1e-100 next to eps_x)
-    pr = L.Params()
-    lib.rcp_params_default(C.byref(pr))
-    pr.eps_x = 1e-120
-    assert lib.rcp_pack_init(3, box, 3, dp, 1.0, 0, 1, C.byref(pr), None, C.byref(h)) == L.RCP_EINVAL
-    assert b"rcp_params" in lib.rcp_last_error()
+    # non-finite Adam constants and a kappa epsilon <= 0 are refused
+    for field, bad in (("eps_x", float("inf")), ("eps_k", 0.0), ("eps_k", float("nan")),
+                       ("beta1", 1.0), ("skin_s", -1.0), ("skin_g", float("inf"))):
+        pr = L.Params()
+        lib.rcp_params_default(C.byref(pr))
+        setattr(pr, field, bad)
+        assert lib.rcp_pack_init(3, box, 3, dp, 1.0, 0, 1, C.byref(pr), None,
+                                 C.byref(h)) == L.RCP_EINVAL, field
+        assert b"rcp_params" in lib.rcp_last_error()
 
 
 def test_tuning_defaults(L):

@@ -17,13 +17,30 @@ def test_more_than_one_gpu_is_refused():
     assert r.stdout == ""
 
 
-def test_traffic_counters_match_kernel_sources():
+def test_traffic_counters_only_for_their_kernel_and_workload(tmp_path, monkeypatch):
+    # the committed HBM byte counters are used only while the kernel sources
+    # hash to the value they were taken on and for the workload they were
+    # taken on; otherwise traffic is null
     sys.path.insert(0, ROOT)
     import bench
+    t = {"kernel": "k_iterate", "workload": "w", "source_sha256": bench.kernel_source_hash(),
+         "fetch_kib_per_launch": 100.0, "write_kib_per_launch": 50.0, "fetch_scale": 2.0,
+         "write_scale": 1.0, "summary": "profiles/x.md"}
+    f = tmp_path / "t.json"
+    f.write_text(json.dumps(t))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    b, _ = bench.counter_traffic("w")
+    assert b == (100.0 * 2.0 + 50.0 * 1.0) * 1024.0
+    assert bench.counter_traffic("other")[0] is None
+    t["source_sha256"] = "0" * 64
+    f.write_text(json.dumps(t))
+    assert bench.counter_traffic("w")[0] is None
+
+
+def test_committed_counter_summary_exists():
     with open(os.path.join(ROOT, "profiles", "k_iterate_traffic.json")) as fh:
         t = json.load(fh)
-    assert t["source_sha256"] == bench.kernel_source_hash()
-    b, _ = bench.counter_traffic()
-    assert b == (t["fetch_kib_per_launch"] * t["fetch_scale"] +
-                 t["write_kib_per_launch"] * t["write_scale"]) * 1024.0
     assert os.path.exists(os.path.join(ROOT, t["summary"]))
+    for k in ("workload", "source_sha256", "fetch_kib_per_launch", "write_kib_per_launch",
+              "fetch_scale", "write_scale", "commands"):
+        assert k in t, k

@@ -404,3 +404,214 @@ def test_table_cap_sanity(orc, alpha, S, phi_paper):
     status, res, _ = orc.run(st, orc.default_params(d0, s=1.0), orc.default_schedule(2000, S=S))
     assert status == 0
     assert abs(res.phi - phi_paper) < 0.03
+
+
+# ------------------------------------------------- schedule machinery, by hand
+def _separated_pair_schedule(orc, rungs, tol, eps_k):
+    d0 = np.array([1.0, 2.0])
+    x = np.array([[5.0, 5.0, 5.0], [25.0, 5.0, 5.0]])   # 20 apart: never touching
+    P = orc.Params()
+    P.beta1, P.beta2, P.eps_x, P.eps_k, P.skin_s, P.skin_g = 0.0, 0.0, 1e-12, eps_k, 0.1, 0.02
+    S = orc.Schedule()
+    S.n_rungs, S.absolute, S.tol = len(rungs), 0, tol
+    for r, (mu, ex, ek, dc, b) in enumerate(rungs):
+        S.mu[r], S.eta_x[r], S.eta_k[r], S.decay[r], S.budget[r] = mu, ex, ek, dc, b
+    st = orc.RunState(x, d0, 50.0, 1.0)
+    status, res, tr = orc.run(st, P, S, trace_cap=64)
+    return d0, x, st, status, res, tr
+
+
+RUNGS3 = [(0.6, 1e-2, 0.05, 1.0, 3), (0.2, 4e-3, 0.02, 0.5, 2), (0.1, 2e-3, 0.03, 0.8, 4)]
+
+
+def _kappa_by_hand(rungs, eps_k, n_iters, stop_in_final):
+    """The schedule of App. A as a table of rungs, worked in exact rational
+    arithmetic for two spheres that never touch (D0 = 1, 2): the overlap
+    terms vanish, so dE/dkappa = -mu sum D0 = -3 mu, and with beta1 = beta2
+    = 0 Adam's bias-corrected step is eta g / (|g| + eps) (m_hat = g,
+    v_hat = g^2).  At a rung start mu = mu~ N_v / (kappa sum D0) with N_v =
+    (sum D0^3)^2 / sum D0^6 = 81/65, eta_k = eta~_k kappa, eta_x = eta~_x
+    kappa D0_min; every iteration of rung r multiplies mu and both step
+    sizes by decay[r]."""
+    from fractions import Fraction as F
+    nv = F(81, 65)
+    kap = F(1)
+    ks = []
+    r, itr = 0, 0
+
+    def start(r, kap):
+        mu_t, ex_t, ek_t = (F(v) for v in rungs[r][:3])
+        return mu_t * nv / (kap * 3), ex_t * kap, ek_t * kap
+
+    mu, ex, ek = start(0, kap)
+    iters = 0
+    while iters < n_iters:
+        if stop_in_final and r == len(rungs) - 1:
+            break                                  # max delta = 0 < tol
+        ks.append(kap)
+        g = -3 * mu
+        kap = kap - ek * g / (abs(g) + F(eps_k))
+        dc = F(rungs[r][3])
+        mu, ex, ek = mu * dc, ex * dc, ek * dc
+        itr += 1
+        iters += 1
+        if itr >= rungs[r][4]:
+            if r == len(rungs) - 1:
+                break
+            r, itr = r + 1, 0
+            mu, ex, ek = start(r, kap)
+    return ks, kap, iters, r, (mu, ex, ek)
+
+
+@pytest.mark.parametrize("eps_k", [0.7, 1e-12])
+def test_schedule_machinery_hand_worked_stop(orc, eps_k):
+    # the final rung's stop test (max delta < tol) ends the run before its
+    # first update: 3 + 2 iterations, kappa grown by the hand-worked steps
+    d0, x, st, status, res, tr = _separated_pair_schedule(orc, RUNGS3, 1e-3, eps_k)
+    ks, kap, iters, r, etas = _kappa_by_hand(RUNGS3, eps_k, 100, True)
+    assert status == 0 and res.iterations == iters == 5 and res.rung == r == 2
+    assert np.array_equal(st.x, x)          # zero gradient: positions never move
+    assert st.kappa[0] == pytest.approx(float(kap), rel=1e-14)
+    for it, k in enumerate(ks):
+        assert tr[it, 1] == pytest.approx(float(k), rel=1e-14)
+    # rung 2 started with its own values at the kappa reached then
+    assert st.etas[0] == pytest.approx(float(etas[0]), rel=1e-14)
+    assert st.etas[1] == pytest.approx(float(etas[1]), rel=1e-14)
+    assert st.etas[2] == pytest.approx(float(etas[2]), rel=1e-14)
+    assert list(st.ctl) == [5, 2, 0, 0]
+
+
+def test_schedule_machinery_hand_worked_cap(orc):
+    # no stop (tol < 0): the final rung runs to its budget (status 1), with
+    # mu and the steps decaying by 0.8 per iteration in it
+    eps_k = 0.7
+    d0, x, st, status, res, tr = _separated_pair_schedule(orc, RUNGS3, -1.0, eps_k)
+    ks, kap, iters, r, etas = _kappa_by_hand(RUNGS3, eps_k, 100, False)
+    assert status == 1 and res.iterations == iters == 9 and res.rung == 2
+    assert st.kappa[0] == pytest.approx(float(kap), rel=1e-14)
+    for it, k in enumerate(ks):
+        assert tr[it, 1] == pytest.approx(float(k), rel=1e-14)
+    assert st.etas[0] == pytest.approx(float(etas[0]), rel=1e-14)
+    assert st.etas[2] == pytest.approx(float(etas[2]), rel=1e-14)
+    assert list(st.ctl) == [9, 2, 4, 0]
+
+
+# ------------------------------------------------------ list validity
+def _dense_state(orc, iters=1500, seed=0):
+    w = ri.c1_lognormal(seed)
+    x0 = orc.rsa(w.d0, w.L, 1.0, w.seed)
+    st = orc.RunState(x0, w.d0, w.L, 1.0)
+    orc.run(st, orc.default_params(w.d0, s=0.3, g=0.02), orc.default_schedule(w.n),
+            max_iters=iters)
+    return w, st.x.copy(), float(st.kappa[0])
+
+
+def test_rebuild_trigger_keeps_every_contact_listed(orc):
+    # App. A rebuilds on accumulated displacement; with the rule as stated
+    # every overlapping pair is in the list at every gradient evaluation
+    w, x, k = _dense_state(orc)
+    P = orc.default_params(w.d0, s=0.05, g=0.01)
+    st = orc.RunState(x, w.d0, w.L, k)
+    try:
+        orc.set_list_check(True)
+        status, res, _ = orc.run(st, P, orc.default_schedule(w.n), max_iters=400)
+        assert orc.list_misses() == 0
+        assert res.rebuilds > 5
+        # a planted mistake (ten times the displacement allowance) is caught
+        st2 = orc.RunState(x, w.d0, w.L, k)
+        orc.set_list_check(True, trigger_scale=10.0)
+        orc.run(st2, P, orc.default_schedule(w.n), max_iters=400)
+        assert orc.list_misses() > 0
+    finally:
+        orc.set_list_check(False)
+
+
+def test_skin_changes_only_the_summation_order(orc):
+    # a run that rebuilds at every step (skin 0: any motion invalidates the
+    # list) and one with a skin follow the same trajectory up to rounding
+    w, x, k = _dense_state(orc)
+    mu, ex, ek, steps = 2e-3, 2e-3, 2e-4, 30
+    out = []
+    for s, g in ((0.0, 0.0), (0.5, 0.05)):
+        st = orc.RunState(x, w.d0, w.L, k)
+        _, res, _ = orc.run(st, orc.default_params(w.d0, s=s, g=g),
+                            orc.oracle.absolute_schedule(mu, ex, ek, steps))
+        out.append((st.x.copy(), float(st.kappa[0]), res.rebuilds))
+    assert out[0][2] >= steps and out[1][2] < steps / 3
+    d = np.abs(out[0][0] - out[1][0])
+    d = np.minimum(d, w.L - d)
+    assert d.max() <= 1e-10 * ex * steps
+    assert out[0][1] == pytest.approx(out[1][1], rel=1e-13)
+
+
+# ------------------------------------------- per-row gradient, brute force
+def test_rows_grad_equals_pair_gradient(orc):
+    x, d0, L = _overlapping_case(n=600, phi=0.5, S=6.0, seed=21)
+    pi, pj = _all_overlaps(orc, x, d0, L, 1.0)
+    r = orc.energy_grad(x, d0, L, 1.0, 0.0, pi, pj)
+    rows = np.arange(0, 600, 7)
+    g, gs, st = orc.rows_grad(x, d0, L, 1.0, rows)
+    assert np.all(np.abs(g - r["g"][rows]) <= 1e-13 * r["gscale"][rows])
+    assert np.allclose(gs, r["gscale"][rows], rtol=1e-13, atol=0)
+    gall, _, stall = orc.rows_grad(x, d0, L, 1.0, np.arange(600))
+    # each pair's energy is counted in both of its rows
+    assert stall[:, 0].sum() == pytest.approx(2 * r["E_ov"], rel=1e-12)
+    assert stall[:, 1].sum() == pytest.approx(2 * r["gk_ov"], rel=1e-12)
+    assert stall[:, 2].max() == r["max_delta"]
+    assert np.all(np.abs(gall - r["g"]) <= 1e-13 * r["gscale"])
+
+
+# -------------------------------------- skin predicate, independent numpy
+@pytest.mark.parametrize("S,phi,kb,s,g", [(30.0, 0.4, 1.3, 0.7, 0.05), (4.0, 0.6, 0.9, 0.25, 0.1),
+                                         (200.0, 0.2, 1.0, 2.0, 0.02)])
+def test_skin_predicate_against_numpy(orc, S, phi, kb, s, g):
+    # the listing rule written out directly (same operation order, no
+    # contraction: numpy rounds every operation): minimum image with one
+    # shift beyond +-L/2, r^2 = (dx^2 + dy^2) + dz^2,
+    # c = kb ((1 + g) (D0_i + D0_j)/2 + 2 s D0_min), listed iff r^2 < c^2
+    w = ri.small_polydisperse(1500, S, phi, seed=31, family="powerlaw")
+    x, d0, L = w.x, w.d0, w.L
+    hL = 0.5 * L
+    i, j = np.triu_indices(len(d0), 1)
+    sep = []
+    for a in range(3):
+        t = x[j, a] - x[i, a]
+        sep.append(np.where(t > hL, t - L, np.where(t < -hL, t + L, t)))
+    r2 = (sep[0] * sep[0] + sep[1] * sep[1]) + sep[2] * sep[2]
+    c = kb * ((1.0 + g) * (0.5 * (d0[i] + d0[j])) + (2.0 * s) * d0.min())
+    keep = r2 < c * c
+    oi, oj = orc.pairs_brute(x, d0, L, kb, s, g)
+    assert keep.sum() > 1000
+    assert np.array_equal(oi, i[keep]) and np.array_equal(oj, j[keep])
+
+
+# ------------------------------------------ coincident centres, +-L/2 image
+def test_coincident_centres_hand_values(orc):
+    # r = 0: delta = 1, the pair counts in E (1/2) and in max delta but adds
+    # nothing to dE/dkappa (delta r / (kappa d) = 0) and nothing to the
+    # position gradient (the subgradient 0 is taken)
+    d0 = np.array([1.0, 3.0])
+    x = np.array([[4.0, 5.0, 6.0], [4.0, 5.0, 6.0]])
+    r = orc.energy_grad(x, d0, 20.0, 2.0, 0.0, [0], [1])
+    assert r["E_ov"] == 0.5 and r["gk_ov"] == 0.0 and r["max_delta"] == 1.0
+    assert r["n_overlap"] == 1 and np.all(r["g"] == 0.0)
+
+
+@pytest.mark.parametrize("flip", [False, True])
+def test_half_box_separation_takes_no_shift(orc, flip):
+    # a separation of exactly L/2 (or -L/2) is not shifted: with L = 10, D0 =
+    # (4, 8), kappa = 1: d = 6, r = 5, delta = 1/6; E = 1/72; dE/dkappa =
+    # delta r / (kappa d) = 5/36; dE/dx_i = delta / (d r) (x_j - x_i) = +-1/36
+    d0 = np.array([4.0, 8.0])
+    xa, xb = (6.0, 1.0) if flip else (1.0, 6.0)
+    x = np.array([[xa, 2.0, 3.0], [xb, 2.0, 3.0]])
+    r = orc.energy_grad(x, d0, 10.0, 1.0, 0.0, [0], [1])
+    sgn = -1.0 if flip else 1.0
+    assert r["E_ov"] == pytest.approx(1.0 / 72.0, rel=1e-15)
+    assert r["gk_ov"] == pytest.approx(5.0 / 36.0, rel=1e-15)
+    assert r["g"][0, 0] == pytest.approx(sgn / 36.0, rel=1e-15)
+    assert r["g"][1, 0] == pytest.approx(-sgn / 36.0, rel=1e-15)
+    assert np.all(r["g"][:, 1:] == 0.0)
+    # the listing rule uses the same unshifted separation
+    pi, pj = orc.pairs_brute(x, d0, 10.0, 1.0, 0.0, 0.0)
+    assert list(pi) == [0] and list(pj) == [1]
