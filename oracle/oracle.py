@@ -67,7 +67,7 @@ def lib():
         L.orc_run.restype = C.c_int
         L.orc_run.argtypes = [C.c_int64, dp, dp, C.c_double, dp, dp, dp, dp, lp,
                               dp, C.POINTER(Params), C.POINTER(Schedule),
-                              C.c_int64, C.POINTER(Result), dp, C.c_int64]
+                              C.c_int64, C.POINTER(Result), dp, C.c_int64, dp]
         L.orc_time_iterations.restype = C.c_double
         L.orc_time_iterations.argtypes = [C.c_int64, dp, dp, C.c_double,
                                           C.c_double, C.c_double, C.c_double,
@@ -350,15 +350,21 @@ def default_params(d0, kappa0=1.0, s=0.1, g=0.02):
     return P
 
 
-def run(state, params, sched, max_iters=1 << 62, trace_cap=0):
-    """Advance `state` by the schedule; returns (status, Result, trace)."""
+def run(state, params, sched, max_iters=1 << 62, trace_cap=0, gsmax=None):
+    """Advance `state` by the schedule; returns (status, Result, trace).
+    gsmax (n, 3) float64, optional: raised in place to the largest sum of
+    |pair contributions| per component over the gradients evaluated."""
     res = Result()
     tr = np.zeros((max(trace_cap, 1), 3))
+    if gsmax is not None:
+        assert gsmax.dtype == np.float64 and gsmax.flags.c_contiguous
+        assert gsmax.shape == (state.d0.shape[0], 3)
     st = lib().orc_run(state.d0.shape[0], _d(state.x), _d(state.d0), state.L,
                        _d(state.kappa), _d(state.m), _d(state.v), _d(state.mkvk),
                        _l(state.ctl), _d(state.etas), C.byref(params),
                        C.byref(sched), max_iters, C.byref(res),
-                       _d(tr) if trace_cap else None, trace_cap)
+                       _d(tr) if trace_cap else None, trace_cap,
+                       _d(gsmax) if gsmax is not None else None)
     ntr = min(trace_cap, int(res.iterations) + 1)
     return st, res, (tr[:ntr] if trace_cap else None)
 

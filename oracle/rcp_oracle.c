@@ -658,6 +658,8 @@ typedef struct {
     int32_t *col;
     double kb;               /* kappa at the last list build */
     int64_t rebuilds;
+    double *gsmax;           /* optional: per component, the largest sum of
+                                |pair contributions| over the evaluations */
 } run_t;
 
 static void run_rebuild(run_t *R, double kappa, const orc_params *P)
@@ -715,7 +717,7 @@ static void run_grad(run_t *R, double kappa, double *Eov, double *Sdrd,
     double *re = malloc(sizeof(double) * 3 * (size_t)n);
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
-        double gg[3] = {0, 0, 0}, e = 0, s = 0, m = 0;
+        double gg[3] = {0, 0, 0}, ga[3] = {0, 0, 0}, e = 0, s = 0, m = 0;
         for (int64_t q = R->rp[i]; q < R->rp[i + 1]; ++q) {
             int64_t j = R->col[q];
             double dx, dy, dz;
@@ -730,9 +732,13 @@ static void run_grad(run_t *R, double kappa, double *Eov, double *Sdrd,
             if (r > 0.0) {
                 double f = delta / (d * r);
                 gg[0] += f * dx; gg[1] += f * dy; gg[2] += f * dz;
+                ga[0] += fabs(f * dx); ga[1] += fabs(f * dy); ga[2] += fabs(f * dz);
             }
         }
         R->g[3 * i] = gg[0]; R->g[3 * i + 1] = gg[1]; R->g[3 * i + 2] = gg[2];
+        if (R->gsmax)
+            for (int a = 0; a < 3; ++a)
+                if (ga[a] > R->gsmax[3 * i + a]) R->gsmax[3 * i + a] = ga[a];
         re[3 * i] = e; re[3 * i + 1] = s; re[3 * i + 2] = m;
     }
     nsum_t E = {0, 0}, S = {0, 0};
@@ -796,14 +802,17 @@ static inline double adam(double th, double g, double *m, double *v, double b1,
  *   ctl[3] = 1 when the rung's parameters still have to be set.
  * etas[0..2] = mu, eta_x, eta_k in force (in/out).
  * max_iters bounds the number of iterations of this call (status 2 when hit).
- * trace (may be NULL): per iteration (max delta, kappa, E_ov) up to trace_cap. */
+ * trace (may be NULL): per iteration (max delta, kappa, E_ov) up to trace_cap.
+ * gsmax (n x 3, may be NULL): raised to the largest per-component sum of
+ * |pair contributions| of any gradient evaluated (a scale for tolerances). */
 int orc_run(int64_t n, double *x, const double *d0, double L, double *kappa,
             double *m, double *v, double *mk_vk, int64_t *ctl, double *etas,
             const orc_params *P, const orc_sched *S, int64_t max_iters,
-            orc_result *res, double *trace, int64_t trace_cap)
+            orc_result *res, double *trace, int64_t trace_cap, double *gsmax)
 {
     run_t R;
     memset(&R, 0, sizeof R);
+    R.gsmax = gsmax;
     R.n = n; R.L = L; R.hL = 0.5 * L; R.d0 = d0; R.x = x; R.m = m; R.v = v;
     R.xref = malloc(sizeof(double) * 3 * (size_t)n);
     R.g = malloc(sizeof(double) * 3 * (size_t)n);

@@ -67,40 +67,40 @@ __device__ __forceinline__ double fast_rsq(double x)
     return fma(y, t, y);
 }
 
-// Squared distances below this use the IEEE root (the estimates lose range
-// near the bottom of the exponent range).
-constexpr double kTinyR2 = 1e-200;
-
 // One listed partner's terms (Eq. energy): with q = r/d and delta = 1 - q,
 // E += delta^2 / 4 and S += delta q / 2 (each pair is seen from both ends),
 // and the gradient on x_i gains delta / (d r) (x_j - x_i).
+// delta = 1 - r/d cancels for shallow overlaps (a small sphere grazing one
+// 10^5 times larger has delta ~ 1e-6), so r^2, r and q are formed exactly as
+// the plain definition rounds them: no contraction of r^2, the IEEE root and
+// the IEEE quotient.  Then delta is the correctly rounded value of the
+// definition's own arithmetic; the factor delta / (d r) is well conditioned
+// and takes the hardware reciprocal estimate refined by two Newton steps.
 template <bool kCount = true>
 __device__ __forceinline__ void pair_term(Acc &a, const P4 &qi, const P4 &qj, double kappa,
                                           double L, double iL)
 {
+#pragma clang fp contract(off)
     const double dx = near_image(qj.x - qi.x, L, iL);
     const double dy = near_image(qj.y - qi.y, L, iL);
     const double dz = near_image(qj.z - qi.z, L, iL);
     const double r2 = (dx * dx + dy * dy) + dz * dz;
     const double d = kappa * (0.5 * (qi.d + qj.d));
     if (r2 < d * d) {
-        const double id = fast_rcp(d);
-        double r, ir;
-        if (r2 >= kTinyR2) {
-            ir = fast_rsq(r2);
-            r = r2 * ir;
-        } else {
-            r = sqrt(r2);
-            ir = r > 0.0 ? 1.0 / r : 0.0;
-        }
-        const double q = r * id;
+        const double r = sqrt(r2);
+        const double q = r / d;
         const double delta = 1.0 - q;
         a.e += 0.25 * (delta * delta);
         a.s += 0.5 * (delta * q);
         a.m = fmax(a.m, delta);
         if (kCount) a.c += 0.5;
         if (r > 0.0) {
-            const double f = (delta * id) * ir;
+            // (the estimate loses range near the bottom of the exponent
+            // range: there, a rarely taken branch, the IEEE quotient)
+            const double dr = d * r;
+            double f;
+            if (dr >= 1e-290) f = delta * fast_rcp(dr);
+            else f = delta / dr;
             a.gx += f * dx;
             a.gy += f * dy;
             a.gz += f * dz;

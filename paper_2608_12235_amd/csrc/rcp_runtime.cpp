@@ -24,6 +24,12 @@ int place_rsa(int64_t n, const double *d0, double L, double kappa0, uint64_t see
 
 using namespace rcp;
 
+// Events used only to time work on the context's stream: no system-scope
+// fence when they are recorded (a fence writes back and invalidates the
+// caches, which costs microseconds per event node and slows the launch that
+// follows); their readers synchronise the stream first.
+constexpr unsigned kTimingEvent = hipEventDisableSystemFence;
+
 // ------------------------------------------------------------ errors
 static thread_local std::string g_err;
 
@@ -206,8 +212,8 @@ static int rebuild_events(rcp_ctx *c, std::pair<hipEvent_t, hipEvent_t> &ev)
         c->rb_pool.pop_back();
         return RCP_OK;
     }
-    HIPCHK(hipEventCreate(&ev.first));
-    HIPCHK(hipEventCreate(&ev.second));
+    HIPCHK(hipEventCreateWithFlags(&ev.first, kTimingEvent));
+    HIPCHK(hipEventCreateWithFlags(&ev.second, kTimingEvent));
     return RCP_OK;
 }
 
@@ -851,7 +857,7 @@ static int ensure_kernel_events(rcp_ctx *c, int K)
 {
     while ((int)c->kev.size() < 3 * K) {
         hipEvent_t e;
-        HIPCHK(hipEventCreate(&e));
+        HIPCHK(hipEventCreateWithFlags(&e, kTimingEvent));
         c->kev.push_back(e);
     }
     return RCP_OK;
@@ -1361,7 +1367,8 @@ int rcp_census_init(int dim, int n_prob, const int64_t *n, const double *const *
             if (e != hipSuccess) { rc = fail(RCP_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e)); break; }
             c->own_stream = true;
         }
-        if ((e = hipEventCreate(&c->e0)) != hipSuccess || (e = hipEventCreate(&c->e1)) != hipSuccess) {
+        if ((e = hipEventCreateWithFlags(&c->e0, kTimingEvent)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&c->e1, kTimingEvent)) != hipSuccess) {
             rc = fail(RCP_EDEVICE, "hipEventCreate: %s", hipGetErrorString(e));
             break;
         }
@@ -1916,7 +1923,7 @@ int rcp_time_iterations(rcp_ctx *c, int64_t n_iters, double *iterate_us, double 
                        n_iters);
     constexpr int kBatch = 32;
     std::vector<hipEvent_t> ev(3 * kBatch);
-    for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+    for (auto &e : ev) HIPCHK(hipEventCreateWithFlags(&e, kTimingEvent));
     double it_ms = 0, tl_ms = 0;
     int64_t n_done = 0;
     int rc = RCP_OK;
