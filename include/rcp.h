@@ -106,7 +106,8 @@ typedef struct {
  *     (bits 1-4 and fused_tail do not apply with it); bit 6 selects the
  *     wave-cooperative pair search of the list build (the 64 lanes of a
  *     wave test the flattened candidates of all their cells together; the
- *     same pairs are listed);
+ *     same pairs are listed); bit 7 = each update writes the whole 32-byte
+ *     position record (x, y, z, D0) instead of the three coordinates;
  *   time_kernels: 0 = no timing; 1 = HIP events around the gradient + Adam
  *     and tail launches of the middle iteration (graph_iters / 2) of every
  *     batch of graph_iters (a uniform sample of one launch in graph_iters;
@@ -203,9 +204,9 @@ typedef struct {
 int rcp_version(void);
 const char *rcp_last_error(void);
 void rcp_params_default(rcp_params *p);
-/* Defaults: graph_iters 32, xcd_remap 1, fused_tail 0, variant 64 (the
- * cooperative pair search, the two-gather gradient + Adam kernel), row_cost
- * 10, item_work 2560, time_kernels 0. */
+/* Defaults: graph_iters 32, xcd_remap 1, fused_tail 0, variant 192 (the
+ * cooperative pair search, the two-gather gradient + Adam kernel writing
+ * whole records), row_cost 10, item_work 2560, time_kernels 0. */
 void rcp_tuning_default(rcp_tuning *t);
 
 /* Default rung table for a packing of n spheres in dimension dim with size

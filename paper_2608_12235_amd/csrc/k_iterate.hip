@@ -67,15 +67,26 @@ __device__ __forceinline__ double fast_rsq(double x)
     return fma(y, t, y);
 }
 
+// Squared distances below this use the IEEE root (the estimates lose range
+// near the bottom of the exponent range).
+constexpr double kTinyR2 = 1e-200;
+// Overlaps shallower than this take the definition's own rounding (below).
+constexpr double kShallow = 0x1p-10;
+// Pairs with r^2 below d^2 (1 + 2^-50) are examined: every pair whose
+// correctly rounded r can be below d passes this filter.
+constexpr double kLoose = 1.0 + 0x1p-50;
+
 // One listed partner's terms (Eq. energy): with q = r/d and delta = 1 - q,
 // E += delta^2 / 4 and S += delta q / 2 (each pair is seen from both ends),
-// and the gradient on x_i gains delta / (d r) (x_j - x_i).
-// delta = 1 - r/d cancels for shallow overlaps (a small sphere grazing one
-// 10^5 times larger has delta ~ 1e-6), so r^2, r and q are formed exactly as
-// the plain definition rounds them: no contraction of r^2, the IEEE root and
-// the IEEE quotient.  Then delta is the correctly rounded value of the
-// definition's own arithmetic; the factor delta / (d r) is well conditioned
-// and takes the hardware reciprocal estimate refined by two Newton steps.
+// and the gradient on x_i gains delta / (d r) (x_j - x_i); a pair counts
+// when r < d.  r^2 is formed without contraction.  r and q come from the
+// hardware estimates refined by Newton steps (a few ulp); that is far inside
+// the 1e-10 bar while delta is not small, but delta = 1 - q cancels for
+// shallow overlaps (a small sphere grazing one 10^5 times larger has delta ~
+// 1e-6), so below kShallow r and q are recomputed as the plain definition
+// rounds them (IEEE root and quotient): then delta and the test r < d are
+// exactly the definition's, which also makes the stop test (max delta below
+// the tolerance) exact.  The factor delta / (d r) is well conditioned.
 template <bool kCount = true>
 __device__ __forceinline__ void pair_term(Acc &a, const P4 &qi, const P4 &qj, double kappa,
                                           double L, double iL)
@@ -86,24 +97,34 @@ __device__ __forceinline__ void pair_term(Acc &a, const P4 &qi, const P4 &qj, do
     const double dz = near_image(qj.z - qi.z, L, iL);
     const double r2 = (dx * dx + dy * dy) + dz * dz;
     const double d = kappa * (0.5 * (qi.d + qj.d));
-    if (r2 < d * d) {
-        const double r = sqrt(r2);
-        const double q = r / d;
-        const double delta = 1.0 - q;
-        a.e += 0.25 * (delta * delta);
-        a.s += 0.5 * (delta * q);
-        a.m = fmax(a.m, delta);
-        if (kCount) a.c += 0.5;
-        if (r > 0.0) {
-            // (the estimate loses range near the bottom of the exponent
-            // range: there, a rarely taken branch, the IEEE quotient)
-            const double dr = d * r;
-            double f;
-            if (dr >= 1e-290) f = delta * fast_rcp(dr);
-            else f = delta / dr;
-            a.gx += f * dx;
-            a.gy += f * dy;
-            a.gz += f * dz;
+    if (r2 < (d * d) * kLoose) {
+        const double id = fast_rcp(d);
+        double r, ir;
+        if (r2 >= kTinyR2) {
+            ir = fast_rsq(r2);
+            r = r2 * ir;
+        } else {
+            r = sqrt(r2);
+            ir = r > 0.0 ? 1.0 / r : 0.0;
+        }
+        double q = r * id;
+        double delta = 1.0 - q;
+        if (delta < kShallow) {
+            r = sqrt(r2);
+            q = r / d;
+            delta = 1.0 - q;
+        }
+        if (r < d) {
+            a.e += 0.25 * (delta * delta);
+            a.s += 0.5 * (delta * q);
+            a.m = fmax(a.m, delta);
+            if (kCount) a.c += 0.5;
+            if (r > 0.0) {
+                const double f = (delta * id) * ir;
+                a.gx += f * dx;
+                a.gy += f * dy;
+                a.gz += f * dz;
+            }
         }
     }
 }
@@ -196,11 +217,13 @@ __device__ __forceinline__ Pre preload(const IterPtrs &p, int64_t i)
     return q;
 }
 
-// Adam on particle i's coordinates, new position (and its D0) stored;
+// Adam on particle i's coordinates, new position stored (the three
+// coordinates: the record's D0 in the output buffer is already in place,
+// written when the list order was set; with `full` the whole record);
 // returns |x_new - x_ref|^2 (min image).
 __device__ __forceinline__ double update_particle(const IterPtrs &p, const IterScalars &c,
                                                   int64_t i, const P4 &qi, const Pre &q,
-                                                  double gx, double gy, double gz)
+                                                  double gx, double gy, double gz, bool full)
 {
     double d2 = 0.0;
     P4 o;
@@ -208,8 +231,19 @@ __device__ __forceinline__ double update_particle(const IterPtrs &p, const IterS
     o.y = update_coord(qi.y, gy, q.m1, q.v1, q.r1, p.m1, p.v1, c, i, d2);
     o.z = update_coord(qi.z, gz, q.m2, q.v2, q.r2, p.m2, p.v2, c, i, d2);
     o.d = qi.d;
-    store_p4(p.qo, (int32_t)i, o);
+    if (full) store_p4(p.qo, (int32_t)i, o);
+    else store_xyz(p.qo, (int32_t)i, o.x, o.y, o.z);
     return d2;
+}
+
+// floor(n / d) for 0 <= n < 2^31 and 1 <= d < 2^31 with rd = 1 / d: the
+// truncated product is the quotient or one less (never more), one upward
+// correction settles it; (q + 1) d <= n + d < 2^32.
+__device__ __forceinline__ int32_t div_by(int32_t n, uint32_t d, double rd)
+{
+    uint32_t q = (uint32_t)((double)n * rd);
+    if ((q + 1u) * d <= (uint32_t)n) ++q;
+    return (int32_t)q;
 }
 
 __device__ __forceinline__ void rung_start(SegState *s, int r)
@@ -479,7 +513,8 @@ struct NoHook {
 template <int kU, bool kEarly, bool kStage, int kR, class Hook, bool kCoherentOut = false>
 __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &c, int64_t r0,
                                           int nrow, const int32_t *rp_own, int32_t rp_end,
-                                          ItemLdsR<kR> &L, int32_t *scol, Part4 *out, Hook hook)
+                                          ItemLdsR<kR> &L, int32_t *scol, Part4 *out, Hook hook,
+                                          bool full)
 {
     static_assert(kR == kBlock || (kR == 2 * kBlock && !kEarly), "rows per item");
     constexpr int kOwn = kR / kBlock;
@@ -512,6 +547,7 @@ __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &
     double bd = 0;
     const int32_t e0 = L.srp[0], e1 = L.srp[nrow];
     const int32_t chunk = max(1, (e1 - e0 + kBlock - 1) / kBlock);
+    const double rchunk = 1.0 / (double)chunk;   // block-uniform
     const int32_t cs = e0 + t * chunk, ce = min(cs + chunk, e1);
     if (cs < ce) {
         int lo = 0, hi = nrow - 1;   // the row holding entry cs
@@ -553,7 +589,8 @@ __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &
         const int32_t qb = L.srp[row], qe = L.srp[row + 1];
         double g[3] = {0, 0, 0};
         if (qb < qe) {
-            const int tf = (qb - e0) / chunk, tl = (qe - 1 - e0) / chunk;
+            const int tf = div_by(qb - e0, (uint32_t)chunk, rchunk),
+                      tl = div_by(qe - 1 - e0, (uint32_t)chunk, rchunk);
             if (tf == tl) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) g[d] = L.G[d][row];
@@ -566,7 +603,7 @@ __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &
                 }
             }
         }
-        bd = fmax(bd, update_particle(p, c, io, oq, pre, g[0], g[1], g[2]));
+        bd = fmax(bd, update_particle(p, c, io, oq, pre, g[0], g[1], g[2], full));
     }
     // block reduction of the four partials
     const int lane = t & (kWave - 1);
@@ -645,7 +682,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
     const int32_t rp_end = gload(p.rp, r0 + nrow);
     item_body<kU, kEarly, kStage, kBlock, NoHook, kFusedTail>(
         p, c, r0, nrow, &rp_t, rp_end, L, scol, reinterpret_cast<Part4 *>(partials) + b,
-        NoHook());
+        NoHook(), (flags & 4) != 0);
     if (kFusedTail) {
         // the last block of the packing to finish reduces the partials and
         // runs the tail.  Partials are written through to memory and read
@@ -691,7 +728,8 @@ __global__ __launch_bounds__(kBlock) void k_iterate512(const SegPtrs *__restrict
     rp_own[1] = t + kBlock < nrow ? gload(p.rp, r0 + t + kBlock) : 0;
     const int32_t rp_end = gload(p.rp, r0 + nrow);
     item_body<kU, false, false, 2 * kBlock>(p, c, r0, nrow, rp_own, rp_end, L, nullptr,
-                                            reinterpret_cast<Part4 *>(partials) + b, NoHook());
+                                            reinterpret_cast<Part4 *>(partials) + b, NoHook(),
+                                            (flags & 4) != 0);
 }
 
 // resident blocks of the persistent form: 256 CUs x 5 blocks (the occupancy
@@ -767,7 +805,7 @@ __global__ __launch_bounds__(kBlock) void k_iterate_persist(const SegPtrs *__res
             };
             item_body<kU, false, false, kBlock>(p, c, w.begin, nrow, &rp_t, rp_end, L, nullptr,
                                                 reinterpret_cast<Part4 *>(partials) + item,
-                                                hook);
+                                                hook, (flags & 4) != 0);
         }
         item = next;
         if (item >= hi) break;
@@ -834,9 +872,9 @@ static void launch_variant(const SegPtrs *P, SegState *S, const WorkItem *W, dou
 void launch_iterate(const SegPtrs *P, SegState *S, const WorkItem *W, double *partials,
                     int nitems, int flags, hipStream_t st)
 {
-    // bit 0: XCD-aware order; bit 1: fused tail; bits 8-13: kernel variant
-    // (see launch_variant)
-    const int f = flags & 1, variant = (flags >> 8) & 63;
+    // bit 0: XCD-aware order; bit 1: fused tail; bit 2: whole 32-byte
+    // records written; bits 8-13: kernel variant (see launch_variant)
+    const int f = flags & 5, variant = (flags >> 8) & 63;
     if (variant & 40) launch_variant<false>(P, S, W, partials, nitems, f, variant, st);
     else if (flags & 2) launch_variant<true>(P, S, W, partials, nitems, f, variant, st);
     else launch_variant<false>(P, S, W, partials, nitems, f, variant, st);

@@ -885,6 +885,16 @@ __global__ __launch_bounds__(kBlock) void k_permute_seg(const FrontJob *__restri
     if (k < F.pa.n) permute_one(F.pa, k);
 }
 
+// After the permutation: the other position buffer (the source of the
+// permutation, which the next iteration writes) takes the D0 of the new
+// order, so that iterations need to write only the three coordinates.
+__global__ __launch_bounds__(kBlock) void k_d0_copy_seg(const FrontJob *__restrict__ jobs, int J)
+{
+    const FrontJob &F = jobs[job_of(jobs, J, blockIdx.x, &FrontJob::b0)];
+    const int64_t k = ((int64_t)blockIdx.x - F.b0) * kBlock + threadIdx.x;
+    if (k < F.pa.n) const_cast<P4 *>(F.pa.ps)[k].d = F.pa.pd[k].d;
+}
+
 __global__ __launch_bounds__(kBlock) void k_tables_clear_seg(const FrontJob *__restrict__ jobs,
                                                             int J)
 {
@@ -916,7 +926,9 @@ void launch_keys_seg(const FrontJob *jobs, int J, int64_t nb, hipStream_t s)
 
 void launch_permute_seg(const FrontJob *jobs, int J, int64_t nb, hipStream_t s)
 {
-    if (nb > 0) hipLaunchKernelGGL(k_permute_seg, dim3((unsigned)nb), dim3(kBlock), 0, s, jobs, J);
+    if (nb <= 0) return;
+    hipLaunchKernelGGL(k_permute_seg, dim3((unsigned)nb), dim3(kBlock), 0, s, jobs, J);
+    hipLaunchKernelGGL(k_d0_copy_seg, dim3((unsigned)nb), dim3(kBlock), 0, s, jobs, J);
 }
 
 void launch_tables_seg(const FrontJob *jobs, int J, int64_t nbt, int64_t nb, hipStream_t s)

@@ -130,6 +130,18 @@ __device__ __forceinline__ void store_p4(P4 *base, int32_t j, const P4 &r)
     *(gptr<dbl4>)(b + ((uint32_t)j << 5)) = v;
 }
 
+// The three coordinates of a record, its D0 left as it is (16 + 8 bytes).
+__device__ __forceinline__ void store_xyz(P4 *base, int32_t j, double x, double y, double z)
+{
+    typedef double dbl2 __attribute__((ext_vector_type(2)));
+    const gptr<char> b = (gptr<char>)base + ((uint32_t)j << 5);
+    dbl2 v;
+    v.x = x;
+    v.y = y;
+    *(gptr<dbl2>)b = v;
+    *(gptr<double>)(b + 16) = z;
+}
+
 template <class T>
 __device__ __forceinline__ T gload(const T *base, int64_t i)
 {

@@ -102,8 +102,9 @@ struct BackJob {
     int64_t br0;            // first block in the row grid
 };
 // Front steps for all packings of a batch (jobs in device memory): Morton
-// keys (nb = blocks of the per-particle grid), permutation, cell tables
-// (nbt = blocks of the clear grid; clears the counters too).
+// keys (nb = blocks of the per-particle grid), permutation (then the D0 of
+// the new order into the other position buffer), cell tables (nbt = blocks
+// of the clear grid; clears the counters too).
 void launch_keys_seg(const FrontJob *jobs, int J, int64_t nb, hipStream_t s);
 void launch_permute_seg(const FrontJob *jobs, int J, int64_t nb, hipStream_t s);
 void launch_tables_seg(const FrontJob *jobs, int J, int64_t nbt, int64_t nb, hipStream_t s);
@@ -131,8 +132,8 @@ void launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 
 // -------------------------------------------------------- k_iterate.hip
 // flags bit 0: XCD-aware block order; bit 1: the last block of each packing
-// runs its tail (otherwise launch_tail must follow); bit 2: blocks of the
-// last rows (largest particles) first.
+// runs its tail (otherwise launch_tail must follow); bit 2: whole 32-byte
+// position records written (else the three coordinates only).
 // Work items of packing seg (nslots slots at W): rows are cut so that an
 // item covers item_work units of row_cost * row + row pointer; rp == nullptr
 // leaves every slot empty.

@@ -653,7 +653,10 @@ static int build_backs(rcp_ctx *c, std::vector<BuildJob> &jobs, const std::vecto
         B.item_work = c->tuning.item_work;
         s.list_est = m;
         s.built = true;
-        B.fill = slots_for(c, s.n, m) <= s.blocks ? 1 : 0;
+        // the work table holds this list's items; it is laid out again when
+        // it is too small, or more than twice too large (idle items still
+        // cost a launch slot and a partial for the tail to read)
+        B.fill = (slots_for(c, s.n, m) <= s.blocks && slots_for(c, s.n, 2 * m) >= s.blocks) ? 1 : 0;
         if (!B.fill) {
             s.slot_entries = m + m / 4;
             *relayout = true;
@@ -837,12 +840,19 @@ static bool slot_timed(const rcp_ctx *c, int64_t slot)
     return slot >= 0 && (c->tuning.time_kernels == 2 || (c->tuning.time_kernels == 1 && slot == mid));
 }
 
+// Launch flags of the gradient + Adam kernel from the tuning (see
+// launch_iterate; the fused tail is added by the callers that use it).
+static int iterate_flags(const rcp_ctx *c)
+{
+    return (c->tuning.xcd_remap ? 1 : 0) | ((c->tuning.variant & 128) ? 4 : 0) |
+           ((c->tuning.variant & 63) << 8);
+}
+
 // One iteration: gradient + Adam kernel and tail kernel, bracketed by the
 // slot's three events when the slot is timed.
 static int launch_one_iteration(rcp_ctx *c, int slot)
 {
-    const int flags = (c->tuning.xcd_remap ? 1 : 0) | (c->tuning.fused_tail ? 2 : 0) |
-                      ((c->tuning.variant & 63) << 8);
+    const int flags = iterate_flags(c) | (c->tuning.fused_tail ? 2 : 0);
     const bool timed = slot_timed(c, slot) && 3 * slot + 2 < (int)c->kev.size();
     if (timed) CHK(record_event(c, c->kev[3 * slot]));
     launch_iterate(c->d_ptrs, c->d_state, c->d_work, c->d_partials, c->nitems, flags, c->stream);
@@ -1291,7 +1301,9 @@ void rcp_tuning_default(rcp_tuning *t)
     t->graph_iters = 32;
     t->xcd_remap = 1;
     t->fused_tail = 0;
-    t->variant = 64;   // cooperative pair search
+    // cooperative pair search; whole 32-byte records written (measured at
+    // least as fast as writing the three coordinates alone)
+    t->variant = 64 | 128;
     t->row_cost = 10;
     t->item_work = 2560;
     t->time_kernels = 0;
@@ -1437,7 +1449,7 @@ int rcp_set_tuning(rcp_ctx *c, const rcp_tuning *t)
 {
     if (!c || !t || t->size != sizeof(rcp_tuning)) return fail(RCP_EINVAL, "bad tuning");
     const int64_t max_rows = (t->variant & 32) ? 2 * kBlock : kBlock;
-    if (t->graph_iters < 1 || t->graph_iters > 4096 || t->variant < 0 || t->variant > 127 ||
+    if (t->graph_iters < 1 || t->graph_iters > 4096 || t->variant < 0 || t->variant > 255 ||
         t->row_cost < 1 || t->row_cost > 65536 || t->item_work < 1 ||
         (int64_t)t->item_work > max_rows * t->row_cost)
         return fail(RCP_EINVAL, "bad tuning values");
@@ -1927,8 +1939,7 @@ int rcp_time_iterations(rcp_ctx *c, int64_t n_iters, double *iterate_us, double 
     double it_ms = 0, tl_ms = 0;
     int64_t n_done = 0;
     int rc = RCP_OK;
-    const int flags = (c->tuning.xcd_remap ? 1 : 0) |
-                      ((c->tuning.variant & 63) << 8);
+    const int flags = iterate_flags(c);
     for (;;) {
         if ((rc = pull_state(c)) != RCP_OK) break;
         bool any = false;

@@ -615,3 +615,21 @@ def test_half_box_separation_takes_no_shift(orc, flip):
     # the listing rule uses the same unshifted separation
     pi, pj = orc.pairs_brute(x, d0, 10.0, 1.0, 0.0, 0.0)
     assert list(pi) == [0] and list(pj) == [1]
+
+
+# ------------------------------------------------- stored oracle whole runs
+def test_stored_census_runs_come_from_the_oracle(orc):
+    # the stored whole-run results are the oracle's: its smallest case, rerun,
+    # gives the stored phi to the last bit
+    import json
+    with open(os.path.join(GOLD, "census8_phi_oracle.json")) as fh:
+        runs = json.load(fh)["runs"]
+    w = sorted(ri.census_draw(64), key=lambda w: w.n)[0]
+    g = runs[0]
+    assert (g["n"], g["seed"]) == (w.n, 1000)
+    st = orc.RunState(orc.rsa(w.d0, w.L, 1.0, 1000), w.d0, w.L, 1.0)
+    S = float(w.d0.max() / w.d0.min())
+    status, res, _ = orc.run(st, orc.default_params(w.d0, s=0.5), orc.default_schedule(w.n, S=S))
+    assert status == g["status"] == 0
+    assert res.iterations == g["iterations"]
+    assert res.phi == g["phi"]
