@@ -401,6 +401,24 @@ int rcp_energy_dev(rcp_ctx *ctx, const double *x_dev, double kappa, double mu,
 int rcp_adjoint_dev(rcp_ctx *ctx, const double *x_dev, double kappa, double mu,
                     double *gx_dev, double *gk_dev, void *stream);
 
+/* For callers that cannot allocate device memory (code being captured into
+ * a HIP graph, tight serving loops, harnesses that forbid hipMalloc): the
+ * energy of rcp_energy_dev (E = E_overlap + E_growth to E_dev[0], max overlap
+ * to E_dev[1]; same arguments, same kernels and summation order, so the same
+ * bits) with no allocation and no list rebuild.  Its block partials live in
+ * a fixed device array of the library, one per GPU, sized for at most 2^24
+ * spheres (2 MiB plus 512 bytes), held until the process ends.  Packing 0's
+ * neighbour list must already be valid at (x_dev, kappa) (rcp_neighbor_build
+ * or an rcp_energy_dev call at nearby positions builds one); RCP_ESTATE
+ * otherwise, RCP_EINVAL for more than 2^24 spheres, a null pointer or a bad
+ * kappa or mu.  The array keeps the last call's contents and is shared by
+ * every call on that GPU, whatever the context: calls that overlap on one
+ * GPU (several threads or streams) race, and the caller must serialise them.
+ * The call synchronises the context's stream and `stream` (the validity test
+ * reads one number back). */
+int rcp_energy_dev_static(rcp_ctx *ctx, const double *x_dev, double kappa, double mu,
+                          double *E_dev, void *stream);
+
 /* Kernel timing of the running schedule: like rcp_run_continue(ctx,
  * n_iters) but each iteration is launched on its own, with HIP events
  * recorded on the context's stream around the gradient + Adam kernel and

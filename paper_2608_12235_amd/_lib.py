@@ -113,6 +113,7 @@ SIGNATURES = {
     "rcp_shrink": (C.c_int, [vp, C.c_int, dp, dp]),
     "rcp_energy_dev": (C.c_int, [vp, vp, C.c_double, C.c_double, vp, vp]),
     "rcp_adjoint_dev": (C.c_int, [vp, vp, C.c_double, C.c_double, vp, vp, vp]),
+    "rcp_energy_dev_static": (C.c_int, [vp, vp, C.c_double, C.c_double, vp, vp]),
     "rcp_time_iterations": (C.c_int, [vp, C.c_int64, dp, dp, i64p]),
     "rcp_get_stats": (C.c_int, [vp, C.POINTER(Stats)]),
     "rcp_reset_stats": (C.c_int, [vp]),

@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -189,6 +190,7 @@ struct rcp_ctx {
     // returned to the pool) at the next point where the stream is idle
     std::vector<std::pair<hipEvent_t, hipEvent_t>> rb_pending, rb_pool;
     rcp_stats stats{};
+    double *scratch = nullptr;       // this GPU's fixed scratch array (see below)
 };
 
 static void ptrs_of(const Seg &s, SegPtrs &p)
@@ -245,6 +247,34 @@ static int put_field(rcp_ctx *c, int k, size_t offset, const T &v)
     HIPCHK(hipMemcpyAsync((char *)(c->d_state + k) + offset, &v, sizeof(T),
                           hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    return RCP_OK;
+}
+
+// ------------------------------------------- fixed scratch (no allocation)
+// Block partials and small results of rcp_energy_dev_static: a device array
+// of this module, one copy per GPU, held until the process ends.  Its name
+// is a host-side stand-in; the device address is looked up once per GPU.
+constexpr int64_t kScratchBlocks = (int64_t)1 << 16;        // n <= 2^24 spheres
+constexpr int64_t kScratchWords = 4 * kScratchBlocks + 64;  // 2 MiB + results
+static __device__ __align__(256) double scratch[kScratchWords];
+
+static std::mutex g_scratch_mu;
+static std::vector<double *> g_scratch_addr;   // per device index
+
+// Device address of the current GPU's scratch array (hipGetSymbolAddress on
+// the first call for that device, with it current).
+static int scratch_address(double **out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_addr.size() <= dev) g_scratch_addr.resize(dev + 1, nullptr);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_addr[dev] = (double *)p;
+    }
+    *out = g_scratch_addr[dev];
     return RCP_OK;
 }
 
@@ -1384,6 +1414,7 @@ int rcp_census_init(int dim, int n_prob, const int64_t *n, const double *const *
             rc = fail(RCP_EDEVICE, "hipEventCreate: %s", hipGetErrorString(e));
             break;
         }
+        if ((rc = scratch_address(&c->scratch)) != RCP_OK) break;
         if ((rc = dalloc(&c->d_ptrs, n_prob)) != RCP_OK) break;
         if ((rc = dalloc(&c->d_state, n_prob)) != RCP_OK) break;
         if ((rc = dalloc(&c->totals, 16)) != RCP_OK) break;
@@ -1922,6 +1953,51 @@ int rcp_adjoint_dev(rcp_ctx *c, const double *x_dev, double kappa, double mu, do
     CHK(ensure_valid_at(c, x_dev, kappa, st));
     CHK(eval_current(c, 0, x_dev, kappa, mu, gx_dev, st));
     hipLaunchKernelGGL(k_gk_out, dim3(1), dim3(1), 0, st, c->out, gk_dev);
+    HIPCHK(hipGetLastError());
+    return RCP_OK;
+}
+
+int rcp_energy_dev_static(rcp_ctx *c, const double *x_dev, double kappa, double mu,
+                          double *E_dev, void *stream)
+{
+    if (!c || !x_dev || !E_dev) return fail(RCP_EINVAL, "null argument");
+    if (!(kappa > 0) || !std::isfinite(kappa) || !std::isfinite(mu))
+        return fail(RCP_EINVAL, "bad kappa or mu");
+    const Seg &s = c->segs[0];
+    const int64_t nb = std::max<int64_t>(1, (s.n + kBlock - 1) / kBlock);
+    if (nb > kScratchBlocks)
+        return fail(RCP_EINVAL,
+                    "rcp_energy_dev_static: n = %lld exceeds the fixed scratch (at most %lld "
+                    "spheres)",
+                    (long long)s.n, (long long)(kScratchBlocks * kBlock));
+    if (!c->scratch) return fail(RCP_ESTATE, "no scratch address for this context");
+    hipStream_t st = (hipStream_t)stream;   // NULL: the null stream
+    if (st != c->stream) HIPCHK(hipStreamSynchronize(c->stream));
+    // the context's record, read without touching any growable host list
+    HIPCHK(hipMemcpyAsync(c->h_state, c->d_state, sizeof(SegState) * c->segs.size(),
+                          hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    const SegState &h = c->h_state[0];
+    if (!s.built || (h.flags & (F_REBUILD | F_STALE)))
+        return fail(RCP_ESTATE, "rcp_energy_dev_static: packing 0 has no valid neighbour list");
+    double *part = c->scratch, *res = c->scratch + 4 * kScratchBlocks;
+    // the validity test of the iteration tail at (x_dev, kappa)
+    launch_disp(c->d_ptrs, c->d_state, 0, s.n, x_dev, part, (int)nb, st);
+    launch_max_finish(part, (int)nb, res, st);
+    HIPCHK(hipMemcpyAsync(c->h_out, res, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const double d2 = c->h_out[0];
+    const double excess = std::max(0.0, kappa - h.kappa_lim);
+    if (!(2.0 * std::sqrt(d2) + excess * h.d0max_k <= 2.0 * h.disp_lim))
+        return fail(RCP_ESTATE,
+                    "rcp_energy_dev_static: the neighbour list is not valid at these positions "
+                    "and kappa (rebuild it with rcp_neighbor_build or rcp_energy_dev)");
+    EvalOut o;
+    o.part = part;
+    o.gu = nullptr;
+    launch_eval(c->d_ptrs, c->d_state, 0, s.n, x_dev, kappa, o, (int)nb, st);
+    launch_eval_finish(part, (int)nb, kappa, mu, c->d_state, 0, res + 8, st);
+    hipLaunchKernelGGL(k_energy_out, dim3(1), dim3(1), 0, st, res + 8, E_dev);
     HIPCHK(hipGetLastError());
     return RCP_OK;
 }
