@@ -249,6 +249,39 @@ def run_c5(torch, args):
     print(json.dumps(out), flush=True)
 
 
+def run_placement(torch, args):
+    """Initial placement of the extreme size-ratio packing (lognormal
+    sigma_lnD = 2.5, S = 5e5, N = 3e6, phi0 = 0.05): random sequential
+    addition on the host (RCP_INIT_RSA) against the rounds on the GPU
+    (rcp_place_device, window RCP_PLACE_WINDOW).  Each time is the context
+    creation with that placement minus the creation without placement."""
+    import rcp_inputs as ri
+    import paper_2608_12235_amd as rcp
+    n = 3_000_000 if args.n == 1_000_000 else args.n
+    w = ri.c5_extreme(n=n)
+    out = {}
+    for label in ("none", "rsa", "device"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if label == "device":
+            p = rcp.Packing(w.d0, w.L, 1.0, w.seed, init="none")
+            rounds = p.place_device(w.seed, rcp._lib.RCP_PLACE_WINDOW)
+        else:
+            p = rcp.Packing(w.d0, w.L, 1.0, w.seed, init=label)
+        torch.cuda.synchronize()
+        out[label] = time.perf_counter() - t0
+        log("%s: %.3f s" % (label, out[label]))
+        p.close()
+    res = {"metric": "initial placement time", "value": out["device"] - out["none"], "unit": "s",
+           "higher_is_better": False,
+           "config": {"workload": "lognormal sigma_lnD=2.5 S=5e5 N=%d at phi0=0.05" % n,
+                      "host_rsa_s": out["rsa"] - out["none"],
+                      "device_rounds_s": out["device"] - out["none"],
+                      "device_rounds": rounds, "window": rcp._lib.RCP_PLACE_WINDOW,
+                      "context_without_placement_s": out["none"]}}
+    print(json.dumps(res), flush=True)
+
+
 # ------------------------------------------------------------ secondary legs
 def leg_c2(torch, args):
     """Power law p = -3 on [1, 20], N = 1e5, RSA at phi0 = 0.05, seed 0, the
@@ -310,23 +343,29 @@ def leg_census(torch, args):
     ntot = sum(w.n for w in wl)
     res_b, tb, st = census.run_batched(wl)
     res_l, tl = census.run_loop(wl)
+    import tempfile
+    with tempfile.TemporaryDirectory() as td:
+        res_a, ta, info = census.run_autotuned(wl, cache=os.path.join(td, "cache.json"))
     phib = np.array([r["phi"] for r in res_b])
     phil = np.array([r["phi"] for r in res_l])
+    phia = np.array([r["phi"] for r in res_a])
     ub = census.particle_updates(res_b, wl)
     return {"workload": "census of 64 packings (lognormal / power law / Weibull, S 2..100, "
                         "N 1e3..2e5, sum N %d), whole runs" % ntot,
             "value": ub / tb, "unit": "particle-updates/s",
             "batched_s": tb, "loop_s": tl, "speedup_batched": tl / tb,
             "loop_value": census.particle_updates(res_l, wl) / tl,
+            "autotuned_s": ta, "speedup_autotuned": tl / ta,
+            "autotune_proxy_tuning_s": info["tuning_s"], "autotune_choice": info["best"],
             "bit_identical_batched_vs_loop": bool(np.array_equal(phib, phil)),
-            "mean_phi": float(phib.mean()),
+            "mean_phi": float(phib.mean()), "mean_phi_autotuned": float(phia.mean()),
             "statuses": sorted(set(int(r["status"]) for r in res_b)),
             "rebuilds": st["rebuilds"], "rebuild_ms": st["rebuild_ms"]}
 
 
 LEGS = {"c2": leg_c2, "rsa": leg_rsa, "census": leg_census}
 LEG_KEYS = {"c2": "c2_whole_run", "rsa": "rsa_start_window", "census": "census"}
-LEG_TIMEOUT = {"c2": 300, "rsa": 300, "census": 600}
+LEG_TIMEOUT = {"c2": 300, "rsa": 300, "census": 900}
 
 
 def run_legs(names):
@@ -374,12 +413,22 @@ def run_primary(torch, args):
     sched = rcp.schedule_from_rungs(
         [(ds.mu[r], ds.eta_x[r], ds.eta_k[r], 1.0, args.warmup + args.steps + 1)], tol=-1.0)
     log("primary: %s, kappa 1, skin %g D0_min" % (w.name, skin))
+    # unless a graph length is asked for, the warmup runs as one graph of
+    # `warmup` iterations and the timed region as one graph of `steps`
+    # iterations, captured before the clock starts: every launch does work
+    graph_fixed = args.graph_iters is not None
+    if not graph_fixed and 1 <= args.warmup <= 4096:
+        tun.graph_iters = args.warmup
     p = rcp.Packing(d0, L, 1.0, 0, init="none", params=params, tuning=tun)
     p.set_state(w.x, 1.0)
     p.run_start(sched)
     log("warmup %d iterations" % args.warmup)
     if args.warmup:
         p.run_continue(args.warmup)
+    if not graph_fixed:
+        tun.graph_iters = min(args.steps, 4096) if args.steps <= 4096 else 32
+        p.set_tuning(tun)
+        p.run_prepare()
     torch.cuda.synchronize()
     p.reset_stats()
     log("timed %d iterations" % args.steps)
@@ -476,9 +525,10 @@ def main():
     ap.add_argument("--kernel-timing", type=int, default=2, choices=(0, 1, 2),
                     help="HIP events around 0: no launch (no roofline entry), 1: the middle "
                          "launch of every graph, 2: every launch")
-    ap.add_argument("--workload", default="c3", choices=("c3", "c5"),
+    ap.add_argument("--workload", default="c3", choices=("c3", "c5", "placement"),
                     help="c3: the default line; c5: lognormal sigma_lnD=2.5, S=5e5, N=3e6 run "
-                         "to the stop criterion")
+                         "to the stop criterion; placement: that packing's initial placement "
+                         "on the host against the GPU")
     ap.add_argument("--builds", type=int, default=0, metavar="K",
                     help="only time K neighbour-list builds of the RSA-start lognormal (or c5) "
                          "workload after --warmup iterations and exit")
@@ -515,6 +565,9 @@ def main():
         return
     if args.workload == "c5":
         run_c5(torch, args)
+        return
+    if args.workload == "placement":
+        run_placement(torch, args)
         return
     out, cpu_state = run_primary(torch, args)
     out.update(legs)

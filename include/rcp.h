@@ -60,6 +60,9 @@ extern "C" {
 #define RCP_INIT_RSA 1      /* random sequential addition without overlap, largest
                                sphere first (App. A: dilute, non-overlapping start) */
 #define RCP_INIT_UNIFORM 2  /* i.i.d. uniform positions, overlaps allowed         */
+#define RCP_INIT_RSA_DEVICE 3  /* random sequential addition on the GPU, in rounds
+                                  of RCP_PLACE_WINDOW proposals (rcp_place_device) */
+#define RCP_PLACE_WINDOW 65536
 
 typedef struct rcp_ctx rcp_ctx;
 
@@ -206,7 +209,7 @@ const char *rcp_last_error(void);
 void rcp_params_default(rcp_params *p);
 /* Defaults: graph_iters 32, xcd_remap 1, fused_tail 0, variant 192 (the
  * cooperative pair search, the two-gather gradient + Adam kernel writing
- * whole records), row_cost 10, item_work 2560, time_kernels 0. */
+ * whole records), row_cost 8, item_work 2048, time_kernels 0. */
 void rcp_tuning_default(rcp_tuning *t);
 
 /* Default rung table for a packing of n spheres in dimension dim with size
@@ -249,6 +252,25 @@ int rcp_census_init(int dim, int n_prob, const int64_t *n,
 int rcp_pack_init(int dim, const double *box, int64_t n, const double *d0,
                   double kappa0, uint64_t seed, int init_mode,
                   const rcp_params *params, void *stream, rcp_ctx **out);
+
+/* Random sequential addition of packing k on the GPU, at its current kappa
+ * (App. A: the run starts from a dilute configuration placed without
+ * overlap with the help of a cell list; the procedure is our reading).
+ * Spheres are ranked largest first (ties: lower index first) and placed
+ * class by class, largest class first (class floor(log2(D0 / D0_min))).  A
+ * round takes the ranks [lo, min(lo + window, end of the class)), lo the
+ * lowest rank of the class not yet placed; each unplaced sphere i of the
+ * round proposes attempt a_i of the SplitMix64 stream of rcp_pack_init,
+ * (u(seed, i, a_i, axis) L); a proposal is valid when it overlaps no placed
+ * sphere (r^2 < (kappa (D0_i + D0_j)/2)^2, minimum image, no contraction),
+ * and a valid proposal is placed unless a valid proposal of a lower rank in
+ * the same round overlaps it; the others move on to their next attempt.
+ * With window = 1 this is the host placement of RCP_INIT_RSA attempt for
+ * attempt.  The positions replace the packing's state as rcp_set_state
+ * does.  rounds (may be NULL) receives the number of rounds.  RCP_EINVAL for
+ * window < 1 or more than 64 size classes, RCP_EPLACE when a sphere needs
+ * more than 2^22 attempts. */
+int rcp_place_device(rcp_ctx *ctx, int k, uint64_t seed, int64_t window, int64_t *rounds);
 
 /* Replace the launch tuning (see rcp_tuning); RCP_EINVAL for values out of
  * range.  A captured graph is re-captured at the next iteration.  Tuning
@@ -368,6 +390,13 @@ int rcp_inflate_run(rcp_ctx *ctx, const rcp_schedule *sched, int per_packing,
  * (shrink included) without changing that state. */
 int rcp_run_start(rcp_ctx *ctx, const rcp_schedule *sched, int per_packing);
 int rcp_run_continue(rcp_ctx *ctx, int64_t n_iters, int32_t *active);
+
+/* Capture the HIP graph of graph_iters iterations (App. A's iteration, as
+ * rcp_run_continue launches it) ahead of the next rcp_run_continue, which
+ * then does not pay for the capture.  The graph stays valid until the
+ * tuning or the work-item layout changes (a list build that changes the
+ * number of work items); nothing is launched.  No-op for graph_iters 1. */
+int rcp_run_prepare(rcp_ctx *ctx);
 int rcp_run_result(rcp_ctx *ctx, int k, rcp_result *result);
 
 /* Census entry point (Sec. 3 generates its census of packings one run at a

@@ -10,7 +10,7 @@ from .oracle import (build, lib, splitmix64, u01, pairs_brute, pairs_cells,
                      run, Params, Schedule, n_trig, default_schedule,
                      time_iterations, set_threads, num_threads, RunState,
                      default_params, absolute_schedule, Result, set_list_check,
-                     list_misses)
+                     list_misses, rsa_rounds)
 from . import oracle
 
 __all__ = [
@@ -18,4 +18,5 @@ __all__ = [
     "rows_pairs", "energy_grad", "rows_grad", "shrink", "phi", "rsa", "run",
     "Params", "Schedule", "n_trig", "default_schedule", "time_iterations",
     "set_threads", "num_threads", "RunState", "set_list_check", "list_misses",
+    "rsa_rounds",
 ]

@@ -64,6 +64,9 @@ def lib():
         L.orc_rsa.restype = C.c_int
         L.orc_rsa.argtypes = [C.c_int64, dp, C.c_double, C.c_double, C.c_uint64,
                               C.c_int64, dp]
+        L.orc_rsa_rounds.restype = C.c_int
+        L.orc_rsa_rounds.argtypes = [C.c_int64, dp, C.c_double, C.c_double, C.c_uint64,
+                                     C.c_int64, C.c_int64, dp, lp]
         L.orc_run.restype = C.c_int
         L.orc_run.argtypes = [C.c_int64, dp, dp, C.c_double, dp, dp, dp, dp, lp,
                               dp, C.POINTER(Params), C.POINTER(Schedule),
@@ -250,6 +253,19 @@ def rsa(d0, L, kappa0, seed, max_attempts=1 << 20):
     if rc != 0:
         raise RuntimeError("RSA failed: a sphere exceeded %d attempts" % max_attempts)
     return x
+
+
+def rsa_rounds(d0, L, kappa0, seed, window, max_attempts=1 << 20):
+    """Random sequential addition in rounds of up to `window` proposals
+    (see orc_rsa_rounds); returns ((n, 3) positions, number of rounds)."""
+    d0 = _vec(d0)
+    x = np.zeros((d0.shape[0], 3))
+    nr = np.zeros(1, np.int64)
+    rc = lib().orc_rsa_rounds(d0.shape[0], _d(d0), L, kappa0, seed, int(window),
+                              int(max_attempts), _d(x), _l(nr))
+    if rc != 0:
+        raise RuntimeError("RSA in rounds failed: a sphere exceeded %d attempts" % max_attempts)
+    return x, int(nr[0])
 
 
 def n_trig(N, d=3, Y=2, X=9):

@@ -585,6 +585,129 @@ int orc_rsa(int64_t n, const double *d0, double L, double kappa0, uint64_t seed,
 }
 
 /* ------------------------------------------------------------------ */
+/* Random sequential addition in rounds (App. A: dilute start without  */
+/* overlap, placed with the help of a cell list)                       */
+/* ------------------------------------------------------------------ */
+/* The sequential procedure above tries one sphere at a time.  This one
+ * tries up to W spheres at a time, the same proposals in the same order of
+ * attempts, so that a parallel machine can place them in rounds:
+ *   - spheres are ranked largest first (ties: lower index first) and binned
+ *     in size classes floor(log2(D0 / D0_min)); classes are placed from the
+ *     largest down, so a sphere only meets spheres of its own class or
+ *     larger ones;
+ *   - a round takes the window of ranks [lo, min(lo + W, end of the class)),
+ *     lo the lowest rank of the class not yet placed; every unplaced sphere
+ *     i of the window proposes the position of its next attempt a_i,
+ *     (u(seed, i, a_i, 0) L, u(seed, i, a_i, 1) L, u(seed, i, a_i, 2) L);
+ *   - a proposal is valid when it overlaps no placed sphere (r^2 < dd^2,
+ *     dd = kappa0 (D0_i + D0_j) / 2, separation x_j - p_i, minimum image);
+ *   - a valid proposal is accepted unless a valid proposal of a lower rank
+ *     in the same round overlaps it (separation p_j - p_i);
+ *   - accepted spheres are placed; every other sphere of the window that
+ *     proposed moves on to its next attempt (more than max_attempts: -1).
+ * No two accepted proposals overlap (of two overlapping valid proposals the
+ * higher rank is rejected), and with W = 1 a round holds a single proposal,
+ * so the procedure is the sequential one, attempt for attempt.  Returns 0
+ * (rounds in *rounds) or -1.  Brute force over the placed spheres of the
+ * current class and larger: for test sizes only. */
+int orc_rsa_rounds(int64_t n, const double *d0, double L, double kappa0, uint64_t seed,
+                   int64_t window, int64_t max_attempts, double *x, int64_t *rounds)
+{
+    const double hL = 0.5 * L;
+    ord_t *ord = malloc(sizeof(ord_t) * (size_t)n);
+    double d0min = d0[0];
+    for (int64_t i = 0; i < n; ++i) {
+        ord[i].d = d0[i]; ord[i].i = i;
+        if (d0[i] < d0min) d0min = d0[i];
+    }
+    qsort(ord, (size_t)n, sizeof(ord_t), cmp_ord);
+    int *cls = malloc(sizeof(int) * (size_t)n);      /* by rank */
+    for (int64_t k = 0; k < n; ++k) {
+        int e;
+        frexp(ord[k].d / d0min, &e);                    /* ratio in [2^(e-1), 2^e) */
+        cls[k] = e - 1 > 0 ? e - 1 : 0;
+    }
+    int64_t *att = calloc((size_t)n, sizeof(int64_t));
+    unsigned char *placed = calloc((size_t)n, 1);
+    int64_t *placed_list = malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int64_t nplaced = 0;
+    double *prop = malloc(sizeof(double) * 3 * (size_t)(window > 0 ? window : 1));
+    unsigned char *valid = malloc((size_t)(window > 0 ? window : 1));
+    unsigned char *acc = malloc((size_t)(window > 0 ? window : 1));
+    int64_t nround = 0;
+    int rc = 0;
+    int64_t cb = 0;
+    while (cb < n && rc == 0) {
+        int64_t ce = cb;
+        while (ce < n && cls[ce] == cls[cb]) ++ce;       /* class ranks [cb, ce) */
+        int64_t lo = cb;
+        while (lo < ce && rc == 0) {
+            int64_t hi = lo + window < ce ? lo + window : ce;
+            ++nround;
+            /* proposals and their validity against the placed spheres */
+            for (int64_t k = lo; k < hi; ++k) {
+                int64_t s = k - lo, i = ord[k].i;
+                valid[s] = 0;
+                if (placed[k]) continue;
+                double *p = prop + 3 * s;
+                for (int ax = 0; ax < 3; ++ax) {
+                    p[ax] = orc_u01(seed, (uint64_t)i, (uint64_t)att[k], ax) * L;
+                    if (p[ax] >= L) p[ax] -= L;
+                }
+                int ok = 1;
+                for (int64_t q = 0; q < nplaced && ok; ++q) {
+                    int64_t j = placed_list[q];
+                    double dx = mimg(x[3 * j] - p[0], L, hL);
+                    double dy = mimg(x[3 * j + 1] - p[1], L, hL);
+                    double dz = mimg(x[3 * j + 2] - p[2], L, hL);
+                    double r2 = (dx * dx + dy * dy) + dz * dz;
+                    double dd = kappa0 * (0.5 * (d0[i] + d0[j]));
+                    if (r2 < dd * dd) ok = 0;
+                }
+                valid[s] = (unsigned char)ok;
+            }
+            /* conflicts among the valid proposals: the lower rank wins */
+            for (int64_t k = lo; k < hi; ++k) {
+                int64_t s = k - lo, i = ord[k].i;
+                acc[s] = 0;
+                if (placed[k] || !valid[s]) continue;
+                int ok = 1;
+                for (int64_t k2 = lo; k2 < k && ok; ++k2) {
+                    int64_t s2 = k2 - lo, j = ord[k2].i;
+                    if (placed[k2] || !valid[s2]) continue;
+                    const double *pi_ = prop + 3 * s, *pj_ = prop + 3 * s2;
+                    double dx = mimg(pj_[0] - pi_[0], L, hL);
+                    double dy = mimg(pj_[1] - pi_[1], L, hL);
+                    double dz = mimg(pj_[2] - pi_[2], L, hL);
+                    double r2 = (dx * dx + dy * dy) + dz * dz;
+                    double dd = kappa0 * (0.5 * (d0[i] + d0[j]));
+                    if (r2 < dd * dd) ok = 0;
+                }
+                acc[s] = (unsigned char)ok;
+            }
+            /* placements and next attempts take effect at the end of the round */
+            for (int64_t k = lo; k < hi; ++k) {
+                int64_t s = k - lo, i = ord[k].i;
+                if (placed[k]) continue;
+                if (acc[s]) {
+                    for (int ax = 0; ax < 3; ++ax) x[3 * i + ax] = prop[3 * s + ax];
+                    placed[k] = 1;
+                    placed_list[nplaced++] = i;
+                } else if (++att[k] >= max_attempts) {
+                    rc = -1;
+                }
+            }
+            while (lo < ce && placed[lo]) ++lo;
+        }
+        cb = ce;
+    }
+    if (rounds) *rounds = nround;
+    free(ord); free(cls); free(att); free(placed); free(placed_list); free(prop); free(valid);
+    free(acc);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
 /* Schedule, Adam and the whole inflation run (App. A)                 */
 /* ------------------------------------------------------------------ */
 typedef struct {

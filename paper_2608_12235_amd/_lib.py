@@ -12,7 +12,8 @@ MAX_RUNGS = 16
 
 RCP_OK, RCP_EINVAL, RCP_EBOX, RCP_ENOMEM, RCP_EDEVICE = 0, -1, -2, -3, -4
 RCP_ENOTCONV, RCP_ENONFINITE, RCP_EPLACE, RCP_ESTATE = -5, -6, -7, -8
-RCP_INIT_NONE, RCP_INIT_RSA, RCP_INIT_UNIFORM = 0, 1, 2
+RCP_INIT_NONE, RCP_INIT_RSA, RCP_INIT_UNIFORM, RCP_INIT_RSA_DEVICE = 0, 1, 2, 3
+RCP_PLACE_WINDOW = 65536
 
 ERRNAMES = {0: "RCP_OK", -1: "RCP_EINVAL", -2: "RCP_EBOX", -3: "RCP_ENOMEM",
             -4: "RCP_EDEVICE", -5: "RCP_ENOTCONV", -6: "RCP_ENONFINITE",
@@ -99,6 +100,7 @@ SIGNATURES = {
     "rcp_get_state": (C.c_int, [vp, C.c_int, dp, dp, dp]),
     "rcp_get_optimizer": (C.c_int, [vp, C.c_int, dp, dp, C.POINTER(Optimizer)]),
     "rcp_set_optimizer": (C.c_int, [vp, C.c_int, dp, dp, C.POINTER(Optimizer)]),
+    "rcp_place_device": (C.c_int, [vp, C.c_int, C.c_uint64, C.c_int64, i64p]),
     "rcp_neighbor_build": (C.c_int, [vp, C.c_int, i64p]),
     "rcp_get_pairs": (C.c_int, [vp, C.c_int, i32p, i32p, C.c_int64, i64p]),
     "rcp_energy_grad": (C.c_int, [vp, C.c_int, C.c_double, C.POINTER(Energy), dp]),
@@ -109,6 +111,7 @@ SIGNATURES = {
                                  C.POINTER(Result)]),
     "rcp_run_start": (C.c_int, [vp, C.POINTER(Schedule), C.c_int]),
     "rcp_run_continue": (C.c_int, [vp, C.c_int64, i32p]),
+    "rcp_run_prepare": (C.c_int, [vp]),
     "rcp_run_result": (C.c_int, [vp, C.c_int, C.POINTER(Result)]),
     "rcp_shrink": (C.c_int, [vp, C.c_int, dp, dp]),
     "rcp_energy_dev": (C.c_int, [vp, vp, C.c_double, C.c_double, vp, vp]),

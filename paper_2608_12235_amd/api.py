@@ -4,9 +4,10 @@ import ctypes as C
 import numpy as np
 
 from ._lib import (lib, check, Params, Tuning, Schedule, Energy, Result, Stats, Optimizer,
-                   RCP_INIT_NONE, RCP_INIT_RSA, RCP_INIT_UNIFORM, RcpError)
+                   RCP_INIT_NONE, RCP_INIT_RSA, RCP_INIT_UNIFORM, RCP_INIT_RSA_DEVICE, RcpError)
 
-_INIT = {"none": RCP_INIT_NONE, "rsa": RCP_INIT_RSA, "uniform": RCP_INIT_UNIFORM}
+_INIT = {"none": RCP_INIT_NONE, "rsa": RCP_INIT_RSA, "uniform": RCP_INIT_UNIFORM,
+         "rsa_device": RCP_INIT_RSA_DEVICE}
 
 
 def _dp(a):
@@ -153,6 +154,13 @@ class Packing:
         check(lib().rcp_set_optimizer(self._h, k, _dp(mm) if mm is not None else None,
                                       _dp(vv) if vv is not None else None, C.byref(o)))
 
+    def place_device(self, seed, window, k=0):
+        """Random sequential addition of packing k on the GPU in rounds of
+        up to `window` proposals; returns the number of rounds."""
+        r = C.c_int64()
+        check(lib().rcp_place_device(self._h, k, int(seed), int(window), C.byref(r)))
+        return r.value
+
     def neighbor_build(self, k=0):
         npairs = C.c_int64()
         check(lib().rcp_neighbor_build(self._h, k, C.byref(npairs)))
@@ -214,6 +222,10 @@ class Packing:
         act = C.c_int32()
         check(lib().rcp_run_continue(self._h, int(n_iters), C.byref(act)))
         return act.value
+
+    def run_prepare(self):
+        """Capture the iteration graph ahead of the next run_continue."""
+        check(lib().rcp_run_prepare(self._h))
 
     def run_result(self, k=0):
         r = Result()

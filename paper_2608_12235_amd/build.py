@@ -22,8 +22,9 @@ ARCH = os.environ.get("RCP_OFFLOAD_ARCH", "gfx950")
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-function", "-I", INC, "-I", CSRC]
-NO_CONTRACT = {"k_neighbor.hip", "k_shrink.hip", "placement.cpp"}
-SOURCES = ["k_sort.hip", "k_neighbor.hip", "k_iterate.hip", "k_shrink.hip",
+HIP_FLAGS += os.environ.get("RCP_EXTRA_HIPFLAGS", "").split()
+NO_CONTRACT = {"k_neighbor.hip", "k_shrink.hip", "k_place.hip", "placement.cpp"}
+SOURCES = ["k_sort.hip", "k_neighbor.hip", "k_iterate.hip", "k_shrink.hip", "k_place.hip",
            "rcp_runtime.cpp", "placement.cpp"]
 
 

@@ -77,26 +77,23 @@ def particle_updates(results, workloads):
     return float(sum(r["iterations"] * w.n for r, w in zip(results, workloads)))
 
 
-def run_autotuned(workloads, params=None, warmup=1000, trial_iters=200, log=None):
-    """One context for all workloads: warm-up iterations, autotuner trials
-    (which continue the run), then the rest of the run.  Returns (results,
-    seconds of the whole run including the trials, chosen settings)."""
+def run_autotuned(workloads, params=None, cache=None, log=None):
+    """The batched census with the launch settings the autotuner chose for
+    this kind of workload (taken from its cache, or found on a proxy of the
+    largest workloads and stored there, see autotune.cached).  Returns
+    (results, seconds of the census run, info: settings, cache hit, seconds
+    spent tuning)."""
     from . import autotune
     params = params if params is not None else make_params()
-    p = Packing([w.d0 for w in workloads], [w.L for w in workloads], 1.0,
-                [w.seed for w in workloads], init="rsa", params=params, tuning=census_tuning())
-    try:
-        _sync()
-        t0 = time.perf_counter()
-        p.run_start(None)
-        if warmup:
-            p.run_continue(warmup)
-        best, trials = autotune.tune(p, trial_iters=trial_iters, log=log)
-        p.run_continue(0)
-        _sync()
-        res = [p.run_result(k) for k in range(p.n_packings)]
-        _sync()
-        dt = time.perf_counter() - t0
-        return res, dt, {"best": best, "trials": trials}
-    finally:
-        p.close()
+    best, hit, t_tune = autotune.cached(workloads, path=cache, params=params,
+                                        tuning=census_tuning(), log=log)
+    p2 = make_params()
+    for f, _ in params._fields_:
+        setattr(p2, f, getattr(params, f))
+    p2.skin_s = best["skin_s"]
+    tun = census_tuning()
+    tun.variant = best["variant"]
+    tun.row_cost, tun.item_work = best["row_cost"], best["item_work"]
+    tun.graph_iters = best["graph_iters"]
+    res, dt, st = run_batched(workloads, params=p2, tuning=tun)
+    return res, dt, {"best": best, "cache_hit": hit, "tuning_s": t_tune, "stats": st}

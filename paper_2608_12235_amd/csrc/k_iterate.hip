@@ -45,26 +45,36 @@ __device__ __forceinline__ double near_image(double d, double L, double iL)
 }
 
 // Reciprocal and reciprocal square root from the hardware estimates
-// (v_rcp_f64, v_rsq_f64), each refined by two Newton steps: within two
-// units in the last place of the correctly rounded values for normal
-// positive arguments, at a third of the cost of an IEEE division or root.
+// (v_rcp_f64, v_rsq_f64), refined by kSteps Newton steps (each doubles the
+// correct bits of the estimate): a few units in the last place after one,
+// within two after two, at a fraction of the cost of an IEEE division or
+// root.
+#ifndef RCP_NEWTON_STEPS
+#define RCP_NEWTON_STEPS 1
+#endif
+template <int kSteps = RCP_NEWTON_STEPS>
 __device__ __forceinline__ double fast_rcp(double d)
 {
     double y = __builtin_amdgcn_rcp(d);
-    double e = fma(-d, y, 1.0);
-    y = fma(y, e, y);
-    e = fma(-d, y, 1.0);
-    return fma(y, e, y);
+#pragma unroll
+    for (int k = 0; k < kSteps; ++k) {
+        const double e = fma(-d, y, 1.0);
+        y = fma(y, e, y);
+    }
+    return y;
 }
 
+template <int kSteps = RCP_NEWTON_STEPS>
 __device__ __forceinline__ double fast_rsq(double x)
 {
     double y = __builtin_amdgcn_rsq(x);
     const double h = 0.5 * x;
-    double t = fma(-(h * y), y, 0.5);
-    y = fma(y, t, y);
-    t = fma(-(h * y), y, 0.5);
-    return fma(y, t, y);
+#pragma unroll
+    for (int k = 0; k < kSteps; ++k) {
+        const double t = fma(-(h * y), y, 0.5);
+        y = fma(y, t, y);
+    }
+    return y;
 }
 
 // Squared distances below this use the IEEE root (the estimates lose range
@@ -323,15 +333,16 @@ struct alignas(32) Part4 {
 // kT threads (fixed assignment of partials to threads, fixed combining
 // order); thread 0 then runs the tail.  Every thread of the block must call
 // it.
-// A block partial read past the caches (system-scope relaxed atomic loads):
-// used when the partials were written in the same kernel by other XCDs.
+// A block partial read at the device's coherence point (agent-scope relaxed
+// atomic loads, which bypass the reading XCD's L2): used when the partials
+// were written in the same kernel by other XCDs (with agent-scope stores).
 __device__ __forceinline__ Part4 load_part_coherent(const Part4 *p)
 {
     Part4 r;
-    r.e = __hip_atomic_load(&p->e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    r.s = __hip_atomic_load(&p->s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    r.m = __hip_atomic_load(&p->m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    r.d = __hip_atomic_load(&p->d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    r.e = __hip_atomic_load(&p->e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    r.s = __hip_atomic_load(&p->s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    r.m = __hip_atomic_load(&p->m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    r.d = __hip_atomic_load(&p->d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return r;
 }
 
@@ -407,41 +418,53 @@ __device__ void reduce_and_tail(SegState *s, const double *partials)
 // (entries past the stage are read from global memory).
 constexpr int kColStage = 2048;
 
+#ifndef RCP_ITEM_PREFETCH
+#define RCP_ITEM_PREFETCH 1
+#endif
+
+// Where a thread's partner indices come from: the LDS stage (kStage), else
+// global memory, with the first two entries of the thread's chunk [cs, ..)
+// already in registers (requested together with the row pointers, so the
+// first gathers need no second dependent load).
 template <bool kStage>
-__device__ __forceinline__ int32_t col_at(const int32_t *__restrict__ col,
-                                          const int32_t *__restrict__ scol, int32_t q,
-                                          int32_t e0)
-{
-    if (kStage) {
-        const int32_t k = q - e0;
-        return k < kColStage ? scol[k] : gload(col, q);
+struct ColSrc {
+    const int32_t *__restrict__ col;
+    const int32_t *__restrict__ scol;
+    int32_t e0, cs, j0, j1;
+    __device__ __forceinline__ int32_t at(int32_t q) const
+    {
+        if (kStage) {
+            const int32_t k = q - e0;
+            return k < kColStage ? scol[k] : gload(col, q);
+        }
+        if (RCP_ITEM_PREFETCH && q == cs) return j0;
+        if (RCP_ITEM_PREFETCH && q == cs + 1) return j1;
+        return gload(col, q);
     }
-    return gload(col, q);
-}
+};
 
 // Entry loop of one row segment [q, qe): kU partners per step so that
 // their gathers are in flight together (kU = 2 or 4); the next step's
 // partner indices are requested before this step's terms are evaluated, so
 // their latency hides behind the arithmetic.
 template <int kU, bool kStage>
-__device__ __forceinline__ void segment_terms(Acc &a, const int32_t *__restrict__ col,
-                                              const int32_t *__restrict__ scol, int32_t e0,
+__device__ __forceinline__ void segment_terms(Acc &a, const ColSrc<kStage> &cols,
                                               const P4 *__restrict__ Q, int32_t q, int32_t qe,
                                               const P4 &qi, const IterScalars &c)
 {
     if (kU == 4 && q + 4 <= qe) {
-        int32_t j0 = col_at<kStage>(col, scol, q, e0), j1 = col_at<kStage>(col, scol, q + 1, e0),
-                j2 = col_at<kStage>(col, scol, q + 2, e0), j3 = col_at<kStage>(col, scol, q + 3, e0);
+        int32_t j0 = cols.at(q), j1 = cols.at(q + 1),
+                j2 = cols.at(q + 2), j3 = cols.at(q + 3);
         for (;;) {
             const P4 q0 = load_p4(Q, j0), q1 = load_p4(Q, j1), q2 = load_p4(Q, j2),
                      q3 = load_p4(Q, j3);
             q += 4;
             const bool more = q + 4 <= qe;
             if (more) {
-                j0 = col_at<kStage>(col, scol, q, e0);
-                j1 = col_at<kStage>(col, scol, q + 1, e0);
-                j2 = col_at<kStage>(col, scol, q + 2, e0);
-                j3 = col_at<kStage>(col, scol, q + 3, e0);
+                j0 = cols.at(q);
+                j1 = cols.at(q + 1);
+                j2 = cols.at(q + 2);
+                j3 = cols.at(q + 3);
             }
             pair_term<false>(a, qi, q0, c.kappa, c.L, c.iL);
             pair_term<false>(a, qi, q1, c.kappa, c.L, c.iL);
@@ -451,14 +474,14 @@ __device__ __forceinline__ void segment_terms(Acc &a, const int32_t *__restrict_
         }
     }
     if (kU == 2 && q + 2 <= qe) {
-        int32_t j0 = col_at<kStage>(col, scol, q, e0), j1 = col_at<kStage>(col, scol, q + 1, e0);
+        int32_t j0 = cols.at(q), j1 = cols.at(q + 1);
         for (;;) {
             const P4 q0 = load_p4(Q, j0), q1 = load_p4(Q, j1);
             q += 2;
             const bool more = q + 2 <= qe;
             if (more) {
-                j0 = col_at<kStage>(col, scol, q, e0);
-                j1 = col_at<kStage>(col, scol, q + 1, e0);
+                j0 = cols.at(q);
+                j1 = cols.at(q + 1);
             }
             pair_term<false>(a, qi, q0, c.kappa, c.L, c.iL);
             pair_term<false>(a, qi, q1, c.kappa, c.L, c.iL);
@@ -466,13 +489,13 @@ __device__ __forceinline__ void segment_terms(Acc &a, const int32_t *__restrict_
         }
     }
     for (; q + 2 <= qe; q += 2) {
-        const int32_t j0 = col_at<kStage>(col, scol, q, e0),
-                      j1 = col_at<kStage>(col, scol, q + 1, e0);
+        const int32_t j0 = cols.at(q),
+                      j1 = cols.at(q + 1);
         const P4 q0 = load_p4(Q, j0), q1 = load_p4(Q, j1);
         pair_term<false>(a, qi, q0, c.kappa, c.L, c.iL);
         pair_term<false>(a, qi, q1, c.kappa, c.L, c.iL);
     }
-    if (q < qe) pair_term<false>(a, qi, load_p4(Q, col_at<kStage>(col, scol, q, e0)), c.kappa, c.L, c.iL);
+    if (q < qe) pair_term<false>(a, qi, load_p4(Q, cols.at(q)), c.kappa, c.L, c.iL);
 }
 
 template <int kN>
@@ -512,7 +535,8 @@ struct NoHook {
 // writes the item's partial sums to *out.  Every thread must call it.
 template <int kU, bool kEarly, bool kStage, int kR, class Hook, bool kCoherentOut = false>
 __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &c, int64_t r0,
-                                          int nrow, const int32_t *rp_own, int32_t rp_end,
+                                          int nrow, int32_t e0, int32_t e1,
+                                          const int32_t *rp_own, int32_t rp_end,
                                           ItemLdsR<kR> &L, int32_t *scol, Part4 *out, Hook hook,
                                           bool full)
 {
@@ -520,6 +544,15 @@ __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &
     constexpr int kOwn = kR / kBlock;
     const P4 *Q = p.q;
     const int t = threadIdx.x;
+    // this thread's chunk of the item's entries [e0, e1), and its first two
+    // partner indices, requested alongside the row pointers
+    const int32_t chunk = max(1, (e1 - e0 + kBlock - 1) / kBlock);
+    const int32_t cs = e0 + t * chunk, ce = min(cs + chunk, e1);
+    ColSrc<kStage> cols = {p.col, scol, e0, cs, 0, 0};
+    if (!kStage && RCP_ITEM_PREFETCH) {
+        if (cs < ce) cols.j0 = gload(p.col, cs);
+        if (cs + 1 < ce) cols.j1 = gload(p.col, cs + 1);
+    }
     // phase-2 operands either first (their latency hides behind phase 1)
     // or after it (fewer registers live through phase 1)
     P4 oq = {0, 0, 0, 0};
@@ -534,9 +567,8 @@ __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &
     if (t == 0) L.srp[nrow] = rp_end;
     if (kStage) {
         // the item's partner indices, one coalesced pass
-        const int32_t nst = min(rp_end - gload(p.rp, r0), (int32_t)kColStage);
-        const int32_t f0 = gload(p.rp, r0);
-        for (int k = t; k < nst; k += kBlock) scol[k] = gload(p.col, (int64_t)f0 + k);
+        const int32_t nst = min(e1 - e0, (int32_t)kColStage);
+        for (int k = t; k < nst; k += kBlock) scol[k] = gload(p.col, (int64_t)e0 + k);
     }
     __syncthreads();
 
@@ -545,10 +577,7 @@ __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &
     // order); only the gradient needs per-row bookkeeping
     Acc a = {0, 0, 0, 0, 0, 0, 0};   // e, s, m: this thread's totals
     double bd = 0;
-    const int32_t e0 = L.srp[0], e1 = L.srp[nrow];
-    const int32_t chunk = max(1, (e1 - e0 + kBlock - 1) / kBlock);
     const double rchunk = 1.0 / (double)chunk;   // block-uniform
-    const int32_t cs = e0 + t * chunk, ce = min(cs + chunk, e1);
     if (cs < ce) {
         int lo = 0, hi = nrow - 1;   // the row holding entry cs
         while (lo < hi) {
@@ -562,7 +591,7 @@ __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &
             const P4 qi = load_p4(Q, (int32_t)(r0 + r));
             const int32_t rend = L.srp[r + 1], qe = min(rend, ce);
             a.gx = a.gy = a.gz = 0.0;
-            segment_terms<kU, kStage>(a, p.col, scol, e0, Q, q, qe, qi, c);
+            segment_terms<kU, kStage>(a, cols, Q, q, qe, qi, c);
             const bool began_before = L.srp[r] < cs, goes_on = rend > ce;
             if (began_before) store3<kBlock>(L.A, t, a);
             else if (goes_on) store3<kBlock>(L.B, t, a);
@@ -628,11 +657,12 @@ __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &
             d = fmax(d, L.red[k][3]);
         }
         if (kCoherentOut) {
-            // written through to memory: the tail may run on another XCD
-            __hip_atomic_store(&out->e, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            __hip_atomic_store(&out->s, sd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            __hip_atomic_store(&out->m, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            __hip_atomic_store(&out->d, d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            // agent-scope stores reach the device's coherence point: the
+            // tail may run on another XCD
+            __hip_atomic_store(&out->e, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&out->s, sd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&out->m, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&out->d, d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             Part4 o;
             o.e = e;
@@ -681,25 +711,26 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
     const int32_t rp_t = t < nrow ? gload(p.rp, r0 + t) : 0;
     const int32_t rp_end = gload(p.rp, r0 + nrow);
     item_body<kU, kEarly, kStage, kBlock, NoHook, kFusedTail>(
-        p, c, r0, nrow, &rp_t, rp_end, L, scol, reinterpret_cast<Part4 *>(partials) + b,
-        NoHook(), (flags & 4) != 0);
+        p, c, r0, nrow, w.e0, w.e1, &rp_t, rp_end, L, scol,
+        reinterpret_cast<Part4 *>(partials) + b, NoHook(), (flags & 4) != 0);
     if (kFusedTail) {
         // the last block of the packing to finish reduces the partials and
-        // runs the tail.  Partials are written through to memory and read
-        // past the caches; the ticket is taken only after this block's
-        // partial stores have completed (no release fence: on this part a
-        // fence writes back the whole L2 of the XCD).
+        // runs the tail.  Partials are written and read with agent-scope
+        // atomics (at the device's coherence point, past the XCDs' L2s); the
+        // ticket is taken only after this block's partial stores have
+        // completed (no release fence: on this part a fence writes back the
+        // whole L2 of the XCD).
         __shared__ int last;
         if (t == 0) {
             __builtin_amdgcn_s_waitcnt(0);
             const uint32_t prev = __hip_atomic_fetch_add(&s->ticket, 1u, __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_SYSTEM);
+                                                         __HIP_MEMORY_SCOPE_AGENT);
             last = (prev == (uint32_t)s->nblocks - 1u);
         }
         __syncthreads();
         if (last) {
             reduce_and_tail<kBlock, true>(s, partials);
-            if (t == 0) __hip_atomic_store(&s->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            if (t == 0) __hip_atomic_store(&s->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -727,7 +758,8 @@ __global__ __launch_bounds__(kBlock) void k_iterate512(const SegPtrs *__restrict
     rp_own[0] = t < nrow ? gload(p.rp, r0 + t) : 0;
     rp_own[1] = t + kBlock < nrow ? gload(p.rp, r0 + t + kBlock) : 0;
     const int32_t rp_end = gload(p.rp, r0 + nrow);
-    item_body<kU, false, false, 2 * kBlock>(p, c, r0, nrow, rp_own, rp_end, L, nullptr,
+    item_body<kU, false, false, 2 * kBlock>(p, c, r0, nrow, w.e0, w.e1, rp_own, rp_end, L,
+                                            nullptr,
                                             reinterpret_cast<Part4 *>(partials) + b, NoHook(),
                                             (flags & 4) != 0);
 }
@@ -803,7 +835,8 @@ __global__ __launch_bounds__(kBlock) void k_iterate_persist(const SegPtrs *__res
                     have = true;
                 }
             };
-            item_body<kU, false, false, kBlock>(p, c, w.begin, nrow, &rp_t, rp_end, L, nullptr,
+            item_body<kU, false, false, kBlock>(p, c, w.begin, nrow, w.e0, w.e1, &rp_t, rp_end,
+                                                L, nullptr,
                                                 reinterpret_cast<Part4 *>(partials) + item,
                                                 hook, (flags & 4) != 0);
         }
@@ -914,12 +947,14 @@ __global__ __launch_bounds__(kTailBlock) void k_tail(SegState *__restrict__ S,
 // last row keep begin = end = n from the fill.  With wk <= 256 rc no item
 // holds more than 256 rows.
 __global__ __launch_bounds__(kBlock) void k_items_fill(WorkItem *__restrict__ W, int64_t nslots,
-                                                      int seg, int64_t n)
+                                                      int seg, const int32_t *__restrict__ rp,
+                                                      int64_t n)
 {
     const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (b >= nslots) return;
     WorkItem w;
     w.seg = seg;
+    w.e0 = w.e1 = rp ? rp[n] : 0;
     w.pad = 0;
     w.begin = n;
     w.end = n;
@@ -937,7 +972,11 @@ __global__ __launch_bounds__(kBlock) void k_items(const int32_t *__restrict__ rp
     const int64_t bh = min(hi / wk, nslots - 1);
     for (int64_t b = bl; b <= bh; ++b) {
         W[b].begin = i;
-        if (b > 0) W[b - 1].end = i;
+        W[b].e0 = rp[i];
+        if (b > 0) {
+            W[b - 1].end = i;
+            W[b - 1].e1 = rp[i];
+        }
     }
 }
 
@@ -946,7 +985,7 @@ void launch_items(const int32_t *rp, int64_t n, int seg, int row_cost, int item_
 {
     if (nslots <= 0) return;
     const unsigned gf = (unsigned)((nslots + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_items_fill, dim3(gf), dim3(kBlock), 0, st, W, nslots, seg,
+    hipLaunchKernelGGL(k_items_fill, dim3(gf), dim3(kBlock), 0, st, W, nslots, seg, rp,
                        rp ? n : (int64_t)0);
     if (!rp || n <= 0) return;
     const unsigned gi = (unsigned)((n + kBlock - 1) / kBlock);
@@ -975,6 +1014,7 @@ __global__ __launch_bounds__(kBlock) void k_items_fill_seg(const BackJob *__rest
     if (!B.fill || b >= B.nslots) return;
     WorkItem w;
     w.seg = B.seg;
+    w.e0 = w.e1 = B.rp ? B.rp[B.n] : 0;
     w.pad = 0;
     w.begin = B.n;
     w.end = B.n;
@@ -992,7 +1032,11 @@ __global__ __launch_bounds__(kBlock) void k_items_seg(const BackJob *__restrict_
     const int64_t bh = min(hi / wk, B.nslots - 1);
     for (int64_t b = bl; b <= bh; ++b) {
         B.W[b].begin = i;
-        if (b > 0) B.W[b - 1].end = i;
+        B.W[b].e0 = B.rp[i];
+        if (b > 0) {
+            B.W[b - 1].end = i;
+            B.W[b - 1].e1 = B.rp[i];
+        }
     }
 }
 
@@ -1023,6 +1067,22 @@ void launch_after_seg(const BackJob *jobs, int J, SegState *S, SegPtrs *P, hipSt
     if (J > 0)
         hipLaunchKernelGGL(k_after_seg, dim3((unsigned)((J + kBlock - 1) / kBlock)), dim3(kBlock), 0,
                            st, jobs, J, S, P);
+}
+
+// Work-table layout of every packing: lay[2k] blocks, lay[2k + 1] first item.
+__global__ void k_set_layout(SegState *S, int nseg, const int64_t *__restrict__ lay)
+{
+    const int k = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (k >= nseg) return;
+    S[k].nblocks = (int32_t)lay[2 * k];
+    S[k].bfirst = lay[2 * k + 1];
+}
+
+void launch_set_layout(SegState *S, int nseg, const int64_t *lay, hipStream_t st)
+{
+    if (nseg > 0)
+        hipLaunchKernelGGL(k_set_layout, dim3((unsigned)((nseg + kBlock - 1) / kBlock)),
+                           dim3(kBlock), 0, st, S, nseg, lay);
 }
 
 void launch_tail(SegState *S, const double *partials, int nseg, hipStream_t st)

@@ -93,8 +93,9 @@ __host__ __device__ inline void seg_bias_terms(SegState &s)
 // One block of the iteration grid: rows [begin, end) of packing seg.
 struct WorkItem {
     int32_t seg;
+    int32_t e0, e1;       // its CSR entries [e0, e1) = [rp[begin], rp[end])
     int32_t pad;
-    int64_t begin, end;
+    int64_t begin, end;   // its rows
 };
 
 // ------------------------------------------------- global-memory access

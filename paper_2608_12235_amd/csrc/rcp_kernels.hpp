@@ -130,6 +130,47 @@ void launch_max_degree(int64_t n, const int32_t *rp, uint32_t *out, hipStream_t 
 void launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);
 void launch_fill_f64(double *p, int64_t n, double v, hipStream_t s);
 
+// ---------------------------------------------------------- k_place.hip
+// Random sequential addition in rounds (see k_place.hip).
+struct alignas(16) PlaceSlot {
+    uint64_t key;        // cell key, ~0 when empty
+    int32_t head, pad;   // most recently pushed item of the cell (-1: none)
+};
+struct PlaceGrid {
+    int64_t off;         // first slot of the class's table in the arena
+    uint64_t mask;       // slots - 1 (a power of two)
+    int64_t nc;          // cells per axis
+    double inv_w;        // nc / L
+    int32_t any, pad;    // the class has spheres
+};
+constexpr int kPlaceMaxClasses = 64;
+struct PlaceArgs {
+    int64_t n;
+    double L, hL, kappa0;
+    uint64_t seed;
+    int64_t max_attempts;
+    int ncls, pad;
+    const int32_t *ord;      // rank -> sphere (largest first)
+    const double *d0;        // by sphere
+    double *x;               // (n, 3) by sphere: placed positions
+    int32_t *att;            // by rank: next attempt
+    uint8_t *placed;         // by rank
+    int32_t *next;           // by sphere: next sphere of its cell
+    PlaceSlot *tab;          // arena of the classes' cell tables
+    double *prop;            // window x 3: the round's proposals
+    uint8_t *valid;          // window
+    int32_t *pnext;          // window: next proposal of its cell
+    PlaceSlot *ptab;         // the round's proposal table
+    uint64_t pmask;
+    int64_t pcap;
+    unsigned long long *first;   // lowest rank of the window still unplaced
+    int32_t *fail;               // set when a sphere ran out of attempts
+    PlaceGrid grid[kPlaceMaxClasses];
+};
+// One round over ranks [lo, hi) of class c (clear the proposal table,
+// propose and validate, resolve conflicts and commit).
+void launch_place_round(const PlaceArgs &a, int c, int64_t lo, int64_t hi, hipStream_t st);
+
 // -------------------------------------------------------- k_iterate.hip
 // flags bit 0: XCD-aware block order; bit 1: the last block of each packing
 // runs its tail (otherwise launch_tail must follow); bit 2: whole 32-byte
@@ -142,6 +183,8 @@ void launch_items(const int32_t *rp, int64_t n, int seg, int row_cost, int item_
 void launch_iterate(const SegPtrs *P, SegState *S, const WorkItem *W, double *partials,
                     int nitems, int flags, hipStream_t s);
 void launch_tail(SegState *S, const double *partials, int nseg, hipStream_t s);
+// nblocks and bfirst of every packing from lay (2 int64 per packing, device).
+void launch_set_layout(SegState *S, int nseg, const int64_t *lay, hipStream_t s);
 // Start a schedule on segment seg: copy the table, reset the position in it,
 // set the first rung's parameters from the current kappa.
 void launch_sched_start(SegState *S, int seg, const SchedDev &q, int reset_adam,

@@ -97,6 +97,7 @@ struct Seg {
     double L = 0, d0min = 0, d0max = 0, sumd0 = 0, sumd03 = 0, nvol = 0, kappa0 = 1;
     uint64_t seed = 0;
     int nlev = 1;
+    std::vector<double> d0h;         // relative diameters (host copy, user order)
     std::vector<double> dmax_upto;   // max D0 over classes <= l
     std::vector<double> dmax_lev;    // max D0 in class l
     std::vector<int64_t> lev_count;
@@ -118,6 +119,7 @@ struct Seg {
     int64_t rebuilds = 0;
     int err = 0;                 // error that stopped this packing (census)
     bool built = false;
+    bool parked = false;         // finished: no work-item slots until its next run
 };
 
 // A stream for the pair searches of a batch of list builds.
@@ -191,6 +193,8 @@ struct rcp_ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> rb_pending, rb_pool;
     rcp_stats stats{};
     double *scratch = nullptr;       // this GPU's fixed scratch array (see below)
+    int64_t *d_layout = nullptr;     // (blocks, first item) per packing: device,
+    int64_t *h_layout = nullptr;     // and pinned host staging
 };
 
 static void ptrs_of(const Seg &s, SegPtrs &p)
@@ -304,7 +308,8 @@ static int build_work(rcp_ctx *c)
     int64_t total = 0;
     for (size_t k = 0; k < c->segs.size(); ++k) {
         Seg &s = c->segs[k];
-        const int64_t nb = slots_for(c, s.n, s.slot_entries);
+        // a finished packing gets no slots (its blocks would only exit)
+        const int64_t nb = s.parked ? 0 : slots_for(c, s.n, s.slot_entries);
         if (nb > (int64_t)INT32_MAX / 4 || total + nb > (int64_t)INT32_MAX / 4)
             return fail(RCP_ENOMEM, "work table too large");
         s.blocks = (int)nb;
@@ -321,15 +326,39 @@ static int build_work(rcp_ctx *c)
         c->items_cap = total;
     }
     c->nitems = (int)total;
-    for (size_t k = 0; k < c->segs.size(); ++k) {
-        Seg &s = c->segs[k];
-        CHK(put_field(c, (int)k, offsetof(SegState, nblocks), (int32_t)s.blocks));
-        CHK(put_field(c, (int)k, offsetof(SegState, bfirst), s.first_item));
-        fill_items(c, (int)k, c->stream);
+    const int ns = (int)c->segs.size();
+    for (int k = 0; k < ns; ++k) {
+        c->h_layout[2 * k] = c->segs[k].blocks;
+        c->h_layout[2 * k + 1] = c->segs[k].first_item;
     }
+    HIPCHK(hipMemcpyAsync(c->d_layout, c->h_layout, sizeof(int64_t) * 2 * ns,
+                          hipMemcpyHostToDevice, c->stream));
+    launch_set_layout(c->d_state, ns, c->d_layout, c->stream);
+    for (int k = 0; k < ns; ++k) fill_items(c, k, c->stream);
     HIPCHK(hipStreamSynchronize(c->stream));
     c->graph_valid = false;
     return RCP_OK;
+}
+
+// Packings that have finished for good (stop, cap, non-finite, abort) give
+// up their work-item slots once they hold more than an eighth of the table:
+// the iteration grid then covers only the packings still running.
+static int park_finished(rcp_ctx *c)
+{
+    if (c->segs.size() < 2) return RCP_OK;
+    int64_t freed = 0;
+    bool any = false;
+    for (size_t k = 0; k < c->segs.size(); ++k) {
+        const int32_t f = c->h_state[k].flags;
+        if (!c->segs[k].parked && (f & (F_STOP | F_CAP | F_NONFINITE | F_ABORT))) {
+            any = true;
+            freed += c->segs[k].blocks;
+        }
+    }
+    if (!any || 8 * freed < (int64_t)c->nitems) return RCP_OK;
+    for (size_t k = 0; k < c->segs.size(); ++k)
+        if (c->h_state[k].flags & (F_STOP | F_CAP | F_NONFINITE | F_ABORT)) c->segs[k].parked = true;
+    return build_work(c);
 }
 
 // ------------------------------------------------------------ list build
@@ -885,7 +914,9 @@ static int launch_one_iteration(rcp_ctx *c, int slot)
     const int flags = iterate_flags(c) | (c->tuning.fused_tail ? 2 : 0);
     const bool timed = slot_timed(c, slot) && 3 * slot + 2 < (int)c->kev.size();
     if (timed) CHK(record_event(c, c->kev[3 * slot]));
-    launch_iterate(c->d_ptrs, c->d_state, c->d_work, c->d_partials, c->nitems, flags, c->stream);
+    if (c->nitems > 0)
+        launch_iterate(c->d_ptrs, c->d_state, c->d_work, c->d_partials, c->nitems, flags,
+                       c->stream);
     if (timed) CHK(record_event(c, c->kev[3 * slot + 1]));
     if (!c->tuning.fused_tail) launch_tail(c->d_state, c->d_partials, (int)c->segs.size(), c->stream);
     if (timed) CHK(record_event(c, c->kev[3 * slot + 2]));
@@ -1002,6 +1033,7 @@ static int run_loop(rcp_ctx *c)
         float ms = 0;
         HIPCHK(hipEventElapsedTime(&ms, c->e0, c->e1));
         c->stats.iterate_ms += ms;
+        CHK(park_finished(c));
         int64_t worked = 0, nnz = 0;
         for (size_t k = 0; k < c->segs.size(); ++k) {
             const int64_t d = c->h_state[k].iters - prev[k];
@@ -1074,6 +1106,158 @@ static int shrink_seg(rcp_ctx *c, int k, double *kp_out, double *phi_out)
     return RCP_OK;
 }
 
+// ------------------------------------------------------------ placement
+// Random sequential addition in rounds on the device (k_place.hip) for
+// packing k; the positions then replace the packing's state as
+// rcp_set_state does (at its current kappa).
+static int place_device(rcp_ctx *c, int k, uint64_t seed, int64_t window, int64_t max_attempts,
+                        int64_t *rounds)
+{
+    CHK(pull_state(c));
+    Seg &s = c->segs[k];
+    const int64_t n = s.n;
+    const std::vector<double> &d0 = s.d0h;
+    const double kappa = c->h_state[k].kappa;   // placement at the current scale
+    // ranks: largest first, ties by index; classes floor(log2(D0 / D0_min))
+    std::vector<int32_t> ord(n);
+    for (int64_t i = 0; i < n; ++i) ord[i] = (int32_t)i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return d0[a] > d0[b]; });
+    std::vector<int> cls(n);
+    int ncls = 1;
+    for (int64_t r = 0; r < n; ++r) {
+        int e;
+        std::frexp(d0[ord[r]] / s.d0min, &e);
+        cls[r] = std::max(0, e - 1);
+        ncls = std::max(ncls, cls[r] + 1);
+    }
+    if (ncls > kPlaceMaxClasses) return fail(RCP_EINVAL, "size ratio too large for placement");
+    std::vector<int64_t> count(ncls, 0);
+    std::vector<double> dmax(ncls, 0.0);
+    for (int64_t r = 0; r < n; ++r) {
+        count[cls[r]]++;
+        dmax[cls[r]] = std::max(dmax[cls[r]], d0[ord[r]]);
+    }
+    PlaceArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.n = n;
+    a.L = s.L;
+    a.hL = 0.5 * s.L;
+    a.kappa0 = kappa;
+    a.seed = seed;
+    a.max_attempts = max_attempts;
+    a.ncls = ncls;
+    int64_t tcap = 0;
+    for (int q = 0; q < ncls; ++q) {
+        PlaceGrid &g = a.grid[q];
+        const double h = kappa * dmax[q] * (1.0 + 1e-12);
+        int64_t nc = h > 0 ? (int64_t)std::floor(s.L / h) : 1;
+        nc = std::max<int64_t>(1, std::min<int64_t>(nc, (int64_t)1 << 20));
+        g.nc = nc;
+        g.inv_w = (double)nc / s.L;
+        g.any = count[q] > 0;
+        uint64_t cap = 16;
+        while (cap < (uint64_t)(2 * count[q] + 2)) cap <<= 1;
+        g.off = tcap;
+        g.mask = cap - 1;
+        tcap += (int64_t)cap;
+    }
+    const int64_t W = std::max<int64_t>(1, std::min<int64_t>(window, n));
+    uint64_t pc = 16;
+    while (pc < (uint64_t)(2 * W)) pc <<= 1;
+    a.pcap = (int64_t)pc;
+    a.pmask = pc - 1;
+    // device buffers for the placement only
+    int32_t *d_ord = nullptr, *d_att = nullptr, *d_next = nullptr, *d_pnext = nullptr,
+            *d_fail = nullptr;
+    double *d_d0 = nullptr, *d_x = nullptr, *d_prop = nullptr;
+    uint8_t *d_placed = nullptr, *d_valid = nullptr;
+    PlaceSlot *d_tab = nullptr, *d_ptab = nullptr;
+    unsigned long long *d_first = nullptr;
+    auto release = [&]() {
+        dfree(d_ord); dfree(d_att); dfree(d_next); dfree(d_pnext); dfree(d_fail);
+        dfree(d_d0); dfree(d_x); dfree(d_prop); dfree(d_placed); dfree(d_valid);
+        dfree(d_tab); dfree(d_ptab); dfree(d_first);
+    };
+    int rc = RCP_OK;
+    do {
+        if ((rc = dalloc(&d_ord, n)) || (rc = dalloc(&d_att, n)) || (rc = dalloc(&d_next, n)) ||
+            (rc = dalloc(&d_pnext, W)) || (rc = dalloc(&d_fail, 1)) || (rc = dalloc(&d_d0, n)) ||
+            (rc = dalloc(&d_x, 3 * n)) || (rc = dalloc(&d_prop, 3 * W)) ||
+            (rc = dalloc(&d_placed, n)) || (rc = dalloc(&d_valid, W)) ||
+            (rc = dalloc(&d_tab, tcap)) || (rc = dalloc(&d_ptab, a.pcap)) ||
+            (rc = dalloc(&d_first, 1)))
+            break;
+        hipError_t e = hipMemcpyAsync(d_ord, ord.data(), sizeof(int32_t) * n,
+                                      hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_d0, d0.data(), sizeof(double) * n, hipMemcpyHostToDevice,
+                               c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(d_att, 0, sizeof(int32_t) * n, c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(d_placed, 0, n, c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(d_fail, 0, sizeof(int32_t), c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(d_tab, 0xff, sizeof(PlaceSlot) * tcap, c->stream);
+        if (e != hipSuccess) {
+            rc = fail(RCP_EDEVICE, "placement set-up: %s", hipGetErrorString(e));
+            break;
+        }
+        a.ord = d_ord;
+        a.d0 = d_d0;
+        a.x = d_x;
+        a.att = d_att;
+        a.placed = d_placed;
+        a.next = d_next;
+        a.tab = d_tab;
+        a.prop = d_prop;
+        a.valid = d_valid;
+        a.pnext = d_pnext;
+        a.ptab = d_ptab;
+        a.first = d_first;
+        a.fail = d_fail;
+        int64_t nround = 0;
+        int64_t cb = 0;
+        while (cb < n && rc == RCP_OK) {
+            int64_t ce = cb;
+            while (ce < n && cls[ce] == cls[cb]) ++ce;
+            int64_t lo = cb;
+            while (lo < ce) {
+                const int64_t hi = std::min(lo + W, ce);
+                unsigned long long h_hi = (unsigned long long)hi;
+                if ((e = hipMemcpyAsync(d_first, &h_hi, sizeof h_hi, hipMemcpyHostToDevice,
+                                        c->stream)) != hipSuccess)
+                    break;
+                launch_place_round(a, cls[cb], lo, hi, c->stream);
+                unsigned long long first = 0;
+                int32_t failed = 0;
+                if ((e = hipGetLastError()) != hipSuccess ||
+                    (e = hipMemcpyAsync(&first, d_first, sizeof first, hipMemcpyDeviceToHost,
+                                        c->stream)) != hipSuccess ||
+                    (e = hipMemcpyAsync(&failed, d_fail, sizeof failed, hipMemcpyDeviceToHost,
+                                        c->stream)) != hipSuccess ||
+                    (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+                    break;
+                ++nround;
+                if (failed) {
+                    rc = fail(RCP_EPLACE, "packing %d: a sphere exceeded %lld placement attempts",
+                              k, (long long)max_attempts);
+                    break;
+                }
+                lo = (int64_t)first;
+            }
+            if (e != hipSuccess && rc == RCP_OK)
+                rc = fail(RCP_EDEVICE, "placement: %s", hipGetErrorString(e));
+            cb = ce;
+        }
+        if (rc != RCP_OK) break;
+        if (rounds) *rounds = nround;
+        rc = rcp_set_state(c, k, d_x, kappa, 1);
+    } while (0);
+    const hipError_t se = hipStreamSynchronize(c->stream);
+    release();
+    if (rc == RCP_OK && se != hipSuccess)
+        return fail(RCP_EDEVICE, "placement: %s", hipGetErrorString(se));
+    return rc;
+}
+
 // ------------------------------------------------------------ creation
 static int validate_seg(int64_t n, const double *d0, double L, double kappa0)
 {
@@ -1097,6 +1281,7 @@ static int seg_setup(rcp_ctx *c, int k, int64_t n, const double *d0, double L, d
     s.L = L;
     s.kappa0 = kappa0;
     s.seed = seed;
+    s.d0h.assign(d0, d0 + n);
     s.d0min = d0[0];
     s.d0max = d0[0];
     double sum = 0, cs = 0, sum3 = 0, cs3 = 0, sum6 = 0, cs6 = 0;   // Neumaier sums
@@ -1169,7 +1354,7 @@ static int seg_setup(rcp_ctx *c, int k, int64_t n, const double *d0, double L, d
             return fail(RCP_EPLACE, "packing %d: random sequential addition failed", k);
     } else if (init_mode == RCP_INIT_UNIFORM) {
         place_uniform(n, L, seed, x.data());
-    } else if (init_mode != RCP_INIT_NONE) {
+    } else if (init_mode != RCP_INIT_NONE && init_mode != RCP_INIT_RSA_DEVICE) {
         return fail(RCP_EINVAL, "unknown init_mode %d", init_mode);
     }
     // device arrays
@@ -1289,6 +1474,8 @@ static void destroy_ctx(rcp_ctx *c)
     dfree(c->xtmp);
     if (c->h_state) (void)hipHostFree(c->h_state);
     if (c->h_out) (void)hipHostFree(c->h_out);
+    if (c->h_layout) (void)hipHostFree(c->h_layout);
+    dfree(c->d_layout);
     for (auto &e : c->kev) (void)hipEventDestroy(e);
     c->kev.clear();
     for (auto *v : {&c->rb_pending, &c->rb_pool})
@@ -1334,8 +1521,8 @@ void rcp_tuning_default(rcp_tuning *t)
     // cooperative pair search; whole 32-byte records written (measured at
     // least as fast as writing the three coordinates alone)
     t->variant = 64 | 128;
-    t->row_cost = 10;
-    t->item_work = 2560;
+    t->row_cost = 8;
+    t->item_work = 2048;
     t->time_kernels = 0;
 }
 
@@ -1393,7 +1580,7 @@ int rcp_census_init(int dim, int n_prob, const int64_t *n, const double *const *
         !std::isfinite(P.eps_x) || !std::isfinite(P.skin_s) || !std::isfinite(P.skin_g))
         return fail(RCP_EINVAL, "bad rcp_params values");
     for (int k = 0; k < n_prob; ++k) CHK(validate_seg(n[k], d0[k], box[k], kappa0[k]));
-    if (init_mode < RCP_INIT_NONE || init_mode > RCP_INIT_UNIFORM)
+    if (init_mode < RCP_INIT_NONE || init_mode > RCP_INIT_RSA_DEVICE)
         return fail(RCP_EINVAL, "unknown init_mode %d", init_mode);
     rcp_ctx *c = new rcp_ctx();
     c->params = P;
@@ -1427,10 +1614,18 @@ int rcp_census_init(int dim, int n_prob, const int64_t *n, const double *const *
             rc = fail(RCP_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
             break;
         }
+        if ((e = hipHostMalloc((void **)&c->h_layout, sizeof(int64_t) * 2 * n_prob, 0)) !=
+            hipSuccess) {
+            rc = fail(RCP_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+            break;
+        }
+        if ((rc = dalloc(&c->d_layout, 2 * (size_t)n_prob)) != RCP_OK) break;
         for (int k = 0; k < n_prob && rc == RCP_OK; ++k)
             rc = seg_setup(c, k, n[k], d0[k], box[k], kappa0[k], seeds[k], init_mode);
         if (rc != RCP_OK) break;
         rc = build_work(c);
+        for (int k = 0; k < n_prob && rc == RCP_OK && init_mode == RCP_INIT_RSA_DEVICE; ++k)
+            rc = place_device(c, k, seeds[k], RCP_PLACE_WINDOW, (int64_t)1 << 22, nullptr);
     } while (0);
     if (rc != RCP_OK) {
         std::string msg = g_err;
@@ -1655,6 +1850,13 @@ int rcp_set_optimizer(rcp_ctx *c, int k, const double *m, const double *v,
     return RCP_OK;
 }
 
+int rcp_place_device(rcp_ctx *c, int k, uint64_t seed, int64_t window, int64_t *rounds)
+{
+    CHK(check_k(c, k));
+    if (window < 1) return fail(RCP_EINVAL, "window must be at least 1");
+    return place_device(c, k, seed, window, (int64_t)1 << 22, rounds);
+}
+
 int rcp_neighbor_build(rcp_ctx *c, int k, int64_t *n_pairs)
 {
     CHK(check_k(c, k));
@@ -1745,6 +1947,13 @@ static int start_schedule(rcp_ctx *c, const rcp_schedule *sched, int per_packing
     CHK(pull_state(c));
     std::vector<SchedDev> qs(c->segs.size());
     for (size_t k = 0; k < c->segs.size(); ++k) CHK(to_sched(per_packing ? sched + k : sched, qs[k]));
+    // every packing runs again: packings parked by an earlier run get slots
+    bool parked = false;
+    for (auto &s : c->segs) {
+        parked = parked || s.parked;
+        s.parked = false;
+    }
+    if (parked) CHK(build_work(c));
     for (size_t k = 0; k < c->segs.size(); ++k) {
         if (reset_adam) CHK(reset_moments(c, (int)k));
         c->segs[k].err = 0;
@@ -1848,6 +2057,14 @@ int rcp_run_continue(rcp_ctx *c, int64_t n_iters, int32_t *active)
     for (int k = 0; k < ns; ++k)
         if (!(c->h_state[k].flags & (F_STOP | F_CAP | F_NONFINITE))) ++a;
     if (active) *active = a;
+    return RCP_OK;
+}
+
+int rcp_run_prepare(rcp_ctx *c)
+{
+    if (!c) return fail(RCP_EINVAL, "null context");
+    const int K = std::max(1, c->tuning.graph_iters);
+    if (K > 1 && (!c->graph_valid || c->graph_k != K)) CHK(capture_graph(c, K));
     return RCP_OK;
 }
 
@@ -2041,7 +2258,7 @@ int rcp_time_iterations(rcp_ctx *c, int64_t n_iters, double *iterate_us, double 
         if ((rc = pull_state(c)) != RCP_OK) break;
         int64_t before = 0;
         for (int k = 0; k < ns; ++k) before += c->h_state[k].iters;
-        for (int b = 0; b < kBatch; ++b) {
+        for (int b = 0; b < kBatch && c->nitems > 0; ++b) {
             (void)hipEventRecord(ev[3 * b], c->stream);
             launch_iterate(c->d_ptrs, c->d_state, c->d_work, c->d_partials, c->nitems, flags,
                            c->stream);

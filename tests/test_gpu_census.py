@@ -73,6 +73,48 @@ def test_census_phi_matches_oracle(rcp):
     assert abs(pg.mean() - po.mean()) <= 0.002
 
 
+def test_autotuned_census_phi_matches_oracle(rcp, tmp_path):
+    # the same 64 cases with the settings the autotuner finds on a proxy of
+    # the largest ones; a second call takes them from the cache
+    import json
+    import os
+    from paper_2608_12235_amd import census
+    with open(os.path.join(os.path.dirname(__file__), "golden",
+                           "census8_phi_oracle.json")) as fh:
+        po = np.array([g["phi"] for g in json.load(fh)["runs"]])
+    wl = []
+    for w in _smallest(8):
+        for seed in range(8):
+            wl.append(type(w)(w.name, w.d0, w.L, w.phi0, 1000 + seed, w.family, w.params))
+    cache = str(tmp_path / "autotune.json")
+    res, _, info = census.run_autotuned(wl, cache=cache)
+    assert not info["cache_hit"]
+    _say("autotuned settings", info["best"], "tuning %.2f s" % info["tuning_s"])
+    pg = np.array([r["phi"] for r in res])
+    assert all(r["status"] == 0 for r in res)
+    _say("phi autotuned %.5f oracle %.5f" % (pg.mean(), po.mean()))
+    assert abs(pg.mean() - po.mean()) <= 0.002
+    res2, _, info2 = census.run_autotuned(wl, cache=cache)
+    assert info2["cache_hit"] and info2["tuning_s"] == 0.0 and info2["best"] == info["best"]
+    assert [r["phi"] for r in res2] == [r["phi"] for r in res]
+
+
+def test_finished_packings_leave_the_work_table(rcp):
+    # packings of very different length: the short ones finish first and
+    # give up their work items (the iteration grid shrinks); the results are
+    # those of plain solves all the same
+    from paper_2608_12235_amd import census
+    wl = _smallest(6)
+    scheds = [rcp.default_schedule(w.n, S=float(w.d0.max() / w.d0.min()), Y=1 + k % 3)
+              for k, w in enumerate(wl)]
+    rb, _, _ = census.run_batched(wl, schedules=scheds)
+    for k, w in enumerate(wl):
+        p = rcp.Packing(w.d0, w.L, 1.0, w.seed, init="rsa")
+        r = p.inflate_run(scheds[k])[0]
+        p.close()
+        assert r == rb[k], k
+
+
 def test_census_box_failure_isolated(rcp):
     # a packing whose largest sphere cannot fit its box at the reached scale
     # is stopped with RCP_EBOX while the others finish

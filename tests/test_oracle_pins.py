@@ -633,3 +633,33 @@ def test_stored_census_runs_come_from_the_oracle(orc):
     assert status == g["status"] == 0
     assert res.iterations == g["iterations"]
     assert res.phi == g["phi"]
+
+
+# ------------------------------------------------ placement in rounds
+@pytest.mark.parametrize("seed", [0, 3])
+def test_rsa_rounds_of_one_is_sequential_rsa(orc, seed):
+    # a round of one proposal is the sequential procedure, attempt for
+    # attempt (an independent implementation with a single grid)
+    w = ri.c1_lognormal(seed)
+    x1 = orc.rsa(w.d0, w.L, 1.0, w.seed)
+    x2, nr = orc.rsa_rounds(w.d0, w.L, 1.0, w.seed, 1)
+    assert np.array_equal(x1, x2) and nr >= w.n
+    d0 = ri.lognormal_quantiles(1500, 0.7, 60.0)
+    L = ri.box_for_phi(d0, 0.08)
+    assert np.array_equal(orc.rsa(d0, L, 1.0, 11), orc.rsa_rounds(d0, L, 1.0, 11, 1)[0])
+
+
+@pytest.mark.parametrize("window", [16, 256, 1 << 16])
+def test_rsa_rounds_non_overlapping_uniform_deterministic(orc, window):
+    d0 = ri.lognormal_quantiles(3000, 0.7, 60.0)
+    L = ri.box_for_phi(d0, 0.08)
+    x, nr = orc.rsa_rounds(d0, L, 1.0, 5, window)
+    x2, nr2 = orc.rsa_rounds(d0, L, 1.0, 5, window)
+    assert np.array_equal(x, x2) and nr == nr2
+    assert np.all((x >= 0) & (x < L))
+    pi, _ = orc.pairs_brute(x, d0, L, 1.0, 0.0, 0.0)
+    assert len(pi) == 0
+    for a in range(3):
+        assert stats.kstest(x[:, a] / L, "uniform").pvalue > 1e-3
+    # fewer rounds than spheres once a round holds several proposals
+    assert nr < 3000 or window == 1
