@@ -395,7 +395,8 @@ int rcp_run_continue(rcp_ctx *ctx, int64_t n_iters, int32_t *active);
  * rcp_run_continue launches it) ahead of the next rcp_run_continue, which
  * then does not pay for the capture.  The graph stays valid until the
  * tuning or the work-item layout changes (a list build that changes the
- * number of work items); nothing is launched.  No-op for graph_iters 1. */
+ * number of work items); the graph is uploaded to the device, nothing is
+ * launched.  No-op for graph_iters 1. */
 int rcp_run_prepare(rcp_ctx *ctx);
 int rcp_run_result(rcp_ctx *ctx, int k, rcp_result *result);
 

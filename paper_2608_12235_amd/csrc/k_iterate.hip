@@ -168,7 +168,8 @@ struct IterScalars {
 struct IterPtrs {
     const P4 *q;        // current (x, y, z, D0)
     P4 *qo;             // next positions
-    double *m0, *m1, *m2, *v0, *v1, *v2, *r0, *r1, *r2;
+    double *m0, *m1, *m2, *v0, *v1, *v2;
+    const float *r0, *r1, *r2;
     const int32_t *rp, *col;
 };
 
@@ -208,7 +209,8 @@ __device__ __forceinline__ double update_coord(double xi, double g, double m, do
 }
 
 struct Pre {
-    double m0, m1, m2, v0, v1, v2, r0, r1, r2;
+    double m0, m1, m2, v0, v1, v2;
+    float r0, r1, r2;
 };
 
 // Streamed operands of row i (read once per iteration).
@@ -556,7 +558,7 @@ __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &
     // phase-2 operands either first (their latency hides behind phase 1)
     // or after it (fewer registers live through phase 1)
     P4 oq = {0, 0, 0, 0};
-    Pre pre = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    Pre pre = {0, 0, 0, 0, 0, 0, 0.f, 0.f, 0.f};
     if (kEarly && t < nrow) {
         oq = load_p4(Q, (int32_t)(r0 + t));
         pre = preload(p, r0 + t);
@@ -920,15 +922,22 @@ constexpr int kTailBlock = 1024;
 // writes then cost LDS latency, not memory latency) and the block writes the
 // record back.
 __global__ __launch_bounds__(kTailBlock) void k_tail(SegState *__restrict__ S,
-                                                    const double *__restrict__ partials)
+                                                    const double *__restrict__ partials,
+                                                    int64_t b0, int64_t nb)
 {
     static_assert(sizeof(SegState) % 8 == 0, "SegState is copied in 8-byte words");
     constexpr int kWords = (int)(sizeof(SegState) / 8);
     __shared__ SegState ls;
     SegState *gs = S + blockIdx.x;
     // the partials are loaded before the record is copied, so the two
-    // latencies overlap (an idle packing's stale partials are then dropped)
-    const Part4 mine = thread_partials<kTailBlock, false>(gs->nblocks, gs->bfirst, partials);
+    // latencies overlap (an idle packing's stale partials are then dropped);
+    // with one packing their range comes with the launch (nb >= 0), so the
+    // loads need not wait for the record
+    if (nb < 0) {
+        nb = gs->nblocks;
+        b0 = gs->bfirst;
+    }
+    const Part4 mine = thread_partials<kTailBlock, false>(nb, b0, partials);
     uint64_t *src = reinterpret_cast<uint64_t *>(gs);
     uint64_t *dst = reinterpret_cast<uint64_t *>(&ls);
     for (int k = threadIdx.x; k < kWords; k += kTailBlock) dst[k] = src[k];
@@ -1085,9 +1094,11 @@ void launch_set_layout(SegState *S, int nseg, const int64_t *lay, hipStream_t st
                            dim3(kBlock), 0, st, S, nseg, lay);
 }
 
-void launch_tail(SegState *S, const double *partials, int nseg, hipStream_t st)
+void launch_tail(SegState *S, const double *partials, int nseg, int64_t b0, int64_t nb,
+                 hipStream_t st)
 {
-    hipLaunchKernelGGL(k_tail, dim3(nseg), dim3(kTailBlock), 0, st, S, partials);
+    if (nseg != 1) b0 = 0, nb = -1;
+    hipLaunchKernelGGL(k_tail, dim3(nseg), dim3(kTailBlock), 0, st, S, partials, b0, nb);
 }
 
 __global__ void k_sched_start(SegState *S, int seg, SchedDev q, int reset_adam,
@@ -1254,7 +1265,7 @@ __global__ __launch_bounds__(kBlock) void k_disp(const SegPtrs *__restrict__ P,
         const int64_t u = p.orig[i];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const double dd = min_image(xu[3 * u + a] - p.xref[a][i], L, hL);
+            const double dd = min_image(xu[3 * u + a] - (double)p.xref[a][i], L, hL);
             d2 += dd * dd;
         }
     }

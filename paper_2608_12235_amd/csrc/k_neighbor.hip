@@ -62,9 +62,9 @@ __device__ __forceinline__ void permute_one(const PermArgs &p, int64_t k)
     const int64_t s = p.perm[k];
     const P4 q = p.ps[s];
     p.pd[k] = q;
-    p.xref[0][k] = q.x;
-    p.xref[1][k] = q.y;
-    p.xref[2][k] = q.z;
+    p.xref[0][k] = (float)q.x;
+    p.xref[1][k] = (float)q.y;
+    p.xref[2][k] = (float)q.z;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         p.md[a][k] = p.ms[a][s];

@@ -47,7 +47,9 @@ struct alignas(32) P4 {
 struct SegPtrs {
     P4 *p[2];             // ping-pong (x, y, z, D0)
     double *m[3], *v[3];  // Adam moments, SoA
-    double *xref[3];      // positions at the last list build
+    float *xref[3];       // positions at the last list build, rounded to float
+                          // (they serve only the displacement test, whose
+                          // limit is reduced by the rounding, see kXrefErr)
     int32_t *orig;        // sorted index -> user index
     uint8_t *lev;         // size class
     int32_t *rp;          // row pointers (n + 1) into col

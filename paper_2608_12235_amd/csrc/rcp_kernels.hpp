@@ -59,7 +59,7 @@ struct PermArgs {
     const uint32_t *perm;
     const P4 *ps;
     P4 *pd;
-    double *xref[3];
+    float *xref[3];
     const double *ms[3]; double *md[3];
     const double *vs[3]; double *vd[3];
     const int32_t *os; int32_t *od;
@@ -182,7 +182,10 @@ void launch_items(const int32_t *rp, int64_t n, int seg, int row_cost, int item_
                   WorkItem *W, int64_t nslots, hipStream_t st);
 void launch_iterate(const SegPtrs *P, SegState *S, const WorkItem *W, double *partials,
                     int nitems, int flags, hipStream_t s);
-void launch_tail(SegState *S, const double *partials, int nseg, hipStream_t s);
+// b0, nb: the work-item range of the only packing when nseg == 1 (its
+// layout at launch or capture time), else ignored.
+void launch_tail(SegState *S, const double *partials, int nseg, int64_t b0, int64_t nb,
+                 hipStream_t s);
 // nblocks and bfirst of every packing from lay (2 int64 per packing, device).
 void launch_set_layout(SegState *S, int nseg, const int64_t *lay, hipStream_t s);
 // Start a schedule on segment seg: copy the table, reset the position in it,

@@ -107,7 +107,7 @@ struct Seg {
     double *M[2][3] = {}, *V[2][3] = {};
     int32_t *ORIG[2] = {};
     uint8_t *LEV[2] = {};
-    double *XREF[3] = {};
+    float *XREF[3] = {};
     int32_t *rp = nullptr, *col = nullptr;
     int64_t col_cap = 0;
     int set = 0;
@@ -281,6 +281,10 @@ static int scratch_address(double **out)
     *out = g_scratch_addr[dev];
     return RCP_OK;
 }
+
+// Bound on |x - (double)(float)x| summed over the three axes for positions
+// in [0, L), in units of L: sqrt(3) 2^-23 (twice the rounding bound).
+constexpr double kXrefErr = 1.7320508075688772 * 0x1p-23;
 
 // ------------------------------------------------------------ work table
 // Work-item slots for packing k: enough for row_cost * n + slot_entries
@@ -722,7 +726,11 @@ static int build_backs(rcp_ctx *c, std::vector<BuildJob> &jobs, const std::vecto
         }
         B.cur = s.cur;
         B.kb = j.kappa;
-        B.disp_lim = sk * j.kappa * s.d0min * (1.0 - 1e-9);
+        // the list-reference positions are kept in float: a coordinate in
+        // [0, L) is off by at most L 2^-24, so the displacement allowance
+        // shrinks by sqrt(3) L 2^-23 (never below zero: then every
+        // iteration asks for a build, which is slow but sound)
+        B.disp_lim = std::max(0.0, sk * j.kappa * s.d0min * (1.0 - 1e-9) - kXrefErr * s.L);
         B.kappa_lim = opg * j.kappa * (1.0 - 1e-12);
         ptrs_of(s, B.ptrs);
         B.bc0 = nbc;
@@ -918,7 +926,9 @@ static int launch_one_iteration(rcp_ctx *c, int slot)
         launch_iterate(c->d_ptrs, c->d_state, c->d_work, c->d_partials, c->nitems, flags,
                        c->stream);
     if (timed) CHK(record_event(c, c->kev[3 * slot + 1]));
-    if (!c->tuning.fused_tail) launch_tail(c->d_state, c->d_partials, (int)c->segs.size(), c->stream);
+    if (!c->tuning.fused_tail)
+        launch_tail(c->d_state, c->d_partials, (int)c->segs.size(), c->segs[0].first_item,
+                    c->segs[0].blocks, c->stream);
     if (timed) CHK(record_event(c, c->kev[3 * slot + 2]));
     return RCP_OK;
 }
@@ -1372,10 +1382,10 @@ static int seg_setup(rcp_ctx *c, int k, int64_t n, const double *d0, double L, d
     s.col_cap = std::max<int64_t>(8 * n, 1024);
     CHK(dalloc(&s.col, s.col_cap));
     s.slot_entries = s.col_cap;
-    std::vector<double> soa(n);
+    std::vector<float> soa(n);
     for (int a = 0; a < 3; ++a) {
-        for (int64_t i = 0; i < n; ++i) soa[i] = x[3 * i + a];
-        HIPCHK(hipMemcpy(s.XREF[a], soa.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+        for (int64_t i = 0; i < n; ++i) soa[i] = (float)x[3 * i + a];
+        HIPCHK(hipMemcpy(s.XREF[a], soa.data(), sizeof(float) * n, hipMemcpyHostToDevice));
         HIPCHK(hipMemset(s.M[0][a], 0, sizeof(double) * n));
         HIPCHK(hipMemset(s.V[0][a], 0, sizeof(double) * n));
     }
@@ -2064,7 +2074,10 @@ int rcp_run_prepare(rcp_ctx *c)
 {
     if (!c) return fail(RCP_EINVAL, "null context");
     const int K = std::max(1, c->tuning.graph_iters);
-    if (K > 1 && (!c->graph_valid || c->graph_k != K)) CHK(capture_graph(c, K));
+    if (K <= 1) return RCP_OK;
+    if (!c->graph_valid || c->graph_k != K) CHK(capture_graph(c, K));
+    HIPCHK(hipGraphUpload(c->gexec, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
     return RCP_OK;
 }
 
@@ -2263,7 +2276,8 @@ int rcp_time_iterations(rcp_ctx *c, int64_t n_iters, double *iterate_us, double 
             launch_iterate(c->d_ptrs, c->d_state, c->d_work, c->d_partials, c->nitems, flags,
                            c->stream);
             (void)hipEventRecord(ev[3 * b + 1], c->stream);
-            launch_tail(c->d_state, c->d_partials, ns, c->stream);
+            launch_tail(c->d_state, c->d_partials, ns, c->segs[0].first_item, c->segs[0].blocks,
+                        c->stream);
             (void)hipEventRecord(ev[3 * b + 2], c->stream);
         }
         if ((rc = pull_state(c)) != RCP_OK) break;
