@@ -10,7 +10,8 @@ from .oracle import (build, lib, splitmix64, u01, pairs_brute, pairs_cells,
                      run, Params, Schedule, n_trig, default_schedule,
                      time_iterations, set_threads, num_threads, RunState,
                      default_params, absolute_schedule, Result, set_list_check,
-                     list_misses, rsa_rounds)
+                     list_misses, rsa_rounds, set_frozen, phi_frozen, seat,
+                     cascade, cascade_counts)
 from . import oracle
 
 __all__ = [
@@ -18,5 +19,5 @@ __all__ = [
     "rows_pairs", "energy_grad", "rows_grad", "shrink", "phi", "rsa", "run",
     "Params", "Schedule", "n_trig", "default_schedule", "time_iterations",
     "set_threads", "num_threads", "RunState", "set_list_check", "list_misses",
-    "rsa_rounds",
+    "rsa_rounds", "set_frozen", "phi_frozen", "seat", "cascade", "cascade_counts",
 ]

@@ -78,6 +78,13 @@ def lib():
                                           C.c_int]
         L.orc_set_list_check.restype = None
         L.orc_set_list_check.argtypes = [C.c_int, C.c_double]
+        L.orc_set_frozen.restype = None
+        L.orc_set_frozen.argtypes = [C.c_void_p]
+        L.orc_phi_frozen.restype = C.c_double
+        L.orc_phi_frozen.argtypes = [C.c_int64, dp, C.c_double, C.c_double]
+        L.orc_seat.restype = C.c_int
+        L.orc_seat.argtypes = [C.c_int64, dp, C.c_double, C.c_double, C.c_uint64,
+                               C.c_int64, dp]
         L.orc_list_misses.restype = C.c_int64
         L.orc_num_threads.restype = C.c_int
         L.orc_set_threads.argtypes = [C.c_int]
@@ -148,6 +155,40 @@ def set_list_check(on, trigger_scale=1.0):
 
 def list_misses():
     return int(lib().orc_list_misses())
+
+
+_frozen_ref = None
+
+
+def set_frozen(mask):
+    """Frozen spheres (cascade stages, Sec. 4): mask[i] != 0 holds sphere i
+    fixed, its D0 an absolute diameter (see orc_set_frozen); None clears.
+    Every later energy / run / seat call uses the mask until cleared."""
+    global _frozen_ref
+    if mask is None:
+        _frozen_ref = None
+        lib().orc_set_frozen(None)
+        return
+    _frozen_ref = np.ascontiguousarray(mask, dtype=np.uint8)
+    lib().orc_set_frozen(_frozen_ref.ctypes.data)
+
+
+def phi_frozen(d0, L, kappa):
+    d0 = _vec(d0)
+    assert _frozen_ref is not None and _frozen_ref.shape[0] == d0.shape[0]
+    return lib().orc_phi_frozen(d0.shape[0], _d(d0), L, kappa)
+
+
+def seat(x, d0, L, kappa0, seed, max_attempts=1 << 20):
+    """Seat the spheres that are not frozen in the voids of the frozen ones
+    (see orc_seat); x holds the frozen positions; returns the new (n, 3)."""
+    d0 = _vec(d0)
+    assert _frozen_ref is not None and _frozen_ref.shape[0] == d0.shape[0]
+    x = _pos(x).copy()
+    rc = lib().orc_seat(d0.shape[0], _d(d0), L, kappa0, seed, max_attempts, _d(x))
+    if rc != 0:
+        raise RuntimeError("seating failed: a sphere exceeded %d attempts" % max_attempts)
+    return x
 
 
 def set_threads(n):
@@ -394,3 +435,60 @@ def time_iterations(x, d0, L, kappa, eta_x, iters, s=0.1, g=0.02, threads=0):
     t = lib().orc_time_iterations(d0.shape[0], _d(x), _d(d0), L, kappa, 0.0,
                                   eta_x, s, g, iters, _l(npairs), int(threads))
     return t, int(npairs[0])
+
+
+# ---------------------------------------------------------------- cascade
+def cascade_counts(n1, rho, n_classes, phi1=0.6435):
+    """Class counts of the ideal void-filling cascade (Eq. (cascade)): class
+    c + 1 fills the voids left by classes 1..c, a fraction (1 - phi1)^c of
+    the volume, at the monodisperse fraction phi1, with spheres rho^c times
+    smaller in diameter than class 1, so n_(c+1) = n1 ((1 - phi1) rho^3)^c."""
+    return [int(round(n1 * ((1.0 - phi1) * rho ** 3) ** c)) for c in range(n_classes)]
+
+
+def cascade(n1, rho, n_classes, seed, phi0=0.05, s=0.1, g=0.02, counts=None):
+    """The sequential multimodal cascade (Sec. 4) as our reading takes it:
+    the coarsest class alone is packed by the plain protocol from a random
+    sequential addition at phi0 (D0 = 1); then for each finer class c the
+    spheres packed so far are frozen at their diameters, and the new class
+    (count from cascade_counts, nominal diameter D0 = the previous class's
+    mean diameter / rho) is seated in their voids at the scale kappa0 =
+    (phi0 / 0.6435)^(1/3), the dilution of the protocol's own start
+    relative to the monodisperse packing, and inflated by the protocol
+    (default schedule for the new class alone); then every sphere is
+    released: the plain protocol on all of them (D0 = their diameters,
+    kappa from 1, default schedule for the whole set) down to the shrink.
+    Returns (phi after each class, counts)."""
+    counts = cascade_counts(n1, rho, n_classes) if counts is None else counts
+    d = np.ones(counts[0])
+    L = float((np.pi / 6.0 * np.sum(d ** 3) / phi0) ** (1.0 / 3.0))
+    x = rsa(d, L, 1.0, seed)
+    st = RunState(x, d, L, 1.0)
+    _, res, _ = run(st, default_params(d, 1.0, s, g), default_schedule(counts[0], S=1.0))
+    phis = [res.phi]
+    sig = d * res.kappa_shrunk
+    cls = np.zeros(counts[0], np.int64)
+    x = st.x
+    kappa_seat = (phi0 / 0.6435) ** (1.0 / 3.0)
+    for c in range(1, n_classes):
+        nc, nf = counts[c], sig.shape[0]
+        dn = float(np.mean(sig[cls == c - 1])) / rho
+        d0 = np.concatenate([sig, np.full(nc, dn)])
+        mask = np.concatenate([np.ones(nf, np.uint8), np.zeros(nc, np.uint8)])
+        set_frozen(mask)
+        try:
+            xs = seat(np.concatenate([x, np.zeros((nc, 3))]), d0, L, kappa_seat, seed)
+            st = RunState(xs, d0, L, kappa_seat)
+            run(st, default_params(d0[nf:], kappa_seat, s, g), default_schedule(nc, S=1.0))
+            kf = float(st.kappa[0])
+        finally:
+            set_frozen(None)
+        sig = np.concatenate([sig, kf * d0[nf:]])
+        cls = np.concatenate([cls, np.full(nc, c)])
+        st = RunState(st.x, sig, L, 1.0)
+        _, res, _ = run(st, default_params(sig, 1.0, s, g),
+                        default_schedule(sig.shape[0], S=float(sig.max() / sig.min())))
+        phis.append(res.phi)
+        sig = sig * res.kappa_shrunk
+        x = st.x
+    return phis, counts

@@ -24,7 +24,11 @@
  *     cell-list placement without overlap; the algorithm is our reading);
  *   - candidate pairs: brute force O(N^2), per-row brute force for subsets,
  *     and a plain size-class cell list (App. A uses a k-d tree; any method
- *     that returns the same pair set is equivalent).
+ *     that returns the same pair set is equivalent);
+ *   - frozen spheres for the stages of the sequential multimodal cascade
+ *     (Sec. 4): a frozen sphere keeps its position and an absolute
+ *     diameter while the other spheres inflate (see orc_set_frozen), and
+ *     the seating of a new class in the voids of the frozen ones.
  *
  * Floating point: compiled with -ffp-contract=off; every quantity is double.
  * Sums of many terms (energy, kappa gradient) use Neumaier compensation.
@@ -360,6 +364,35 @@ int64_t orc_pairs_cells(int64_t n, const double *x, const double *d0, double L,
 }
 
 /* ------------------------------------------------------------------ */
+/* Frozen spheres (Sec. 4, the sequential multimodal cascade)          */
+/* ------------------------------------------------------------------ */
+/* A cascade stage seats a finer class in the voids of the coarser ones
+ * and inflates it with the coarser classes held fixed.  Our reading of
+ * "held fixed": a frozen sphere keeps its position and its diameter,
+ * given as an absolute value in D0 (it does not scale with kappa); the
+ * other spheres have D = kappa D0 as in Eq. (energy).  With
+ *   sigma_i = D0_i (frozen) or kappa D0_i,   d_ij = (sigma_i + sigma_j) / 2,
+ *   E = 1/2 sum delta^2 - mu kappa sum_{i not frozen} D0_i,
+ * the position gradient keeps its form and
+ *   dE/dkappa = sum_pairs delta (r / d^2) w_ij - mu sum_{not frozen} D0_i,
+ *   w_ij = dd_ij / dkappa = (g_i D0_i + g_j D0_j) / 2,
+ * g = 0 for a frozen sphere and 1 otherwise.  Frozen spheres take no Adam
+ * step.  With no mask set (the default) nothing is frozen and every
+ * function below is the plain protocol. */
+static const unsigned char *g_frozen = NULL;
+
+void orc_set_frozen(const unsigned char *mask) { g_frozen = mask; }
+
+static inline int frozen(int64_t i) { return g_frozen != NULL && g_frozen[i] != 0; }
+
+static inline double sigma(const double *d0, int64_t i, double kappa)
+{
+    return frozen(i) ? d0[i] : kappa * d0[i];
+}
+
+static inline double wgrow(const double *d0, int64_t i) { return frozen(i) ? 0.0 : d0[i]; }
+
+/* ------------------------------------------------------------------ */
 /* Energy and gradient                                                 */
 /* ------------------------------------------------------------------ */
 typedef struct { double s, c; } nsum_t;   /* Neumaier running sum */
@@ -394,11 +427,15 @@ void orc_energy_grad(int64_t n, const double *x, const double *d0, double L,
         double dx, dy, dz;
         double r2 = sep2(x, i, j, L, hL, &dx, &dy, &dz);
         double r = sqrt(r2);
-        double d = kappa * (0.5 * (d0[i] + d0[j]));
+        double d = g_frozen ? 0.5 * (sigma(d0, i, kappa) + sigma(d0, j, kappa))
+                            : kappa * (0.5 * (d0[i] + d0[j]));
         if (!(r < d)) continue;
         double delta = 1.0 - r / d;
         nadd(&E, 0.5 * delta * delta);
-        nadd(&S, delta * r / d);
+        if (g_frozen)   /* the pair's dE/dkappa: delta (r / d^2) w_ij */
+            nadd(&S, delta * (r / d) * ((0.5 * (wgrow(d0, i) + wgrow(d0, j))) / d));
+        else
+            nadd(&S, delta * r / d);
         if (delta > maxd) maxd = delta;
         ++nov;
         if (r > 0.0) {
@@ -413,10 +450,10 @@ void orc_energy_grad(int64_t n, const double *x, const double *d0, double L,
             }
         }
     }
-    for (int64_t i = 0; i < n; ++i) nadd(&D, d0[i]);
+    for (int64_t i = 0; i < n; ++i) nadd(&D, wgrow(d0, i));
     out[0] = nval(&E);
     out[1] = -mu * kappa * nval(&D);
-    out[2] = nval(&S) / kappa;
+    out[2] = g_frozen ? nval(&S) : nval(&S) / kappa;
     out[3] = -mu * nval(&D);
     out[4] = maxd;
     out[5] = (double)nov;
@@ -502,6 +539,68 @@ double orc_phi(int64_t n, const double *d0, double L, double kappa)
     nsum_t s = {0, 0};
     for (int64_t i = 0; i < n; ++i) nadd(&s, d0[i] * d0[i] * d0[i]);
     return (M_PI / 6.0) * (kappa * kappa * kappa) * nval(&s) / (L * L * L);
+}
+
+/* Volume fraction with the frozen mask: sum over i of sigma_i^3. */
+double orc_phi_frozen(int64_t n, const double *d0, double L, double kappa)
+{
+    nsum_t s = {0, 0};
+    for (int64_t i = 0; i < n; ++i) {
+        const double si = sigma(d0, i, kappa);
+        nadd(&s, si * si * si);
+    }
+    return (M_PI / 6.0) * nval(&s) / (L * L * L);
+}
+
+/* Seating of a new class (Sec. 4: the finer class is seated in the voids
+ * left by the coarser ones).  Every sphere i that is not frozen is placed
+ * on its own: attempt a proposes p = (u(seed,i,a,0) L, u(seed,i,a,1) L,
+ * u(seed,i,a,2) L) and is accepted when no frozen sphere j overlaps it at
+ * the seating scale, r^2 < dd^2 with dd = (D0_j + kappa0 D0_i) / 2 and the
+ * separation x_j - p (minimum image).  Spheres that are not frozen may
+ * overlap one another (the inflation that follows separates them).
+ * x holds the frozen positions on input.  Returns 0, or -1 when a sphere
+ * needs more than max_attempts.  Brute force over the frozen spheres. */
+int orc_seat(int64_t n, const double *d0, double L, double kappa0, uint64_t seed,
+             int64_t max_attempts, double *x)
+{
+    const double hL = 0.5 * L;
+    int64_t nf = 0;
+    for (int64_t j = 0; j < n; ++j) nf += frozen(j);
+    int64_t *fz = malloc(sizeof(int64_t) * (size_t)(nf > 0 ? nf : 1));
+    nf = 0;
+    for (int64_t j = 0; j < n; ++j)
+        if (frozen(j)) fz[nf++] = j;
+    int rc = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(min : rc)
+    for (int64_t i = 0; i < n; ++i) {
+        if (frozen(i)) continue;
+        int64_t a;
+        for (a = 0; a < max_attempts; ++a) {
+            double p[3];
+            for (int ax = 0; ax < 3; ++ax) {
+                p[ax] = orc_u01(seed, (uint64_t)i, (uint64_t)a, ax) * L;
+                if (p[ax] >= L) p[ax] -= L;
+            }
+            int ok = 1;
+            for (int64_t q = 0; q < nf && ok; ++q) {
+                const int64_t j = fz[q];
+                double dx = mimg(x[3 * j] - p[0], L, hL);
+                double dy = mimg(x[3 * j + 1] - p[1], L, hL);
+                double dz = mimg(x[3 * j + 2] - p[2], L, hL);
+                double r2 = (dx * dx + dy * dy) + dz * dz;
+                double dd = 0.5 * (d0[j] + kappa0 * d0[i]);
+                if (r2 < dd * dd) ok = 0;
+            }
+            if (ok) {
+                for (int ax = 0; ax < 3; ++ax) x[3 * i + ax] = p[ax];
+                break;
+            }
+        }
+        if (a == max_attempts) rc = -1;
+    }
+    free(fz);
+    return rc;
 }
 
 /* ------------------------------------------------------------------ */
@@ -785,8 +884,11 @@ typedef struct {
                                 |pair contributions| over the evaluations */
 } run_t;
 
+/* With frozen spheres (absolute D0) the list is built at scale
+ * max(kappa, 1): every cutoff is then at least the contact distance. */
 static void run_rebuild(run_t *R, double kappa, const orc_params *P)
 {
+    if (g_frozen && kappa < 1.0) kappa = 1.0;
     free(R->pi); free(R->pj); free(R->rp); free(R->col);
     if (R->n <= 2048) {
         int64_t cap = 1024, np;
@@ -824,7 +926,7 @@ static void list_check(const run_t *R, double kappa)
         for (int64_t j = i + 1; j < n; ++j) {
             double dx, dy, dz;
             double r2 = sep2(R->x, i, j, R->L, R->hL, &dx, &dy, &dz);
-            double d = kappa * (0.5 * (R->d0[i] + R->d0[j]));
+            double d = 0.5 * (sigma(R->d0, i, kappa) + sigma(R->d0, j, kappa));
             if (r2 < d * d && !in[i * n + j]) ++g_list_misses;
         }
     free(in);
@@ -846,11 +948,16 @@ static void run_grad(run_t *R, double kappa, double *Eov, double *Sdrd,
             double dx, dy, dz;
             double r2 = sep2(R->x, i, j, R->L, R->hL, &dx, &dy, &dz);
             double r = sqrt(r2);
-            double d = kappa * (0.5 * (R->d0[i] + R->d0[j]));
+            double d = g_frozen ? 0.5 * (sigma(R->d0, i, kappa) + sigma(R->d0, j, kappa))
+                                : kappa * (0.5 * (R->d0[i] + R->d0[j]));
             if (!(r < d)) continue;
             double delta = 1.0 - r / d;
             e += 0.25 * delta * delta;    /* each pair appears in two rows */
-            s += 0.5 * (delta * r / d);
+            if (g_frozen)   /* half the pair's dE/dkappa (see orc_set_frozen) */
+                s += 0.5 * (delta * (r / d) *
+                            ((0.5 * (wgrow(R->d0, i) + wgrow(R->d0, j))) / d));
+            else
+                s += 0.5 * (delta * r / d);
             if (delta > m) m = delta;
             if (r > 0.0) {
                 double f = delta / (d * r);
@@ -939,9 +1046,12 @@ int orc_run(int64_t n, double *x, const double *d0, double L, double *kappa,
     R.n = n; R.L = L; R.hL = 0.5 * L; R.d0 = d0; R.x = x; R.m = m; R.v = v;
     R.xref = malloc(sizeof(double) * 3 * (size_t)n);
     R.g = malloc(sizeof(double) * 3 * (size_t)n);
-    R.d0min = d0[0];
+    /* schedule scales (sum D0, N_v, D0_min) over the spheres that are not
+     * frozen: they alone inflate and move */
+    R.d0min = INFINITY;
     nsum_t sd = {0, 0}, s3 = {0, 0}, s6 = {0, 0};
     for (int64_t i = 0; i < n; ++i) {
+        if (frozen(i)) continue;
         if (d0[i] < R.d0min) R.d0min = d0[i];
         nadd(&sd, d0[i]);
         const double c3 = d0[i] * d0[i] * d0[i];
@@ -975,11 +1085,12 @@ int orc_run(int64_t n, double *x, const double *d0, double L, double *kappa,
             trace[3 * it] = maxd; trace[3 * it + 1] = *kappa; trace[3 * it + 2] = Eov;
         }
         if (r == S->n_rungs - 1 && maxd < S->tol) { status = 0; break; }
-        double gk = Sdrd / *kappa - mu * R.sumd0;
+        double gk = g_frozen ? Sdrd - mu * R.sumd0 : Sdrd / *kappa - mu * R.sumd0;
         t += 1;
         b1t *= b1; b2t *= b2;
 #pragma omp parallel for schedule(static)
         for (int64_t q = 0; q < 3 * n; ++q) {
+            if (frozen(q / 3)) continue;   /* held fixed: no step */
             double th = adam(x[q], R.g[q], &m[q], &v[q], b1, b2, b1t, b2t, ex,
                              P->eps_x);
             if (th < 0.0) th += L;
@@ -1027,9 +1138,16 @@ int orc_run(int64_t n, double *x, const double *d0, double L, double *kappa,
             res->energy = Eov;
         }
         res->max_overlap = maxd;
-        double kp = orc_shrink(n, x, d0, L, *kappa, R.np, R.pi, R.pj);
-        res->kappa_shrunk = kp;
-        res->phi = orc_phi(n, d0, L, kp);
+        if (g_frozen) {
+            /* a cascade stage: no shrink (the release that follows resolves
+             * the remaining overlaps below the tolerance) */
+            res->kappa_shrunk = *kappa;
+            res->phi = orc_phi_frozen(n, d0, L, *kappa);
+        } else {
+            double kp = orc_shrink(n, x, d0, L, *kappa, R.np, R.pi, R.pj);
+            res->kappa_shrunk = kp;
+            res->phi = orc_phi(n, d0, L, kp);
+        }
     }
     free(R.xref); free(R.g); free(R.pi); free(R.pj); free(R.rp); free(R.col);
     return status;

@@ -663,3 +663,176 @@ def test_rsa_rounds_non_overlapping_uniform_deterministic(orc, window):
         assert stats.kstest(x[:, a] / L, "uniform").pvalue > 1e-3
     # fewer rounds than spheres once a round holds several proposals
     assert nr < 3000 or window == 1
+
+
+# ------------------------------------------ frozen spheres (cascade stages)
+def test_frozen_two_sphere_hand_values(orc):
+    # a frozen sphere against a growing one (tests/golden/two_sphere_frozen.txt)
+    gd = _golden("two_sphere_frozen.txt")
+    d0 = np.array(gd["D0"])
+    L = 20.0
+    x = np.array([[10.0, 7.0, 9.0], [10.0 + gd["r"], 7.0, 9.0]])
+    pi, pj = np.array([0], np.int32), np.array([1], np.int32)
+    orc.set_frozen(np.array([1, 0], np.uint8))
+    try:
+        r = orc.energy_grad(x, d0, L, gd["kappa"], gd["mu"], pi, pj)
+        assert r["E_ov"] == pytest.approx(gd["E_overlap"], rel=1e-15)
+        assert r["gk_ov"] == pytest.approx(gd["dEdkappa_overlap"], rel=1e-15)
+        assert r["E_growth"] == pytest.approx(gd["E_growth"], rel=1e-15)
+        assert r["gk_growth"] == pytest.approx(gd["dEdkappa_growth"], rel=1e-15)
+        assert r["max_delta"] == pytest.approx(0.25, rel=1e-15)
+        assert r["g"][0, 0] == pytest.approx(gd["grad_along_line"], rel=1e-15)
+        assert r["g"][1, 0] == pytest.approx(-gd["grad_along_line"], rel=1e-15)
+        assert np.all(r["g"][:, 1:] == 0.0)
+        touch = orc.energy_grad(x, d0, L, 1.0, gd["mu"], pi, pj)
+        assert touch["E_ov"] == 0.0 and touch["n_overlap"] == 0
+        # the frozen sphere's diameter does not follow kappa: with the mask
+        # cleared the same numbers give the plain two-sphere case
+        orc.set_frozen(None)
+        plain = orc.energy_grad(x, d0, L, gd["kappa"], gd["mu"], pi, pj)
+        assert plain["E_ov"] != pytest.approx(gd["E_overlap"])
+    finally:
+        orc.set_frozen(None)
+
+
+def test_frozen_mask_of_zeros_is_the_plain_protocol(orc):
+    x, d0, L = _overlapping_case(n=120, phi=0.5)
+    pi, pj = _all_overlaps(orc, x, d0, L, 1.0)
+    ref = orc.energy_grad(x, d0, L, 1.0, 0.3, pi, pj)
+    orc.set_frozen(np.zeros(d0.shape[0], np.uint8))
+    try:
+        got = orc.energy_grad(x, d0, L, 1.0, 0.3, pi, pj)
+    finally:
+        orc.set_frozen(None)
+    for k in ("E_ov", "gk_ov", "E_growth", "gk_growth", "max_delta"):
+        assert got[k] == pytest.approx(ref[k], rel=1e-13, abs=1e-300), k
+    assert np.allclose(got["g"], ref["g"], rtol=1e-13, atol=1e-15)
+
+
+def test_frozen_energy_central_finite_differences(orc):
+    # dE/dkappa and dE/dx with a third of the spheres frozen (absolute
+    # diameters), against central differences of the energy
+    x, d0, L = _overlapping_case(n=150, phi=0.5)
+    rng = np.random.default_rng(5)
+    mask = (rng.random(d0.shape[0]) < 0.33).astype(np.uint8)
+    kappa = 1.0
+    d = d0.copy()
+    d[mask == 1] *= kappa   # the frozen ones at their size for kappa = 1
+    orc.set_frozen(mask)
+    try:
+        def E(xx, kk):
+            pi, pj = orc.pairs_brute(xx, np.where(mask == 1, d, d * kk), L, 1.0)
+            return orc.energy_grad(xx, d, L, kk, 0.3, pi, pj)
+        r = E(x, kappa)
+        assert r["n_overlap"] > 50
+        hk = 1e-7
+        Ep, Em = E(x, kappa + hk), E(x, kappa - hk)
+        fdk = ((Ep["E_ov"] + Ep["E_growth"]) - (Em["E_ov"] + Em["E_growth"])) / (2 * hk)
+        assert fdk == pytest.approx(r["gk_ov"] + r["gk_growth"], rel=1e-6)
+        h = 1e-7 * d0.min()
+        checked = 0
+        for i in rng.choice(x.shape[0], 30, replace=False):
+            for a in range(3):
+                xp, xm = x.copy(), x.copy()
+                xp[i, a] += h
+                xm[i, a] -= h
+                fd = (E(xp, kappa)["E_ov"] - E(xm, kappa)["E_ov"]) / (2 * h)
+                sc = r["gscale"][i, a]
+                if sc == 0:
+                    continue
+                assert abs(fd - r["g"][i, a]) <= 1e-6 * max(sc, abs(r["E_ov"]) * 1e-3)
+                checked += 1
+        assert checked > 20
+    finally:
+        orc.set_frozen(None)
+
+
+def test_frozen_spheres_hold_still_while_the_others_inflate(orc):
+    # a cascade stage in miniature: 10 frozen spheres, 300 small ones seated
+    # in their voids and inflated until the stop criterion
+    d = np.ones(10)
+    L = float((np.pi / 6.0 * 10 / 0.3) ** (1.0 / 3.0))
+    xb = orc.rsa(d, L, 1.0, 4)
+    d0 = np.concatenate([d, np.full(300, 0.2)])
+    mask = np.concatenate([np.ones(10, np.uint8), np.zeros(300, np.uint8)])
+    orc.set_frozen(mask)
+    try:
+        xs = orc.seat(np.concatenate([xb, np.zeros((300, 3))]), d0, L, 0.4, 4)
+        assert np.array_equal(xs[:10], xb)
+        st = orc.RunState(xs, d0, L, 0.4)
+        status, res, _ = orc.run(st, orc.default_params(d0[10:], 0.4),
+                                 orc.default_schedule(300, S=1.0))
+        assert status == 0 and res.max_overlap < 5e-4
+        assert np.array_equal(st.x[:10], xb)            # positions held
+        assert np.all(st.m[:10] == 0) and np.all(st.v[:10] == 0)
+        assert st.kappa[0] > 0.4                        # the small ones grew
+        phi_f = orc.phi_frozen(d0, L, st.kappa[0])
+        big = np.pi / 6.0 * 10 / L ** 3
+        assert phi_f == pytest.approx(big + np.pi / 6.0 * 300 * (0.2 * st.kappa[0]) ** 3 / L ** 3,
+                                      rel=1e-12)
+        assert res.phi == pytest.approx(phi_f, rel=1e-15)
+    finally:
+        orc.set_frozen(None)
+
+
+def test_seating_is_the_first_free_proposal(orc):
+    # every seated sphere sits at its first proposal that overlaps no frozen
+    # sphere (checked by brute force in numpy), whatever the thread count
+    d = np.ones(12)
+    L = float((np.pi / 6.0 * 12 / 0.3) ** (1.0 / 3.0))
+    xb = orc.rsa(d, L, 1.0, 9)
+    n = 200
+    d0 = np.concatenate([d, np.full(n, 0.3)])
+    mask = np.concatenate([np.ones(12, np.uint8), np.zeros(n, np.uint8)])
+    k0 = 0.5
+    orc.set_frozen(mask)
+    try:
+        xs = orc.seat(np.concatenate([xb, np.zeros((n, 3))]), d0, L, k0, 9)
+        orc.set_threads(1)
+        xs1 = orc.seat(np.concatenate([xb, np.zeros((n, 3))]), d0, L, k0, 9)
+    finally:
+        orc.set_threads(0)
+        orc.set_frozen(None)
+    assert np.array_equal(xs, xs1)
+    hL = 0.5 * L
+    for i in range(12, 12 + n):
+        for a in range(1 << 12):
+            p = np.array([orc.u01(9, i, a, ax) * L for ax in range(3)])
+            p[p >= L] -= L
+            sep = xb - p
+            sep = np.where(sep > hL, sep - L, np.where(sep < -hL, sep + L, sep))
+            r2 = (sep[:, 0] * sep[:, 0] + sep[:, 1] * sep[:, 1]) + sep[:, 2] * sep[:, 2]
+            dd = 0.5 * (d + k0 * 0.3)
+            if np.all(r2 >= dd * dd):
+                assert np.array_equal(xs[i], p), i
+                break
+        else:
+            raise AssertionError("no free proposal for %d" % i)
+
+
+def test_cascade_counts_give_eq_cascade():
+    # with every class filling its voids at phi1 (nominal diameters
+    # rho^-c), the counts give the ideal phi_n = 1 - (1 - phi1)^n of
+    # Eq. (cascade)
+    from oracle import cascade_counts
+    phi1, rho = 0.6435, 7.0
+    n1 = 1000
+    counts = cascade_counts(n1, rho, 4, phi1)
+    V = n1 / phi1   # box volume in units of one class-1 sphere
+    for n in range(1, 5):
+        vol = sum(counts[c] * rho ** (-3 * c) for c in range(n))
+        assert vol / V == pytest.approx(1.0 - (1.0 - phi1) ** n, rel=2e-3)
+
+
+@pytest.mark.slow
+def test_binary_cascade_fills_the_voids(orc):
+    # Table (tab:cascade): one class packs near 0.62-0.64, two classes at a
+    # diameter ratio of about 7 near 0.80 (0.800 printed for 30-60 coarse
+    # spheres); a cascade of 8 coarse spheres lands in the same range, and
+    # the second class raises phi by far more than a monodisperse packing's
+    # finite-size scatter
+    phis, counts = orc.cascade(8, 7.0, 2, seed=0)
+    assert counts == [8, 978]
+    assert 0.58 < phis[0] < 0.70
+    assert 0.74 < phis[1] < 0.85
+    assert phis[1] - phis[0] > 0.1
