@@ -272,6 +272,37 @@ int rcp_pack_init(int dim, const double *box, int64_t n, const double *d0,
  * more than 2^22 attempts. */
 int rcp_place_device(rcp_ctx *ctx, int k, uint64_t seed, int64_t window, int64_t *rounds);
 
+/* Frozen spheres, for the stages of the sequential multimodal cascade
+ * (Sec. 4: a finer class is seated in the voids of the coarser ones and
+ * inflated with the coarser classes held fixed).  mask: n bytes in user
+ * order (host, copied); mask[i] != 0 freezes sphere i: its D0 (as given at
+ * creation) is then an absolute diameter that does not scale with kappa,
+ * and it takes no Adam step; the others keep D = kappa D0.  The energy of
+ * Eq. (energy) becomes E = 1/2 sum delta^2 - mu kappa sum over the spheres
+ * not frozen of D0, with d_ij = (sigma_i + sigma_j) / 2 (sigma = D0 frozen,
+ * kappa D0 otherwise), and dE/dkappa = sum delta (r / d^2) dd_ij/dkappa -
+ * mu sum D0 over the spheres not frozen; the relative schedule's scales
+ * (sum D0, N_v, D0_min) are taken over the spheres not frozen.  Lists are
+ * built at max(kappa, 1).  No shrink is done for such a packing: its
+ * result reports kappa and phi as they are (the release that follows, a
+ * new context with every sphere free, ends with the shrink).  mask = NULL
+ * (or all zero) frees every sphere.  While any packing of the context has
+ * frozen spheres, the iteration uses the two-gather kernel whatever the
+ * tuning variant, and the tail is not fused.  RCP_EINVAL when every sphere
+ * would be frozen. */
+int rcp_set_frozen(rcp_ctx *ctx, int k, const uint8_t *mask);
+
+/* Seating of a new class in the voids of the frozen spheres (Sec. 4): every
+ * sphere of packing k that is not frozen gets, independently, its first
+ * proposal of the placement counter stream (the one of rcp_place_device,
+ * attempt a = 0, 1, ...) that overlaps no frozen sphere at the seating scale
+ * kappa0: r^2 < ((D_frozen + kappa0 D0_i) / 2)^2 rejects.  Spheres that are not
+ * frozen may overlap one another (the inflation that follows separates
+ * them).  Frozen positions are kept; then the state is set as by
+ * rcp_set_state(positions, kappa0).  RCP_EINVAL for kappa0 <= 0 or
+ * max_attempts < 1, RCP_EPLACE when a sphere needs more than max_attempts. */
+int rcp_seat_device(rcp_ctx *ctx, int k, double kappa0, uint64_t seed, int64_t max_attempts);
+
 /* Replace the launch tuning (see rcp_tuning); RCP_EINVAL for values out of
  * range.  A captured graph is re-captured at the next iteration.  Tuning
  * changes launch shapes only; the method (App. A) is unchanged. */

@@ -446,6 +446,20 @@ def cascade_counts(n1, rho, n_classes, phi1=0.6435):
     return [int(round(n1 * ((1.0 - phi1) * rho ** 3) ** c)) for c in range(n_classes)]
 
 
+def release_schedule(N, S):
+    """The release of a cascade stage (Sec. 4: every sphere relaxes
+    together, the numerical analogue of vibration): the final relaxation
+    rung of the default schedule for the whole set (mu annealed towards 0,
+    the stop criterion, cap 2 n_trig), as one rung."""
+    d = default_schedule(N, S=S)
+    r = d.n_rungs - 1
+    Sc = Schedule()
+    Sc.n_rungs, Sc.absolute, Sc.tol = 1, 0, d.tol
+    Sc.mu[0], Sc.eta_x[0], Sc.eta_k[0] = d.mu[r], d.eta_x[r], d.eta_k[r]
+    Sc.decay[0], Sc.budget[0] = d.decay[r], d.budget[r]
+    return Sc
+
+
 def cascade(n1, rho, n_classes, seed, phi0=0.05, s=0.1, g=0.02, counts=None):
     """The sequential multimodal cascade (Sec. 4) as our reading takes it:
     the coarsest class alone is packed by the plain protocol from a random
@@ -456,8 +470,9 @@ def cascade(n1, rho, n_classes, seed, phi0=0.05, s=0.1, g=0.02, counts=None):
     (phi0 / 0.6435)^(1/3), the dilution of the protocol's own start
     relative to the monodisperse packing, and inflated by the protocol
     (default schedule for the new class alone); then every sphere is
-    released: the plain protocol on all of them (D0 = their diameters,
-    kappa from 1, default schedule for the whole set) down to the shrink.
+    released: all of them relax together (D0 = their diameters, kappa from
+    1) under the final relaxation rung of the default schedule for the
+    whole set (release_schedule), down to the stop and the shrink.
     Returns (phi after each class, counts)."""
     counts = cascade_counts(n1, rho, n_classes) if counts is None else counts
     d = np.ones(counts[0])
@@ -487,7 +502,7 @@ def cascade(n1, rho, n_classes, seed, phi0=0.05, s=0.1, g=0.02, counts=None):
         cls = np.concatenate([cls, np.full(nc, c)])
         st = RunState(st.x, sig, L, 1.0)
         _, res, _ = run(st, default_params(sig, 1.0, s, g),
-                        default_schedule(sig.shape[0], S=float(sig.max() / sig.min())))
+                        release_schedule(sig.shape[0], float(sig.max() / sig.min())))
         phis.append(res.phi)
         sig = sig * res.kappa_shrunk
         x = st.x

@@ -223,6 +223,22 @@ class Packing:
         check(lib().rcp_run_continue(self._h, int(n_iters), C.byref(act)))
         return act.value
 
+    def set_frozen(self, mask, k=0):
+        """Freeze spheres (mask[i] != 0) of packing k for a cascade stage:
+        their D0 becomes an absolute diameter, they take no step; None frees
+        every sphere."""
+        if mask is None:
+            check(lib().rcp_set_frozen(self._h, k, None))
+            return
+        m = np.ascontiguousarray(mask, dtype=np.uint8)
+        assert m.shape[0] == self.n[k]
+        check(lib().rcp_set_frozen(self._h, k, m.ctypes.data))
+
+    def seat(self, kappa0, seed, max_attempts=1 << 22, k=0):
+        """Seat the spheres that are not frozen in the voids of the frozen
+        ones at scale kappa0 (then kappa = kappa0)."""
+        check(lib().rcp_seat_device(self._h, k, float(kappa0), int(seed), int(max_attempts)))
+
     def run_prepare(self):
         """Capture the iteration graph ahead of the next run_continue."""
         check(lib().rcp_run_prepare(self._h))

@@ -97,7 +97,14 @@ constexpr double kLoose = 1.0 + 0x1p-50;
 // rounds them (IEEE root and quotient): then delta and the test r < d are
 // exactly the definition's, which also makes the stop test (max delta below
 // the tolerance) exact.  The factor delta / (d r) is well conditioned.
-template <bool kCount = true>
+//
+// kMixed: some spheres are frozen (a cascade stage, Sec. 4): a record with a
+// negative D0 holds a frozen sphere whose diameter is -D0 in absolute
+// units, the others have D = kappa D0.  Then d = (sigma_i + sigma_j) / 2 and
+// the pair's dE/dkappa is delta (r / d^2) dd/dkappa with dd/dkappa = (g_i D0_i
+// + g_j D0_j) / 2 (g = 0 for a frozen sphere); S gains delta q (kappa dd/dkappa
+// / d) / 2, so that S / kappa in the tail is that derivative summed.
+template <bool kCount = true, bool kMixed = false>
 __device__ __forceinline__ void pair_term(Acc &a, const P4 &qi, const P4 &qj, double kappa,
                                           double L, double iL)
 {
@@ -106,7 +113,9 @@ __device__ __forceinline__ void pair_term(Acc &a, const P4 &qi, const P4 &qj, do
     const double dy = near_image(qj.y - qi.y, L, iL);
     const double dz = near_image(qj.z - qi.z, L, iL);
     const double r2 = (dx * dx + dy * dy) + dz * dz;
-    const double d = kappa * (0.5 * (qi.d + qj.d));
+    const double d = kMixed ? 0.5 * ((qi.d > 0.0 ? kappa * qi.d : -qi.d) +
+                                     (qj.d > 0.0 ? kappa * qj.d : -qj.d))
+                            : kappa * (0.5 * (qi.d + qj.d));
     if (r2 < (d * d) * kLoose) {
         const double id = fast_rcp(d);
         double r, ir;
@@ -126,7 +135,11 @@ __device__ __forceinline__ void pair_term(Acc &a, const P4 &qi, const P4 &qj, do
         }
         if (r < d) {
             a.e += 0.25 * (delta * delta);
-            a.s += 0.5 * (delta * q);
+            if (kMixed)
+                a.s += 0.5 * (delta * q) *
+                       ((kappa * (0.5 * (fmax(qi.d, 0.0) + fmax(qj.d, 0.0)))) * id);
+            else
+                a.s += 0.5 * (delta * q);
             a.m = fmax(a.m, delta);
             if (kCount) a.c += 0.5;
             if (r > 0.0) {
@@ -233,10 +246,16 @@ __device__ __forceinline__ Pre preload(const IterPtrs &p, int64_t i)
 // coordinates: the record's D0 in the output buffer is already in place,
 // written when the list order was set; with `full` the whole record);
 // returns |x_new - x_ref|^2 (min image).
+template <bool kMixed = false>
 __device__ __forceinline__ double update_particle(const IterPtrs &p, const IterScalars &c,
                                                   int64_t i, const P4 &qi, const Pre &q,
                                                   double gx, double gy, double gz, bool full)
 {
+    if (kMixed && qi.d < 0.0) {
+        // a frozen sphere: no step, its record carried to the other buffer
+        store_p4(p.qo, (int32_t)i, qi);
+        return 0.0;
+    }
     double d2 = 0.0;
     P4 o;
     o.x = update_coord(qi.x, gx, q.m0, q.v0, q.r0, p.m0, p.v0, c, i, d2);
@@ -449,7 +468,7 @@ struct ColSrc {
 // their gathers are in flight together (kU = 2 or 4); the next step's
 // partner indices are requested before this step's terms are evaluated, so
 // their latency hides behind the arithmetic.
-template <int kU, bool kStage>
+template <int kU, bool kStage, bool kMixed = false>
 __device__ __forceinline__ void segment_terms(Acc &a, const ColSrc<kStage> &cols,
                                               const P4 *__restrict__ Q, int32_t q, int32_t qe,
                                               const P4 &qi, const IterScalars &c)
@@ -468,10 +487,10 @@ __device__ __forceinline__ void segment_terms(Acc &a, const ColSrc<kStage> &cols
                 j2 = cols.at(q + 2);
                 j3 = cols.at(q + 3);
             }
-            pair_term<false>(a, qi, q0, c.kappa, c.L, c.iL);
-            pair_term<false>(a, qi, q1, c.kappa, c.L, c.iL);
-            pair_term<false>(a, qi, q2, c.kappa, c.L, c.iL);
-            pair_term<false>(a, qi, q3, c.kappa, c.L, c.iL);
+            pair_term<false, kMixed>(a, qi, q0, c.kappa, c.L, c.iL);
+            pair_term<false, kMixed>(a, qi, q1, c.kappa, c.L, c.iL);
+            pair_term<false, kMixed>(a, qi, q2, c.kappa, c.L, c.iL);
+            pair_term<false, kMixed>(a, qi, q3, c.kappa, c.L, c.iL);
             if (!more) break;
         }
     }
@@ -485,8 +504,8 @@ __device__ __forceinline__ void segment_terms(Acc &a, const ColSrc<kStage> &cols
                 j0 = cols.at(q);
                 j1 = cols.at(q + 1);
             }
-            pair_term<false>(a, qi, q0, c.kappa, c.L, c.iL);
-            pair_term<false>(a, qi, q1, c.kappa, c.L, c.iL);
+            pair_term<false, kMixed>(a, qi, q0, c.kappa, c.L, c.iL);
+            pair_term<false, kMixed>(a, qi, q1, c.kappa, c.L, c.iL);
             if (!more) break;
         }
     }
@@ -494,10 +513,10 @@ __device__ __forceinline__ void segment_terms(Acc &a, const ColSrc<kStage> &cols
         const int32_t j0 = cols.at(q),
                       j1 = cols.at(q + 1);
         const P4 q0 = load_p4(Q, j0), q1 = load_p4(Q, j1);
-        pair_term<false>(a, qi, q0, c.kappa, c.L, c.iL);
-        pair_term<false>(a, qi, q1, c.kappa, c.L, c.iL);
+        pair_term<false, kMixed>(a, qi, q0, c.kappa, c.L, c.iL);
+        pair_term<false, kMixed>(a, qi, q1, c.kappa, c.L, c.iL);
     }
-    if (q < qe) pair_term<false>(a, qi, load_p4(Q, cols.at(q)), c.kappa, c.L, c.iL);
+    if (q < qe) pair_term<false, kMixed>(a, qi, load_p4(Q, cols.at(q)), c.kappa, c.L, c.iL);
 }
 
 template <int kN>
@@ -535,7 +554,8 @@ struct NoHook {
 // timing.  Phase 2: one thread per row applies Adam (coalesced).  hook() runs
 // between the phases (the persistent kernel prefetches there).  Thread 0
 // writes the item's partial sums to *out.  Every thread must call it.
-template <int kU, bool kEarly, bool kStage, int kR, class Hook, bool kCoherentOut = false>
+template <int kU, bool kEarly, bool kStage, int kR, class Hook, bool kCoherentOut = false,
+          bool kMixed = false>
 __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &c, int64_t r0,
                                           int nrow, int32_t e0, int32_t e1,
                                           const int32_t *rp_own, int32_t rp_end,
@@ -593,7 +613,7 @@ __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &
             const P4 qi = load_p4(Q, (int32_t)(r0 + r));
             const int32_t rend = L.srp[r + 1], qe = min(rend, ce);
             a.gx = a.gy = a.gz = 0.0;
-            segment_terms<kU, kStage>(a, cols, Q, q, qe, qi, c);
+            segment_terms<kU, kStage, kMixed>(a, cols, Q, q, qe, qi, c);
             const bool began_before = L.srp[r] < cs, goes_on = rend > ce;
             if (began_before) store3<kBlock>(L.A, t, a);
             else if (goes_on) store3<kBlock>(L.B, t, a);
@@ -634,7 +654,7 @@ __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &
                 }
             }
         }
-        bd = fmax(bd, update_particle(p, c, io, oq, pre, g[0], g[1], g[2], full));
+        bd = fmax(bd, update_particle<kMixed>(p, c, io, oq, pre, g[0], g[1], g[2], full));
     }
     // block reduction of the four partials
     const int lane = t & (kWave - 1);
@@ -692,7 +712,7 @@ __device__ __forceinline__ void load_scalars(const SegState *s, IterScalars &c)
 
 // One block per work item; kWaves > 1 asks the compiler for that many
 // waves per SIMD (fewer registers, a little spilling).
-template <bool kFusedTail, int kU, bool kEarly, bool kStage, int kWaves>
+template <bool kFusedTail, int kU, bool kEarly, bool kStage, int kWaves, bool kMixed = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))) void k_iterate(const SegPtrs *__restrict__ P,
                                                    SegState *__restrict__ S,
                                                    const WorkItem *__restrict__ W,
@@ -712,7 +732,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
     const int nrow = (int)(w.end - w.begin);
     const int32_t rp_t = t < nrow ? gload(p.rp, r0 + t) : 0;
     const int32_t rp_end = gload(p.rp, r0 + nrow);
-    item_body<kU, kEarly, kStage, kBlock, NoHook, kFusedTail>(
+    item_body<kU, kEarly, kStage, kBlock, NoHook, kFusedTail, kMixed>(
         p, c, r0, nrow, w.e0, w.e1, &rp_t, rp_end, L, scol,
         reinterpret_cast<Part4 *>(partials) + b, NoHook(), (flags & 4) != 0);
     if (kFusedTail) {
@@ -848,12 +868,12 @@ __global__ __launch_bounds__(kBlock) void k_iterate_persist(const SegPtrs *__res
     }
 }
 
-template <bool kF, int kU, bool kE, bool kNT, int kW>
+template <bool kF, int kU, bool kE, bool kNT, int kW, bool kMixed = false>
 static void launch_one(const SegPtrs *P, SegState *S, const WorkItem *W, double *partials,
                        int nitems, int f, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_iterate<kF, kU, kE, kNT, kW>), dim3(nitems), dim3(kBlock), 0, st, P, S,
-                       W, partials, f);
+    hipLaunchKernelGGL((k_iterate<kF, kU, kE, kNT, kW, kMixed>), dim3(nitems), dim3(kBlock), 0,
+                       st, P, S, W, partials, f);
 }
 
 template <bool kF, int kW>
@@ -908,9 +928,12 @@ void launch_iterate(const SegPtrs *P, SegState *S, const WorkItem *W, double *pa
                     int nitems, int flags, hipStream_t st)
 {
     // bit 0: XCD-aware order; bit 1: fused tail; bit 2: whole 32-byte
-    // records written; bits 8-13: kernel variant (see launch_variant)
+    // records written; bit 4: some packing has frozen spheres (then the
+    // two-gather kernel with the mixed pair terms runs, whatever the
+    // variant); bits 8-13: kernel variant (see launch_variant)
     const int f = flags & 5, variant = (flags >> 8) & 63;
-    if (variant & 40) launch_variant<false>(P, S, W, partials, nitems, f, variant, st);
+    if (flags & 16) launch_one<false, 2, false, false, 1, true>(P, S, W, partials, nitems, f, st);
+    else if (variant & 40) launch_variant<false>(P, S, W, partials, nitems, f, variant, st);
     else if (flags & 2) launch_variant<true>(P, S, W, partials, nitems, f, variant, st);
     else launch_variant<false>(P, S, W, partials, nitems, f, variant, st);
 }
@@ -1169,7 +1192,12 @@ __global__ __launch_bounds__(kBlock) void k_eval(const SegPtrs *__restrict__ P,
         };
         const P4 qi = pos(i);
         Acc a = {0, 0, 0, 0, 0, 0, 0};
-        for (int32_t q = p.rp[i]; q < p.rp[i + 1]; ++q) pair_term(a, qi, pos(p.col[q]), kappa, L, iL);
+        if (s->mixed)
+            for (int32_t q = p.rp[i]; q < p.rp[i + 1]; ++q)
+                pair_term<true, true>(a, qi, pos(p.col[q]), kappa, L, iL);
+        else
+            for (int32_t q = p.rp[i]; q < p.rp[i + 1]; ++q)
+                pair_term(a, qi, pos(p.col[q]), kappa, L, iL);
         be = a.e;
         bs = a.s;
         bm = a.m;
@@ -1284,6 +1312,26 @@ void launch_disp(const SegPtrs *P, const SegState *S, int seg, int64_t n, const 
                  double *part, int nblocks, hipStream_t st)
 {
     hipLaunchKernelGGL(k_disp, dim3(nblocks), dim3(kBlock), 0, st, P, S, seg, n, xu, part);
+}
+
+__global__ __launch_bounds__(kBlock) void k_set_frozen(const SegPtrs *__restrict__ P, int seg,
+                                                      int64_t n, const uint8_t *__restrict__ mask)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const SegPtrs &p = P[seg];
+    const bool f = mask[p.orig[i]] != 0;
+    for (int b = 0; b < 2; ++b) {
+        const double d = fabs(p.p[b][i].d);
+        p.p[b][i].d = f ? -d : d;
+    }
+}
+
+void launch_set_frozen(const SegPtrs *P, int seg, int64_t n, const uint8_t *mask, hipStream_t st)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_set_frozen, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
+                           0, st, P, seg, n, mask);
 }
 
 __global__ __launch_bounds__(kBlock) void k_set_positions(const SegPtrs *__restrict__ P,

@@ -237,7 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_search(BuildArgs a, uint64_t *__rest
     const int64_t i = (int64_t)blk * kBlock + threadIdx.x;
     if (i < a.n) {
         const P4 qi = a.pos[i];
-        const double xi = qi.x, yi = qi.y, zi = qi.z, di = qi.d;
+        const double xi = qi.x, yi = qi.y, zi = qi.z, di = fabs(qi.d);
         const int li = a.lev[i];
         const uint64_t rowi = (uint64_t)i << row_bits;
         for (int L = li; L < a.nlev; ++L) {
@@ -325,7 +325,7 @@ __global__ __launch_bounds__(kBlock) void k_search(BuildArgs a, uint64_t *__rest
                             const double dy = min_image(qj.y - yi, a.L, a.hL);
                             const double dz = min_image(qj.z - zi, a.L, a.hL);
                             const double r2 = (dx * dx + dy * dy) + dz * dz;
-                            const double cc = a.kb * (a.opg * (0.5 * (di + qj.d)) + a.sk2);
+                            const double cc = a.kb * (a.opg * (0.5 * (di + fabs(qj.d))) + a.sk2);
                             if (r2 < cc * cc) {
                                 const uint64_t e0 = rowi | (uint64_t)j;
                                 const uint64_t e1 = ((uint64_t)j << row_bits) | (uint64_t)i;
@@ -718,7 +718,7 @@ __device__ __forceinline__ void test_plane(const BuildArgs &a, const SearchOut &
             const double dy = min_image(qj.y - oq.y, a.L, a.hL);
             const double dz = min_image(qj.z - oq.z, a.L, a.hL);
             const double r2 = (dx * dx + dy * dy) + dz * dz;
-            const double cc = a.kb * (a.opg * (0.5 * (oq.d + qj.d)) + a.sk2);
+            const double cc = a.kb * (a.opg * (0.5 * (fabs(oq.d) + fabs(qj.d))) + a.sk2);
             hit = r2 < cc * cc;
         }
         const uint64_t bal = __ballot(hit);
@@ -783,7 +783,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         xi = qi.x;
         yi = qi.y;
         zi = qi.z;
-        di = qi.d;
+        di = fabs(qi.d);
         li = gload(a.lev, i);
     }
     own[threadIdx.x] = P4{xi, yi, zi, di};

@@ -220,6 +220,68 @@ __global__ __launch_bounds__(kBlock) void k_place_commit(PlaceArgs a, int c, int
     }
 }
 
+// Seating (a cascade stage, Sec. 4: the finer class is seated in the voids
+// of the coarser ones): each sphere on its own, its first proposal of the
+// placement counter stream that overlaps no frozen sphere, r^2 < dd^2 with
+// dd = (D_j + kappa0 D0_i) / 2 and the separation x_j - p (minimum image).
+__global__ __launch_bounds__(kBlock) void k_seat(SeatArgs a, int64_t ng)
+{
+#pragma clang fp contract(off)
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= ng) return;
+    const int32_t i = a.gidx[t];
+    const double di = a.gd[t];
+    const int64_t nc = a.nc;
+    const int64_t lo3 = nc >= 3 ? -1 : 0, hi3 = nc >= 3 ? 1 : nc - 1;
+    for (int64_t att = 0; att < a.max_attempts; ++att) {
+        double p[3];
+        for (int ax = 0; ax < 3; ++ax) {
+            double v = place_u01(a.seed, (uint64_t)i, (uint64_t)att, ax) * a.L;
+            if (v >= a.L) v -= a.L;
+            p[ax] = v;
+        }
+        const int64_t cx = place_cell(p[0], a.inv_w, nc), cy = place_cell(p[1], a.inv_w, nc),
+                      cz = place_cell(p[2], a.inv_w, nc);
+        bool ok = true;
+        for (int64_t ox = lo3; ox <= hi3 && ok; ++ox)
+            for (int64_t oy = lo3; oy <= hi3 && ok; ++oy)
+                for (int64_t oz = lo3; oz <= hi3 && ok; ++oz) {
+                    int64_t ax = cx + ox, ay = cy + oy, az = cz + oz;
+                    if (nc >= 3) {
+                        ax = ax < 0 ? ax + nc : (ax >= nc ? ax - nc : ax);
+                        ay = ay < 0 ? ay + nc : (ay >= nc ? ay - nc : ay);
+                        az = az < 0 ? az + nc : (az >= nc ? az - nc : az);
+                    }
+                    const int64_t q = (ax * nc + ay) * nc + az;
+                    for (int32_t o = a.start[q]; o < a.start[q + 1]; ++o) {
+                        const double dx = place_mi(a.fxd[4 * o] - p[0], a.L, a.hL);
+                        const double dy = place_mi(a.fxd[4 * o + 1] - p[1], a.L, a.hL);
+                        const double dz = place_mi(a.fxd[4 * o + 2] - p[2], a.L, a.hL);
+                        const double r2 = (dx * dx + dy * dy) + dz * dz;
+                        const double dd = 0.5 * (a.fxd[4 * o + 3] + a.kappa0 * di);
+                        if (r2 < dd * dd) {
+                            ok = false;
+                            break;
+                        }
+                    }
+                }
+        if (ok) {
+            a.x[3 * (int64_t)i] = p[0];
+            a.x[3 * (int64_t)i + 1] = p[1];
+            a.x[3 * (int64_t)i + 2] = p[2];
+            return;
+        }
+    }
+    atomicOr(a.fail, 1);
+}
+
+void launch_seat(const SeatArgs &a, int64_t ng, hipStream_t st)
+{
+    if (ng <= 0) return;
+    hipLaunchKernelGGL(k_seat, dim3((unsigned)((ng + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                       a, ng);
+}
+
 void launch_place_round(const PlaceArgs &a, int c, int64_t lo, int64_t hi, hipStream_t st)
 {
     const int64_t w = hi - lo;

@@ -38,7 +38,8 @@ struct SchedDev {
 };
 
 // Position and relative diameter of one particle, 32 bytes: a neighbour
-// gather touches a single cache line.
+// gather touches a single cache line.  A frozen sphere (cascade stage)
+// stores -(its absolute diameter) in d; list builds use |d|.
 struct alignas(32) P4 {
     double x, y, z, d;
 };
@@ -65,7 +66,8 @@ struct SegState {
     double nvol;          // (sum D0^3)^2 / sum D0^6, the pressure normaliser
     double d0max_k;       // max D0 (1 + 1e-9), for the list-validity test
     double beta1, beta2, eps_x, eps_k;
-    int32_t pad_h;
+    int32_t mixed;        // 1: some spheres are frozen (negative D0 in the records:
+                          // absolute diameter -D0, no step; a cascade stage)
     int32_t nblocks;      // iteration-grid blocks of this segment
     int64_t bfirst;       // first of them (index into the work table)
     // set at each list build (k_after_seg)

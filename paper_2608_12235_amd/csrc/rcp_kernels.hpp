@@ -167,6 +167,33 @@ struct PlaceArgs {
     int32_t *fail;               // set when a sphere ran out of attempts
     PlaceGrid grid[kPlaceMaxClasses];
 };
+
+// Seating of the spheres that are not frozen in the voids of the frozen ones
+// (a cascade stage; k_place.hip).  Frozen spheres sorted by cell of an nc^3
+// grid: fxd[4 o .. 4 o + 3] = (x, y, z, diameter), cell q holds o in
+// [start[q], start[q + 1]).  Sphere gidx[t] (user index, relative diameter
+// gd[t]) gets the first proposal of the counter stream that overlaps no
+// frozen sphere at the seating scale kappa0, written to x (user order, n x
+// 3); *fail is set when one needs more than max_attempts.
+struct SeatArgs {
+    const double *fxd;
+    const int32_t *start;
+    const double *gd;
+    const int32_t *gidx;
+    double *x;
+    int32_t *fail;
+    int64_t nc;
+    double inv_w, L, hL, kappa0;
+    uint64_t seed;
+    int64_t max_attempts;
+};
+void launch_seat(const SeatArgs &a, int64_t ng, hipStream_t st);
+
+// Frozen spheres of packing seg: the D0 field of every record in both
+// position buffers gets the sign -1 where mask (user order) is set, +1
+// elsewhere.
+void launch_set_frozen(const SegPtrs *P, int seg, int64_t n, const uint8_t *mask, hipStream_t st);
+
 // One round over ranks [lo, hi) of class c (clear the proposal table,
 // propose and validate, resolve conflicts and commit).
 void launch_place_round(const PlaceArgs &a, int c, int64_t lo, int64_t hi, hipStream_t st);

@@ -120,6 +120,11 @@ struct Seg {
     int err = 0;                 // error that stopped this packing (census)
     bool built = false;
     bool parked = false;         // finished: no work-item slots until its next run
+    // frozen spheres (a cascade stage): mask in user order, their D0 is an
+    // absolute diameter; sum of D0^3 over the frozen and the other spheres
+    bool mixed = false;
+    std::vector<uint8_t> frozen;
+    double sum3_frozen = 0, sum3_grow = 0;
 };
 
 // A stream for the pair searches of a batch of list builds.
@@ -135,6 +140,7 @@ constexpr int kBuildLanes = 4;
 struct rcp_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    bool any_mixed = false;         // some packing has frozen spheres
     rcp_params params{};
     rcp_tuning tuning{};
     std::vector<Seg> segs;
@@ -404,6 +410,11 @@ static int build_plan(rcp_ctx *c, int k, double kappa, int64_t min_entries, Buil
     const int64_t n = s.n;
     const double g = c->params.skin_g, sk = c->params.skin_s;
     const double opg = 1.0 + g, sk2 = (2.0 * sk) * s.d0min;
+    // with frozen spheres (absolute diameters |D0|, the others kappa D0) the
+    // list is built at max(kappa, 1): every cutoff is then at least the
+    // contact distance, and the build's growth allowance covers kappa up
+    // to (1 + g) times that scale
+    if (s.mixed && kappa < 1.0) kappa = 1.0;
     // largest cutoff must stay below half the box (minimum image)
     const double cmax = kappa * (opg * s.d0max + sk2);
     if (!(cmax < 0.5 * s.L))
@@ -912,21 +923,28 @@ static bool slot_timed(const rcp_ctx *c, int64_t slot)
 static int iterate_flags(const rcp_ctx *c)
 {
     return (c->tuning.xcd_remap ? 1 : 0) | ((c->tuning.variant & 128) ? 4 : 0) |
-           ((c->tuning.variant & 63) << 8);
+           (c->any_mixed ? 16 : 0) | ((c->tuning.variant & 63) << 8);
+}
+
+// The tail runs inside the gradient kernel only when asked for and when no
+// packing has frozen spheres (their kernel has no fused tail).
+static bool tail_fused(const rcp_ctx *c)
+{
+    return c->tuning.fused_tail && !c->any_mixed;
 }
 
 // One iteration: gradient + Adam kernel and tail kernel, bracketed by the
 // slot's three events when the slot is timed.
 static int launch_one_iteration(rcp_ctx *c, int slot)
 {
-    const int flags = iterate_flags(c) | (c->tuning.fused_tail ? 2 : 0);
+    const int flags = iterate_flags(c) | (tail_fused(c) ? 2 : 0);
     const bool timed = slot_timed(c, slot) && 3 * slot + 2 < (int)c->kev.size();
     if (timed) CHK(record_event(c, c->kev[3 * slot]));
     if (c->nitems > 0)
         launch_iterate(c->d_ptrs, c->d_state, c->d_work, c->d_partials, c->nitems, flags,
                        c->stream);
     if (timed) CHK(record_event(c, c->kev[3 * slot + 1]));
-    if (!c->tuning.fused_tail)
+    if (!tail_fused(c))
         launch_tail(c->d_state, c->d_partials, (int)c->segs.size(), c->segs[0].first_item,
                     c->segs[0].blocks, c->stream);
     if (timed) CHK(record_event(c, c->kev[3 * slot + 2]));
@@ -1096,6 +1114,16 @@ static int reset_moments(rcp_ctx *c, int k)
 static int shrink_seg(rcp_ctx *c, int k, double *kp_out, double *phi_out)
 {
     CHK(pull_state(c));
+    if (c->segs[k].mixed) {
+        // a cascade stage: no shrink (the release that follows starts from
+        // this state); phi from the frozen diameters and kappa D0 of the rest
+        const Seg &s = c->segs[k];
+        const double kp = c->h_state[k].kappa;
+        *kp_out = kp;
+        *phi_out = (M_PI / 6.0) * (s.sum3_frozen + kp * kp * kp * s.sum3_grow) /
+                   (s.L * s.L * s.L);
+        return RCP_OK;
+    }
     if (c->h_state[k].flags & (F_REBUILD | F_STALE)) CHK(rebuild(c, k, c->h_state[k].kappa));
     Seg &s = c->segs[k];
     const int nb = (int)std::max<int64_t>(1, (s.n + kBlock - 1) / kBlock);
@@ -1668,7 +1696,7 @@ int rcp_set_skin(rcp_ctx *c, double skin_s, double skin_g)
     CHK(pull_state(c));
     for (size_t k = 0; k < c->segs.size(); ++k) {
         const Seg &s = c->segs[k];
-        const double kap = c->h_state[k].kappa;
+        const double kap = s.mixed ? std::max(1.0, c->h_state[k].kappa) : c->h_state[k].kappa;
         if (!(kap * ((1.0 + skin_g) * s.d0max + (2.0 * skin_s) * s.d0min) < 0.5 * s.L))
             return fail(RCP_EBOX, "packing %d: listing cutoff with this skin is not below L/2",
                         (int)k);
@@ -1746,6 +1774,155 @@ int rcp_set_state(rcp_ctx *c, int k, const double *x, double kappa, int is_devic
     return RCP_OK;
 }
 
+int rcp_set_frozen(rcp_ctx *c, int k, const uint8_t *mask)
+{
+    CHK(check_k(c, k));
+    Seg &s = c->segs[k];
+    CHK(pull_state(c));
+    const int64_t n = s.n;
+    std::vector<uint8_t> fz(n, 0);
+    if (mask)
+        for (int64_t i = 0; i < n; ++i) fz[i] = mask[i] ? 1 : 0;
+    // schedule scales over the spheres that are not frozen (they alone
+    // inflate and move), compensated sums as at set-up
+    double sum = 0, cs = 0, sum3 = 0, cs3 = 0, sum6 = 0, cs6 = 0, dmin = INFINITY, f3 = 0;
+    int64_t ng = 0;
+    auto nadd = [](double &a, double &comp, double v) {
+        const double t = a + v;
+        comp += std::fabs(a) >= std::fabs(v) ? (a - t) + v : (v - t) + a;
+        a = t;
+    };
+    for (int64_t i = 0; i < n; ++i) {
+        const double d = s.d0h[i];
+        if (fz[i]) {
+            f3 += d * d * d;
+            continue;
+        }
+        ++ng;
+        dmin = std::min(dmin, d);
+        nadd(sum, cs, d);
+        nadd(sum3, cs3, d * d * d);
+        nadd(sum6, cs6, (d * d * d) * (d * d * d));
+    }
+    if (ng == 0) return fail(RCP_EINVAL, "packing %d: every sphere frozen", k);
+    CHK(dgrow(&c->xtmp, &c->xtmp_cap, (n + 7) / 8));
+    HIPCHK(hipMemcpyAsync(c->xtmp, fz.data(), (size_t)n, hipMemcpyHostToDevice, c->stream));
+    launch_set_frozen(c->d_ptrs, k, n, reinterpret_cast<const uint8_t *>(c->xtmp), c->stream);
+    SegState st = c->h_state[k];
+    st.mixed = ng < n ? 1 : 0;
+    st.sumd0 = sum + cs;
+    st.nvol = ((sum3 + cs3) * (sum3 + cs3)) / (sum6 + cs6);
+    st.d0min = dmin;
+    HIPCHK(hipMemcpyAsync(c->d_state + k, &st, sizeof st, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->h_state[k] = st;
+    s.mixed = ng < n;
+    s.frozen = s.mixed ? fz : std::vector<uint8_t>();
+    s.sum3_frozen = f3;
+    s.sum3_grow = sum3 + cs3;
+    c->any_mixed = false;
+    for (const Seg &q : c->segs) c->any_mixed = c->any_mixed || q.mixed;
+    c->graph_valid = false;
+    return RCP_OK;
+}
+
+int rcp_seat_device(rcp_ctx *c, int k, double kappa0, uint64_t seed, int64_t max_attempts)
+{
+    CHK(check_k(c, k));
+    Seg &s = c->segs[k];
+    if (!(kappa0 > 0) || !std::isfinite(kappa0) || max_attempts < 1)
+        return fail(RCP_EINVAL, "bad seating arguments");
+    const int64_t n = s.n;
+    std::vector<double> x(3 * n);
+    double kap = 0;
+    CHK(rcp_get_state(c, k, x.data(), &kap, nullptr));
+    // the frozen spheres, binned on a grid whose cells are at least as wide
+    // as the largest seating distance (27 cells hold every frozen sphere a
+    // proposal can overlap)
+    double fdmax = 0, gdmax = 0;
+    std::vector<int32_t> fidx, gidx;
+    for (int64_t i = 0; i < n; ++i) {
+        if (s.mixed && s.frozen[i]) {
+            fidx.push_back((int32_t)i);
+            fdmax = std::max(fdmax, s.d0h[i]);
+        } else {
+            gidx.push_back((int32_t)i);
+            gdmax = std::max(gdmax, s.d0h[i]);
+        }
+    }
+    const double wmin = 0.5 * (fdmax + kappa0 * gdmax) * (1.0 + 1e-12);
+    int64_t nc = wmin > 0 ? (int64_t)std::floor(s.L / wmin) : 1;
+    nc = std::max<int64_t>(1, std::min<int64_t>(nc, 64));
+    const int64_t ncell = nc * nc * nc;
+    SeatArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.nc = nc;
+    a.inv_w = (double)nc / s.L;
+    a.L = s.L;
+    a.hL = 0.5 * s.L;
+    a.kappa0 = kappa0;
+    a.seed = seed;
+    a.max_attempts = max_attempts;
+    const int64_t nf = (int64_t)fidx.size(), ng = (int64_t)gidx.size();
+    std::vector<double> fxd(4 * std::max<int64_t>(nf, 1));
+    std::vector<int32_t> start(ncell + 1, 0);
+    std::vector<int64_t> cell(nf);
+    auto cell_of = [&](double v) {
+        int64_t q = (int64_t)(v * a.inv_w);
+        return q < 0 ? 0 : (q >= nc ? nc - 1 : q);
+    };
+    for (int64_t f = 0; f < nf; ++f) {
+        const int64_t j = fidx[f];
+        cell[f] = (cell_of(x[3 * j]) * nc + cell_of(x[3 * j + 1])) * nc + cell_of(x[3 * j + 2]);
+        start[cell[f] + 1]++;
+    }
+    for (int64_t q = 0; q < ncell; ++q) start[q + 1] += start[q];
+    std::vector<int32_t> fill(start.begin(), start.end() - 1);
+    for (int64_t f = 0; f < nf; ++f) {
+        const int64_t j = fidx[f], o = fill[cell[f]]++;
+        fxd[4 * o] = x[3 * j];
+        fxd[4 * o + 1] = x[3 * j + 1];
+        fxd[4 * o + 2] = x[3 * j + 2];
+        fxd[4 * o + 3] = s.d0h[j];
+    }
+    std::vector<double> gd(std::max<int64_t>(ng, 1));
+    for (int64_t t = 0; t < ng; ++t) gd[t] = s.d0h[gidx[t]];
+    double *d_f = nullptr, *d_g = nullptr, *d_x = nullptr;
+    int32_t *d_start = nullptr, *d_gi = nullptr, *d_fail = nullptr;
+    int rc = RCP_OK;
+    do {
+        if ((rc = dalloc(&d_f, fxd.size())) != RCP_OK) break;
+        if ((rc = dalloc(&d_g, gd.size())) != RCP_OK) break;
+        if ((rc = dalloc(&d_x, (size_t)(3 * n))) != RCP_OK) break;
+        if ((rc = dalloc(&d_start, start.size())) != RCP_OK) break;
+        if ((rc = dalloc(&d_gi, (size_t)std::max<int64_t>(ng, 1))) != RCP_OK) break;
+        if ((rc = dalloc(&d_fail, 1)) != RCP_OK) break;
+        hipError_t e = hipMemcpy(d_f, fxd.data(), sizeof(double) * fxd.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(d_g, gd.data(), sizeof(double) * gd.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(d_x, x.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(d_start, start.data(), sizeof(int32_t) * start.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess && ng > 0) e = hipMemcpy(d_gi, gidx.data(), sizeof(int32_t) * ng, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemset(d_fail, 0, sizeof(int32_t));
+        if (e != hipSuccess) { rc = fail(RCP_EDEVICE, "seating upload: %s", hipGetErrorString(e)); break; }
+        a.fxd = d_f;
+        a.gd = d_g;
+        a.start = d_start;
+        a.gidx = d_gi;
+        a.x = d_x;
+        a.fail = d_fail;
+        launch_seat(a, ng, c->stream);
+        int32_t failed = 0;
+        e = hipMemcpyAsync(&failed, d_fail, sizeof failed, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(x.data(), d_x, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) { rc = fail(RCP_EDEVICE, "seating: %s", hipGetErrorString(e)); break; }
+        if (failed) { rc = fail(RCP_EPLACE, "seating: a sphere exceeded %lld attempts", (long long)max_attempts); break; }
+    } while (false);
+    dfree(d_f); dfree(d_g); dfree(d_x); dfree(d_start); dfree(d_gi); dfree(d_fail);
+    if (rc != RCP_OK) return rc;
+    return rcp_set_state(c, k, x.data(), kappa0, 0);
+}
+
 int rcp_get_state(rcp_ctx *c, int k, double *x, double *kappa, double *diam)
 {
     CHK(check_k(c, k));
@@ -1764,7 +1941,7 @@ int rcp_get_state(rcp_ctx *c, int k, double *x, double *kappa, double *diam)
             x[3 * u + 1] = q[i].y;
             x[3 * u + 2] = q[i].z;
         }
-        if (diam) diam[u] = kap * q[i].d;
+        if (diam) diam[u] = q[i].d > 0.0 ? kap * q[i].d : -q[i].d;
     }
     if (kappa) *kappa = kap;
     return RCP_OK;

@@ -8,6 +8,10 @@ criterion, then shrink to contact (App. A).
 
     python tests/golden/make_oracle_phi.py c2        # -> c2_phi_oracle.json
     python tests/golden/make_oracle_phi.py census8   # -> census8_phi_oracle.json
+    python tests/golden/make_oracle_phi.py cascade   # -> cascade_phi_oracle.json
+
+The cascade case runs the oracle's sequential multimodal cascade (Sec. 4,
+oracle.cascade): 20 coarse spheres, diameter ratio 7, two classes.
 """
 import json
 import os
@@ -58,9 +62,22 @@ def census8():
             "runs": runs}
 
 
+def cascade():
+    n1, rho, classes = 20, 7.0, 2
+    runs = []
+    for seed in range(8):
+        t0 = time.time()
+        phis, counts = oracle.cascade(n1, rho, classes, seed=seed)
+        runs.append({"seed": seed, "phi": phis, "counts": counts, "seconds": time.time() - t0})
+        print(runs[-1], flush=True)
+    return {"workload": "sequential multimodal cascade, 20 coarse spheres, diameter ratio 7, "
+                        "two classes (counts of the ideal cascade), seeds 0-7",
+            "n1": n1, "rho": rho, "classes": classes, "runs": runs}
+
+
 if __name__ == "__main__":
     which = sys.argv[1]
-    out = {"c2": c2, "census8": census8}[which]()
+    out = {"c2": c2, "census8": census8, "cascade": cascade}[which]()
     out["threads"] = oracle.num_threads()
     path = os.path.join(HERE, "%s_phi_oracle.json" % which)
     with open(path, "w") as fh:
