@@ -363,9 +363,35 @@ def leg_census(torch, args):
             "rebuilds": st["rebuilds"], "rebuild_ms": st["rebuild_ms"]}
 
 
-LEGS = {"c2": leg_c2, "rsa": leg_rsa, "census": leg_census}
-LEG_KEYS = {"c2": "c2_whole_run", "rsa": "rsa_start_window", "census": "census"}
-LEG_TIMEOUT = {"c2": 300, "rsa": 300, "census": 900}
+def leg_cascade(torch, args):
+    """Sequential multimodal cascade (Sec. 4, Table (tab:cascade)): 60
+    coarse spheres, diameter ratio 7, three classes (N = 904534), seed 0,
+    every stage and release to its stop criterion; phi after each class
+    against the paper's 0.624 / 0.800 / 0.879."""
+    from paper_2608_12235_amd import cascade
+    torch.cuda.synchronize()
+    out = cascade.run_cascade(60, 7.0, 3, 0)
+    torch.cuda.synchronize()
+    # sphere updates: every sphere of a stage's context, per iteration
+    upd = 0
+    for s in out["stages"]:
+        nst = sum(out["counts"][:s["class"]])
+        upd += nst * (s["iterations"] + s.get("iterations_frozen_stage", 0))
+    return {"workload": "ternary cascade, 60 coarse spheres, diameter ratio 7, counts %s "
+                        "(ideal void-filling cascade), seed 0, stages and releases to the stop "
+                        "criterion" % out["counts"],
+            "value": upd / out["seconds"], "unit": "particle-updates/s",
+            "seconds": out["seconds"], "phi": out["phi"], "phi_paper": [0.624, 0.800, 0.879],
+            "phi_ideal": [cascade.ideal_phi(c + 1) for c in range(3)],
+            "statuses": [s["status"] for s in out["stages"]],
+            "iterations": [s["iterations"] for s in out["stages"]],
+            "iterations_frozen_stages": [s.get("iterations_frozen_stage") for s in out["stages"]]}
+
+
+LEGS = {"c2": leg_c2, "rsa": leg_rsa, "census": leg_census, "cascade": leg_cascade}
+LEG_KEYS = {"c2": "c2_whole_run", "rsa": "rsa_start_window", "census": "census",
+            "cascade": "cascade"}
+LEG_TIMEOUT = {"c2": 300, "rsa": 300, "census": 900, "cascade": 600}
 
 
 def run_legs(names):
@@ -544,9 +570,9 @@ def main():
     ap.add_argument("--xcd-remap", dest="xcd_remap", type=int, default=None)
     ap.add_argument("--variant", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="c2,rsa,census",
+    ap.add_argument("--legs", default="c2,rsa,census,cascade",
                     help="secondary legs run first in child processes (comma list of c2, rsa, "
-                         "census; empty for none)")
+                         "census, cascade; empty for none)")
     ap.add_argument("--leg", default=None, choices=sorted(LEGS), help=argparse.SUPPRESS)
     ap.add_argument("--kernel-timing", type=int, default=2, choices=(0, 1, 2),
                     help="kernel-timing pass after the timed region (c3 workload), HIP "
