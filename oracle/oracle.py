@@ -78,6 +78,8 @@ def lib():
                                           C.c_int]
         L.orc_set_list_check.restype = None
         L.orc_set_list_check.argtypes = [C.c_int, C.c_double]
+        L.orc_set_dim.restype = None
+        L.orc_set_dim.argtypes = [C.c_int]
         L.orc_set_frozen.restype = None
         L.orc_set_frozen.argtypes = [C.c_void_p]
         L.orc_phi_frozen.restype = C.c_double
@@ -155,6 +157,22 @@ def set_list_check(on, trigger_scale=1.0):
 
 def list_misses():
     return int(lib().orc_list_misses())
+
+
+_dim = 3
+
+
+def set_dim(d):
+    """Spatial dimension, 3 (default) or 2 (disks in the plane z = 0; see
+    orc_set_dim).  Every later call uses it until changed."""
+    global _dim
+    assert d in (2, 3)
+    _dim = d
+    lib().orc_set_dim(int(d))
+
+
+def get_dim():
+    return _dim
 
 
 _frozen_ref = None

@@ -28,7 +28,9 @@
  *   - frozen spheres for the stages of the sequential multimodal cascade
  *     (Sec. 4): a frozen sphere keeps its position and an absolute
  *     diameter while the other spheres inflate (see orc_set_frozen), and
- *     the seating of a new class in the voids of the frozen ones.
+ *     the seating of a new class in the voids of the frozen ones;
+ *   - the spatial dimension d (the paper's input, Sec. 2; Fig. 1 is
+ *     2-D): d = 2 packs disks in the plane z = 0 (see orc_set_dim).
  *
  * Floating point: compiled with -ffp-contract=off; every quantity is double.
  * Sums of many terms (energy, kappa gradient) use Neumaier compensation.
@@ -58,6 +60,19 @@ double orc_u01(uint64_t seed, uint64_t i, uint64_t attempt, int axis)
 {
     uint64_t k = ((i << 24) | attempt) * 4u + (uint64_t)axis;
     return (double)(orc_splitmix64(seed, k) >> 11) * 0x1p-53;
+}
+
+/* The spatial dimension, 3 or 2 (see orc_set_dim). */
+static int g_dim = 3;
+
+/* Coordinate ax of attempt a of sphere i: u(seed, i, a, ax) L in [0, L);
+ * 0 for ax = 2 in two dimensions (not drawn). */
+static inline double coord_draw(uint64_t seed, int64_t i, int64_t a, int ax, double L)
+{
+    if (ax == 2 && g_dim == 2) return 0.0;
+    double v = orc_u01(seed, (uint64_t)i, (uint64_t)a, ax) * L;
+    if (v >= L) v -= L;
+    return v;
 }
 
 int orc_num_threads(void)
@@ -364,6 +379,17 @@ int64_t orc_pairs_cells(int64_t n, const double *x, const double *d0, double L,
 }
 
 /* ------------------------------------------------------------------ */
+/* Spatial dimension (Sec. 2: the dimension is an input; Fig. 1, 2-D)  */
+/* ------------------------------------------------------------------ */
+/* d = 3 (default) or 2.  With d = 2 every position has z = 0: placement
+ * proposes only x and y (axis 2 of the counter stream is not drawn), the
+ * energy, its gradient (whose z components then vanish) and Adam are the
+ * 3-D ones restricted to the plane, the volume participation number of
+ * the schedule is (sum D^2)^2 / sum D^4 and the packing fraction is the
+ * area fraction (pi / 4) sum D^2 / L^2. */
+void orc_set_dim(int d) { g_dim = (d == 2) ? 2 : 3; }
+
+/* ------------------------------------------------------------------ */
 /* Frozen spheres (Sec. 4, the sequential multimodal cascade)          */
 /* ------------------------------------------------------------------ */
 /* A cascade stage seats a finer class in the voids of the coarser ones
@@ -537,6 +563,10 @@ double orc_shrink(int64_t n, const double *x, const double *d0, double L,
 double orc_phi(int64_t n, const double *d0, double L, double kappa)
 {
     nsum_t s = {0, 0};
+    if (g_dim == 2) {
+        for (int64_t i = 0; i < n; ++i) nadd(&s, d0[i] * d0[i]);
+        return (M_PI / 4.0) * (kappa * kappa) * nval(&s) / (L * L);
+    }
     for (int64_t i = 0; i < n; ++i) nadd(&s, d0[i] * d0[i] * d0[i]);
     return (M_PI / 6.0) * (kappa * kappa * kappa) * nval(&s) / (L * L * L);
 }
@@ -547,9 +577,10 @@ double orc_phi_frozen(int64_t n, const double *d0, double L, double kappa)
     nsum_t s = {0, 0};
     for (int64_t i = 0; i < n; ++i) {
         const double si = sigma(d0, i, kappa);
-        nadd(&s, si * si * si);
+        nadd(&s, g_dim == 2 ? si * si : si * si * si);
     }
-    return (M_PI / 6.0) * nval(&s) / (L * L * L);
+    return g_dim == 2 ? (M_PI / 4.0) * nval(&s) / (L * L)
+                      : (M_PI / 6.0) * nval(&s) / (L * L * L);
 }
 
 /* Seating of a new class (Sec. 4: the finer class is seated in the voids
@@ -578,10 +609,7 @@ int orc_seat(int64_t n, const double *d0, double L, double kappa0, uint64_t seed
         int64_t a;
         for (a = 0; a < max_attempts; ++a) {
             double p[3];
-            for (int ax = 0; ax < 3; ++ax) {
-                p[ax] = orc_u01(seed, (uint64_t)i, (uint64_t)a, ax) * L;
-                if (p[ax] >= L) p[ax] -= L;
-            }
+            for (int ax = 0; ax < 3; ++ax) p[ax] = coord_draw(seed, i, a, ax, L);
             int ok = 1;
             for (int64_t q = 0; q < nf && ok; ++q) {
                 const int64_t j = fz[q];
@@ -646,8 +674,7 @@ int orc_rsa(int64_t n, const double *d0, double L, double kappa0, uint64_t seed,
         for (a = 0; a < max_attempts; ++a) {
             double p[3];
             for (int ax = 0; ax < 3; ++ax) {
-                p[ax] = orc_u01(seed, (uint64_t)i, (uint64_t)a, ax) * L;
-                if (p[ax] >= L) p[ax] -= L;
+                p[ax] = coord_draw(seed, i, a, ax, L);
                 x[3 * i + ax] = p[ax];
             }
             int64_t c[3];
@@ -749,10 +776,7 @@ int orc_rsa_rounds(int64_t n, const double *d0, double L, double kappa0, uint64_
                 valid[s] = 0;
                 if (placed[k]) continue;
                 double *p = prop + 3 * s;
-                for (int ax = 0; ax < 3; ++ax) {
-                    p[ax] = orc_u01(seed, (uint64_t)i, (uint64_t)att[k], ax) * L;
-                    if (p[ax] >= L) p[ax] -= L;
-                }
+                for (int ax = 0; ax < 3; ++ax) p[ax] = coord_draw(seed, i, att[k], ax, L);
                 int ok = 1;
                 for (int64_t q = 0; q < nplaced && ok; ++q) {
                     int64_t j = placed_list[q];
@@ -1054,7 +1078,8 @@ int orc_run(int64_t n, double *x, const double *d0, double L, double *kappa,
         if (frozen(i)) continue;
         if (d0[i] < R.d0min) R.d0min = d0[i];
         nadd(&sd, d0[i]);
-        const double c3 = d0[i] * d0[i] * d0[i];
+        /* volume (area in 2-D) participation number */
+        const double c3 = g_dim == 2 ? d0[i] * d0[i] : d0[i] * d0[i] * d0[i];
         nadd(&s3, c3);
         nadd(&s6, c3 * c3);
     }

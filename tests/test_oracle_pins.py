@@ -836,3 +836,72 @@ def test_binary_cascade_fills_the_voids(orc):
     assert 0.58 < phis[0] < 0.70
     assert 0.74 < phis[1] < 0.85
     assert phis[1] - phis[0] > 0.1
+
+
+# ------------------------------------------------- two dimensions (Sec. 2)
+@pytest.fixture
+def orc2(orc):
+    orc.set_dim(2)
+    yield orc
+    orc.set_dim(3)
+
+
+def test_2d_square_lattice_shrinks_to_touching(orc2):
+    # n x n equal disks on a square lattice of spacing 1 in a periodic box
+    # of side n: at kappa = 1.3 every lattice neighbour overlaps; the
+    # shrink lands on touching, kappa' = 1, and the area fraction is then
+    # pi / 4 (closed form); gradients vanish by symmetry
+    n = 6
+    g = np.arange(n) + 0.5
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    x = np.stack([X.ravel(), Y.ravel(), np.zeros(n * n)], axis=1)
+    d0 = np.ones(n * n)
+    L = float(n)
+    pi, pj = orc2.pairs_brute(x, d0, L, 1.3, 0.0, 0.0)
+    assert pi.shape[0] == 2 * n * n        # 4 neighbours each, pairs counted once
+    r = orc2.energy_grad(x, d0, L, 1.3, 0.0, pi, pj)
+    delta = 1.0 - 1.0 / 1.3
+    assert r["E_ov"] == pytest.approx(2 * n * n * 0.5 * delta ** 2, rel=1e-13)
+    assert np.abs(r["g"]).max() <= 1e-13
+    kp = orc2.shrink(x, d0, L, 1.3, pi, pj)
+    assert kp == 1.0
+    assert orc2.phi(d0, L, kp) == pytest.approx(np.pi / 4.0, rel=1e-15)
+
+
+def test_2d_rsa_stays_in_the_plane(orc2):
+    w = ri.small_polydisperse(400, 3.0, 0.3, seed=5)
+    L = float(np.sqrt(np.pi / 4.0 * np.sum(w.d0 ** 2) / 0.3))
+    x = orc2.rsa(w.d0, L, 1.0, 8)
+    assert np.all(x[:, 2] == 0.0)
+    pi, pj = orc2.pairs_brute(x, w.d0, L, 1.0, 0.0, 0.0)
+    assert pi.shape[0] == 0
+    for ax in range(2):
+        assert stats.kstest(x[:, ax] / L, "uniform").pvalue > 1e-3
+    assert np.array_equal(x, orc2.rsa(w.d0, L, 1.0, 8))
+
+
+def test_2d_area_participation_number_sets_mu(orc2):
+    # two disks, D0 = 1 and 2: N_v = (1 + 4)^2 / (1 + 16) = 25/17 in 2-D
+    # (against (1 + 8)^2 / (1 + 64) = 81/65 in 3-D); the rung start sets
+    # mu = mu~ N_v / (kappa sum D0)
+    d0 = np.array([1.0, 2.0])
+    x = np.array([[1.0, 1.0, 0.0], [5.0, 5.0, 0.0]])
+    sc = orc2.default_schedule(2, d=2)
+    st = orc2.RunState(x, d0, 10.0, 1.0)
+    orc2.run(st, orc2.default_params(d0), sc, max_iters=1)
+    assert st.etas[0] == pytest.approx(sc.mu[0] * (25.0 / 17.0) / 3.0, rel=1e-14)
+
+
+def test_2d_bidisperse_run_jams_in_the_plane(orc2):
+    # 50:50 disks of diameter ratio 1.4 (the usual 2-D glass former): the
+    # protocol stops with z untouched, at an area fraction in the range
+    # reported for random close packing of such mixtures (about 0.84)
+    n = 512
+    d0 = np.where(np.arange(n) % 2 == 0, 1.0, 1.4)
+    L = float(np.sqrt(np.pi / 4.0 * np.sum(d0 ** 2) / 0.1))
+    x = orc2.rsa(d0, L, 1.0, 2)
+    st = orc2.RunState(x, d0, L, 1.0)
+    status, res, _ = orc2.run(st, orc2.default_params(d0), orc2.default_schedule(n, d=2, S=1.4))
+    assert status == 0 and res.max_overlap < 5e-4
+    assert np.all(st.x[:, 2] == 0.0)
+    assert 0.80 < res.phi < 0.88
