@@ -21,7 +21,10 @@
  * Conventions for every call:
  *   - return value 0 on success, a negative RCP_E* code on failure; the
  *     message of the last failure on the calling thread is rcp_last_error();
- *   - positions at this boundary are row-major (n, 3) doubles in user order;
+ *   - positions (and gradients and Adam moments) at this boundary are
+ *     row-major (n, dim) doubles in user order (dim = 3, or 2 for disks:
+ *     Fig. 1 of the paper is 2-D); inside, a disk packing is a packing in the
+ *     plane z = 0, whose z gradients vanish so its z coordinates never move;
  *   - host arrays are borrowed for the duration of the call and copied;
  *   - device arrays given to *_dev calls are borrowed until the work queued
  *     on the given stream has completed;
@@ -43,7 +46,7 @@ extern "C" {
 
 /* error codes */
 #define RCP_OK 0
-#define RCP_EINVAL -1      /* bad argument: n <= 0, D0 <= 0 or not finite, dim != 3,
+#define RCP_EINVAL -1      /* bad argument: n <= 0, D0 <= 0 or not finite, dim not 2 or 3,
                               non-cubic box, kappa <= 0, bad schedule              */
 #define RCP_EBOX -2        /* largest listing cutoff >= L/2 (a sphere would meet its
                               own periodic image, Sec. 2)                          */
@@ -237,9 +240,11 @@ int rcp_schedule_default(int64_t n, int dim, double S, int Y, int X, int64_t n_m
  * 2^27) with relative
  * diameters d0[k][0..n[k]) (host), cube edge box[k], starting scale
  * kappa0[k] and placement seed seeds[k] (SplitMix64 counter stream, see
- * rcp_pack_init).  dim must be 3.  stream is a hipStream_t (NULL: the
- * library creates one).  Returns RCP_EBOX if a packing's largest cutoff
- * is not below L/2. */
+ * rcp_pack_init).  dim is 3, or 2 (Sec. 2: the dimension is an input; in
+ * two dimensions placement does not draw the z axis, the schedule's
+ * participation number is (sum D0^2)^2 / sum D0^4 and phi is the area
+ * fraction).  stream is a hipStream_t (NULL: the library creates one).
+ * Returns RCP_EBOX if a packing's largest cutoff is not below L/2. */
 int rcp_census_init(int dim, int n_prob, const int64_t *n,
                     const double *const *d0, const double *box,
                     const double *kappa0, const uint64_t *seeds, int init_mode,
@@ -316,17 +321,18 @@ int rcp_set_tuning(rcp_ctx *ctx, const rcp_tuning *t);
  * kappa would not be below L/2 (nothing is changed then). */
 int rcp_set_skin(rcp_ctx *ctx, double skin_s, double skin_g);
 
-/* Replace positions (row-major (n, 3), user order) and kappa of packing k
+/* Replace positions (row-major (n, dim), user order) and kappa of packing k
  * (the state of the optimised energy, Eq. (energy) of App. A); x is a host
  * pointer (is_device == 0, every value in [-L, 2L), wrapped into [0, L)) or
- * a device pointer (is_device != 0, values already in [0, L)).  Resets the
+ * a device pointer (is_device != 0, values already in [0, L); dim = 3
+ * only).  Resets the
  * Adam moments and step counter (as after placement) and the schedule
  * position, and marks the neighbour list stale.  RCP_EINVAL for a bad
  * kappa or a host position outside [-L, 2L). */
 int rcp_set_state(rcp_ctx *ctx, int k, const double *x, double kappa,
                   int is_device);
 
-/* Copy positions (n, 3, user order), kappa and optionally the working
+/* Copy positions (n, dim, user order), kappa and optionally the working
  * diameters kappa D0 (n) of packing k to host memory (App. A: the outputs
  * of a run are the positions and the scaled diameters).  x, kappa and diam
  * may each be NULL. */
@@ -347,7 +353,7 @@ typedef struct {
 } rcp_optimizer;
 
 /* Copy the optimiser state of packing k: the first and second moments of
- * every coordinate (m, v: (n, 3) row-major, user order, host; either may be
+ * every coordinate (m, v: (n, dim) row-major, user order, host; either may be
  * NULL) and the scalars in *opt.  Together with rcp_get_state this is a
  * complete checkpoint of a run in progress. */
 int rcp_get_optimizer(rcp_ctx *ctx, int k, double *m, double *v, rcp_optimizer *opt);
@@ -382,7 +388,7 @@ int rcp_get_pairs(rcp_ctx *ctx, int k, int32_t *i, int32_t *j, int64_t cap,
 
 /* Energy terms and gradient of Eq. (energy) at packing k's current state
  * with the given mu; rebuilds the list first if it is not valid.  grad_x
- * (n, 3, user order, host) may be NULL. */
+ * (n, dim, user order, host) may be NULL. */
 int rcp_energy_grad(rcp_ctx *ctx, int k, double mu, rcp_energy *e,
                     double *grad_x);
 
@@ -446,7 +452,7 @@ int rcp_census_run(rcp_ctx *ctx, const rcp_schedule *sched, int per_packing,
 int rcp_shrink(rcp_ctx *ctx, int k, double *kappa_shrunk, double *phi);
 
 /* Raw device entry points for torch.autograd.Function (packing 0; App. A,
- * Eq. (energy) and its gradient).  x_dev: (n, 3) row-major positions in user
+ * Eq. (energy) and its gradient; dim = 3 only).  x_dev: (n, 3) row-major positions in user
  * order on the device, borrowed until the work on `stream` completes.
  * stream is the caller's hipStream_t and NULL means the null stream (not
  * the context's own): reads of x_dev and writes of the outputs are ordered

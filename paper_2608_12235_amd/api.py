@@ -67,7 +67,7 @@ class Packing:
     """One or several independent periodic packings on the GPU (an rcp_ctx)."""
 
     def __init__(self, d0, L, kappa0=1.0, seed=0, init="rsa", params=None, stream=None,
-                 tuning=None):
+                 tuning=None, dim=3):
         d0s = d0 if isinstance(d0, (list, tuple)) else [d0]
         Ls = L if isinstance(L, (list, tuple, np.ndarray)) else [L]
         P = len(d0s)
@@ -83,7 +83,8 @@ class Packing:
         sd = (C.c_uint64 * P)(*[int(v) for v in seeds])
         self.params = params if params is not None else make_params()
         h = C.c_void_p()
-        check(lib().rcp_census_init(3, P, ns, ptrs, box, kap, sd, _INIT[init],
+        self.dim = int(dim)
+        check(lib().rcp_census_init(self.dim, P, ns, ptrs, box, kap, sd, _INIT[init],
                                     C.byref(self.params), stream, C.byref(h)))
         self._h = h
         self.tuning = make_tuning()
@@ -120,12 +121,12 @@ class Packing:
         self.params.skin_g = float(skin_g)
 
     def set_state(self, x, kappa, k=0):
-        x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
+        x = np.ascontiguousarray(x, np.float64).reshape(-1, self.dim)
         assert x.shape[0] == self.n[k]
         check(lib().rcp_set_state(self._h, k, x.ctypes.data_as(C.c_void_p), float(kappa), 0))
 
     def get_state(self, k=0, diameters=False):
-        x = np.empty((self.n[k], 3))
+        x = np.empty((self.n[k], self.dim))
         kap = C.c_double()
         dm = np.empty(self.n[k]) if diameters else None
         check(lib().rcp_get_state(self._h, k, _dp(x), C.byref(kap),
@@ -137,8 +138,8 @@ class Packing:
         (n, 3) arrays in user order (None when moments is False)."""
         o = Optimizer()
         o.size = C.sizeof(Optimizer)
-        m = np.empty((self.n[k], 3)) if moments else None
-        v = np.empty((self.n[k], 3)) if moments else None
+        m = np.empty((self.n[k], self.dim)) if moments else None
+        v = np.empty((self.n[k], self.dim)) if moments else None
         check(lib().rcp_get_optimizer(self._h, k, _dp(m) if moments else None,
                                       _dp(v) if moments else None, C.byref(o)))
         return m, v, {f: getattr(o, f) for f, _ in Optimizer._fields_ if f != "size"}
@@ -149,8 +150,8 @@ class Packing:
         o.size = C.sizeof(Optimizer)
         for f, val in opt.items():
             setattr(o, f, val)
-        mm = None if m is None else np.ascontiguousarray(m, np.float64).reshape(self.n[k], 3)
-        vv = None if v is None else np.ascontiguousarray(v, np.float64).reshape(self.n[k], 3)
+        mm = None if m is None else np.ascontiguousarray(m, np.float64).reshape(self.n[k], self.dim)
+        vv = None if v is None else np.ascontiguousarray(v, np.float64).reshape(self.n[k], self.dim)
         check(lib().rcp_set_optimizer(self._h, k, _dp(mm) if mm is not None else None,
                                       _dp(vv) if vv is not None else None, C.byref(o)))
 
@@ -178,7 +179,7 @@ class Packing:
 
     def energy_grad(self, mu=0.0, k=0, grad=True):
         e = Energy()
-        g = np.empty((self.n[k], 3)) if grad else None
+        g = np.empty((self.n[k], self.dim)) if grad else None
         check(lib().rcp_energy_grad(self._h, k, float(mu), C.byref(e),
                                     _dp(g) if grad else None))
         out = {f: getattr(e, f) for f, _ in Energy._fields_}
@@ -205,7 +206,8 @@ class Packing:
         return [_result_dict(r) for r in res]
 
     def default_schedules(self):
-        return [default_schedule(n, S=float(d.max() / d.min())) for n, d in zip(self.n, self._d0)]
+        return [default_schedule(n, dim=self.dim, S=float(d.max() / d.min()))
+                for n, d in zip(self.n, self._d0)]
 
     def run_start(self, schedule=None):
         P = self.n_packings

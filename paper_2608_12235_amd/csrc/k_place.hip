@@ -121,7 +121,8 @@ __global__ __launch_bounds__(kBlock) void k_place_propose(PlaceArgs a, int c, in
     const double di = a.d0[i];
     double p[3];
     for (int ax = 0; ax < 3; ++ax) {
-        double v = place_u01(a.seed, (uint64_t)i, (uint64_t)a.att[k], ax) * a.L;
+        // in two dimensions z = 0 (axis 2 of the stream is not drawn)
+        double v = ax < a.dim ? place_u01(a.seed, (uint64_t)i, (uint64_t)a.att[k], ax) * a.L : 0.0;
         if (v >= a.L) v -= a.L;
         p[ax] = v;
         a.prop[3 * s + ax] = v;
@@ -236,7 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_seat(SeatArgs a, int64_t ng)
     for (int64_t att = 0; att < a.max_attempts; ++att) {
         double p[3];
         for (int ax = 0; ax < 3; ++ax) {
-            double v = place_u01(a.seed, (uint64_t)i, (uint64_t)att, ax) * a.L;
+            double v = ax < a.dim ? place_u01(a.seed, (uint64_t)i, (uint64_t)att, ax) * a.L : 0.0;
             if (v >= a.L) v -= a.L;
             p[ax] = v;
         }

@@ -8,7 +8,8 @@
 // decisions are reproducible: a proposal for sphere i is rejected when
 //     r2 < dd * dd,  r2 = (dx dx + dy dy) + dz dz,  dx = mi(x_j - x_i),
 //     dd = kappa0 * (0.5 * (D0_i + D0_j))
-// for some placed sphere j.
+// for some placed sphere j.  In two dimensions (dim = 2) every sphere lies
+// in the plane z = 0: axis 2 of the counter stream is not drawn.
 #include <stdint.h>
 
 #include <algorithm>
@@ -84,11 +85,11 @@ static inline double mimage(double d, double L, double hL)
     return d > hL ? d - L : (d < -hL ? d + L : d);
 }
 
-void place_uniform(int64_t n, double L, uint64_t seed, double *x)
+void place_uniform(int64_t n, double L, uint64_t seed, int dim, double *x)
 {
     for (int64_t i = 0; i < n; ++i)
         for (int a = 0; a < 3; ++a) {
-            double p = uniform01(seed, (uint64_t)i, 0, a) * L;
+            double p = a < dim ? uniform01(seed, (uint64_t)i, 0, a) * L : 0.0;
             if (p >= L) p -= L;
             x[3 * i + a] = p;
         }
@@ -99,7 +100,7 @@ void place_uniform(int64_t n, double L, uint64_t seed, double *x)
 // with cells no narrower than kappa0 times the class's largest diameter;
 // since every placed sphere is at least as large as the candidate, a
 // candidate only has to look at its own and larger classes.
-int place_rsa(int64_t n, const double *d0, double L, double kappa0, uint64_t seed,
+int place_rsa(int64_t n, const double *d0, double L, double kappa0, uint64_t seed, int dim,
               int64_t max_attempts, double *x)
 {
     const double hL = 0.5 * L;
@@ -150,7 +151,7 @@ int place_rsa(int64_t n, const double *d0, double L, double kappa0, uint64_t see
         for (a = 0; a < max_attempts; ++a) {
             double p[3];
             for (int ax = 0; ax < 3; ++ax) {
-                p[ax] = uniform01(seed, (uint64_t)i, (uint64_t)a, ax) * L;
+                p[ax] = ax < dim ? uniform01(seed, (uint64_t)i, (uint64_t)a, ax) * L : 0.0;
                 if (p[ax] >= L) p[ax] -= L;
             }
             bool ok = true;

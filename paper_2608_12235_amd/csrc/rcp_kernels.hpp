@@ -149,6 +149,7 @@ struct PlaceArgs {
     double L, hL, kappa0;
     uint64_t seed;
     int64_t max_attempts;
+    int32_t dim;             // 3, or 2: the z coordinate is 0
     int ncls, pad;
     const int32_t *ord;      // rank -> sphere (largest first)
     const double *d0;        // by sphere
@@ -186,6 +187,7 @@ struct SeatArgs {
     double inv_w, L, hL, kappa0;
     uint64_t seed;
     int64_t max_attempts;
+    int32_t dim;             // 3, or 2: the z coordinate is 0
 };
 void launch_seat(const SeatArgs &a, int64_t ng, hipStream_t st);
 

@@ -18,8 +18,8 @@
 
 namespace rcp {
 double uniform01(uint64_t seed, uint64_t i, uint64_t attempt, int axis);
-void place_uniform(int64_t n, double L, uint64_t seed, double *x);
-int place_rsa(int64_t n, const double *d0, double L, double kappa0, uint64_t seed,
+void place_uniform(int64_t n, double L, uint64_t seed, int dim, double *x);
+int place_rsa(int64_t n, const double *d0, double L, double kappa0, uint64_t seed, int dim,
               int64_t max_attempts, double *x);
 }  // namespace rcp
 
@@ -141,6 +141,7 @@ struct rcp_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     bool any_mixed = false;         // some packing has frozen spheres
+    int dim = 3;                    // 3, or 2: disks in the plane z = 0
     rcp_params params{};
     rcp_tuning tuning{};
     std::vector<Seg> segs;
@@ -1120,8 +1121,10 @@ static int shrink_seg(rcp_ctx *c, int k, double *kp_out, double *phi_out)
         const Seg &s = c->segs[k];
         const double kp = c->h_state[k].kappa;
         *kp_out = kp;
-        *phi_out = (M_PI / 6.0) * (s.sum3_frozen + kp * kp * kp * s.sum3_grow) /
-                   (s.L * s.L * s.L);
+        *phi_out = c->dim == 2 ? (M_PI / 4.0) * (s.sum3_frozen + kp * kp * s.sum3_grow) /
+                                     (s.L * s.L)
+                               : (M_PI / 6.0) * (s.sum3_frozen + kp * kp * kp * s.sum3_grow) /
+                                     (s.L * s.L * s.L);
         return RCP_OK;
     }
     if (c->h_state[k].flags & (F_REBUILD | F_STALE)) CHK(rebuild(c, k, c->h_state[k].kappa));
@@ -1140,9 +1143,16 @@ static int shrink_seg(rcp_ctx *c, int k, double *kp_out, double *phi_out)
     const double kappa = c->h_state[k].kappa;
     const double kp = std::min(kappa, kmin);
     *kp_out = kp;
-    *phi_out = (M_PI / 6.0) * (kp * kp * kp) * s.sumd03 / (s.L * s.L * s.L);
+    // the volume fraction; the area fraction in two dimensions
+    *phi_out = c->dim == 2 ? (M_PI / 4.0) * (kp * kp) * s.sumd03 / (s.L * s.L)
+                           : (M_PI / 6.0) * (kp * kp * kp) * s.sumd03 / (s.L * s.L * s.L);
     return RCP_OK;
 }
+
+// State in three coordinates per sphere (the boundary calls convert from and
+// to (n, dim)).
+static int set_state3(rcp_ctx *c, int k, const double *x, double kappa, int is_device);
+static int get_state3(rcp_ctx *c, int k, double *x, double *kappa, double *diam);
 
 // ------------------------------------------------------------ placement
 // Random sequential addition in rounds on the device (k_place.hip) for
@@ -1183,6 +1193,7 @@ static int place_device(rcp_ctx *c, int k, uint64_t seed, int64_t window, int64_
     a.kappa0 = kappa;
     a.seed = seed;
     a.max_attempts = max_attempts;
+    a.dim = c->dim;
     a.ncls = ncls;
     int64_t tcap = 0;
     for (int q = 0; q < ncls; ++q) {
@@ -1287,7 +1298,7 @@ static int place_device(rcp_ctx *c, int k, uint64_t seed, int64_t window, int64_
         }
         if (rc != RCP_OK) break;
         if (rounds) *rounds = nround;
-        rc = rcp_set_state(c, k, d_x, kappa, 1);
+        rc = set_state3(c, k, d_x, kappa, 1);
     } while (0);
     const hipError_t se = hipStreamSynchronize(c->stream);
     release();
@@ -1333,7 +1344,8 @@ static int seg_setup(rcp_ctx *c, int k, int64_t n, const double *d0, double L, d
         s.d0min = std::min(s.d0min, d0[i]);
         s.d0max = std::max(s.d0max, d0[i]);
         nadd(sum, cs, d0[i]);
-        const double c3 = d0[i] * d0[i] * d0[i];
+        // D0^d: the volume (area in two dimensions) of a sphere up to a constant
+        const double c3 = c->dim == 2 ? d0[i] * d0[i] : d0[i] * d0[i] * d0[i];
         nadd(sum3, cs3, c3);
         nadd(sum6, cs6, c3 * c3);
     }
@@ -1388,10 +1400,10 @@ static int seg_setup(rcp_ctx *c, int k, int64_t n, const double *d0, double L, d
     // placement
     std::vector<double> x(3 * n, 0.0);
     if (init_mode == RCP_INIT_RSA) {
-        if (place_rsa(n, d0, L, kappa0, seed, (int64_t)1 << 22, x.data()) != 0)
+        if (place_rsa(n, d0, L, kappa0, seed, c->dim, (int64_t)1 << 22, x.data()) != 0)
             return fail(RCP_EPLACE, "packing %d: random sequential addition failed", k);
     } else if (init_mode == RCP_INIT_UNIFORM) {
-        place_uniform(n, L, seed, x.data());
+        place_uniform(n, L, seed, c->dim, x.data());
     } else if (init_mode != RCP_INIT_NONE && init_mode != RCP_INIT_RSA_DEVICE) {
         return fail(RCP_EINVAL, "unknown init_mode %d", init_mode);
     }
@@ -1606,7 +1618,7 @@ int rcp_census_init(int dim, int n_prob, const int64_t *n, const double *const *
 {
     if (!out) return fail(RCP_EINVAL, "null output pointer");
     *out = nullptr;
-    if (dim != 3) return fail(RCP_EINVAL, "only dim = 3 is implemented (got %d)", dim);
+    if (dim != 2 && dim != 3) return fail(RCP_EINVAL, "dim must be 2 or 3 (got %d)", dim);
     if (n_prob < 1 || !n || !d0 || !box || !kappa0 || !seeds)
         return fail(RCP_EINVAL, "bad census arguments");
     if (params && params->size != sizeof(rcp_params)) return fail(RCP_EINVAL, "rcp_params: bad size");
@@ -1623,6 +1635,7 @@ int rcp_census_init(int dim, int n_prob, const int64_t *n, const double *const *
     rcp_ctx *c = new rcp_ctx();
     c->params = P;
     rcp_tuning_default(&c->tuning);
+    c->dim = dim;
     c->segs.resize(n_prob);
     int rc = RCP_OK;
     do {
@@ -1679,7 +1692,7 @@ int rcp_pack_init(int dim, const double *box, int64_t n, const double *d0, doubl
                   uint64_t seed, int init_mode, const rcp_params *params, void *stream,
                   rcp_ctx **out)
 {
-    if (dim != 3) return fail(RCP_EINVAL, "only dim = 3 is implemented (got %d)", dim);
+    if (dim != 2 && dim != 3) return fail(RCP_EINVAL, "dim must be 2 or 3 (got %d)", dim);
     if (!box) return fail(RCP_EINVAL, "null box");
     for (int a = 1; a < dim; ++a)
         if (box[a] != box[0]) return fail(RCP_EINVAL, "only cubic boxes are implemented");
@@ -1732,7 +1745,32 @@ static int check_k(rcp_ctx *c, int k)
     return RCP_OK;
 }
 
+// Positions at the boundary are (n, dim) row-major; inside, every packing
+// keeps three coordinates (z = 0 in two dimensions).
+static void expand_dim(const rcp_ctx *c, int64_t n, const double *xu, std::vector<double> &x3)
+{
+    x3.assign(3 * n, 0.0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < c->dim; ++a) x3[3 * i + a] = xu[c->dim * i + a];
+}
+
+static void reduce_dim(const rcp_ctx *c, int64_t n, const double *x3, double *xu)
+{
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < c->dim; ++a) xu[c->dim * i + a] = x3[3 * i + a];
+}
+
 int rcp_set_state(rcp_ctx *c, int k, const double *x, double kappa, int is_device)
+{
+    CHK(check_k(c, k));
+    if (c->dim == 3 || !x) return set_state3(c, k, x, kappa, is_device);
+    if (is_device) return fail(RCP_EINVAL, "device positions need dim = 3");
+    std::vector<double> x3;
+    expand_dim(c, c->segs[k].n, x, x3);
+    return set_state3(c, k, x3.data(), kappa, 0);
+}
+
+static int set_state3(rcp_ctx *c, int k, const double *x, double kappa, int is_device)
 {
     CHK(check_k(c, k));
     Seg &s = c->segs[k];
@@ -1794,15 +1832,16 @@ int rcp_set_frozen(rcp_ctx *c, int k, const uint8_t *mask)
     };
     for (int64_t i = 0; i < n; ++i) {
         const double d = s.d0h[i];
+        const double dd = c->dim == 2 ? d * d : d * d * d;   // D0^dim
         if (fz[i]) {
-            f3 += d * d * d;
+            f3 += dd;
             continue;
         }
         ++ng;
         dmin = std::min(dmin, d);
         nadd(sum, cs, d);
-        nadd(sum3, cs3, d * d * d);
-        nadd(sum6, cs6, (d * d * d) * (d * d * d));
+        nadd(sum3, cs3, dd);
+        nadd(sum6, cs6, dd * dd);
     }
     if (ng == 0) return fail(RCP_EINVAL, "packing %d: every sphere frozen", k);
     CHK(dgrow(&c->xtmp, &c->xtmp_cap, (n + 7) / 8));
@@ -1835,7 +1874,7 @@ int rcp_seat_device(rcp_ctx *c, int k, double kappa0, uint64_t seed, int64_t max
     const int64_t n = s.n;
     std::vector<double> x(3 * n);
     double kap = 0;
-    CHK(rcp_get_state(c, k, x.data(), &kap, nullptr));
+    CHK(get_state3(c, k, x.data(), &kap, nullptr));
     // the frozen spheres, binned on a grid whose cells are at least as wide
     // as the largest seating distance (27 cells hold every frozen sphere a
     // proposal can overlap)
@@ -1863,6 +1902,7 @@ int rcp_seat_device(rcp_ctx *c, int k, double kappa0, uint64_t seed, int64_t max
     a.kappa0 = kappa0;
     a.seed = seed;
     a.max_attempts = max_attempts;
+    a.dim = c->dim;
     const int64_t nf = (int64_t)fidx.size(), ng = (int64_t)gidx.size();
     std::vector<double> fxd(4 * std::max<int64_t>(nf, 1));
     std::vector<int32_t> start(ncell + 1, 0);
@@ -1920,10 +1960,20 @@ int rcp_seat_device(rcp_ctx *c, int k, double kappa0, uint64_t seed, int64_t max
     } while (false);
     dfree(d_f); dfree(d_g); dfree(d_x); dfree(d_start); dfree(d_gi); dfree(d_fail);
     if (rc != RCP_OK) return rc;
-    return rcp_set_state(c, k, x.data(), kappa0, 0);
+    return set_state3(c, k, x.data(), kappa0, 0);
 }
 
 int rcp_get_state(rcp_ctx *c, int k, double *x, double *kappa, double *diam)
+{
+    CHK(check_k(c, k));
+    if (c->dim == 3 || !x) return get_state3(c, k, x, kappa, diam);
+    std::vector<double> x3(3 * c->segs[k].n);
+    CHK(get_state3(c, k, x3.data(), kappa, diam));
+    reduce_dim(c, c->segs[k].n, x3.data(), x);
+    return RCP_OK;
+}
+
+static int get_state3(rcp_ctx *c, int k, double *x, double *kappa, double *diam)
 {
     CHK(check_k(c, k));
     CHK(pull_state(c));
@@ -1967,13 +2017,12 @@ int rcp_get_optimizer(rcp_ctx *c, int k, double *m, double *v, rcp_optimizer *o)
         CHK(dgrow(&c->xtmp, &c->xtmp_cap, 6 * s.n));
         launch_moments_io(c->d_ptrs, k, s.n, c->xtmp, c->xtmp + 3 * s.n, 0, c->stream);
         HIPCHK(hipGetLastError());
-        if (m)
-            HIPCHK(hipMemcpyAsync(m, c->xtmp, sizeof(double) * 3 * s.n, hipMemcpyDeviceToHost,
-                                  c->stream));
-        if (v)
-            HIPCHK(hipMemcpyAsync(v, c->xtmp + 3 * s.n, sizeof(double) * 3 * s.n,
-                                  hipMemcpyDeviceToHost, c->stream));
+        std::vector<double> h(6 * s.n);
+        HIPCHK(hipMemcpyAsync(h.data(), c->xtmp, sizeof(double) * 6 * s.n, hipMemcpyDeviceToHost,
+                              c->stream));
         HIPCHK(hipStreamSynchronize(c->stream));
+        if (m) reduce_dim(c, s.n, h.data(), m);
+        if (v) reduce_dim(c, s.n, h.data() + 3 * s.n, v);
     }
     return RCP_OK;
 }
@@ -1993,12 +2042,21 @@ int rcp_set_optimizer(rcp_ctx *c, int k, const double *m, const double *v,
         !(o->eta_k >= 0) || !std::isfinite(o->eta_k))
         return fail(RCP_EINVAL, "rcp_optimizer: bad value");
     const Seg &s = c->segs[k];
-    const int64_t n3 = 3 * s.n;
-    for (int64_t q = 0; m && q < n3; ++q)
+    const int64_t n3 = 3 * s.n, nd = (int64_t)c->dim * s.n;
+    for (int64_t q = 0; m && q < nd; ++q)
         if (!std::isfinite(m[q])) return fail(RCP_EINVAL, "first moment %lld is not finite", (long long)q);
-    for (int64_t q = 0; v && q < n3; ++q)
+    for (int64_t q = 0; v && q < nd; ++q)
         if (!(v[q] >= 0) || !std::isfinite(v[q]))
             return fail(RCP_EINVAL, "second moment %lld is negative or not finite", (long long)q);
+    std::vector<double> m3, v3;   // (n, 3) copies; the z moments stay 0 in two dimensions
+    if (m) {
+        expand_dim(c, s.n, m, m3);
+        m = m3.data();
+    }
+    if (v) {
+        expand_dim(c, s.n, v, v3);
+        v = v3.data();
+    }
     SegState st = c->h_state[k];
     st.t = o->t;
     // beta powers as repeated products, as the iteration forms them
@@ -2113,10 +2171,12 @@ int rcp_energy_grad(rcp_ctx *c, int k, double mu, rcp_energy *e, double *grad_x)
     CHK(eval_current(c, k, nullptr, c->h_state[k].kappa, mu, gdev, c->stream));
     double o[6];
     HIPCHK(hipMemcpyAsync(o, c->out, sizeof o, hipMemcpyDeviceToHost, c->stream));
+    std::vector<double> g3(grad_x && c->dim != 3 ? 3 * s.n : 0);
     if (grad_x)
-        HIPCHK(hipMemcpyAsync(grad_x, gdev, sizeof(double) * 3 * s.n, hipMemcpyDeviceToHost,
-                              c->stream));
+        HIPCHK(hipMemcpyAsync(c->dim == 3 ? grad_x : g3.data(), gdev, sizeof(double) * 3 * s.n,
+                              hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    if (grad_x && c->dim != 3) reduce_dim(c, s.n, g3.data(), grad_x);
     e->E_overlap = o[0];
     e->E_growth = o[1];
     e->dE_dkappa_overlap = o[2];
@@ -2344,6 +2404,7 @@ int rcp_energy_dev(rcp_ctx *c, const double *x_dev, double kappa, double mu, dou
                    void *stream)
 {
     if (!c || !x_dev || !E_dev) return fail(RCP_EINVAL, "null argument");
+    if (c->dim != 3) return fail(RCP_EINVAL, "device position arrays need dim = 3");
     hipStream_t st = (hipStream_t)stream;   // NULL: the null stream
     CHK(ensure_valid_at(c, x_dev, kappa, st));
     CHK(eval_current(c, 0, x_dev, kappa, mu, nullptr, st));
@@ -2356,6 +2417,7 @@ int rcp_adjoint_dev(rcp_ctx *c, const double *x_dev, double kappa, double mu, do
                     double *gk_dev, void *stream)
 {
     if (!c || !x_dev || !gx_dev || !gk_dev) return fail(RCP_EINVAL, "null argument");
+    if (c->dim != 3) return fail(RCP_EINVAL, "device position arrays need dim = 3");
     hipStream_t st = (hipStream_t)stream;   // NULL: the null stream
     CHK(ensure_valid_at(c, x_dev, kappa, st));
     CHK(eval_current(c, 0, x_dev, kappa, mu, gx_dev, st));
@@ -2368,6 +2430,7 @@ int rcp_energy_dev_static(rcp_ctx *c, const double *x_dev, double kappa, double 
                           double *E_dev, void *stream)
 {
     if (!c || !x_dev || !E_dev) return fail(RCP_EINVAL, "null argument");
+    if (c->dim != 3) return fail(RCP_EINVAL, "device position arrays need dim = 3");
     if (!(kappa > 0) || !std::isfinite(kappa) || !std::isfinite(mu))
         return fail(RCP_EINVAL, "bad kappa or mu");
     const Seg &s = c->segs[0];

@@ -76,7 +76,9 @@ def test_invalid_arguments_rejected_without_device(L):
     assert b"diameter 2" in lib.rcp_last_error()
     d0 = np.array([1.0, 2.0, 3.0])
     dp = d0.ctypes.data_as(C.POINTER(C.c_double))
-    assert lib.rcp_pack_init(2, box, 3, dp, 1.0, 0, 1, None, None, C.byref(h)) == L.RCP_EINVAL
+    # dimensions other than 2 and 3 are refused
+    assert lib.rcp_pack_init(4, box, 3, dp, 1.0, 0, 1, None, None, C.byref(h)) == L.RCP_EINVAL
+    assert lib.rcp_pack_init(1, box, 3, dp, 1.0, 0, 1, None, None, C.byref(h)) == L.RCP_EINVAL
     assert lib.rcp_pack_init(3, box, 0, dp, 1.0, 0, 1, None, None, C.byref(h)) == L.RCP_EINVAL
     box2 = (C.c_double * 3)(10.0, 11.0, 10.0)
     assert lib.rcp_pack_init(3, box2, 3, dp, 1.0, 0, 1, None, None, C.byref(h)) == L.RCP_EINVAL
