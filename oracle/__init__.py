@@ -11,7 +11,8 @@ from .oracle import (build, lib, splitmix64, u01, pairs_brute, pairs_cells,
                      time_iterations, set_threads, num_threads, RunState,
                      default_params, absolute_schedule, Result, set_list_check,
                      list_misses, rsa_rounds, set_frozen, phi_frozen, seat,
-                     cascade, cascade_counts, set_dim, get_dim, release_schedule)
+                     cascade, cascade_counts, set_dim, get_dim, release_schedule,
+                     set_boundary, get_boundary)
 from . import oracle
 
 __all__ = [
@@ -20,5 +21,5 @@ __all__ = [
     "Params", "Schedule", "n_trig", "default_schedule", "time_iterations",
     "set_threads", "num_threads", "RunState", "set_list_check", "list_misses",
     "rsa_rounds", "set_frozen", "phi_frozen", "seat", "cascade", "cascade_counts",
-    "set_dim", "get_dim", "release_schedule",
+    "set_dim", "get_dim", "release_schedule", "set_boundary", "get_boundary",
 ]

@@ -80,6 +80,8 @@ def lib():
         L.orc_set_list_check.argtypes = [C.c_int, C.c_double]
         L.orc_set_dim.restype = None
         L.orc_set_dim.argtypes = [C.c_int]
+        L.orc_set_boundary.restype = None
+        L.orc_set_boundary.argtypes = [C.c_uint, C.c_uint]
         L.orc_set_frozen.restype = None
         L.orc_set_frozen.argtypes = [C.c_void_p]
         L.orc_phi_frozen.restype = C.c_double
@@ -173,6 +175,26 @@ def set_dim(d):
 
 def get_dim():
     return _dim
+
+
+_boundary = (0, 0)
+
+
+def set_boundary(walls=0, round=0):
+    """Hard walls (see orc_set_boundary): bit a of walls = flat walls at
+    x_a = 0 and x_a = L; round = the axes of a round container (ball of
+    diameter L centred at L/2 on them, two or three axes).  (0, 0) is the
+    periodic box.  Every later call uses it until changed."""
+    global _boundary
+    walls, round = int(walls), int(round)
+    assert 0 <= walls < 8 and 0 <= round < 8 and not (walls & round)
+    assert round == 0 or bin(round).count("1") >= 2
+    _boundary = (walls, round)
+    lib().orc_set_boundary(walls, round)
+
+
+def get_boundary():
+    return _boundary
 
 
 _frozen_ref = None

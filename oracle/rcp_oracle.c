@@ -30,7 +30,10 @@
  *     diameter while the other spheres inflate (see orc_set_frozen), and
  *     the seating of a new class in the voids of the frozen ones;
  *   - the spatial dimension d (the paper's input, Sec. 2; Fig. 1 is
- *     2-D): d = 2 packs disks in the plane z = 0 (see orc_set_dim).
+ *     2-D): d = 2 packs disks in the plane z = 0 (see orc_set_dim);
+ *   - hard walls (Sec. 2: each axis periodic or bounded by a flat or curved
+ *     hard wall): flat walls per axis and a round container over two or
+ *     three axes (see orc_set_boundary).
  *
  * Floating point: compiled with -ffp-contract=off; every quantity is double.
  * Sums of many terms (energy, kappa gradient) use Neumaier compensation.
@@ -64,6 +67,12 @@ double orc_u01(uint64_t seed, uint64_t i, uint64_t attempt, int axis)
 
 /* The spatial dimension, 3 or 2 (see orc_set_dim). */
 static int g_dim = 3;
+
+/* Boundary (see orc_set_boundary): bit a of g_walls = flat walls across
+ * axis a, bit a of g_round = axis a is one of the round container's. */
+static unsigned g_walls = 0, g_round = 0;
+
+static inline int periodic(int a) { return !(((g_walls | g_round) >> a) & 1u); }
 
 /* Coordinate ax of attempt a of sphere i: u(seed, i, a, ax) L in [0, L);
  * 0 for ax = 2 in two dimensions (not drawn). */
@@ -106,12 +115,18 @@ static inline double mimg(double d, double L, double hL)
     return d;
 }
 
+/* Along an axis bounded by walls there is no image: the plain difference. */
+static inline double mimg_ax(double d, int a, double L, double hL)
+{
+    return periodic(a) ? mimg(d, L, hL) : d;
+}
+
 static inline double sep2(const double *x, int64_t i, int64_t j, double L,
                           double hL, double *dx, double *dy, double *dz)
 {
-    *dx = mimg(x[3 * j] - x[3 * i], L, hL);
-    *dy = mimg(x[3 * j + 1] - x[3 * i + 1], L, hL);
-    *dz = mimg(x[3 * j + 2] - x[3 * i + 2], L, hL);
+    *dx = mimg_ax(x[3 * j] - x[3 * i], 0, L, hL);
+    *dy = mimg_ax(x[3 * j + 1] - x[3 * i + 1], 1, L, hL);
+    *dz = mimg_ax(x[3 * j + 2] - x[3 * i + 2], 2, L, hL);
     return (*dx * *dx + *dy * *dy) + *dz * *dz;
 }
 
@@ -390,6 +405,178 @@ int64_t orc_pairs_cells(int64_t n, const double *x, const double *d0, double L,
 void orc_set_dim(int d) { g_dim = (d == 2) ? 2 : 3; }
 
 /* ------------------------------------------------------------------ */
+/* Hard walls (Sec. 2: every axis periodic or bounded by a flat or     */
+/* curved hard wall; Fig. capabilities)                                */
+/* ------------------------------------------------------------------ */
+/* The paper names the boundaries but prints no wall energy.  Our reading:
+ *   - flat walls across axis a (bit a of walls): planes x_a = 0 and
+ *     x_a = L;
+ *   - a round container over the axes of `round` (two or three of them):
+ *     the ball of diameter L centred at L/2 on those axes (a circle in
+ *     2-D, a cylinder along the remaining axis or a sphere in 3-D);
+ *   - other axes stay periodic; a bounded axis has no image;
+ *   - a sphere of diameter sigma whose centre is at distance h from a wall
+ *     overlaps it when 2h < sigma, with delta = 1 - 2h / sigma (the overlap
+ *     depth over the radius, as 1 - r/d is the depth over the contact
+ *     distance of a pair; equivalently the pair term with the sphere's
+ *     mirror image, r = 2h and d = sigma) and energy delta^2 / 2, added to
+ *     the pair energy of Eq. (energy) and to the max overlap of the stop
+ *     rule;
+ *   - 2h is 2 x_a and 2 (L - x_a) for the flat walls and L - 2 rho for the
+ *     round one, rho the distance from the axis (or centre) over the round
+ *     axes, summed in axis order;
+ *   - gradient: d delta / d x_a = -2 / sigma and +2 / sigma for the lower and
+ *     upper flat walls, 2 (x_a - L/2) / (sigma rho) for the round wall;
+ *     dE/dkappa gains delta (2h / sigma) / kappa (sigma = kappa D0);
+ *   - the packing fraction is the sphere volume over the domain's volume
+ *     (the round axes contribute the disk or ball of diameter L);
+ *   - placement accepts only proposals that touch no wall at the placement
+ *     scale, and shrink to contact keeps every sphere clear of the walls.
+ * Frozen spheres are not combined with walls. */
+void orc_set_boundary(unsigned walls, unsigned round)
+{
+    g_walls = walls & 7u;
+    g_round = round & 7u;
+}
+
+/* rho^2 of position p over the round axes, in axis order. */
+static inline double round_rho2(const double *p, double L)
+{
+    double r2 = 0.0;
+    for (int a = 0; a < 3; ++a)
+        if ((g_round >> a) & 1u) {
+            const double u = p[a] - 0.5 * L;
+            r2 = r2 + u * u;
+        }
+    return r2;
+}
+
+/* Wall terms of a sphere of diameter sig at p: e += delta^2 / 2, s +=
+ * delta (2h / sig), m = max(m, delta), *cnt += contacts; g3 += dE/dx and
+ * gs3 += |dE/dx| (each may be NULL). */
+static void wall_terms(const double *p, double sig, double L, double *g3, double *gs3,
+                       double *e, double *s, double *m, int64_t *cnt)
+{
+    for (int a = 0; a < 3; ++a) {
+        if (!((g_walls >> a) & 1u)) continue;
+        for (int side = 0; side < 2; ++side) {
+            const double gap = side == 0 ? 2.0 * p[a] : 2.0 * (L - p[a]);
+            if (!(gap < sig)) continue;
+            const double delta = 1.0 - gap / sig;
+            *e += 0.5 * delta * delta;
+            *s += delta * (gap / sig);
+            if (delta > *m) *m = delta;
+            ++*cnt;
+            const double c = (side == 0 ? -2.0 : 2.0) * delta / sig;
+            if (g3) g3[a] += c;
+            if (gs3) gs3[a] += fabs(c);
+        }
+    }
+    if (g_round) {
+        const double rho = sqrt(round_rho2(p, L));
+        const double gap = L - 2.0 * rho;
+        if (gap < sig) {
+            const double delta = 1.0 - gap / sig;
+            *e += 0.5 * delta * delta;
+            *s += delta * (gap / sig);
+            if (delta > *m) *m = delta;
+            ++*cnt;
+            if (rho > 0.0)
+                for (int a = 0; a < 3; ++a)
+                    if ((g_round >> a) & 1u) {
+                        const double c = 2.0 * delta * (p[a] - 0.5 * L) / (sig * rho);
+                        if (g3) g3[a] += c;
+                        if (gs3) gs3[a] += fabs(c);
+                    }
+        }
+    }
+}
+
+/* Does a sphere of diameter fl(k D0) at p clear the round wall?  In squares,
+ * so that the answer is fixed by the rounding of + and * alone:
+ * t = L - k D0 >= 0 and t^2 >= 4 rho^2 (the same as L - 2 rho >= k D0). */
+static inline int round_clear(double k, double d0, double L, double q4)
+{
+    const double t = L - k * d0;
+    return t >= 0.0 && t * t >= q4;
+}
+
+/* Largest double k with fl(k D0) <= gap (a flat wall), or with
+ * round_clear (the round wall); 0 when even k = 0 does not clear. */
+static double flat_kmax(double gap, double d0)
+{
+    if (!(gap > 0.0)) return 0.0;
+    double k = gap / d0;
+    while (k > 0.0 && k * d0 > gap) k = nextafter(k, 0.0);
+    for (;;) {
+        const double up = nextafter(k, INFINITY);
+        if (up * d0 <= gap) k = up; else break;
+    }
+    return k;
+}
+
+static double round_kmax(double q4, double d0, double L)
+{
+    if (!round_clear(0.0, d0, L, q4)) return 0.0;
+    double k = (L - sqrt(q4)) / d0;
+    if (k < 0.0) k = 0.0;
+    while (k > 0.0 && !round_clear(k, d0, L, q4)) k = nextafter(k, 0.0);
+    for (;;) {
+        const double up = nextafter(k, INFINITY);
+        if (round_clear(up, d0, L, q4)) k = up; else break;
+    }
+    return k;
+}
+
+/* Largest scale at which sphere i (relative diameter d0) at p clears every
+ * wall (INFINITY with no walls). */
+static double wall_kmax(const double *p, double d0, double L)
+{
+    double k = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        if (!((g_walls >> a) & 1u)) continue;
+        const double lo = flat_kmax(2.0 * p[a], d0), hi = flat_kmax(2.0 * (L - p[a]), d0);
+        if (lo < k) k = lo;
+        if (hi < k) k = hi;
+    }
+    if (g_round) {
+        const double r = round_kmax(4.0 * round_rho2(p, L), d0, L);
+        if (r < k) k = r;
+    }
+    return k;
+}
+
+/* Placement test: a sphere of diameter sig at p touches no wall (touching
+ * allowed), with the predicates of the shrink. */
+static int inside_walls(const double *p, double sig, double L)
+{
+    for (int a = 0; a < 3; ++a) {
+        if (!((g_walls >> a) & 1u)) continue;
+        if (!(sig <= 2.0 * p[a]) || !(sig <= 2.0 * (L - p[a]))) return 0;
+    }
+    if (g_round) {
+        const double t = L - sig;
+        if (!(t >= 0.0 && t * t >= 4.0 * round_rho2(p, L))) return 0;
+    }
+    return 1;
+}
+
+/* Volume (area in 2-D) of the domain: L per plain axis, the disk or ball of
+ * diameter L over the round axes. */
+static double domain_volume(double L)
+{
+    int k = 0;
+    double v = 1.0;
+    for (int a = 0; a < g_dim; ++a) {
+        if ((g_round >> a) & 1u) ++k;
+        else v = v * L;
+    }
+    if (k == 2) v = v * ((M_PI / 4.0) * (L * L));
+    if (k == 3) v = v * ((M_PI / 6.0) * (L * L * L));
+    return v;
+}
+
+/* ------------------------------------------------------------------ */
 /* Frozen spheres (Sec. 4, the sequential multimodal cascade)          */
 /* ------------------------------------------------------------------ */
 /* A cascade stage seats a finer class in the voids of the coarser ones
@@ -433,8 +620,10 @@ static inline void nadd(nsum_t *a, double v)
 static inline double nval(const nsum_t *a) { return a->s + a->c; }
 
 /* Energy terms over a list of half pairs (i, j); pairs with r >= d add
- * nothing.  out = [E_overlap, E_growth, dE/dkappa overlap part,
- * dE/dkappa growth part, max fractional overlap, number overlapping].
+ * nothing; with walls, then every sphere's wall terms in index order.
+ * out = [E_overlap, E_growth, dE/dkappa overlap part, dE/dkappa growth
+ * part, max fractional overlap, number overlapping (pairs and wall
+ * contacts)].
  * gx (n x 3, may be NULL): dE/dx.  gscale (n x 3, may be NULL): per
  * component sum of |pair contributions|, the scale used by the parity
  * tolerance.  Pairs are processed in the order given. */
@@ -476,6 +665,14 @@ void orc_energy_grad(int64_t n, const double *x, const double *d0, double L,
             }
         }
     }
+    if (g_walls | g_round)
+        for (int64_t i = 0; i < n; ++i) {
+            double e = 0.0, sw = 0.0;
+            wall_terms(x + 3 * i, kappa * d0[i], L, gx ? gx + 3 * i : NULL,
+                       gscale ? gscale + 3 * i : NULL, &e, &sw, &maxd, &nov);
+            nadd(&E, e);
+            nadd(&S, sw);
+        }
     for (int64_t i = 0; i < n; ++i) nadd(&D, wgrow(d0, i));
     out[0] = nval(&E);
     out[1] = -mu * kappa * nval(&D);
@@ -489,7 +686,8 @@ void orc_energy_grad(int64_t n, const double *x, const double *d0, double L,
  * the true overlap condition r < d (no list).  For row k (particle i):
  * g[3k..3k+2] = dE/dx_i, gscale likewise, rowstat[3k] = sum_j delta^2/2
  * (each pair's energy counted in full for this row), rowstat[3k+1] =
- * sum_j delta r / d, rowstat[3k+2] = max_j delta. */
+ * sum_j delta r / d, rowstat[3k+2] = max_j delta; the row's wall terms
+ * (with walls) are included in all of them. */
 void orc_rows_grad(int64_t n, const double *x, const double *d0, double L,
                    double kappa, const int64_t *rows, int64_t nrows, double *g,
                    double *gscale, double *rowstat)
@@ -517,6 +715,10 @@ void orc_rows_grad(int64_t n, const double *x, const double *d0, double L,
                 for (int a = 0; a < 3; ++a) { gg[a] += c[a]; sc[a] += fabs(c[a]); }
             }
         }
+        if (g_walls | g_round) {
+            int64_t cnt = 0;
+            wall_terms(x + 3 * i, kappa * d0[i], L, gg, sc, &e, &s, &m, &cnt);
+        }
         for (int a = 0; a < 3; ++a) {
             g[3 * k + a] = gg[a];
             if (gscale) gscale[3 * k + a] = sc[a];
@@ -542,12 +744,12 @@ static double pair_kmax(double r2, double dd)
     return k;
 }
 
-/* kappa' = min(kappa, min over the pairs of pair_kmax).  Touching (r = d)
- * counts as no overlap. */
+/* kappa' = min(kappa, min over the pairs of pair_kmax, and with walls the
+ * min over the spheres of wall_kmax).  Touching (r = d, 2h = sigma) counts
+ * as no overlap. */
 double orc_shrink(int64_t n, const double *x, const double *d0, double L,
                   double kappa, int64_t np, const int32_t *pi, const int32_t *pj)
 {
-    (void)n;
     const double hL = 0.5 * L;
     double kp = kappa;
     for (int64_t p = 0; p < np; ++p) {
@@ -557,6 +759,11 @@ double orc_shrink(int64_t n, const double *x, const double *d0, double L,
         double k = pair_kmax(r2, dd);
         if (k < kp) kp = k;
     }
+    if (g_walls | g_round)
+        for (int64_t i = 0; i < n; ++i) {
+            const double k = wall_kmax(x + 3 * i, d0[i], L);
+            if (k < kp) kp = k;
+        }
     return kp;
 }
 
@@ -565,10 +772,10 @@ double orc_phi(int64_t n, const double *d0, double L, double kappa)
     nsum_t s = {0, 0};
     if (g_dim == 2) {
         for (int64_t i = 0; i < n; ++i) nadd(&s, d0[i] * d0[i]);
-        return (M_PI / 4.0) * (kappa * kappa) * nval(&s) / (L * L);
+        return (M_PI / 4.0) * (kappa * kappa) * nval(&s) / domain_volume(L);
     }
     for (int64_t i = 0; i < n; ++i) nadd(&s, d0[i] * d0[i] * d0[i]);
-    return (M_PI / 6.0) * (kappa * kappa * kappa) * nval(&s) / (L * L * L);
+    return (M_PI / 6.0) * (kappa * kappa * kappa) * nval(&s) / domain_volume(L);
 }
 
 /* Volume fraction with the frozen mask: sum over i of sigma_i^3. */
@@ -579,8 +786,8 @@ double orc_phi_frozen(int64_t n, const double *d0, double L, double kappa)
         const double si = sigma(d0, i, kappa);
         nadd(&s, g_dim == 2 ? si * si : si * si * si);
     }
-    return g_dim == 2 ? (M_PI / 4.0) * nval(&s) / (L * L)
-                      : (M_PI / 6.0) * nval(&s) / (L * L * L);
+    return g_dim == 2 ? (M_PI / 4.0) * nval(&s) / domain_volume(L)
+                      : (M_PI / 6.0) * nval(&s) / domain_volume(L);
 }
 
 /* Seating of a new class (Sec. 4: the finer class is seated in the voids
@@ -613,9 +820,9 @@ int orc_seat(int64_t n, const double *d0, double L, double kappa0, uint64_t seed
             int ok = 1;
             for (int64_t q = 0; q < nf && ok; ++q) {
                 const int64_t j = fz[q];
-                double dx = mimg(x[3 * j] - p[0], L, hL);
-                double dy = mimg(x[3 * j + 1] - p[1], L, hL);
-                double dz = mimg(x[3 * j + 2] - p[2], L, hL);
+                double dx = mimg_ax(x[3 * j] - p[0], 0, L, hL);
+                double dy = mimg_ax(x[3 * j + 1] - p[1], 1, L, hL);
+                double dz = mimg_ax(x[3 * j + 2] - p[2], 2, L, hL);
                 double r2 = (dx * dx + dy * dy) + dz * dz;
                 double dd = 0.5 * (d0[j] + kappa0 * d0[i]);
                 if (r2 < dd * dd) ok = 0;
@@ -636,7 +843,8 @@ int orc_seat(int64_t n, const double *d0, double L, double kappa0, uint64_t seed
 /* ------------------------------------------------------------------ */
 /* Largest sphere first (ties: lower index first).  Attempt a of sphere i
  * proposes (u(seed,i,a,0) L, u(seed,i,a,1) L, u(seed,i,a,2) L) and is
- * rejected when r^2 < (kappa0 * 0.5 * (D0_i + D0_j))^2 for a placed j.
+ * rejected when r^2 < (kappa0 * 0.5 * (D0_i + D0_j))^2 for a placed j, or
+ * (with walls) when the sphere at scale kappa0 would overlap a wall.
  * Returns 0, or -1 when a sphere needs more than max_attempts. */
 typedef struct { double d; int64_t i; } ord_t;
 
@@ -677,6 +885,7 @@ int orc_rsa(int64_t n, const double *d0, double L, double kappa0, uint64_t seed,
                 p[ax] = coord_draw(seed, i, a, ax, L);
                 x[3 * i + ax] = p[ax];
             }
+            if (!inside_walls(p, kappa0 * d0[i], L)) continue;
             int64_t c[3];
             for (int ax = 0; ax < 3; ++ax) c[ax] = cell_of(p[ax], w, nc);
             int ok = 1;
@@ -726,7 +935,8 @@ int orc_rsa(int64_t n, const double *d0, double L, double kappa0, uint64_t seed,
  *     i of the window proposes the position of its next attempt a_i,
  *     (u(seed, i, a_i, 0) L, u(seed, i, a_i, 1) L, u(seed, i, a_i, 2) L);
  *   - a proposal is valid when it overlaps no placed sphere (r^2 < dd^2,
- *     dd = kappa0 (D0_i + D0_j) / 2, separation x_j - p_i, minimum image);
+ *     dd = kappa0 (D0_i + D0_j) / 2, separation x_j - p_i, minimum image)
+ *     and, with walls, no wall at scale kappa0;
  *   - a valid proposal is accepted unless a valid proposal of a lower rank
  *     in the same round overlaps it (separation p_j - p_i);
  *   - accepted spheres are placed; every other sphere of the window that
@@ -777,12 +987,12 @@ int orc_rsa_rounds(int64_t n, const double *d0, double L, double kappa0, uint64_
                 if (placed[k]) continue;
                 double *p = prop + 3 * s;
                 for (int ax = 0; ax < 3; ++ax) p[ax] = coord_draw(seed, i, att[k], ax, L);
-                int ok = 1;
+                int ok = inside_walls(p, kappa0 * d0[i], L);
                 for (int64_t q = 0; q < nplaced && ok; ++q) {
                     int64_t j = placed_list[q];
-                    double dx = mimg(x[3 * j] - p[0], L, hL);
-                    double dy = mimg(x[3 * j + 1] - p[1], L, hL);
-                    double dz = mimg(x[3 * j + 2] - p[2], L, hL);
+                    double dx = mimg_ax(x[3 * j] - p[0], 0, L, hL);
+                    double dy = mimg_ax(x[3 * j + 1] - p[1], 1, L, hL);
+                    double dz = mimg_ax(x[3 * j + 2] - p[2], 2, L, hL);
                     double r2 = (dx * dx + dy * dy) + dz * dz;
                     double dd = kappa0 * (0.5 * (d0[i] + d0[j]));
                     if (r2 < dd * dd) ok = 0;
@@ -799,9 +1009,9 @@ int orc_rsa_rounds(int64_t n, const double *d0, double L, double kappa0, uint64_
                     int64_t s2 = k2 - lo, j = ord[k2].i;
                     if (placed[k2] || !valid[s2]) continue;
                     const double *pi_ = prop + 3 * s, *pj_ = prop + 3 * s2;
-                    double dx = mimg(pj_[0] - pi_[0], L, hL);
-                    double dy = mimg(pj_[1] - pi_[1], L, hL);
-                    double dz = mimg(pj_[2] - pi_[2], L, hL);
+                    double dx = mimg_ax(pj_[0] - pi_[0], 0, L, hL);
+                    double dy = mimg_ax(pj_[1] - pi_[1], 1, L, hL);
+                    double dz = mimg_ax(pj_[2] - pi_[2], 2, L, hL);
                     double r2 = (dx * dx + dy * dy) + dz * dz;
                     double dd = kappa0 * (0.5 * (d0[i] + d0[j]));
                     if (r2 < dd * dd) ok = 0;
@@ -989,6 +1199,10 @@ static void run_grad(run_t *R, double kappa, double *Eov, double *Sdrd,
                 ga[0] += fabs(f * dx); ga[1] += fabs(f * dy); ga[2] += fabs(f * dz);
             }
         }
+        if (g_walls | g_round) {   /* the row's wall terms, in full */
+            int64_t cnt = 0;
+            wall_terms(R->x + 3 * i, kappa * R->d0[i], R->L, gg, ga, &e, &s, &m, &cnt);
+        }
         R->g[3 * i] = gg[0]; R->g[3 * i + 1] = gg[1]; R->g[3 * i + 2] = gg[2];
         if (R->gsmax)
             for (int a = 0; a < 3; ++a)
@@ -1118,8 +1332,10 @@ int orc_run(int64_t n, double *x, const double *d0, double L, double *kappa,
             if (frozen(q / 3)) continue;   /* held fixed: no step */
             double th = adam(x[q], R.g[q], &m[q], &v[q], b1, b2, b1t, b2t, ex,
                              P->eps_x);
-            if (th < 0.0) th += L;
-            if (th >= L) th -= L;
+            if (periodic((int)(q % 3))) {   /* no wrap across walls */
+                if (th < 0.0) th += L;
+                if (th >= L) th -= L;
+            }
             x[q] = th;
         }
         *kappa = adam(*kappa, gk, &mk, &vk, b1, b2, b1t, b2t, ek, P->eps_k);
@@ -1137,9 +1353,9 @@ int orc_run(int64_t n, double *x, const double *d0, double L, double *kappa,
         double lim = g_trigger_scale * (P->skin_s * R.kb * R.d0min);
         double md2 = 0.0;
         for (int64_t i = 0; i < n; ++i) {
-            double dx = mimg(x[3 * i] - R.xref[3 * i], L, R.hL);
-            double dy = mimg(x[3 * i + 1] - R.xref[3 * i + 1], L, R.hL);
-            double dz = mimg(x[3 * i + 2] - R.xref[3 * i + 2], L, R.hL);
+            double dx = mimg_ax(x[3 * i] - R.xref[3 * i], 0, L, R.hL);
+            double dy = mimg_ax(x[3 * i + 1] - R.xref[3 * i + 1], 1, L, R.hL);
+            double dz = mimg_ax(x[3 * i + 2] - R.xref[3 * i + 2], 2, L, R.hL);
             double d2 = (dx * dx + dy * dy) + dz * dz;
             if (d2 > md2) md2 = d2;
         }
