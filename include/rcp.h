@@ -274,7 +274,9 @@ int rcp_pack_init(int dim, const double *box, int64_t n, const double *d0,
  * attempt.  The positions replace the packing's state as rcp_set_state
  * does.  rounds (may be NULL) receives the number of rounds.  RCP_EINVAL for
  * window < 1 or more than 64 size classes, RCP_EPLACE when a sphere needs
- * more than 2^22 attempts. */
+ * more than 2^22 attempts (a fraction above what random sequential addition
+ * can reach, about 0.38 for equal spheres and 0.55 for equal disks, takes
+ * that many rounds before it fails: minutes). */
 int rcp_place_device(rcp_ctx *ctx, int k, uint64_t seed, int64_t window, int64_t *rounds);
 
 /* Frozen spheres, for the stages of the sequential multimodal cascade
@@ -294,8 +296,40 @@ int rcp_place_device(rcp_ctx *ctx, int k, uint64_t seed, int64_t window, int64_t
  * (or all zero) frees every sphere.  While any packing of the context has
  * frozen spheres, the iteration uses the two-gather kernel whatever the
  * tuning variant, and the tail is not fused.  RCP_EINVAL when every sphere
- * would be frozen. */
+ * would be frozen, or when the packing has walls (rcp_set_boundary). */
 int rcp_set_frozen(rcp_ctx *ctx, int k, const uint8_t *mask);
+
+/* Hard walls of packing k (Sec. 2: every coordinate direction may be
+ * periodic or bounded by a flat or curved hard wall; rectilinear, circular,
+ * cylindrical and spherical domains).  Bit a of `walls` puts flat walls at
+ * x_a = 0 and x_a = L across axis a; `round` names the axes (two or three)
+ * of a round container, the disk or ball of diameter L centred at L/2 on
+ * them (a circle in two dimensions; in three, a cylinder along the
+ * remaining axis, or a sphere); the remaining axes stay periodic.  A
+ * bounded axis has no image and positions on it are not wrapped.  The
+ * paper gives no wall energy; ours: a sphere of diameter sigma whose centre
+ * is at distance h from a wall overlaps it when 2h < sigma, with
+ * delta = 1 - 2h / sigma (the pair term of Eq. (energy) with the sphere's
+ * mirror image) and energy delta^2 / 2, counted in E_overlap,
+ * dE_dkappa_overlap (delta (2h / sigma) / kappa), max_overlap (so in the
+ * stop test) and n_overlap.  2h is 2 x_a and 2 (L - x_a) for flat walls and
+ * L - 2 rho for the round one, rho the distance from the container's axis
+ * or centre.  Device placement (rcp_place_device) then accepts only
+ * proposals that touch no wall at the placement scale (flat:
+ * fl(kappa D0) <= 2 x_a and <= 2 (L - x_a); round: t = L - fl(kappa D0) >= 0
+ * and t^2 >= 4 rho^2, no contraction), the shrink keeps every sphere clear
+ * of the walls by the same tests, and phi divides by the container's
+ * volume (L per plain axis, (pi/4) L^2 or (pi/6) L^3 over the round axes).
+ * Host placement at creation (RCP_INIT_RSA) knows no walls: create with
+ * RCP_INIT_NONE, set the boundary, then place with rcp_place_device or set
+ * positions with rcp_set_state.  The list is rebuilt before the next
+ * evaluation.  While any packing has walls, the iteration uses the
+ * two-gather kernel whatever the tuning variant, and the tail is not
+ * fused.  walls = round = 0 is the periodic box.  RCP_EINVAL for an axis
+ * beyond dim, an axis in both masks, a round container of one axis, or a
+ * packing with frozen spheres (walls and frozen spheres are not
+ * combined). */
+int rcp_set_boundary(rcp_ctx *ctx, int k, uint32_t walls, uint32_t round);
 
 /* Seating of a new class in the voids of the frozen spheres (Sec. 4): every
  * sphere of packing k that is not frozen gets, independently, its first

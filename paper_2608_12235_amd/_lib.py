@@ -113,6 +113,7 @@ SIGNATURES = {
     "rcp_run_continue": (C.c_int, [vp, C.c_int64, i32p]),
     "rcp_run_prepare": (C.c_int, [vp]),
     "rcp_set_frozen": (C.c_int, [vp, C.c_int, C.c_void_p]),
+    "rcp_set_boundary": (C.c_int, [vp, C.c_int, C.c_uint32, C.c_uint32]),
     "rcp_seat_device": (C.c_int, [vp, C.c_int, C.c_double, C.c_uint64, C.c_int64]),
     "rcp_run_result": (C.c_int, [vp, C.c_int, C.POINTER(Result)]),
     "rcp_shrink": (C.c_int, [vp, C.c_int, dp, dp]),

@@ -4,7 +4,8 @@ import ctypes as C
 import numpy as np
 
 from ._lib import (lib, check, Params, Tuning, Schedule, Energy, Result, Stats, Optimizer,
-                   RCP_INIT_NONE, RCP_INIT_RSA, RCP_INIT_UNIFORM, RCP_INIT_RSA_DEVICE, RcpError)
+                   RCP_INIT_NONE, RCP_INIT_RSA, RCP_INIT_UNIFORM, RCP_INIT_RSA_DEVICE,
+                   RCP_PLACE_WINDOW, RcpError)
 
 _INIT = {"none": RCP_INIT_NONE, "rsa": RCP_INIT_RSA, "uniform": RCP_INIT_UNIFORM,
          "rsa_device": RCP_INIT_RSA_DEVICE}
@@ -64,10 +65,15 @@ def _result_dict(r):
 
 
 class Packing:
-    """One or several independent periodic packings on the GPU (an rcp_ctx)."""
+    """One or several independent packings on the GPU (an rcp_ctx); periodic
+    unless `boundary` gives hard walls."""
 
     def __init__(self, d0, L, kappa0=1.0, seed=0, init="rsa", params=None, stream=None,
-                 tuning=None, dim=3):
+                 tuning=None, dim=3, boundary=None):
+        """boundary: None (periodic), or (walls, round) axis masks (see
+        set_boundary) for every packing, or a list of them, one per packing.
+        With walls, init "rsa" and "rsa_device" both place on the device
+        after the walls are set (the host placement knows no walls)."""
         d0s = d0 if isinstance(d0, (list, tuple)) else [d0]
         Ls = L if isinstance(L, (list, tuple, np.ndarray)) else [L]
         P = len(d0s)
@@ -84,9 +90,24 @@ class Packing:
         self.params = params if params is not None else make_params()
         h = C.c_void_p()
         self.dim = int(dim)
-        check(lib().rcp_census_init(self.dim, P, ns, ptrs, box, kap, sd, _INIT[init],
+        bnd = None
+        if boundary is not None:
+            bnd = list(boundary) if isinstance(boundary, list) else [tuple(boundary)] * P
+            assert len(bnd) == P
+        walled = bnd is not None and any(w or r for w, r in bnd)
+        mode = _INIT[init]
+        if walled and init in ("rsa", "rsa_device"):
+            mode = RCP_INIT_NONE
+        check(lib().rcp_census_init(self.dim, P, ns, ptrs, box, kap, sd, mode,
                                     C.byref(self.params), stream, C.byref(h)))
         self._h = h
+        self.boundary = [(0, 0)] * P
+        if bnd is not None:
+            for k, (w, r) in enumerate(bnd):
+                self.set_boundary(w, r, k)
+            if walled and init in ("rsa", "rsa_device"):
+                for k in range(P):
+                    self.place_device(seeds[k], RCP_PLACE_WINDOW, k)
         self.tuning = make_tuning()
         if tuning is not None:
             self.set_tuning(tuning)
@@ -235,6 +256,13 @@ class Packing:
         m = np.ascontiguousarray(mask, dtype=np.uint8)
         assert m.shape[0] == self.n[k]
         check(lib().rcp_set_frozen(self._h, k, m.ctypes.data))
+
+    def set_boundary(self, walls=0, round=0, k=0):
+        """Hard walls of packing k: bit a of `walls` = flat walls at 0 and L
+        across axis a; `round` = the axes (two or three) of a round container
+        of diameter L centred at L/2; (0, 0) = periodic."""
+        check(lib().rcp_set_boundary(self._h, k, int(walls), int(round)))
+        self.boundary[k] = (int(walls), int(round))
 
     def seat(self, kappa0, seed, max_attempts=1 << 22, k=0):
         """Seat the spheres that are not frozen in the voids of the frozen

@@ -104,14 +104,17 @@ constexpr double kLoose = 1.0 + 0x1p-50;
 // the pair's dE/dkappa is delta (r / d^2) dd/dkappa with dd/dkappa = (g_i D0_i
 // + g_j D0_j) / 2 (g = 0 for a frozen sphere); S gains delta q (kappa dd/dkappa
 // / d) / 2, so that S / kappa in the tail is that derivative summed.
+//
+// iLa[a] is 1 / L on a periodic axis and 0 on an axis bounded by walls
+// (no image: near_image then returns the plain difference).
 template <bool kCount = true, bool kMixed = false>
 __device__ __forceinline__ void pair_term(Acc &a, const P4 &qi, const P4 &qj, double kappa,
-                                          double L, double iL)
+                                          double L, const double (&iLa)[3])
 {
 #pragma clang fp contract(off)
-    const double dx = near_image(qj.x - qi.x, L, iL);
-    const double dy = near_image(qj.y - qi.y, L, iL);
-    const double dz = near_image(qj.z - qi.z, L, iL);
+    const double dx = near_image(qj.x - qi.x, L, iLa[0]);
+    const double dy = near_image(qj.y - qi.y, L, iLa[1]);
+    const double dz = near_image(qj.z - qi.z, L, iLa[2]);
     const double r2 = (dx * dx + dy * dy) + dz * dz;
     const double d = kMixed ? 0.5 * ((qi.d > 0.0 ? kappa * qi.d : -qi.d) +
                                      (qj.d > 0.0 ? kappa * qj.d : -qj.d))
@@ -153,7 +156,8 @@ __device__ __forceinline__ void pair_term(Acc &a, const P4 &qi, const P4 &qj, do
 }
 
 // Adam on one coordinate (Kingma and Ba, bias corrected; ib1 = 1 / (1 -
-// beta1^t), ib2 = 1 / (1 - beta2^t)), then wrapped into [0, L).
+// beta1^t), ib2 = 1 / (1 - beta2^t)), then wrapped into [0, L) (L = 0 on an
+// axis bounded by walls leaves the coordinate as it is).
 __device__ __forceinline__ double adam_coord(double th, double g, double &m, double &v,
                                              double b1, double b2, double ib1, double ib2,
                                              double eta, double eps, double L)
@@ -173,6 +177,10 @@ __device__ __forceinline__ double adam_coord(double th, double g, double &m, dou
 
 struct IterScalars {
     double kappa, L, hL, iL, b1, b2, ib1, ib2, eta, eps;
+    // per axis: 1 / L and the wrap period L, both 0 on an axis bounded by
+    // walls; the walls themselves (see wall_terms)
+    double iLa[3], Pa[3];
+    int32_t walls, round;
 };
 
 // Pointers of one segment with the ping-pong buffers already selected
@@ -211,9 +219,9 @@ __device__ __forceinline__ IterPtrs select_ptrs(const SegPtrs *__restrict__ P, i
 // list reference to d2.
 __device__ __forceinline__ double update_coord(double xi, double g, double m, double v, double r,
                                                double *mm, double *vv, const IterScalars &c,
-                                               int64_t i, double &d2)
+                                               int64_t i, double &d2, double period)
 {
-    const double xn = adam_coord(xi, g, m, v, c.b1, c.b2, c.ib1, c.ib2, c.eta, c.eps, c.L);
+    const double xn = adam_coord(xi, g, m, v, c.b1, c.b2, c.ib1, c.ib2, c.eta, c.eps, period);
     gstore(mm, i, m);
     gstore(vv, i, v);
     const double dd = min_image(xn - r, c.L, c.hL);
@@ -258,9 +266,9 @@ __device__ __forceinline__ double update_particle(const IterPtrs &p, const IterS
     }
     double d2 = 0.0;
     P4 o;
-    o.x = update_coord(qi.x, gx, q.m0, q.v0, q.r0, p.m0, p.v0, c, i, d2);
-    o.y = update_coord(qi.y, gy, q.m1, q.v1, q.r1, p.m1, p.v1, c, i, d2);
-    o.z = update_coord(qi.z, gz, q.m2, q.v2, q.r2, p.m2, p.v2, c, i, d2);
+    o.x = update_coord(qi.x, gx, q.m0, q.v0, q.r0, p.m0, p.v0, c, i, d2, c.Pa[0]);
+    o.y = update_coord(qi.y, gy, q.m1, q.v1, q.r1, p.m1, p.v1, c, i, d2, c.Pa[1]);
+    o.z = update_coord(qi.z, gz, q.m2, q.v2, q.r2, p.m2, p.v2, c, i, d2, c.Pa[2]);
     o.d = qi.d;
     if (full) store_p4(p.qo, (int32_t)i, o);
     else store_xyz(p.qo, (int32_t)i, o.x, o.y, o.z);
@@ -487,10 +495,10 @@ __device__ __forceinline__ void segment_terms(Acc &a, const ColSrc<kStage> &cols
                 j2 = cols.at(q + 2);
                 j3 = cols.at(q + 3);
             }
-            pair_term<false, kMixed>(a, qi, q0, c.kappa, c.L, c.iL);
-            pair_term<false, kMixed>(a, qi, q1, c.kappa, c.L, c.iL);
-            pair_term<false, kMixed>(a, qi, q2, c.kappa, c.L, c.iL);
-            pair_term<false, kMixed>(a, qi, q3, c.kappa, c.L, c.iL);
+            pair_term<false, kMixed>(a, qi, q0, c.kappa, c.L, c.iLa);
+            pair_term<false, kMixed>(a, qi, q1, c.kappa, c.L, c.iLa);
+            pair_term<false, kMixed>(a, qi, q2, c.kappa, c.L, c.iLa);
+            pair_term<false, kMixed>(a, qi, q3, c.kappa, c.L, c.iLa);
             if (!more) break;
         }
     }
@@ -504,8 +512,8 @@ __device__ __forceinline__ void segment_terms(Acc &a, const ColSrc<kStage> &cols
                 j0 = cols.at(q);
                 j1 = cols.at(q + 1);
             }
-            pair_term<false, kMixed>(a, qi, q0, c.kappa, c.L, c.iL);
-            pair_term<false, kMixed>(a, qi, q1, c.kappa, c.L, c.iL);
+            pair_term<false, kMixed>(a, qi, q0, c.kappa, c.L, c.iLa);
+            pair_term<false, kMixed>(a, qi, q1, c.kappa, c.L, c.iLa);
             if (!more) break;
         }
     }
@@ -513,10 +521,10 @@ __device__ __forceinline__ void segment_terms(Acc &a, const ColSrc<kStage> &cols
         const int32_t j0 = cols.at(q),
                       j1 = cols.at(q + 1);
         const P4 q0 = load_p4(Q, j0), q1 = load_p4(Q, j1);
-        pair_term<false, kMixed>(a, qi, q0, c.kappa, c.L, c.iL);
-        pair_term<false, kMixed>(a, qi, q1, c.kappa, c.L, c.iL);
+        pair_term<false, kMixed>(a, qi, q0, c.kappa, c.L, c.iLa);
+        pair_term<false, kMixed>(a, qi, q1, c.kappa, c.L, c.iLa);
     }
-    if (q < qe) pair_term<false, kMixed>(a, qi, load_p4(Q, cols.at(q)), c.kappa, c.L, c.iL);
+    if (q < qe) pair_term<false, kMixed>(a, qi, load_p4(Q, cols.at(q)), c.kappa, c.L, c.iLa);
 }
 
 template <int kN>
@@ -555,7 +563,7 @@ struct NoHook {
 // between the phases (the persistent kernel prefetches there).  Thread 0
 // writes the item's partial sums to *out.  Every thread must call it.
 template <int kU, bool kEarly, bool kStage, int kR, class Hook, bool kCoherentOut = false,
-          bool kMixed = false>
+          bool kMixed = false, bool kWalls = false>
 __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &c, int64_t r0,
                                           int nrow, int32_t e0, int32_t e1,
                                           const int32_t *rp_own, int32_t rp_end,
@@ -654,6 +662,17 @@ __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &
                 }
             }
         }
+        if (kWalls) {
+            // the row's wall terms (a sphere against the walls, in full)
+            WallAcc w = {{0.0, 0.0, 0.0}, 0.0, 0.0, 0.0, 0.0};
+            const double px[3] = {oq.x, oq.y, oq.z};
+            wall_terms(px, c.kappa * oq.d, c.L, c.walls, c.round, w);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) g[d] += w.g[d];
+            a.e += w.e;
+            a.s += w.s;
+            a.m = fmax(a.m, w.m);
+        }
         bd = fmax(bd, update_particle<kMixed>(p, c, io, oq, pre, g[0], g[1], g[2], full));
     }
     // block reduction of the four partials
@@ -696,6 +715,7 @@ __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &
     }
 }
 
+template <bool kWalls = false>
 __device__ __forceinline__ void load_scalars(const SegState *s, IterScalars &c)
 {
     c.kappa = s->kappa;
@@ -708,11 +728,21 @@ __device__ __forceinline__ void load_scalars(const SegState *s, IterScalars &c)
     c.ib2 = s->ib2n;
     c.eta = s->eta_x;
     c.eps = s->eps_x;
+    const int32_t bounded = kWalls ? (s->walls | s->round) : 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const bool b = (bounded >> a) & 1;
+        c.iLa[a] = b ? 0.0 : c.iL;
+        c.Pa[a] = b ? 0.0 : c.L;
+    }
+    c.walls = kWalls ? s->walls : 0;
+    c.round = kWalls ? s->round : 0;
 }
 
 // One block per work item; kWaves > 1 asks the compiler for that many
 // waves per SIMD (fewer registers, a little spilling).
-template <bool kFusedTail, int kU, bool kEarly, bool kStage, int kWaves, bool kMixed = false>
+template <bool kFusedTail, int kU, bool kEarly, bool kStage, int kWaves, bool kMixed = false,
+          bool kWalls = false>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))) void k_iterate(const SegPtrs *__restrict__ P,
                                                    SegState *__restrict__ S,
                                                    const WorkItem *__restrict__ W,
@@ -723,7 +753,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
     SegState *s = S + w.seg;
     if (s->flags & F_IDLE) return;
     IterScalars c;
-    load_scalars(s, c);
+    load_scalars<kWalls>(s, c);
     const IterPtrs p = select_ptrs(P, w.seg, s->cur);
     __shared__ ItemLds L;
     __shared__ int32_t scol[kStage ? kColStage : 1];
@@ -732,7 +762,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
     const int nrow = (int)(w.end - w.begin);
     const int32_t rp_t = t < nrow ? gload(p.rp, r0 + t) : 0;
     const int32_t rp_end = gload(p.rp, r0 + nrow);
-    item_body<kU, kEarly, kStage, kBlock, NoHook, kFusedTail, kMixed>(
+    item_body<kU, kEarly, kStage, kBlock, NoHook, kFusedTail, kMixed, kWalls>(
         p, c, r0, nrow, w.e0, w.e1, &rp_t, rp_end, L, scol,
         reinterpret_cast<Part4 *>(partials) + b, NoHook(), (flags & 4) != 0);
     if (kFusedTail) {
@@ -868,12 +898,12 @@ __global__ __launch_bounds__(kBlock) void k_iterate_persist(const SegPtrs *__res
     }
 }
 
-template <bool kF, int kU, bool kE, bool kNT, int kW, bool kMixed = false>
+template <bool kF, int kU, bool kE, bool kNT, int kW, bool kMixed = false, bool kWalls = false>
 static void launch_one(const SegPtrs *P, SegState *S, const WorkItem *W, double *partials,
                        int nitems, int f, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_iterate<kF, kU, kE, kNT, kW, kMixed>), dim3(nitems), dim3(kBlock), 0,
-                       st, P, S, W, partials, f);
+    hipLaunchKernelGGL((k_iterate<kF, kU, kE, kNT, kW, kMixed, kWalls>), dim3(nitems),
+                       dim3(kBlock), 0, st, P, S, W, partials, f);
 }
 
 template <bool kF, int kW>
@@ -930,9 +960,14 @@ void launch_iterate(const SegPtrs *P, SegState *S, const WorkItem *W, double *pa
     // bit 0: XCD-aware order; bit 1: fused tail; bit 2: whole 32-byte
     // records written; bit 4: some packing has frozen spheres (then the
     // two-gather kernel with the mixed pair terms runs, whatever the
-    // variant); bits 8-13: kernel variant (see launch_variant)
+    // variant); bit 5: some packing has walls (then the two-gather kernel
+    // with the wall terms runs, whatever the variant; never together with
+    // bit 4); bits 8-13: kernel variant (see launch_variant)
     const int f = flags & 5, variant = (flags >> 8) & 63;
-    if (flags & 16) launch_one<false, 2, false, false, 1, true>(P, S, W, partials, nitems, f, st);
+    if (flags & 32)
+        launch_one<false, 2, false, false, 1, false, true>(P, S, W, partials, nitems, f, st);
+    else if (flags & 16)
+        launch_one<false, 2, false, false, 1, true>(P, S, W, partials, nitems, f, st);
     else if (variant & 40) launch_variant<false>(P, S, W, partials, nitems, f, variant, st);
     else if (flags & 2) launch_variant<true>(P, S, W, partials, nitems, f, variant, st);
     else launch_variant<false>(P, S, W, partials, nitems, f, variant, st);
@@ -1165,7 +1200,8 @@ void launch_set_flags(SegState *S, int seg, int32_t clear, int32_t set, hipStrea
 // ------------------------------------------------------- evaluation
 // Thread per row over the whole list (not on the iteration path); positions
 // from the user-order array xu (gathered through orig) or from the current
-// buffer.  Partials per block: E_ov, S, max delta, overlapping pairs.
+// buffer.  Partials per block: E_ov, S, max delta, overlapping pairs (and
+// wall contacts, with walls).
 __global__ __launch_bounds__(kBlock) void k_eval(const SegPtrs *__restrict__ P,
                                                 const SegState *__restrict__ S, int seg,
                                                 int64_t n, const double *__restrict__ xu,
@@ -1176,6 +1212,9 @@ __global__ __launch_bounds__(kBlock) void k_eval(const SegPtrs *__restrict__ P,
     const IterPtrs p = select_ptrs(P, seg, s->cur);
     const int32_t *orig = P[seg].orig;
     const double L = s->L, iL = 1.0 / L;
+    const int32_t bounded = s->walls | s->round;
+    const double iLa[3] = {(bounded & 1) ? 0.0 : iL, (bounded & 2) ? 0.0 : iL,
+                           (bounded & 4) ? 0.0 : iL};
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     double be = 0, bs = 0, bm = 0, bn = 0;
     if (i < n) {
@@ -1194,10 +1233,22 @@ __global__ __launch_bounds__(kBlock) void k_eval(const SegPtrs *__restrict__ P,
         Acc a = {0, 0, 0, 0, 0, 0, 0};
         if (s->mixed)
             for (int32_t q = p.rp[i]; q < p.rp[i + 1]; ++q)
-                pair_term<true, true>(a, qi, pos(p.col[q]), kappa, L, iL);
+                pair_term<true, true>(a, qi, pos(p.col[q]), kappa, L, iLa);
         else
             for (int32_t q = p.rp[i]; q < p.rp[i + 1]; ++q)
-                pair_term(a, qi, pos(p.col[q]), kappa, L, iL);
+                pair_term(a, qi, pos(p.col[q]), kappa, L, iLa);
+        if (bounded) {
+            WallAcc w = {{0.0, 0.0, 0.0}, 0.0, 0.0, 0.0, 0.0};
+            const double px[3] = {qi.x, qi.y, qi.z};
+            wall_terms(px, kappa * qi.d, L, s->walls, s->round, w);
+            a.gx += w.g[0];
+            a.gy += w.g[1];
+            a.gz += w.g[2];
+            a.e += w.e;
+            a.s += w.s;
+            a.m = fmax(a.m, w.m);
+            a.c += w.c;
+        }
         be = a.e;
         bs = a.s;
         bm = a.m;

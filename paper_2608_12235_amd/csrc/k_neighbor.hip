@@ -321,9 +321,9 @@ __global__ __launch_bounds__(kBlock) void k_search(BuildArgs a, uint64_t *__rest
                         for (int64_t j = r.x; j < (int64_t)r.x + r.y; ++j) {
                             if (L == li && j <= i) continue;
                             const P4 qj = a.pos[j];
-                            const double dx = min_image(qj.x - xi, a.L, a.hL);
-                            const double dy = min_image(qj.y - yi, a.L, a.hL);
-                            const double dz = min_image(qj.z - zi, a.L, a.hL);
+                            const double dx = min_image(qj.x - xi, a.L, a.hLa[0]);
+                            const double dy = min_image(qj.y - yi, a.L, a.hLa[1]);
+                            const double dz = min_image(qj.z - zi, a.L, a.hLa[2]);
                             const double r2 = (dx * dx + dy * dy) + dz * dz;
                             const double cc = a.kb * (a.opg * (0.5 * (di + fabs(qj.d))) + a.sk2);
                             if (r2 < cc * cc) {
@@ -714,9 +714,9 @@ __device__ __forceinline__ void test_plane(const BuildArgs &a, const SearchOut &
         if (has && (uint64_t)j < (uint64_t)a.n) {
             const P4 oq = out.own[o];
             const P4 qj = load_pos(a.pos, j);
-            const double dx = min_image(qj.x - oq.x, a.L, a.hL);
-            const double dy = min_image(qj.y - oq.y, a.L, a.hL);
-            const double dz = min_image(qj.z - oq.z, a.L, a.hL);
+            const double dx = min_image(qj.x - oq.x, a.L, a.hLa[0]);
+            const double dy = min_image(qj.y - oq.y, a.L, a.hLa[1]);
+            const double dz = min_image(qj.z - oq.z, a.L, a.hLa[2]);
             const double r2 = (dx * dx + dy * dy) + dz * dz;
             const double cc = a.kb * (a.opg * (0.5 * (fabs(oq.d) + fabs(qj.d))) + a.sk2);
             hit = r2 < cc * cc;

@@ -83,14 +83,15 @@ __device__ __forceinline__ int32_t place_push(PlaceSlot *tab, uint64_t mask, uin
     }
 }
 
+// hLa[ax] = L / 2, or +inf on an axis bounded by walls (no image).
 __device__ __forceinline__ bool place_overlap(double xj, double yj, double zj, const double *p,
                                               double dj, double di, double kappa0, double L,
-                                              double hL)
+                                              const double *hLa)
 {
 #pragma clang fp contract(off)
-    const double dx = place_mi(xj - p[0], L, hL);
-    const double dy = place_mi(yj - p[1], L, hL);
-    const double dz = place_mi(zj - p[2], L, hL);
+    const double dx = place_mi(xj - p[0], L, hLa[0]);
+    const double dy = place_mi(yj - p[1], L, hLa[1]);
+    const double dz = place_mi(zj - p[2], L, hLa[2]);
     const double r2 = (dx * dx + dy * dy) + dz * dz;
     const double dd = kappa0 * (0.5 * (di + dj));
     return r2 < dd * dd;
@@ -107,8 +108,8 @@ __global__ __launch_bounds__(kBlock) void k_place_clear(PlaceSlot *tab, int64_t 
 }
 
 // Proposals of ranks [lo, hi) of class c: position of the next attempt,
-// validity against the placed spheres (classes c and larger), and the valid
-// ones binned in the proposal table.
+// validity (clear of the walls, if any, and of the placed spheres of
+// classes c and larger), and the valid ones binned in the proposal table.
 __global__ __launch_bounds__(kBlock) void k_place_propose(PlaceArgs a, int c, int64_t lo,
                                                          int64_t hi)
 {
@@ -127,7 +128,10 @@ __global__ __launch_bounds__(kBlock) void k_place_propose(PlaceArgs a, int c, in
         p[ax] = v;
         a.prop[3 * s + ax] = v;
     }
-    bool ok = true;
+    const int32_t bounded = a.walls | a.round;
+    const double hLa[3] = {(bounded & 1) ? INFINITY : a.hL, (bounded & 2) ? INFINITY : a.hL,
+                           (bounded & 4) ? INFINITY : a.hL};
+    bool ok = !bounded || inside_walls(p, a.kappa0 * di, a.L, a.walls, a.round);
     for (int cc = c; cc < a.ncls && ok; ++cc) {
         const PlaceGrid &g = a.grid[cc];
         if (!g.any) continue;
@@ -149,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_place_propose(PlaceArgs a, int c, in
                     for (int32_t j = place_find(a.tab + g.off, g.mask, key); j >= 0;
                          j = a.next[j])
                         if (place_overlap(a.x[3 * j], a.x[3 * j + 1], a.x[3 * j + 2], p, a.d0[j],
-                                          di, a.kappa0, a.L, a.hL)) {
+                                          di, a.kappa0, a.L, hLa)) {
                             ok = false;
                             break;
                         }
@@ -176,6 +180,9 @@ __global__ __launch_bounds__(kBlock) void k_place_commit(PlaceArgs a, int c, int
     const int32_t i = a.ord[k];
     const double di = a.d0[i];
     const double p[3] = {a.prop[3 * s], a.prop[3 * s + 1], a.prop[3 * s + 2]};
+    const int32_t bounded = a.walls | a.round;
+    const double hLa[3] = {(bounded & 1) ? INFINITY : a.hL, (bounded & 2) ? INFINITY : a.hL,
+                           (bounded & 4) ? INFINITY : a.hL};
     bool acc = a.valid[s] != 0;
     if (acc) {
         const PlaceGrid &g = a.grid[c];
@@ -198,7 +205,7 @@ __global__ __launch_bounds__(kBlock) void k_place_commit(PlaceArgs a, int c, int
                         if (s2 >= s) continue;
                         const int32_t j = a.ord[lo + s2];
                         if (place_overlap(a.prop[3 * s2], a.prop[3 * s2 + 1], a.prop[3 * s2 + 2],
-                                          p, a.d0[j], di, a.kappa0, a.L, a.hL)) {
+                                          p, a.d0[j], di, a.kappa0, a.L, hLa)) {
                             acc = false;
                             break;
                         }

@@ -72,7 +72,10 @@ struct SegState {
     int64_t bfirst;       // first of them (index into the work table)
     // set at each list build (k_after_seg)
     double kb, disp_lim, kappa_lim;
-    int32_t pad0, pad0b;
+    // host: hard walls (bit a = axis a): flat walls at 0 and L across the
+    // axes of `walls`, a round container (disk or ball of diameter L
+    // centred at L/2) over the axes of `round`; other axes are periodic
+    int32_t walls, round;
     // reciprocals the iteration kernel would otherwise divide for in every
     // wave: 1 / L, and the bias corrections of the next position step,
     // 1 / (1 - beta1^(t+1)) and 1 / (1 - beta2^(t+1))
@@ -168,6 +171,99 @@ __device__ __forceinline__ double min_image(double d, double L, double hL)
     // d > hL gives d - L and d < -hL gives d - (-L) = d + L exactly: one
     // compare on |d| and one select instead of two of each
     return fabs(d) > hL ? d - copysign(L, d) : d;
+}
+
+// ------------------------------------------------------------ hard walls
+// Sec. 2: an axis may be bounded by flat hard walls (planes 0 and L) or be
+// one of two or three axes of a round container (the disk or ball of
+// diameter L centred at L/2).  A sphere of diameter sig at distance h from
+// a wall overlaps it when gap = 2h < sig, with delta = 1 - gap / sig (the
+// pair term with its mirror image) and energy delta^2 / 2.  gap is 2 x_a
+// and 2 (L - x_a) for the flat walls and L - 2 rho for the round one, rho
+// the distance from the container's axis or centre.  Every expression is
+// evaluated as written (no contraction): the placement and shrink
+// predicates must round exactly as stated.
+
+// rho^2 over the round axes, summed in axis order.
+__device__ __forceinline__ double round_rho2(double x, double y, double z, double L,
+                                             int32_t round)
+{
+#pragma clang fp contract(off)
+    double r2 = 0.0;
+    if (round & 1) {
+        const double u = x - 0.5 * L;
+        r2 = r2 + u * u;
+    }
+    if (round & 2) {
+        const double u = y - 0.5 * L;
+        r2 = r2 + u * u;
+    }
+    if (round & 4) {
+        const double u = z - 0.5 * L;
+        r2 = r2 + u * u;
+    }
+    return r2;
+}
+
+// Running sums of a sphere's wall terms: gradient, energy, kappa-gradient
+// part delta (gap / sig) (dE/dkappa is its sum over kappa), max delta,
+// contacts.
+struct WallAcc {
+    double g[3], e, s, m, c;
+};
+
+__device__ __forceinline__ void wall_terms(const double p[3], double sig, double L, int32_t walls,
+                                           int32_t round, WallAcc &w)
+{
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (!((walls >> a) & 1)) continue;
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const double gap = side == 0 ? 2.0 * p[a] : 2.0 * (L - p[a]);
+            if (!(gap < sig)) continue;
+            const double delta = 1.0 - gap / sig;
+            w.e += 0.5 * delta * delta;
+            w.s += delta * (gap / sig);
+            w.m = fmax(w.m, delta);
+            w.c += 1.0;
+            w.g[a] += (side == 0 ? -2.0 : 2.0) * delta / sig;
+        }
+    }
+    if (round) {
+        const double rho = sqrt(round_rho2(p[0], p[1], p[2], L, round));
+        const double gap = L - 2.0 * rho;
+        if (gap < sig) {
+            const double delta = 1.0 - gap / sig;
+            w.e += 0.5 * delta * delta;
+            w.s += delta * (gap / sig);
+            w.m = fmax(w.m, delta);
+            w.c += 1.0;
+            if (rho > 0.0) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    if ((round >> a) & 1) w.g[a] += 2.0 * delta * (p[a] - 0.5 * L) / (sig * rho);
+            }
+        }
+    }
+}
+
+// Placement test: a sphere of diameter sig at p touches no wall (touching
+// allowed); round: t = L - sig >= 0 and t^2 >= 4 rho^2.
+__device__ __forceinline__ bool inside_walls(const double p[3], double sig, double L,
+                                             int32_t walls, int32_t round)
+{
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if ((walls >> a) & 1)
+            if (!(sig <= 2.0 * p[a]) || !(sig <= 2.0 * (L - p[a]))) return false;
+    if (round) {
+        const double t = L - sig;
+        if (!(t >= 0.0 && t * t >= 4.0 * round_rho2(p[0], p[1], p[2], L, round))) return false;
+    }
+    return true;
 }
 
 // ------------------------------------------------------------ reductions

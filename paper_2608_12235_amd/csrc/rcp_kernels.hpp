@@ -45,6 +45,7 @@ struct BuildArgs {
     int32_t nlev, mb;       // classes; Morton bits below the class field
     int32_t tshift, tiles;  // key bit of the tile field; tiles per axis (power of 2)
     double L, hL, kb, opg, sk2;
+    double hLa[3];          // per axis: hL, or +inf on an axis bounded by walls (no image)
     const P4 *pos;
     const uint8_t *lev;
     const uint64_t *skey;   // sorted keys (after the sort)
@@ -150,7 +151,9 @@ struct PlaceArgs {
     uint64_t seed;
     int64_t max_attempts;
     int32_t dim;             // 3, or 2: the z coordinate is 0
-    int ncls, pad;
+    int ncls;
+    int32_t walls, round;    // hard walls (see inside_walls); bounded axes have no image
+    int32_t pad;
     const int32_t *ord;      // rank -> sphere (largest first)
     const double *d0;        // by sphere
     double *x;               // (n, 3) by sphere: placed positions

@@ -125,6 +125,9 @@ struct Seg {
     bool mixed = false;
     std::vector<uint8_t> frozen;
     double sum3_frozen = 0, sum3_grow = 0;
+    // hard walls (rcp_set_boundary): flat walls across the axes of `walls`,
+    // a round container over the axes of `round`
+    int32_t walls = 0, round = 0;
 };
 
 // A stream for the pair searches of a batch of list builds.
@@ -141,6 +144,7 @@ struct rcp_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     bool any_mixed = false;         // some packing has frozen spheres
+    bool any_walls = false;         // some packing has hard walls
     int dim = 3;                    // 3, or 2: disks in the plane z = 0
     rcp_params params{};
     rcp_tuning tuning{};
@@ -429,6 +433,8 @@ static int build_plan(rcp_ctx *c, int k, double kappa, int64_t min_entries, Buil
     a.nlev = s.nlev;
     a.L = s.L;
     a.hL = 0.5 * s.L;
+    for (int ax = 0; ax < 3; ++ax)   // no image across an axis bounded by walls
+        a.hLa[ax] = (((s.walls | s.round) >> ax) & 1) ? INFINITY : 0.5 * s.L;
     a.kb = kappa;
     a.opg = opg;
     a.sk2 = sk2;
@@ -924,14 +930,14 @@ static bool slot_timed(const rcp_ctx *c, int64_t slot)
 static int iterate_flags(const rcp_ctx *c)
 {
     return (c->tuning.xcd_remap ? 1 : 0) | ((c->tuning.variant & 128) ? 4 : 0) |
-           (c->any_mixed ? 16 : 0) | ((c->tuning.variant & 63) << 8);
+           (c->any_mixed ? 16 : 0) | (c->any_walls ? 32 : 0) | ((c->tuning.variant & 63) << 8);
 }
 
 // The tail runs inside the gradient kernel only when asked for and when no
-// packing has frozen spheres (their kernel has no fused tail).
+// packing has frozen spheres or walls (their kernels have no fused tail).
 static bool tail_fused(const rcp_ctx *c)
 {
-    return c->tuning.fused_tail && !c->any_mixed;
+    return c->tuning.fused_tail && !c->any_mixed && !c->any_walls;
 }
 
 // One iteration: gradient + Adam kernel and tail kernel, bracketed by the
@@ -1112,6 +1118,21 @@ static int reset_moments(rcp_ctx *c, int k)
     return RCP_OK;
 }
 
+// Volume (area in two dimensions) of packing k's domain: L per plain or
+// flat-walled axis, the disk or ball of diameter L over the round axes.
+static double domain_volume(const rcp_ctx *c, const Seg &s)
+{
+    int nr = 0;
+    double v = 1.0;
+    for (int a = 0; a < c->dim; ++a) {
+        if ((s.round >> a) & 1) ++nr;
+        else v = v * s.L;
+    }
+    if (nr == 2) v = v * ((M_PI / 4.0) * (s.L * s.L));
+    if (nr == 3) v = v * ((M_PI / 6.0) * (s.L * s.L * s.L));
+    return v;
+}
+
 static int shrink_seg(rcp_ctx *c, int k, double *kp_out, double *phi_out)
 {
     CHK(pull_state(c));
@@ -1143,9 +1164,10 @@ static int shrink_seg(rcp_ctx *c, int k, double *kp_out, double *phi_out)
     const double kappa = c->h_state[k].kappa;
     const double kp = std::min(kappa, kmin);
     *kp_out = kp;
-    // the volume fraction; the area fraction in two dimensions
-    *phi_out = c->dim == 2 ? (M_PI / 4.0) * (kp * kp) * s.sumd03 / (s.L * s.L)
-                           : (M_PI / 6.0) * (kp * kp * kp) * s.sumd03 / (s.L * s.L * s.L);
+    // the volume fraction; the area fraction in two dimensions (over the
+    // container's volume: L^d for a box, periodic or walled)
+    *phi_out = c->dim == 2 ? (M_PI / 4.0) * (kp * kp) * s.sumd03 / domain_volume(c, s)
+                           : (M_PI / 6.0) * (kp * kp * kp) * s.sumd03 / domain_volume(c, s);
     return RCP_OK;
 }
 
@@ -1195,6 +1217,8 @@ static int place_device(rcp_ctx *c, int k, uint64_t seed, int64_t window, int64_
     a.max_attempts = max_attempts;
     a.dim = c->dim;
     a.ncls = ncls;
+    a.walls = s.walls;
+    a.round = s.round;
     int64_t tcap = 0;
     for (int q = 0; q < ncls; ++q) {
         PlaceGrid &g = a.grid[q];
@@ -1782,9 +1806,12 @@ static int set_state3(rcp_ctx *c, int k, const double *x, double kappa, int is_d
                               c->stream));
     } else {
         std::vector<double> w(x, x + 3 * s.n);
-        for (auto &v : w) {
+        const int32_t bounded = s.walls | s.round;
+        for (size_t q = 0; q < w.size(); ++q) {
+            double &v = w[q];
             if (!std::isfinite(v) || v < -s.L || v >= 2 * s.L)
                 return fail(RCP_EINVAL, "position outside [-L, 2L)");
+            if ((bounded >> (q % 3)) & 1) continue;   // no wrap across walls
             if (v < 0) v += s.L;
             if (v >= s.L) v -= s.L;
         }
@@ -1844,6 +1871,8 @@ int rcp_set_frozen(rcp_ctx *c, int k, const uint8_t *mask)
         nadd(sum6, cs6, dd * dd);
     }
     if (ng == 0) return fail(RCP_EINVAL, "packing %d: every sphere frozen", k);
+    if (ng < n && (s.walls | s.round))
+        return fail(RCP_EINVAL, "packing %d: frozen spheres are not combined with walls", k);
     CHK(dgrow(&c->xtmp, &c->xtmp_cap, (n + 7) / 8));
     HIPCHK(hipMemcpyAsync(c->xtmp, fz.data(), (size_t)n, hipMemcpyHostToDevice, c->stream));
     launch_set_frozen(c->d_ptrs, k, n, reinterpret_cast<const uint8_t *>(c->xtmp), c->stream);
@@ -1861,6 +1890,34 @@ int rcp_set_frozen(rcp_ctx *c, int k, const uint8_t *mask)
     s.sum3_grow = sum3 + cs3;
     c->any_mixed = false;
     for (const Seg &q : c->segs) c->any_mixed = c->any_mixed || q.mixed;
+    c->graph_valid = false;
+    return RCP_OK;
+}
+
+int rcp_set_boundary(rcp_ctx *c, int k, uint32_t walls, uint32_t round)
+{
+    CHK(check_k(c, k));
+    Seg &s = c->segs[k];
+    const uint32_t axes = c->dim == 2 ? 3u : 7u;
+    const int nround = (int)((round >> 0) & 1) + (int)((round >> 1) & 1) + (int)((round >> 2) & 1);
+    if ((walls & ~axes) || (round & ~axes) || (walls & round) || nround == 1)
+        return fail(RCP_EINVAL, "packing %d: bad boundary (walls 0x%x, round 0x%x, dim %d)", k,
+                    walls, round, c->dim);
+    if (s.mixed && (walls | round))
+        return fail(RCP_EINVAL, "packing %d: frozen spheres are not combined with walls", k);
+    CHK(pull_state(c));
+    SegState st = c->h_state[k];
+    st.walls = (int32_t)walls;
+    st.round = (int32_t)round;
+    st.flags |= F_STALE;   // the list depends on which axes have images
+    HIPCHK(hipMemcpyAsync(c->d_state + k, &st, sizeof st, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->h_state[k] = st;
+    s.walls = (int32_t)walls;
+    s.round = (int32_t)round;
+    s.built = false;
+    c->any_walls = false;
+    for (const Seg &q : c->segs) c->any_walls = c->any_walls || (q.walls | q.round) != 0;
     c->graph_valid = false;
     return RCP_OK;
 }
