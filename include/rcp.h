@@ -243,7 +243,10 @@ int rcp_schedule_default(int64_t n, int dim, double S, int Y, int X, int64_t n_m
  * rcp_pack_init).  dim is 3, or 2 (Sec. 2: the dimension is an input; in
  * two dimensions placement does not draw the z axis, the schedule's
  * participation number is (sum D0^2)^2 / sum D0^4 and phi is the area
- * fraction).  stream is a hipStream_t (NULL: the library creates one).
+ * fraction; the iteration then runs a kernel instantiated for two
+ * coordinates, which leaves the z moments and reference unread, whatever
+ * the tuning variant, and the tail is not fused).  stream is a hipStream_t
+ * (NULL: the library creates one).
  * Returns RCP_EBOX if a packing's largest cutoff is not below L/2. */
 int rcp_census_init(int dim, int n_prob, const int64_t *n,
                     const double *const *d0, const double *box,

@@ -107,15 +107,19 @@ constexpr double kLoose = 1.0 + 0x1p-50;
 //
 // iLa[a] is 1 / L on a periodic axis and 0 on an axis bounded by walls
 // (no image: near_image then returns the plain difference).
-template <bool kCount = true, bool kMixed = false>
+//
+// kDim = 2: disks in the plane z = 0 (every z is 0, so dz = 0 and r^2 is
+// dx^2 + dy^2 exactly as the three-term sum rounds it); the z terms are
+// left out.
+template <bool kCount = true, bool kMixed = false, int kDim = 3>
 __device__ __forceinline__ void pair_term(Acc &a, const P4 &qi, const P4 &qj, double kappa,
                                           double L, const double (&iLa)[3])
 {
 #pragma clang fp contract(off)
     const double dx = near_image(qj.x - qi.x, L, iLa[0]);
     const double dy = near_image(qj.y - qi.y, L, iLa[1]);
-    const double dz = near_image(qj.z - qi.z, L, iLa[2]);
-    const double r2 = (dx * dx + dy * dy) + dz * dz;
+    const double dz = kDim == 3 ? near_image(qj.z - qi.z, L, iLa[2]) : 0.0;
+    const double r2 = kDim == 3 ? (dx * dx + dy * dy) + dz * dz : dx * dx + dy * dy;
     const double d = kMixed ? 0.5 * ((qi.d > 0.0 ? kappa * qi.d : -qi.d) +
                                      (qj.d > 0.0 ? kappa * qj.d : -qj.d))
                             : kappa * (0.5 * (qi.d + qj.d));
@@ -149,7 +153,7 @@ __device__ __forceinline__ void pair_term(Acc &a, const P4 &qi, const P4 &qj, do
                 const double f = (delta * id) * ir;
                 a.gx += f * dx;
                 a.gy += f * dy;
-                a.gz += f * dz;
+                if (kDim == 3) a.gz += f * dz;
             }
         }
     }
@@ -234,27 +238,30 @@ struct Pre {
     float r0, r1, r2;
 };
 
-// Streamed operands of row i (read once per iteration).
+// Streamed operands of row i (read once per iteration); in two dimensions
+// the z moments and reference are not read.
+template <int kDim = 3>
 __device__ __forceinline__ Pre preload(const IterPtrs &p, int64_t i)
 {
     Pre q;
     q.m0 = gload(p.m0, i);
     q.m1 = gload(p.m1, i);
-    q.m2 = gload(p.m2, i);
+    q.m2 = kDim == 3 ? gload(p.m2, i) : 0.0;
     q.v0 = gload(p.v0, i);
     q.v1 = gload(p.v1, i);
-    q.v2 = gload(p.v2, i);
+    q.v2 = kDim == 3 ? gload(p.v2, i) : 0.0;
     q.r0 = gload(p.r0, i);
     q.r1 = gload(p.r1, i);
-    q.r2 = gload(p.r2, i);
+    q.r2 = kDim == 3 ? gload(p.r2, i) : 0.0f;
     return q;
 }
 
 // Adam on particle i's coordinates, new position stored (the three
 // coordinates: the record's D0 in the output buffer is already in place,
 // written when the list order was set; with `full` the whole record);
-// returns |x_new - x_ref|^2 (min image).
-template <bool kMixed = false>
+// returns |x_new - x_ref|^2 (min image).  kDim = 2: z stays 0 and its
+// moments are neither read nor written (they stay 0, as its gradient is 0).
+template <bool kMixed = false, int kDim = 3>
 __device__ __forceinline__ double update_particle(const IterPtrs &p, const IterScalars &c,
                                                   int64_t i, const P4 &qi, const Pre &q,
                                                   double gx, double gy, double gz, bool full)
@@ -268,7 +275,8 @@ __device__ __forceinline__ double update_particle(const IterPtrs &p, const IterS
     P4 o;
     o.x = update_coord(qi.x, gx, q.m0, q.v0, q.r0, p.m0, p.v0, c, i, d2, c.Pa[0]);
     o.y = update_coord(qi.y, gy, q.m1, q.v1, q.r1, p.m1, p.v1, c, i, d2, c.Pa[1]);
-    o.z = update_coord(qi.z, gz, q.m2, q.v2, q.r2, p.m2, p.v2, c, i, d2, c.Pa[2]);
+    o.z = kDim == 3 ? update_coord(qi.z, gz, q.m2, q.v2, q.r2, p.m2, p.v2, c, i, d2, c.Pa[2])
+                    : qi.z;
     o.d = qi.d;
     if (full) store_p4(p.qo, (int32_t)i, o);
     else store_xyz(p.qo, (int32_t)i, o.x, o.y, o.z);
@@ -476,7 +484,7 @@ struct ColSrc {
 // their gathers are in flight together (kU = 2 or 4); the next step's
 // partner indices are requested before this step's terms are evaluated, so
 // their latency hides behind the arithmetic.
-template <int kU, bool kStage, bool kMixed = false>
+template <int kU, bool kStage, bool kMixed = false, int kDim = 3>
 __device__ __forceinline__ void segment_terms(Acc &a, const ColSrc<kStage> &cols,
                                               const P4 *__restrict__ Q, int32_t q, int32_t qe,
                                               const P4 &qi, const IterScalars &c)
@@ -495,10 +503,10 @@ __device__ __forceinline__ void segment_terms(Acc &a, const ColSrc<kStage> &cols
                 j2 = cols.at(q + 2);
                 j3 = cols.at(q + 3);
             }
-            pair_term<false, kMixed>(a, qi, q0, c.kappa, c.L, c.iLa);
-            pair_term<false, kMixed>(a, qi, q1, c.kappa, c.L, c.iLa);
-            pair_term<false, kMixed>(a, qi, q2, c.kappa, c.L, c.iLa);
-            pair_term<false, kMixed>(a, qi, q3, c.kappa, c.L, c.iLa);
+            pair_term<false, kMixed, kDim>(a, qi, q0, c.kappa, c.L, c.iLa);
+            pair_term<false, kMixed, kDim>(a, qi, q1, c.kappa, c.L, c.iLa);
+            pair_term<false, kMixed, kDim>(a, qi, q2, c.kappa, c.L, c.iLa);
+            pair_term<false, kMixed, kDim>(a, qi, q3, c.kappa, c.L, c.iLa);
             if (!more) break;
         }
     }
@@ -512,8 +520,8 @@ __device__ __forceinline__ void segment_terms(Acc &a, const ColSrc<kStage> &cols
                 j0 = cols.at(q);
                 j1 = cols.at(q + 1);
             }
-            pair_term<false, kMixed>(a, qi, q0, c.kappa, c.L, c.iLa);
-            pair_term<false, kMixed>(a, qi, q1, c.kappa, c.L, c.iLa);
+            pair_term<false, kMixed, kDim>(a, qi, q0, c.kappa, c.L, c.iLa);
+            pair_term<false, kMixed, kDim>(a, qi, q1, c.kappa, c.L, c.iLa);
             if (!more) break;
         }
     }
@@ -521,10 +529,11 @@ __device__ __forceinline__ void segment_terms(Acc &a, const ColSrc<kStage> &cols
         const int32_t j0 = cols.at(q),
                       j1 = cols.at(q + 1);
         const P4 q0 = load_p4(Q, j0), q1 = load_p4(Q, j1);
-        pair_term<false, kMixed>(a, qi, q0, c.kappa, c.L, c.iLa);
-        pair_term<false, kMixed>(a, qi, q1, c.kappa, c.L, c.iLa);
+        pair_term<false, kMixed, kDim>(a, qi, q0, c.kappa, c.L, c.iLa);
+        pair_term<false, kMixed, kDim>(a, qi, q1, c.kappa, c.L, c.iLa);
     }
-    if (q < qe) pair_term<false, kMixed>(a, qi, load_p4(Q, cols.at(q)), c.kappa, c.L, c.iLa);
+    if (q < qe)
+        pair_term<false, kMixed, kDim>(a, qi, load_p4(Q, cols.at(q)), c.kappa, c.L, c.iLa);
 }
 
 template <int kN>
@@ -563,7 +572,7 @@ struct NoHook {
 // between the phases (the persistent kernel prefetches there).  Thread 0
 // writes the item's partial sums to *out.  Every thread must call it.
 template <int kU, bool kEarly, bool kStage, int kR, class Hook, bool kCoherentOut = false,
-          bool kMixed = false, bool kWalls = false>
+          bool kMixed = false, bool kWalls = false, int kDim = 3>
 __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &c, int64_t r0,
                                           int nrow, int32_t e0, int32_t e1,
                                           const int32_t *rp_own, int32_t rp_end,
@@ -589,7 +598,7 @@ __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &
     Pre pre = {0, 0, 0, 0, 0, 0, 0.f, 0.f, 0.f};
     if (kEarly && t < nrow) {
         oq = load_p4(Q, (int32_t)(r0 + t));
-        pre = preload(p, r0 + t);
+        pre = preload<kDim>(p, r0 + t);
     }
 #pragma unroll
     for (int k = 0; k < kOwn; ++k)
@@ -621,7 +630,7 @@ __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &
             const P4 qi = load_p4(Q, (int32_t)(r0 + r));
             const int32_t rend = L.srp[r + 1], qe = min(rend, ce);
             a.gx = a.gy = a.gz = 0.0;
-            segment_terms<kU, kStage, kMixed>(a, cols, Q, q, qe, qi, c);
+            segment_terms<kU, kStage, kMixed, kDim>(a, cols, Q, q, qe, qi, c);
             const bool began_before = L.srp[r] < cs, goes_on = rend > ce;
             if (began_before) store3<kBlock>(L.A, t, a);
             else if (goes_on) store3<kBlock>(L.B, t, a);
@@ -643,7 +652,7 @@ __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &
         const int64_t io = r0 + row;
         if (!kEarly) {
             oq = load_p4(Q, (int32_t)io);
-            pre = preload(p, io);
+            pre = preload<kDim>(p, io);
         }
         const int32_t qb = L.srp[row], qe = L.srp[row + 1];
         double g[3] = {0, 0, 0};
@@ -673,7 +682,7 @@ __device__ __forceinline__ void item_body(const IterPtrs &p, const IterScalars &
             a.s += w.s;
             a.m = fmax(a.m, w.m);
         }
-        bd = fmax(bd, update_particle<kMixed>(p, c, io, oq, pre, g[0], g[1], g[2], full));
+        bd = fmax(bd, update_particle<kMixed, kDim>(p, c, io, oq, pre, g[0], g[1], g[2], full));
     }
     // block reduction of the four partials
     const int lane = t & (kWave - 1);
@@ -742,7 +751,7 @@ __device__ __forceinline__ void load_scalars(const SegState *s, IterScalars &c)
 // One block per work item; kWaves > 1 asks the compiler for that many
 // waves per SIMD (fewer registers, a little spilling).
 template <bool kFusedTail, int kU, bool kEarly, bool kStage, int kWaves, bool kMixed = false,
-          bool kWalls = false>
+          bool kWalls = false, int kDim = 3>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))) void k_iterate(const SegPtrs *__restrict__ P,
                                                    SegState *__restrict__ S,
                                                    const WorkItem *__restrict__ W,
@@ -762,7 +771,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves))
     const int nrow = (int)(w.end - w.begin);
     const int32_t rp_t = t < nrow ? gload(p.rp, r0 + t) : 0;
     const int32_t rp_end = gload(p.rp, r0 + nrow);
-    item_body<kU, kEarly, kStage, kBlock, NoHook, kFusedTail, kMixed, kWalls>(
+    item_body<kU, kEarly, kStage, kBlock, NoHook, kFusedTail, kMixed, kWalls, kDim>(
         p, c, r0, nrow, w.e0, w.e1, &rp_t, rp_end, L, scol,
         reinterpret_cast<Part4 *>(partials) + b, NoHook(), (flags & 4) != 0);
     if (kFusedTail) {
@@ -898,11 +907,12 @@ __global__ __launch_bounds__(kBlock) void k_iterate_persist(const SegPtrs *__res
     }
 }
 
-template <bool kF, int kU, bool kE, bool kNT, int kW, bool kMixed = false, bool kWalls = false>
+template <bool kF, int kU, bool kE, bool kNT, int kW, bool kMixed = false, bool kWalls = false,
+          int kDim = 3>
 static void launch_one(const SegPtrs *P, SegState *S, const WorkItem *W, double *partials,
                        int nitems, int f, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_iterate<kF, kU, kE, kNT, kW, kMixed, kWalls>), dim3(nitems),
+    hipLaunchKernelGGL((k_iterate<kF, kU, kE, kNT, kW, kMixed, kWalls, kDim>), dim3(nitems),
                        dim3(kBlock), 0, st, P, S, W, partials, f);
 }
 
@@ -962,9 +972,19 @@ void launch_iterate(const SegPtrs *P, SegState *S, const WorkItem *W, double *pa
     // two-gather kernel with the mixed pair terms runs, whatever the
     // variant); bit 5: some packing has walls (then the two-gather kernel
     // with the wall terms runs, whatever the variant; never together with
-    // bit 4); bits 8-13: kernel variant (see launch_variant)
+    // bit 4); bit 6: two dimensions (the two-gather kernel for two
+    // coordinates, whatever the variant); bits 8-13: kernel variant (see
+    // launch_variant)
     const int f = flags & 5, variant = (flags >> 8) & 63;
-    if (flags & 32)
+    if (flags & 64) {
+        if (flags & 32)
+            launch_one<false, 2, false, false, 1, false, true, 2>(P, S, W, partials, nitems, f, st);
+        else if (flags & 16)
+            launch_one<false, 2, false, false, 1, true, false, 2>(P, S, W, partials, nitems, f, st);
+        else
+            launch_one<false, 2, false, false, 1, false, false, 2>(P, S, W, partials, nitems, f,
+                                                                   st);
+    } else if (flags & 32)
         launch_one<false, 2, false, false, 1, false, true>(P, S, W, partials, nitems, f, st);
     else if (flags & 16)
         launch_one<false, 2, false, false, 1, true>(P, S, W, partials, nitems, f, st);

@@ -149,3 +149,23 @@ def test_2d_whole_runs_match_oracle(rcp, orc2):
     pg, po = np.array(pg), np.array(po)
     _say("2-D phi gpu %.5f +- %.5f oracle %.5f +- %.5f" % (pg.mean(), pg.std(), po.mean(), po.std()))
     assert abs(pg.mean() - po.mean()) <= 0.002
+
+
+def test_2d_kernel_equals_3d_kernel_on_the_plane(rcp):
+    # the kernel instantiated for two coordinates leaves out terms that are
+    # exactly zero on the plane: a 3-D context holding the same disks at
+    # z = 0 must give the same positions and kappa, bit for bit
+    d0, L = _disks(6000, 40.0, 0.8, seed=12)
+    xy = ri.rng.uniform_positions(6000, L, 7)[:, :2]
+    out = []
+    for dim in (2, 3):
+        p = rcp.Packing(d0, L, 1.0, 0, init="none", dim=dim,
+                        params=rcp.make_params(skin_s=0.3, skin_g=0.02),
+                        tuning=rcp.make_tuning(graph_iters=8))
+        p.set_state(xy if dim == 2 else np.column_stack([xy, np.zeros(6000)]), 1.0)
+        p.adam_step(2e-3, 2e-3, 2e-4, 24)
+        x, k = p.get_state()
+        p.close()
+        out.append((x[:, :2], k, x))
+    assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
+    assert np.all(out[1][2][:, 2] == 0.0)
