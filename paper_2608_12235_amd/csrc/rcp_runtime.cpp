@@ -128,6 +128,9 @@ struct Seg {
     // hard walls (rcp_set_boundary): flat walls across the axes of `walls`,
     // a round container over the axes of `round`
     int32_t walls = 0, round = 0;
+    // iteration count at the last list build and the length of the last
+    // interval between builds (0: not yet known), for the graph length
+    int64_t it_build = -1, interval = 0;
 };
 
 // A stream for the pair searches of a batch of list builds.
@@ -193,9 +196,9 @@ struct rcp_ctx {
     double *xtmp = nullptr;          // staging of user-order positions
     int64_t xtmp_cap = 0;
     double *h_out = nullptr;         // pinned small results
-    // iteration graph
-    hipGraphExec_t gexec = nullptr;
-    int graph_k = 0;
+    // iteration graphs by length (see graph_len); graph_valid = false
+    // drops them all before the next launch
+    std::vector<std::pair<int, hipGraphExec_t>> graphs;
     bool graph_valid = false;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     std::vector<hipEvent_t> kev;     // per-launch kernel timing events (3 per iteration)
@@ -930,14 +933,16 @@ static bool slot_timed(const rcp_ctx *c, int64_t slot)
 static int iterate_flags(const rcp_ctx *c)
 {
     return (c->tuning.xcd_remap ? 1 : 0) | ((c->tuning.variant & 128) ? 4 : 0) |
-           (c->any_mixed ? 16 : 0) | (c->any_walls ? 32 : 0) | ((c->tuning.variant & 63) << 8);
+           (c->any_mixed ? 16 : 0) | (c->any_walls ? 32 : 0) | (c->dim == 2 ? 64 : 0) |
+           ((c->tuning.variant & 63) << 8);
 }
 
 // The tail runs inside the gradient kernel only when asked for and when no
-// packing has frozen spheres or walls (their kernels have no fused tail).
+// packing has frozen spheres or walls and the packings are 3-D (the other
+// kernels have no fused tail).
 static bool tail_fused(const rcp_ctx *c)
 {
-    return c->tuning.fused_tail && !c->any_mixed && !c->any_walls;
+    return c->tuning.fused_tail && !c->any_mixed && !c->any_walls && c->dim == 3;
 }
 
 // One iteration: gradient + Adam kernel and tail kernel, bracketed by the
@@ -984,13 +989,23 @@ static void add_kernel_times(rcp_ctx *c, int64_t worked, int64_t nnz)
     }
 }
 
-static int capture_graph(rcp_ctx *c, int K)
+static bool seg_done(int32_t f);
+
+// The graph of K iterations, captured on first use (every graph is dropped
+// when the launch layout or the tuning changes).
+static int graph_for(rcp_ctx *c, int K, hipGraphExec_t *out)
 {
-    if (c->gexec) {
-        (void)hipGraphExecDestroy(c->gexec);
-        c->gexec = nullptr;
+    if (!c->graph_valid) {
+        for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
+        c->graphs.clear();
+        c->graph_valid = true;
     }
-    if (c->tuning.time_kernels) CHK(ensure_kernel_events(c, K));
+    for (auto &g : c->graphs)
+        if (g.first == K) {
+            *out = g.second;
+            return RCP_OK;
+        }
+    if (c->tuning.time_kernels) CHK(ensure_kernel_events(c, std::max(1, c->tuning.graph_iters)));
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
     int rc = RCP_OK;
@@ -1001,12 +1016,52 @@ static int capture_graph(rcp_ctx *c, int K)
         return rc;
     }
     if (ee != hipSuccess) return fail(RCP_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ee));
-    hipError_t e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    hipGraphExec_t x = nullptr;
+    hipError_t e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return fail(RCP_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
-    c->graph_k = K;
-    c->graph_valid = true;
+    c->graphs.push_back({K, x});
+    *out = x;
     return RCP_OK;
+}
+
+// Graph lengths a context keeps: the tuning's K, and the powers of two from
+// kMinGraph below it.
+constexpr int kMinGraph = 8;
+
+// Iterations of the next graph launch.  A packing whose list needs a
+// rebuild idles for the rest of the graph (the host rebuilds between
+// launches), so the launch is cut to about the iterations the busiest
+// packing still has before its next build: its last interval between
+// builds less the iterations since, or before a second build the
+// displacement allowance left at the displacement rate so far (and no more
+// than the iterations left before any limit); then the largest kept length
+// not above that, at least kMinGraph.  Results do not depend on it, only
+// how many launches idle.
+static int graph_len(const rcp_ctx *c, int K)
+{
+    if (K <= kMinGraph) return K;
+    int64_t want = 0;
+    for (size_t k = 0; k < c->segs.size(); ++k) {
+        const SegState &h = c->h_state[k];
+        if (seg_done(h.flags)) continue;
+        const Seg &s = c->segs[k];
+        const int64_t since = s.it_build >= 0 ? h.iters - s.it_build : 0;
+        int64_t r = K;
+        if (s.interval > 0 && s.it_build >= 0) {
+            r = s.interval - since;
+        } else if (since > 0 && h.max_disp2 > 0.0 && h.disp_lim > 0.0) {
+            const double d = std::sqrt(h.max_disp2);
+            const double est = d < h.disp_lim ? (double)since * (h.disp_lim / d - 1.0) : 0.0;
+            r = est < (double)K ? (int64_t)est : K;
+        }
+        if (h.iter_limit > 0) r = std::min<int64_t>(r, h.iter_limit - h.iters);
+        want = std::max(want, r);
+    }
+    if (want >= K) return K;
+    int G = kMinGraph;
+    while (2 * G <= want && 2 * G < K) G *= 2;
+    return G;
 }
 
 static bool seg_done(int32_t f)
@@ -1037,7 +1092,13 @@ static int run_loop(rcp_ctx *c)
             std::vector<int> rcs;
             CHK(rebuild_batch(c, ks, kap, rcs));
             for (size_t i = 0; i < ks.size(); ++i) {
-                if (rcs[i] == RCP_OK) continue;
+                if (rcs[i] == RCP_OK) {
+                    Seg &sg = c->segs[ks[i]];
+                    const int64_t it = c->h_state[ks[i]].iters;
+                    if (sg.it_build >= 0 && it > sg.it_build) sg.interval = it - sg.it_build;
+                    sg.it_build = it;
+                    continue;
+                }
                 if (c->segs.size() == 1) return rcs[i];
                 // one packing outgrew its box: stop it, let the others run
                 const int k = ks[i];
@@ -1053,10 +1114,12 @@ static int run_loop(rcp_ctx *c)
         int64_t before = 0;
         for (size_t k = 0; k < c->segs.size(); ++k) before += c->h_state[k].iters;
         if (c->tuning.time_kernels) CHK(ensure_kernel_events(c, K));
+        const int G = graph_len(c, K);
         HIPCHK(hipEventRecord(c->e0, c->stream));
         if (K > 1) {
-            if (!c->graph_valid || c->graph_k != K) CHK(capture_graph(c, K));
-            HIPCHK(hipGraphLaunch(c->gexec, c->stream));
+            hipGraphExec_t gx = nullptr;
+            CHK(graph_for(c, G, &gx));
+            HIPCHK(hipGraphLaunch(gx, c->stream));
             c->stats.graph_launches += 1;
         } else {
             CHK(launch_one_iteration(c, 0));
@@ -1079,7 +1142,7 @@ static int run_loop(rcp_ctx *c)
         }
         // a packing runs consecutive launches until it goes idle, so the
         // first `worked` launches of this batch did work
-        if (c->tuning.time_kernels) add_kernel_times(c, std::min<int64_t>(worked, K), nnz);
+        if (c->tuning.time_kernels) add_kernel_times(c, std::min<int64_t>(worked, K > 1 ? G : 1), nnz);
         (void)before;
     }
     return RCP_OK;
@@ -1499,7 +1562,7 @@ static void destroy_ctx(rcp_ctx *c)
 {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
     for (auto &s : c->segs) {
         for (int b = 0; b < 2; ++b) {
             for (int a = 0; a < 3; ++a) {
@@ -2369,8 +2432,19 @@ int rcp_run_prepare(rcp_ctx *c)
     if (!c) return fail(RCP_EINVAL, "null context");
     const int K = std::max(1, c->tuning.graph_iters);
     if (K <= 1) return RCP_OK;
-    if (!c->graph_valid || c->graph_k != K) CHK(capture_graph(c, K));
-    HIPCHK(hipGraphUpload(c->gexec, c->stream));
+    // every length the run loop may launch (see graph_len): K, and the
+    // powers of two from kMinGraph below it
+    std::vector<int> lens = {K};
+    if (K > kMinGraph) {
+        int G = kMinGraph;
+        while (2 * G < K) G *= 2;
+        for (; G >= kMinGraph; G /= 2) lens.push_back(G);
+    }
+    for (int G : lens) {
+        hipGraphExec_t gx = nullptr;
+        CHK(graph_for(c, G, &gx));
+        HIPCHK(hipGraphUpload(gx, c->stream));
+    }
     HIPCHK(hipStreamSynchronize(c->stream));
     return RCP_OK;
 }
