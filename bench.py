@@ -388,10 +388,66 @@ def leg_cascade(torch, args):
             "iterations_frozen_stages": [s.get("iterations_frozen_stage") for s in out["stages"]]}
 
 
-LEGS = {"c2": leg_c2, "rsa": leg_rsa, "census": leg_census, "cascade": leg_cascade}
+# algorithmic bytes per disk update of the two-coordinate kernel, by the
+# same count as BYTES_PER_SPHERE: read x, y (16), D0 (8), m, v (32), x_ref
+# (16); write x', y' (16), m, v (32); one row pointer (4); 4 per partner
+BYTES_PER_DISK = 124.0
+
+
+def leg_disks(torch, args):
+    """Two dimensions: lognormal sigma_lnD = 1.0, S = 1e3, N = 1e6 disks,
+    i.i.d. uniform at area fraction 0.6 (the C3 state in the plane), kappa
+    1, mu and the step sizes of the final rung held fixed; 64 + 200
+    iterations of the two-coordinate kernel, every launch timed."""
+    import rcp_inputs as ri
+    import paper_2608_12235_amd as rcp
+    n = 1_000_000
+    d0 = ri.lognormal_quantiles(n, 1.0, 1e3)
+    L = float(np.sqrt(np.sum(d0 ** 2) / 0.6))   # (pi/4) sum D^2 / L^2 = 0.6
+    x = ri.uniform_positions(n, L, 0)[:, :2]
+    S = float(d0.max() / d0.min())
+    ds = rcp.default_schedule(n, S=S, dim=2)
+    r = ds.n_rungs - 1
+    sched = rcp.schedule_from_rungs([(ds.mu[r], ds.eta_x[r], ds.eta_k[r], 1.0, 10 ** 6)],
+                                    tol=-1.0)
+    tun = rcp.make_tuning(graph_iters=64)
+    p = rcp.Packing(d0, L, 1.0, 0, init="none", dim=2, tuning=tun,
+                    params=rcp.make_params(skin_s=C3_SKIN, skin_g=0.02))
+    p.set_state(x, 1.0)
+    p.run_start(sched)
+    p.run_continue(64)
+    torch.cuda.synchronize()
+    p.reset_stats()
+    t0 = time.perf_counter()
+    p.run_continue(200)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tun.time_kernels = 2
+    p.set_tuning(tun)
+    p.run_continue(64)
+    torch.cuda.synchronize()
+    p.reset_stats()
+    p.run_continue(200)
+    torch.cuda.synchronize()
+    st = p.stats()
+    p.close()
+    nl = max(st["kernel_launches"], 1)
+    it_us = 1e3 * st["kernel_ms"] / nl
+    nnz = st["kernel_nnz"] / nl
+    b = BYTES_PER_DISK * n + BYTES_PER_PARTNER * nnz
+    return {"workload": "disks: lognormal sigma_lnD=1.0 S=1e3 N=1e6, uniform at area fraction "
+                        "0.6, final-rung mu and steps, skin %g D0_min" % C3_SKIN,
+            "value": n * 200 / wall, "unit": "particle-updates/s",
+            "k_iterate_us": it_us, "bytes_per_launch": b,
+            "k_iterate_frac": b / (it_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+            "tail_us": 1e3 * st["tail_kernel_ms"] / nl, "nnz_per_disk": nnz / n}
+
+
+LEGS = {"c2": leg_c2, "rsa": leg_rsa, "census": leg_census, "cascade": leg_cascade,
+        "disks": leg_disks}
 LEG_KEYS = {"c2": "c2_whole_run", "rsa": "rsa_start_window", "census": "census",
-            "cascade": "cascade"}
-LEG_TIMEOUT = {"c2": 300, "rsa": 300, "census": 900, "cascade": 600}
+            "cascade": "cascade", "disks": "disks_2d"}
+LEG_TIMEOUT = {"c2": 300, "rsa": 300, "census": 900, "cascade": 600, "disks": 300}
 
 
 def run_legs(names):
@@ -570,7 +626,7 @@ def main():
     ap.add_argument("--xcd-remap", dest="xcd_remap", type=int, default=None)
     ap.add_argument("--variant", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="c2,rsa,census,cascade",
+    ap.add_argument("--legs", default="c2,rsa,census,cascade,disks",
                     help="secondary legs run first in child processes (comma list of c2, rsa, "
                          "census, cascade; empty for none)")
     ap.add_argument("--leg", default=None, choices=sorted(LEGS), help=argparse.SUPPRESS)
