@@ -484,8 +484,10 @@ int rcp_census_run(rcp_ctx *ctx, const rcp_schedule *sched, int per_packing,
 
 /* Shrink to contact of packing k at its current state (Sec. 2, App. A):
  * kappa' is the largest double <= kappa such that every listed pair has
- * fl(fl(kappa' d0)^2) <= r^2 with d0 = (D0_i + D0_j)/2; phi is the volume
- * fraction at kappa'. */
+ * fl(fl(kappa' d0)^2) <= r^2 with d0 = (D0_i + D0_j)/2 and, with walls
+ * (rcp_set_boundary), every sphere clears them by the placement tests at
+ * scale kappa'; phi is the volume (area) fraction at kappa' over the
+ * container's volume. */
 int rcp_shrink(rcp_ctx *ctx, int k, double *kappa_shrunk, double *phi);
 
 /* Raw device entry points for torch.autograd.Function (packing 0; App. A,

@@ -2418,8 +2418,9 @@ int rcp_run_continue(rcp_ctx *c, int64_t n_iters, int32_t *active)
     const int ns = (int)c->segs.size();
     hipLaunchKernelGGL(k_extend, dim3((ns + 63) / 64), dim3(64), 0, c->stream, c->d_state, ns,
                        n_iters);
+    // run_loop returns right after reading every record back (nothing is
+    // launched after its last read), so the host mirror is current here
     CHK(run_loop(c));
-    CHK(pull_state(c));
     int32_t a = 0;
     for (int k = 0; k < ns; ++k)
         if (!(c->h_state[k].flags & (F_STOP | F_CAP | F_NONFINITE))) ++a;
