@@ -257,3 +257,27 @@ def test_boundary_arguments_checked(rcp):
         q.set_boundary(Z, 0)        # no z axis in two dimensions
     q.set_boundary(0, X | Y)
     q.close()
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 40])
+@pytest.mark.parametrize("walls,round_axes", [(X | Y | Z, 0), (0, X | Y | Z)])
+def test_walled_pairs_tiny_grids(rcp, orw, n, walls, round_axes):
+    # few spheres in a small walled box (class grids of fewer than 3 cells
+    # per axis, positions up to 1 past the walls): no image pairs
+    d0 = np.linspace(1.0, 2.0, n)
+    L = 9.0
+    x = np.random.default_rng(n).uniform(-1.0, L + 1.0, (n, 3))
+    p = rcp.Packing(d0, L, 1.5, 0, init="none", boundary=(walls, round_axes),
+                    params=rcp.make_params(skin_s=0.2, skin_g=0.02))
+    p.set_state(x, 1.5)
+    p.neighbor_build()
+    gi, gj = p.pairs()
+    e = p.energy_grad()
+    p.close()
+    orw.set_boundary(walls, round_axes)
+    oi, oj = orw.pairs_brute(x, d0, L, 1.5, 0.2, 0.02)
+    assert np.array_equal(gi, oi) and np.array_equal(gj, oj)
+    ai, aj = orw.pairs_brute(x, d0, L, 1.5, 0.0, 0.0)
+    r = orw.energy_grad(x, d0, L, 1.5, 0.0, ai, aj)
+    assert e["n_overlap"] == r["n_overlap"]
+    assert e["E_overlap"] == pytest.approx(r["E_ov"], rel=TOL, abs=1e-300)
