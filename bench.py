@@ -443,11 +443,41 @@ def leg_disks(torch, args):
             "tail_us": 1e3 * st["tail_kernel_ms"] / nl, "nnz_per_disk": nnz / n}
 
 
+def leg_extreme2d(torch, args):
+    """The two-dimensional packing of Fig. (extreme): truncated lognormal
+    sigma_lnD = 1.3, N = 1e5, S = 8.4e3 realised, device RSA at area fraction
+    0.05, seed 0, the default schedule for d = 2 with every rung's budget
+    but the last times 8 (the default budgets end at the iteration cap on
+    this set), listing skin 256 D0_min; phi after the shrink against the
+    paper's 0.91."""
+    import rcp_inputs as ri
+    import paper_2608_12235_amd as rcp
+    d0 = ri.lognormal_quantiles(100_000, 1.3, 8.55e3)
+    S = float(d0.max() / d0.min())
+    L = float(np.sqrt(np.pi / 4.0 * np.sum(d0 ** 2) / 0.05))
+    s = rcp.default_schedule(d0.shape[0], dim=2, S=S)
+    for r in range(s.n_rungs - 1):
+        s.budget[r] *= 8
+    t0 = time.perf_counter()
+    p = rcp.Packing(d0, L, 1.0, 0, init="rsa_device", dim=2,
+                    params=rcp.make_params(skin_s=256.0))
+    res = p.inflate_run(s)[0]
+    st = p.stats()
+    p.close()
+    wall = time.perf_counter() - t0
+    return {"workload": "2-D truncated lognormal sigma_lnD=1.3 N=1e5 S=%.4g, RSA at area "
+                        "fraction 0.05, default d=2 schedule with budgets x 8" % S,
+            "value": 1e5 * res["iterations"] / wall, "unit": "particle-updates/s",
+            "seconds": wall, "iterations": res["iterations"], "phi": res["phi"],
+            "phi_paper": 0.91, "status": res["status"], "rebuilds": st["rebuilds"]}
+
+
 LEGS = {"c2": leg_c2, "rsa": leg_rsa, "census": leg_census, "cascade": leg_cascade,
-        "disks": leg_disks}
+        "disks": leg_disks, "extreme2d": leg_extreme2d}
 LEG_KEYS = {"c2": "c2_whole_run", "rsa": "rsa_start_window", "census": "census",
-            "cascade": "cascade", "disks": "disks_2d"}
-LEG_TIMEOUT = {"c2": 300, "rsa": 300, "census": 900, "cascade": 600, "disks": 300}
+            "cascade": "cascade", "disks": "disks_2d", "extreme2d": "extreme_2d"}
+LEG_TIMEOUT = {"c2": 300, "rsa": 300, "census": 900, "cascade": 600, "disks": 300,
+               "extreme2d": 300}
 
 
 def run_legs(names):
@@ -626,7 +656,7 @@ def main():
     ap.add_argument("--xcd-remap", dest="xcd_remap", type=int, default=None)
     ap.add_argument("--variant", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="c2,rsa,census,cascade,disks",
+    ap.add_argument("--legs", default="c2,rsa,census,cascade,disks,extreme2d",
                     help="secondary legs run first in child processes (comma list of c2, rsa, "
                          "census, cascade; empty for none)")
     ap.add_argument("--leg", default=None, choices=sorted(LEGS), help=argparse.SUPPRESS)

@@ -169,3 +169,24 @@ def test_2d_kernel_equals_3d_kernel_on_the_plane(rcp):
         out.append((x[:, :2], k, x))
     assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
     assert np.all(out[1][2][:, 2] == 0.0)
+
+
+def test_2d_extreme_packing_reaches_the_papers_phi(rcp):
+    # Fig. (extreme): truncated lognormal sigma_lnD = 1.3, N = 1e5,
+    # S = 8.4e3, phi ~ 0.91 (2-D, periodic).  Device RSA at area fraction
+    # 0.05, the default d = 2 schedule with the budgets of every rung but the
+    # last times 8 (the default lengths end at the cap on this set)
+    d0 = ri.lognormal_quantiles(100_000, 1.3, 8.55e3)
+    S = float(d0.max() / d0.min())
+    assert abs(S - 8.4e3) < 0.01 * 8.4e3
+    L = float(np.sqrt(np.pi / 4.0 * np.sum(d0 ** 2) / 0.05))
+    s = rcp.default_schedule(d0.shape[0], dim=2, S=S)
+    for r in range(s.n_rungs - 1):
+        s.budget[r] *= 8
+    p = rcp.Packing(d0, L, 1.0, 0, init="rsa_device", dim=2,
+                    params=rcp.make_params(skin_s=256.0))
+    r = p.inflate_run(s)[0]
+    p.close()
+    _say("2-D extreme packing: phi %.4f after %d iterations" % (r["phi"], r["iterations"]))
+    assert r["status"] == 0 and r["max_overlap"] < 5e-4
+    assert abs(r["phi"] - 0.91) <= 0.015
