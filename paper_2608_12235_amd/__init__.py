@@ -9,7 +9,7 @@ autotuner (`autotune`).
 """
 from ._lib import lib, RcpError, LIB_PATH
 from .api import (Packing, make_params, make_tuning, default_schedule,
-                  absolute_schedule, schedule_from_rungs)
+                  absolute_schedule, schedule_from_rungs, longer_schedule)
 
 
 def overlap_energy(x, kappa, packing, mu=0.0):
@@ -19,4 +19,5 @@ def overlap_energy(x, kappa, packing, mu=0.0):
 
 
 __all__ = ["lib", "RcpError", "LIB_PATH", "Packing", "make_params", "make_tuning",
-           "default_schedule", "absolute_schedule", "schedule_from_rungs", "overlap_energy"]
+           "default_schedule", "absolute_schedule", "schedule_from_rungs", "longer_schedule",
+           "overlap_energy"]

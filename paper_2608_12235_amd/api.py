@@ -60,6 +60,20 @@ def schedule_from_rungs(rungs, tol=5e-4, absolute=0):
     return s
 
 
+def longer_schedule(s, f):
+    """A copy of schedule s with every rung f times longer and the same
+    annealing over each rung (decay^(1/f) per iteration).  The default
+    budgets are our reading; broad size distributions need longer ones to
+    reach the paper's packing fractions (see the bench's extreme2d leg)."""
+    t = Schedule()
+    C.memmove(C.byref(t), C.byref(s), C.sizeof(Schedule))
+    for r in range(t.n_rungs):
+        t.budget[r] = int(t.budget[r]) * int(f)
+        if t.decay[r] != 1.0:
+            t.decay[r] = t.decay[r] ** (1.0 / f)
+    return t
+
+
 def _result_dict(r):
     return {f: getattr(r, f) for f, _ in Result._fields_}
 

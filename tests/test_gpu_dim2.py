@@ -174,15 +174,13 @@ def test_2d_kernel_equals_3d_kernel_on_the_plane(rcp):
 def test_2d_extreme_packing_reaches_the_papers_phi(rcp):
     # Fig. (extreme): truncated lognormal sigma_lnD = 1.3, N = 1e5,
     # S = 8.4e3, phi ~ 0.91 (2-D, periodic).  Device RSA at area fraction
-    # 0.05, the default d = 2 schedule with the budgets of every rung but the
-    # last times 8 (the default lengths end at the cap on this set)
+    # 0.05, the default d = 2 schedule 8 times longer (the default lengths
+    # end at the cap on this set)
     d0 = ri.lognormal_quantiles(100_000, 1.3, 8.55e3)
     S = float(d0.max() / d0.min())
     assert abs(S - 8.4e3) < 0.01 * 8.4e3
     L = float(np.sqrt(np.pi / 4.0 * np.sum(d0 ** 2) / 0.05))
-    s = rcp.default_schedule(d0.shape[0], dim=2, S=S)
-    for r in range(s.n_rungs - 1):
-        s.budget[r] *= 8
+    s = rcp.longer_schedule(rcp.default_schedule(d0.shape[0], dim=2, S=S), 8)
     p = rcp.Packing(d0, L, 1.0, 0, init="rsa_device", dim=2,
                     params=rcp.make_params(skin_s=256.0))
     r = p.inflate_run(s)[0]

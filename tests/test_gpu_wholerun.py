@@ -49,3 +49,25 @@ def test_c2_whole_runs_match_oracle(rcp):
     print("phi gpu %.5f +- %.5f oracle %.5f +- %.5f" % (pg.mean(), pg.std(), po.mean(), po.std()))
     assert len(pg) == 8
     assert abs(pg.mean() - po.mean()) <= 0.002
+
+
+@pytest.mark.parametrize("alpha,S,n,paper", [(0.7, 773.0, 8784, 0.735), (0.9, 5167.0, 75966, 0.772)])
+def test_table_cap_rows_with_a_longer_schedule(rcp, alpha, S, n, paper):
+    # Table (tab:cap), lognormal rows: with the default schedule phi falls
+    # below the paper's value as S grows; the same schedule 8 times longer
+    # (longer_schedule) closes most of the gap (a check of the schedule
+    # reading against the paper's numbers, not of parity; seed 0)
+    d0 = ri.lognormal_quantiles(n, alpha, S)
+    L = ri.box_for_phi(d0, 0.05)
+    Sr = float(d0.max() / d0.min())
+    phi = {}
+    for f in (1, 8):
+        p = rcp.Packing(d0, L, 1.0, 0, init="rsa_device")
+        r = p.inflate_run(rcp.longer_schedule(rcp.default_schedule(n, S=Sr), f))[0]
+        p.close()
+        assert r["status"] == 0 and r["max_overlap"] < 5e-4, r
+        phi[f] = r["phi"]
+    print("tab:cap S=%g: phi %.4f (default), %.4f (x8), paper %.3f" % (S, phi[1], phi[8], paper),
+          flush=True)
+    assert phi[8] > phi[1] + 0.005
+    assert abs(phi[8] - paper) <= 0.006
