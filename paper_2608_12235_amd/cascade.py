@@ -22,7 +22,7 @@ import time
 
 import numpy as np
 
-from .api import Packing, default_schedule, make_params, schedule_from_rungs
+from .api import Packing, default_schedule, longer_schedule, make_params, schedule_from_rungs
 
 PHI1 = 0.6435   # the monodisperse value the paper quotes for Eq. (cascade)
 
@@ -49,12 +49,14 @@ def release_schedule(n, S):
 
 
 def run_cascade(n1, rho, n_classes, seed, phi0=0.05, params=None, tuning=None, counts=None,
-                log=None):
+                log=None, length=1):
     """Returns a dict: phi after each class (after its release), the class
     counts, the packing's final diameters and positions, per-stage
     iterations and seconds.  The default listing skin is 0.05 D0_min: the
     coarse class of a cascade spans a large part of the box (D / L up to
-    about 0.4 at 20 spheres), and the listing cutoff must stay below L / 2."""
+    about 0.4 at 20 spheres), and the listing cutoff must stay below L / 2.
+    length > 1 runs every schedule that many times longer (longer_schedule)."""
+    sch = (lambda s: s) if length == 1 else (lambda s: longer_schedule(s, length))
     params = params if params is not None else make_params(skin_s=0.05)
     counts = class_counts(n1, rho, n_classes) if counts is None else list(counts)
     d = np.ones(counts[0])
@@ -62,7 +64,7 @@ def run_cascade(n1, rho, n_classes, seed, phi0=0.05, params=None, tuning=None, c
     t0 = time.perf_counter()
     p = Packing(d, L, 1.0, seed, init="rsa", params=params, tuning=tuning)
     try:
-        r = p.inflate_run(default_schedule(counts[0], S=1.0))[0]
+        r = p.inflate_run(sch(default_schedule(counts[0], S=1.0)))[0]
         x, _ = p.get_state()
     finally:
         p.close()
@@ -89,7 +91,7 @@ def run_cascade(n1, rho, n_classes, seed, phi0=0.05, params=None, tuning=None, c
             p.set_state(np.concatenate([x, np.zeros((nc, 3))]), 1.0)
             p.set_frozen(mask)
             p.seat(0.5 * kappa_seat, seed)
-            rf = p.inflate_run(default_schedule(nc, S=1.0))[0]
+            rf = p.inflate_run(sch(default_schedule(nc, S=1.0)))[0]
             x, kf = p.get_state()
         finally:
             p.close()
@@ -98,7 +100,7 @@ def run_cascade(n1, rho, n_classes, seed, phi0=0.05, params=None, tuning=None, c
         p = Packing(sig, L, 1.0, seed, init="none", params=params, tuning=tuning)
         try:
             p.set_state(x, 1.0)
-            r = p.inflate_run(release_schedule(sig.shape[0], float(sig.max() / sig.min())))[0]
+            r = p.inflate_run(sch(release_schedule(sig.shape[0], float(sig.max() / sig.min()))))[0]
             x, _ = p.get_state()
         finally:
             p.close()
