@@ -69,23 +69,30 @@ def _check_state(orc, p, st, L, d0, eta_x, steps, gs, label):
     assert opt["v_kappa"] == pytest.approx(st.mkvk[1], rel=1e-9, abs=1e-300), label
 
 
-def _steps_vs_oracle(rcp, orc, d0, L, x, kappa, skin, mu, ex, ek, label, tuning=None):
+def _steps_vs_oracle(rcp, orc, d0, L, x, kappa, skin, mu, ex, ek, label, tuning=None,
+                     boundary=None):
     """One Adam step, then nine more in a second call, from (x, kappa) with
-    fresh moments: GPU against the oracle after 1 and after 10 steps."""
+    fresh moments: GPU against the oracle after 1 and after 10 steps (with
+    the hard walls `boundary` = (walls, round) on both sides, if given)."""
     P = orc.default_params(d0, s=0.1, g=0.02)
     p = rcp.Packing(d0, L, kappa, 0, init="none",
                     params=rcp.make_params(skin_s=skin, skin_g=0.02, eps_x=P.eps_x),
-                    tuning=tuning)
+                    tuning=tuning, boundary=boundary)
     p.set_state(x, kappa)
     st = orc.RunState(x, d0, L, kappa)
     gs = np.zeros((len(d0), 3))
     done = 0
-    for k in (1, 9):
-        p.adam_step(mu, ex, ek, k)
-        st.new_schedule()
-        orc.run(st, P, orc.oracle.absolute_schedule(mu, ex, ek, k), gsmax=gs)
-        done += k
-        _check_state(orc, p, st, L, d0, ex, done, gs, "%s after %d" % (label, done))
+    if boundary is not None:
+        orc.set_boundary(*boundary)
+    try:
+        for k in (1, 9):
+            p.adam_step(mu, ex, ek, k)
+            st.new_schedule()
+            orc.run(st, P, orc.oracle.absolute_schedule(mu, ex, ek, k), gsmax=gs)
+            done += k
+            _check_state(orc, p, st, L, d0, ex, done, gs, "%s after %d" % (label, done))
+    finally:
+        orc.set_boundary(0, 0)
     stats = p.stats()
     p.close()
     return stats
@@ -98,6 +105,18 @@ def test_c3_state_adam_steps_full_size(rcp, orc):
     _say("C3 full-size Adam steps")
     st = _steps_vs_oracle(rcp, orc, w.d0, w.L, w.x, 1.0, 4.0, 1e-6, 0.0125, 1e-4, "C3")
     assert st["rebuilds"] == 1 and st["nnz"] > 2_000_000
+
+
+def test_c3_state_in_a_walled_box_adam_steps_full_size(rcp, orc):
+    # the same state and launch shape with flat walls across every axis
+    # (the walls instantiation of the kernel: wall terms in the Adam phase,
+    # no images), and in a cylinder along z (round over x and y)
+    w = ri.c3_lognormal_dense(seed=0)
+    for bnd, label in (((7, 0), "C3 walled box"), ((4, 3), "C3 cylinder")):
+        _say("%s full-size Adam steps" % label)
+        st = _steps_vs_oracle(rcp, orc, w.d0, w.L, w.x, 1.0, 4.0, 1e-6, 0.0125, 1e-4, label,
+                              boundary=bnd)
+        assert st["rebuilds"] == 1 and st["nnz"] > 2_000_000
 
 
 @pytest.fixture(scope="module")
