@@ -295,3 +295,44 @@ def test_every_overlapping_pair_is_listed_or_a_rebuild_follows(rcp, orc):
     _say("steps whose list had to be rebuilt before the next gradient:", missed)
     assert p.stats()["rebuilds"] > 3
     p.close()
+
+
+def test_disks_state_adam_steps_full_size(rcp, orc):
+    # the C3 state in the plane (N = 1e6 disks, area fraction 0.6) through the
+    # kernel instantiated for two coordinates, against the oracle in 2-D
+    n = 1_000_000
+    d0 = ri.lognormal_quantiles(n, 1.0, 1e3)
+    L = float(np.sqrt(np.sum(d0 ** 2) / 0.6))
+    x = np.column_stack([ri.uniform_positions(n, L, 0)[:, :2], np.zeros(n)])
+    mu, ex, ek = 1e-6, 0.0125, 1e-4
+    P = orc.default_params(d0, s=0.1, g=0.02)
+    p = rcp.Packing(d0, L, 1.0, 0, init="none", dim=2,
+                    params=rcp.make_params(skin_s=4.0, skin_g=0.02, eps_x=P.eps_x))
+    p.set_state(x[:, :2], 1.0)
+    orc.set_dim(2)
+    try:
+        st = orc.RunState(x, d0, L, 1.0)
+        gs = np.zeros((n, 3))
+        done = 0
+        for k in (1, 9):
+            p.adam_step(mu, ex, ek, k)
+            st.new_schedule()
+            orc.run(st, P, orc.oracle.absolute_schedule(mu, ex, ek, k), gsmax=gs)
+            done += k
+            xg, kg = p.get_state()
+            mg, vg, _ = p.get_optimizer()
+            d = np.abs(xg - st.x[:, :2])
+            d = np.minimum(d, L - d)
+            bx = TOL * ex * done + done * np.spacing(np.maximum(np.abs(xg), np.abs(st.x[:, :2])))
+            _say("disks after %d: max |dx|/bar %.3g, max |dm|/gs %.3g" %
+                 (done, float(np.max(d / bx)),
+                  float(np.max(np.abs(mg - st.m[:, :2]) / (gs[:, :2] + 1e-300)))))
+            assert np.all(d <= bx)
+            assert np.all(np.abs(mg - st.m[:, :2]) <= TOL * gs[:, :2])
+            assert np.all(np.abs(vg - st.v[:, :2]) <= 2 * TOL * gs[:, :2] ** 2)
+            assert np.all(st.x[:, 2] == 0.0)
+            assert kg == pytest.approx(st.kappa[0], rel=1e-12)
+    finally:
+        orc.set_dim(3)
+    assert p.stats()["nnz"] > 1_000_000
+    p.close()
