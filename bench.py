@@ -249,6 +249,69 @@ def run_c5(torch, args):
     print(json.dumps(out), flush=True)
 
 
+# Table (tab:cap): lognormal width alpha, size ratio S = e^(2 a alpha)
+# (the truncation, Eq. (S)), N, the paper's phi and compute minutes on 14
+# CPU cores
+TABCAP_ROWS = [(0.10, 3.0, 2000, 0.641, 0.0), (0.50, 116.0, 2000, 0.698, 0.1),
+               (0.70, 773.0, 8784, 0.735, 0.2), (0.90, 5167.0, 75966, 0.772, 2.9),
+               (1.00, 13360.0, 195929, 0.788, 12.8), (1.10, 34544.0, 413799, 0.799, 35.9),
+               (1.25, 143631.0, 883556, 0.809, 98.3), (1.30, 230960.0, 1049699, 0.813, 124.2)]
+
+
+def run_tabcap(torch, args):
+    """Every row of Table (tab:cap), one seed: device RSA at phi0 = 0.05,
+    the default schedule made `--tabcap-length` times longer, whole runs to
+    the stop criterion and the shrink; phi and wall time beside the
+    paper's.  Listing skin S / 250 D0_min above S = 1e3 (the largest cutoff
+    stays below L / 2 on these rows, whose largest sphere spans about 0.4 L),
+    the library default below, and the C5 work cut above S = 1e4."""
+    import rcp_inputs as ri
+    import paper_2608_12235_amd as rcp
+    rows = [r for k, r in enumerate(TABCAP_ROWS)
+            if args.tabcap_rows is None or str(k) in args.tabcap_rows.split(",")]
+    out_rows = []
+    t_all = time.perf_counter()
+    upd = 0
+    for alpha, S, n, phi_paper, minutes in rows:
+        d0 = ri.lognormal_quantiles(n, alpha, S)
+        L = ri.box_for_phi(d0, 0.05)
+        Sr = float(d0.max() / d0.min())
+        params = rcp.make_params(skin_s=S / 250.0) if S > 1e3 else rcp.make_params()
+        tun = rcp.make_tuning(row_cost=16, item_work=4096) if S > 1e4 else rcp.make_tuning()
+        sched = rcp.longer_schedule(rcp.default_schedule(n, S=Sr), args.tabcap_length)
+        log("tab:cap alpha %.2f S %.6g N %d: placement" % (alpha, S, n))
+        t0 = time.perf_counter()
+        p = rcp.Packing(d0, L, 1.0, 0, init="rsa_device", params=params, tuning=tun)
+        p.run_start(sched)
+        while True:
+            act = p.run_continue(100000)
+            torch.cuda.synchronize()
+            log("  %d iterations, %.1f s" % (p.run_result()["iterations"],
+                                              time.perf_counter() - t0))
+            if act == 0:
+                break
+        res = p.run_result()
+        st = p.stats()
+        p.close()
+        wall = time.perf_counter() - t0
+        upd += n * res["iterations"]
+        row = {"alpha": alpha, "S": S, "N": n, "phi": res["phi"], "phi_paper": phi_paper,
+               "status": res["status"], "iterations": res["iterations"], "seconds": wall,
+               "paper_minutes_14_cores": minutes, "rebuilds": st["rebuilds"]}
+        log("  phi %.4f (paper %.3f), %.1f s (paper %.1f min on 14 cores)" %
+            (res["phi"], phi_paper, wall, minutes))
+        out_rows.append(row)
+    wall = time.perf_counter() - t_all
+    out = {"metric": METRIC, "value": upd / wall, "unit": "particle-updates/s", "n_gpus": 1,
+           "steps": sum(r["iterations"] for r in out_rows), "warmup": 0,
+           "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "Table (tab:cap) lognormal rows, seed 0, RSA at phi0=0.05, "
+                                  "default schedule x %d" % args.tabcap_length,
+                      "rows": out_rows, "seconds": wall}}
+    print(json.dumps(out), flush=True)
+
+
 def run_placement(torch, args):
     """Initial placement of the extreme size-ratio packing (lognormal
     sigma_lnD = 2.5, S = 5e5, N = 3e6, phi0 = 0.05): random sequential
@@ -662,7 +725,11 @@ def main():
                     help="kernel-timing pass after the timed region (c3 workload), HIP "
                          "events around 0: no launch (no pass, no roofline entry), 1: the "
                          "middle launch of every graph, 2: every launch")
-    ap.add_argument("--workload", default="c3", choices=("c3", "c5", "placement"),
+    ap.add_argument("--tabcap-length", dest="tabcap_length", type=int, default=8,
+                    help="schedule length factor of --workload tabcap")
+    ap.add_argument("--tabcap-rows", dest="tabcap_rows", default=None,
+                    help="comma-separated row indices of --workload tabcap (default all)")
+    ap.add_argument("--workload", default="c3", choices=("c3", "c5", "placement", "tabcap"),
                     help="c3: the default line; c5: lognormal sigma_lnD=2.5, S=5e5, N=3e6 run "
                          "to the stop criterion; placement: that packing's initial placement "
                          "on the host against the GPU")
@@ -705,6 +772,9 @@ def main():
         return
     if args.workload == "placement":
         run_placement(torch, args)
+        return
+    if args.workload == "tabcap":
+        run_tabcap(torch, args)
         return
     out, cpu_state = run_primary(torch, args)
     out.update(legs)
