@@ -121,3 +121,20 @@ def test_oracle_not_reachable_from_package():
             if f.endswith((".py", ".hip", ".cpp", ".hpp")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "rcp_oracle" not in txt, f
+
+
+def test_longer_schedule_keeps_each_rungs_annealing(L):
+    # f times the iterations per rung at decay^(1/f) per iteration: the same
+    # total decay over each rung, the same rung values, the input untouched
+    import paper_2608_12235_amd as rcp
+    s = rcp.default_schedule(200_000, S=5e3)
+    b0 = [s.budget[r] for r in range(s.n_rungs)]
+    for f in (1, 2, 8):
+        t = rcp.longer_schedule(s, f)
+        assert t.n_rungs == s.n_rungs and t.tol == s.tol and t.absolute == s.absolute
+        for r in range(s.n_rungs):
+            assert t.budget[r] == f * s.budget[r]
+            assert (t.mu[r], t.eta_x[r], t.eta_k[r]) == (s.mu[r], s.eta_x[r], s.eta_k[r])
+            assert t.decay[r] ** t.budget[r] == pytest.approx(s.decay[r] ** s.budget[r],
+                                                               rel=1e-9)
+    assert [s.budget[r] for r in range(s.n_rungs)] == b0
