@@ -1,14 +1,16 @@
 /*
  * rcp.h -- C ABI of the MI355X library for the Adam-based inflation protocol
- * (random close packings of polydisperse spheres, 3-D periodic cube).
+ * (random close packings of polydisperse spheres in a periodic cube, or
+ * disks in a periodic square, optionally bounded by hard walls).
  *
  * The library keeps every per-particle array in device memory (FP64 SoA,
  * Morton order inside; user order at this boundary) and runs every step of
  * an inflation iteration in its own HIP kernels for gfx950.
  *
  * Problem statement (Sec. 1 and App. A of the paper): a list of N positive
- * relative diameters D0_i, the spatial dimension and the domain (here a
- * periodic cube of edge L).  Diameters are D_i = kappa D0_i with one global
+ * relative diameters D0_i, the spatial dimension and the domain (a periodic
+ * cube or square of edge L; rcp_set_boundary adds flat or round hard walls,
+ * Sec. 2).  Diameters are D_i = kappa D0_i with one global
  * scale kappa.  The optimised energy is Eq. (energy):
  *     E(x, kappa) = 1/2 sum_{i<j} (1 - r_ij/d_ij)^2 Theta(1 - r_ij/d_ij)
  *                   - mu sum_i D_i,       d_ij = (D_i + D_j)/2,
