@@ -330,3 +330,32 @@ def test_adam_does_not_wrap_across_a_wall(orw):
     st = orw.RunState(np.array([[-0.1, 5.0, 5.0]]), d0, 10.0, 1.0)
     orw.run(st, orw.default_params(d0), orw.oracle.absolute_schedule(0.0, 0.01, 0.0, 1))
     assert st.x[0, 0] == pytest.approx(9.9, rel=1e-12)
+
+
+@pytest.mark.parametrize("walls,round_axes", [(X | Y, 0), (0, X | Y), (X, 0)])
+def test_wall_gradient_finite_differences_2d(orw, walls, round_axes):
+    # disks (z = 0) against flat walls and a circle: central differences of
+    # E in x, y and kappa; the z gradient stays exactly zero
+    orw.set_dim(2)
+    orw.set_boundary(walls, round_axes)
+    L, kappa, mu = 8.0, 1.1, 3e-3
+    rng = np.random.default_rng(walls + 4 * round_axes)
+    x = np.column_stack([rng.uniform(0, L, (70, 2)), np.zeros(70)])
+    d0 = rng.uniform(0.8, 1.6, 70)
+    r = _eval(orw, x, d0, L, kappa, mu)
+    assert r["n_overlap"] > 20 and np.all(r["g"][:, 2] == 0.0)
+
+    def etot(xx, k):
+        q = _eval(orw, xx, d0, L, k, mu)
+        return q["E_ov"] + q["E_growth"]
+
+    h = 1e-6
+    for i in rng.choice(70, 12, replace=False):
+        for a in range(2):
+            xp, xm = x.copy(), x.copy()
+            xp[i, a] += h
+            xm[i, a] -= h
+            fd = (etot(xp, kappa) - etot(xm, kappa)) / (2 * h)
+            assert r["g"][i, a] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+    fdk = (etot(x, kappa + h) - etot(x, kappa - h)) / (2 * h)
+    assert r["gk_ov"] + r["gk_growth"] == pytest.approx(fdk, rel=1e-6, abs=1e-8)
