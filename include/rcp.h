@@ -214,7 +214,7 @@ const char *rcp_last_error(void);
 void rcp_params_default(rcp_params *p);
 /* Defaults: graph_iters 32, xcd_remap 1, fused_tail 0, variant 192 (the
  * cooperative pair search, the two-gather gradient + Adam kernel writing
- * whole records), row_cost 8, item_work 2048, time_kernels 0. */
+ * whole records), row_cost 6, item_work 1536, time_kernels 0. */
 void rcp_tuning_default(rcp_tuning *t);
 
 /* Default rung table for a packing of n spheres in dimension dim with size

@@ -103,7 +103,7 @@ def test_tuning_defaults(L):
     lib.rcp_tuning_default(C.byref(t))
     assert t.size == C.sizeof(L.Tuning)
     assert (t.graph_iters, t.xcd_remap, t.fused_tail, t.variant) == (32, 1, 0, 192)
-    assert (t.row_cost, t.item_work, t.time_kernels) == (8, 2048, 0)
+    assert (t.row_cost, t.item_work, t.time_kernels) == (6, 1536, 0)
     # every item holds at most 256 rows: item_work <= 256 row_cost
     assert t.item_work <= 256 * t.row_cost
 
