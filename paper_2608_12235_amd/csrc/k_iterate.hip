@@ -293,72 +293,103 @@ __device__ __forceinline__ int32_t div_by(int32_t n, uint32_t d, double rd)
     return (int32_t)q;
 }
 
-__device__ __forceinline__ void rung_start(SegState *s, int r)
+// The values a rung starts from: given, or scaled from the relative ones
+// by the current kappa (mu by N_v / (kappa sum D0), eta_x by kappa D0_min,
+// eta_k by kappa).
+__device__ __forceinline__ void rung_values(const SchedDev &q, int r, double kappa, double nvol,
+                                            double sumd0, double d0min, double &mu,
+                                            double &eta_x, double &eta_k)
 {
-    const SchedDev &q = s->sched;
     if (q.absolute) {
-        s->mu = q.mu[r];
-        s->eta_x = q.eta_x[r];
-        s->eta_k = q.eta_k[r];
+        mu = q.mu[r];
+        eta_x = q.eta_x[r];
+        eta_k = q.eta_k[r];
     } else {
-        s->mu = (q.mu[r] * s->nvol) / (s->kappa * s->sumd0);
-        s->eta_x = q.eta_x[r] * (s->kappa * s->d0min);
-        s->eta_k = q.eta_k[r] * s->kappa;
+        mu = (q.mu[r] * nvol) / (kappa * sumd0);
+        eta_x = q.eta_x[r] * (kappa * d0min);
+        eta_k = q.eta_k[r] * kappa;
     }
 }
 
+__device__ __forceinline__ void rung_start(SegState *s, int r)
+{
+    rung_values(s->sched, r, s->kappa, s->nvol, s->sumd0, s->d0min, s->mu, s->eta_x, s->eta_k);
+}
+
+// The serial end of one iteration: store the reduced sums, run the stop
+// tests, take the Adam step on kappa, decay the rung's values, advance the
+// rung and set the list-validity flag.  Every field it reads is loaded
+// before any is stored and the results are stored once at the end, so the
+// stores force no reloads: the step is one dependent chain of arithmetic,
+// not of memory (or LDS) round trips.
 __device__ void tail_logic(SegState *s, double E, double S, double md, double mdisp2)
 {
+    const SchedDev &q = s->sched;
+    const int r = s->rung, last = q.n_rungs - 1;
+    const double kappa = s->kappa, mu = s->mu, sumd0 = s->sumd0, tol = q.tol;
+    const double beta1 = s->beta1, beta2 = s->beta2, eps_k = s->eps_k;
+    const double b1t0 = s->b1t, b2t0 = s->b2t, mk0 = s->mk, vk0 = s->vk;
+    const double eta_x0 = s->eta_x, eta_k0 = s->eta_k, dec = q.decay[r];
+    const double kappa_lim = s->kappa_lim, d0max_k = s->d0max_k, disp_lim = s->disp_lim;
+    const int64_t t = s->t, it_rung0 = s->it_rung, iters0 = s->iters;
+    const int64_t iter_limit = s->iter_limit, budget = q.budget[r];
+    const int32_t cur = s->cur;
+    int32_t flags = s->flags;
     s->E_ov = E;
     s->S_drd = S;
     s->max_delta = md;
     s->max_disp2 = mdisp2;
-    const SchedDev &q = s->sched;
-    const int r = s->rung, last = q.n_rungs - 1;
-    const double kappa = s->kappa;
-    const double gk = S / kappa - s->mu * s->sumd0;
+    const double gk = S / kappa - mu * sumd0;
     if (!isfinite(E) || !isfinite(gk) || !isfinite(mdisp2)) {
-        s->flags |= F_NONFINITE;
+        s->flags = flags | F_NONFINITE;
         return;
     }
-    if (r == last && md < q.tol) {
-        s->flags |= F_STOP;
+    if (r == last && md < tol) {
+        s->flags = flags | F_STOP;
         return;
     }
-    s->t += 1;
-    s->b1t *= s->beta1;
-    s->b2t *= s->beta2;
-    seg_bias_terms(*s);
-    double mk = s->mk, vk = s->vk;
-    mk = s->beta1 * mk + (1.0 - s->beta1) * gk;
-    vk = s->beta2 * vk + (1.0 - s->beta2) * (gk * gk);
-    const double mh = mk / (1.0 - s->b1t), vh = vk / (1.0 - s->b2t);
-    s->kappa = kappa - s->eta_k * mh / (sqrt(vh) + s->eps_k);
-    s->mk = mk;
-    s->vk = vk;
-    s->cur ^= 1;
-    s->mu *= q.decay[r];
-    s->eta_x *= q.decay[r];
-    s->eta_k *= q.decay[r];
-    s->it_rung += 1;
-    s->iters += 1;
-    if (s->it_rung >= q.budget[r]) {
+    const double b1t = b1t0 * beta1, b2t = b2t0 * beta2;
+    const double mk = beta1 * mk0 + (1.0 - beta1) * gk;
+    const double vk = beta2 * vk0 + (1.0 - beta2) * (gk * gk);
+    const double mh = mk / (1.0 - b1t), vh = vk / (1.0 - b2t);
+    const double kappa1 = kappa - eta_k0 * mh / (sqrt(vh) + eps_k);
+    double mu1 = mu * dec, eta_x1 = eta_x0 * dec, eta_k1 = eta_k0 * dec;
+    int64_t it_rung = it_rung0 + 1;
+    const int64_t iters = iters0 + 1;
+    int rung = r;
+    if (it_rung >= budget) {
         if (r == last) {
-            s->flags |= F_CAP;
+            flags |= F_CAP;
         } else {
-            s->rung = r + 1;
-            s->it_rung = 0;
-            rung_start(s, r + 1);
+            rung = r + 1;
+            it_rung = 0;
+            rung_values(q, r + 1, kappa1, s->nvol, sumd0, s->d0min, mu1, eta_x1, eta_k1);
         }
     }
-    if (!(s->kappa > 0.0) || !isfinite(s->kappa)) s->flags |= F_NONFINITE;
+    if (!(kappa1 > 0.0) || !isfinite(kappa1)) flags |= F_NONFINITE;
     // list validity: an unlisted pair had r >= kb ((1 + g) d0_ij + 2 s D0_min)
     // at the build, so it cannot touch while 2 max|dx| + max(0, kappa - (1 +
     // g) kb) D0_max <= 2 s kb D0_min (growth beyond the g allowance is paid
     // from the displacement skin)
-    const double excess = fmax(0.0, s->kappa - s->kappa_lim);
-    if (!(2.0 * sqrt(mdisp2) + excess * s->d0max_k <= 2.0 * s->disp_lim)) s->flags |= F_REBUILD;
-    if (s->iter_limit > 0 && s->iters >= s->iter_limit) s->flags |= F_HOLD;
+    const double excess = fmax(0.0, kappa1 - kappa_lim);
+    if (!(2.0 * sqrt(mdisp2) + excess * d0max_k <= 2.0 * disp_lim)) flags |= F_REBUILD;
+    if (iter_limit > 0 && iters >= iter_limit) flags |= F_HOLD;
+    s->t = t + 1;
+    s->b1t = b1t;
+    s->b2t = b2t;
+    s->ib1n = 1.0 / (1.0 - b1t * beta1);
+    s->ib2n = 1.0 / (1.0 - b2t * beta2);
+    s->mk = mk;
+    s->vk = vk;
+    s->kappa = kappa1;
+    s->cur = cur ^ 1;
+    s->mu = mu1;
+    s->eta_x = eta_x1;
+    s->eta_k = eta_k1;
+    s->it_rung = it_rung;
+    s->iters = iters;
+    s->rung = rung;
+    s->flags = flags;
 }
 
 // Per-block partial sums of one iteration: E_ov, S, max delta, max disp^2.
@@ -413,33 +444,27 @@ __device__ __forceinline__ Part4 thread_partials(int64_t nb, int64_t b0, const d
     return a;
 }
 
-// Block reduction of the threads' shares (DPP within waves, then the waves
-// in order by thread 0), then thread 0 runs the tail.  Every thread of the
-// block must call it.
+// Block reduction of the threads' shares (DPP within waves, then the
+// waves' sums by a second DPP pass in wave 0), then thread 0 runs the tail.
+// Every thread of the block must call it.
 template <int kT>
 __device__ __forceinline__ void block_tail(SegState *s, const Part4 &mine)
 {
     constexpr int kW = kT / kWave;
+    static_assert(kW <= kWave, "one wave combines the waves' sums");
     const double e = wave_sum_dpp(mine.e), sd = wave_sum_dpp(mine.s);
     const double m = wave_max_dpp(mine.m), d = wave_max_dpp(mine.d);
-    __shared__ double red[kW][4];
+    __shared__ Part4 red[kW];
     const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-    if (lane == 0) {
-        red[wv][0] = e;
-        red[wv][1] = sd;
-        red[wv][2] = m;
-        red[wv][3] = d;
-    }
+    if (lane == 0) red[wv] = Part4{e, sd, m, d};
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double te = 0, ts = 0, tm = 0, td = 0;
-        for (int k = 0; k < kW; ++k) {
-            te += red[k][0];
-            ts += red[k][1];
-            tm = fmax(tm, red[k][2]);
-            td = fmax(td, red[k][3]);
-        }
-        tail_logic(s, te, ts, tm, td);
+    if (wv == 0) {
+        // lanes past the waves contribute zeros (the maxima are of values
+        // >= 0, as the per-thread shares start from 0)
+        const Part4 w = lane < kW ? red[lane] : Part4{0, 0, 0, 0};
+        const double te = wave_sum_dpp(w.e), ts = wave_sum_dpp(w.s);
+        const double tm = wave_max_dpp(w.m), td = wave_max_dpp(w.d);
+        if (lane == 0) tail_logic(s, te, ts, tm, td);
     }
 }
 
