@@ -905,3 +905,123 @@ def test_2d_bidisperse_run_jams_in_the_plane(orc2):
     assert status == 0 and res.max_overlap < 5e-4
     assert np.all(st.x[:, 2] == 0.0)
     assert 0.80 < res.phi < 0.88
+
+
+# ------------------------------------- close-packed lattices (closed forms)
+def _lattice(kind, n):
+    # n^3 cubic cells of side 1 in a periodic cube of side n: face-centred
+    # (4 sites a cell, nearest neighbours at 1/sqrt(2), 12 of them) or
+    # body-centred (2 sites, nearest at sqrt(3)/2 along the body diagonals,
+    # 8 of them); sites offset by a quarter cell so that no coordinate sits
+    # on the wrap point
+    basis = {"fcc": [(0, 0, 0), (0.5, 0.5, 0), (0.5, 0, 0.5), (0, 0.5, 0.5)],
+             "bcc": [(0, 0, 0), (0.5, 0.5, 0.5)]}[kind]
+    c = np.stack(np.meshgrid(*(np.arange(n),) * 3, indexing="ij"), -1).reshape(-1, 3)
+    x = (c[:, None, :] + np.array(basis)[None, :, :] + 0.25).reshape(-1, 3)
+    contact, z, phi = {"fcc": (np.sqrt(0.5), 12, np.pi / (3.0 * np.sqrt(2.0))),
+                       "bcc": (np.sqrt(0.75), 8, np.pi * np.sqrt(3.0) / 8.0)}[kind]
+    return x.astype(np.float64), contact, z, phi, float(n)
+
+
+@pytest.mark.parametrize("kind", ["fcc", "bcc"])
+def test_close_packed_lattices_closed_forms(orc, kind):
+    # equal spheres of diameter the nearest-neighbour distance: at kappa > 1
+    # exactly the z nearest neighbours of each site overlap, each pair by
+    # delta = 1 - 1/kappa (r = D0, d = kappa D0), so E = (z N / 2) delta^2 / 2
+    # and dE/dkappa = (z N / 2) delta / kappa^2; every gradient vanishes by
+    # the lattice's inversion symmetry; the shrink lands on touching,
+    # kappa' = 1, and phi is the lattice's packing fraction
+    x, D, z, phi_lat, L = _lattice(kind, 3)
+    n = x.shape[0]
+    d0 = np.full(n, D)
+    kappa = 1.15
+    pi, pj = orc.pairs_brute(x, d0, L, kappa, 0.0, 0.0)
+    assert pi.shape[0] == z * n // 2
+    assert np.all(np.bincount(np.concatenate([pi, pj]), minlength=n) == z)
+    r = orc.energy_grad(x, d0, L, kappa, 0.0, pi, pj)
+    delta = 1.0 - 1.0 / kappa
+    P = z * n / 2
+    assert r["n_overlap"] == P
+    assert r["E_ov"] == pytest.approx(P * 0.5 * delta ** 2, rel=1e-12)
+    assert r["gk_ov"] == pytest.approx(P * delta / kappa ** 2, rel=1e-12)
+    assert r["max_delta"] == pytest.approx(delta, rel=1e-12)
+    assert np.abs(r["g"]).max() <= 1e-12
+    kp = orc.shrink(x, d0, L, kappa, pi, pj)
+    assert kp == pytest.approx(1.0, rel=1e-15)
+    assert orc.phi(d0, L, kp) == pytest.approx(phi_lat, rel=1e-14)
+    # at kappa just below touching no pair overlaps and the shrink keeps kappa
+    pi0, pj0 = orc.pairs_brute(x, d0, L, 0.999, 0.0, 0.0)
+    assert pi0.shape[0] == 0
+    assert orc.energy_grad(x, d0, L, 0.999, 0.0, pi, pj)["E_ov"] == 0.0
+
+
+def test_fcc_site_displacement_restoring_force(orc):
+    # one site of the face-centred lattice moved by e along x, at kappa =
+    # 1.2 (every nearest-neighbour pair overlapping by delta = 1/6): its
+    # gradient is dE/de = sum_j delta_j (a_jx - e) / (kappa D r_j) over its
+    # 12 neighbours a_j (|a_j| = D = 1/sqrt(2)); to first order in e that
+    # is k e with k = c (12 c - 12 / D + sum_j a_jx^2 / D^3), c = 1 / (kappa
+    # D), and sum_j a_jx^2 = 2 (8 neighbours with a_jx = +-1/2): k = (2 /
+    # kappa) (12 / kappa - 8) = 10/3.  Checked by the central difference of
+    # the oracle's gradient and against a brute-force sum over every site
+    x, D, z, _, L = _lattice("fcc", 3)
+    n = x.shape[0]
+    d0 = np.full(n, D)
+    kappa = 1.2
+    pi, pj = orc.pairs_brute(x, d0, L, kappa + 0.05, 0.0, 0.0)
+    site = 13
+
+    def g(e):
+        y = x.copy()
+        y[site, 0] += e
+        return orc.energy_grad(y, d0, L, kappa, 0.0, pi, pj)["g"][site]
+
+    def brute(e):
+        p = x[site] + np.array([e, 0.0, 0.0])
+        out = np.zeros(3)
+        for j in range(n):
+            if j == site:
+                continue
+            dv = x[j] - p
+            dv -= L * np.round(dv / L)
+            rj = np.linalg.norm(dv)
+            dl = 1.0 - rj / (kappa * D)
+            if dl > 0:
+                out += dl / (kappa * D) * dv / rj
+        return out      # dE/dx of the displaced site (d delta / dp = dv / (kappa D r))
+
+    k = (2.0 / kappa) * (12.0 / kappa - 8.0)
+    h = 1e-6
+    assert (g(h)[0] - g(-h)[0]) / (2 * h) == pytest.approx(k, rel=1e-8)
+    for e in (1e-3, -2e-3, 0.01):
+        np.testing.assert_allclose(g(e), brute(e), rtol=1e-11, atol=1e-14)
+        assert g(e)[0] * e > 0   # the energy rises as the site leaves its cage
+        assert abs(g(e)[1]) <= 1e-14 and abs(g(e)[2]) <= 1e-14
+
+
+@pytest.mark.parametrize("kind", ["fcc", "bcc"])
+def test_lattice_kappa_adam_is_the_scalar_recurrence(orc, kind):
+    # with the position step zero the sites stay on the lattice and every
+    # iteration sees E(kappa) = (z N / 2) (1 - 1/kappa)^2 / 2 exactly, so
+    # Adam on kappa (App. A; Kingma and Ba, bias-corrected) is the scalar
+    # recurrence on dE/dkappa = (z N / 2) (1 - 1/kappa) / kappa^2
+    x, D, z, _, L = _lattice(kind, 4)
+    n = x.shape[0]
+    d0 = np.full(n, D)
+    kappa, eta_k, steps = 1.1, 2e-3, 12
+    P = orc.default_params(d0, s=0.2, g=0.02)
+    st = orc.RunState(x, d0, L, kappa)
+    status, res, _ = orc.run(st, P, orc.absolute_schedule(0.0, 0.0, eta_k, steps))
+    assert status == 1 and res.iterations == steps
+    m = v = 0.0
+    b1t = b2t = 1.0
+    k = kappa
+    for _ in range(steps):
+        g = (z * n / 2) * (1.0 - 1.0 / k) / k ** 2
+        b1t *= P.beta1
+        b2t *= P.beta2
+        m = P.beta1 * m + (1.0 - P.beta1) * g
+        v = P.beta2 * v + (1.0 - P.beta2) * g * g
+        k = k - eta_k * (m / (1.0 - b1t)) / (np.sqrt(v / (1.0 - b2t)) + P.eps_k)
+    assert st.kappa[0] == pytest.approx(k, rel=1e-13)
+    assert np.array_equal(st.x, x)
