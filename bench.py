@@ -214,9 +214,11 @@ def run_c5(torch, args):
     # where the kernel starts to slow)
     skin = C5_SKIN if args.skin is None else args.skin
     log("placement (random sequential addition, N=%d, S=%.3g)" % (n, S))
-    # work cut 16 / 4096 measured faster than the library default on this
-    # workload (176 against 196 us per iteration launch at skin 2048)
-    tun = rcp.make_tuning(time_kernels=1, row_cost=16, item_work=4096)
+    # the library's work cut (6 / 1536) is the fastest of those measured on
+    # this workload: 135 us per iteration launch against 136, 137, 141, 144,
+    # 149 and 153 us at 8 / 2048, 10 / 2560, 12 / 3072, 16 / 4096, 24 / 6144
+    # and 32 / 8192 (skin 2048, whole runs)
+    tun = rcp.make_tuning(time_kernels=1)
     _apply_tuning_args(tun, args)
     p = rcp.Packing(w.d0, w.L, 1.0, w.seed, init="rsa", params=rcp.make_params(skin_s=skin),
                     tuning=tun)
