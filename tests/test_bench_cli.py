@@ -44,3 +44,21 @@ def test_committed_counter_summary_exists():
     for k in ("workload", "source_sha256", "fetch_kib_per_launch", "write_kib_per_launch",
               "fetch_scale", "write_scale", "commands"):
         assert k in t, k
+
+
+def test_committed_counters_match_the_committed_kernel():
+    # the counters were taken on the kernel sources as committed, so the
+    # bench line carries traffic; and the summary they point to names the
+    # same source hash.  Traffic lies near the algorithmic bytes of the
+    # C3 state (176 N + 4 (N + nnz), N = 1e6, nnz / N = 2.305): above it by
+    # the whole-record writes, below 1.5 x (no gross re-reads)
+    sys.path.insert(0, ROOT)
+    import bench
+    with open(bench.TRAFFIC_FILE) as fh:
+        t = json.load(fh)
+    assert t["source_sha256"] == bench.kernel_source_hash()
+    with open(os.path.join(ROOT, t["summary"])) as fh:
+        assert t["source_sha256"] in fh.read()
+    b, _ = bench.counter_traffic(t["workload"])
+    algorithmic = 176.0 * 1e6 + 4.0 * (1e6 + 2.305e6)
+    assert 0.9 * algorithmic < b < 1.5 * algorithmic
