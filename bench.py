@@ -599,7 +599,11 @@ def run_primary(torch, args):
     if not graph_fixed and 1 <= args.warmup <= 4096:
         tun.graph_iters = args.warmup
     p = rcp.Packing(d0, L, 1.0, 0, init="none", params=params, tuning=tun)
-    p.set_state(w.x, 1.0)
+    torch.cuda.synchronize()
+    tu = time.perf_counter()
+    p.set_state(w.x, 1.0)       # positions host -> device (N x 3 FP64)
+    torch.cuda.synchronize()
+    t_up = time.perf_counter() - tu
     p.run_start(sched)
     log("warmup %d iterations" % args.warmup)
     if args.warmup:
@@ -635,7 +639,10 @@ def run_primary(torch, args):
         st = p.stats()
     _, _, opt = p.get_optimizer(moments=False)
     res = p.run_result()
-    xs, kap = p.get_state()
+    torch.cuda.synchronize()
+    td = time.perf_counter()
+    xs, kap = p.get_state()     # positions device -> host
+    t_down = time.perf_counter() - td
     p.close()
     iters = st_timed["iterations"]
     wall = t1 - t0
@@ -695,6 +702,10 @@ def run_primary(torch, args):
                                   % (args.warmup + 2 * iters, args.warmup + 3 * iters, iters),
             "tail_us": tail_us,
             "kernel_rate": n / (rf["avg_launch_us"] * 1e-6) if rf["avg_launch_us"] > 0 else None,
+            # a job that hands over host positions once and reads them back
+            # once: the timed region plus those two copies (not `value`)
+            "host_transfer_ms": {"positions_in": 1e3 * t_up, "positions_out": 1e3 * t_down},
+            "value_with_host_transfers": n * iters / (wall + t_up + t_down),
         },
         "roofline": rf,
     }

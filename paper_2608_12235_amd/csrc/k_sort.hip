@@ -229,4 +229,30 @@ int radix_sort_segs(const SortSeg *sg, int nseg, int64_t ntiles, int nbits, bool
     return par;
 }
 
+// ------------------------------------------------ positions out of list order
+// Positions of packing seg from list order back into user order (xu:
+// n x 3 row-major), the reverse of k_set_positions; orig is a permutation
+// of [0, n).
+__global__ __launch_bounds__(kBlock) void k_get_positions(const SegPtrs *__restrict__ P,
+                                                         int seg, int64_t n,
+                                                         double *__restrict__ xu, int cur)
+{
+    const P4 *Q = cur ? P[seg].p[1] : P[seg].p[0];
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int64_t u = P[seg].orig[i];
+    const P4 q = Q[i];
+    xu[3 * u] = q.x;
+    xu[3 * u + 1] = q.y;
+    xu[3 * u + 2] = q.z;
+}
+
+void launch_get_positions(const SegPtrs *P, int seg, int64_t n, double *xu, int cur,
+                          hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_get_positions, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
+                       0, st, P, seg, n, xu, cur);
+}
+
 }  // namespace rcp

@@ -248,6 +248,9 @@ void launch_moments_io(const SegPtrs *P, int seg, int64_t n, double *mu, double 
 // Gather user-order positions xu (n x 3) into the current SoA buffer.
 void launch_set_positions(const SegPtrs *P, SegState *S, int seg, int64_t n, const double *xu,
                           int cur, hipStream_t s);
+// Scatter the current positions into user order xu (n x 3, device).
+void launch_get_positions(const SegPtrs *P, int seg, int64_t n, double *xu, int cur,
+                          hipStream_t s);
 // Shrink to contact: per-block minima of the pair contact scales in
 // part[0..nblocks), their minimum in part[nblocks].
 void launch_shrink(const SegPtrs *P, const SegState *S, int seg, int64_t n, double *part,

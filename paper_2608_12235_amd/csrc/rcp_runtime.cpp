@@ -2101,6 +2101,19 @@ static int get_state3(rcp_ctx *c, int k, double *x, double *kappa, double *diam)
     CHK(pull_state(c));
     Seg &s = c->segs[k];
     const int64_t n = s.n;
+    if (!diam) {
+        // positions scattered into user order on the device, one copy out
+        if (x && n > 0) {
+            CHK(dgrow(&c->xtmp, &c->xtmp_cap, 3 * n));
+            launch_get_positions(c->d_ptrs, k, n, c->xtmp, s.cur, c->stream);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(x, c->xtmp, sizeof(double) * 3 * n, hipMemcpyDeviceToHost,
+                                  c->stream));
+            HIPCHK(hipStreamSynchronize(c->stream));
+        }
+        if (kappa) *kappa = c->h_state[k].kappa;
+        return RCP_OK;
+    }
     std::vector<P4> q(n);
     std::vector<int32_t> orig(n);
     HIPCHK(hipMemcpy(orig.data(), s.ORIG[s.set], sizeof(int32_t) * n, hipMemcpyDeviceToHost));
