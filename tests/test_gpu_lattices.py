@@ -1,6 +1,7 @@
 """Close-packed lattices on the GPU, through the C ABI, against closed forms
 that do not involve the oracle: equal spheres on face- and body-centred
-cubic lattices in a periodic cube, touching at kappa = 1.
+cubic lattices in a periodic cube, touching at kappa = 1.  Also: the two
+read-back paths of the state give the same positions.
 
 At kappa > 1 exactly the z nearest neighbours of every site overlap, each
 pair by delta = 1 - 1/kappa (Eq. (energy) with r = D0, d = kappa D0); the
@@ -100,3 +101,27 @@ def test_lattice_adam_on_kappa_is_the_scalar_recurrence(rcp, kind):
     assert kg < kappa
     assert kg == pytest.approx(k, rel=1e-12)
     assert np.array_equal(xg, x)
+
+
+@pytest.mark.parametrize("dim", [3, 2])
+def test_state_readback_paths_agree(rcp, dim):
+    # positions read back in user order by the device scatter (positions
+    # only) and by the host path (with diameters) are the same bits, after
+    # a run has permuted the records through list builds; the
+    # diameters are kappa D0 in user order
+    import rcp_inputs as ri
+    w = ri.small_polydisperse(20000, 20.0, 0.3, seed=4)
+    d0 = w.d0
+    L = w.L if dim == 3 else float(np.sqrt(np.pi / 4.0 * np.sum(d0 ** 2) / 0.3))
+    p = rcp.Packing(d0, L, 1.0, 3, init="rsa_device", dim=dim,
+                    params=rcp.make_params(skin_s=0.05))
+    p.run_start(rcp.default_schedule(len(d0), dim=dim, S=float(d0.max() / d0.min())))
+    p.run_continue(600)
+    assert p.stats()["rebuilds"] >= 1
+    x1, k1 = p.get_state()
+    x2, k2, dm = p.get_state(diameters=True)
+    p.close()
+    assert k1 == k2
+    assert x1.shape == (len(d0), dim)
+    assert np.array_equal(x1, x2)
+    np.testing.assert_allclose(dm, k1 * d0, rtol=1e-15)
